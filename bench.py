@@ -1,0 +1,178 @@
+#!/usr/bin/env python
+"""Benchmark: one shared-timestep step of the N-body/SPH hot path on the
+16M-particle synthetic disk galaxy (8e6 stars, 6.4e6 halo, 1.6e6 gas;
+theta = 0.5 with quadrupoles, groups of <= 256, SPH with 64 neighbours,
+dt = 2,000 yr), on one MI355X.
+
+A step is the whole hot path: half kick + drift (FP64), gravity tree build,
+interaction lists and pairwise gravity (FP32 group-relative), gas tree build,
+kernel size + density, hydro force, second half kick, FP64 energy audit.
+
+Prints ONE JSON line.  ``value`` = gravity interactions (particle-particle +
+particle-cell) per second of whole-step wall time.  ``roofline`` reports the
+dominant kernel (pairwise gravity) against the FP32 vector peak, timed live
+with HIP events on the library's stream.  ``cpu_baseline`` times the FP64
+oracle's tree gravity on a seeded sample of the same workload's groups.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "interactions/s & s/step at 16M particles; SN region: surrogate vs plain SPH"
+YEAR_IN_KPC_TIME = 1.0 / 0.97779e9  # time unit kpc/(km/s) = 0.97779 Gyr
+PEAK_FP32 = 157.3e12                 # MI355X FP32 vector, FLOP/s
+HBM_PEAK = 8.0e12                    # B/s
+FLOP_PP = 27                         # per particle-particle interaction (Table 4 convention)
+FLOP_PC = 63                         # per particle-cell interaction, monopole + quadrupole
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=16_000_000)
+    ap.add_argument("--seed", type=int, default=4)
+    ap.add_argument("--cpu-groups", type=int, default=1024,
+                    help="groups in the oracle's timed sample (0 skips the CPU baseline)")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(d, n_groups_sample, seed):
+    import oracle
+    import ics
+    t0 = time.perf_counter()
+    T = oracle.Tree(d, 16, 256)
+    build_s = time.perf_counter() - t0
+    gsel = ics.sample_indices(T.n_groups, n_groups_sample, seed)
+    t0 = time.perf_counter()
+    r = T.gravity_groups(gsel, ics.G_KPC, 0.5, True)
+    dt = time.perf_counter() - t0
+    inter = r[4] + r[5]
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": inter / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
+            "sample": (f"FP64 oracle tree gravity (theta 0.5, quadrupole) for {len(gsel)} of "
+                       f"{T.n_groups} groups of the 16M disk ({inter:.3e} interactions in "
+                       f"{dt:.2f} s; oracle tree build {build_s:.1f} s not included)")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                          "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+    import torch
+    import ics
+    import paper_2510_23330_amd as gx
+    from paper_2510_23330_amd.sim import GalaxyStep, StepConfig
+
+    t0 = time.perf_counter()
+    d = ics.disk_galaxy(args.n, args.seed)
+    log(f"[bench] generated {args.n} particles in {time.perf_counter() - t0:.1f} s")
+    eng = gx.Engine(0)
+    p = gx.ParticleSet.from_numpy(d)
+    u = torch.as_tensor(d["u_gas"], device="cuda")
+    cfg = StepConfig(G=ics.G_KPC, dt=2000.0 * YEAR_IN_KPC_TIME, theta=0.5, quad=True,
+                     n_leaf=16, n_group=256, sph_leaf=8, sph_group=64, n_ngb=64.0,
+                     u_floor=10.0 * ics.U_PER_K)
+    sim = GalaxyStep(eng, p, int(d["gas_offset"]), u, cfg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.initial_forces()
+    torch.cuda.synchronize()
+    log(f"[bench] initial forces (cold kernel sizes) {time.perf_counter() - t0:.2f} s")
+    for w in range(args.warmup):
+        sim.step()
+        sim.energy()
+        log(f"[bench] warmup step {w} done")
+    torch.cuda.synchronize()
+
+    per = []
+    grav_ms, grav_kernel_ms, dens_ms, hydro_ms, tree_ms = [], [], [], [], []
+    n_pp = n_pc = n_sph = 0
+    energies = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        st = sim.step()
+        energies.append(sim.energy())
+        per.append(time.perf_counter() - ts)
+        grav_ms.append(st["gravity"]["ms"])
+        grav_kernel_ms.append(st["gravity"]["ms_kernel"])
+        dens_ms.append(st["density"]["ms"])
+        hydro_ms.append(st["hydro"]["ms"])
+        tree_ms.append(st["tree_all"]["ms"] + st["tree_gas"]["ms"])
+        n_pp += st["gravity"]["n_pp"]
+        n_pc += st["gravity"]["n_pc"]
+        n_sph += st["density"]["n_sph_list"] + st["hydro"]["n_sph_list"]
+        log(f"[bench] step {k}: {per[-1] * 1e3:.1f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_step = elapsed / args.steps * 1e3
+    inter_step = (n_pp + n_pc) / args.steps
+    value = inter_step / (ms_step / 1e3)
+    kernel_s = float(np.mean(grav_kernel_ms)) / 1e3
+    flops = (FLOP_PP * n_pp + FLOP_PC * n_pc) / args.steps
+    achieved = flops / kernel_s
+    E0 = sum(energies[0])
+    E1 = sum(energies[-1])
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "disk galaxy 16M: 8e6 disk stars, 6.4e6 NFW halo, 1.6e6 gas disk; "
+                               "theta 0.5 + quadrupole, n_leaf 16, groups <= 256; SPH Wendland C4, "
+                               "64 neighbours, groups <= 64; dt 2000 yr",
+                   "n_particles": args.n, "seed": args.seed},
+        "s_per_step": ms_step / 1e3,
+        "grav_interactions_per_step": inter_step,
+        "grav_pp_per_step": n_pp / args.steps,
+        "grav_pc_per_step": n_pc / args.steps,
+        "sph_pairs_per_step": n_sph / args.steps,
+        "phase_ms": {"tree_builds": float(np.mean(tree_ms)), "gravity": float(np.mean(grav_ms)),
+                     "gravity_kernel": float(np.mean(grav_kernel_ms)),
+                     "sph_density": float(np.mean(dens_ms)), "sph_force": float(np.mean(hydro_ms))},
+        "gravity_kernel_interactions_per_s": inter_step / kernel_s,
+        "energy_drift_rel": abs(E1 - E0) / abs(E0),
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
+                     "kernel": "k_grav_force<float,true>",
+                     "flop_convention": f"{FLOP_PP}/pp + {FLOP_PC}/pc"},
+    }
+    if not args.no_cpu and args.cpu_groups > 0:
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(d, args.cpu_groups, 99)
+        log(f"[bench] cpu baseline {time.perf_counter() - t0:.1f} s")
+    else:
+        out["cpu_baseline"] = None
+    eng.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

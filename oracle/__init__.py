@@ -68,12 +68,13 @@ def lib():
         L.orc_tree_list_counts.argtypes = [P, D, P, P, P]
         L.orc_tree_list_fill.argtypes = [P, D, P, P, P, P]
         L.orc_tree_gravity.argtypes = [P, D, D, C.c_int, P, P, P, P, P, P]
+        L.orc_tree_gravity_groups.argtypes = [P, D, D, C.c_int, I64, P, P, P, P, P, P, P]
         L.orc_node_field.argtypes = [P, I64, C.c_int, P, P]
         L.orc_wendland_c4.argtypes = [D, D]
         L.orc_wendland_c4.restype = D
         L.orc_wendland_c4_dr.argtypes = [D, D]
         L.orc_wendland_c4_dr.restype = D
-        L.orc_sph_density.argtypes = [I64, P, P, P, P, D, D, C.c_int, I64, P, P, P, P, P]
+        L.orc_sph_density.argtypes = [I64, P, P, P, P, D, D, C.c_int, I64, P, P, P, P, P, P]
         L.orc_sph_density.restype = I64
         L.orc_sph_force.argtypes = [I64, P, P, P, P, P, P, P, P, P, P, D, D, I64, P,
                                     P, P, P, P, P]
@@ -190,6 +191,17 @@ class Tree:
                                C.byref(npp), C.byref(npc))
         return (*out, npp.value, npc.value)
 
+    def gravity_groups(self, groups, G: float = 1.0, theta: float = 0.5, quad: bool = True):
+        """FP64 tree force for the receivers of the given groups only (original indices;
+        other entries stay zero): (ax, ay, az, pot, n_pp, n_pc)."""
+        gsel = np.ascontiguousarray(groups, np.int64)
+        out = [np.zeros(self.n) for _ in range(4)]
+        npp = C.c_int64(0)
+        npc = C.c_int64(0)
+        lib().orc_tree_gravity_groups(self._h, G, theta, int(quad), gsel.size, _ptr(gsel),
+                                      *(_ptr(o) for o in out), C.byref(npp), C.byref(npc))
+        return (*out, npp.value, npc.value)
+
     def node_field(self, node: int, r, quad: bool = True):
         out = np.zeros(4)
         r = _f64(r)
@@ -206,8 +218,11 @@ def wendland_c4_dr(r: float, H: float) -> float:
 
 
 def sph_density(gas: dict, n_ngb: float = 64.0, tol: float = 1e-10, max_iter: int = 200,
-                idx=None, H_guess=None):
-    """Kernel size and density by safeguarded Newton.  Returns (H, rho, iters, n_fail)."""
+                idx=None, H_guess=None, with_slope=False):
+    """Kernel size and density by safeguarded Newton.
+
+    Returns (H, rho, iters, n_fail), plus dN_eff/dln H at the solution when
+    ``with_slope``."""
     x, y, z, m = (_f64(gas[k]) for k in ("x", "y", "z", "m"))
     n = x.size
     if idx is not None:
@@ -217,8 +232,12 @@ def sph_density(gas: dict, n_ngb: float = 64.0, tol: float = 1e-10, max_iter: in
     rho = np.zeros(k)
     it = np.zeros(k, np.int32)
     hg = None if H_guess is None else _f64(H_guess)
+    slope = np.zeros(k)
     nfail = lib().orc_sph_density(n, _ptr(x), _ptr(y), _ptr(z), _ptr(m), n_ngb, tol, max_iter,
-                                  k, _ptr(idx), _ptr(hg), _ptr(H), _ptr(rho), _ptr(it))
+                                  k, _ptr(idx), _ptr(hg), _ptr(H), _ptr(rho), _ptr(it),
+                                  _ptr(slope))
+    if with_slope:
+        return H, rho, it, int(nfail), slope
     return H, rho, it, int(nfail)
 
 

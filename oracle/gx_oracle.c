@@ -404,13 +404,17 @@ ORC_API void orc_tree_list_fill(const orc_tree* T, double theta, const int64_t* 
  *   a   += -G [M r / R^3 - Q r / R^5 + (5/2) (r.Q.r) r / R^7],
  * with r = r_i - s (s = centre of mass) and R^2 = |r|^2 + eps_i^2 + mean eps_c^2.
  * Results are written at original particle indices. */
-ORC_API void orc_tree_gravity(const orc_tree* T, double G, double theta, int quad, double* ax,
-                              double* ay, double* az, double* pot, int64_t* n_pp_out,
-                              int64_t* n_pc_out) {
+/* Gravity for the receivers of the listed groups (all groups when gsel is
+ * NULL); outputs at original indices.  Returns interaction counts. */
+static void tree_gravity_groups(const orc_tree* T, double G, double theta, int quad,
+                                int64_t ngs, const int64_t* gsel, double* ax, double* ay,
+                                double* az, double* pot, int64_t* n_pp_out, int64_t* n_pc_out) {
     double theta2 = theta * theta;
     int64_t tot_pp = 0, tot_pc = 0;
+    int64_t nsel = gsel ? ngs : T->ng;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : tot_pp, tot_pc)
-    for (int64_t g = 0; g < T->ng; g++) {
+    for (int64_t k = 0; k < nsel; k++) {
+        int64_t g = gsel ? gsel[k] : k;
         int64_t a, c, p;
         walk_group(T, g, theta2, &a, &c, &p, NULL, NULL);
         int64_t* leaves = malloc((a + 1) * sizeof(int64_t));
@@ -474,6 +478,27 @@ ORC_API void orc_tree_gravity(const orc_tree* T, double G, double theta, int qua
     }
     if (n_pp_out) *n_pp_out = tot_pp;
     if (n_pc_out) *n_pc_out = tot_pc;
+}
+
+/* Tree gravity in FP64: for each receiver in each group, the exact pair law
+ * over the particles of every listed leaf (self excluded), plus for every
+ * accepted cell the monopole and, when quad != 0, the quadrupole term
+ *   phi += -G [M/R + r.Q.r / (2 R^5)],
+ *   a   += -G [M r / R^3 - Q r / R^5 + (5/2) (r.Q.r) r / R^7],
+ * with r = r_i - s (s = centre of mass) and R^2 = |r|^2 + eps_i^2 + mean eps_c^2.
+ * Results are written at original particle indices. */
+ORC_API void orc_tree_gravity(const orc_tree* T, double G, double theta, int quad, double* ax,
+                              double* ay, double* az, double* pot, int64_t* n_pp_out,
+                              int64_t* n_pc_out) {
+    tree_gravity_groups(T, G, theta, quad, 0, NULL, ax, ay, az, pot, n_pp_out, n_pc_out);
+}
+
+/* The same for a subset of groups (a bounded sample of a large workload). */
+ORC_API void orc_tree_gravity_groups(const orc_tree* T, double G, double theta, int quad,
+                                     int64_t ngs, const int64_t* gsel, double* ax, double* ay,
+                                     double* az, double* pot, int64_t* n_pp_out,
+                                     int64_t* n_pc_out) {
+    tree_gravity_groups(T, G, theta, quad, ngs, gsel, ax, ay, az, pot, n_pp_out, n_pc_out);
 }
 
 /* Potential and acceleration at point r from one node's multipole expansion
@@ -582,11 +607,13 @@ static void neff_eval(const double* r, const double* mj, int64_t k, double mi, d
  * Root of N_eff(H) = n_ngb by Newton safeguarded with a bracket (bisection or
  * doubling when a step leaves it), until |N_eff - n_ngb| <= tol.
  * Hguess (per receiver slot, may be NULL or <= 0) seeds the iteration.
+ * dlnh_out (may be NULL) receives dN_eff/dln H at the returned H.
  * Returns the number of receivers that hit max_iter. */
 ORC_API int64_t orc_sph_density(int64_t n, const double* x, const double* y, const double* z,
                                 const double* m, double n_ngb, double tol, int max_iter,
                                 int64_t ni, const int64_t* idx, const double* Hguess,
-                                double* H_out, double* rho_out, int32_t* iters_out) {
+                                double* H_out, double* rho_out, int32_t* iters_out,
+                                double* dlnh_out) {
     orc_tree* T = orc_tree_build(n, x, y, z, m, NULL, 8, 64);
     int64_t* inv = malloc(n * sizeof(int64_t));
     for (int64_t s = 0; s < n; s++) inv[T->perm[s]] = s;
@@ -662,6 +689,7 @@ ORC_API int64_t orc_sph_density(int64_t n, const double* x, const double* y, con
             H_out[k] = H;
             rho_out[k] = rho;
             if (iters_out) iters_out[k] = ok ? it : max_iter;
+            if (dlnh_out) dlnh_out[k] = H * dneff; /* dN_eff / dln H at the solution */
         }
         free(cand);
         free(rr);

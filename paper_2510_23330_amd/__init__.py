@@ -1,0 +1,269 @@
+"""paper_2510_23330_amd -- Python binding of libgx, the MI355X interaction
+engine for the N-body/SPH galaxy integrator of arXiv 2510.23330.
+
+Everything here is argument marshalling: PyTorch provides device memory and
+the current HIP stream, and every step of the path runs in libgx's HIP
+kernels.  Function names follow the C ABI in include/gx.h without the
+``gx_`` prefix.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib
+from ._lib import (GX_DIRECT, GX_PREC_FP64, GX_QUAD, GX_TREE_ALL, GX_TREE_GAS, GxGas,
+                   GxParticles, GxStats)
+
+__all__ = ["Engine", "ParticleSet", "GasState", "GxError", "GX_QUAD", "GX_DIRECT",
+           "GX_PREC_FP64", "GX_TREE_ALL", "GX_TREE_GAS"]
+
+
+class GxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_lib.STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t, dtype=None):
+    if t is None:
+        return None
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("libgx takes device tensors")
+    if not t.is_contiguous():
+        raise ValueError("libgx takes contiguous tensors")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    return C.c_void_p(t.data_ptr())
+
+
+@dataclass
+class ParticleSet:
+    """Device structure-of-arrays particle view (torch tensors)."""
+    x: object
+    y: object
+    z: object
+    vx: object
+    vy: object
+    vz: object
+    m: object
+    eps2: object = None
+    id: object = None
+    type: object = None
+
+    @property
+    def n(self):
+        return int(self.x.shape[0])
+
+    @classmethod
+    def from_numpy(cls, d: dict, device="cuda", sl=slice(None)):
+        torch = _torch()
+        f64 = lambda k: torch.as_tensor(np.ascontiguousarray(d[k][sl], np.float64), device=device)
+        eps2 = d.get("eps2")
+        return cls(x=f64("x"), y=f64("y"), z=f64("z"), vx=f64("vx"), vy=f64("vy"), vz=f64("vz"),
+                   m=f64("m"),
+                   eps2=None if eps2 is None else torch.as_tensor(
+                       np.ascontiguousarray(eps2[sl], np.float32), device=device),
+                   id=None if "id" not in d else torch.as_tensor(
+                       np.ascontiguousarray(d["id"][sl], np.int64), device=device),
+                   type=None if "type" not in d else torch.as_tensor(
+                       np.ascontiguousarray(d["type"][sl], np.uint8), device=device))
+
+    def view(self, vel=None):
+        """ctypes gx_particles; ``vel`` optionally replaces (vx, vy, vz)."""
+        torch = _torch()
+        vx, vy, vz = vel if vel is not None else (self.vx, self.vy, self.vz)
+        s = GxParticles()
+        s.x, s.y, s.z = _ptr(self.x, torch.float64), _ptr(self.y, torch.float64), _ptr(self.z, torch.float64)
+        s.vx, s.vy, s.vz = _ptr(vx, torch.float64), _ptr(vy, torch.float64), _ptr(vz, torch.float64)
+        s.m = _ptr(self.m, torch.float64)
+        s.eps2 = _ptr(self.eps2, torch.float32)
+        s.id = _ptr(self.id, torch.int64)
+        s.type = _ptr(self.type, torch.uint8)
+        s.n = self.n
+        for t in (self.y, self.z, vx, vy, vz, self.m):
+            if t.shape[0] != s.n:
+                raise ValueError("particle arrays differ in length")
+        return s
+
+
+@dataclass
+class GasState:
+    """Device gas state (torch tensors), same order as the gas ParticleSet."""
+    u: object
+    dudt: object
+    H64: object
+    H: object
+    rho: object
+    P: object
+    cs: object
+    vsig: object
+
+    @classmethod
+    def zeros(cls, n, u=None, device="cuda"):
+        torch = _torch()
+        z64 = lambda: torch.zeros(n, dtype=torch.float64, device=device)
+        z32 = lambda: torch.zeros(n, dtype=torch.float32, device=device)
+        uu = z64() if u is None else torch.as_tensor(np.ascontiguousarray(u, np.float64), device=device)
+        return cls(u=uu, dudt=z64(), H64=z64(), H=z32(), rho=z32(), P=z32(), cs=z32(), vsig=z32())
+
+    def view(self, u=None):
+        torch = _torch()
+        g = GxGas()
+        g.u = _ptr(self.u if u is None else u, torch.float64)
+        g.dudt = _ptr(self.dudt, torch.float64)
+        g.H64 = _ptr(self.H64, torch.float64)
+        g.H, g.rho, g.P = (_ptr(t, torch.float32) for t in (self.H, self.rho, self.P))
+        g.cs, g.vsig = _ptr(self.cs, torch.float32), _ptr(self.vsig, torch.float32)
+        g.n = int(self.u.shape[0])
+        return g
+
+
+class Engine:
+    """One libgx context bound to a device and (by default) torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        self.lib = _lib.load()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._stream = stream
+        h = C.c_void_p()
+        self._check(self.lib.gx_create(C.byref(h), device, C.c_void_p(stream.cuda_stream)), None)
+        self.ctx = h
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.gx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, ctx="self", allow=()):
+        if rc != 0 and rc not in allow:
+            c = self.ctx if ctx == "self" else None
+            msg = self.lib.gx_last_error(c).decode() if c else ""
+            raise GxError(rc, msg)
+        return rc
+
+    def set_stream(self, stream):
+        self._stream = stream
+        self._check(self.lib.gx_set_stream(self.ctx, C.c_void_p(stream.cuda_stream)))
+
+    # ---- hot path ----------------------------------------------------------
+    def tree_build(self, p: ParticleSet, which=GX_TREE_ALL, n_leaf=16, n_group=256, perm_out=None,
+                   vel=None):
+        st = GxStats()
+        v = p.view(vel)
+        self._check(self.lib.gx_tree_build(self.ctx, C.byref(v), which, n_leaf, n_group,
+                                           _ptr(perm_out), C.byref(st)))
+        return st.as_dict()
+
+    def gravity_forces(self, p: ParticleSet, G, theta, flags, ax, ay, az, pot, stats=True):
+        st = GxStats()
+        v = p.view()
+        self._check(self.lib.gx_gravity_forces(self.ctx, C.byref(v), float(G), float(theta),
+                                               int(flags), _ptr(ax), _ptr(ay), _ptr(az),
+                                               _ptr(pot), C.byref(st) if stats else None))
+        return st.as_dict() if stats else None
+
+    def sph_density(self, gas: ParticleSet, g: GasState, n_ngb=64.0, gamma=5.0 / 3.0, tol=1e-3,
+                    max_iter=64, stats=True, allow_noconv=False, u=None):
+        st = GxStats()
+        v = gas.view()
+        gv = g.view(u)
+        rc = self._check(self.lib.gx_sph_density(self.ctx, C.byref(v), C.byref(gv), float(n_ngb),
+                                                 float(gamma), float(tol), int(max_iter),
+                                                 C.byref(st) if stats else None),
+                         allow=(_lib.GX_ENOCONV,) if allow_noconv else ())
+        d = st.as_dict() if stats else {}
+        d["status"] = rc
+        return d
+
+    def sph_forces(self, gas: ParticleSet, g: GasState, ax, ay, az, gamma=5.0 / 3.0, alpha=1.0,
+                   vel=None, u=None, stats=True):
+        st = GxStats()
+        v = gas.view(vel)
+        gv = g.view(u)
+        self._check(self.lib.gx_sph_forces(self.ctx, C.byref(v), C.byref(gv), float(gamma),
+                                           float(alpha), _ptr(ax), _ptr(ay), _ptr(az),
+                                           C.byref(st) if stats else None))
+        return st.as_dict() if stats else None
+
+    def kick_drift(self, p: ParticleSet, dt_kick, dt_drift, ax, ay, az, u=None, dudt=None,
+                   u_floor=0.0, vpred=None, upred=None):
+        n_u = 0 if u is None else int(u.shape[0])
+        self._check(self.lib.gx_kick_drift(self.ctx, p.n, float(dt_kick), float(dt_drift),
+                                           _ptr(p.x), _ptr(p.y), _ptr(p.z), _ptr(p.vx),
+                                           _ptr(p.vy), _ptr(p.vz), _ptr(ax), _ptr(ay), _ptr(az),
+                                           n_u, _ptr(u), _ptr(dudt), float(u_floor), _ptr(vpred),
+                                           _ptr(upred)))
+
+    def energy(self, p: ParticleSet, pot, m_gas=None, u=None):
+        out = (C.c_double * 3)()
+        n_gas = 0 if u is None else int(u.shape[0])
+        self._check(self.lib.gx_energy(self.ctx, C.byref(p.view()), _ptr(pot), n_gas,
+                                       _ptr(m_gas), _ptr(u), out))
+        return tuple(out)
+
+    def sph_timestep(self, g: GasState, c_cfl, dt_out, cube_id=None, n_cubes=1):
+        gv = g.view()
+        self._check(self.lib.gx_sph_timestep(self.ctx, C.byref(gv), float(c_cfl), _ptr(cube_id),
+                                             int(n_cubes), _ptr(dt_out)))
+
+    # ---- inspection ----------------------------------------------------------
+    def tree_counts(self, which=GX_TREE_ALL):
+        nn, ng = C.c_int64(), C.c_int64()
+        self._check(self.lib.gx_tree_counts(self.ctx, which, C.byref(nn), C.byref(ng)))
+        return nn.value, ng.value
+
+    def tree_export(self, which=GX_TREE_ALL, n=None):
+        nn, ng = self.tree_counts(which)
+        if n is None:
+            raise ValueError("pass n (particle count)")
+        o = dict(keys=np.zeros(n, np.uint64), perm=np.zeros(n, np.int32), box=np.zeros(4),
+                 begin=np.zeros(nn, np.int32), end=np.zeros(nn, np.int32),
+                 next=np.zeros(nn, np.int32), level=np.zeros(nn, np.int32),
+                 leaf=np.zeros(nn, np.int8), mass=np.zeros(nn), com=np.zeros((nn, 3)),
+                 quad=np.zeros((nn, 6), np.float32), eps2bar=np.zeros(nn, np.float32),
+                 lo=np.zeros((nn, 3)), hi=np.zeros((nn, 3)), groups=np.zeros(ng, np.int32))
+        pp = lambda a: a.ctypes.data_as(C.c_void_p)
+        self._check(self.lib.gx_tree_export(self.ctx, which, *(pp(o[k]) for k in (
+            "keys", "perm", "box", "begin", "end", "next", "level", "leaf", "mass", "com", "quad",
+            "eps2bar", "lo", "hi", "groups"))))
+        return o
+
+    def gravity_lists(self):
+        ng, npc, npr = C.c_int64(), C.c_int64(), C.c_int64()
+        self._check(self.lib.gx_gravity_list_sizes(self.ctx, C.byref(ng), C.byref(npc), C.byref(npr)))
+        o = dict(pc_off=np.zeros(ng.value + 1, np.int64), pc=np.zeros(max(1, npc.value), np.int32),
+                 pp_off=np.zeros(ng.value + 1, np.int64),
+                 pp_begin=np.zeros(max(1, npr.value), np.int32),
+                 pp_end=np.zeros(max(1, npr.value), np.int32))
+        pp = lambda a: a.ctypes.data_as(C.c_void_p)
+        self._check(self.lib.gx_gravity_list_export(self.ctx, pp(o["pc_off"]), pp(o["pc"]),
+                                                    pp(o["pp_off"]), pp(o["pp_begin"]),
+                                                    pp(o["pp_end"])))
+        o["pc"] = o["pc"][:npc.value]
+        o["pp_begin"] = o["pp_begin"][:npr.value]
+        o["pp_end"] = o["pp_end"][:npr.value]
+        return o
+
+
+def version() -> str:
+    return _lib.load().gx_version().decode()

@@ -1,0 +1,187 @@
+// gx_internal.hpp -- context, scratch buffers and device primitives shared by
+// the libgx translation units (HIP C++ for gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "gx.h"
+
+#define GX_MAX_LEVEL 21
+#define GX_WAVE 64
+
+// ---------------------------------------------------------------------------
+// Tree records (device, 64-byte aligned so one node visit is one cache line)
+// ---------------------------------------------------------------------------
+struct alignas(64) NodeRec {
+    double lo[3];
+    double hi[3];
+    int32_t next;   // pre-order id of the first node after this subtree
+    int32_t begin;  // sorted-slot range [begin, end)
+    int32_t end;
+    int16_t level;
+    int8_t leaf;
+    int8_t pad;
+};
+
+// Multipole record read by the force kernel: FP64 centre of mass and mass,
+// FP32 traceless quadrupole (xx, yy, zz, xy, xz, yz) and mean eps^2.
+struct alignas(64) MomRec {
+    double cx, cy, cz, M;
+    float q[6];
+    float e2;
+    float hmax;  // SPH: largest kernel size among the node's particles
+};
+
+struct Buf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+struct TreeSlot {
+    int built = 0;
+    const double* x = nullptr;
+    const double* y = nullptr;
+    const double* z = nullptr;
+    int64_t n = 0;
+    int n_leaf = 0, n_group = 0;
+    Buf key[2], val[2];  // radix sort ping-pong (u64 keys, u32 slots)
+    Buf pos4;            // double4 {x, y, z, m} in sorted order
+    Buf e2s;             // float eps^2 in sorted order
+    Buf win, cnt, lmax;  // node-count construction scratch
+    Buf nodes, mom, q64, parent, lvl_ids, lvl_fill, flag;
+    Buf groups;          // int32 node id of each group (pre-order)
+    Buf box;             // double[8]: x0, y0, z0, L, 2^21/L, min eps^2
+    int64_t n_nodes = 0, n_groups = 0;
+    int64_t lvl_hist[GX_MAX_LEVEL + 1] = {};
+    int32_t* perm() const { return (int32_t*)val[0].p; }
+    const uint64_t* keys() const { return (const uint64_t*)key[0].p; }
+};
+
+struct ListSet {  // per-group interaction lists (CSR)
+    Buf pc_cnt, pc_off, pc_list;
+    Buf pr_cnt, pr_off, pr_begin, pr_cum, pp_tot;
+    Buf tot;  // device counters: [0] n_pc entries, [1] n_ranges, [2] n_pp inter, [3] n_pc inter
+    int64_t n_groups = 0, n_pc = 0, n_ranges = 0;
+};
+
+struct gx_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    TreeSlot tree[2];
+    ListSet grav, sph;
+    Buf scan_tmp[3], hist, partial, small, host_small;
+    Buf sph_work[16];
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+};
+
+// ---------------------------------------------------------------------------
+// Host helpers
+// ---------------------------------------------------------------------------
+int gx_fail(gx_ctx* ctx, int code, const char* fmt, ...);
+int gx_reserve(gx_ctx* ctx, Buf& b, size_t bytes);
+// Zero `bytes` (rounded up to 4) of device memory on the context stream.
+int gx_zero(gx_ctx* ctx, void* p, size_t bytes);
+
+#define GX_HIP(ctx, call)                                                               \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return gx_fail((ctx), GX_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define GX_TRY(expr)              \
+    do {                          \
+        int r_ = (expr);          \
+        if (r_ != GX_OK) return r_; \
+    } while (0)
+
+#define GX_LAUNCH_CHECK(ctx) GX_HIP(ctx, hipGetLastError())
+
+static inline unsigned gx_blocks(int64_t n, int threads) {
+    return (unsigned)((n + threads - 1) / threads);
+}
+
+// Exclusive scan of n elements (device), total written to device *total
+// (may be NULL).  Types: uint32_t -> uint32_t, uint32_t -> int64_t.
+template <typename TI, typename TO>
+int gx_scan(gx_ctx* ctx, const TI* in, TO* out, int64_t n, TO* total);
+
+// Stable LSD radix sort of (u64 key, u32 value) pairs; result in slot 0.
+int gx_radix_sort(gx_ctx* ctx, TreeSlot& T, int64_t n, int key_bits);
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int gx_lane() { return (int)__lane_id(); }
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+#pragma unroll
+    for (int o = 1; o < GX_WAVE; o <<= 1) {
+        T t = __shfl_up(v, o, GX_WAVE);
+        if (gx_lane() >= o) v += t;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = GX_WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, GX_WAVE);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+    for (int o = GX_WAVE / 2; o > 0; o >>= 1) {
+        T t = __shfl_xor(v, o, GX_WAVE);
+        v = t < v ? t : v;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+    for (int o = GX_WAVE / 2; o > 0; o >>= 1) {
+        T t = __shfl_xor(v, o, GX_WAVE);
+        v = t > v ? t : v;
+    }
+    return v;
+}
+
+// Block-wide exclusive scan for blockDim.x == 256 (4 waves).  Returns the
+// exclusive prefix of v; *block_total receives the sum.  Uses 4 shared slots.
+template <typename T>
+__device__ __forceinline__ T block_excl_scan256(T v, T* sh4, T* block_total) {
+    T inc = wave_incl_scan(v);
+    int w = threadIdx.x / GX_WAVE;
+    if (gx_lane() == GX_WAVE - 1) sh4[w] = inc;
+    __syncthreads();
+    T off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        T s = sh4[k];
+        if (k < w) off += s;
+        tot += s;
+    }
+    __syncthreads();
+    *block_total = tot;
+    return off + inc - v;
+}
+
+// Map a linear block index to a work item so that each of the 8 XCDs (which
+// receive blocks round-robin) works on one contiguous eighth of the items:
+// neighbouring groups share tree nodes and then share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int n_items) {
+    int per = (n_items + 7) / 8;
+    return (b % 8) * per + b / 8;
+}
+static inline unsigned xcd_grid(int64_t n_items) { return (unsigned)(8 * ((n_items + 7) / 8)); }

@@ -1,0 +1,313 @@
+// gx_prims.hip -- context management, device-wide exclusive scan and the
+// stable LSD radix sort of (63-bit Morton key, slot) pairs.
+#include "gx_internal.hpp"
+
+#include <cstdlib>
+#include <cstring>
+#include <utility>
+
+// ---------------------------------------------------------------------------
+// Errors and scratch
+// ---------------------------------------------------------------------------
+int gx_fail(gx_ctx* ctx, int code, const char* fmt, ...) {
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return code;
+}
+
+int gx_reserve(gx_ctx* ctx, Buf& b, size_t bytes) {
+    if (bytes <= b.cap) return GX_OK;
+    size_t want = bytes + bytes / 4 + 256;
+    if (b.p) {
+        // grow-only: the old contents are not preserved
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return gx_fail(ctx, GX_EHIP, "sync before realloc: %s", hipGetErrorString(e));
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return gx_fail(ctx, GX_ENOMEM, "hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
+    }
+    b.p = p;
+    b.cap = want;
+    return GX_OK;
+}
+
+static void free_buf(Buf& b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+// Zero device memory with a fill kernel (no memset nodes, so callers may
+// capture the stream into a graph).
+__global__ void k_zero_words(uint32_t* p, int64_t nw) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nw) p[i] = 0u;
+}
+
+int gx_zero(gx_ctx* ctx, void* p, size_t bytes) {
+    int64_t nw = (int64_t)((bytes + 3) / 4);
+    if (nw == 0) return GX_OK;
+    hipLaunchKernelGGL(k_zero_words, dim3(gx_blocks(nw, 256)), dim3(256), 0, ctx->stream,
+                       (uint32_t*)p, nw);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+extern "C" int gx_create(gx_ctx** out, int device, void* hip_stream) {
+    if (!out) return GX_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        (void)hipGetLastError();
+        return GX_EINVAL;
+    }
+    if (hipSetDevice(device) != hipSuccess) return GX_EHIP;
+    gx_ctx* c = new gx_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+        hipEventCreate(&c->ev2) != hipSuccess || hipEventCreate(&c->ev3) != hipSuccess) {
+        delete c;
+        return GX_EHIP;
+    }
+    *out = c;
+    return GX_OK;
+}
+
+extern "C" int gx_destroy(gx_ctx* ctx) {
+    if (!ctx) return GX_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& T : ctx->tree) {
+        for (auto* b : {&T.key[0], &T.key[1], &T.val[0], &T.val[1], &T.pos4, &T.e2s, &T.win,
+                        &T.cnt, &T.lmax, &T.nodes, &T.mom, &T.q64, &T.parent, &T.lvl_ids,
+                        &T.lvl_fill, &T.flag, &T.groups, &T.box})
+            free_buf(*b);
+    }
+    for (auto* L : {&ctx->grav, &ctx->sph})
+        for (auto* b : {&L->pc_cnt, &L->pc_off, &L->pc_list, &L->pr_cnt, &L->pr_off, &L->pr_begin,
+                        &L->pr_cum, &L->pp_tot, &L->tot})
+            free_buf(*b);
+    for (auto& b : ctx->scan_tmp) free_buf(b);
+    for (auto& b : ctx->sph_work) free_buf(b);
+    free_buf(ctx->hist);
+    free_buf(ctx->partial);
+    free_buf(ctx->small);
+    if (ctx->host_small.p) (void)hipHostFree(ctx->host_small.p);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->ev2) (void)hipEventDestroy(ctx->ev2);
+    if (ctx->ev3) (void)hipEventDestroy(ctx->ev3);
+    delete ctx;
+    return GX_OK;
+}
+
+extern "C" int gx_set_stream(gx_ctx* ctx, void* hip_stream) {
+    if (!ctx) return GX_EINVAL;
+    ctx->stream = (hipStream_t)hip_stream;
+    return GX_OK;
+}
+
+extern "C" const char* gx_last_error(const gx_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : "null context";
+}
+
+extern "C" const char* gx_version(void) {
+    return "libgx gfx950 wave64";
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan: 3 phases (per-block scan of 1024 items, scan of block sums
+// by one block, add block offsets).
+// ---------------------------------------------------------------------------
+#define SCAN_ITEMS 4
+#define SCAN_TILE (256 * SCAN_ITEMS)
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_scan_tile(const TI* in, TO* out, TO* __restrict__ bsum,
+                                                   int64_t n) {
+    __shared__ TO sh[4];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    TO v[SCAN_ITEMS];
+    TO s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        v[k] = (base + k < n) ? (TO)in[base + k] : (TO)0;
+        s += v[k];
+    }
+    TO tot;
+    TO off = block_excl_scan256<TO>(s, sh, &tot);
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        if (base + k < n) out[base + k] = off;
+        off += v[k];
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+template <typename TO>
+__global__ __launch_bounds__(256) void k_scan_sums(TO* __restrict__ bsum, int64_t nb,
+                                                   TO* __restrict__ total) {
+    __shared__ TO sh[4];
+    TO carry = 0;
+    for (int64_t c = 0; c < nb; c += 256) {
+        int64_t i = c + threadIdx.x;
+        TO v = i < nb ? bsum[i] : (TO)0;
+        TO tot;
+        TO off = block_excl_scan256<TO>(v, sh, &tot);
+        if (i < nb) bsum[i] = carry + off;
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+template <typename TO>
+__global__ __launch_bounds__(256) void k_scan_add(TO* __restrict__ out, const TO* __restrict__ bsum,
+                                                  int64_t n) {
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    TO add = bsum[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; k++)
+        if (base + k < n) out[base + k] += add;
+}
+
+template <typename TI, typename TO>
+int gx_scan(gx_ctx* ctx, const TI* in, TO* out, int64_t n, TO* total) {
+    if (n <= 0) {
+        if (total) GX_TRY(gx_zero(ctx, total, sizeof(TO)));
+        return GX_OK;
+    }
+    int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    GX_TRY(gx_reserve(ctx, ctx->scan_tmp[0], nb * sizeof(TO)));
+    TO* bsum = (TO*)ctx->scan_tmp[0].p;
+    hipLaunchKernelGGL((k_scan_tile<TI, TO>), dim3((unsigned)nb), dim3(256), 0, ctx->stream, in, out,
+                       bsum, n);
+    hipLaunchKernelGGL((k_scan_sums<TO>), dim3(1), dim3(256), 0, ctx->stream, bsum, nb, total);
+    hipLaunchKernelGGL((k_scan_add<TO>), dim3((unsigned)nb), dim3(256), 0, ctx->stream, out, bsum, n);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+template int gx_scan<uint32_t, uint32_t>(gx_ctx*, const uint32_t*, uint32_t*, int64_t, uint32_t*);
+template int gx_scan<uint32_t, int64_t>(gx_ctx*, const uint32_t*, int64_t*, int64_t, int64_t*);
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort, 8-bit digits.  Per pass: block histograms (digit-
+// major layout so one exclusive scan gives every (digit, block) offset), then
+// a scatter in which each block ranks its tile stably: items are taken in
+// rounds of 256 (round-major, then thread order), ranked within each wave by
+// ballot matching on the 8 digit bits, and across waves and rounds through
+// per-digit counters in LDS.
+// ---------------------------------------------------------------------------
+#define RS_ITEMS 16
+#define RS_TILE (256 * RS_ITEMS)
+
+__global__ __launch_bounds__(256) void k_rs_hist(const uint64_t* __restrict__ key, int64_t n,
+                                                 int shift, uint32_t* __restrict__ hist, int nblk) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+#pragma unroll 4
+    for (int r = 0; r < RS_ITEMS; r++) {
+        int64_t i = base + r * 256 + threadIdx.x;
+        if (i < n) atomicAdd(&h[(key[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_rs_scatter(const uint64_t* __restrict__ kin,
+                                                    const uint32_t* __restrict__ vin,
+                                                    uint64_t* __restrict__ kout,
+                                                    uint32_t* __restrict__ vout, int64_t n, int shift,
+                                                    const uint32_t* __restrict__ off, int nblk) {
+    __shared__ uint32_t running[256];
+    __shared__ uint32_t wcnt[2][4][256];
+    __shared__ uint32_t boff[256];
+    const int t = threadIdx.x, w = t / GX_WAVE, lane = gx_lane();
+    running[t] = 0;
+    boff[t] = off[(int64_t)t * nblk + blockIdx.x];
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ITEMS; r++) {
+        uint32_t(*wc)[256] = wcnt[r & 1];
+#pragma unroll
+        for (int k = 0; k < 4; k++) wc[k][t] = 0;
+        __syncthreads();
+        int64_t i = base + r * 256 + t;
+        bool valid = i < n;
+        uint64_t k = valid ? kin[i] : 0;
+        uint32_t v = valid ? vin[i] : 0;
+        uint32_t d = (uint32_t)(k >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            bool bit = (d >> b) & 1u;
+            uint64_t bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        uint32_t rank = (uint32_t)__popcll(peers & lt);
+        if (valid && (peers >> lane) == 1ull) wc[w][d] = (uint32_t)__popcll(peers);  // last peer
+        __syncthreads();
+        {
+            uint32_t c0 = wc[0][t], c1 = wc[1][t], c2 = wc[2][t], c3 = wc[3][t];
+            uint32_t run = running[t];
+            wc[0][t] = run;
+            wc[1][t] = run + c0;
+            wc[2][t] = run + c0 + c1;
+            wc[3][t] = run + c0 + c1 + c2;
+            running[t] = run + c0 + c1 + c2 + c3;
+        }
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = boff[d] + wc[w][d] + rank;
+            kout[pos] = k;
+            vout[pos] = v;
+        }
+    }
+}
+
+__global__ void k_iota(uint32_t* v, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = (uint32_t)i;
+}
+
+int gx_radix_sort(gx_ctx* ctx, TreeSlot& T, int64_t n, int key_bits) {
+    int nblk = (int)((n + RS_TILE - 1) / RS_TILE);
+    int64_t nh = (int64_t)256 * nblk;
+    GX_TRY(gx_reserve(ctx, ctx->hist, nh * sizeof(uint32_t)));
+    uint32_t* hist = (uint32_t*)ctx->hist.p;
+    int npass = (key_bits + 7) / 8;
+    int cur = 0;
+    for (int p = 0; p < npass; p++) {
+        int shift = 8 * p;
+        uint64_t* kin = (uint64_t*)T.key[cur].p;
+        uint32_t* vin = (uint32_t*)T.val[cur].p;
+        uint64_t* kout = (uint64_t*)T.key[cur ^ 1].p;
+        uint32_t* vout = (uint32_t*)T.val[cur ^ 1].p;
+        hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(256), 0, ctx->stream, kin, n, shift, hist, nblk);
+        GX_TRY((gx_scan<uint32_t, uint32_t>(ctx, hist, hist, nh, nullptr)));
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(256), 0, ctx->stream, kin, vin, kout, vout,
+                           n, shift, hist, nblk);
+        GX_LAUNCH_CHECK(ctx);
+        cur ^= 1;
+    }
+    if (cur != 0) {  // leave the result in slot 0
+        std::swap(T.key[0], T.key[1]);
+        std::swap(T.val[0], T.val[1]);
+    }
+    return GX_OK;
+}

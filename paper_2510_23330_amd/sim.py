@@ -1,0 +1,116 @@
+"""Shared-timestep leapfrog step of the N-body/SPH integrator on the device.
+
+One step follows Sec. 3.2: half kick and drift of every particle (predicting
+the gas velocity and internal energy at the drifted positions), force
+evaluation (tree gravity on all particles, then SPH kernel size, density and
+hydro force on the gas), second half kick, and the FP64 energy audit.  Every
+arithmetic step runs in libgx; this module only sequences the calls.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+from . import GX_QUAD, GX_TREE_ALL, GX_TREE_GAS, Engine, GasState, ParticleSet
+
+
+def _slice(p: ParticleSet, a: int, b: int) -> ParticleSet:
+    s = lambda t: None if t is None else t[a:b]
+    return ParticleSet(x=p.x[a:b], y=p.y[a:b], z=p.z[a:b], vx=p.vx[a:b], vy=p.vy[a:b],
+                       vz=p.vz[a:b], m=p.m[a:b], eps2=s(p.eps2), id=s(p.id), type=s(p.type))
+
+
+@dataclass
+class StepConfig:
+    G: float
+    dt: float
+    theta: float = 0.5
+    quad: bool = True
+    n_leaf: int = 16
+    n_group: int = 256
+    sph_leaf: int = 8
+    sph_group: int = 64
+    n_ngb: float = 64.0
+    gamma: float = 5.0 / 3.0
+    alpha: float = 1.0
+    h_tol: float = 1e-3
+    max_iter: int = 64
+    u_floor: float = 0.0
+
+
+@dataclass
+class GalaxyStep:
+    """Particles (gas as the contiguous tail [gas_offset, n)) and step buffers."""
+    eng: Engine
+    p: ParticleSet
+    gas_offset: int
+    u: object
+    cfg: StepConfig
+    stats: dict = field(default_factory=dict)
+
+    def __post_init__(self):
+        import torch
+        n, o = self.p.n, self.gas_offset
+        ng = n - o
+        dev = self.p.x.device
+        z64 = lambda k: torch.zeros(k, dtype=torch.float64, device=dev)
+        self.ax, self.ay, self.az, self.pot = z64(n), z64(n), z64(n), z64(n)
+        self.stars = _slice(self.p, 0, o)
+        self.gas = _slice(self.p, o, n)
+        self.g = GasState.zeros(ng, device=dev)
+        self.g.u = self.u
+        self.vpred = z64(3 * ng)
+        self.upred = z64(ng)
+        self.ng = ng
+
+    def _acc(self, a, b):
+        return self.ax[a:b], self.ay[a:b], self.az[a:b]
+
+    def forces(self, predicted: bool = True):
+        """Gravity on all particles, then SPH on the gas (accelerations added)."""
+        c, s = self.cfg, self.stats
+        s["tree_all"] = self.eng.tree_build(self.p, GX_TREE_ALL, c.n_leaf, c.n_group)
+        s["gravity"] = self.eng.gravity_forces(self.p, c.G, c.theta, GX_QUAD if c.quad else 0,
+                                               self.ax, self.ay, self.az, self.pot)
+        if self.ng == 0:
+            return
+        s["tree_gas"] = self.eng.tree_build(self.gas, GX_TREE_GAS, c.sph_leaf, c.sph_group)
+        ng = self.ng
+        if predicted:
+            vel = (self.vpred[:ng], self.vpred[ng:2 * ng], self.vpred[2 * ng:])
+            u = self.upred
+        else:
+            vel, u = None, None
+        gas_view = self.gas if vel is None else ParticleSet(
+            x=self.gas.x, y=self.gas.y, z=self.gas.z, vx=vel[0], vy=vel[1], vz=vel[2],
+            m=self.gas.m, eps2=self.gas.eps2)
+        s["density"] = self.eng.sph_density(gas_view, self.g, c.n_ngb, c.gamma, c.h_tol,
+                                            c.max_iter, u=u)
+        s["hydro"] = self.eng.sph_forces(gas_view, self.g, *self._acc(self.gas_offset, self.p.n),
+                                         gamma=c.gamma, alpha=c.alpha, u=u)
+
+    def initial_forces(self):
+        self.forces(predicted=False)
+
+    def step(self):
+        c, o, n = self.cfg, self.gas_offset, self.p.n
+        dt = c.dt
+        # (1) half kick + (2) drift; gas also predicts v and u at the drifted positions
+        if o > 0:
+            self.eng.kick_drift(self.stars, dt / 2, dt, *self._acc(0, o))
+        if self.ng:
+            self.eng.kick_drift(self.gas, dt / 2, dt, *self._acc(o, n), u=self.g.u,
+                                dudt=self.g.dudt, u_floor=c.u_floor, vpred=self.vpred,
+                                upred=self.upred)
+        # (3) forces
+        self.forces(predicted=True)
+        # (4) second half kick
+        if o > 0:
+            self.eng.kick_drift(self.stars, dt / 2, 0.0, *self._acc(0, o))
+        if self.ng:
+            self.eng.kick_drift(self.gas, dt / 2, 0.0, *self._acc(o, n), u=self.g.u,
+                                dudt=self.g.dudt, u_floor=c.u_floor)
+        return self.stats
+
+    def energy(self):
+        m_gas = self.gas.m if self.ng else None
+        return self.eng.energy(self.p, self.pot, m_gas, self.g.u if self.ng else None)
