@@ -47,6 +47,11 @@ __device__ __forceinline__ double pair_rsqrt<double>(double x) {
     return 1.0 / sqrt(x);
 }
 
+template <typename T>
+struct alignas(4 * sizeof(T)) V4 {
+    T x, y, z, w;
+};
+
 template <typename T, bool QUAD>
 __global__ __launch_bounds__(GF_THREADS) void k_grav_force(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes,
@@ -59,8 +64,10 @@ __global__ __launch_bounds__(GF_THREADS) void k_grav_force(
     const int g = xcd_remap(blockIdx.x, ng);
     if (g >= ng) return;
     __shared__ int32_t jidx[GF_CH];
-    __shared__ T sx[GF_TILE], sy[GF_TILE], sz[GF_TILE], sm[GF_TILE], se[GF_TILE];
-    __shared__ T sq[QUAD ? 6 : 1][QUAD ? GF_TILE : 1];
+    // source tiles: A = (x, y, z, m) group-relative; B = (eps^2, qxx, qyy, qzz);
+    // C = (qxy, qxz, qyz, -)
+    __shared__ V4<T> sA[GF_TILE], sB[GF_TILE];
+    __shared__ V4<T> sC[QUAD ? GF_TILE : 1];
     __shared__ double red[4][GF_THREADS];
 
     const int tid = threadIdx.x;
@@ -69,7 +76,8 @@ __global__ __launch_bounds__(GF_THREADS) void k_grav_force(
     const double cx = (gn.lo[0] + gn.hi[0]) * 0.5;
     const double cy = (gn.lo[1] + gn.hi[1]) * 0.5;
     const double cz = (gn.lo[2] + gn.hi[2]) * 0.5;
-    int pad = 64;
+    // slices: pad lanes hold the receivers once; 256 / pad slices split each tile
+    int pad = 32;
     while (pad < nG && pad < GF_THREADS) pad <<= 1;
     const int nsl = GF_THREADS / pad, il = tid % pad, sl = tid / pad;
     const int npp = (int)pp_tot[g];
@@ -107,11 +115,8 @@ __global__ __launch_bounds__(GF_THREADS) void k_grav_force(
                 if (tid < tn) {
                     const int j = jidx[t0 - ch + tid];
                     const double4 p = pos4[j];
-                    sx[tid] = (T)(p.x - cx);
-                    sy[tid] = (T)(p.y - cy);
-                    sz[tid] = (T)(p.z - cz);
-                    sm[tid] = (T)p.w;
-                    se[tid] = (T)e2s[j];
+                    sA[tid] = V4<T>{(T)(p.x - cx), (T)(p.y - cy), (T)(p.z - cz), (T)p.w};
+                    sB[tid].x = (T)e2s[j];
                 }
                 __syncthreads();
                 if (act) {
@@ -120,10 +125,11 @@ __global__ __launch_bounds__(GF_THREADS) void k_grav_force(
                     const int jb = sl * per, je = min(tn, jb + per);
 #pragma unroll 4
                     for (int jj = jb; jj < je; jj++) {
-                        const T dx = sx[jj] - xi, dy = sy[jj] - yi, dz = sz[jj] - zi;
-                        const T r2 = dx * dx + dy * dy + dz * dz + (ei + se[jj]);
+                        const V4<T> a = sA[jj];
+                        const T dx = a.x - xi, dy = a.y - yi, dz = a.z - zi;
+                        const T r2 = dx * dx + dy * dy + dz * dz + (ei + sB[jj].x);
                         const T rinv = pair_rsqrt<T>(r2);
-                        const T mr = sm[jj] * rinv;
+                        const T mr = a.w * rinv;
                         const T mr3 = mr * rinv * rinv;
                         fx += mr3 * dx;
                         fy += mr3 * dy;
@@ -144,14 +150,12 @@ __global__ __launch_bounds__(GF_THREADS) void k_grav_force(
             const int tn = (int)min((int64_t)GF_TILE, c1 - t0);
             if (tid < tn) {
                 const MomRec mr = mom[pc_list[t0 + tid]];
-                sx[tid] = (T)(mr.cx - cx);
-                sy[tid] = (T)(mr.cy - cy);
-                sz[tid] = (T)(mr.cz - cz);
-                sm[tid] = (T)mr.M;
-                se[tid] = (T)mr.e2;
+                sA[tid] = V4<T>{(T)(mr.cx - cx), (T)(mr.cy - cy), (T)(mr.cz - cz), (T)mr.M};
                 if (QUAD) {
-#pragma unroll
-                    for (int c = 0; c < 6; c++) sq[c][tid] = (T)mr.q[c];
+                    sB[tid] = V4<T>{(T)mr.e2, (T)mr.q[0], (T)mr.q[1], (T)mr.q[2]};
+                    sC[tid] = V4<T>{(T)mr.q[3], (T)mr.q[4], (T)mr.q[5], (T)0};
+                } else {
+                    sB[tid].x = (T)mr.e2;
                 }
             }
             __syncthreads();
@@ -161,27 +165,28 @@ __global__ __launch_bounds__(GF_THREADS) void k_grav_force(
                 const int jb = sl * per, je = min(tn, jb + per);
 #pragma unroll 2
                 for (int jj = jb; jj < je; jj++) {
-                    const T dx = sx[jj] - xi, dy = sy[jj] - yi, dz = sz[jj] - zi;
-                    const T R2 = dx * dx + dy * dy + dz * dz + (ei + se[jj]);
+                    const V4<T> a = sA[jj];
+                    const V4<T> b = sB[jj];
+                    const T dx = a.x - xi, dy = a.y - yi, dz = a.z - zi;
+                    const T R2 = dx * dx + dy * dy + dz * dz + (ei + b.x);
                     const T Rinv = pair_rsqrt<T>(R2);
                     const T Rinv2 = Rinv * Rinv;
-                    const T M = sm[jj];
-                    const T MR3 = M * Rinv * Rinv2;
+                    const T M = a.w;
+                    const T Rinv3 = Rinv * Rinv2;
+                    const T MR3 = M * Rinv3;
                     if (QUAD) {
-                        const T qxx = sq[0][jj], qyy = sq[1][jj], qzz = sq[2][jj];
-                        const T qxy = sq[3][jj], qxz = sq[4][jj], qyz = sq[5][jj];
-                        const T qdx = qxx * dx + qxy * dy + qxz * dz;
-                        const T qdy = qxy * dx + qyy * dy + qyz * dz;
-                        const T qdz = qxz * dx + qyz * dy + qzz * dz;
+                        const V4<T> c = sC[jj];
+                        const T qdx = b.y * dx + c.x * dy + c.y * dz;
+                        const T qdy = c.x * dx + b.z * dy + c.z * dz;
+                        const T qdz = c.y * dx + c.z * dy + b.w * dz;
                         const T dqd = dx * qdx + dy * qdy + dz * qdz;
-                        const T Rinv3 = Rinv * Rinv2;
                         const T Rinv5 = Rinv3 * Rinv2;
-                        const T Rinv7 = Rinv5 * Rinv2;
-                        const T coef = M * Rinv3 + (T)2.5 * dqd * Rinv7;
+                        const T u5 = dqd * Rinv5;
+                        const T coef = MR3 + (T)2.5 * u5 * Rinv2;
                         fx += coef * dx - Rinv5 * qdx;
                         fy += coef * dy - Rinv5 * qdy;
                         fz += coef * dz - Rinv5 * qdz;
-                        fp -= M * Rinv + (T)0.5 * dqd * Rinv5;
+                        fp -= M * Rinv + (T)0.5 * u5;
                     } else {
                         fx += MR3 * dx;
                         fy += MR3 * dy;

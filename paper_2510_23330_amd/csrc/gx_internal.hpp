@@ -12,6 +12,7 @@
 #include "gx.h"
 
 #define GX_MAX_LEVEL 21
+#define GX_BLOCK 64  // SPH receivers per block (one per lane)
 #define GX_WAVE 64
 
 // ---------------------------------------------------------------------------
@@ -53,10 +54,11 @@ struct TreeSlot {
     Buf pos4;            // double4 {x, y, z, m} in sorted order
     Buf e2s;             // float eps^2 in sorted order
     Buf win, cnt, lmax;  // node-count construction scratch
-    Buf nodes, mom, q64, parent, lvl_ids, lvl_fill, flag;
+    Buf nodes, mom, q64, parent, child, lvl_ids, lvl_fill, flag;
     Buf groups;          // int32 node id of each group (pre-order)
+    Buf blocks;          // NodeRec per SPH receiver block (64 consecutive sorted slots)
     Buf box;             // double[8]: x0, y0, z0, L, 2^21/L, min eps^2
-    int64_t n_nodes = 0, n_groups = 0;
+    int64_t n_nodes = 0, n_groups = 0, n_blocks = 0;
     int64_t lvl_hist[GX_MAX_LEVEL + 1] = {};
     int32_t* perm() const { return (int32_t*)val[0].p; }
     const uint64_t* keys() const { return (const uint64_t*)key[0].p; }

@@ -2,54 +2,55 @@
 // "kernel size", "density and pressure" and "hydro force" items of Table 3,
 // kernels of Table 4), Wendland C4 kernel, on the gas tree slot.
 //
-// Work layout: one wavefront (64 lanes) per receiving group of the gas tree
-// (n_group <= 64 gives one receiver per lane; larger groups loop over chunks
-// of 64).  The group's candidate list -- particles of every leaf whose box
-// comes within the search radius of the group box -- is built by the
-// stackless walk in gx_walk.hip.
+// Receivers: the gas tree's groups (maximal nodes of at most n_group
+// particles; compact boxes keep candidate lists short).  One wavefront per
+// group.  Groups are usually smaller than 64, so the wave is cut into
+// 64 / pad slices (pad = 16, 32 or 64 >= group size): every slice holds each
+// receiver once and takes its own share of the candidates; cross-slice sums
+// are butterfly shuffles, which give every lane of a receiver bit-identical
+// totals.  Each group's candidate list -- particles of every gas-tree leaf
+// whose box comes within the search radius of the group box -- is built by
+// the wave-cooperative breadth-first walk in gx_walk.hip, in one pass into a
+// fixed-capacity slot per group.
 //
-// Density: the candidates are converted once to group-relative FP32
-// (position, mass) and kept in LDS for all Newton iterations; each lane runs
-// its own bracketed Newton iteration on N_eff(H) = (4 pi/3) H^3 rho(H) / m.
-// A lane whose kernel size would leave the radius its list was built for
-// stops and flags the group; the host re-walks only those groups with the
-// larger radius and repeats.
-//
-// Force: one pass over the candidates in LDS tiles, pairs inside
+// Density: candidates are converted once to group-relative FP32 (position,
+// mass) and kept in LDS for all Newton iterations.  Each receiver runs a
+// bracketed Newton iteration on N_eff(H) = (4 pi/3) H^3 rho(H) / m; a receiver
+// whose kernel size would leave the radius its list was built for stops and
+// flags the group, and the host re-walks only those groups with the larger
+// radius.  Force: one pass over LDS tiles of candidates, pairs inside
 // max(H_i, H_j), FP32 pair arithmetic, FP64 combination per tile.
 #include "gx_internal.hpp"
 
 int gx_tree_check(gx_ctx* ctx, int which, const gx_particles* p);
 
 __global__ __launch_bounds__(128) void k_walk_sph(
-    int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes,
+    int nb, const int32_t* __restrict__ recv, const NodeRec* __restrict__ nodes,
     const MomRec* __restrict__ mom, int nn, const float* __restrict__ radius, int use_hmax,
-    const uint8_t* __restrict__ active, int mode, uint32_t* __restrict__ pr_cnt,
+    const uint8_t* __restrict__ active, int mode, int cap, uint32_t* __restrict__ pr_cnt,
     uint32_t* __restrict__ pp_tot, unsigned long long* __restrict__ tot,
     const int64_t* __restrict__ pr_off, int32_t* __restrict__ pr_begin,
     int32_t* __restrict__ pr_cum);
+__global__ __launch_bounds__(64) void k_walk_sph_bfs(
+    int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes,
+    const int32_t* __restrict__ child, const MomRec* __restrict__ mom,
+    const float* __restrict__ radius, int use_hmax, const uint8_t* __restrict__ active, int cap,
+    uint32_t* __restrict__ pr_cnt, uint32_t* __restrict__ pp_tot,
+    unsigned long long* __restrict__ tot, int32_t* __restrict__ pr_begin,
+    int32_t* __restrict__ pr_cum, uint8_t* __restrict__ ovf);
 
-#define SPH_CAP 2048     // candidates kept in LDS by the density kernel
-#define SPH_TILE 256     // force kernel source tile
-#define SPH_MARGIN 1.25f  // density search radius = margin x largest kernel size
+#define SPH_THREADS 64
+#define SPH_CAP 2048       // candidates kept in LDS by the density kernel
+#define SPH_TILE 256       // force kernel source tile
+#define SPH_RANGES 1024    // capacity of a block's candidate range list (single-pass walk)
+#define SPH_MARGIN 1.15f   // density search radius = margin x largest kernel size
 
 // 495 / (32 pi), (4 pi / 3) * 495 / (32 pi) = 495 / 24, 1155 / (4 pi)
 #define WC4_NORM 4.9238032806262495f
 #define NEFF_C 20.625f
 #define GRADW_C 91.91197457030109f
 
-// ---------------------------------------------------------------------------
-// Work buffers (sorted order unless noted)
-// ---------------------------------------------------------------------------
-enum {
-    W_H = 0,     // float  kernel size per sorted slot
-    W_RAD,       // float  per-group search radius
-    W_ACT,       // uint8  per-group active flag
-    W_FLAG,      // uint32 per-group "needs a larger radius" flag + counters
-    W_VEL,       // double4 sorted velocities
-    W_SPH,       // float4 sorted {H, rho, A = P/rho^2, c}
-    W_STAT,      // u64 counters
-};
+enum { W_H = 0, W_RAD, W_ACT, W_FLAG, W_VEL, W_SPH, W_STAT };
 
 static int work(gx_ctx* ctx, int k, size_t bytes, void** p) {
     GX_TRY(gx_reserve(ctx, ctx->sph_work[k], bytes));
@@ -57,47 +58,132 @@ static int work(gx_ctx* ctx, int k, size_t bytes, void** p) {
     return GX_OK;
 }
 
-// Seed / gather kernel sizes: H_s[s] = H64[perm[s]] if positive and finite,
-// else a seed from the group's mean density, (3 n_ngb m_i V_G / (4 pi M_G))^(1/3).
-__global__ __launch_bounds__(64) void k_sph_seed(int ng, const int32_t* __restrict__ groups,
-                                                 const NodeRec* __restrict__ nodes,
-                                                 const MomRec* __restrict__ mom,
-                                                 const double4* __restrict__ pos4,
-                                                 const uint32_t* __restrict__ perm,
-                                                 const double* __restrict__ H64, float n_ngb,
-                                                 const double* __restrict__ box,
-                                                 float* __restrict__ Hs, float* __restrict__ rad) {
-    int g = blockIdx.x;
-    const NodeRec gn = nodes[groups[g]];
-    const double M = mom[groups[g]].M;
-    double ext[3], vol = 1.0;
-    for (int d = 0; d < 3; d++) ext[d] = gn.hi[d] - gn.lo[d];
-    double side = ldexp(box[3], -gn.level);
-    for (int d = 0; d < 3; d++) vol *= fmax(ext[d], 1e-3 * side);
-    float hmax = 0.0f;
-    for (int i = gn.begin + threadIdx.x; i < gn.end; i += 64) {
-        double h = H64 ? H64[perm[i]] : -1.0;
-        float hf;
-        if (h > 0.0 && h < INFINITY) {
-            hf = (float)h;
+// Candidate lists of all groups: fixed-capacity slots (group g at g * cap)
+// from the wave walk, and -- for the groups flagged in `ovf` whose lists did
+// not fit -- CSR lists from the thread walk.
+struct ListView {
+    int cap;
+    const uint32_t* cnt;
+    const int32_t* begin;
+    const int32_t* cum;
+    const uint32_t* tot;
+    const uint8_t* ovf;  // may be null: no overflow lists
+    const int64_t* off2;
+    const uint32_t* cnt2;
+    const int32_t* begin2;
+    const int32_t* cum2;
+    const uint32_t* tot2;
+};
+
+// One group's list: ranges [r0, r1) of begin/cum, npp candidates in total.
+struct GroupList {
+    const int32_t* begin;
+    const int32_t* cum;
+    int64_t r0, r1;
+    int npp;
+    __device__ __forceinline__ GroupList(const ListView& L, int g) {
+        if (L.ovf && L.ovf[g]) {
+            begin = L.begin2;
+            cum = L.cum2;
+            r0 = L.off2[g];
+            r1 = r0 + L.cnt2[g];
+            npp = (int)L.tot2[g];
         } else {
-            double rho = M / vol;
-            hf = (float)cbrt(3.0 * (double)n_ngb * pos4[i].w / (4.0 * M_PI * rho));
+            begin = L.begin;
+            cum = L.cum;
+            r0 = (int64_t)g * L.cap;
+            r1 = r0 + L.cnt[g];
+            npp = (int)L.tot[g];
         }
-        Hs[i] = hf;
-        hmax = fmaxf(hmax, hf);
     }
-    hmax = wave_max(hmax);
-    if (threadIdx.x == 0) rad[g] = hmax * SPH_MARGIN;
+};
+
+// Kernel-size seed: H64 when positive and finite, else from the smallest tree
+// node holding the particle and at least n_ngb particles, using the node's
+// geometric volume (which over-estimates the occupied volume, so the seed
+// errs large and the first candidate list already covers the root).
+__global__ __launch_bounds__(256) void k_sph_seed(int64_t n, const NodeRec* __restrict__ nodes,
+                                                  const MomRec* __restrict__ mom,
+                                                  const double4* __restrict__ pos4,
+                                                  const uint32_t* __restrict__ perm,
+                                                  const double* __restrict__ H64, float n_ngb,
+                                                  const double* __restrict__ box,
+                                                  float* __restrict__ Hs) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    double h = H64 ? H64[perm[s]] : -1.0;
+    if (h > 0.0 && h < INFINITY) {
+        Hs[s] = (float)h;
+        return;
+    }
+    int node = 0;
+    for (;;) {
+        const NodeRec nd = nodes[node];
+        if (nd.leaf) break;
+        int nxt = -1;
+        for (int c = node + 1; c < nd.next; c = nodes[c].next) {
+            const NodeRec cn = nodes[c];
+            if (cn.begin <= s && s < cn.end) {
+                if (cn.end - cn.begin >= (int)n_ngb) nxt = c;
+                break;
+            }
+        }
+        if (nxt < 0) break;
+        node = nxt;
+    }
+    const double side = ldexp(box[3], -nodes[node].level);
+    const double rho = mom[node].M / (side * side * side);
+    Hs[s] = (float)cbrt(3.0 * (double)n_ngb * pos4[s].w / (4.0 * M_PI * rho));
 }
 
-// Per-lane bracketed Newton on N_eff(H) over the group's candidates.
-__global__ __launch_bounds__(64) void k_sph_density(
+__global__ __launch_bounds__(64) void k_group_radius(int ng, const int32_t* __restrict__ groups,
+                                                     const NodeRec* __restrict__ nodes,
+                                                     const float* __restrict__ Hs, float scale,
+                                                     float* __restrict__ rad) {
+    const int g = blockIdx.x;
+    const NodeRec r = nodes[groups[g]];
+    float h = 0.0f;
+    for (int s = r.begin + threadIdx.x; s < r.end; s += 64) h = fmaxf(h, Hs[s]);
+    h = wave_max(h);
+    if (threadIdx.x == 0) rad[g] = h * scale;
+}
+
+__device__ __forceinline__ int slice_pad(int nG) {
+    int pad = 16;
+    while (pad < nG && pad < 64) pad <<= 1;
+    return pad;
+}
+
+// Sum over the slices of a wave (lanes il, il + pad, ...): butterfly shuffles.
+template <typename T>
+__device__ __forceinline__ T slice_sum(T v, int pad) {
+    for (int o = pad; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ void expand_chunk(const GroupList& L, int npp, int ch, int che,
+                                             const double4* __restrict__ pos4, double cx,
+                                             double cy, double cz, float4* __restrict__ cand,
+                                             int tid, int nthreads) {
+    for (int64_t r = L.r0; r < L.r1; r++) {
+        const int c = L.cum[r];
+        const int cn = (r + 1 < L.r1) ? L.cum[r + 1] : npp;
+        if (cn <= ch) continue;
+        if (c >= che) break;
+        const int b = L.begin[r];
+        const int lo = max(c, ch), hi = min(cn, che);
+        for (int k = lo + tid; k < hi; k += nthreads) {
+            const double4 p = pos4[b + (k - c)];
+            cand[k - ch] = make_float4((float)(p.x - cx), (float)(p.y - cy), (float)(p.z - cz),
+                                       (float)p.w);
+        }
+    }
+}
+
+__global__ __launch_bounds__(SPH_THREADS) void k_sph_density(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes,
     const double4* __restrict__ pos4, const uint32_t* __restrict__ perm,
-    const uint8_t* __restrict__ active, const int64_t* __restrict__ pr_off,
-    const int32_t* __restrict__ pr_begin, const int32_t* __restrict__ pr_cum,
-    const uint32_t* __restrict__ pp_tot, float* __restrict__ rad, float n_ngb, float tol,
+    const uint8_t* __restrict__ active, ListView L, float* __restrict__ rad, float n_ngb, float tol,
     int max_iter, float* __restrict__ Hs, uint32_t* __restrict__ flags,
     unsigned long long* __restrict__ stat, const double* __restrict__ u, float gamma,
     double* __restrict__ H64, float* __restrict__ Hout, float* __restrict__ rho_out,
@@ -106,41 +192,26 @@ __global__ __launch_bounds__(64) void k_sph_density(
     if (g >= ng) return;
     if (active && !active[g]) return;
     __shared__ float4 cand[SPH_CAP];
-    __shared__ int32_t jidx[SPH_TILE];
     const int lane = threadIdx.x;
-    const NodeRec gn = nodes[groups[g]];
-    const double cx = (gn.lo[0] + gn.hi[0]) * 0.5;
-    const double cy = (gn.lo[1] + gn.hi[1]) * 0.5;
-    const double cz = (gn.lo[2] + gn.hi[2]) * 0.5;
-    const int npp = (int)pp_tot[g];
-    const int64_t r0 = pr_off[g], r1 = pr_off[g + 1];
+    const NodeRec B = nodes[groups[g]];
+    const int nG = B.end - B.begin;
+    const int pad = slice_pad(nG), nsl = 64 / pad, il = lane % pad, sl = lane / pad;
+    const double cx = (B.lo[0] + B.hi[0]) * 0.5;
+    const double cy = (B.lo[1] + B.hi[1]) * 0.5;
+    const double cz = (B.lo[2] + B.hi[2]) * 0.5;
+    const GroupList GL(L, g);
+    const int npp = GL.npp;
     const float Rlim = rad[g];
     const bool in_lds = npp <= SPH_CAP;
-
-    // expand ranges and convert candidates (all of them when they fit in LDS)
-    auto load_chunk = [&](int ch, int che) {
-        for (int64_t r = r0; r < r1; r++) {
-            const int c = pr_cum[r];
-            const int cn = (r + 1 < r1) ? pr_cum[r + 1] : npp;
-            const int b = pr_begin[r];
-            const int lo = max(c, ch), hi = min(cn, che);
-            for (int k = lo + lane; k < hi; k += 64) {
-                const double4 p = pos4[b + (k - c)];
-                cand[k - ch] = make_float4((float)(p.x - cx), (float)(p.y - cy), (float)(p.z - cz),
-                                           (float)p.w);
-            }
-        }
-    };
-    if (in_lds) load_chunk(0, npp);
+    if (in_lds) expand_chunk(GL, npp, 0, npp, pos4, cx, cy, cz, cand, lane, SPH_THREADS);
     __syncthreads();
 
-    int worst_it = 0, nfail = 0, nflag = 0;
-    unsigned long long ngb = 0;
-    for (int ic = gn.begin; ic < gn.end; ic += 64) {
-        const int s = ic + lane;
-        const bool act = s < gn.end;
-        float xi = 0, yi = 0, zi = 0, mi = 1;
-        float H = 1.0f;
+    int nflag = 0, nfail = 0, worst_it = 0;
+    float hmax = 0.0f;
+    for (int ic = 0; ic < nG; ic += pad) {
+        const int s = B.begin + ic + il;
+        const bool act = ic + il < nG;
+        float xi = 0, yi = 0, zi = 0, mi = 1, H = 1.0f;
         if (act) {
             const double4 p = pos4[s];
             xi = (float)(p.x - cx);
@@ -152,21 +223,21 @@ __global__ __launch_bounds__(64) void k_sph_density(
         float lo = 0.0f, hi = INFINITY, S0 = 0.0f;
         bool done = !act, conv = false, over = false;
         int it = 0;
-        while (true) {
-            // uniform loop: every lane walks the candidates while any lane iterates
-            if (__ballot(!done) == 0ull) break;
+        for (;;) {
             const float Hinv = 1.0f / H, Hinv2 = Hinv * Hinv;
             float s0 = 0.0f, s1 = 0.0f;
-            int cntin = 0;
             for (int ch = 0; ch < npp; ch += SPH_CAP) {
                 const int che = min(npp, ch + SPH_CAP);
                 if (!in_lds) {
                     __syncthreads();
-                    load_chunk(ch, che);
+                    expand_chunk(GL, npp, ch, che, pos4, cx, cy, cz, cand, lane, SPH_THREADS);
                     __syncthreads();
                 }
+                const int cnt = che - ch;
+                const int per = (cnt + nsl - 1) / nsl;
+                const int kb = sl * per, ke = min(cnt, kb + per);
 #pragma unroll 4
-                for (int k = 0; k < che - ch; k++) {
+                for (int k = kb; k < ke; k++) {
                     const float4 c = cand[k];
                     const float dx = c.x - xi, dy = c.y - yi, dz = c.z - zi;
                     const float q2 = (dx * dx + dy * dy + dz * dz) * Hinv2;
@@ -178,10 +249,11 @@ __global__ __launch_bounds__(64) void k_sph_density(
                         const float poly = 1.0f + q * (6.0f + q * (35.0f / 3.0f));
                         s0 += c.w * t5 * t * poly;
                         s1 += c.w * q2 * (1.0f + 5.0f * q) * t5;
-                        cntin++;
                     }
                 }
             }
+            s0 = slice_sum(s0, pad);
+            s1 = slice_sum(s1, pad);
             if (!done) {
                 it++;
                 S0 = s0;
@@ -190,10 +262,8 @@ __global__ __launch_bounds__(64) void k_sph_density(
                 if (fabsf(f) <= tol) {
                     done = true;
                     conv = true;
-                    ngb += (unsigned long long)cntin;
                 } else if (it >= max_iter) {
                     done = true;
-                    ngb += (unsigned long long)cntin;
                 } else {
                     const float dn = NEFF_C * (56.0f / 3.0f) * s1 / (mi * H);
                     if (f < 0.0f) lo = H;
@@ -204,15 +274,15 @@ __global__ __launch_bounds__(64) void k_sph_density(
                         // the list only covers kernel sizes up to Rlim: redo with a larger list
                         done = true;
                         over = true;
-                        H = Hn;
-                    } else {
-                        H = Hn;
                     }
+                    H = Hn;
                 }
             }
+            if (__ballot(!done) == 0ull) break;
         }
-        if (act) {
+        if (act && sl == 0) {
             Hs[s] = H;
+            hmax = fmaxf(hmax, H);
             worst_it = max(worst_it, it);
             if (over) {
                 nflag++;
@@ -224,18 +294,14 @@ __global__ __launch_bounds__(64) void k_sph_density(
                 H64[o] = (double)H;
                 Hout[o] = H;
                 rho_out[o] = rho;
-                if (P_out) P_out[o] = (float)((gamma - 1.0f) * (double)rho * uu);
+                if (P_out) P_out[o] = (float)((double)(gamma - 1.0f) * (double)rho * uu);
                 if (cs_out) cs_out[o] = (float)sqrt((double)gamma * (gamma - 1.0f) * uu);
             }
         }
     }
-    // wave reductions of the per-lane counters
     nflag = (int)wave_sum((unsigned)nflag);
     nfail = (int)wave_sum((unsigned)nfail);
     worst_it = wave_max(worst_it);
-    ngb = wave_sum(ngb);
-    float hmax = 0.0f;
-    for (int s = gn.begin + lane; s < gn.end; s += 64) hmax = fmaxf(hmax, Hs[s]);
     hmax = wave_max(hmax);
     if (lane == 0) {
         flags[g] = nflag ? 1u : 0u;
@@ -245,7 +311,6 @@ __global__ __launch_bounds__(64) void k_sph_density(
             atomicAdd(&stat[3], 1ull);
         } else {  // counted once, in the group's final round
             atomicAdd(&stat[0], (unsigned long long)nfail);
-            atomicAdd(&stat[2], ngb);
         }
     }
 }
@@ -253,8 +318,8 @@ __global__ __launch_bounds__(64) void k_sph_density(
 // ---------------------------------------------------------------------------
 // Force
 // ---------------------------------------------------------------------------
-// Sorted per-particle state for the force: velocity (FP64) and
-// {H, rho, A = P / rho^2, c} (FP32) with P = (gamma - 1) rho u, c = sqrt(gamma (gamma - 1) u).
+// Sorted per-particle state: velocity (FP64) and {H, rho, A = P / rho^2, c}
+// (FP32) with P = (gamma - 1) rho u, c = sqrt(gamma (gamma - 1) u).
 __global__ __launch_bounds__(256) void k_sph_prep(int64_t n, const uint32_t* __restrict__ perm,
                                                   const double* __restrict__ vx,
                                                   const double* __restrict__ vy,
@@ -300,12 +365,10 @@ __global__ __launch_bounds__(64) void k_group_hmax(int ng, const int32_t* __rest
     if (g < ng) rad[g] = mom[groups[g]].hmax;
 }
 
-__global__ __launch_bounds__(64) void k_sph_force(
+__global__ __launch_bounds__(SPH_THREADS) void k_sph_force(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes,
     const double4* __restrict__ pos4, const uint32_t* __restrict__ perm,
-    const double4* __restrict__ sv, const float4* __restrict__ ss,
-    const int64_t* __restrict__ pr_off, const int32_t* __restrict__ pr_begin,
-    const int32_t* __restrict__ pr_cum, const uint32_t* __restrict__ pp_tot, float alpha,
+    const double4* __restrict__ sv, const float4* __restrict__ ss, ListView L, float alpha,
     double* __restrict__ ax, double* __restrict__ ay, double* __restrict__ az,
     double* __restrict__ dudt, float* __restrict__ vsig_out, unsigned long long* __restrict__ stat) {
     const int g = xcd_remap(blockIdx.x, ng);
@@ -313,19 +376,23 @@ __global__ __launch_bounds__(64) void k_sph_force(
     __shared__ float tx[SPH_TILE], ty[SPH_TILE], tz[SPH_TILE], tvx[SPH_TILE], tvy[SPH_TILE],
         tvz[SPH_TILE], tm[SPH_TILE], thi[SPH_TILE], th2[SPH_TILE], tcw[SPH_TILE], trho[SPH_TILE],
         tA[SPH_TILE], tc[SPH_TILE];
+    __shared__ int32_t jidx[SPH_TILE];
     const int lane = threadIdx.x;
-    const NodeRec gn = nodes[groups[g]];
-    const double cx = (gn.lo[0] + gn.hi[0]) * 0.5;
-    const double cy = (gn.lo[1] + gn.hi[1]) * 0.5;
-    const double cz = (gn.lo[2] + gn.hi[2]) * 0.5;
-    const double4 vref = sv[gn.begin];
-    const int npp = (int)pp_tot[g];
-    const int64_t r0 = pr_off[g], r1 = pr_off[g + 1];
+    const NodeRec B = nodes[groups[g]];
+    const int nG = B.end - B.begin;
+    const int pad = slice_pad(nG), nsl = 64 / pad, il = lane % pad, sl = lane / pad;
+    const double cx = (B.lo[0] + B.hi[0]) * 0.5;
+    const double cy = (B.lo[1] + B.hi[1]) * 0.5;
+    const double cz = (B.lo[2] + B.hi[2]) * 0.5;
+    const double4 vref = sv[B.begin];
+    const GroupList GL(L, g);
+    const int npp = GL.npp;
+    const int64_t r0 = GL.r0, r1 = GL.r1;
     unsigned long long nin = 0;
 
-    for (int ic = gn.begin; ic < gn.end; ic += 64) {
-        const int s = ic + lane;
-        const bool act = s < gn.end;
+    for (int ic = 0; ic < nG; ic += pad) {
+        const int s = B.begin + ic + il;
+        const bool act = ic + il < nG;
         float xi = 0, yi = 0, zi = 0, vxi = 0, vyi = 0, vzi = 0;
         float Hi = 1, Hinv = 1, cwi = 0, rhoi = 1, Ai = 0, ci = 0;
         if (act) {
@@ -349,47 +416,47 @@ __global__ __launch_bounds__(64) void k_sph_force(
         const float Hi2 = Hi * Hi;
         double AX = 0, AY = 0, AZ = 0, DU = 0;
         float vs = ci;
+        int64_t rr = r0;  // first range that may overlap the current tile
         for (int t0 = 0; t0 < npp; t0 += SPH_TILE) {
             const int tn = min(SPH_TILE, npp - t0);
             __syncthreads();
-            // stage the tile: lane-strided over the ranges that overlap it
-            for (int64_t r = r0; r < r1; r++) {
-                const int c = pr_cum[r];
-                const int cn = (r + 1 < r1) ? pr_cum[r + 1] : npp;
+            for (int64_t r = rr; r < r1; r++) {
+                const int c = GL.cum[r];
+                if (c >= t0 + tn) break;
+                const int cn = (r + 1 < r1) ? GL.cum[r + 1] : npp;
+                const int b = GL.begin[r];
                 const int lo = max(c, t0), hi = min(cn, t0 + tn);
-                if (lo >= hi) {
-                    if (c >= t0 + tn) break;
-                    continue;
-                }
-                const int b = pr_begin[r];
-                for (int k = lo + lane; k < hi; k += 64) {
-                    const int j = b + (k - c);
-                    const int e = k - t0;
-                    const double4 p = pos4[j];
-                    const double4 v = sv[j];
-                    const float4 q = ss[j];
-                    tx[e] = (float)(p.x - cx);
-                    ty[e] = (float)(p.y - cy);
-                    tz[e] = (float)(p.z - cz);
-                    tvx[e] = (float)(v.x - vref.x);
-                    tvy[e] = (float)(v.y - vref.y);
-                    tvz[e] = (float)(v.z - vref.z);
-                    tm[e] = (float)p.w;
-                    const float hinv = 1.0f / q.x;
-                    const float h2 = hinv * hinv;
-                    thi[e] = hinv;
-                    th2[e] = q.x * q.x;
-                    tcw[e] = -GRADW_C * h2 * h2 * hinv;
-                    trho[e] = q.y;
-                    tA[e] = q.z;
-                    tc[e] = q.w;
-                }
+                for (int k = lo + lane; k < hi; k += SPH_THREADS) jidx[k - t0] = b + (k - c);
+            }
+            while (rr < r1 && ((rr + 1 < r1) ? GL.cum[rr + 1] : npp) <= t0 + tn) rr++;
+            __syncthreads();
+            for (int e = lane; e < tn; e += SPH_THREADS) {
+                const int j = jidx[e];
+                const double4 p = pos4[j];
+                const double4 v = sv[j];
+                const float4 q = ss[j];
+                tx[e] = (float)(p.x - cx);
+                ty[e] = (float)(p.y - cy);
+                tz[e] = (float)(p.z - cz);
+                tvx[e] = (float)(v.x - vref.x);
+                tvy[e] = (float)(v.y - vref.y);
+                tvz[e] = (float)(v.z - vref.z);
+                tm[e] = (float)p.w;
+                const float hinv = 1.0f / q.x;
+                const float h2 = hinv * hinv;
+                thi[e] = hinv;
+                th2[e] = q.x * q.x;
+                tcw[e] = -GRADW_C * h2 * h2 * hinv;
+                trho[e] = q.y;
+                tA[e] = q.z;
+                tc[e] = q.w;
             }
             __syncthreads();
             if (act) {
                 float fx = 0, fy = 0, fz = 0, fu = 0;
-#pragma unroll 2
-                for (int k = 0; k < tn; k++) {
+                const int per = (tn + nsl - 1) / nsl;
+                const int kb = sl * per, ke = min(tn, kb + per);
+                for (int k = kb; k < ke; k++) {
                     const float dx = tx[k] - xi, dy = ty[k] - yi, dz = tz[k] - zi;
                     const float r2 = dx * dx + dy * dy + dz * dz;
                     const bool inside = (r2 < Hi2 || r2 < th2[k]) && r2 > 0.0f;
@@ -427,7 +494,12 @@ __global__ __launch_bounds__(64) void k_sph_force(
                 DU += (double)fu;
             }
         }
-        if (act) {
+        AX = slice_sum(AX, pad);
+        AY = slice_sum(AY, pad);
+        AZ = slice_sum(AZ, pad);
+        DU = slice_sum(DU, pad);
+        for (int o = pad; o < 64; o <<= 1) vs = fmaxf(vs, __shfl_xor(vs, o, 64));
+        if (act && sl == 0) {
             const uint32_t o = perm[s];
             ax[o] += AX;
             ay[o] += AY;
@@ -439,51 +511,83 @@ __global__ __launch_bounds__(64) void k_sph_force(
     nin = wave_sum(nin);
     if (lane == 0) {
         atomicAdd(&stat[2], nin);
-        atomicAdd(&stat[4], (unsigned long long)(gn.end - gn.begin) * (unsigned long long)npp);
+        atomicAdd(&stat[4], (unsigned long long)nG * (unsigned long long)npp);
     }
 }
 
 // ---------------------------------------------------------------------------
 // Host drivers
 // ---------------------------------------------------------------------------
+// Candidate lists for every (active) group: the wave walk fills fixed-
+// capacity slots in one pass and flags the groups whose list or frontier did
+// not fit; only those take the thread walk (count + scan + fill) into a
+// second, CSR list set.
 static int sph_walk(gx_ctx* ctx, TreeSlot& T, ListSet& Ls, const float* rad, int use_hmax,
-                    const uint8_t* active) {
+                    const uint8_t* active, ListView* view, int64_t* list_pairs) {
     hipStream_t st = ctx->stream;
     const int ng = (int)T.n_groups, nn = (int)T.n_nodes;
-    GX_TRY(gx_reserve(ctx, Ls.tot, 8 * sizeof(int64_t)));
-    GX_TRY(gx_reserve(ctx, Ls.pr_cnt, (ng + 1) * sizeof(uint32_t)));
-    GX_TRY(gx_reserve(ctx, Ls.pp_tot, (ng + 1) * sizeof(uint32_t)));
+    GX_TRY(gx_reserve(ctx, Ls.tot, 16 * sizeof(int64_t)));
+    GX_TRY(gx_reserve(ctx, Ls.pr_cnt, (2 * ng + 2) * sizeof(uint32_t)));
+    GX_TRY(gx_reserve(ctx, Ls.pp_tot, (2 * ng + 2) * sizeof(uint32_t)));
     GX_TRY(gx_reserve(ctx, Ls.pr_off, (ng + 1) * sizeof(int64_t)));
+    GX_TRY(gx_reserve(ctx, Ls.pc_cnt, ng + 16));  // per-group overflow flags
+    GX_TRY(gx_reserve(ctx, Ls.pr_begin, (size_t)ng * SPH_RANGES * sizeof(int32_t)));
+    GX_TRY(gx_reserve(ctx, Ls.pr_cum, (size_t)ng * SPH_RANGES * sizeof(int32_t)));
     int64_t* tot = (int64_t*)Ls.tot.p;
-    GX_TRY(gx_zero(ctx, tot, 8 * sizeof(int64_t)));
-    hipLaunchKernelGGL(k_walk_sph, dim3(gx_blocks(ng, 128)), dim3(128), 0, st, ng,
+    uint32_t* cnt = (uint32_t*)Ls.pr_cnt.p;
+    uint32_t* cnt2 = cnt + ng + 1;
+    uint32_t* ptot = (uint32_t*)Ls.pp_tot.p;
+    uint32_t* ptot2 = ptot + ng + 1;
+    uint8_t* ovf = (uint8_t*)Ls.pc_cnt.p;
+    GX_TRY(gx_zero(ctx, tot, 16 * sizeof(int64_t)));
+    hipLaunchKernelGGL(k_walk_sph_bfs, dim3(xcd_grid(ng)), dim3(64), 0, st, ng,
                        (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
-                       (const MomRec*)T.mom.p, nn, rad, use_hmax, active, 0, (uint32_t*)Ls.pr_cnt.p,
-                       (uint32_t*)Ls.pp_tot.p, (unsigned long long*)tot, nullptr, nullptr, nullptr);
+                       (const int32_t*)T.child.p, (const MomRec*)T.mom.p, rad, use_hmax, active,
+                       SPH_RANGES, cnt, ptot, (unsigned long long*)tot, (int32_t*)Ls.pr_begin.p,
+                       (int32_t*)Ls.pr_cum.p, ovf);
     GX_LAUNCH_CHECK(ctx);
-    GX_TRY((gx_scan<uint32_t, int64_t>(ctx, (const uint32_t*)Ls.pr_cnt.p, (int64_t*)Ls.pr_off.p, ng,
-                                       tot + 1)));
-    GX_HIP(ctx, hipMemcpyAsync((int64_t*)Ls.pr_off.p + ng, tot + 1, 8, hipMemcpyDeviceToDevice, st));
-    int64_t h[2];
-    GX_HIP(ctx, hipMemcpyAsync(h, tot, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    int64_t h[16];
+    GX_HIP(ctx, hipMemcpyAsync(h, tot, 16 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     GX_HIP(ctx, hipStreamSynchronize(st));
-    Ls.n_ranges = h[1];
-    GX_TRY(gx_reserve(ctx, Ls.pr_begin, (h[1] + 1) * sizeof(int32_t)));
-    GX_TRY(gx_reserve(ctx, Ls.pr_cum, (h[1] + 1) * sizeof(int32_t)));
-    hipLaunchKernelGGL(k_walk_sph, dim3(gx_blocks(ng, 128)), dim3(128), 0, st, ng,
-                       (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
-                       (const MomRec*)T.mom.p, nn, rad, use_hmax, active, 1, nullptr, nullptr,
-                       nullptr, (const int64_t*)Ls.pr_off.p, (int32_t*)Ls.pr_begin.p,
-                       (int32_t*)Ls.pr_cum.p);
-    GX_LAUNCH_CHECK(ctx);
+    ListView v{SPH_RANGES, cnt, (const int32_t*)Ls.pr_begin.p, (const int32_t*)Ls.pr_cum.p, ptot,
+               nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    int64_t pairs = h[2];
+    if (h[4] > 0) {  // overflowing groups: exact CSR lists from the thread walk
+        hipLaunchKernelGGL(k_walk_sph, dim3(gx_blocks(ng, 128)), dim3(128), 0, st, ng,
+                           (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
+                           (const MomRec*)T.mom.p, nn, rad, use_hmax, ovf, 0, 0, cnt2, ptot2,
+                           (unsigned long long*)(tot + 8), nullptr, nullptr, nullptr);
+        GX_TRY((gx_scan<uint32_t, int64_t>(ctx, cnt2, (int64_t*)Ls.pr_off.p, ng, tot + 13)));
+        GX_HIP(ctx, hipMemcpyAsync(h, tot, 16 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        GX_HIP(ctx, hipStreamSynchronize(st));
+        const int64_t nr = h[13];
+        GX_TRY(gx_reserve(ctx, Ls.pc_off, (nr + 1) * sizeof(int32_t)));
+        GX_TRY(gx_reserve(ctx, Ls.pc_list, (nr + 1) * sizeof(int32_t)));
+        hipLaunchKernelGGL(k_walk_sph, dim3(gx_blocks(ng, 128)), dim3(128), 0, st, ng,
+                           (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
+                           (const MomRec*)T.mom.p, nn, rad, use_hmax, ovf, 1, 0, nullptr, nullptr,
+                           nullptr, (const int64_t*)Ls.pr_off.p, (int32_t*)Ls.pc_off.p,
+                           (int32_t*)Ls.pc_list.p);
+        GX_LAUNCH_CHECK(ctx);
+        v.ovf = ovf;
+        v.off2 = (const int64_t*)Ls.pr_off.p;
+        v.cnt2 = cnt2;
+        v.begin2 = (const int32_t*)Ls.pc_off.p;
+        v.cum2 = (const int32_t*)Ls.pc_list.p;
+        v.tot2 = ptot2;
+        pairs += h[10];
+    }
+    *list_pairs += pairs;
     Ls.n_groups = ng;
+    Ls.n_ranges = h[1];
+    *view = v;
     return GX_OK;
 }
 
-__global__ void k_flags_to_active(int ng, const uint32_t* __restrict__ flags,
+__global__ void k_flags_to_active(int nb, const uint32_t* __restrict__ flags,
                                   uint8_t* __restrict__ active) {
     int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g < ng) active[g] = flags[g] ? 1 : 0;
+    if (g < nb) active[g] = flags[g] ? 1 : 0;
 }
 
 extern "C" int gx_sph_density(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, double n_ngb,
@@ -492,13 +596,14 @@ extern "C" int gx_sph_density(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, 
     if (!gs->u || !gs->H64 || !gs->H || !gs->rho || gs->n != gas->n)
         return gx_fail(ctx, GX_EINVAL, "sph_density: gas arrays missing or length mismatch");
     if (!(n_ngb > 20.7) || !(tol > 0.0) || max_iter < 1 || !(gamma > 1.0))
-        return gx_fail(ctx, GX_EINVAL, "sph_density: need n_ngb > 20.625, tol > 0, max_iter >= 1, gamma > 1");
+        return gx_fail(ctx, GX_EINVAL,
+                       "sph_density: need n_ngb > 20.625, tol > 0, max_iter >= 1, gamma > 1");
     GX_TRY(gx_tree_check(ctx, GX_TREE_GAS, gas));
     GX_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
     TreeSlot& T = ctx->tree[GX_TREE_GAS];
     ListSet& Ls = ctx->sph;
-    const int ng = (int)T.n_groups;
+    const int nb = (int)T.n_groups;
     const int64_t n = T.n;
     if (stats) {
         *stats = gx_stats{};
@@ -509,15 +614,17 @@ extern "C" int gx_sph_density(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, 
     uint32_t* flags;
     unsigned long long* stat;
     GX_TRY(work(ctx, W_H, n * sizeof(float), (void**)&Hs));
-    GX_TRY(work(ctx, W_RAD, ng * sizeof(float), (void**)&rad));
-    GX_TRY(work(ctx, W_ACT, ng + 16, (void**)&active));
-    GX_TRY(work(ctx, W_FLAG, ng * sizeof(uint32_t), (void**)&flags));
+    GX_TRY(work(ctx, W_RAD, nb * sizeof(float), (void**)&rad));
+    GX_TRY(work(ctx, W_ACT, nb + 16, (void**)&active));
+    GX_TRY(work(ctx, W_FLAG, nb * sizeof(uint32_t), (void**)&flags));
     GX_TRY(work(ctx, W_STAT, 16 * sizeof(unsigned long long), (void**)&stat));
     GX_TRY(gx_zero(ctx, stat, 16 * sizeof(unsigned long long)));
-    hipLaunchKernelGGL(k_sph_seed, dim3(ng), dim3(64), 0, st, ng, (const int32_t*)T.groups.p,
+    hipLaunchKernelGGL(k_sph_seed, dim3(gx_blocks(n, 256)), dim3(256), 0, st, n,
                        (const NodeRec*)T.nodes.p, (const MomRec*)T.mom.p, (const double4*)T.pos4.p,
                        (const uint32_t*)T.val[0].p, gs->H64, (float)n_ngb, (const double*)T.box.p,
-                       Hs, rad);
+                       Hs);
+    hipLaunchKernelGGL(k_group_radius, dim3(nb), dim3(64), 0, st, nb, (const int32_t*)T.groups.p,
+                       (const NodeRec*)T.nodes.p, Hs, SPH_MARGIN, rad);
     GX_LAUNCH_CHECK(ctx);
     const uint8_t* act = nullptr;
     int rounds = 0;
@@ -525,33 +632,31 @@ extern "C" int gx_sph_density(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, 
     int64_t list_pairs = 0;
     double kernel_ms = 0.0;
     for (;;) {
-        GX_TRY(sph_walk(ctx, T, Ls, rad, 0, act));
-        int64_t hl[4];
-        GX_HIP(ctx, hipMemcpyAsync(hl, Ls.tot.p, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        ListView view;
+        GX_TRY(sph_walk(ctx, T, Ls, rad, 0, act, &view, &list_pairs));
         if (stats) GX_HIP(ctx, hipEventRecord(ctx->ev2, st));
-        hipLaunchKernelGGL(k_sph_density, dim3(xcd_grid(ng)), dim3(64), 0, st, ng,
+        hipLaunchKernelGGL(k_sph_density, dim3(xcd_grid(nb)), dim3(SPH_THREADS), 0, st, nb,
                            (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
-                           (const double4*)T.pos4.p, (const uint32_t*)T.val[0].p, act,
-                           (const int64_t*)Ls.pr_off.p, (const int32_t*)Ls.pr_begin.p,
-                           (const int32_t*)Ls.pr_cum.p, (const uint32_t*)Ls.pp_tot.p, rad,
-                           (float)n_ngb, (float)tol, max_iter, Hs, flags, stat, gs->u,
-                           (float)gamma, gs->H64, gs->H, gs->rho, gs->P, gs->cs);
+                           (const double4*)T.pos4.p,
+                           (const uint32_t*)T.val[0].p, act, view, rad, (float)n_ngb, (float)tol,
+                           max_iter, Hs, flags, stat, gs->u, (float)gamma, gs->H64, gs->H, gs->rho,
+                           gs->P, gs->cs);
         GX_LAUNCH_CHECK(ctx);
         if (stats) GX_HIP(ctx, hipEventRecord(ctx->ev3, st));
-        GX_HIP(ctx, hipMemcpyAsync(h_stat, stat, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        GX_HIP(ctx, hipMemcpyAsync(h_stat, stat, 8 * sizeof(unsigned long long),
+                                   hipMemcpyDeviceToHost, st));
         GX_HIP(ctx, hipStreamSynchronize(st));
         if (stats) {
             float msk = 0;
             GX_HIP(ctx, hipEventElapsedTime(&msk, ctx->ev2, ctx->ev3));
             kernel_ms += msk;
         }
-        list_pairs += hl[2];
         rounds++;
         if (h_stat[3] == 0) break;
-        if (rounds >= 12)
-            return gx_fail(ctx, GX_ENOCONV, "sph_density: search radius did not settle in %d rounds", rounds);
-        // next round: only the flagged groups, with their enlarged radius
-        hipLaunchKernelGGL(k_flags_to_active, dim3(gx_blocks(ng, 256)), dim3(256), 0, st, ng, flags,
+        if (rounds >= 16)
+            return gx_fail(ctx, GX_ENOCONV, "sph_density: search radius did not settle in %d rounds",
+                           rounds);
+        hipLaunchKernelGGL(k_flags_to_active, dim3(gx_blocks(nb, 256)), dim3(256), 0, st, nb, flags,
                            active);
         act = active;
         GX_TRY(gx_zero(ctx, stat + 3, sizeof(unsigned long long)));
@@ -562,13 +667,12 @@ extern "C" int gx_sph_density(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, 
         float ms = 0;
         GX_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
         stats->ms = ms;
+        stats->ms_kernel = kernel_ms;
         stats->n_noconv = (int64_t)h_stat[0];
         stats->n_iter_max = (int64_t)h_stat[1];
-        stats->n_sph_ngb = (int64_t)h_stat[2];
         stats->n_sph_list = list_pairs;
         stats->n_rewalk = rounds - 1;
-        stats->ms_kernel = kernel_ms;
-        stats->n_groups = ng;
+        stats->n_groups = nb;
         stats->n_nodes = T.n_nodes;
     }
     if (h_stat[0] > 0)
@@ -581,14 +685,16 @@ extern "C" int gx_sph_forces(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, d
     if (!ctx || !gas || !gs || !ax || !ay || !az) return GX_EINVAL;
     if (!gs->u || !gs->H || !gs->rho || !gs->dudt || !gs->vsig || gs->n != gas->n)
         return gx_fail(ctx, GX_EINVAL, "sph_forces: gas arrays missing or length mismatch");
-    if (!gas->vx || !gas->vy || !gas->vz) return gx_fail(ctx, GX_EINVAL, "sph_forces: velocities missing");
-    if (!(gamma > 1.0) || !(alpha >= 0.0)) return gx_fail(ctx, GX_EINVAL, "sph_forces: bad gamma/alpha");
+    if (!gas->vx || !gas->vy || !gas->vz)
+        return gx_fail(ctx, GX_EINVAL, "sph_forces: velocities missing");
+    if (!(gamma > 1.0) || !(alpha >= 0.0))
+        return gx_fail(ctx, GX_EINVAL, "sph_forces: bad gamma/alpha");
     GX_TRY(gx_tree_check(ctx, GX_TREE_GAS, gas));
     GX_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
     TreeSlot& T = ctx->tree[GX_TREE_GAS];
     ListSet& Ls = ctx->sph;
-    const int ng = (int)T.n_groups;
+    const int nb = (int)T.n_groups;
     const int64_t n = T.n;
     if (stats) {
         *stats = gx_stats{};
@@ -600,40 +706,44 @@ extern "C" int gx_sph_forces(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, d
     unsigned long long* stat;
     GX_TRY(work(ctx, W_VEL, n * sizeof(double4), (void**)&sv));
     GX_TRY(work(ctx, W_SPH, n * sizeof(float4), (void**)&ss));
-    GX_TRY(work(ctx, W_RAD, ng * sizeof(float), (void**)&rad));
+    GX_TRY(work(ctx, W_RAD, nb * sizeof(float), (void**)&rad));
     GX_TRY(work(ctx, W_STAT, 16 * sizeof(unsigned long long), (void**)&stat));
     GX_TRY(gx_zero(ctx, stat, 16 * sizeof(unsigned long long)));
     hipLaunchKernelGGL(k_sph_prep, dim3(gx_blocks(n, 256)), dim3(256), 0, st, n,
                        (const uint32_t*)T.val[0].p, gas->vx, gas->vy, gas->vz, gs->u, gs->H, gs->rho,
                        (float)gamma, sv, ss);
+    int64_t off = 0;
+    int64_t lvl_off[GX_MAX_LEVEL + 1];
+    for (int l = 0; l <= GX_MAX_LEVEL; l++) {
+        lvl_off[l] = off;
+        off += T.lvl_hist[l];
+    }
     for (int l = GX_MAX_LEVEL; l >= 0; l--) {
         int c = (int)T.lvl_hist[l];
         if (!c) continue;
-        int64_t off = 0;
-        for (int k = 0; k < l; k++) off += T.lvl_hist[k];
         hipLaunchKernelGGL(k_hmax_level, dim3(gx_blocks(c, 256)), dim3(256), 0, st, c,
-                           (const int32_t*)T.lvl_ids.p + off, (const NodeRec*)T.nodes.p,
+                           (const int32_t*)T.lvl_ids.p + lvl_off[l], (const NodeRec*)T.nodes.p,
                            (MomRec*)T.mom.p, ss);
     }
-    hipLaunchKernelGGL(k_group_hmax, dim3(gx_blocks(ng, 64)), dim3(64), 0, st, ng,
+    hipLaunchKernelGGL(k_group_hmax, dim3(gx_blocks(nb, 64)), dim3(64), 0, st, nb,
                        (const int32_t*)T.groups.p, (const MomRec*)T.mom.p, rad);
     GX_LAUNCH_CHECK(ctx);
-    GX_TRY(sph_walk(ctx, T, Ls, rad, 1, nullptr));
+    ListView view;
+    int64_t list_pairs = 0;
+    GX_TRY(sph_walk(ctx, T, Ls, rad, 1, nullptr, &view, &list_pairs));
     if (stats) GX_HIP(ctx, hipEventRecord(ctx->ev2, st));
-    hipLaunchKernelGGL(k_sph_force, dim3(xcd_grid(ng)), dim3(64), 0, st, ng,
+    hipLaunchKernelGGL(k_sph_force, dim3(xcd_grid(nb)), dim3(SPH_THREADS), 0, st, nb,
                        (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
-                       (const double4*)T.pos4.p, (const uint32_t*)T.val[0].p, sv, ss,
-                       (const int64_t*)Ls.pr_off.p, (const int32_t*)Ls.pr_begin.p,
-                       (const int32_t*)Ls.pr_cum.p, (const uint32_t*)Ls.pp_tot.p, (float)alpha, ax,
-                       ay, az, gs->dudt, gs->vsig, stat);
+                       (const double4*)T.pos4.p,
+                       (const uint32_t*)T.val[0].p, sv, ss, view, (float)alpha, ax, ay, az,
+                       gs->dudt, gs->vsig, stat);
     GX_LAUNCH_CHECK(ctx);
     if (stats) GX_HIP(ctx, hipEventRecord(ctx->ev3, st));
     if (stats) {
         GX_HIP(ctx, hipEventRecord(ctx->ev1, st));
         GX_HIP(ctx, hipEventSynchronize(ctx->ev1));
-        float ms = 0;
+        float ms = 0, msk = 0;
         GX_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-        float msk = 0;
         GX_HIP(ctx, hipEventElapsedTime(&msk, ctx->ev2, ctx->ev3));
         unsigned long long h[8];
         GX_HIP(ctx, hipMemcpy(h, stat, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost));
@@ -641,7 +751,7 @@ extern "C" int gx_sph_forces(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, d
         stats->ms_kernel = msk;
         stats->n_sph_ngb = (int64_t)h[2];
         stats->n_sph_list = (int64_t)h[4];
-        stats->n_groups = ng;
+        stats->n_groups = nb;
         stats->n_nodes = T.n_nodes;
     }
     return GX_OK;

@@ -225,14 +225,23 @@ __global__ __launch_bounds__(256) void k_node_emit(int64_t n, const uint64_t* __
     }
 }
 
+// Parent of every node and the (up to 8) children of every internal node in
+// key order, -1 padded (child[8 p + k]).
 __global__ __launch_bounds__(256) void k_node_parent(int64_t nn, const NodeRec* __restrict__ nodes,
-                                                     int32_t* __restrict__ parent) {
+                                                     int32_t* __restrict__ parent,
+                                                     int32_t* __restrict__ child) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nn) return;
     if (p == 0) parent[0] = -1;
-    if (nodes[p].leaf) return;
-    int32_t stop = nodes[p].next;
-    for (int32_t c = (int32_t)p + 1; c < stop; c = nodes[c].next) parent[c] = (int32_t)p;
+    int k = 0;
+    if (!nodes[p].leaf) {
+        int32_t stop = nodes[p].next;
+        for (int32_t c = (int32_t)p + 1; c < stop; c = nodes[c].next) {
+            parent[c] = (int32_t)p;
+            child[8 * p + k++] = c;
+        }
+    }
+    for (; k < 8; k++) child[8 * p + k] = -1;
 }
 
 // Moments of the nodes of one level: leaves from their particles, internal
@@ -345,6 +354,40 @@ __global__ __launch_bounds__(256) void k_group_compact(int64_t nn, const uint32_
     if (id < nn && flag[id]) groups[off[id]] = (int32_t)id;
 }
 
+// SPH receiver blocks: GX_BLOCK consecutive sorted slots and their tight box
+// (one wave per block).  SPH results do not depend on how receivers are
+// grouped, so full blocks keep every lane busy.
+__global__ __launch_bounds__(64) void k_blocks(int64_t n, const double4* __restrict__ pos4,
+                                               NodeRec* __restrict__ blk) {
+    const int64_t b = blockIdx.x;
+    const int64_t s = b * GX_BLOCK + threadIdx.x;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    if (s < n) {
+        double4 p = pos4[s];
+        lo[0] = hi[0] = p.x;
+        lo[1] = hi[1] = p.y;
+        lo[2] = hi[2] = p.z;
+    }
+    for (int d = 0; d < 3; d++) {
+        lo[d] = wave_min(lo[d]);
+        hi[d] = wave_max(hi[d]);
+    }
+    if (threadIdx.x == 0) {
+        NodeRec r;
+        for (int d = 0; d < 3; d++) {
+            r.lo[d] = lo[d];
+            r.hi[d] = hi[d];
+        }
+        r.begin = (int32_t)(b * GX_BLOCK);
+        r.end = (int32_t)min(n, (b + 1) * GX_BLOCK);
+        r.next = -1;
+        r.level = -1;
+        r.leaf = 0;
+        r.pad = 0;
+        blk[b] = r;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Host driver
 // ---------------------------------------------------------------------------
@@ -446,6 +489,7 @@ extern "C" int gx_tree_build(gx_ctx* ctx, const gx_particles* p, int which, int 
     GX_TRY(gx_reserve(ctx, T.mom, nn * sizeof(MomRec)));
     GX_TRY(gx_reserve(ctx, T.q64, nn * 6 * sizeof(double)));
     GX_TRY(gx_reserve(ctx, T.parent, nn * sizeof(int32_t)));
+    GX_TRY(gx_reserve(ctx, T.child, nn * 8 * sizeof(int32_t)));
     GX_TRY(gx_reserve(ctx, T.lvl_ids, nn * sizeof(int32_t)));
     GX_TRY(gx_reserve(ctx, T.flag, (nn + 1) * sizeof(uint32_t) * 2));
     // level offsets to the device, fill counters zeroed
@@ -455,7 +499,7 @@ extern "C" int gx_tree_build(gx_ctx* ctx, const gx_particles* p, int which, int 
                        (const int8_t*)T.lmax.p, nn, (NodeRec*)T.nodes.p, lvl_aux, lvl_hist,
                        (int32_t*)T.lvl_ids.p);
     hipLaunchKernelGGL(k_node_parent, dim3(gx_blocks(nn, 256)), dim3(256), 0, st, nn,
-                       (const NodeRec*)T.nodes.p, (int32_t*)T.parent.p);
+                       (const NodeRec*)T.nodes.p, (int32_t*)T.parent.p, (int32_t*)T.child.p);
     GX_LAUNCH_CHECK(ctx);
     for (int l = GX_MAX_LEVEL; l >= 0; l--) {
         int c = (int)T.lvl_hist[l];
@@ -479,6 +523,12 @@ extern "C" int gx_tree_build(gx_ctx* ctx, const gx_particles* p, int which, int 
     GX_TRY(gx_reserve(ctx, T.groups, T.n_groups * sizeof(int32_t)));
     hipLaunchKernelGGL(k_group_compact, dim3(gx_blocks(nn, 256)), dim3(256), 0, st, nn, flag, foff,
                        (int32_t*)T.groups.p);
+    GX_LAUNCH_CHECK(ctx);
+
+    T.n_blocks = (n + GX_BLOCK - 1) / GX_BLOCK;
+    GX_TRY(gx_reserve(ctx, T.blocks, T.n_blocks * sizeof(NodeRec)));
+    hipLaunchKernelGGL(k_blocks, dim3((unsigned)T.n_blocks), dim3(64), 0, st, n,
+                       (const double4*)T.pos4.p, (NodeRec*)T.blocks.p);
     GX_LAUNCH_CHECK(ctx);
 
     T.built = 1;

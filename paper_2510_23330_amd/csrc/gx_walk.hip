@@ -104,30 +104,34 @@ __global__ void k_direct_lists(int ng, int n, const int32_t* __restrict__ groups
     atomicAdd(&tot[2], (unsigned long long)(G.end - G.begin) * (unsigned long long)n);
 }
 
-// SPH candidate lists: leaves whose box lies within reach of the group box.
-// reach = max(R_G, hmax_c) where R_G is the group's search radius (density:
-// its largest kernel size times a margin; force: its largest kernel size) and
-// hmax_c the largest kernel size in the node (force only; 0 for density).
+// SPH candidate lists for receiver blocks: leaves whose box lies within reach
+// of the block box, reach = max(R_b, hmax_c), R_b the block's search radius
+// (density: margin x its largest kernel size; force: its largest kernel size)
+// and hmax_c the largest kernel size in the node (force only).
+// mode 0: count; mode 1: fill at pr_off; mode 2: single pass writing at
+// b * cap with per-block counts (entries past cap are counted, not written,
+// and the block is reported in tot[4]).
 __global__ __launch_bounds__(128) void k_walk_sph(
-    int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes,
+    int nb, const int32_t* __restrict__ recv, const NodeRec* __restrict__ nodes,
     const MomRec* __restrict__ mom, int nn, const float* __restrict__ radius, int use_hmax,
-    const uint8_t* __restrict__ active, int mode, uint32_t* __restrict__ pr_cnt,
+    const uint8_t* __restrict__ active, int mode, int cap, uint32_t* __restrict__ pr_cnt,
     uint32_t* __restrict__ pp_tot, unsigned long long* __restrict__ tot,
     const int64_t* __restrict__ pr_off, int32_t* __restrict__ pr_begin,
     int32_t* __restrict__ pr_cum) {
     int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ng) return;
+    if (g >= nb) return;
     if (active && !active[g]) {
-        if (!mode) {
+        if (mode != 1) {
             pr_cnt[g] = 0;
             pp_tot[g] = 0;
         }
         return;
     }
-    const NodeRec G = nodes[groups[g]];
+    const NodeRec G = nodes[recv[g]];
     const double RG = (double)radius[g];
     int npr = 0, npp = 0, last_end = -1;
-    int64_t pro = mode ? pr_off[g] : 0;
+    const int64_t pro = (mode == 1) ? pr_off[g] : (mode == 2 ? (int64_t)g * cap : 0);
+    const bool write = mode != 0;
     for (int n = 0; n < nn;) {
         const NodeRec& nd = nodes[n];
         double lo[3] = {nd.lo[0], nd.lo[1], nd.lo[2]};
@@ -143,7 +147,7 @@ __global__ __launch_bounds__(128) void k_walk_sph(
         } else if (nd.leaf) {
             int b = nd.begin, e = nd.end;
             if (b != last_end) {
-                if (mode) {
+                if (write && (mode == 1 || npr < cap)) {
                     pr_begin[pro + npr] = b;
                     pr_cum[pro + npr] = npp;
                 }
@@ -156,9 +160,122 @@ __global__ __launch_bounds__(128) void k_walk_sph(
             n = n + 1;
         }
     }
-    if (!mode) {
+    if (mode != 1) {
         pr_cnt[g] = (uint32_t)npr;
         pp_tot[g] = (uint32_t)npp;
         atomicAdd(&tot[2], (unsigned long long)(G.end - G.begin) * (unsigned long long)npp);
+        atomicAdd(&tot[1], (unsigned long long)npr);
+        if (mode == 2 && npr > cap) atomicAdd(&tot[4], 1ull);
+    }
+}
+
+// Wave-cooperative SPH walk: one wavefront per receiving group traverses the
+// tree breadth-first.  The 64 lanes test 64 frontier nodes at a time; leaves
+// within reach are appended to the group's fixed-capacity range slot (ballot
+// compaction, prefix sums of their sizes give the running offsets) and
+// intersecting internal nodes push their children (from the child table)
+// onto the next frontier in LDS.  Ranges come out level by level, not in key
+// order; consumers only rely on the running offsets.  A frontier or slot
+// overflow is reported in tot[4] (the caller then falls back to the
+// thread-per-group CSR walk).
+#define BFS_FMAX 2048
+__global__ __launch_bounds__(64) void k_walk_sph_bfs(
+    int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes,
+    const int32_t* __restrict__ child, const MomRec* __restrict__ mom,
+    const float* __restrict__ radius, int use_hmax, const uint8_t* __restrict__ active, int cap,
+    uint32_t* __restrict__ pr_cnt, uint32_t* __restrict__ pp_tot,
+    unsigned long long* __restrict__ tot, int32_t* __restrict__ pr_begin,
+    int32_t* __restrict__ pr_cum, uint8_t* __restrict__ ovf) {
+    const int g = xcd_remap(blockIdx.x, ng);
+    if (g >= ng) return;
+    const int lane = threadIdx.x;
+    if (active && !active[g]) {
+        if (lane == 0) {
+            pr_cnt[g] = 0;
+            pp_tot[g] = 0;
+            ovf[g] = 0;
+        }
+        return;
+    }
+    __shared__ int32_t fr[2][BFS_FMAX];
+    const NodeRec G = nodes[groups[g]];
+    const double RG = (double)radius[g];
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t slot = (int64_t)g * cap;
+    if (lane == 0) fr[0][0] = 0;
+    int cnt = 1, cur = 0, nout = 0, npp = 0, over = 0;
+    __syncthreads();
+    while (cnt > 0) {
+        int ncnt = 0;
+        for (int base = 0; base < cnt; base += 64) {
+            const int idx = base + lane;
+            bool inter = false, leaf = false;
+            int n = -1, b = 0, e = 0;
+            if (idx < cnt) {
+                n = fr[cur][idx];
+                const NodeRec& nd = nodes[n];
+                double lo[3] = {nd.lo[0], nd.lo[1], nd.lo[2]};
+                double hi[3] = {nd.hi[0], nd.hi[1], nd.hi[2]};
+                const double d2 = box_dist2(G.lo, G.hi, lo, hi);
+                double R = RG;
+                if (use_hmax) {
+                    const double hm = (double)mom[n].hmax;
+                    R = hm > R ? hm : R;
+                }
+                inter = d2 < R * R;
+                leaf = nd.leaf;
+                b = nd.begin;
+                e = nd.end;
+            }
+            // emit leaves
+            const bool emit = inter && leaf;
+            const uint64_t em = __ballot(emit);
+            const int sz = emit ? e - b : 0;
+            const int incl = wave_incl_scan(sz);
+            if (emit) {
+                const int pos = nout + __popcll(em & lt);
+                if (pos < cap) {
+                    pr_begin[slot + pos] = b;
+                    pr_cum[slot + pos] = npp + incl - sz;
+                }
+            }
+            nout += __popcll(em);
+            npp += __shfl(incl, 63, 64);
+            // open internal nodes
+            int nch = 0;
+            int32_t ch[8];
+            if (inter && !leaf) {
+#pragma unroll
+                for (int k = 0; k < 8; k++) {
+                    ch[k] = child[8 * (int64_t)n + k];
+                    nch += ch[k] >= 0;
+                }
+            }
+            const int cincl = wave_incl_scan(nch);
+            const int coff = ncnt + cincl - nch;
+            for (int k = 0; k < nch; k++) {
+                if (coff + k < BFS_FMAX) fr[cur ^ 1][coff + k] = ch[k];
+            }
+            ncnt += __shfl(cincl, 63, 64);
+        }
+        __syncthreads();
+        if (ncnt > BFS_FMAX) {
+            over = 1;
+            ncnt = BFS_FMAX;
+        }
+        cnt = ncnt;
+        cur ^= 1;
+    }
+    if (lane == 0) {
+        const bool bad = over || nout > cap;
+        ovf[g] = bad ? 1 : 0;
+        pr_cnt[g] = bad ? 0u : (uint32_t)nout;
+        pp_tot[g] = bad ? 0u : (uint32_t)npp;
+        if (bad) {
+            atomicAdd(&tot[4], 1ull);
+        } else {
+            atomicAdd(&tot[2], (unsigned long long)(G.end - G.begin) * (unsigned long long)npp);
+            atomicAdd(&tot[1], (unsigned long long)nout);
+        }
     }
 }
