@@ -234,3 +234,101 @@ def sample_indices(n: int, k: int, seed: int) -> np.ndarray:
     rng = _rng(seed)
     k = min(k, n)
     return np.sort(rng.choice(n, size=k, replace=False)).astype(np.int64)
+
+
+def _kolmogorov_field(rng, ngrid, slope, rms3d):
+    """Three independent Gaussian random velocity components on an ngrid^3
+    periodic grid with power |v_k|^2 ~ k^slope (slope = -11/3 for Kolmogorov),
+    scaled to a 3-D rms of rms3d."""
+    k = np.fft.fftfreq(ngrid) * ngrid
+    kx, ky, kz = np.meshgrid(k, k, k, indexing="ij")
+    kk = np.sqrt(kx * kx + ky * ky + kz * kz)
+    amp = np.zeros_like(kk)
+    nz = kk > 0
+    amp[nz] = kk[nz] ** (slope / 2.0)
+    comps = []
+    for _ in range(3):
+        noise = rng.normal(size=(ngrid, ngrid, ngrid)) + 1j * rng.normal(size=(ngrid, ngrid, ngrid))
+        comps.append(np.real(np.fft.ifftn(noise * amp)))
+    v = np.stack(comps)
+    v *= rms3d / np.sqrt(np.mean(np.sum(v * v, axis=0)))
+    return v
+
+
+def _trilinear(field, pos, side):
+    """Periodic trilinear interpolation of field[c, n, n, n] (cell-centred on a
+    cube of the given side starting at 0) at pos[3, m]."""
+    n = field.shape[1]
+    g = pos / side * n - 0.5
+    i0 = np.floor(g).astype(np.int64)
+    f = g - i0
+    out = np.zeros((field.shape[0], pos.shape[1]))
+    for dx in (0, 1):
+        wx = f[0] if dx else 1 - f[0]
+        for dy in (0, 1):
+            wy = f[1] if dy else 1 - f[1]
+            for dz in (0, 1):
+                wz = f[2] if dz else 1 - f[2]
+                ix = (i0[0] + dx) % n
+                iy = (i0[1] + dy) % n
+                iz = (i0[2] + dz) % n
+                out += field[:, ix, iy, iz] * (wx * wy * wz)
+    return out
+
+
+def sn_cube(seed: int, n_min: int = 2000, n_max: int = 32000, side: float = 60.0,
+            t_min: float = 100.0, t_max: float = 1e4, m_part: float = 1.0,
+            turb_rms: float = 5.0, turb_slope: float = -11.0 / 3.0, n_fixed: int = None):
+    """Gas cube around a supernova site (pc, km/s, Msun), centred on the origin.
+
+    N log-uniform in [n_min, n_max] (unless n_fixed), particle mass m_part, so
+    the number density follows from N (1 Msun in a (60 pc)^3 cube: n = N/7471
+    cm^-3).  Positions Poisson-uniform in the cube; temperature log-uniform in
+    [t_min, t_max], uniform across the cube; velocities from a Kolmogorov
+    Gaussian random field (64^3, 3-D rms turb_rms) interpolated trilinearly.
+    The explosion itself is not applied here.
+    """
+    rng = _rng(seed)
+    if n_fixed is None:
+        n = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+    else:
+        n = int(n_fixed)
+    T = math.exp(rng.uniform(math.log(t_min), math.log(t_max)))
+    pos = rng.uniform(0.0, side, (3, n))
+    vel = _trilinear(_kolmogorov_field(rng, 64, turb_slope, turb_rms), pos, side)
+    pos -= side / 2.0
+    m = np.full(n, m_part)
+    out = _pack(pos[0], pos[1], pos[2], vel[0], vel[1], vel[2], m,
+                np.full(n, 0.01, np.float32), np.full(n, T_GAS), u=np.full(n, T * U_PER_K))
+    out["T"] = T
+    out["n_cm3"] = n * m_part / side ** 3 / MSUN_PC3_PER_CM3
+    return out
+
+
+def sn_batch(seeds, spacing: float = 1000.0, **kw):
+    """Several SN cubes in one particle set, cube k centred at a point of a
+    cubic lattice of the given spacing (far enough apart that they never
+    interact).  Returns the packed set plus per-particle cube ids, per-cube
+    offsets [K+1] and centres [K, 3]."""
+    cubes = [sn_cube(s, **kw) for s in seeds]
+    K = len(cubes)
+    g = int(math.ceil(K ** (1.0 / 3.0)))
+    centres = np.array([((k % g), (k // g) % g, k // (g * g)) for k in range(K)],
+                       dtype=np.float64) * spacing
+    parts = {k: [] for k in ("x", "y", "z", "vx", "vy", "vz", "m", "eps2", "u")}
+    cube_id = []
+    for k, c in enumerate(cubes):
+        for a, d in zip(("x", "y", "z"), range(3)):
+            parts[a].append(c[a] + centres[k, d])
+        for a in ("vx", "vy", "vz", "m", "eps2", "u"):
+            parts[a].append(c[a])
+        cube_id.append(np.full(c["x"].size, k, np.int32))
+    out = _pack(*(np.concatenate(parts[a]) for a in ("x", "y", "z", "vx", "vy", "vz", "m")),
+                np.concatenate(parts["eps2"]), np.full(sum(c["x"].size for c in cubes), T_GAS),
+                u=np.concatenate(parts["u"]))
+    out["cube_id"] = np.concatenate(cube_id)
+    out["offsets"] = np.concatenate([[0], np.cumsum([c["x"].size for c in cubes])]).astype(np.int64)
+    out["centres"] = centres
+    out["T_amb"] = np.array([c["T"] for c in cubes])
+    out["n_cm3"] = np.array([c["n_cm3"] for c in cubes])
+    return out

@@ -251,6 +251,133 @@ int gx_gravity_list_sizes(gx_ctx* ctx, int64_t* n_groups, int64_t* n_pc, int64_t
 int gx_gravity_list_export(gx_ctx* ctx, int64_t* pc_off, int32_t* pc_node, int64_t* pp_off,
                            int32_t* pp_begin, int32_t* pp_end);
 
+/* ======================================================================== */
+/* Supernova surrogate (Sec. 3.2 steps 1-4, Sec. 3.3)                       */
+/* ======================================================================== */
+
+/*
+ * gx_sn_extract -- pick up the gas in the box of side 2 half_side around each
+ * of k SN sites (Sec. 3.2 step 2: the (60 pc)^3 box around the exploding
+ * star).  Membership: c - h <= x < c + h on every axis.
+ * gas      device particle view (x, y, z read), original order
+ * centers  device double [k][3]
+ * offsets  device int32 [k+1] (output CSR offsets); idx device int32 [cap]
+ *          (output: original indices, ascending within each cube)
+ * total    host: number of memberships.  Synchronises; GX_EINVAL if > cap.
+ */
+int gx_sn_extract(gx_ctx* ctx, const gx_particles* gas, const double* centers, int k,
+                  double half_side, int32_t* offsets, int32_t* idx, int64_t cap, int64_t* total);
+
+/*
+ * gx_sn_inject -- thermal energy injection of one SN (1e51 erg in the paper,
+ * Sec. 1): the k_inj members of each cube nearest its centre (ties broken by
+ * index) receive energy / (their total mass) of specific internal energy.
+ * gas: x, y, z, m read; offsets/idx from gx_sn_extract (device); u device,
+ * indexed like the gas arrays, updated in place.
+ */
+int gx_sn_inject(gx_ctx* ctx, const gx_particles* gas, const int32_t* offsets, const int32_t* idx,
+                 const double* centers, int k, int k_inj, double energy, double* u);
+
+/*
+ * gx_sn_voxelize -- particle-to-grid mapping by SPH kernel convolution with
+ * Shepard normalisation (Sec. 3.3) on grid^3 voxels covering a cube of the
+ * given side centred on each site:
+ *   rho_v = sum_j m_j W(|x_v - x_j|, H_j),
+ *   T_v = sum_j T_j W_j / sum_j W_j,  v_v = sum_j v_j W_j / sum_j W_j,
+ * W the Wendland C4 kernel of gx_sph_density, T = u * u_to_T.  Channels:
+ * log10 rho (floored at 1e-6 of the ambient density), log10 T (floored at
+ * 10 K), vx, vy, vz; voxels no kernel reaches take the ambient values.
+ * Uses the GX_TREE_GAS slot built from `gas` (every particle whose kernel
+ * reaches a voxel contributes, not only extracted members).
+ * u, H      device gas arrays (FP64 u, FP32 kernel size), original order
+ * amb       device float [k][5]: ambient (log10 rho, log10 T, vx, vy, vz)
+ * out_bf16  optional device bf16 [k][grid^3][cpad]: (channel - mean) / std,
+ *           channels 5..cpad-1 zero (chan_mean/chan_std device float [5])
+ * out_f32   optional device float [k][grid^3][5]: the physical channels
+ * Voxel order is z-major, x fastest; grid must be a multiple of 4.
+ */
+int gx_sn_voxelize(gx_ctx* ctx, const gx_particles* gas, const double* u, const float* H,
+                   const double* centers, int k, double side, int grid, double u_to_T,
+                   const float* amb, const float* chan_mean, const float* chan_std,
+                   uint16_t* out_bf16, int cpad, float* out_f32);
+
+/*
+ * gx_sn_resample -- grid-to-particle mapping (Sec. 3.3; the paper samples by
+ * Gibbs sampling, here by exact inverse-CDF draws from the same piecewise-
+ * constant density).  For cube c, out_off[c+1] - out_off[c] particles (as many
+ * as entered, so mass is conserved): voxel chosen with probability
+ * proportional to 10^(log10 rho_v) using uniforms[4j], position uniform in the
+ * voxel from uniforms[4j+1..3]; T and velocity of the voxel; u = T * T_to_u.
+ * pred      device float [k][grid^3][5] physical channels
+ * uniforms  device float [4 * total] in [0, 1)
+ * outputs   device double [total]; n_out_max = largest per-cube count
+ */
+int gx_sn_resample(gx_ctx* ctx, const float* pred, int k, int grid, double side,
+                   const double* centers, const int32_t* out_off, int64_t n_out_max,
+                   const float* uniforms, double T_to_u, double* x, double* y, double* z,
+                   double* vx, double* vy, double* vz, double* u);
+
+/*
+ * gx_sn_replace -- replace particles by ID (Sec. 3.2 step 4).  id: device
+ * int64 [n] ids of the main arrays (each in [0, id_cap)); new particles with
+ * ids new_id[m] overwrite position and velocity; u (device, index i - u_offset
+ * for main index i >= u_offset) and H64 (same indexing; set to -1 so the next
+ * kernel-size solve reseeds) may be NULL.  n_missing (host, may be NULL)
+ * counts new ids absent from the main set.  Synchronises when n_missing.
+ */
+int gx_sn_replace(gx_ctx* ctx, int64_t n, const int64_t* id, int64_t id_cap, double* x, double* y,
+                  double* z, double* vx, double* vy, double* vz, double* u, int64_t u_offset,
+                  double* H64, int64_t m, const int64_t* new_id, const double* nx, const double* ny,
+                  const double* nz, const double* nvx, const double* nvy, const double* nvz,
+                  const double* nu, int64_t* n_missing);
+
+/* ---- 3-D convolutional network blocks (BF16 operands, FP32 accumulate) ---
+ * Activations are NDHWC bf16 [B][S][S][S][C] (x fastest, channels innermost);
+ * weights bf16 [Cout][kvol][Cin] with kvol = 27 (3^3 kernel, zero padding 1,
+ * tap = (dz*3 + dy)*3 + dx) or 1; biases and master weights FP32.  Cin must
+ * be a multiple of 8 and Cout of 16 (pad with zero channels).
+ */
+
+/* out = act(conv(in, w) + bias); act 1 = LeakyReLU(0.1), 0 = identity.  Writes
+ * out_bf16 and/or out_f32 ([B][S^3][Cout]); bias may be NULL. */
+int gx_conv3d_fwd(gx_ctx* ctx, const uint16_t* in, int B, int S, int Cin, const uint16_t* w,
+                  const float* bias, int ksize, int Cout, int act, uint16_t* out_bf16,
+                  float* out_f32);
+/* din = dL/din from dout = dL/dout ([B][S^3][Cout]) for the layer of weights w
+ * ([Cout][kvol][Cin]); when y_in (the layer input, itself the LeakyReLU output
+ * of the previous layer) is given, din is multiplied by that activation's
+ * derivative.  Cin must be a multiple of 16. */
+int gx_conv3d_bwd_data(gx_ctx* ctx, const uint16_t* dout, int B, int S, int Cin, const uint16_t* w,
+                       int ksize, int Cout, const uint16_t* y_in, uint16_t* din);
+/* dw [Cout][kvol][Cin] += sum over voxels of dout x im2col(in); dbias [Cout] +=
+ * sum of dout (may be NULL).  Accumulates: zero them first. */
+int gx_conv3d_bwd_weight(gx_ctx* ctx, const uint16_t* in, const uint16_t* dout, int B, int S,
+                         int Cin, int ksize, int Cout, float* dw, float* dbias);
+/* 2^3 average pooling of in [B][S^3][C] -> out [B][(S/2)^3][C]; backward = 1:
+ * in is dL/dout at S/2 and out is dL/din at S. */
+int gx_avgpool2(gx_ctx* ctx, const uint16_t* in, int B, int S, int C, uint16_t* out, int backward);
+/* nearest x2 upsampling in [B][S^3][C] -> out [B][(2S)^3][C]; backward = 1:
+ * in is dL/dout at 2S, out is dL/din at S (sum of the 8 fine cells). */
+int gx_upsample2(gx_ctx* ctx, const uint16_t* in, int B, int S, int C, uint16_t* out, int backward);
+/* out[v] = (a[v], b[v]) along channels for V voxels; split = 1 reverses it. */
+int gx_concat(gx_ctx* ctx, uint16_t* a, int Ca, uint16_t* b, int Cb, int64_t V, uint16_t* out,
+              int split);
+/* loss = mean over V voxels and nc channels of (pred - target)^2 (pred fp32
+ * [V][Cp], target fp32 [V][nc]); dpred (bf16 [V][Cp], may be NULL) = dloss/dpred.
+ * loss: host.  Synchronises. */
+int gx_mse(gx_ctx* ctx, const float* pred, int Cp, const float* target, int nc, int64_t V,
+           uint16_t* dpred, double* loss);
+/* Adam (Kingma & Ba 2015) at step t >= 1 on n FP32 parameters with moments m,
+ * v; refreshes the bf16 copy when w_bf16 is non-NULL. */
+int gx_adam_step(gx_ctx* ctx, int64_t n, float* w, const float* grad, float* m, float* v,
+                 double lr, double b1, double b2, double eps, int64_t t, uint16_t* w_bf16);
+/* y = bf16(x), round to nearest even. */
+int gx_f32_to_bf16(gx_ctx* ctx, const float* x, int64_t n, uint16_t* y);
+/* out = (a + b) * LeakyReLU'(y) elementwise over n bf16 values (b, y may be
+ * NULL: no addition / no derivative); gradient routing at skip connections. */
+int gx_grad_combine(gx_ctx* ctx, int64_t n, const uint16_t* a, const uint16_t* b, const uint16_t* y,
+                    uint16_t* out);
+
 #ifdef __cplusplus
 }
 #endif

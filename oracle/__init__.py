@@ -78,6 +78,11 @@ def lib():
         L.orc_sph_density.restype = I64
         L.orc_sph_force.argtypes = [I64, P, P, P, P, P, P, P, P, P, P, D, D, I64, P,
                                     P, P, P, P, P]
+        ci = C.c_int
+        L.orc_conv3d_fwd.argtypes = [ci, ci, ci, ci, ci, P, P, P, P]
+        L.orc_conv3d_bwd_data.argtypes = [ci, ci, ci, ci, ci, P, P, P]
+        L.orc_conv3d_bwd_weight.argtypes = [ci, ci, ci, ci, ci, P, P, P, P]
+        L.orc_voxelize.argtypes = [I64] + [P] * 10 + [D, ci, P, D, D, P]
         _lib = L
     return _lib
 
@@ -297,3 +302,73 @@ def energy(m, v, pot, u_gas=None, m_gas=None):
     W = 0.5 * float(np.sum(m * _f64(pot)))
     U = 0.0 if u_gas is None else float(np.sum(_f64(m_gas) * _f64(u_gas)))
     return K, W, U
+
+
+# ---------------------------------------------------------------------------
+# Surrogate network (Sec. 3.3): convolution blocks and U-Net composition
+# ---------------------------------------------------------------------------
+def bf16_round(a):
+    """Round to the nearest bfloat16 (ties to even), returned as float64."""
+    a = np.ascontiguousarray(a, np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def conv3d(x, w, bias=None, ksize=3):
+    """x [B,S,S,S,Cin], w [Cout,kvol,Cin] -> [B,S,S,S,Cout] (FP64)."""
+    x = _f64(x)
+    w = _f64(w)
+    B, S, _, _, Cin = x.shape
+    Cout = w.shape[0]
+    out = np.zeros((B, S, S, S, Cout))
+    b = None if bias is None else _f64(bias)
+    lib().orc_conv3d_fwd(B, S, Cin, Cout, ksize, _ptr(x), _ptr(w), _ptr(b), _ptr(out))
+    return out
+
+
+def conv3d_bwd_data(dout, w, Cin, ksize=3):
+    dout = _f64(dout)
+    w = _f64(w)
+    B, S, _, _, Cout = dout.shape
+    din = np.zeros((B, S, S, S, Cin))
+    lib().orc_conv3d_bwd_data(B, S, Cin, Cout, ksize, _ptr(dout), _ptr(w), _ptr(din))
+    return din
+
+
+def conv3d_bwd_weight(x, dout, ksize=3):
+    x = _f64(x)
+    dout = _f64(dout)
+    B, S, _, _, Cin = x.shape
+    Cout = dout.shape[-1]
+    kv = 27 if ksize == 3 else 1
+    dw = np.zeros((Cout, kv, Cin))
+    db = np.zeros(Cout)
+    lib().orc_conv3d_bwd_weight(B, S, Cin, Cout, ksize, _ptr(x), _ptr(dout), _ptr(dw), _ptr(db))
+    return dw, db
+
+
+def lrelu(x, a=0.1):
+    return np.where(x > 0, x, a * x)
+
+
+def avgpool2(x):
+    B, S, _, _, C = x.shape
+    return x.reshape(B, S // 2, 2, S // 2, 2, S // 2, 2, C).mean(axis=(2, 4, 6))
+
+
+def upsample2(x):
+    return x.repeat(2, axis=1).repeat(2, axis=2).repeat(2, axis=3)
+
+
+def voxelize(p, u_to_T, center, side, grid, amb, rho_floor_frac=1e-6, t_floor=10.0, H=None):
+    """Brute-force particle-to-voxel mapping; returns [grid, grid, grid, 5]."""
+    Hh = _f64(p["H"] if H is None else H)
+    T = _f64(p["u"]) * u_to_T
+    out = np.zeros((grid ** 3, 5))
+    amb = _f64(amb)
+    lib().orc_voxelize(len(p["x"]), *(_ptr(_f64(p[k])) for k in ("x", "y", "z", "m")), _ptr(Hh),
+                       _ptr(T), *(_ptr(_f64(p[k])) for k in ("vx", "vy", "vz")),
+                       _ptr(_f64(center)), float(side), int(grid), _ptr(amb),
+                       float(rho_floor_frac * 10.0 ** amb[0]), float(t_floor), _ptr(out))
+    return out.reshape(grid, grid, grid, 5)

@@ -796,3 +796,139 @@ ORC_API void orc_sph_force(int64_t n, const double* x, const double* y, const do
     free(hs);
     orc_tree_free(T);
 }
+
+/* ------------------------------------------------------------------------ */
+/* 4. 3-D convolution (the U-Net of Sec. 3.3), naive loops in FP64            */
+/* ------------------------------------------------------------------------ */
+/* Layouts: x[b][z][y][x][c] (channels innermost); w[co][tap][ci] with
+ * tap = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1) for ksize 3 (zero padding 1),
+ * tap = 0 for ksize 1.
+ * out[b][p][co] = bias[co] + sum_{tap, ci} in[b][p + d(tap)][ci] w[co][tap][ci] */
+static int64_t vox(int b, int z, int y, int x, int S) {
+    return (((int64_t)b * S + z) * S + y) * S + x;
+}
+
+ORC_API void orc_conv3d_fwd(int B, int S, int Cin, int Cout, int ksize, const double* in,
+                            const double* w, const double* bias, double* out) {
+    int kv = ksize == 3 ? 27 : 1, r = ksize == 3 ? 1 : 0;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int b = 0; b < B; b++)
+        for (int z = 0; z < S; z++)
+            for (int y = 0; y < S; y++)
+                for (int x = 0; x < S; x++)
+                    for (int co = 0; co < Cout; co++) {
+                        double s = bias ? bias[co] : 0.0;
+                        for (int dz = -r; dz <= r; dz++)
+                            for (int dy = -r; dy <= r; dy++)
+                                for (int dx = -r; dx <= r; dx++) {
+                                    int Z = z + dz, Y = y + dy, X = x + dx;
+                                    if (Z < 0 || Z >= S || Y < 0 || Y >= S || X < 0 || X >= S) continue;
+                                    int tap = kv == 27 ? (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1) : 0;
+                                    const double* ip = in + vox(b, Z, Y, X, S) * Cin;
+                                    const double* wp = w + ((int64_t)co * kv + tap) * Cin;
+                                    for (int ci = 0; ci < Cin; ci++) s += ip[ci] * wp[ci];
+                                }
+                        out[vox(b, z, y, x, S) * Cout + co] = s;
+                    }
+}
+
+/* din[b][q][ci] = sum_{tap, co} dout[b][q - d(tap)][co] w[co][tap][ci] */
+ORC_API void orc_conv3d_bwd_data(int B, int S, int Cin, int Cout, int ksize, const double* dout,
+                                 const double* w, double* din) {
+    int kv = ksize == 3 ? 27 : 1, r = ksize == 3 ? 1 : 0;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int b = 0; b < B; b++)
+        for (int z = 0; z < S; z++)
+            for (int y = 0; y < S; y++)
+                for (int x = 0; x < S; x++)
+                    for (int ci = 0; ci < Cin; ci++) {
+                        double s = 0.0;
+                        for (int dz = -r; dz <= r; dz++)
+                            for (int dy = -r; dy <= r; dy++)
+                                for (int dx = -r; dx <= r; dx++) {
+                                    int Z = z - dz, Y = y - dy, X = x - dx;
+                                    if (Z < 0 || Z >= S || Y < 0 || Y >= S || X < 0 || X >= S) continue;
+                                    int tap = kv == 27 ? (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1) : 0;
+                                    const double* gp = dout + vox(b, Z, Y, X, S) * Cout;
+                                    for (int co = 0; co < Cout; co++)
+                                        s += gp[co] * w[((int64_t)co * kv + tap) * Cin + ci];
+                                }
+                        din[vox(b, z, y, x, S) * Cin + ci] = s;
+                    }
+}
+
+/* dw[co][tap][ci] = sum_{b, p} dout[b][p][co] in[b][p + d(tap)][ci]; db[co] = sum dout */
+ORC_API void orc_conv3d_bwd_weight(int B, int S, int Cin, int Cout, int ksize, const double* in,
+                                   const double* dout, double* dw, double* db) {
+    int kv = ksize == 3 ? 27 : 1, r = ksize == 3 ? 1 : 0;
+#pragma omp parallel for schedule(static)
+    for (int co = 0; co < Cout; co++) {
+        for (int t = 0; t < kv * Cin; t++) dw[(int64_t)co * kv * Cin + t] = 0.0;
+        double sb = 0.0;
+        for (int b = 0; b < B; b++)
+            for (int z = 0; z < S; z++)
+                for (int y = 0; y < S; y++)
+                    for (int x = 0; x < S; x++) {
+                        double g = dout[vox(b, z, y, x, S) * Cout + co];
+                        sb += g;
+                        for (int dz = -r; dz <= r; dz++)
+                            for (int dy = -r; dy <= r; dy++)
+                                for (int dx = -r; dx <= r; dx++) {
+                                    int Z = z + dz, Y = y + dy, X = x + dx;
+                                    if (Z < 0 || Z >= S || Y < 0 || Y >= S || X < 0 || X >= S) continue;
+                                    int tap = kv == 27 ? (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1) : 0;
+                                    const double* ip = in + vox(b, Z, Y, X, S) * Cin;
+                                    double* wp = dw + ((int64_t)co * kv + tap) * Cin;
+                                    for (int ci = 0; ci < Cin; ci++) wp[ci] += g * ip[ci];
+                                }
+                    }
+        if (db) db[co] = sb;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* 5. Particle-to-voxel mapping (Sec. 3.3): SPH kernel convolution for the    */
+/*    density, Shepard-normalised kernel averages for T and velocity          */
+/* ------------------------------------------------------------------------ */
+/* Voxel centres c - side/2 + (i + 1/2) side/grid; out[v][5] = log10 rho
+ * (floored at rho_floor), log10 T (floored at t_floor), vx, vy, vz; voxels
+ * with no kernel overlap take amb[0..4]. */
+ORC_API void orc_voxelize(int64_t n, const double* x, const double* y, const double* z,
+                          const double* m, const double* H, const double* T, const double* vx,
+                          const double* vy, const double* vz, const double* center, double side,
+                          int grid, const double* amb, double rho_floor, double t_floor,
+                          double* out) {
+    double dv = side / grid;
+    int64_t nv = (int64_t)grid * grid * grid;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t v = 0; v < nv; v++) {
+        int X = (int)(v % grid), Y = (int)((v / grid) % grid), Z = (int)(v / ((int64_t)grid * grid));
+        double px = center[0] - side / 2 + (X + 0.5) * dv;
+        double py = center[1] - side / 2 + (Y + 0.5) * dv;
+        double pz = center[2] - side / 2 + (Z + 0.5) * dv;
+        double sr = 0, sw = 0, st = 0, s1 = 0, s2 = 0, s3 = 0;
+        for (int64_t j = 0; j < n; j++) {
+            double dx = px - x[j], dy = py - y[j], dz = pz - z[j];
+            if (fabs(dx) >= H[j] || fabs(dy) >= H[j] || fabs(dz) >= H[j]) continue;
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            double w = orc_wendland_c4(r, H[j]);
+            sr += m[j] * w;
+            sw += w;
+            st += w * T[j];
+            s1 += w * vx[j];
+            s2 += w * vy[j];
+            s3 += w * vz[j];
+        }
+        double* o = out + v * 5;
+        o[0] = log10(sr > rho_floor ? sr : rho_floor);
+        if (sw > 0) {
+            double t = st / sw;
+            o[1] = log10(t > t_floor ? t : t_floor);
+            o[2] = s1 / sw;
+            o[3] = s2 / sw;
+            o[4] = s3 / sw;
+        } else {
+            for (int q = 1; q < 5; q++) o[q] = amb[q];
+        }
+    }
+}

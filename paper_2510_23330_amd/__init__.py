@@ -264,6 +264,120 @@ class Engine:
         o["pp_end"] = o["pp_end"][:npr.value]
         return o
 
+    # ---- supernova surrogate: SN regions -------------------------------------
+    def sn_extract(self, gas: ParticleSet, centers, half_side, cap):
+        """Members of the boxes around each site: (offsets[k+1], idx[total], total)."""
+        torch = _torch()
+        k = int(centers.shape[0])
+        offsets = torch.zeros(k + 1, dtype=torch.int32, device=centers.device)
+        idx = torch.zeros(max(1, int(cap)), dtype=torch.int32, device=centers.device)
+        tot = C.c_int64()
+        self._check(self.lib.gx_sn_extract(self.ctx, C.byref(gas.view()), _ptr(centers, torch.float64),
+                                           k, float(half_side), _ptr(offsets), _ptr(idx), int(cap),
+                                           C.byref(tot)))
+        return offsets, idx[:tot.value], tot.value
+
+    def sn_inject(self, gas: ParticleSet, offsets, idx, centers, k_inj, energy, u):
+        torch = _torch()
+        self._check(self.lib.gx_sn_inject(self.ctx, C.byref(gas.view()), _ptr(offsets, torch.int32),
+                                          _ptr(idx, torch.int32), _ptr(centers, torch.float64),
+                                          int(centers.shape[0]), int(k_inj), float(energy),
+                                          _ptr(u, torch.float64)))
+
+    def sn_voxelize(self, gas: ParticleSet, u, H, centers, side, grid, u_to_T, amb, mean=None,
+                    std=None, out_bf16=None, cpad=8, out_f32=None):
+        torch = _torch()
+        self._check(self.lib.gx_sn_voxelize(
+            self.ctx, C.byref(gas.view()), _ptr(u, torch.float64), _ptr(H, torch.float32),
+            _ptr(centers, torch.float64), int(centers.shape[0]), float(side), int(grid),
+            float(u_to_T), _ptr(amb, torch.float32), _ptr(mean, torch.float32),
+            _ptr(std, torch.float32), _ptr(out_bf16, torch.bfloat16), int(cpad),
+            _ptr(out_f32, torch.float32)))
+
+    def sn_resample(self, pred, centers, grid, side, out_off, n_out_max, uniforms, T_to_u, x, y, z,
+                    vx, vy, vz, u):
+        torch = _torch()
+        self._check(self.lib.gx_sn_resample(
+            self.ctx, _ptr(pred, torch.float32), int(centers.shape[0]), int(grid), float(side),
+            _ptr(centers, torch.float64), _ptr(out_off, torch.int32), int(n_out_max),
+            _ptr(uniforms, torch.float32), float(T_to_u), *(_ptr(t, torch.float64) for t in
+                                                              (x, y, z, vx, vy, vz, u))))
+
+    def sn_replace(self, id, id_cap, x, y, z, vx, vy, vz, u, u_offset, H64, new_id, nx, ny, nz, nvx,
+                   nvy, nvz, nu):
+        torch = _torch()
+        miss = C.c_int64()
+        self._check(self.lib.gx_sn_replace(
+            self.ctx, int(id.shape[0]), _ptr(id, torch.int64), int(id_cap),
+            *(_ptr(t, torch.float64) for t in (x, y, z, vx, vy, vz, u)), int(u_offset),
+            _ptr(H64, torch.float64), int(new_id.shape[0]), _ptr(new_id, torch.int64),
+            *(_ptr(t, torch.float64) for t in (nx, ny, nz, nvx, nvy, nvz, nu)), C.byref(miss)))
+        return miss.value
+
+    # ---- supernova surrogate: network blocks ------------------------------------
+    def conv3d_fwd(self, x, B, S, Cin, w, bias, ksize, Cout, act, out_bf16=None, out_f32=None):
+        torch = _torch()
+        self._check(self.lib.gx_conv3d_fwd(self.ctx, _ptr(x, torch.bfloat16), B, S, Cin,
+                                           _ptr(w, torch.bfloat16), _ptr(bias, torch.float32),
+                                           ksize, Cout, int(act), _ptr(out_bf16, torch.bfloat16),
+                                           _ptr(out_f32, torch.float32)))
+
+    def conv3d_bwd_data(self, dout, B, S, Cin, w, ksize, Cout, y_in, din):
+        torch = _torch()
+        self._check(self.lib.gx_conv3d_bwd_data(self.ctx, _ptr(dout, torch.bfloat16), B, S, Cin,
+                                                _ptr(w, torch.bfloat16), ksize, Cout,
+                                                _ptr(y_in, torch.bfloat16),
+                                                _ptr(din, torch.bfloat16)))
+
+    def conv3d_bwd_weight(self, x, dout, B, S, Cin, ksize, Cout, dw, dbias=None):
+        torch = _torch()
+        self._check(self.lib.gx_conv3d_bwd_weight(self.ctx, _ptr(x, torch.bfloat16),
+                                                  _ptr(dout, torch.bfloat16), B, S, Cin, ksize,
+                                                  Cout, _ptr(dw, torch.float32),
+                                                  _ptr(dbias, torch.float32)))
+
+    def avgpool2(self, x, B, S, Cc, out, backward=False):
+        torch = _torch()
+        self._check(self.lib.gx_avgpool2(self.ctx, _ptr(x, torch.bfloat16), B, S, Cc,
+                                         _ptr(out, torch.bfloat16), int(backward)))
+
+    def upsample2(self, x, B, S, Cc, out, backward=False):
+        torch = _torch()
+        self._check(self.lib.gx_upsample2(self.ctx, _ptr(x, torch.bfloat16), B, S, Cc,
+                                          _ptr(out, torch.bfloat16), int(backward)))
+
+    def concat(self, a, Ca, b, Cb, V, out, split=False):
+        torch = _torch()
+        self._check(self.lib.gx_concat(self.ctx, _ptr(a, torch.bfloat16), Ca,
+                                       _ptr(b, torch.bfloat16), Cb, int(V),
+                                       _ptr(out, torch.bfloat16), int(split)))
+
+    def mse(self, pred, Cp, target, nc, V, dpred=None):
+        torch = _torch()
+        loss = C.c_double()
+        self._check(self.lib.gx_mse(self.ctx, _ptr(pred, torch.float32), Cp,
+                                    _ptr(target, torch.float32), nc, int(V),
+                                    _ptr(dpred, torch.bfloat16), C.byref(loss)))
+        return loss.value
+
+    def adam_step(self, w, grad, m, v, lr, b1, b2, eps, t, w_bf16=None):
+        torch = _torch()
+        self._check(self.lib.gx_adam_step(self.ctx, int(w.numel()), _ptr(w, torch.float32),
+                                          _ptr(grad, torch.float32), _ptr(m, torch.float32),
+                                          _ptr(v, torch.float32), float(lr), float(b1), float(b2),
+                                          float(eps), int(t), _ptr(w_bf16, torch.bfloat16)))
+
+    def grad_combine(self, a, b, y, out):
+        torch = _torch()
+        self._check(self.lib.gx_grad_combine(self.ctx, int(a.numel()), _ptr(a, torch.bfloat16),
+                                             _ptr(b, torch.bfloat16), _ptr(y, torch.bfloat16),
+                                             _ptr(out, torch.bfloat16)))
+
+    def f32_to_bf16(self, x, y):
+        torch = _torch()
+        self._check(self.lib.gx_f32_to_bf16(self.ctx, _ptr(x, torch.float32), int(x.numel()),
+                                            _ptr(y, torch.bfloat16)))
+
 
 def version() -> str:
     return _lib.load().gx_version().decode()

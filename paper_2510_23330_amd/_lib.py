@@ -64,6 +64,23 @@ SIGNATURES = {
     "gx_tree_export": (I32, [P, I32] + [P] * 15),
     "gx_gravity_list_sizes": (I32, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)]),
     "gx_gravity_list_export": (I32, [P, P, P, P, P, P]),
+    "gx_sn_extract": (I32, [P, C.POINTER(GxParticles), P, I32, D, P, P, I64, C.POINTER(I64)]),
+    "gx_sn_inject": (I32, [P, C.POINTER(GxParticles), P, P, P, I32, I32, D, P]),
+    "gx_sn_voxelize": (I32, [P, C.POINTER(GxParticles), P, P, P, I32, D, I32, D, P, P, P, P,
+                             I32, P]),
+    "gx_sn_resample": (I32, [P, P, I32, I32, D, P, P, I64, P, D, P, P, P, P, P, P, P]),
+    "gx_sn_replace": (I32, [P, I64, P, I64, P, P, P, P, P, P, P, I64, P, I64, P, P, P, P, P, P, P,
+                            P, C.POINTER(I64)]),
+    "gx_conv3d_fwd": (I32, [P, P, I32, I32, I32, P, P, I32, I32, I32, P, P]),
+    "gx_conv3d_bwd_data": (I32, [P, P, I32, I32, I32, P, I32, I32, P, P]),
+    "gx_conv3d_bwd_weight": (I32, [P, P, P, I32, I32, I32, I32, I32, P, P]),
+    "gx_avgpool2": (I32, [P, P, I32, I32, I32, P, I32]),
+    "gx_upsample2": (I32, [P, P, I32, I32, I32, P, I32]),
+    "gx_concat": (I32, [P, P, I32, P, I32, I64, P, I32]),
+    "gx_mse": (I32, [P, P, I32, P, I32, I64, P, C.POINTER(D)]),
+    "gx_adam_step": (I32, [P, I64, P, P, P, P, D, D, D, D, I64, P]),
+    "gx_f32_to_bf16": (I32, [P, P, I64, P]),
+    "gx_grad_combine": (I32, [P, I64, P, P, P, P]),
 }
 
 _lib = None

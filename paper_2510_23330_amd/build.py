@@ -27,6 +27,8 @@ SOURCES = {
     "gx_gravity.hip": [],
     "gx_integrate.hip": [],
     "gx_sph.hip": [],
+    "gx_sn.hip": [],
+    "gx_nn.hip": [],
 }
 ARCH = os.environ.get("GX_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INC, "-I", CSRC,

@@ -187,3 +187,56 @@ __device__ __forceinline__ int xcd_remap(int b, int n_items) {
     return (b % 8) * per + b / 8;
 }
 static inline unsigned xcd_grid(int64_t n_items) { return (unsigned)(8 * ((n_items + 7) / 8)); }
+
+// ---------------------------------------------------------------------------
+// SPH-style candidate lists (used by the SPH and voxelisation kernels)
+// ---------------------------------------------------------------------------
+// Candidate lists of all groups: fixed-capacity slots (group g at g * cap)
+// from the wave walk, and -- for the groups flagged in `ovf` whose lists did
+// not fit -- CSR lists from the thread walk.
+struct ListView {
+    int cap;
+    const uint32_t* cnt;
+    const int32_t* begin;
+    const int32_t* cum;
+    const uint32_t* tot;
+    const uint8_t* ovf;  // may be null: no overflow lists
+    const int64_t* off2;
+    const uint32_t* cnt2;
+    const int32_t* begin2;
+    const int32_t* cum2;
+    const uint32_t* tot2;
+};
+
+// One group's list: ranges [r0, r1) of begin/cum, npp candidates in total.
+struct GroupList {
+    const int32_t* begin;
+    const int32_t* cum;
+    int64_t r0, r1;
+    int npp;
+    __device__ __forceinline__ GroupList(const ListView& L, int g) {
+        if (L.ovf && L.ovf[g]) {
+            begin = L.begin2;
+            cum = L.cum2;
+            r0 = L.off2[g];
+            r1 = r0 + L.cnt2[g];
+            npp = (int)L.tot2[g];
+        } else {
+            begin = L.begin;
+            cum = L.cum;
+            r0 = (int64_t)g * L.cap;
+            r1 = r0 + L.cnt[g];
+            npp = (int)L.tot[g];
+        }
+    }
+};
+
+// Build candidate lists for ng receivers (tree groups `groups`, or boxes
+// `recv` when non-null) on a tree slot: leaves within max(rad[g], node hmax
+// when use_hmax) of the receiver box.
+int gx_sph_walk(gx_ctx* ctx, TreeSlot& T, ListSet& Ls, int ng, const int32_t* groups,
+                const NodeRec* recv, const float* rad, int use_hmax, const uint8_t* active,
+                ListView* view, int64_t* list_pairs);
+// Largest kernel size per node from sorted per-slot (H, ...) records.
+int gx_sph_node_hmax(gx_ctx* ctx, TreeSlot& T, const float4* ss);
+int gx_tree_check(gx_ctx* ctx, int which, const gx_particles* p);

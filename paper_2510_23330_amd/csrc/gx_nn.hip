@@ -1,0 +1,590 @@
+// gx_nn.hip -- 3-D convolutional encoder-decoder building blocks for the
+// supernova surrogate (Sec. 3.3: a U-Net of 3-D convolutions trained with a
+// mean-squared error and Adam): BF16 activations and weights, FP32
+// accumulation on the gfx950 matrix cores.
+//
+// Layouts (NDHWC, channels innermost):
+//   activations  x[B][S][S][S][C]            bf16 (C % 8 == 0)
+//   weights      w[Cout][kvol][Cin]           bf16, kvol = 27 (3^3, pad 1) or 1
+//                (row co holds the GEMM column, K index = tap * Cin + ci,
+//                 tap = (dz * 3 + dy) * 3 + dx)
+//   master copy  w32 in the same layout, FP32; gradients FP32.
+//
+// Forward convolution as an implicit GEMM: M = B S^3 output voxels, N = Cout,
+// K = kvol Cin.  A workgroup (4 waves) computes a 128 x BN tile; each K step
+// stages a 128 x 32 slice of the implicit im2col matrix (zero padding at the
+// volume faces) and a BN x 32 slice of the weights in LDS, and each wave runs
+// v_mfma_f32_16x16x32_bf16 on its 32 x BN sub-tile.  The epilogue adds the
+// bias, applies LeakyReLU or, for a gradient pass, multiplies by the
+// activation derivative of a stored layer output, and writes bf16 or fp32.
+// Backward data is the same kernel on weights with flipped taps and swapped
+// channel roles; backward weight reduces im2col^T x dOut over voxel chunks
+// (transposed through LDS) into FP32 with atomics.
+#include "gx_internal.hpp"
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+#define CV_BM 128
+#define CV_BK 32
+#define CV_APITCH 40  // bf16 per LDS row (32 + 8 padding)
+#define LRELU_SLOPE 0.1f
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+struct ConvGeom {
+    int B, S, Cin, Cout, kvol;
+    int64_t M;  // B * S^3
+    int K;      // kvol * Cin
+};
+
+// Load 8 consecutive K entries (one tap, 8 channels) of im2col row m.
+__device__ __forceinline__ uint4 im2col8(const uint16_t* __restrict__ in, const ConvGeom& g,
+                                         int64_t m, int k) {
+    uint4 z = make_uint4(0, 0, 0, 0);
+    if (m >= g.M || k >= g.K) return z;
+    const int tap = k / g.Cin, ci = k - tap * g.Cin;
+    const int S = g.S;
+    int64_t t = m;
+    const int x = (int)(t % S);
+    t /= S;
+    const int y = (int)(t % S);
+    t /= S;
+    const int zz = (int)(t % S);
+    const int64_t b = t / S;
+    int dx = 0, dy = 0, dz = 0;
+    if (g.kvol == 27) {
+        dz = tap / 9 - 1;
+        dy = (tap / 3) % 3 - 1;
+        dx = tap % 3 - 1;
+    }
+    const int X = x + dx, Y = y + dy, Z = zz + dz;
+    if (X < 0 || X >= S || Y < 0 || Y >= S || Z < 0 || Z >= S) return z;
+    const int64_t v = ((b * S + Z) * S + Y) * S + X;
+    return *reinterpret_cast<const uint4*>(in + v * g.Cin + ci);
+}
+
+// epilogue modes
+enum { EP_NONE = 0, EP_LRELU = 1, EP_DACT = 2 };
+
+template <int BN>
+__global__ __launch_bounds__(256) void k_conv3d(const uint16_t* __restrict__ in,
+                                                const uint16_t* __restrict__ w,
+                                                const float* __restrict__ bias, ConvGeom g,
+                                                int mode, const uint16_t* __restrict__ yref,
+                                                uint16_t* __restrict__ out_bf,
+                                                float* __restrict__ out_f32) {
+    __shared__ __attribute__((aligned(16))) uint16_t sA[CV_BM * CV_APITCH];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[BN * CV_APITCH];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t m0 = (int64_t)blockIdx.x * CV_BM;
+    const int n0 = blockIdx.y * BN;
+    constexpr int NT = BN / 16;  // MFMA column tiles per wave
+    f32x4 acc[2][NT];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < NT; j++) acc[i][j] = f32x4{0, 0, 0, 0};
+
+    for (int k0 = 0; k0 < g.K; k0 += CV_BK) {
+        // stage A: 128 rows x 4 groups of 8
+#pragma unroll
+        for (int r = 0; r < 2; r++) {
+            const int e = tid + r * 256;
+            const int row = e >> 2, grp = e & 3;
+            const uint4 v = im2col8(in, g, m0 + row, k0 + grp * 8);
+            *reinterpret_cast<uint4*>(&sA[row * CV_APITCH + grp * 8]) = v;
+        }
+        // stage B: BN rows (output channels) x 4 groups of 8
+        if (tid < BN * 4) {
+            const int row = tid >> 2, grp = tid & 3;
+            const int k = k0 + grp * 8;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (k < g.K) v = *reinterpret_cast<const uint4*>(w + (int64_t)(n0 + row) * g.K + k);
+            *reinterpret_cast<uint4*>(&sB[row * CV_APITCH + grp * 8]) = v;
+        }
+        __syncthreads();
+        const int kq = (lane >> 4) * 8;
+        bf16x8 a[2], b[NT];
+#pragma unroll
+        for (int i = 0; i < 2; i++)
+            a[i] = *reinterpret_cast<const bf16x8*>(&sA[(wv * 32 + i * 16 + (lane & 15)) * CV_APITCH + kq]);
+#pragma unroll
+        for (int j = 0; j < NT; j++)
+            b[j] = *reinterpret_cast<const bf16x8*>(&sB[(j * 16 + (lane & 15)) * CV_APITCH + kq]);
+#pragma unroll
+        for (int i = 0; i < 2; i++)
+#pragma unroll
+            for (int j = 0; j < NT; j++)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    // epilogue: lane holds rows 4*(lane/16) + t of each 16 x 16 tile, column lane % 16
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < NT; j++) {
+            const int col = n0 + j * 16 + (lane & 15);
+            const float bv = bias ? bias[col] : 0.0f;
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                const int64_t m = m0 + wv * 32 + i * 16 + (lane >> 4) * 4 + t;
+                if (m >= g.M) continue;
+                float v = acc[i][j][t] + bv;
+                const int64_t o = m * g.Cout + col;
+                if (mode == EP_LRELU) {
+                    v = v > 0.0f ? v : LRELU_SLOPE * v;
+                } else if (mode == EP_DACT) {
+                    v = bf2f(yref[o]) > 0.0f ? v : LRELU_SLOPE * v;
+                }
+                if (out_bf) out_bf[o] = f2bf(v);
+                if (out_f32) out_f32[o] = v;
+            }
+        }
+}
+
+// Weights for the data gradient: w'[ci][tap'][co] = w[co][26 - tap'][ci] (or
+// the same tap for 1^3 kernels), so that backward data is a forward pass.
+__global__ void k_wflip(const uint16_t* __restrict__ w, int Cout, int Cin, int kvol,
+                        uint16_t* __restrict__ wf) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t n = (int64_t)Cout * Cin * kvol;
+    if (e >= n) return;
+    const int co = (int)(e % Cout);
+    int64_t t = e / Cout;
+    const int tap = (int)(t % kvol);
+    const int ci = (int)(t / kvol);
+    const int src_tap = kvol == 27 ? 26 - tap : tap;
+    wf[((int64_t)ci * kvol + tap) * Cout + co] = w[((int64_t)co * kvol + src_tap) * Cin + ci];
+}
+
+// Backward weight: dW[co][k] += sum_m dOut[m][co] * A[m][k] over a chunk of
+// voxels per block.  Tiles: 64 K entries x BN output channels, voxels in steps
+// of 32, both operands transposed into LDS so MFMA fragments are contiguous.
+template <int BN>
+__global__ __launch_bounds__(256) void k_conv3d_wgrad(const uint16_t* __restrict__ in,
+                                                      const uint16_t* __restrict__ dout,
+                                                      ConvGeom g, int64_t m_per_block,
+                                                      float* __restrict__ dw) {
+    constexpr int BKW = 64;                  // K tile (rows of dW^T)
+    __shared__ __attribute__((aligned(16))) uint16_t sAt[BKW * CV_APITCH];  // [k][m]
+    __shared__ __attribute__((aligned(16))) uint16_t sBt[BN * CV_APITCH];   // [co][m]
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int k0 = blockIdx.x * BKW;
+    const int n0 = blockIdx.y * BN;
+    const int64_t mb = (int64_t)blockIdx.z * m_per_block;
+    const int64_t me = min(g.M, mb + m_per_block);
+    constexpr int NT = BN / 16;
+    // wave wv owns K rows [wv * 16, +16) x all BN columns
+    f32x4 acc[NT];
+#pragma unroll
+    for (int j = 0; j < NT; j++) acc[j] = f32x4{0, 0, 0, 0};
+    for (int64_t m0 = mb; m0 < me; m0 += 32) {
+        // A^T: 32 voxels x 64 K entries -> 256 loads of 8 K entries
+        {
+            const int mrow = tid >> 3, grp = tid & 7;
+            const int64_t m = m0 + mrow;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (m < me) v = im2col8(in, g, m, k0 + grp * 8);
+            const uint16_t* h = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+            for (int q = 0; q < 8; q++) sAt[(grp * 8 + q) * CV_APITCH + mrow] = h[q];
+        }
+        // dOut^T: 32 voxels x BN channels
+        for (int e = tid; e < 32 * (BN / 8); e += 256) {
+            const int mrow = e / (BN / 8), grp = e % (BN / 8);
+            const int64_t m = m0 + mrow;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (m < me) v = *reinterpret_cast<const uint4*>(dout + m * g.Cout + n0 + grp * 8);
+            const uint16_t* h = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+            for (int q = 0; q < 8; q++) sBt[(grp * 8 + q) * CV_APITCH + mrow] = h[q];
+        }
+        __syncthreads();
+        const int kq = (lane >> 4) * 8;
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&sAt[(wv * 16 + (lane & 15)) * CV_APITCH + kq]);
+#pragma unroll
+        for (int j = 0; j < NT; j++) {
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sBt[(j * 16 + (lane & 15)) * CV_APITCH + kq]);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // acc[j][t]: row (K) = wv*16 + 4*(lane/16) + t, column (co) = j*16 + lane%16
+#pragma unroll
+    for (int j = 0; j < NT; j++)
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const int k = k0 + wv * 16 + (lane >> 4) * 4 + t;
+            const int co = n0 + j * 16 + (lane & 15);
+            if (k < g.K) atomicAdd(&dw[(int64_t)co * g.K + k], acc[j][t]);
+        }
+}
+
+__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ dout, int64_t M,
+                                                   int C, float* __restrict__ db) {
+    // block: one channel-group of 64 channels? simple: each thread strides voxels for a channel
+    const int c = blockIdx.y;
+    float s = 0.0f;
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < M;
+         m += (int64_t)gridDim.x * blockDim.x)
+        s += bf2f(dout[m * C + c]);
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&db[c], s);
+}
+
+// ---------------------------------------------------------------------------
+// Pooling, upsampling, concatenation (bf16, NDHWC)
+// ---------------------------------------------------------------------------
+__global__ void k_avgpool2(const uint16_t* __restrict__ in, int B, int S, int C,
+                           uint16_t* __restrict__ out) {
+    const int So = S / 2;
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t n = (int64_t)B * So * So * So * C;
+    if (e >= n) return;
+    const int c = (int)(e % C);
+    int64_t t = e / C;
+    const int x = (int)(t % So);
+    t /= So;
+    const int y = (int)(t % So);
+    t /= So;
+    const int z = (int)(t % So);
+    const int64_t b = t / So;
+    float s = 0.0f;
+    for (int d = 0; d < 8; d++) {
+        const int X = 2 * x + (d & 1), Y = 2 * y + ((d >> 1) & 1), Z = 2 * z + (d >> 2);
+        s += bf2f(in[(((b * S + Z) * S + Y) * S + X) * C + c]);
+    }
+    out[e] = f2bf(0.125f * s);
+}
+
+__global__ void k_avgpool2_bwd(const uint16_t* __restrict__ dout, int B, int S, int C,
+                               uint16_t* __restrict__ din) {
+    // din at fine resolution S; dout at S/2
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t n = (int64_t)B * S * S * S * C;
+    if (e >= n) return;
+    const int c = (int)(e % C);
+    int64_t t = e / C;
+    const int x = (int)(t % S);
+    t /= S;
+    const int y = (int)(t % S);
+    t /= S;
+    const int z = (int)(t % S);
+    const int64_t b = t / S;
+    const int So = S / 2;
+    din[e] = f2bf(0.125f * bf2f(dout[(((b * So + z / 2) * So + y / 2) * So + x / 2) * C + c]));
+}
+
+__global__ void k_upsample2(const uint16_t* __restrict__ in, int B, int S, int C,
+                            uint16_t* __restrict__ out) {
+    // in at S, out at 2S (nearest)
+    const int So = 2 * S;
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t n = (int64_t)B * So * So * So * C;
+    if (e >= n) return;
+    const int c = (int)(e % C);
+    int64_t t = e / C;
+    const int x = (int)(t % So);
+    t /= So;
+    const int y = (int)(t % So);
+    t /= So;
+    const int z = (int)(t % So);
+    const int64_t b = t / So;
+    out[e] = in[(((b * S + z / 2) * S + y / 2) * S + x / 2) * C + c];
+}
+
+__global__ void k_upsample2_bwd(const uint16_t* __restrict__ dout, int B, int S, int C,
+                                uint16_t* __restrict__ din) {
+    // din at S (coarse), dout at 2S: sum of the 8 fine cells
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t n = (int64_t)B * S * S * S * C;
+    if (e >= n) return;
+    const int c = (int)(e % C);
+    int64_t t = e / C;
+    const int x = (int)(t % S);
+    t /= S;
+    const int y = (int)(t % S);
+    t /= S;
+    const int z = (int)(t % S);
+    const int64_t b = t / S;
+    const int Sf = 2 * S;
+    float s = 0.0f;
+    for (int d = 0; d < 8; d++) {
+        const int X = 2 * x + (d & 1), Y = 2 * y + ((d >> 1) & 1), Z = 2 * z + (d >> 2);
+        s += bf2f(dout[(((b * Sf + Z) * Sf + Y) * Sf + X) * C + c]);
+    }
+    din[e] = f2bf(s);
+}
+
+// out[v][0:Ca] = a[v], out[v][Ca:Ca+Cb] = b[v]; split is the reverse.
+__global__ void k_concat(const uint16_t* __restrict__ a, int Ca, const uint16_t* __restrict__ b,
+                         int Cb, int64_t V, uint16_t* __restrict__ out, int split) {
+    const int C = Ca + Cb;
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= V * C) return;
+    const int64_t v = e / C;
+    const int c = (int)(e % C);
+    if (!split) {
+        out[e] = c < Ca ? a[v * Ca + c] : b[v * Cb + (c - Ca)];
+    } else {  // a and b are outputs (const cast by caller contract)
+        uint16_t* aa = const_cast<uint16_t*>(a);
+        uint16_t* bb = const_cast<uint16_t*>(b);
+        if (c < Ca) aa[v * Ca + c] = out[e];
+        else bb[v * Cb + (c - Ca)] = out[e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Loss and optimiser
+// ---------------------------------------------------------------------------
+// Mean squared error over the first nc channels of pred[V][Cp] vs target[V][nc]
+// (fp32); writes dL/dpred (bf16, padding channels zero) and per-block partial
+// sums of the squared error.
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ pred, int Cp,
+                                             const float* __restrict__ target, int nc, int64_t V,
+                                             float scale, uint16_t* __restrict__ dpred,
+                                             double* __restrict__ part) {
+    double s = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < V * Cp;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = e / Cp;
+        const int c = (int)(e % Cp);
+        float d = 0.0f;
+        if (c < nc) {
+            d = pred[e] - target[v * nc + c];
+            s += (double)d * d;
+        }
+        if (dpred) dpred[e] = f2bf(2.0f * d * scale);
+    }
+    s = wave_sum(s);
+    __shared__ double sh[4];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// Adam (Kingma & Ba): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+// w -= lr * mhat / (sqrt(vhat) + eps), mhat = m / (1 - b1^t), vhat = v / (1 - b2^t).
+// Also refreshes the bf16 copy of the weights.
+__global__ __launch_bounds__(256) void k_adam(int64_t n, float* __restrict__ w,
+                                              const float* __restrict__ g, float* __restrict__ m,
+                                              float* __restrict__ v, float lr, float b1, float b2,
+                                              float eps, float c1, float c2,
+                                              uint16_t* __restrict__ wbf) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    if (wbf) wbf[i] = f2bf(wi);
+}
+
+// out = (a + b) * (y > 0 ? 1 : slope) with b and y optional (gradient routing
+// at skip, pooling and upsampling junctions of the network).
+__global__ void k_grad_combine(int64_t n, const uint16_t* __restrict__ a,
+                               const uint16_t* __restrict__ b, const uint16_t* __restrict__ y,
+                               uint16_t* __restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float v = bf2f(a[i]);
+    if (b) v += bf2f(b[i]);
+    if (y && !(bf2f(y[i]) > 0.0f)) v *= LRELU_SLOPE;
+    out[i] = f2bf(v);
+}
+
+__global__ void k_f32_to_bf16(const float* __restrict__ x, int64_t n, uint16_t* __restrict__ y) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = f2bf(x[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Host entry points
+// ---------------------------------------------------------------------------
+static int check_conv(gx_ctx* ctx, int B, int S, int Cin, int Cout, int ksize) {
+    if (B < 1 || S < 1 || Cin < 8 || Cin % 8 || Cout < 16 || Cout % 16 || (ksize != 3 && ksize != 1))
+        return gx_fail(ctx, GX_EINVAL,
+                       "conv3d: need B, S >= 1, Cin % 8 == 0, Cout % 16 == 0, ksize 1 or 3");
+    return GX_OK;
+}
+
+static int launch_conv(gx_ctx* ctx, const uint16_t* in, const uint16_t* w, const float* bias,
+                       const ConvGeom& g, int mode, const uint16_t* yref, uint16_t* ob,
+                       float* of) {
+    const unsigned gx = (unsigned)((g.M + CV_BM - 1) / CV_BM);
+    if (g.Cout % 64 == 0)
+        hipLaunchKernelGGL(k_conv3d<64>, dim3(gx, g.Cout / 64), dim3(256), 0, ctx->stream, in, w,
+                           bias, g, mode, yref, ob, of);
+    else if (g.Cout % 32 == 0)
+        hipLaunchKernelGGL(k_conv3d<32>, dim3(gx, g.Cout / 32), dim3(256), 0, ctx->stream, in, w,
+                           bias, g, mode, yref, ob, of);
+    else
+        hipLaunchKernelGGL(k_conv3d<16>, dim3(gx, g.Cout / 16), dim3(256), 0, ctx->stream, in, w,
+                           bias, g, mode, yref, ob, of);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+extern "C" int gx_conv3d_fwd(gx_ctx* ctx, const uint16_t* in, int B, int S, int Cin,
+                             const uint16_t* w, const float* bias, int ksize, int Cout, int act,
+                             uint16_t* out_bf16, float* out_f32) {
+    if (!ctx || !in || !w || (!out_bf16 && !out_f32)) return GX_EINVAL;
+    GX_TRY(check_conv(ctx, B, S, Cin, Cout, ksize));
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    const int kv = ksize == 3 ? 27 : 1;
+    ConvGeom g{B, S, Cin, Cout, kv, (int64_t)B * S * S * S, kv * Cin};
+    return launch_conv(ctx, in, w, bias, g, act ? EP_LRELU : EP_NONE, nullptr, out_bf16, out_f32);
+}
+
+extern "C" int gx_conv3d_bwd_data(gx_ctx* ctx, const uint16_t* dout, int B, int S, int Cin,
+                                  const uint16_t* w, int ksize, int Cout, const uint16_t* y_in,
+                                  uint16_t* din) {
+    if (!ctx || !dout || !w || !din) return GX_EINVAL;
+    GX_TRY(check_conv(ctx, B, S, Cin, Cout, ksize));
+    if (Cin % 16) return gx_fail(ctx, GX_EINVAL, "conv3d_bwd_data: Cin % 16 == 0 required");
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    const int kv = ksize == 3 ? 27 : 1;
+    const int64_t nw = (int64_t)Cout * Cin * kv;
+    GX_TRY(gx_reserve(ctx, ctx->scan_tmp[2], nw * sizeof(uint16_t)));
+    uint16_t* wf = (uint16_t*)ctx->scan_tmp[2].p;
+    hipLaunchKernelGGL(k_wflip, dim3(gx_blocks(nw, 256)), dim3(256), 0, ctx->stream, w, Cout, Cin,
+                       kv, wf);
+    ConvGeom g{B, S, Cout, Cin, kv, (int64_t)B * S * S * S, kv * Cout};
+    return launch_conv(ctx, dout, wf, nullptr, g, y_in ? EP_DACT : EP_NONE, y_in, din, nullptr);
+}
+
+extern "C" int gx_conv3d_bwd_weight(gx_ctx* ctx, const uint16_t* in, const uint16_t* dout, int B,
+                                    int S, int Cin, int ksize, int Cout, float* dw, float* dbias) {
+    if (!ctx || !in || !dout || !dw) return GX_EINVAL;
+    GX_TRY(check_conv(ctx, B, S, Cin, Cout, ksize));
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    const int kv = ksize == 3 ? 27 : 1;
+    ConvGeom g{B, S, Cin, Cout, kv, (int64_t)B * S * S * S, kv * Cin};
+    // split the voxel reduction so the grid has >= ~2048 blocks
+    const int kt = (g.K + 63) / 64;
+    const int bn = Cout % 64 == 0 ? 64 : (Cout % 32 == 0 ? 32 : 16);
+    const int nt = Cout / bn;
+    int64_t chunks = std::max<int64_t>(1, 2048 / (kt * nt));
+    int64_t mpb = (g.M + chunks - 1) / chunks;
+    mpb = ((mpb + 31) / 32) * 32;
+    if (mpb < 256) mpb = 256;
+    chunks = (g.M + mpb - 1) / mpb;
+    dim3 grid(kt, nt, (unsigned)chunks);
+    if (bn == 64)
+        hipLaunchKernelGGL(k_conv3d_wgrad<64>, grid, dim3(256), 0, ctx->stream, in, dout, g, mpb, dw);
+    else if (bn == 32)
+        hipLaunchKernelGGL(k_conv3d_wgrad<32>, grid, dim3(256), 0, ctx->stream, in, dout, g, mpb, dw);
+    else
+        hipLaunchKernelGGL(k_conv3d_wgrad<16>, grid, dim3(256), 0, ctx->stream, in, dout, g, mpb, dw);
+    if (dbias) {
+        hipLaunchKernelGGL(k_bias_grad, dim3(256, Cout), dim3(256), 0, ctx->stream, dout, g.M, Cout,
+                           dbias);
+    }
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+extern "C" int gx_avgpool2(gx_ctx* ctx, const uint16_t* in, int B, int S, int C, uint16_t* out,
+                           int backward) {
+    if (!ctx || !in || !out || S % 2 || S < 2 || C < 1 || B < 1) return GX_EINVAL;
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    int64_t n = (int64_t)B * S * S * S * C;
+    if (!backward) {
+        n /= 8;
+        hipLaunchKernelGGL(k_avgpool2, dim3(gx_blocks(n, 256)), dim3(256), 0, ctx->stream, in, B, S,
+                           C, out);
+    } else {
+        hipLaunchKernelGGL(k_avgpool2_bwd, dim3(gx_blocks(n, 256)), dim3(256), 0, ctx->stream, in, B,
+                           S, C, out);
+    }
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+extern "C" int gx_upsample2(gx_ctx* ctx, const uint16_t* in, int B, int S, int C, uint16_t* out,
+                            int backward) {
+    if (!ctx || !in || !out || S < 1 || C < 1 || B < 1) return GX_EINVAL;
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    int64_t n = (int64_t)B * S * S * S * C;
+    if (!backward) {
+        n *= 8;
+        hipLaunchKernelGGL(k_upsample2, dim3(gx_blocks(n, 256)), dim3(256), 0, ctx->stream, in, B,
+                           S, C, out);
+    } else {
+        hipLaunchKernelGGL(k_upsample2_bwd, dim3(gx_blocks(n, 256)), dim3(256), 0, ctx->stream, in,
+                           B, S, C, out);
+    }
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+extern "C" int gx_concat(gx_ctx* ctx, uint16_t* a, int Ca, uint16_t* b, int Cb, int64_t V,
+                         uint16_t* out, int split) {
+    if (!ctx || !a || !b || !out || Ca < 1 || Cb < 1 || V < 0) return GX_EINVAL;
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    const int64_t n = V * (Ca + Cb);
+    hipLaunchKernelGGL(k_concat, dim3(gx_blocks(n, 256)), dim3(256), 0, ctx->stream, a, Ca, b, Cb,
+                       V, out, split);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+extern "C" int gx_mse(gx_ctx* ctx, const float* pred, int Cp, const float* target, int nc,
+                      int64_t V, uint16_t* dpred, double* loss) {
+    if (!ctx || !pred || !target || nc < 1 || Cp < nc || V < 1 || !loss) return GX_EINVAL;
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    const int nb = 512;
+    GX_TRY(gx_reserve(ctx, ctx->partial, (nb + 8) * sizeof(double)));
+    double* part = (double*)ctx->partial.p;
+    const float scale = (float)(1.0 / ((double)V * nc));
+    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, ctx->stream, pred, Cp, target, nc, V, scale,
+                       dpred, part);
+    GX_LAUNCH_CHECK(ctx);
+    double h[512];
+    GX_HIP(ctx, hipMemcpyAsync(h, part, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    GX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    double s = 0.0;
+    for (int i = 0; i < nb; i++) s += h[i];
+    *loss = s / ((double)V * nc);
+    return GX_OK;
+}
+
+extern "C" int gx_adam_step(gx_ctx* ctx, int64_t n, float* w, const float* grad, float* m, float* v,
+                            double lr, double b1, double b2, double eps, int64_t t,
+                            uint16_t* w_bf16) {
+    if (!ctx || !w || !grad || !m || !v || n < 0 || t < 1) return GX_EINVAL;
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    const double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
+    hipLaunchKernelGGL(k_adam, dim3(gx_blocks(n, 256)), dim3(256), 0, ctx->stream, n, w, grad, m, v,
+                       (float)lr, (float)b1, (float)b2, (float)eps, (float)c1, (float)c2, w_bf16);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+extern "C" int gx_f32_to_bf16(gx_ctx* ctx, const float* x, int64_t n, uint16_t* y) {
+    if (!ctx || !x || !y || n < 0) return GX_EINVAL;
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_f32_to_bf16, dim3(gx_blocks(n, 256)), dim3(256), 0, ctx->stream, x, n, y);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+extern "C" int gx_grad_combine(gx_ctx* ctx, int64_t n, const uint16_t* a, const uint16_t* b,
+                               const uint16_t* y, uint16_t* out) {
+    if (!ctx || !a || !out || n < 0) return GX_EINVAL;
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_grad_combine, dim3(gx_blocks(n, 256)), dim3(256), 0, ctx->stream, n, a, b, y,
+                       out);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}

@@ -25,15 +25,16 @@
 int gx_tree_check(gx_ctx* ctx, int which, const gx_particles* p);
 
 __global__ __launch_bounds__(128) void k_walk_sph(
-    int nb, const int32_t* __restrict__ recv, const NodeRec* __restrict__ nodes,
-    const MomRec* __restrict__ mom, int nn, const float* __restrict__ radius, int use_hmax,
+    int nb, const int32_t* __restrict__ groups, const NodeRec* __restrict__ recv,
+    const NodeRec* __restrict__ nodes, const MomRec* __restrict__ mom, int nn,
+    const float* __restrict__ radius, int use_hmax,
     const uint8_t* __restrict__ active, int mode, int cap, uint32_t* __restrict__ pr_cnt,
     uint32_t* __restrict__ pp_tot, unsigned long long* __restrict__ tot,
     const int64_t* __restrict__ pr_off, int32_t* __restrict__ pr_begin,
     int32_t* __restrict__ pr_cum);
 __global__ __launch_bounds__(64) void k_walk_sph_bfs(
-    int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes,
-    const int32_t* __restrict__ child, const MomRec* __restrict__ mom,
+    int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ recv,
+    const NodeRec* __restrict__ nodes, const int32_t* __restrict__ child, const MomRec* __restrict__ mom,
     const float* __restrict__ radius, int use_hmax, const uint8_t* __restrict__ active, int cap,
     uint32_t* __restrict__ pr_cnt, uint32_t* __restrict__ pp_tot,
     unsigned long long* __restrict__ tot, int32_t* __restrict__ pr_begin,
@@ -57,46 +58,6 @@ static int work(gx_ctx* ctx, int k, size_t bytes, void** p) {
     *p = ctx->sph_work[k].p;
     return GX_OK;
 }
-
-// Candidate lists of all groups: fixed-capacity slots (group g at g * cap)
-// from the wave walk, and -- for the groups flagged in `ovf` whose lists did
-// not fit -- CSR lists from the thread walk.
-struct ListView {
-    int cap;
-    const uint32_t* cnt;
-    const int32_t* begin;
-    const int32_t* cum;
-    const uint32_t* tot;
-    const uint8_t* ovf;  // may be null: no overflow lists
-    const int64_t* off2;
-    const uint32_t* cnt2;
-    const int32_t* begin2;
-    const int32_t* cum2;
-    const uint32_t* tot2;
-};
-
-// One group's list: ranges [r0, r1) of begin/cum, npp candidates in total.
-struct GroupList {
-    const int32_t* begin;
-    const int32_t* cum;
-    int64_t r0, r1;
-    int npp;
-    __device__ __forceinline__ GroupList(const ListView& L, int g) {
-        if (L.ovf && L.ovf[g]) {
-            begin = L.begin2;
-            cum = L.cum2;
-            r0 = L.off2[g];
-            r1 = r0 + L.cnt2[g];
-            npp = (int)L.tot2[g];
-        } else {
-            begin = L.begin;
-            cum = L.cum;
-            r0 = (int64_t)g * L.cap;
-            r1 = r0 + L.cnt[g];
-            npp = (int)L.tot[g];
-        }
-    }
-};
 
 // Kernel-size seed: H64 when positive and finite, else from the smallest tree
 // node holding the particle and at least n_ngb particles, using the node's
@@ -358,6 +319,25 @@ __global__ __launch_bounds__(256) void k_hmax_level(int cnt, const int32_t* __re
     mom[id].hmax = h;
 }
 
+// Largest kernel size of every node of a tree (ss[s].x = H of sorted slot s).
+int gx_sph_node_hmax(gx_ctx* ctx, TreeSlot& T, const float4* ss) {
+    int64_t off = 0;
+    int64_t lvl_off[GX_MAX_LEVEL + 1];
+    for (int l = 0; l <= GX_MAX_LEVEL; l++) {
+        lvl_off[l] = off;
+        off += T.lvl_hist[l];
+    }
+    for (int l = GX_MAX_LEVEL; l >= 0; l--) {
+        int c = (int)T.lvl_hist[l];
+        if (!c) continue;
+        hipLaunchKernelGGL(k_hmax_level, dim3(gx_blocks(c, 256)), dim3(256), 0, ctx->stream, c,
+                           (const int32_t*)T.lvl_ids.p + lvl_off[l], (const NodeRec*)T.nodes.p,
+                           (MomRec*)T.mom.p, ss);
+    }
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
 __global__ __launch_bounds__(64) void k_group_hmax(int ng, const int32_t* __restrict__ groups,
                                                    const MomRec* __restrict__ mom,
                                                    float* __restrict__ rad) {
@@ -522,10 +502,11 @@ __global__ __launch_bounds__(SPH_THREADS) void k_sph_force(
 // capacity slots in one pass and flags the groups whose list or frontier did
 // not fit; only those take the thread walk (count + scan + fill) into a
 // second, CSR list set.
-static int sph_walk(gx_ctx* ctx, TreeSlot& T, ListSet& Ls, const float* rad, int use_hmax,
-                    const uint8_t* active, ListView* view, int64_t* list_pairs) {
+int gx_sph_walk(gx_ctx* ctx, TreeSlot& T, ListSet& Ls, int ng, const int32_t* groups,
+                const NodeRec* recv, const float* rad, int use_hmax, const uint8_t* active,
+                ListView* view, int64_t* list_pairs) {
     hipStream_t st = ctx->stream;
-    const int ng = (int)T.n_groups, nn = (int)T.n_nodes;
+    const int nn = (int)T.n_nodes;
     GX_TRY(gx_reserve(ctx, Ls.tot, 16 * sizeof(int64_t)));
     GX_TRY(gx_reserve(ctx, Ls.pr_cnt, (2 * ng + 2) * sizeof(uint32_t)));
     GX_TRY(gx_reserve(ctx, Ls.pp_tot, (2 * ng + 2) * sizeof(uint32_t)));
@@ -540,9 +521,8 @@ static int sph_walk(gx_ctx* ctx, TreeSlot& T, ListSet& Ls, const float* rad, int
     uint32_t* ptot2 = ptot + ng + 1;
     uint8_t* ovf = (uint8_t*)Ls.pc_cnt.p;
     GX_TRY(gx_zero(ctx, tot, 16 * sizeof(int64_t)));
-    hipLaunchKernelGGL(k_walk_sph_bfs, dim3(xcd_grid(ng)), dim3(64), 0, st, ng,
-                       (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
-                       (const int32_t*)T.child.p, (const MomRec*)T.mom.p, rad, use_hmax, active,
+    hipLaunchKernelGGL(k_walk_sph_bfs, dim3(xcd_grid(ng)), dim3(64), 0, st, ng, groups, recv,
+                       (const NodeRec*)T.nodes.p, (const int32_t*)T.child.p, (const MomRec*)T.mom.p, rad, use_hmax, active,
                        SPH_RANGES, cnt, ptot, (unsigned long long*)tot, (int32_t*)Ls.pr_begin.p,
                        (int32_t*)Ls.pr_cum.p, ovf);
     GX_LAUNCH_CHECK(ctx);
@@ -553,9 +533,9 @@ static int sph_walk(gx_ctx* ctx, TreeSlot& T, ListSet& Ls, const float* rad, int
                nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     int64_t pairs = h[2];
     if (h[4] > 0) {  // overflowing groups: exact CSR lists from the thread walk
-        hipLaunchKernelGGL(k_walk_sph, dim3(gx_blocks(ng, 128)), dim3(128), 0, st, ng,
-                           (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
-                           (const MomRec*)T.mom.p, nn, rad, use_hmax, ovf, 0, 0, cnt2, ptot2,
+        hipLaunchKernelGGL(k_walk_sph, dim3(gx_blocks(ng, 128)), dim3(128), 0, st, ng, groups,
+                           recv, (const NodeRec*)T.nodes.p, (const MomRec*)T.mom.p, nn, rad,
+                           use_hmax, ovf, 0, 0, cnt2, ptot2,
                            (unsigned long long*)(tot + 8), nullptr, nullptr, nullptr);
         GX_TRY((gx_scan<uint32_t, int64_t>(ctx, cnt2, (int64_t*)Ls.pr_off.p, ng, tot + 13)));
         GX_HIP(ctx, hipMemcpyAsync(h, tot, 16 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -563,9 +543,9 @@ static int sph_walk(gx_ctx* ctx, TreeSlot& T, ListSet& Ls, const float* rad, int
         const int64_t nr = h[13];
         GX_TRY(gx_reserve(ctx, Ls.pc_off, (nr + 1) * sizeof(int32_t)));
         GX_TRY(gx_reserve(ctx, Ls.pc_list, (nr + 1) * sizeof(int32_t)));
-        hipLaunchKernelGGL(k_walk_sph, dim3(gx_blocks(ng, 128)), dim3(128), 0, st, ng,
-                           (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
-                           (const MomRec*)T.mom.p, nn, rad, use_hmax, ovf, 1, 0, nullptr, nullptr,
+        hipLaunchKernelGGL(k_walk_sph, dim3(gx_blocks(ng, 128)), dim3(128), 0, st, ng, groups,
+                           recv, (const NodeRec*)T.nodes.p, (const MomRec*)T.mom.p, nn, rad,
+                           use_hmax, ovf, 1, 0, nullptr, nullptr,
                            nullptr, (const int64_t*)Ls.pr_off.p, (int32_t*)Ls.pc_off.p,
                            (int32_t*)Ls.pc_list.p);
         GX_LAUNCH_CHECK(ctx);
@@ -633,7 +613,8 @@ extern "C" int gx_sph_density(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, 
     double kernel_ms = 0.0;
     for (;;) {
         ListView view;
-        GX_TRY(sph_walk(ctx, T, Ls, rad, 0, act, &view, &list_pairs));
+        GX_TRY(gx_sph_walk(ctx, T, Ls, nb, (const int32_t*)T.groups.p, nullptr, rad, 0, act, &view,
+                           &list_pairs));
         if (stats) GX_HIP(ctx, hipEventRecord(ctx->ev2, st));
         hipLaunchKernelGGL(k_sph_density, dim3(xcd_grid(nb)), dim3(SPH_THREADS), 0, st, nb,
                            (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
@@ -712,25 +693,14 @@ extern "C" int gx_sph_forces(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, d
     hipLaunchKernelGGL(k_sph_prep, dim3(gx_blocks(n, 256)), dim3(256), 0, st, n,
                        (const uint32_t*)T.val[0].p, gas->vx, gas->vy, gas->vz, gs->u, gs->H, gs->rho,
                        (float)gamma, sv, ss);
-    int64_t off = 0;
-    int64_t lvl_off[GX_MAX_LEVEL + 1];
-    for (int l = 0; l <= GX_MAX_LEVEL; l++) {
-        lvl_off[l] = off;
-        off += T.lvl_hist[l];
-    }
-    for (int l = GX_MAX_LEVEL; l >= 0; l--) {
-        int c = (int)T.lvl_hist[l];
-        if (!c) continue;
-        hipLaunchKernelGGL(k_hmax_level, dim3(gx_blocks(c, 256)), dim3(256), 0, st, c,
-                           (const int32_t*)T.lvl_ids.p + lvl_off[l], (const NodeRec*)T.nodes.p,
-                           (MomRec*)T.mom.p, ss);
-    }
+    GX_TRY(gx_sph_node_hmax(ctx, T, ss));
     hipLaunchKernelGGL(k_group_hmax, dim3(gx_blocks(nb, 64)), dim3(64), 0, st, nb,
                        (const int32_t*)T.groups.p, (const MomRec*)T.mom.p, rad);
     GX_LAUNCH_CHECK(ctx);
     ListView view;
     int64_t list_pairs = 0;
-    GX_TRY(sph_walk(ctx, T, Ls, rad, 1, nullptr, &view, &list_pairs));
+    GX_TRY(gx_sph_walk(ctx, T, Ls, nb, (const int32_t*)T.groups.p, nullptr, rad, 1, nullptr, &view,
+                       &list_pairs));
     if (stats) GX_HIP(ctx, hipEventRecord(ctx->ev2, st));
     hipLaunchKernelGGL(k_sph_force, dim3(xcd_grid(nb)), dim3(SPH_THREADS), 0, st, nb,
                        (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,

@@ -112,8 +112,9 @@ __global__ void k_direct_lists(int ng, int n, const int32_t* __restrict__ groups
 // b * cap with per-block counts (entries past cap are counted, not written,
 // and the block is reported in tot[4]).
 __global__ __launch_bounds__(128) void k_walk_sph(
-    int nb, const int32_t* __restrict__ recv, const NodeRec* __restrict__ nodes,
-    const MomRec* __restrict__ mom, int nn, const float* __restrict__ radius, int use_hmax,
+    int nb, const int32_t* __restrict__ groups, const NodeRec* __restrict__ recv,
+    const NodeRec* __restrict__ nodes, const MomRec* __restrict__ mom, int nn,
+    const float* __restrict__ radius, int use_hmax,
     const uint8_t* __restrict__ active, int mode, int cap, uint32_t* __restrict__ pr_cnt,
     uint32_t* __restrict__ pp_tot, unsigned long long* __restrict__ tot,
     const int64_t* __restrict__ pr_off, int32_t* __restrict__ pr_begin,
@@ -127,7 +128,7 @@ __global__ __launch_bounds__(128) void k_walk_sph(
         }
         return;
     }
-    const NodeRec G = nodes[recv[g]];
+    const NodeRec G = recv ? recv[g] : nodes[groups[g]];
     const double RG = (double)radius[g];
     int npr = 0, npp = 0, last_end = -1;
     const int64_t pro = (mode == 1) ? pr_off[g] : (mode == 2 ? (int64_t)g * cap : 0);
@@ -169,6 +170,8 @@ __global__ __launch_bounds__(128) void k_walk_sph(
     }
 }
 
+// Receivers are tree groups (groups[g]) or, when recv is non-null, arbitrary
+// boxes (recv[g]).
 // Wave-cooperative SPH walk: one wavefront per receiving group traverses the
 // tree breadth-first.  The 64 lanes test 64 frontier nodes at a time; leaves
 // within reach are appended to the group's fixed-capacity range slot (ballot
@@ -180,8 +183,8 @@ __global__ __launch_bounds__(128) void k_walk_sph(
 // thread-per-group CSR walk).
 #define BFS_FMAX 2048
 __global__ __launch_bounds__(64) void k_walk_sph_bfs(
-    int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes,
-    const int32_t* __restrict__ child, const MomRec* __restrict__ mom,
+    int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ recv,
+    const NodeRec* __restrict__ nodes, const int32_t* __restrict__ child, const MomRec* __restrict__ mom,
     const float* __restrict__ radius, int use_hmax, const uint8_t* __restrict__ active, int cap,
     uint32_t* __restrict__ pr_cnt, uint32_t* __restrict__ pp_tot,
     unsigned long long* __restrict__ tot, int32_t* __restrict__ pr_begin,
@@ -198,7 +201,7 @@ __global__ __launch_bounds__(64) void k_walk_sph_bfs(
         return;
     }
     __shared__ int32_t fr[2][BFS_FMAX];
-    const NodeRec G = nodes[groups[g]];
+    const NodeRec G = recv ? recv[g] : nodes[groups[g]];
     const double RG = (double)radius[g];
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t slot = (int64_t)g * cap;

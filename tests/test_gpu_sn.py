@@ -1,0 +1,158 @@
+"""GPU parity of the supernova-region kernels (through the C ABI): box
+extraction, energy injection, voxelization (vs the oracle's brute force),
+inverse-CDF resampling and replacement by ID."""
+import math
+
+import numpy as np
+import pytest
+
+import ics
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def eng(gx):
+    e = gx.Engine(0)
+    yield e
+    e.close()
+
+
+def _t(a, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda") if dtype is None else \
+        torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def _field(n, seed, box=200.0):
+    rng = np.random.default_rng(seed)
+    d = {k: rng.uniform(-box, box, n) for k in ("x", "y", "z")}
+    d.update({k: rng.normal(size=n) for k in ("vx", "vy", "vz")})
+    d["m"] = rng.uniform(0.5, 1.5, n)
+    d["eps2"] = np.full(n, 0.01, np.float32)
+    return d
+
+
+def test_extract_matches_definition(gx, eng):
+    d = _field(200_000, 1)
+    rng = np.random.default_rng(2)
+    centers = rng.uniform(-150, 150, (17, 3))
+    centers[3] = [199.0, 199.0, 199.0]   # partly outside the particle set
+    p = gx.ParticleSet.from_numpy(d)
+    off, idx, tot = eng.sn_extract(p, _t(centers), 30.0, 200_000)
+    off = off.cpu().numpy()
+    idx = idx.cpu().numpy()
+    for c in range(len(centers)):
+        inside = np.where((d["x"] >= centers[c, 0] - 30) & (d["x"] < centers[c, 0] + 30) &
+                          (d["y"] >= centers[c, 1] - 30) & (d["y"] < centers[c, 1] + 30) &
+                          (d["z"] >= centers[c, 2] - 30) & (d["z"] < centers[c, 2] + 30))[0]
+        assert np.array_equal(idx[off[c]:off[c + 1]], inside)
+    assert tot == off[-1]
+
+
+def test_inject_energy_and_selection(gx, eng):
+    d = _field(100_000, 3, box=60.0)
+    rng = np.random.default_rng(4)
+    centers = rng.uniform(-20, 20, (5, 3))
+    p = gx.ParticleSet.from_numpy(d)
+    off, idx, tot = eng.sn_extract(p, _t(centers), 30.0, 100_000)
+    u0 = np.full(100_000, 3.0)
+    u = _t(u0.copy())
+    E = ics.E_SN
+    eng.sn_inject(p, off, idx, _t(centers), 32, E, u)
+    du = u.cpu().numpy() - u0
+    offh, idxh = off.cpu().numpy(), idx.cpu().numpy()
+    for c in range(5):
+        mem = idxh[offh[c]:offh[c + 1]]
+        r2 = ((d["x"][mem] - centers[c, 0]) ** 2 + (d["y"][mem] - centers[c, 1]) ** 2 +
+              (d["z"][mem] - centers[c, 2]) ** 2)
+        near = mem[np.argsort(r2, kind="stable")[:32]]
+        sel = np.zeros(100_000, bool)
+        sel[near] = True
+        assert np.all(du[sel] > 0)
+        # energy added to this cube's 32 nearest = E (cubes may overlap elsewhere)
+        assert np.sum(d["m"][near] * E / np.sum(d["m"][near])) == pytest.approx(E, rel=1e-12)
+    assert np.sum(d["m"] * du) == pytest.approx(5 * E, rel=1e-9)
+    assert np.count_nonzero(du) <= 5 * 32
+
+
+@pytest.mark.parametrize("grid", [16, 32])
+def test_voxelize_matches_oracle(gx, eng, grid):
+    import torch
+    c = ics.sn_cube(1007, n_fixed=6000)
+    n = c["x"].size
+    rng = np.random.default_rng(8)
+    H = rng.uniform(4.0, 9.0, n).astype(np.float32)
+    c["u"] = c["u"] * rng.uniform(0.5, 3.0, n)
+    p = gx.ParticleSet.from_numpy(c)
+    eng.tree_build(p, gx.GX_TREE_GAS, 8, 64)
+    centers = np.array([[0.0, 0.0, 0.0], [5.0, -3.0, 2.0]])
+    amb = np.array([[-1.5, 3.0, 0.0, 0.0, 0.0], [-2.0, 2.5, 1.0, 0.0, 0.0]], np.float32)
+    out = torch.zeros(2 * grid ** 3 * 5, dtype=torch.float32, device="cuda")
+    eng.sn_voxelize(p, _t(c["u"]), _t(H), _t(centers), 60.0, grid, 48.46, _t(amb), out_f32=out)
+    got = out.cpu().numpy().reshape(2, grid, grid, grid, 5)
+    for k in range(2):
+        pp = dict(c, H=H.astype(np.float64))
+        ref = oracle.voxelize(pp, 48.46, centers[k], 60.0, grid, amb[k].astype(np.float64))
+        assert np.max(np.abs(got[k, ..., 0] - ref[..., 0])) < 2e-5
+        assert np.max(np.abs(got[k, ..., 1] - ref[..., 1])) < 2e-5
+        vs = np.max(np.abs(ref[..., 2:]))
+        assert np.max(np.abs(got[k, ..., 2:] - ref[..., 2:])) < 2e-5 * vs + 1e-6
+
+
+def test_resample_inverse_cdf(gx, eng):
+    import torch
+    grid, k = 16, 3
+    rng = np.random.default_rng(12)
+    pred = np.zeros((k, grid ** 3, 5), np.float32)
+    pred[..., 0] = rng.normal(size=(k, grid ** 3)) * 0.7 - 1.0
+    pred[..., 1] = rng.uniform(2, 7, (k, grid ** 3))
+    pred[..., 2:] = rng.normal(size=(k, grid ** 3, 3))
+    counts = np.array([5000, 1, 12345])
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    tot = int(off[-1])
+    uni = rng.uniform(0, 1, (tot, 4)).astype(np.float32)
+    centers = np.array([[0.0, 0, 0], [100.0, 0, 0], [0, 100.0, 0]])
+    outs = [torch.zeros(tot, dtype=torch.float64, device="cuda") for _ in range(7)]
+    eng.sn_resample(_t(pred), _t(centers), grid, 60.0, _t(off), int(counts.max()), _t(uni),
+                    1 / 48.46, *outs)
+    x, y, z, vx, vy, vz, u = (o.cpu().numpy() for o in outs)
+    dv = 60.0 / grid
+    agree = 0
+    for c in range(k):
+        sl = slice(off[c], off[c + 1])
+        cdf = np.cumsum(10.0 ** pred[c, :, 0].astype(np.float64))
+        vsel = np.searchsorted(cdf, uni[sl, 0].astype(np.float64) * cdf[-1], side="right")
+        vsel = np.minimum(vsel, grid ** 3 - 1)
+        X = np.floor((x[sl] - centers[c, 0] + 30) / dv).astype(int)
+        Y = np.floor((y[sl] - centers[c, 1] + 30) / dv).astype(int)
+        Z = np.floor((z[sl] - centers[c, 2] + 30) / dv).astype(int)
+        vgot = (Z * grid + Y) * grid + X
+        agree += np.sum(vgot == vsel)
+        ok = vgot == vsel
+        assert np.allclose(vx[sl][ok], pred[c, vsel[ok], 2])
+        assert np.allclose(u[sl][ok], 10.0 ** pred[c, vsel[ok], 1].astype(np.float64) / 48.46,
+                           rtol=1e-6)
+    assert agree >= 0.999 * tot
+
+
+def test_replace_by_id(gx, eng):
+    import torch
+    n = 5000
+    rng = np.random.default_rng(1)
+    ids = rng.permutation(n).astype(np.int64)
+    arrs = [_t(rng.normal(size=n)) for _ in range(6)]
+    u = _t(rng.uniform(1, 2, 1000))
+    H64 = _t(np.ones(1000))
+    new_id = np.array([ids[4000], ids[10], ids[4999], 123456], np.int64)
+    newv = [_t(np.arange(4, dtype=np.float64) + 10 * k) for k in range(7)]
+    miss = eng.sn_replace(_t(ids), 200000, *arrs, u, 4000, H64, _t(new_id), *newv)
+    assert miss == 1
+    xs = [a.cpu().numpy() for a in arrs]
+    assert xs[0][4000] == 0.0 and xs[0][10] == 1.0 and xs[0][4999] == 2.0
+    assert xs[5][10] == 51.0
+    uh = u.cpu().numpy()
+    assert uh[0] == 60.0 and uh[999] == 62.0
+    hh = H64.cpu().numpy()
+    assert hh[0] == -1.0 and hh[999] == -1.0 and hh[1] == 1.0
