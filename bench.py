@@ -45,6 +45,11 @@ def parse():
     ap.add_argument("--cpu-groups", type=int, default=1024,
                     help="groups in the oracle's timed sample (0 skips the CPU baseline)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--sn-sites", type=int, default=64,
+                    help="SN regions handed to the surrogate per step (0: plain step only)")
+    ap.add_argument("--sn-cubes", type=int, default=64,
+                    help="SN cubes of the plain-SPH vs surrogate region comparison (0 skips)")
+    ap.add_argument("--sn-infer-batch", type=int, default=256)
     return ap.parse_args()
 
 
@@ -70,11 +75,52 @@ def cpu_baseline(d, n_groups_sample, seed):
                        f"{dt:.2f} s; oracle tree build {build_s:.1f} s not included)")}
 
 
+def sn_region_leg(eng, n_cubes, infer_batch, seed0=5000):
+    """Per SN region: plain small-dt SPH to 0.1 Myr vs the surrogate path
+    (extract, ambient, gas tree, voxelize, infer, resample) on the same cubes,
+    plus network inference throughput at the stated batch."""
+    import torch
+    import ics
+    from paper_2510_23330_amd.sn import GRID, SNBatch, Surrogate, generate
+    from paper_2510_23330_amd.unet import flops_forward
+    seeds = list(range(seed0, seed0 + n_cubes))
+    x, y, info = generate(eng, seeds)
+    plain_s = info["seconds"]
+    sur = Surrogate(eng, batch=32, seed=0, train=False)
+    sb = SNBatch(eng, ics.sn_batch(seeds))
+    sb.voxelize()
+    sur.regions(sb.p, sb.g, sb.centers, cap=sb.n)         # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sur.regions(sb.p, sb.g, sb.centers, cap=sb.n)
+    torch.cuda.synchronize()
+    sur_s = time.perf_counter() - t0
+    # inference throughput at infer_batch regions (chunks of the network's batch)
+    V = GRID ** 3
+    xin = torch.zeros(infer_batch * V * 8, dtype=torch.bfloat16, device="cuda")
+    pred = torch.empty(infer_batch * V * 5, dtype=torch.float32, device="cuda")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sur.infer(xin[:32 * V * 8], 32, pred)
+    ev0.record()
+    sur.infer(xin, infer_batch, pred)
+    ev1.record()
+    torch.cuda.synchronize()
+    inf_s = ev0.elapsed_time(ev1) / 1e3
+    fl = flops_forward(GRID) * infer_batch
+    return {"regions": n_cubes, "particles": info["n_particles"], "plain_sph_steps": info["steps"],
+            "plain_sph_s": plain_s, "surrogate_s": sur_s, "speedup": plain_s / sur_s,
+            "plain_sph_ms_per_region": plain_s / n_cubes * 1e3,
+            "surrogate_ms_per_region": sur_s / n_cubes * 1e3,
+            "infer_batch": infer_batch, "infer_s": inf_s,
+            "infer_tflops": fl / inf_s / 1e12, "infer_frac_bf16_peak": fl / inf_s / 2.5e15,
+            "weights": "random init (timing only; accuracy comes from the trained network)"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                          "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+                          "(sharding across GPUs is not built)"}))
         sys.exit(2)
     import torch
     import ics
@@ -91,15 +137,36 @@ def main():
                      n_leaf=16, n_group=256, sph_leaf=8, sph_group=64, n_ngb=64.0,
                      u_floor=10.0 * ics.U_PER_K)
     sim = GalaxyStep(eng, p, int(d["gas_offset"]), u, cfg)
+    coupling = None
+    if args.sn_sites > 0:
+        from paper_2510_23330_amd.coupling import SNCoupling
+        from paper_2510_23330_amd.sn import Surrogate
+        sur_eng = gx.Engine(0)
+        coupling = SNCoupling(sim, Surrogate(sur_eng, batch=32, seed=0, train=False),
+                              n_sites=args.sn_sites, delay=50)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.initial_forces()
     torch.cuda.synchronize()
     log(f"[bench] initial forces (cold kernel sizes) {time.perf_counter() - t0:.2f} s")
+    sn_ms = []
+
+    def sn_phase(i):
+        if coupling is None:
+            return
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        coupling.apply_due(i)
+        coupling.launch(i)
+        torch.cuda.synchronize()
+        sn_ms.append((time.perf_counter() - t) * 1e3)
+
     for w in range(args.warmup):
         sim.step()
+        sn_phase(w)
         sim.energy()
         log(f"[bench] warmup step {w} done")
+    sn_ms.clear()
     torch.cuda.synchronize()
 
     per = []
@@ -111,6 +178,7 @@ def main():
     for k in range(args.steps):
         ts = time.perf_counter()
         st = sim.step()
+        sn_phase(args.warmup + k)
         energies.append(sim.energy())
         per.append(time.perf_counter() - ts)
         grav_ms.append(st["gravity"]["ms"])
@@ -156,7 +224,10 @@ def main():
         "sph_pairs_per_step": n_sph / args.steps,
         "phase_ms": {"tree_builds": float(np.mean(tree_ms)), "gravity": float(np.mean(grav_ms)),
                      "gravity_kernel": float(np.mean(grav_kernel_ms)),
-                     "sph_density": float(np.mean(dens_ms)), "sph_force": float(np.mean(hydro_ms))},
+                     "sph_density": float(np.mean(dens_ms)), "sph_force": float(np.mean(hydro_ms)),
+                     "sn_surrogate": float(np.mean(sn_ms)) if sn_ms else None},
+        "sn_coupling": None if coupling is None else dict(coupling.stats, sites_per_step=args.sn_sites,
+                                                          delay_steps=50),
         "gravity_kernel_interactions_per_s": inter_step / kernel_s,
         "energy_drift_rel": abs(E1 - E0) / abs(E0),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
@@ -164,6 +235,10 @@ def main():
                      "kernel": "k_grav_force<float,true>",
                      "flop_convention": f"{FLOP_PP}/pp + {FLOP_PC}/pc"},
     }
+    if args.sn_cubes > 0:
+        t0 = time.perf_counter()
+        out["sn_region"] = sn_region_leg(eng, args.sn_cubes, args.sn_infer_batch)
+        log(f"[bench] SN region leg {time.perf_counter() - t0:.1f} s")
     if not args.no_cpu and args.cpu_groups > 0:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(d, args.cpu_groups, 99)

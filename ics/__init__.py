@@ -305,6 +305,12 @@ def sn_cube(seed: int, n_min: int = 2000, n_max: int = 32000, side: float = 60.0
     return out
 
 
+def sn_cube_n(seed: int, n_min: int = 2000, n_max: int = 32000) -> int:
+    """Particle count sn_cube(seed) will draw (its first random number)."""
+    rng = _rng(seed)
+    return int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+
+
 def sn_batch(seeds, spacing: float = 1000.0, **kw):
     """Several SN cubes in one particle set, cube k centred at a point of a
     cubic lattice of the given spacing (far enough apart that they never

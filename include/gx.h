@@ -279,6 +279,41 @@ int gx_sn_inject(gx_ctx* ctx, const gx_particles* gas, const int32_t* offsets, c
                  const double* centers, int k, int k_inj, double energy, double* u);
 
 /*
+ * gx_sn_ambient -- ambient state of each extracted box, the value of voxels
+ * that no particle kernel reaches (Sec. 3.3 mapping): amb[c] = (log10 of the
+ * members' total mass over side^3, log10 of their mass-weighted temperature
+ * u * u_to_T floored at 10 K, mass-weighted vx, vy, vz).  Boxes with no
+ * member get (-30, 1, 0, 0, 0).
+ * offsets/idx from gx_sn_extract (device); u device FP64 per gas particle;
+ * amb device float [k][5] (output).
+ */
+int gx_sn_ambient(gx_ctx* ctx, const gx_particles* gas, const double* u, const int32_t* offsets,
+                  const int32_t* idx, int k, double side, double u_to_T, float* amb);
+
+/*
+ * gx_sn_gather -- hand a region to the surrogate (Sec. 3.2 step 2): pack the
+ * members of each box (CSR offsets/idx from gx_sn_extract) into compact
+ * device arrays in the box's own frame: position (x - centers[c]) * scale +
+ * dst[c], velocity, mass and u unchanged, kernel size H * scale (Ho may be
+ * NULL; H NULL writes -1, i.e. unknown).  n_max bounds the members of one
+ * box.  Outputs are indexed like idx (length offsets[k]).
+ */
+int gx_sn_gather(gx_ctx* ctx, const gx_particles* gas, const double* u, const float* H,
+                 const int32_t* offsets, const int32_t* idx, int k, int64_t n_max,
+                 const double* centers, const double* dst, double scale, double* x, double* y,
+                 double* z, double* vx, double* vy, double* vz, double* m, double* uo, float* Ho);
+
+/*
+ * gx_sn_unframe -- back to the simulation frame, in place, for replacement
+ * particles in CSR order: x = (x - src[c]) / scale + centers[c] + v_c dt, with
+ * v_c the box's bulk velocity (amb columns 2..4 of gx_sn_ambient; amb NULL:
+ * no drift) and dt the hand-over delay in simulation time units.
+ */
+int gx_sn_unframe(gx_ctx* ctx, const int32_t* offsets, int k, int64_t n_max, const double* src,
+                  const double* centers, const float* amb, double dt, double scale, double* x,
+                  double* y, double* z);
+
+/*
  * gx_sn_voxelize -- particle-to-grid mapping by SPH kernel convolution with
  * Shepard normalisation (Sec. 3.3) on grid^3 voxels covering a cube of the
  * given side centred on each site:
@@ -371,6 +406,19 @@ int gx_mse(gx_ctx* ctx, const float* pred, int Cp, const float* target, int nc, 
  * v; refreshes the bf16 copy when w_bf16 is non-NULL. */
 int gx_adam_step(gx_ctx* ctx, int64_t n, float* w, const float* grad, float* m, float* v,
                  double lr, double b1, double b2, double eps, int64_t t, uint16_t* w_bf16);
+/* Per-channel sums over V rows of in (fp32, row stride `stride`, channels
+ * [0, nc), nc <= 16): sums[c] += sum_v x, sums[nc + c] += sum_v x^2 (device
+ * double [2 nc]); FP64, fixed summation order.  Gives the training-set mean
+ * and standard deviation used to standardise the network's channels. */
+int gx_chan_stats(gx_ctx* ctx, int64_t V, const float* in, int stride, int nc, double* sums);
+/* y[v][c] = in[v][c] * scale[c] + shift[c], c < nc (scale/shift device float
+ * [nc]): standardisation ((x - mean) / std) or its inverse on predictions.
+ * out: fp32 rows of out_stride (NULL: skipped); out_bf16: bf16 rows of
+ * bf_stride with channels nc.. zero (NULL: skipped); in place is allowed for
+ * out when out_stride == in_stride. */
+int gx_chan_affine(gx_ctx* ctx, int64_t V, const float* in, int in_stride, int nc,
+                   const float* scale, const float* shift, float* out, int out_stride,
+                   uint16_t* out_bf16, int bf_stride);
 /* y = bf16(x), round to nearest even. */
 int gx_f32_to_bf16(gx_ctx* ctx, const float* x, int64_t n, uint16_t* y);
 /* out = (a + b) * LeakyReLU'(y) elementwise over n bf16 values (b, y may be

@@ -114,7 +114,12 @@ class GasState:
         torch = _torch()
         z64 = lambda: torch.zeros(n, dtype=torch.float64, device=device)
         z32 = lambda: torch.zeros(n, dtype=torch.float32, device=device)
-        uu = z64() if u is None else torch.as_tensor(np.ascontiguousarray(u, np.float64), device=device)
+        if u is None:
+            uu = z64()
+        elif isinstance(u, torch.Tensor):
+            uu = u.to(device=device, dtype=torch.float64).contiguous()
+        else:
+            uu = torch.as_tensor(np.ascontiguousarray(u, np.float64), device=device)
         return cls(u=uu, dudt=z64(), H64=z64(), H=z32(), rho=z32(), P=z32(), cs=z32(), vsig=z32())
 
     def view(self, u=None):
@@ -284,6 +289,37 @@ class Engine:
                                           int(centers.shape[0]), int(k_inj), float(energy),
                                           _ptr(u, torch.float64)))
 
+    def sn_ambient(self, gas: ParticleSet, u, offsets, idx, side, u_to_T, amb=None):
+        """Per-box ambient (log10 rho, log10 T, vx, vy, vz) from the extracted members."""
+        torch = _torch()
+        k = int(offsets.shape[0]) - 1
+        if amb is None:
+            amb = torch.zeros(k * 5, dtype=torch.float32, device=u.device)
+        self._check(self.lib.gx_sn_ambient(self.ctx, C.byref(gas.view()), _ptr(u, torch.float64),
+                                           _ptr(offsets, torch.int32), _ptr(idx, torch.int32), k,
+                                           float(side), float(u_to_T), _ptr(amb, torch.float32)))
+        return amb
+
+    def sn_gather(self, gas: ParticleSet, u, H, offsets, idx, n_max, centers, dst, scale, out: dict):
+        """Pack box members into `out` (x, y, z, vx, vy, vz, m, u FP64; H FP32 or absent)."""
+        torch = _torch()
+        k = int(offsets.shape[0]) - 1
+        f = [_ptr(out[a], torch.float64) for a in ("x", "y", "z", "vx", "vy", "vz", "m", "u")]
+        self._check(self.lib.gx_sn_gather(self.ctx, C.byref(gas.view()), _ptr(u, torch.float64),
+                                          _ptr(H, torch.float32), _ptr(offsets, torch.int32),
+                                          _ptr(idx, torch.int32), k, int(n_max),
+                                          _ptr(centers, torch.float64), _ptr(dst, torch.float64),
+                                          float(scale), *f, _ptr(out.get("H"), torch.float32)))
+
+    def sn_unframe(self, offsets, n_max, src, centers, amb, dt, scale, x, y, z):
+        torch = _torch()
+        k = int(offsets.shape[0]) - 1
+        self._check(self.lib.gx_sn_unframe(self.ctx, _ptr(offsets, torch.int32), k, int(n_max),
+                                           _ptr(src, torch.float64), _ptr(centers, torch.float64),
+                                           _ptr(amb, torch.float32), float(dt), float(scale),
+                                           _ptr(x, torch.float64), _ptr(y, torch.float64),
+                                           _ptr(z, torch.float64)))
+
     def sn_voxelize(self, gas: ParticleSet, u, H, centers, side, grid, u_to_T, amb, mean=None,
                     std=None, out_bf16=None, cpad=8, out_f32=None):
         torch = _torch()
@@ -372,6 +408,22 @@ class Engine:
         self._check(self.lib.gx_grad_combine(self.ctx, int(a.numel()), _ptr(a, torch.bfloat16),
                                              _ptr(b, torch.bfloat16), _ptr(y, torch.bfloat16),
                                              _ptr(out, torch.bfloat16)))
+
+    def chan_stats(self, x, stride, nc, sums):
+        """sums (device float64 [2 nc]) += per-channel sum and sum of squares."""
+        torch = _torch()
+        V = int(x.numel()) // int(stride)
+        self._check(self.lib.gx_chan_stats(self.ctx, V, _ptr(x, torch.float32), int(stride), int(nc),
+                                           _ptr(sums, torch.float64)))
+
+    def chan_affine(self, x, in_stride, nc, scale, shift, out=None, out_stride=None, out_bf16=None,
+                    bf_stride=None):
+        torch = _torch()
+        V = int(x.numel()) // int(in_stride)
+        self._check(self.lib.gx_chan_affine(
+            self.ctx, V, _ptr(x, torch.float32), int(in_stride), int(nc), _ptr(scale, torch.float32),
+            _ptr(shift, torch.float32), _ptr(out, torch.float32), int(out_stride or nc),
+            _ptr(out_bf16, torch.bfloat16), int(bf_stride or nc)))
 
     def f32_to_bf16(self, x, y):
         torch = _torch()

@@ -66,6 +66,10 @@ SIGNATURES = {
     "gx_gravity_list_export": (I32, [P, P, P, P, P, P]),
     "gx_sn_extract": (I32, [P, C.POINTER(GxParticles), P, I32, D, P, P, I64, C.POINTER(I64)]),
     "gx_sn_inject": (I32, [P, C.POINTER(GxParticles), P, P, P, I32, I32, D, P]),
+    "gx_sn_ambient": (I32, [P, C.POINTER(GxParticles), P, P, P, I32, D, D, P]),
+    "gx_sn_gather": (I32, [P, C.POINTER(GxParticles), P, P, P, P, I32, I64, P, P, D, P, P, P, P, P,
+                           P, P, P, P]),
+    "gx_sn_unframe": (I32, [P, P, I32, I64, P, P, P, D, D, P, P, P]),
     "gx_sn_voxelize": (I32, [P, C.POINTER(GxParticles), P, P, P, I32, D, I32, D, P, P, P, P,
                              I32, P]),
     "gx_sn_resample": (I32, [P, P, I32, I32, D, P, P, I64, P, D, P, P, P, P, P, P, P]),
@@ -80,6 +84,8 @@ SIGNATURES = {
     "gx_mse": (I32, [P, P, I32, P, I32, I64, P, C.POINTER(D)]),
     "gx_adam_step": (I32, [P, I64, P, P, P, P, D, D, D, D, I64, P]),
     "gx_f32_to_bf16": (I32, [P, P, I64, P]),
+    "gx_chan_stats": (I32, [P, I64, P, I32, I32, P]),
+    "gx_chan_affine": (I32, [P, I64, P, I32, I32, P, P, P, I32, P, I32]),
     "gx_grad_combine": (I32, [P, I64, P, P, P, P]),
 }
 

@@ -376,13 +376,15 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ pred, int
 __global__ __launch_bounds__(256) void k_adam(int64_t n, float* __restrict__ w,
                                               const float* __restrict__ g, float* __restrict__ m,
                                               float* __restrict__ v, float lr, float b1, float b2,
-                                              float eps, float c1, float c2,
-                                              uint16_t* __restrict__ wbf) {
+                                              float omb1, float omb2, float eps, float c1,
+                                              float c2, uint16_t* __restrict__ wbf) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float gi = g[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    // omb = 1 - b, rounded once from the double value (1.0f - b in FP32 would
+    // lose the low bits of b2 = 0.999)
+    const float mi = b1 * m[i] + omb1 * gi;
+    const float vi = b2 * v[i] + omb2 * gi * gi;
     m[i] = mi;
     v[i] = vi;
     const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
@@ -411,6 +413,65 @@ __global__ void k_f32_to_bf16(const float* __restrict__ x, int64_t n, uint16_t* 
 // ---------------------------------------------------------------------------
 // Host entry points
 // ---------------------------------------------------------------------------
+
+// ---------------------------------------------------------------------------
+// Per-channel statistics and affine maps (standardisation of network inputs
+// and targets, and its inverse on predictions)
+// ---------------------------------------------------------------------------
+#define ST_BLOCKS 256
+#define ST_MAXC 16
+// Per-block FP64 partial sums of x and x^2 of channels [0, nc) over V rows of
+// stride `stride`; part[b][2*nc].
+__global__ __launch_bounds__(256) void k_chan_stats(const float* __restrict__ in, int stride, int nc,
+                                                    int64_t V, double* __restrict__ part) {
+    __shared__ double sh[4][2 * ST_MAXC];
+    double s[2 * ST_MAXC];
+    for (int c = 0; c < 2 * nc; c++) s[c] = 0.0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        for (int c = 0; c < nc; c++) {
+            const double x = in[v * stride + c];
+            s[c] += x;
+            s[nc + c] += x * x;
+        }
+    }
+    for (int c = 0; c < 2 * nc; c++) {
+        const double t = wave_sum(s[c]);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6][c] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * nc) {
+        const int c = threadIdx.x;
+        part[(int64_t)blockIdx.x * 2 * nc + c] = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
+    }
+}
+
+// sums[c] += sum over blocks of part[b][c], in block order (deterministic).
+__global__ void k_chan_stats_final(const double* __restrict__ part, int nb, int m,
+                                   double* __restrict__ sums) {
+    const int c = threadIdx.x;
+    if (c >= m) return;
+    double t = 0.0;
+    for (int b = 0; b < nb; b++) t += part[(int64_t)b * m + c];
+    sums[c] += t;
+}
+
+// out[v][c] = in[v][c] * scale[c] + shift[c] for c < nc, written as FP32 (row
+// stride out_stride) and/or BF16 (row stride bf_stride, channels nc.. zero).
+__global__ void k_chan_affine(const float* __restrict__ in, int in_stride, int nc, int64_t V,
+                              const float* __restrict__ scale, const float* __restrict__ shift,
+                              float* __restrict__ out, int out_stride, uint16_t* __restrict__ obf,
+                              int bf_stride) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    float y[ST_MAXC];
+    for (int c = 0; c < nc; c++) y[c] = fmaf(in[v * in_stride + c], scale[c], shift[c]);
+    if (out)
+        for (int c = 0; c < nc; c++) out[v * out_stride + c] = y[c];
+    if (obf)
+        for (int c = 0; c < bf_stride; c++) obf[v * bf_stride + c] = c < nc ? f2bf(y[c]) : (uint16_t)0;
+}
+
 static int check_conv(gx_ctx* ctx, int B, int S, int Cin, int Cout, int ksize) {
     if (B < 1 || S < 1 || Cin < 8 || Cin % 8 || Cout < 16 || Cout % 16 || (ksize != 3 && ksize != 1))
         return gx_fail(ctx, GX_EINVAL,
@@ -566,7 +627,8 @@ extern "C" int gx_adam_step(gx_ctx* ctx, int64_t n, float* w, const float* grad,
     GX_HIP(ctx, hipSetDevice(ctx->device));
     const double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
     hipLaunchKernelGGL(k_adam, dim3(gx_blocks(n, 256)), dim3(256), 0, ctx->stream, n, w, grad, m, v,
-                       (float)lr, (float)b1, (float)b2, (float)eps, (float)c1, (float)c2, w_bf16);
+                       (float)lr, (float)b1, (float)b2, (float)(1.0 - b1), (float)(1.0 - b2),
+                       (float)eps, (float)c1, (float)c2, w_bf16);
     GX_LAUNCH_CHECK(ctx);
     return GX_OK;
 }
@@ -585,6 +647,35 @@ extern "C" int gx_grad_combine(gx_ctx* ctx, int64_t n, const uint16_t* a, const 
     GX_HIP(ctx, hipSetDevice(ctx->device));
     hipLaunchKernelGGL(k_grad_combine, dim3(gx_blocks(n, 256)), dim3(256), 0, ctx->stream, n, a, b, y,
                        out);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+extern "C" int gx_chan_stats(gx_ctx* ctx, int64_t V, const float* in, int stride, int nc,
+                             double* sums) {
+    if (!ctx || !in || !sums || V < 0 || nc < 1 || nc > ST_MAXC || stride < nc) return GX_EINVAL;
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    GX_TRY(gx_reserve(ctx, ctx->partial, (size_t)ST_BLOCKS * 2 * nc * sizeof(double)));
+    double* part = (double*)ctx->partial.p;
+    hipLaunchKernelGGL(k_chan_stats, dim3(ST_BLOCKS), dim3(256), 0, ctx->stream, in, stride, nc, V,
+                       part);
+    GX_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_chan_stats_final, dim3(1), dim3(64), 0, ctx->stream, part, ST_BLOCKS,
+                       2 * nc, sums);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+extern "C" int gx_chan_affine(gx_ctx* ctx, int64_t V, const float* in, int in_stride, int nc,
+                              const float* scale, const float* shift, float* out, int out_stride,
+                              uint16_t* out_bf16, int bf_stride) {
+    if (!ctx || !in || !scale || !shift || V < 0 || nc < 1 || nc > ST_MAXC || in_stride < nc ||
+        (!out && !out_bf16) || (out && out_stride < nc) || (out_bf16 && bf_stride < nc) ||
+        (out_bf16 && bf_stride > ST_MAXC * 4))
+        return GX_EINVAL;
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_chan_affine, dim3(gx_blocks(V, 256)), dim3(256), 0, ctx->stream, in,
+                       in_stride, nc, V, scale, shift, out, out_stride, out_bf16, bf_stride);
     GX_LAUNCH_CHECK(ctx);
     return GX_OK;
 }

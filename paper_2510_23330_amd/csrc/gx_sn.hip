@@ -194,6 +194,150 @@ extern "C" int gx_sn_inject(gx_ctx* ctx, const gx_particles* gas, const int32_t*
     return GX_OK;
 }
 
+// Ambient state of each box from its members: mean density (total mass over
+// the box volume), mass-weighted temperature and bulk velocity.  One block per
+// box; FP64 sums in a fixed order.
+__global__ __launch_bounds__(256) void k_sn_ambient(const double* __restrict__ vx,
+                                                    const double* __restrict__ vy,
+                                                    const double* __restrict__ vz,
+                                                    const double* __restrict__ m,
+                                                    const double* __restrict__ u,
+                                                    const int32_t* __restrict__ offsets,
+                                                    const int32_t* __restrict__ idx, double volume,
+                                                    double u_to_T, float t_floor,
+                                                    float* __restrict__ amb) {
+    const int c = blockIdx.x;
+    const int b = offsets[c], e = offsets[c + 1];
+    double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int j = b + threadIdx.x; j < e; j += 256) {
+        const int i = idx[j];
+        const double mi = m[i];
+        s[0] += mi;
+        s[1] += mi * u[i];
+        s[2] += mi * vx[i];
+        s[3] += mi * vy[i];
+        s[4] += mi * vz[i];
+    }
+    __shared__ double sh[4][5];
+    for (int q = 0; q < 5; q++) {
+        const double t = wave_sum(s[q]);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6][q] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t[5];
+        for (int q = 0; q < 5; q++) t[q] = (sh[0][q] + sh[1][q]) + (sh[2][q] + sh[3][q]);
+        float* a = amb + 5 * c;
+        if (t[0] > 0.0) {
+            a[0] = (float)log10(t[0] / volume);
+            a[1] = (float)log10(fmax(t[1] / t[0] * u_to_T, (double)t_floor));
+            a[2] = (float)(t[2] / t[0]);
+            a[3] = (float)(t[3] / t[0]);
+            a[4] = (float)(t[4] / t[0]);
+        } else {
+            a[0] = -30.0f;
+            a[1] = log10f(t_floor);
+            a[2] = a[3] = a[4] = 0.0f;
+        }
+    }
+}
+
+extern "C" int gx_sn_ambient(gx_ctx* ctx, const gx_particles* gas, const double* u,
+                             const int32_t* offsets, const int32_t* idx, int k, double side,
+                             double u_to_T, float* amb) {
+    if (!ctx || !gas || !u || !offsets || !idx || !amb || k < 1 || !(side > 0) || !(u_to_T > 0))
+        return GX_EINVAL;
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_sn_ambient, dim3(k), dim3(256), 0, ctx->stream, gas->vx, gas->vy, gas->vz,
+                       gas->m, u, offsets, idx, side * side * side, u_to_T, 10.0f, amb);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+// Pack the members of each box into a compact particle set in the box's own
+// frame (the hand-over of a region to the surrogate, Sec. 3.2 step 2):
+// position (x - c_k) * scale + dst_k, velocity unchanged, kernel size * scale;
+// the members keep their CSR order.
+__global__ void k_sn_gather(int k, const int32_t* __restrict__ offsets,
+                            const int32_t* __restrict__ idx, const double* __restrict__ centers,
+                            const double* __restrict__ dst, double scale,
+                            const double* __restrict__ x, const double* __restrict__ y,
+                            const double* __restrict__ z, const double* __restrict__ vx,
+                            const double* __restrict__ vy, const double* __restrict__ vz,
+                            const double* __restrict__ m, const double* __restrict__ u,
+                            const float* __restrict__ H, double* __restrict__ ox,
+                            double* __restrict__ oy, double* __restrict__ oz,
+                            double* __restrict__ ovx, double* __restrict__ ovy,
+                            double* __restrict__ ovz, double* __restrict__ om,
+                            double* __restrict__ ou, float* __restrict__ oH) {
+    const int c = blockIdx.y;
+    const int b = offsets[c], e = offsets[c + 1];
+    const int j = b + blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= e) return;
+    const int i = idx[j];
+    ox[j] = (x[i] - centers[3 * c]) * scale + dst[3 * c];
+    oy[j] = (y[i] - centers[3 * c + 1]) * scale + dst[3 * c + 1];
+    oz[j] = (z[i] - centers[3 * c + 2]) * scale + dst[3 * c + 2];
+    ovx[j] = vx[i];
+    ovy[j] = vy[i];
+    ovz[j] = vz[i];
+    om[j] = m[i];
+    ou[j] = u[i];
+    if (oH) oH[j] = H ? (float)(H[i] * scale) : -1.0f;
+}
+
+extern "C" int gx_sn_gather(gx_ctx* ctx, const gx_particles* gas, const double* u, const float* H,
+                            const int32_t* offsets, const int32_t* idx, int k, int64_t n_max,
+                            const double* centers, const double* dst, double scale, double* x,
+                            double* y, double* z, double* vx, double* vy, double* vz, double* m,
+                            double* uo, float* Ho) {
+    if (!ctx || !gas || !u || !offsets || !idx || !centers || !dst || k < 1 || n_max < 0 ||
+        !(scale > 0) || !x || !y || !z || !vx || !vy || !vz || !m || !uo)
+        return GX_EINVAL;
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    if (n_max == 0) return GX_OK;
+    const int gxb = (int)((n_max + 255) / 256);
+    hipLaunchKernelGGL(k_sn_gather, dim3(gxb, k), dim3(256), 0, ctx->stream, k, offsets, idx,
+                       centers, dst, scale, gas->x, gas->y, gas->z, gas->vx, gas->vy, gas->vz,
+                       gas->m, u, H, x, y, z, vx, vy, vz, m, uo, Ho);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+// Inverse of the gather for replacement particles: x = (x - src_k) / scale
+// + c_k + v_k dt (v_k = the box's bulk velocity, columns 2..4 of amb, so the
+// particles follow the region's mean motion over the hand-over delay).
+__global__ void k_sn_unframe(int k, const int32_t* __restrict__ offsets,
+                             const double* __restrict__ src, const double* __restrict__ centers,
+                             const float* __restrict__ amb, double dt, double inv_scale,
+                             double* __restrict__ x, double* __restrict__ y,
+                             double* __restrict__ z) {
+    const int c = blockIdx.y;
+    const int b = offsets[c], e = offsets[c + 1];
+    const int j = b + blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= e) return;
+    double s[3];
+    for (int d = 0; d < 3; d++) s[d] = centers[3 * c + d] + (amb ? (double)amb[5 * c + 2 + d] * dt : 0.0);
+    x[j] = (x[j] - src[3 * c]) * inv_scale + s[0];
+    y[j] = (y[j] - src[3 * c + 1]) * inv_scale + s[1];
+    z[j] = (z[j] - src[3 * c + 2]) * inv_scale + s[2];
+}
+
+extern "C" int gx_sn_unframe(gx_ctx* ctx, const int32_t* offsets, int k, int64_t n_max,
+                             const double* src, const double* centers, const float* amb,
+                             double dt, double scale, double* x, double* y, double* z) {
+    if (!ctx || !offsets || !src || !centers || k < 1 || n_max < 0 || !(scale > 0) || !x || !y ||
+        !z)
+        return GX_EINVAL;
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    if (n_max == 0) return GX_OK;
+    const int gxb = (int)((n_max + 255) / 256);
+    hipLaunchKernelGGL(k_sn_unframe, dim3(gxb, k), dim3(256), 0, ctx->stream, k, offsets, src,
+                       centers, amb, dt, 1.0 / scale, x, y, z);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Voxelisation: rho_v = sum_j m_j W(|x_v - x_j|, H_j); T_v and v_v are Shepard
 // averages sum_j f_j W_j / sum_j W_j.  Voxels are grouped into 4^3 blocks (one

@@ -55,6 +55,7 @@ class SNBatch:
         self.dt = torch.zeros(1, dtype=torch.float64, device=device)
         self.t = 0.0
         self.steps = 0
+        self.noconv = 0          # kernel-size solves that hit the iteration cap
         self.u_floor = cfg.t_floor * U_PER_K
 
     def ambient(self):
@@ -85,7 +86,9 @@ class SNBatch:
             u = self.upred
         else:
             view, u = self.p, None
-        self.eng.sph_density(view, self.g, c.n_ngb, c.gamma, c.h_tol, c.max_iter, u=u)
+        d = self.eng.sph_density(view, self.g, c.n_ngb, c.gamma, c.h_tol, c.max_iter, u=u,
+                                 allow_noconv=True)
+        self.noconv += int(d.get("n_noconv", 0))
         self.eng.sph_forces(view, self.g, self.ax, self.ay, self.az, gamma=c.gamma, alpha=c.alpha,
                             u=u)
 
@@ -108,9 +111,22 @@ class SNBatch:
                                 dudt=self.g.dudt, u_floor=self.u_floor)
             self.t += dt
             self.steps += 1
+            self._guard()
             if log and self.steps % 50 == 0:
                 log(f"[sn] step {self.steps} t = {self.t / MYR * 1e3:.2f} kyr dt = {dt / MYR * 1e6:.1f} yr")
         return self.steps
+
+    def _guard(self, x_max: float = 1e7, u_max: float = 1e12):
+        """Stop a run whose state left the representable range (a forced
+        timestep far above the Courant limit can do that) before the next tree
+        build or kernel-size solve sees it."""
+        torch = self.torch
+        p = self.p
+        m = torch.stack([p.x.abs().max(), p.y.abs().max(), p.z.abs().max(), self.g.u.max()])
+        m = m.cpu().numpy()
+        if not (np.all(np.isfinite(m)) and m[:3].max() < x_max and m[3] < u_max):
+            raise FloatingPointError(f"SPH state diverged at step {self.steps} "
+                                     f"(max |x| {m[:3].max():.3g}, max u {m[3]:.3g})")
 
     def energy(self):
         """(kinetic, thermal) totals; no gravity inside cubes."""
@@ -132,20 +148,129 @@ class SNBatch:
         return out_f32
 
 
-def generate(eng: Engine, seeds, t_end_myr: float = 0.1, log=None, cfg: SPHConfig = SPHConfig()):
+def generate(eng: Engine, seeds, t_end_myr: float = 0.1, log=None, cfg: SPHConfig = SPHConfig(),
+             dt_fixed_myr: float = None, keep=False):
     """One batch of training pairs: voxel grids just before the explosion and
-    t_end after it, from plain small-dt SPH.  Returns (x, y, info) with x, y
-    device float [K, 64^3, 5]."""
+    t_end after it, from plain small-dt SPH (or fixed steps of dt_fixed_myr).
+    Returns (x, y, info) with x, y device float [K * 64^3 * 5] physical
+    channels; info["batch"] is the SNBatch at t = 0 voxelization state when
+    keep is set (its particles then hold the final state)."""
     import ics
     b = ics.sn_batch(seeds)
     sb = SNBatch(eng, b, cfg)
     x = sb.voxelize()
-    sb.inject()
+    sb.torch.cuda.synchronize()
     t0 = time.perf_counter()
-    steps = sb.run(t_end_myr * MYR, log=log)
+    sb.inject()
+    steps = sb.run(t_end_myr * MYR, log=log,
+                   dt_fixed=None if dt_fixed_myr is None else dt_fixed_myr * MYR)
     sb.torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     y = sb.voxelize()
-    info = {"steps": steps, "seconds": wall, "n_particles": sb.n, "K": sb.K,
+    info = {"steps": steps, "seconds": wall, "n_particles": sb.n, "K": sb.K, "noconv": sb.noconv,
             "n_cm3": b["n_cm3"].tolist(), "T": b["T_amb"].tolist()}
+    if keep:
+        info["batch"] = sb
     return x, y, info
+
+
+class Surrogate:
+    """The learned replacement of a supernova region's plain SPH (Sec. 3.3):
+    U-Net weights plus the channel statistics that standardise its inputs and
+    targets.  Inputs are the voxelized state just before the explosion,
+    outputs the physical channels 0.1 Myr after it."""
+
+    def __init__(self, eng: Engine, batch: int = 4, base: int = 32, levels: int = 4,
+                 grid: int = GRID, seed: int = 0, device="cuda", train: bool = True):
+        import torch
+        from .unet import UNet
+        self.torch, self.eng, self.grid, self.device = torch, eng, grid, device
+        self.net = UNet(eng, S=grid, batch=batch, base=base, levels=levels, seed=seed, device=device,
+                        train=train)
+        f = dict(dtype=torch.float32, device=device)
+        self.mean_in, self.std_in = torch.zeros(5, **f), torch.ones(5, **f)
+        self.mean_out, self.std_out = torch.zeros(5, **f), torch.ones(5, **f)
+        self.V = grid ** 3
+
+    # ---- statistics -----------------------------------------------------------
+    @staticmethod
+    def _moments(sums, count):
+        s = sums.double().cpu().numpy()
+        nc = s.size // 2
+        mean = s[:nc] / count
+        var = np.maximum(s[nc:] / count - mean ** 2, 0.0)
+        return mean, np.sqrt(var)
+
+    def set_stats(self, sums_in, sums_out, count, min_std: float = 1e-3):
+        torch = self.torch
+        mi, si = self._moments(sums_in, count)
+        mo, so = self._moments(sums_out, count)
+        for dst, v in ((self.mean_in, mi), (self.std_in, np.maximum(si, min_std)),
+                       (self.mean_out, mo), (self.std_out, np.maximum(so, min_std))):
+            dst.copy_(torch.as_tensor(v, dtype=torch.float32))
+
+    def standardize(self, x_f32, which="in", out_f32=None, out_bf16=None):
+        """(x - mean) / std per channel of physical [.., 5] rows."""
+        mean, std = (self.mean_in, self.std_in) if which == "in" else (self.mean_out, self.std_out)
+        self.eng.chan_affine(x_f32, 5, 5, 1.0 / std, -mean / std, out=out_f32, out_stride=5,
+                             out_bf16=out_bf16, bf_stride=8)
+
+    # ---- inference ------------------------------------------------------------
+    def infer(self, x_bf16, K: int, out_f32):
+        """x_bf16 [K * V * 8] standardized inputs -> out_f32 [K * V * 5] physical."""
+        net, V, B = self.net, self.V, self.net.B
+        for a in range(0, K, B):
+            b = min(B, K - a)
+            net.Bcur = b
+            pred = net.forward(x_bf16[a * V * 8:(a + b) * V * 8])
+            self.eng.chan_affine(pred[:b * V * 16], 16, 5, self.std_out, self.mean_out,
+                                 out=out_f32[a * V * 5:(a + b) * V * 5], out_stride=5)
+        net.Bcur = B
+        return out_f32
+
+    def regions(self, p: ParticleSet, g: GasState, centers, side: float = SIDE, cap: int = None,
+                cfg: SPHConfig = SPHConfig(), uniforms=None, build_tree=True):
+        """Extract -> voxelize -> infer -> resample for K regions (Sec. 3.2
+        steps 2-4).  Returns (offsets, idx, new) with new = dict of device FP64
+        arrays x, y, z, vx, vy, vz, u of the replacement particles (CSR by
+        region, same count as the members idx it replaces)."""
+        torch, eng = self.torch, self.eng
+        K = int(centers.shape[0])
+        dev = centers.device
+        off, idx, tot = eng.sn_extract(p, centers, side / 2, cap or p.n)
+        amb = eng.sn_ambient(p, g.u, off, idx, side, 1.0 / U_PER_K)
+        if build_tree:
+            eng.tree_build(p, GX_TREE_GAS, cfg.n_leaf, cfg.n_group)
+        xin = torch.empty(K * self.V * 8, dtype=torch.bfloat16, device=dev)
+        eng.sn_voxelize(p, g.u, g.H, centers, side, self.grid, 1.0 / U_PER_K, amb,
+                        mean=self.mean_in, std=self.std_in, out_bf16=xin, cpad=8)
+        pred = torch.empty(K * self.V * 5, dtype=torch.float32, device=dev)
+        self.infer(xin, K, pred)
+        new = {k: torch.empty(max(tot, 1), dtype=torch.float64, device=dev)
+               for k in ("x", "y", "z", "vx", "vy", "vz", "u")}
+        if tot > 0:
+            n_max = int((off[1:] - off[:-1]).max().item())
+            if uniforms is None:
+                uniforms = torch.rand(tot * 4, dtype=torch.float32, device=dev)
+            eng.sn_resample(pred, centers, self.grid, side, off, n_max, uniforms, U_PER_K,
+                            *(new[k] for k in ("x", "y", "z", "vx", "vy", "vz", "u")))
+        return off, idx, {k: v[:tot] for k, v in new.items()}, pred
+
+    # ---- persistence ----------------------------------------------------------
+    def save(self, path, moments: bool = False):
+        """Weights (FP32 master copy) and channel statistics; Adam moments only
+        when asked (they triple the file)."""
+        d = self.net.state_dict()
+        extra = {"m": d["m"], "v": d["v"]} if moments else {}
+        np.savez(path, w32=d["w32"], t=d["t"], **extra,
+                 mean_in=self.mean_in.cpu().numpy(), std_in=self.std_in.cpu().numpy(),
+                 mean_out=self.mean_out.cpu().numpy(), std_out=self.std_out.cpu().numpy())
+
+    def load(self, path):
+        d = np.load(path)
+        z = np.zeros_like(d["w32"])
+        self.net.load_state_dict({"w32": d["w32"], "m": d["m"] if "m" in d else z,
+                                  "v": d["v"] if "v" in d else z,
+                                  "t": int(d["t"]) if "m" in d else 0})
+        for k in ("mean_in", "std_in", "mean_out", "std_out"):
+            getattr(self, k).copy_(self.torch.as_tensor(d[k]))

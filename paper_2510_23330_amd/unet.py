@@ -84,7 +84,7 @@ def flops_forward(S: int, base: int = 32, levels: int = 4) -> float:
 
 class UNet:
     def __init__(self, eng, S: int = 64, batch: int = 4, base: int = 32, levels: int = 4,
-                 seed: int = 0, device="cuda"):
+                 seed: int = 0, device="cuda", train: bool = True):
         import torch
         self.torch = torch
         self.eng = eng
@@ -116,6 +116,7 @@ class UNet:
         eng.f32_to_bf16(self.w32, self.wbf)
         self.t = 0
         self.device = device
+        self.train_mode = train
         self.acts = {}
         self._alloc(batch)
 
@@ -140,10 +141,13 @@ class UNet:
             A[f"d{l}b"] = torch.zeros(B * s ** 3 * ch[l], **bf)
         self.pred = torch.zeros(B * S ** 3 * COUT_PAD, dtype=torch.float32, device=self.device)
         self.acts = A
-        self.G = {k: torch.zeros_like(v) for k, v in A.items()}
-        self.G["skip"] = {l: torch.zeros(B * (S // 2 ** l) ** 3 * ch[l], **bf)
-                          for l in range(self.levels - 1)}
-        self.dpred = torch.zeros(B * S ** 3 * COUT_PAD, **bf)
+        if self.train_mode:
+            self.G = {k: torch.zeros_like(v) for k, v in A.items()}
+            self.G["skip"] = {l: torch.zeros(B * (S // 2 ** l) ** 3 * ch[l], **bf)
+                              for l in range(self.levels - 1)}
+            self.dpred = torch.zeros(B * S ** 3 * COUT_PAD, **bf)
+        else:
+            self.G, self.dpred = None, None
         self.Bcur = B
 
     def _w(self, ly):

@@ -156,3 +156,128 @@ def test_replace_by_id(gx, eng):
     assert uh[0] == 60.0 and uh[999] == 62.0
     hh = H64.cpu().numpy()
     assert hh[0] == -1.0 and hh[999] == -1.0 and hh[1] == 1.0
+
+
+def _sedov_cube(n_side=31, side=60.0, T=100.0):
+    dx = side / n_side
+    g = (np.arange(n_side) + 0.5) * dx - side / 2
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    n = n_side ** 3
+    d = {"x": X.ravel().copy(), "y": Y.ravel().copy(), "z": Z.ravel().copy(),
+         "vx": np.zeros(n), "vy": np.zeros(n), "vz": np.zeros(n), "m": np.ones(n),
+         "eps2": np.full(n, 0.01, np.float32), "u": np.full(n, T * ics.U_PER_K)}
+    d["offsets"] = np.array([0, n], np.int64)
+    d["centres"] = np.zeros((1, 3))
+    d["T_amb"] = np.array([T])
+    d["n_cm3"] = np.array([n / side ** 3 / ics.MSUN_PC3_PER_CM3])
+    return d
+
+
+def test_sedov_taylor_blast(gx, eng):
+    # Point explosion of 1e51 erg in a uniform cold cube (n ~ 4 cm^-3): the
+    # density peak of the shell sits at the Sedov-Taylor radius
+    # R = 1.15 (E t^2 / rho)^(1/5) (gamma = 5/3) after 0.1 Myr, and total
+    # energy is conserved while the blast stays inside the cube.
+    from paper_2510_23330_amd.sn import MYR, SNBatch
+    d = _sedov_cube()
+    sb = SNBatch(eng, d)
+    sb._forces(predicted=False)
+    sb.inject()
+    K0, U0 = sb.energy()
+    E0 = K0 + U0
+    t_end = 0.1 * MYR
+    steps = sb.run(t_end)
+    K1, U1 = sb.energy()
+    rho0 = d["m"].sum() / 60.0 ** 3
+    R_st = 1.15 * (ics.E_SN * t_end ** 2 / rho0) ** 0.2
+    x, y, z = (a.cpu().numpy() for a in (sb.p.x, sb.p.y, sb.p.z))
+    r = np.sqrt(x * x + y * y + z * z)
+    rho = sb.g.rho.cpu().numpy().astype(np.float64)
+    edges = np.arange(0.0, 30.5, 1.0)
+    which = np.digitize(r, edges) - 1
+    prof = np.array([rho[which == b].mean() if np.any(which == b) else 0.0
+                     for b in range(len(edges) - 1)])
+    R_peak = 0.5 * (edges[np.argmax(prof)] + edges[np.argmax(prof) + 1])
+    dE = abs((K1 + U1) - E0) / E0
+    print(f"sedov: steps {steps} R_peak {R_peak:.2f} pc R_ST {R_st:.2f} pc "
+          f"peak/rho0 {prof.max() / rho0:.2f} dE/E {dE:.2e} K/E {K1 / (K1 + U1):.3f}")
+    assert abs(R_peak - R_st) <= 0.1 * R_st
+    assert prof.max() > 2.0 * rho0
+    # kinetic fraction of the Sedov solution (gamma = 5/3): about 0.28
+    assert 0.2 < K1 / (K1 + U1) < 0.36
+    assert dE <= 1e-3
+
+
+def test_coupling_replaces_by_id(gx, eng):
+    # Surrogate-coupled galaxy step: the gas in each site's box is replaced,
+    # by ID, after the delay, with as many particles as were extracted, placed
+    # inside the box drifted by its bulk velocity, carrying the predicted
+    # state.  A network with zero weights predicts exactly its output mean,
+    # which fixes every replaced value.
+    import torch
+    from paper_2510_23330_amd.coupling import SNCoupling
+    from paper_2510_23330_amd.sim import GalaxyStep, StepConfig
+    from paper_2510_23330_amd.sn import Surrogate
+    d = ics.disk_galaxy(200_000, seed=3)
+    p = gx.ParticleSet.from_numpy(d)
+    go = d["gas_offset"]
+    u = torch.as_tensor(d["u_gas"], device="cuda")
+    cfg = StepConfig(G=ics.G_KPC, dt=2000.0 / 0.97779e9)
+    st = GalaxyStep(eng, p, go, u, cfg)
+    st.initial_forces()
+    sur_eng = gx.Engine(0)
+    sur = Surrogate(sur_eng, batch=4, base=16, levels=3, grid=16, seed=0)
+    sur.net.w32.zero_()
+    sur_eng.f32_to_bf16(sur.net.w32, sur.net.wbf)
+    mean_out = torch.tensor([-1.0, 4.0, 1.0, 2.0, 3.0], device="cuda")
+    sur.mean_out.copy_(mean_out)
+    side_pc = 600.0
+    cp = SNCoupling(st, sur, n_sites=16, delay=1, side_pc=side_pc, seed=11)
+    centers = cp.sites(0).cpu().numpy()
+    gx_, gy, gz = (a.cpu().numpy() for a in (st.gas.x, st.gas.y, st.gas.z))
+    gvx, gvy, gvz = (a.cpu().numpy() for a in (st.gas.vx, st.gas.vy, st.gas.vz))
+    gm = st.gas.m.cpu().numpy()
+    gid = d["id"][go:]
+    h = 0.5 * side_pc / 1000.0
+    members = []
+    for c in centers:
+        inb = np.nonzero((gx_ >= c[0] - h) & (gx_ < c[0] + h) & (gy >= c[1] - h) & (gy < c[1] + h) &
+                         (gz >= c[2] - h) & (gz < c[2] + h))[0]
+        members.append(inb)
+    assert sum(len(m) for m in members) > 50
+    cp.launch(0)
+    st.step()
+    cp.apply_due(1)
+    assert cp.stats["missing_ids"] == 0
+    assert cp.stats["particles_replaced"] == sum(len(m) for m in members)
+    ids = st.p.id.cpu().numpy()
+    pos = {int(i): k for k, i in enumerate(ids)}
+    X, Y, Z = (a.cpu().numpy() for a in (st.p.x, st.p.y, st.p.z))
+    VX, VY, VZ = (a.cpu().numpy() for a in (st.p.vx, st.p.vy, st.p.vz))
+    U = st.g.u.cpu().numpy()
+    dt_delay = cfg.dt * 1
+    boxes = []
+    for c, mem in zip(centers, members):
+        if len(mem):
+            w = gm[mem] / gm[mem].sum()
+            vb = np.array([np.sum(w * gvx[mem]), np.sum(w * gvy[mem]), np.sum(w * gvz[mem])])
+            boxes.append(c + vb * dt_delay)
+        else:
+            boxes.append(None)
+    for mem in members:
+        if len(mem) == 0:
+            continue
+        k = np.array([pos[int(gid[j])] for j in mem])
+        # each replaced particle lies in (one of) the drifted boxes it was taken from
+        inside = np.zeros(len(k), bool)
+        for b, mem2 in zip(boxes, members):
+            if b is None:
+                continue
+            common = np.isin(mem, mem2)
+            tol = h * (1 + 1e-9)
+            inside |= common & (np.abs(X[k] - b[0]) <= tol) & (np.abs(Y[k] - b[1]) <= tol) & \
+                (np.abs(Z[k] - b[2]) <= tol)
+        assert inside.all()
+        assert np.allclose(VX[k], 1.0) and np.allclose(VY[k], 2.0) and np.allclose(VZ[k], 3.0)
+        assert np.allclose(U[k - go], 1e4 * ics.U_PER_K, rtol=1e-5)
+    sur_eng.close()
