@@ -8,11 +8,19 @@ A step is the whole hot path: half kick + drift (FP64), gravity tree build,
 interaction lists and pairwise gravity (FP32 group-relative), gas tree build,
 kernel size + density, hydro force, second half kick, FP64 energy audit.
 
+Each step also hands 64 supernova regions (60 pc boxes around seeded disk
+stars) to the surrogate -- extract, voxelize, U-Net inference, resample --
+and replaces returned regions by particle ID 50 steps later (the network is
+randomly initialised here: only its cost is measured).
+
 Prints ONE JSON line.  ``value`` = gravity interactions (particle-particle +
 particle-cell) per second of whole-step wall time.  ``roofline`` reports the
 dominant kernel (pairwise gravity) against the FP32 vector peak, timed live
-with HIP events on the library's stream.  ``cpu_baseline`` times the FP64
-oracle's tree gravity on a seeded sample of the same workload's groups.
+with HIP events on the library's stream.  ``sn_region`` compares, for 64 SN
+cubes of 1 Msun particles, the plain small-timestep SPH to 0.1 Myr with the
+surrogate path on the same cubes, and the network's inference throughput at
+batch 256.  ``cpu_baseline`` times the FP64 oracle's tree gravity on a
+seeded sample of the same workload's groups.
 """
 from __future__ import annotations
 
@@ -145,6 +153,7 @@ def main():
         coupling = SNCoupling(sim, Surrogate(sur_eng, batch=32, seed=0, train=False),
                               n_sites=args.sn_sites, delay=50)
     torch.cuda.synchronize()
+    log("[bench] set-up done; initial forces (cold kernel sizes) ...")
     t0 = time.perf_counter()
     sim.initial_forces()
     torch.cuda.synchronize()
@@ -215,7 +224,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "disk galaxy 16M: 8e6 disk stars, 6.4e6 NFW halo, 1.6e6 gas disk; "
                                "theta 0.5 + quadrupole, n_leaf 16, groups <= 256; SPH Wendland C4, "
-                               "64 neighbours, groups <= 64; dt 2000 yr",
+                               "64 neighbours, groups <= 64; dt 2000 yr; 64 SN regions per step "
+                               "to the surrogate",
                    "n_particles": args.n, "seed": args.seed},
         "s_per_step": ms_step / 1e3,
         "grav_interactions_per_step": inter_step,

@@ -67,6 +67,7 @@ struct TreeSlot {
 struct ListSet {  // per-group interaction lists (CSR)
     Buf pc_cnt, pc_off, pc_list;
     Buf pr_cnt, pr_off, pr_begin, pr_cum, pp_tot;
+    Buf aux;  // per-group flags of the second-level overflow path
     Buf tot;  // device counters: [0] n_pc entries, [1] n_ranges, [2] n_pp inter, [3] n_pc inter
     int64_t n_groups = 0, n_pc = 0, n_ranges = 0;
 };

@@ -42,31 +42,49 @@ struct ConvGeom {
     int B, S, Cin, Cout, kvol;
     int64_t M;  // B * S^3
     int K;      // kvol * Cin
+    int lgC;    // log2(Cin): the GEMM's K channel count is a power of two
 };
 
-// Load 8 consecutive K entries (one tap, 8 channels) of im2col row m.
-__device__ __forceinline__ uint4 im2col8(const uint16_t* __restrict__ in, const ConvGeom& g,
-                                         int64_t m, int k) {
+// Voxel coordinates of implicit-GEMM row m (one decomposition per row, reused
+// for every K slice).
+struct RowXYZ {
+    int64_t m;
+    int x, y, z;
+    bool ok;
+};
+
+__device__ __forceinline__ RowXYZ row_xyz(const ConvGeom& g, int64_t m) {
+    RowXYZ r{m, 0, 0, 0, m < g.M};
+    if (r.ok) {
+        const int S = g.S;
+        int64_t t = m / S;
+        r.x = (int)(m - t * S);
+        const int64_t t2 = t / S;
+        r.y = (int)(t - t2 * S);
+        r.z = (int)(t2 % S);
+    }
+    return r;
+}
+
+// 8 consecutive K entries (one tap, 8 channels) of im2col row r.
+__device__ __forceinline__ uint4 im2col8r(const uint16_t* __restrict__ in, const ConvGeom& g,
+                                          const RowXYZ& r, int k) {
     uint4 z = make_uint4(0, 0, 0, 0);
-    if (m >= g.M || k >= g.K) return z;
-    const int tap = k / g.Cin, ci = k - tap * g.Cin;
-    const int S = g.S;
-    int64_t t = m;
-    const int x = (int)(t % S);
-    t /= S;
-    const int y = (int)(t % S);
-    t /= S;
-    const int zz = (int)(t % S);
-    const int64_t b = t / S;
+    if (!r.ok || k >= g.K) return z;
+    const int tap = k >> g.lgC, ci = k & (g.Cin - 1);
     int dx = 0, dy = 0, dz = 0;
     if (g.kvol == 27) {
-        dz = tap / 9 - 1;
-        dy = (tap / 3) % 3 - 1;
-        dx = tap % 3 - 1;
+        dz = tap / 9;
+        const int rr = tap - dz * 9;
+        dy = rr / 3;
+        dx = rr - dy * 3 - 1;
+        dy -= 1;
+        dz -= 1;
     }
-    const int X = x + dx, Y = y + dy, Z = zz + dz;
+    const int S = g.S;
+    const int X = r.x + dx, Y = r.y + dy, Z = r.z + dz;
     if (X < 0 || X >= S || Y < 0 || Y >= S || Z < 0 || Z >= S) return z;
-    const int64_t v = ((b * S + Z) * S + Y) * S + X;
+    const int64_t v = r.m + ((int64_t)dz * S + dy) * S + dx;
     return *reinterpret_cast<const uint4*>(in + v * g.Cin + ci);
 }
 
@@ -80,8 +98,10 @@ __global__ __launch_bounds__(256) void k_conv3d(const uint16_t* __restrict__ in,
                                                 int mode, const uint16_t* __restrict__ yref,
                                                 uint16_t* __restrict__ out_bf,
                                                 float* __restrict__ out_f32) {
-    __shared__ __attribute__((aligned(16))) uint16_t sA[CV_BM * CV_APITCH];
-    __shared__ __attribute__((aligned(16))) uint16_t sB[BN * CV_APITCH];
+    // two LDS stages: the next K slice is fetched into registers while the
+    // current one feeds the matrix cores, then stored into the other stage
+    __shared__ __attribute__((aligned(16))) uint16_t sA[2][CV_BM * CV_APITCH];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN * CV_APITCH];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t m0 = (int64_t)blockIdx.x * CV_BM;
     const int n0 = blockIdx.y * BN;
@@ -92,38 +112,49 @@ __global__ __launch_bounds__(256) void k_conv3d(const uint16_t* __restrict__ in,
 #pragma unroll
         for (int j = 0; j < NT; j++) acc[i][j] = f32x4{0, 0, 0, 0};
 
+    // staging roles: A rows tid/4 and 64 + tid/4, 8-channel group tid%4;
+    // B row tid/4 (output channel) for tid < 4 BN
+    const int grp = tid & 3;
+    const RowXYZ r0 = row_xyz(g, m0 + (tid >> 2));
+    const RowXYZ r1 = row_xyz(g, m0 + 64 + (tid >> 2));
+    const bool bst = tid < BN * 4;
+    const uint16_t* wrow = w + (int64_t)(n0 + (tid >> 2)) * g.K;
+    uint4 va0, va1, vb = make_uint4(0, 0, 0, 0);
+    auto fetch = [&](int k0) {
+        const int k = k0 + grp * 8;
+        va0 = im2col8r(in, g, r0, k);
+        va1 = im2col8r(in, g, r1, k);
+        if (bst) vb = k < g.K ? *reinterpret_cast<const uint4*>(wrow + k) : make_uint4(0, 0, 0, 0);
+    };
+    auto stage = [&](int buf) {
+        *reinterpret_cast<uint4*>(&sA[buf][(tid >> 2) * CV_APITCH + grp * 8]) = va0;
+        *reinterpret_cast<uint4*>(&sA[buf][(64 + (tid >> 2)) * CV_APITCH + grp * 8]) = va1;
+        if (bst) *reinterpret_cast<uint4*>(&sB[buf][(tid >> 2) * CV_APITCH + grp * 8]) = vb;
+    };
+    fetch(0);
+    stage(0);
+    __syncthreads();
+    int cur = 0;
+    const int kq = (lane >> 4) * 8;
     for (int k0 = 0; k0 < g.K; k0 += CV_BK) {
-        // stage A: 128 rows x 4 groups of 8
-#pragma unroll
-        for (int r = 0; r < 2; r++) {
-            const int e = tid + r * 256;
-            const int row = e >> 2, grp = e & 3;
-            const uint4 v = im2col8(in, g, m0 + row, k0 + grp * 8);
-            *reinterpret_cast<uint4*>(&sA[row * CV_APITCH + grp * 8]) = v;
-        }
-        // stage B: BN rows (output channels) x 4 groups of 8
-        if (tid < BN * 4) {
-            const int row = tid >> 2, grp = tid & 3;
-            const int k = k0 + grp * 8;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (k < g.K) v = *reinterpret_cast<const uint4*>(w + (int64_t)(n0 + row) * g.K + k);
-            *reinterpret_cast<uint4*>(&sB[row * CV_APITCH + grp * 8]) = v;
-        }
-        __syncthreads();
-        const int kq = (lane >> 4) * 8;
+        const bool more = k0 + CV_BK < g.K;
+        if (more) fetch(k0 + CV_BK);
         bf16x8 a[2], b[NT];
 #pragma unroll
         for (int i = 0; i < 2; i++)
-            a[i] = *reinterpret_cast<const bf16x8*>(&sA[(wv * 32 + i * 16 + (lane & 15)) * CV_APITCH + kq]);
+            a[i] = *reinterpret_cast<const bf16x8*>(
+                &sA[cur][(wv * 32 + i * 16 + (lane & 15)) * CV_APITCH + kq]);
 #pragma unroll
         for (int j = 0; j < NT; j++)
-            b[j] = *reinterpret_cast<const bf16x8*>(&sB[(j * 16 + (lane & 15)) * CV_APITCH + kq]);
+            b[j] = *reinterpret_cast<const bf16x8*>(&sB[cur][(j * 16 + (lane & 15)) * CV_APITCH + kq]);
 #pragma unroll
         for (int i = 0; i < 2; i++)
 #pragma unroll
             for (int j = 0; j < NT; j++)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        if (more) stage(cur ^ 1);
         __syncthreads();
+        cur ^= 1;
     }
     // epilogue: lane holds rows 4*(lane/16) + t of each 16 x 16 tile, column lane % 16
 #pragma unroll
@@ -191,7 +222,7 @@ __global__ __launch_bounds__(256) void k_conv3d_wgrad(const uint16_t* __restrict
             const int mrow = tid >> 3, grp = tid & 7;
             const int64_t m = m0 + mrow;
             uint4 v = make_uint4(0, 0, 0, 0);
-            if (m < me) v = im2col8(in, g, m, k0 + grp * 8);
+            if (m < me) v = im2col8r(in, g, row_xyz(g, m), k0 + grp * 8);
             const uint16_t* h = reinterpret_cast<const uint16_t*>(&v);
 #pragma unroll
             for (int q = 0; q < 8; q++) sAt[(grp * 8 + q) * CV_APITCH + mrow] = h[q];
@@ -472,10 +503,22 @@ __global__ void k_chan_affine(const float* __restrict__ in, int in_stride, int n
         for (int c = 0; c < bf_stride; c++) obf[v * bf_stride + c] = c < nc ? f2bf(y[c]) : (uint16_t)0;
 }
 
-static int check_conv(gx_ctx* ctx, int B, int S, int Cin, int Cout, int ksize) {
+static int ilog2(int v) {
+    int l = 0;
+    while ((1 << l) < v) l++;
+    return l;
+}
+static bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// kch: the channel count that forms the GEMM's K dimension with the taps (Cin
+// for forward and weight gradient, Cout for the data gradient); it must be a
+// power of two >= 8 so that a K slice splits into tap and channel by shifts.
+static int check_conv(gx_ctx* ctx, int B, int S, int Cin, int Cout, int ksize, int kch) {
     if (B < 1 || S < 1 || Cin < 8 || Cin % 8 || Cout < 16 || Cout % 16 || (ksize != 3 && ksize != 1))
         return gx_fail(ctx, GX_EINVAL,
                        "conv3d: need B, S >= 1, Cin % 8 == 0, Cout % 16 == 0, ksize 1 or 3");
+    if (!pow2(kch))
+        return gx_fail(ctx, GX_EINVAL, "conv3d: the reduced channel count must be a power of two");
     return GX_OK;
 }
 
@@ -500,10 +543,10 @@ extern "C" int gx_conv3d_fwd(gx_ctx* ctx, const uint16_t* in, int B, int S, int 
                              const uint16_t* w, const float* bias, int ksize, int Cout, int act,
                              uint16_t* out_bf16, float* out_f32) {
     if (!ctx || !in || !w || (!out_bf16 && !out_f32)) return GX_EINVAL;
-    GX_TRY(check_conv(ctx, B, S, Cin, Cout, ksize));
+    GX_TRY(check_conv(ctx, B, S, Cin, Cout, ksize, Cin));
     GX_HIP(ctx, hipSetDevice(ctx->device));
     const int kv = ksize == 3 ? 27 : 1;
-    ConvGeom g{B, S, Cin, Cout, kv, (int64_t)B * S * S * S, kv * Cin};
+    ConvGeom g{B, S, Cin, Cout, kv, (int64_t)B * S * S * S, kv * Cin, ilog2(Cin)};
     return launch_conv(ctx, in, w, bias, g, act ? EP_LRELU : EP_NONE, nullptr, out_bf16, out_f32);
 }
 
@@ -511,7 +554,7 @@ extern "C" int gx_conv3d_bwd_data(gx_ctx* ctx, const uint16_t* dout, int B, int 
                                   const uint16_t* w, int ksize, int Cout, const uint16_t* y_in,
                                   uint16_t* din) {
     if (!ctx || !dout || !w || !din) return GX_EINVAL;
-    GX_TRY(check_conv(ctx, B, S, Cin, Cout, ksize));
+    GX_TRY(check_conv(ctx, B, S, Cin, Cout, ksize, Cout));
     if (Cin % 16) return gx_fail(ctx, GX_EINVAL, "conv3d_bwd_data: Cin % 16 == 0 required");
     GX_HIP(ctx, hipSetDevice(ctx->device));
     const int kv = ksize == 3 ? 27 : 1;
@@ -520,17 +563,17 @@ extern "C" int gx_conv3d_bwd_data(gx_ctx* ctx, const uint16_t* dout, int B, int 
     uint16_t* wf = (uint16_t*)ctx->scan_tmp[2].p;
     hipLaunchKernelGGL(k_wflip, dim3(gx_blocks(nw, 256)), dim3(256), 0, ctx->stream, w, Cout, Cin,
                        kv, wf);
-    ConvGeom g{B, S, Cout, Cin, kv, (int64_t)B * S * S * S, kv * Cout};
+    ConvGeom g{B, S, Cout, Cin, kv, (int64_t)B * S * S * S, kv * Cout, ilog2(Cout)};
     return launch_conv(ctx, dout, wf, nullptr, g, y_in ? EP_DACT : EP_NONE, y_in, din, nullptr);
 }
 
 extern "C" int gx_conv3d_bwd_weight(gx_ctx* ctx, const uint16_t* in, const uint16_t* dout, int B,
                                     int S, int Cin, int ksize, int Cout, float* dw, float* dbias) {
     if (!ctx || !in || !dout || !dw) return GX_EINVAL;
-    GX_TRY(check_conv(ctx, B, S, Cin, Cout, ksize));
+    GX_TRY(check_conv(ctx, B, S, Cin, Cout, ksize, Cin));
     GX_HIP(ctx, hipSetDevice(ctx->device));
     const int kv = ksize == 3 ? 27 : 1;
-    ConvGeom g{B, S, Cin, Cout, kv, (int64_t)B * S * S * S, kv * Cin};
+    ConvGeom g{B, S, Cin, Cout, kv, (int64_t)B * S * S * S, kv * Cin, ilog2(Cin)};
     // split the voxel reduction so the grid has >= ~2048 blocks
     const int kt = (g.K + 63) / 64;
     const int bn = Cout % 64 == 0 ? 64 : (Cout % 32 == 0 ? 32 : 16);

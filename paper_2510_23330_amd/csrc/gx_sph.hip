@@ -39,6 +39,14 @@ __global__ __launch_bounds__(64) void k_walk_sph_bfs(
     uint32_t* __restrict__ pr_cnt, uint32_t* __restrict__ pp_tot,
     unsigned long long* __restrict__ tot, int32_t* __restrict__ pr_begin,
     int32_t* __restrict__ pr_cum, uint8_t* __restrict__ ovf);
+__global__ __launch_bounds__(64) void k_walk_sph_wave(
+    int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ recv,
+    const NodeRec* __restrict__ nodes, const int32_t* __restrict__ child,
+    const MomRec* __restrict__ mom, const float* __restrict__ radius, int use_hmax,
+    const uint8_t* __restrict__ active, int mode, uint32_t* __restrict__ pr_cnt,
+    uint32_t* __restrict__ pp_tot, unsigned long long* __restrict__ tot,
+    const int64_t* __restrict__ pr_off, int32_t* __restrict__ pr_begin,
+    int32_t* __restrict__ pr_cum, uint8_t* __restrict__ sovf);
 
 #define SPH_THREADS 64
 #define SPH_CAP 2048       // candidates kept in LDS by the density kernel
@@ -122,11 +130,26 @@ __device__ __forceinline__ T slice_sum(T v, int pad) {
     return v;
 }
 
+// First range of a group list that overlaps candidate position ch: the last
+// range whose running offset is <= ch (offsets increase strictly), found by
+// bisection so that expanding one chunk of a long list costs O(log R) plus
+// the ranges the chunk touches.
+__device__ __forceinline__ int64_t first_range(const GroupList& L, int ch) {
+    int64_t lo = L.r0, hi = L.r1 - 1;
+    if (hi < lo) return lo;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (L.cum[mid] <= ch) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 __device__ __forceinline__ void expand_chunk(const GroupList& L, int npp, int ch, int che,
                                              const double4* __restrict__ pos4, double cx,
                                              double cy, double cz, float4* __restrict__ cand,
                                              int tid, int nthreads) {
-    for (int64_t r = L.r0; r < L.r1; r++) {
+    for (int64_t r = first_range(L, ch); r < L.r1; r++) {
         const int c = L.cum[r];
         const int cn = (r + 1 < L.r1) ? L.cum[r + 1] : npp;
         if (cn <= ch) continue;
@@ -532,23 +555,46 @@ int gx_sph_walk(gx_ctx* ctx, TreeSlot& T, ListSet& Ls, int ng, const int32_t* gr
     ListView v{SPH_RANGES, cnt, (const int32_t*)Ls.pr_begin.p, (const int32_t*)Ls.pr_cum.p, ptot,
                nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     int64_t pairs = h[2];
-    if (h[4] > 0) {  // overflowing groups: exact CSR lists from the thread walk
-        hipLaunchKernelGGL(k_walk_sph, dim3(gx_blocks(ng, 128)), dim3(128), 0, st, ng, groups,
-                           recv, (const NodeRec*)T.nodes.p, (const MomRec*)T.mom.p, nn, rad,
-                           use_hmax, ovf, 0, 0, cnt2, ptot2,
-                           (unsigned long long*)(tot + 8), nullptr, nullptr, nullptr);
+    if (h[4] > 0) {
+        // overflowing groups: exact CSR lists from the wave depth-first walk
+        // (count, scan, fill); groups whose walk stack would overflow take
+        // the thread-level walk into the same CSR arrays
+        GX_TRY(gx_reserve(ctx, Ls.aux, ng + 16));
+        uint8_t* sovf = (uint8_t*)Ls.aux.p;
+        const NodeRec* nodes = (const NodeRec*)T.nodes.p;
+        const int32_t* child = (const int32_t*)T.child.p;
+        const MomRec* mom = (const MomRec*)T.mom.p;
+        hipLaunchKernelGGL(k_walk_sph_wave, dim3(xcd_grid(ng)), dim3(64), 0, st, ng, groups, recv,
+                           nodes, child, mom, rad, use_hmax, ovf, 0, cnt2, ptot2,
+                           (unsigned long long*)tot, nullptr, nullptr, nullptr, sovf);
+        GX_LAUNCH_CHECK(ctx);
+        GX_HIP(ctx, hipMemcpyAsync(h, tot, 16 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        GX_HIP(ctx, hipStreamSynchronize(st));
+        const bool deep = h[5] > 0;
+        if (deep) {
+            hipLaunchKernelGGL(k_walk_sph, dim3(gx_blocks(ng, 128)), dim3(128), 0, st, ng, groups,
+                               recv, nodes, mom, nn, rad, use_hmax, sovf, 3, 0, cnt2, ptot2,
+                               (unsigned long long*)(tot + 8), nullptr, nullptr, nullptr);
+            GX_LAUNCH_CHECK(ctx);
+        }
         GX_TRY((gx_scan<uint32_t, int64_t>(ctx, cnt2, (int64_t*)Ls.pr_off.p, ng, tot + 13)));
         GX_HIP(ctx, hipMemcpyAsync(h, tot, 16 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
         GX_HIP(ctx, hipStreamSynchronize(st));
         const int64_t nr = h[13];
         GX_TRY(gx_reserve(ctx, Ls.pc_off, (nr + 1) * sizeof(int32_t)));
         GX_TRY(gx_reserve(ctx, Ls.pc_list, (nr + 1) * sizeof(int32_t)));
-        hipLaunchKernelGGL(k_walk_sph, dim3(gx_blocks(ng, 128)), dim3(128), 0, st, ng, groups,
-                           recv, (const NodeRec*)T.nodes.p, (const MomRec*)T.mom.p, nn, rad,
-                           use_hmax, ovf, 1, 0, nullptr, nullptr,
-                           nullptr, (const int64_t*)Ls.pr_off.p, (int32_t*)Ls.pc_off.p,
-                           (int32_t*)Ls.pc_list.p);
+        hipLaunchKernelGGL(k_walk_sph_wave, dim3(xcd_grid(ng)), dim3(64), 0, st, ng, groups, recv,
+                           nodes, child, mom, rad, use_hmax, ovf, 1, nullptr, nullptr, nullptr,
+                           (const int64_t*)Ls.pr_off.p, (int32_t*)Ls.pc_off.p,
+                           (int32_t*)Ls.pc_list.p, sovf);
         GX_LAUNCH_CHECK(ctx);
+        if (deep) {
+            hipLaunchKernelGGL(k_walk_sph, dim3(gx_blocks(ng, 128)), dim3(128), 0, st, ng, groups,
+                               recv, nodes, mom, nn, rad, use_hmax, sovf, 1, 0, nullptr, nullptr,
+                               nullptr, (const int64_t*)Ls.pr_off.p, (int32_t*)Ls.pc_off.p,
+                               (int32_t*)Ls.pc_list.p);
+            GX_LAUNCH_CHECK(ctx);
+        }
         v.ovf = ovf;
         v.off2 = (const int64_t*)Ls.pr_off.p;
         v.cnt2 = cnt2;

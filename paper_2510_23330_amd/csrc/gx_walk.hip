@@ -32,6 +32,27 @@ __device__ __forceinline__ double box_dist2(const double* glo, const double* ghi
     return s;
 }
 
+// Largest squared distance from a point of box [lo, hi] to box [glo, ghi]
+// (per axis max(0, glo - lo, hi - ghi)), summed in the order of box_dist2.
+// For every box inside [lo, hi] box_dist2 is <= this value in floating point
+// (each operation is monotone), so a node with box_far2 < R^2 holds only
+// leaves the SPH walks would accept one by one: its whole sorted range is
+// emitted at once, giving the same candidate set in fewer, longer ranges.
+__device__ __forceinline__ double box_far2(const double* glo, const double* ghi, const double* lo,
+                                           const double* hi) {
+    double s = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        double t1 = glo[d] - lo[d];
+        double t2 = hi[d] - ghi[d];
+        double t = t1 > t2 ? t1 : t2;
+        t = t < 0.0 ? 0.0 : t;
+        double tt = t * t;
+        s = s + tt;
+    }
+    return s;
+}
+
 // mode 0: count (pc cells, pp ranges, pp particles; interaction totals)
 // mode 1: fill the CSR lists at the offsets produced from the counts
 __global__ __launch_bounds__(128) void k_walk_grav(
@@ -110,7 +131,8 @@ __global__ void k_direct_lists(int ng, int n, const int32_t* __restrict__ groups
 // and hmax_c the largest kernel size in the node (force only).
 // mode 0: count; mode 1: fill at pr_off; mode 2: single pass writing at
 // b * cap with per-block counts (entries past cap are counted, not written,
-// and the block is reported in tot[4]).
+// and the block is reported in tot[4]); mode 3: count like mode 0 but leave
+// the counts of inactive blocks untouched.
 __global__ __launch_bounds__(128) void k_walk_sph(
     int nb, const int32_t* __restrict__ groups, const NodeRec* __restrict__ recv,
     const NodeRec* __restrict__ nodes, const MomRec* __restrict__ mom, int nn,
@@ -122,7 +144,7 @@ __global__ __launch_bounds__(128) void k_walk_sph(
     int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= nb) return;
     if (active && !active[g]) {
-        if (mode != 1) {
+        if (mode == 0 || mode == 2) {
             pr_cnt[g] = 0;
             pp_tot[g] = 0;
         }
@@ -132,7 +154,7 @@ __global__ __launch_bounds__(128) void k_walk_sph(
     const double RG = (double)radius[g];
     int npr = 0, npp = 0, last_end = -1;
     const int64_t pro = (mode == 1) ? pr_off[g] : (mode == 2 ? (int64_t)g * cap : 0);
-    const bool write = mode != 0;
+    const bool write = mode == 1 || mode == 2;
     for (int n = 0; n < nn;) {
         const NodeRec& nd = nodes[n];
         double lo[3] = {nd.lo[0], nd.lo[1], nd.lo[2]};
@@ -145,7 +167,7 @@ __global__ __launch_bounds__(128) void k_walk_sph(
         }
         if (d2 >= R * R) {
             n = nd.next;
-        } else if (nd.leaf) {
+        } else if (nd.leaf || box_far2(G.lo, G.hi, lo, hi) < RG * RG) {
             int b = nd.begin, e = nd.end;
             if (b != last_end) {
                 if (write && (mode == 1 || npr < cap)) {
@@ -226,11 +248,11 @@ __global__ __launch_bounds__(64) void k_walk_sph_bfs(
                     R = hm > R ? hm : R;
                 }
                 inter = d2 < R * R;
-                leaf = nd.leaf;
+                leaf = nd.leaf || (inter && box_far2(G.lo, G.hi, lo, hi) < RG * RG);
                 b = nd.begin;
                 e = nd.end;
             }
-            // emit leaves
+            // emit leaves (and wholly covered nodes)
             const bool emit = inter && leaf;
             const uint64_t em = __ballot(emit);
             const int sz = emit ? e - b : 0;
@@ -279,6 +301,114 @@ __global__ __launch_bounds__(64) void k_walk_sph_bfs(
         } else {
             atomicAdd(&tot[2], (unsigned long long)(G.end - G.begin) * (unsigned long long)npp);
             atomicAdd(&tot[1], (unsigned long long)nout);
+        }
+    }
+}
+
+// Wave-cooperative depth-first walk for the groups whose lists overflow the
+// fixed slots of k_walk_sph_bfs (large kernel sizes: many candidate leaves).
+// One wavefront per group; an LDS stack of pending nodes: each iteration pops
+// up to 64 nodes from the top, one per lane, emits the intersecting leaves
+// and pushes the children of intersecting internal nodes.  Working from the
+// top keeps the stack shallow (it grows with tree depth, not with the
+// frontier width).  mode 0 counts ranges and list length per group; mode 1
+// writes them at pr_off[g] in the same order.  A group whose stack would
+// overflow is flagged in sovf (and counted in tot[5]); the caller walks those
+// with the thread-level walk instead.
+#define WDFS_STACK 8192
+__global__ __launch_bounds__(64) void k_walk_sph_wave(
+    int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ recv,
+    const NodeRec* __restrict__ nodes, const int32_t* __restrict__ child,
+    const MomRec* __restrict__ mom, const float* __restrict__ radius, int use_hmax,
+    const uint8_t* __restrict__ active, int mode, uint32_t* __restrict__ pr_cnt,
+    uint32_t* __restrict__ pp_tot, unsigned long long* __restrict__ tot,
+    const int64_t* __restrict__ pr_off, int32_t* __restrict__ pr_begin,
+    int32_t* __restrict__ pr_cum, uint8_t* __restrict__ sovf) {
+    const int g = xcd_remap(blockIdx.x, ng);
+    if (g >= ng) return;
+    const int lane = threadIdx.x;
+    if (!active[g] || (mode == 1 && sovf[g])) {
+        if (mode == 0 && lane == 0) {
+            pr_cnt[g] = 0;
+            pp_tot[g] = 0;
+            sovf[g] = 0;
+        }
+        return;
+    }
+    __shared__ int32_t stk[WDFS_STACK];
+    const NodeRec G = recv ? recv[g] : nodes[groups[g]];
+    const double RG = (double)radius[g];
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t base_out = (mode == 1) ? pr_off[g] : 0;
+    if (lane == 0) stk[0] = 0;
+    int sp = 1, nout = 0, npp = 0, over = 0;
+    __syncthreads();
+    while (sp > 0 && !over) {
+        const int take = sp < 64 ? sp : 64;
+        const int b0 = sp - take;
+        int n = -1;
+        if (lane < take) n = stk[b0 + lane];
+        __syncthreads();  // every lane has read its node before pushes reuse the slots
+        sp = b0;
+        bool inter = false, leaf = false;
+        int b = 0, e = 0;
+        if (n >= 0) {
+            const NodeRec& nd = nodes[n];
+            double lo[3] = {nd.lo[0], nd.lo[1], nd.lo[2]};
+            double hi[3] = {nd.hi[0], nd.hi[1], nd.hi[2]};
+            const double d2 = box_dist2(G.lo, G.hi, lo, hi);
+            double R = RG;
+            if (use_hmax) {
+                const double hm = (double)mom[n].hmax;
+                R = hm > R ? hm : R;
+            }
+            inter = d2 < R * R;
+            leaf = nd.leaf || (inter && box_far2(G.lo, G.hi, lo, hi) < RG * RG);
+            b = nd.begin;
+            e = nd.end;
+        }
+        const bool emit = inter && leaf;
+        const uint64_t em = __ballot(emit);
+        const int sz = emit ? e - b : 0;
+        const int incl = wave_incl_scan(sz);
+        if (emit && mode == 1) {
+            const int64_t pos = base_out + nout + __popcll(em & lt);
+            pr_begin[pos] = b;
+            pr_cum[pos] = npp + incl - sz;
+        }
+        nout += __popcll(em);
+        npp += __shfl(incl, 63, 64);
+        int nch = 0;
+        int32_t ch[8];
+        if (inter && !leaf) {
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                ch[k] = child[8 * (int64_t)n + k];
+                nch += ch[k] >= 0;
+            }
+        }
+        const int cincl = wave_incl_scan(nch);
+        const int ctot = __shfl(cincl, 63, 64);
+        if (sp + ctot > WDFS_STACK) {
+            over = 1;
+        } else {
+            const int coff = sp + cincl - nch;
+            for (int k = 0; k < nch; k++) stk[coff + k] = ch[k];
+            sp += ctot;
+        }
+        __syncthreads();
+    }
+    if (lane == 0) {
+        if (mode == 0) {
+            sovf[g] = over ? 1 : 0;
+            pr_cnt[g] = over ? 0u : (uint32_t)nout;
+            pp_tot[g] = over ? 0u : (uint32_t)npp;
+            if (over) {
+                atomicAdd(&tot[5], 1ull);
+            } else {
+                atomicAdd(&tot[10], (unsigned long long)(G.end - G.begin) * (unsigned long long)npp);
+                atomicAdd(&tot[9], (unsigned long long)nout);
+            }
         }
     }
 }

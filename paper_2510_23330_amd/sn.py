@@ -149,7 +149,7 @@ class SNBatch:
 
 
 def generate(eng: Engine, seeds, t_end_myr: float = 0.1, log=None, cfg: SPHConfig = SPHConfig(),
-             dt_fixed_myr: float = None, keep=False):
+             dt_fixed_myr: float = None, keep=False, grid: int = GRID):
     """One batch of training pairs: voxel grids just before the explosion and
     t_end after it, from plain small-dt SPH (or fixed steps of dt_fixed_myr).
     Returns (x, y, info) with x, y device float [K * 64^3 * 5] physical
@@ -158,7 +158,7 @@ def generate(eng: Engine, seeds, t_end_myr: float = 0.1, log=None, cfg: SPHConfi
     import ics
     b = ics.sn_batch(seeds)
     sb = SNBatch(eng, b, cfg)
-    x = sb.voxelize()
+    x = sb.voxelize(grid=grid)
     sb.torch.cuda.synchronize()
     t0 = time.perf_counter()
     sb.inject()
@@ -166,7 +166,7 @@ def generate(eng: Engine, seeds, t_end_myr: float = 0.1, log=None, cfg: SPHConfi
                    dt_fixed=None if dt_fixed_myr is None else dt_fixed_myr * MYR)
     sb.torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    y = sb.voxelize()
+    y = sb.voxelize(grid=grid)
     info = {"steps": steps, "seconds": wall, "n_particles": sb.n, "K": sb.K, "noconv": sb.noconv,
             "n_cm3": b["n_cm3"].tolist(), "T": b["T_amb"].tolist()}
     if keep:

@@ -53,11 +53,11 @@ def batches_by_size(seeds, per_batch):
     return [seeds[i:i + per_batch] for i in range(0, len(seeds), per_batch)]
 
 
-def generate_set(eng, seeds, per_batch, log, dt_fixed_myr=None):
+def generate_set(eng, seeds, per_batch, log, dt_fixed_myr=None, grid=GRID):
     """Plain-SPH pairs for `seeds`; returns (X, Y, order, infos) with X, Y
     device float [n, V * 5] in the order `order` (a permutation of seeds)."""
     import torch
-    V5 = GRID ** 3 * 5
+    V5 = grid ** 3 * 5
     n = len(seeds)
     X = torch.empty((n, V5), dtype=torch.float32, device="cuda")
     Y = torch.empty((n, V5), dtype=torch.float32, device="cuda")
@@ -65,7 +65,7 @@ def generate_set(eng, seeds, per_batch, log, dt_fixed_myr=None):
     k = 0
     for bs in batches_by_size(seeds, per_batch):
         try:
-            x, y, info = generate(eng, bs, dt_fixed_myr=dt_fixed_myr, log=log)
+            x, y, info = generate(eng, bs, dt_fixed_myr=dt_fixed_myr, log=log, grid=grid)
         except (FloatingPointError, GxError) as e:
             if dt_fixed_myr is None:
                 raise
@@ -76,7 +76,7 @@ def generate_set(eng, seeds, per_batch, log, dt_fixed_myr=None):
             # a diverged run predicts nothing: count it as the pre-explosion state
             import ics
             sb = SNBatch(eng, ics.sn_batch(bs))
-            x = sb.voxelize()
+            x = sb.voxelize(grid=grid)
             y = torch.full_like(x, float("nan"))
             info["n_particles"] = sb.n
         X[k:k + len(bs)] = x.view(len(bs), V5)
@@ -172,6 +172,7 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--base", type=int, default=32)
     ap.add_argument("--levels", type=int, default=4)
+    ap.add_argument("--grid", type=int, default=GRID)
     ap.add_argument("--epochs", type=int, default=100)
     ap.add_argument("--train-seconds", type=float, default=600)
     ap.add_argument("--lr", type=float, default=1e-4)
@@ -183,20 +184,20 @@ def main(argv=None):
     os.makedirs(a.out, exist_ok=True)
     log = _log_fn(os.path.join(a.out, "log.txt"))
     eng = Engine(0)
-    V = GRID ** 3
+    V = a.grid ** 3
     metrics = {"config": vars(a)}
     train_seeds = list(range(a.seed0, a.seed0 + a.n_train))
     test_seeds = list(range(a.seed0 + a.n_train, a.seed0 + a.n_train + a.n_test))
 
     # 1. data
     t0 = time.perf_counter()
-    Xp, Yp, order, infos = generate_set(eng, train_seeds, a.per_batch, log)
+    Xp, Yp, order, infos = generate_set(eng, train_seeds, a.per_batch, log, grid=a.grid)
     metrics["train_generation_s"] = time.perf_counter() - t0
-    Xtp, Ytp, torder, tinfos = generate_set(eng, test_seeds, a.per_batch, log)
+    Xtp, Ytp, torder, tinfos = generate_set(eng, test_seeds, a.per_batch, log, grid=a.grid)
     metrics["test_plain_sph"] = tinfos
 
     # 2. statistics and standardized copies
-    sur = Surrogate(eng, batch=a.batch, base=a.base, levels=a.levels, seed=1)
+    sur = Surrogate(eng, batch=a.batch, base=a.base, levels=a.levels, grid=a.grid, seed=1)
     if a.init:
         sur.load(a.init)
     else:
@@ -228,7 +229,7 @@ def main(argv=None):
     steps = hist[-1]["steps"] if hist else 0
     metrics["training"] = {"history": hist, "seconds": ttrain, "steps": steps,
                            "samples_per_s": steps * a.batch / max(ttrain, 1e-9),
-                           "tflops_est": 3 * flops_forward(GRID, a.base, a.levels) * steps * a.batch
+                           "tflops_est": 3 * flops_forward(a.grid, a.base, a.levels) * steps * a.batch
                            / max(ttrain, 1e-9) / 1e12}
     sur.save(os.path.join(a.out, "surrogate.npz"))
 
@@ -238,7 +239,15 @@ def main(argv=None):
     sur.infer(Xts.view(-1), n_t, pred)
     metrics["surrogate_vs_sph"] = summarize(pred, Ytp)
     metrics["persistence_vs_sph"] = summarize(Xtp, Ytp)
-    _, Yc, _, cinfos = generate_set(eng, test_seeds, a.per_batch, log, dt_fixed_myr=DT_GLOBAL_MYR)
+    # the same comparison in the standardized target channels the loss uses
+    pers = torch.empty_like(Xtp)
+    sur.standardize(Xtp.view(-1), "out", out_f32=pers.view(-1))
+    metrics["mse_standardized"] = {
+        "surrogate": evaluate_mse(sur, Xts, Yts),
+        "persistence": sur.eng.mse(pers.view(-1), 5, Yts.reshape(-1), 5, n_t * V)}
+    del pers
+    _, Yc, _, cinfos = generate_set(eng, test_seeds, a.per_batch, log, dt_fixed_myr=DT_GLOBAL_MYR,
+                                    grid=a.grid)
     metrics["coarse_dt_sph_vs_sph"] = summarize(Yc, Ytp)
     metrics["coarse_dt_sph"] = cinfos
     del Yc
@@ -250,7 +259,7 @@ def main(argv=None):
     k = 0
     for bs in batches_by_size(test_seeds, a.per_batch):
         sb = SNBatch(eng, ics.sn_batch(bs), cfg)
-        sb.voxelize()                       # kernel sizes of the pre-explosion state
+        sb.voxelize(grid=a.grid)            # kernel sizes of the pre-explosion state
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         off, idx, new, _ = sur.regions(sb.p, sb.g, sb.centers, cap=sb.n)
@@ -264,7 +273,8 @@ def main(argv=None):
         eng.tree_build(q, GX_TREE_GAS, cfg.n_leaf, cfg.n_group)
         eng.sph_density(q, g, cfg.n_ngb, cfg.gamma, cfg.h_tol, cfg.max_iter)
         vox = torch.zeros(len(bs) * V * 5, dtype=torch.float32, device="cuda")
-        eng.sn_voxelize(q, g.u, g.H, sb.centers, SIDE, GRID, 1.0 / U_PER_K, sb.ambient(), out_f32=vox)
+        eng.sn_voxelize(q, g.u, g.H, sb.centers, SIDE, a.grid, 1.0 / U_PER_K, sb.ambient(),
+                        out_f32=vox)
         rt.append((vox, k, len(bs)))
         k += len(bs)
     # truth rows follow the same size-sorted order as generate_set produced
@@ -275,7 +285,7 @@ def main(argv=None):
                          "speedup": plain_s / max(sur_s, 1e-12),
                          "plain_sph_s_per_64": plain_s / nreg * 64,
                          "surrogate_s_per_64": sur_s / nreg * 64}
-    log(json.dumps({k: metrics[k] for k in ("surrogate_vs_sph", "persistence_vs_sph",
+    log(json.dumps({k: metrics[k] for k in ("mse_standardized", "surrogate_vs_sph", "persistence_vs_sph",
                                              "coarse_dt_sph_vs_sph", "replaced_particles_vs_sph",
                                              "timing")}))
     with open(os.path.join(a.out, "metrics.json"), "w") as f:
