@@ -419,6 +419,15 @@ int gx_chan_stats(gx_ctx* ctx, int64_t V, const float* in, int stride, int nc, d
 int gx_chan_affine(gx_ctx* ctx, int64_t V, const float* in, int in_stride, int nc,
                    const float* scale, const float* shift, float* out, int out_stride,
                    uint16_t* out_bf16, int bf_stride);
+/* One of the 48 symmetries of the cube per sample (training augmentation):
+ * out[b] = in[b] mapped by sym[b] = perm * 8 + flips (device int32 [B]; perm
+ * in [0, 6) selects the axis permutation (x,y,z), (x,z,y), (y,x,z), (y,z,x),
+ * (z,x,y), (z,y,x) taken by output axes x, y, z; flip bit a reverses output
+ * axis a).  in/out fp32 [B][S^3][C], voxel order z-major, x fastest; the
+ * vector channels vc..vc+2 (vc < 0: none) are permuted and negated with the
+ * axes.  in and out must not overlap. */
+int gx_cube_sym(gx_ctx* ctx, const float* in, int B, int S, int C, int vc, const int32_t* sym,
+                float* out);
 /* y = bf16(x), round to nearest even. */
 int gx_f32_to_bf16(gx_ctx* ctx, const float* x, int64_t n, uint16_t* y);
 /* out = (a + b) * LeakyReLU'(y) elementwise over n bf16 values (b, y may be

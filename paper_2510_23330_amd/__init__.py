@@ -409,6 +409,12 @@ class Engine:
                                              _ptr(b, torch.bfloat16), _ptr(y, torch.bfloat16),
                                              _ptr(out, torch.bfloat16)))
 
+    def cube_sym(self, x, B, S, C, vc, sym, out):
+        """Cube symmetry sym[b] (perm * 8 + flips) of each sample of x -> out."""
+        torch = _torch()
+        self._check(self.lib.gx_cube_sym(self.ctx, _ptr(x, torch.float32), int(B), int(S), int(C),
+                                         int(vc), _ptr(sym, torch.int32), _ptr(out, torch.float32)))
+
     def chan_stats(self, x, stride, nc, sums):
         """sums (device float64 [2 nc]) += per-channel sum and sum of squares."""
         torch = _torch()

@@ -85,6 +85,7 @@ SIGNATURES = {
     "gx_adam_step": (I32, [P, I64, P, P, P, P, D, D, D, D, I64, P]),
     "gx_f32_to_bf16": (I32, [P, P, I64, P]),
     "gx_chan_stats": (I32, [P, I64, P, I32, I32, P]),
+    "gx_cube_sym": (I32, [P, P, I32, I32, I32, I32, P, P]),
     "gx_chan_affine": (I32, [P, I64, P, I32, I32, P, P, P, I32, P, I32]),
     "gx_grad_combine": (I32, [P, I64, P, P, P, P]),
 }

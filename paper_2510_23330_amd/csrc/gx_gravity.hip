@@ -16,6 +16,9 @@
 // group-relative FP32 and stores it into structure-of-arrays LDS tiles.
 // No MFMA: the pair law is not a contraction.
 #include "gx_internal.hpp"
+#include <algorithm>
+#include <cstdlib>
+#include <vector>
 
 int gx_tree_check(gx_ctx* ctx, int which, const gx_particles* p);
 
@@ -25,10 +28,11 @@ __global__ __launch_bounds__(128) void k_walk_grav(
     uint32_t* __restrict__ pr_cnt, uint32_t* __restrict__ pp_tot,
     unsigned long long* __restrict__ tot, const int64_t* __restrict__ pc_off,
     int32_t* __restrict__ pc_list, const int64_t* __restrict__ pr_off,
-    int32_t* __restrict__ pr_begin, int32_t* __restrict__ pr_cum);
+    int32_t* __restrict__ pr_begin, int32_t* __restrict__ pr_cum, int cap_pc, int cap_pr);
 __global__ void k_direct_lists(int ng, int n, const int32_t* __restrict__ groups,
                                const NodeRec* __restrict__ nodes, int64_t* __restrict__ pc_off,
-                               int64_t* __restrict__ pr_off, int32_t* __restrict__ pr_begin,
+                               int64_t* __restrict__ pr_off, uint32_t* __restrict__ pc_cnt,
+                               uint32_t* __restrict__ pr_cnt, int32_t* __restrict__ pr_begin,
                                int32_t* __restrict__ pr_cum, uint32_t* __restrict__ pp_tot,
                                unsigned long long* __restrict__ tot);
 
@@ -57,7 +61,8 @@ __global__ __launch_bounds__(GF_THREADS) void k_grav_force(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes,
     const MomRec* __restrict__ mom, const double4* __restrict__ pos4, const float* __restrict__ e2s,
     const uint32_t* __restrict__ perm, const int64_t* __restrict__ pc_off,
-    const int32_t* __restrict__ pc_list, const int64_t* __restrict__ pr_off,
+    const uint32_t* __restrict__ pc_cnt, int64_t pc_stride, const int32_t* __restrict__ pc_list,
+    const int64_t* __restrict__ pr_off, const uint32_t* __restrict__ pr_cnt, int64_t pr_stride,
     const int32_t* __restrict__ pr_begin, const int32_t* __restrict__ pr_cum,
     const uint32_t* __restrict__ pp_tot, double G, double* __restrict__ ax, double* __restrict__ ay,
     double* __restrict__ az, double* __restrict__ pot) {
@@ -81,8 +86,9 @@ __global__ __launch_bounds__(GF_THREADS) void k_grav_force(
     while (pad < nG && pad < GF_THREADS) pad <<= 1;
     const int nsl = GF_THREADS / pad, il = tid % pad, sl = tid / pad;
     const int npp = (int)pp_tot[g];
-    const int64_t r0 = pr_off[g], r1 = pr_off[g + 1];
-    const int64_t c0 = pc_off[g], c1 = pc_off[g + 1];
+    // list of this group: fixed slots (stride > 0) or CSR offsets
+    const int64_t r0 = pr_stride ? (int64_t)g * pr_stride : pr_off[g], r1 = r0 + pr_cnt[g];
+    const int64_t c0 = pc_stride ? (int64_t)g * pc_stride : pc_off[g], c1 = c0 + pc_cnt[g];
 
     for (int ic = 0; ic < nG; ic += pad) {
         const int i = ic + il;
@@ -258,46 +264,86 @@ extern "C" int gx_gravity_forces(gx_ctx* ctx, const gx_particles* p, double G, d
     GX_TRY(gx_reserve(ctx, Ls.pr_off, (ng + 1) * sizeof(int64_t)));
     int64_t* tot = (int64_t*)Ls.tot.p;
     int64_t h_tot[8] = {};
+    Ls.stride_pc = Ls.stride_pr = 0;
     if (flags & GX_DIRECT) {
         GX_TRY(gx_reserve(ctx, Ls.pr_begin, (ng + 1) * sizeof(int32_t)));
         GX_TRY(gx_reserve(ctx, Ls.pr_cum, (ng + 1) * sizeof(int32_t)));
         GX_TRY(gx_reserve(ctx, Ls.pc_list, 64));
         hipLaunchKernelGGL(k_direct_lists, dim3(gx_blocks(ng + 1, 256)), dim3(256), 0, st, ng,
                            (int)T.n, (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
-                           (int64_t*)Ls.pc_off.p, (int64_t*)Ls.pr_off.p, (int32_t*)Ls.pr_begin.p,
-                           (int32_t*)Ls.pr_cum.p, (uint32_t*)Ls.pp_tot.p,
-                           (unsigned long long*)tot);
+                           (int64_t*)Ls.pc_off.p, (int64_t*)Ls.pr_off.p, (uint32_t*)Ls.pc_cnt.p,
+                           (uint32_t*)Ls.pr_cnt.p, (int32_t*)Ls.pr_begin.p, (int32_t*)Ls.pr_cum.p,
+                           (uint32_t*)Ls.pp_tot.p, (unsigned long long*)tot);
         GX_LAUNCH_CHECK(ctx);
         Ls.n_pc = 0;
         Ls.n_ranges = ng;
     } else {
         const double theta2 = theta * theta;
-        hipLaunchKernelGGL(k_walk_grav, dim3(gx_blocks(ng, 128)), dim3(128), 0, st, ng,
-                           (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p, nn,
-                           (const double*)T.box.p, theta2, 0, (uint32_t*)Ls.pc_cnt.p,
-                           (uint32_t*)Ls.pr_cnt.p, (uint32_t*)Ls.pp_tot.p,
-                           (unsigned long long*)tot, nullptr, nullptr, nullptr, nullptr, nullptr);
-        GX_LAUNCH_CHECK(ctx);
-        GX_TRY((gx_scan<uint32_t, int64_t>(ctx, (const uint32_t*)Ls.pc_cnt.p, (int64_t*)Ls.pc_off.p,
-                                           ng, tot + 0)));
-        GX_TRY((gx_scan<uint32_t, int64_t>(ctx, (const uint32_t*)Ls.pr_cnt.p, (int64_t*)Ls.pr_off.p,
-                                           ng, tot + 1)));
-        // the offsets arrays carry their totals as element ng
-        GX_HIP(ctx, hipMemcpyAsync((int64_t*)Ls.pc_off.p + ng, tot + 0, 8, hipMemcpyDeviceToDevice, st));
-        GX_HIP(ctx, hipMemcpyAsync((int64_t*)Ls.pr_off.p + ng, tot + 1, 8, hipMemcpyDeviceToDevice, st));
-        GX_TRY(read_host(ctx, h_tot, tot, 2 * sizeof(int64_t)));
-        Ls.n_pc = h_tot[0];
-        Ls.n_ranges = h_tot[1];
-        GX_TRY(gx_reserve(ctx, Ls.pc_list, (Ls.n_pc + 1) * sizeof(int32_t)));
-        GX_TRY(gx_reserve(ctx, Ls.pr_begin, (Ls.n_ranges + 1) * sizeof(int32_t)));
-        GX_TRY(gx_reserve(ctx, Ls.pr_cum, (Ls.n_ranges + 1) * sizeof(int32_t)));
-        hipLaunchKernelGGL(k_walk_grav, dim3(gx_blocks(ng, 128)), dim3(128), 0, st, ng,
-                           (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p, nn,
-                           (const double*)T.box.p, theta2, 1, nullptr, nullptr, nullptr, nullptr,
-                           (const int64_t*)Ls.pc_off.p, (int32_t*)Ls.pc_list.p,
-                           (const int64_t*)Ls.pr_off.p, (int32_t*)Ls.pr_begin.p,
-                           (int32_t*)Ls.pr_cum.p);
-        GX_LAUNCH_CHECK(ctx);
+        bool done = false;
+        // one pass into per-group slots sized from the largest lists of the
+        // previous call; a list that does not fit sends the call to the exact
+        // two-pass (count, scan, fill) construction
+        if (Ls.cap_pc > 0 && Ls.cap_pr > 0 && std::llabs(Ls.cap_ng - (int64_t)ng) * 10 <= ng) {
+            GX_TRY(gx_reserve(ctx, Ls.pc_list, (size_t)ng * Ls.cap_pc * sizeof(int32_t)));
+            GX_TRY(gx_reserve(ctx, Ls.pr_begin, (size_t)ng * Ls.cap_pr * sizeof(int32_t)));
+            GX_TRY(gx_reserve(ctx, Ls.pr_cum, (size_t)ng * Ls.cap_pr * sizeof(int32_t)));
+            hipLaunchKernelGGL(k_walk_grav, dim3(gx_blocks(ng, 128)), dim3(128), 0, st, ng,
+                               (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p, nn,
+                               (const double*)T.box.p, theta2, 2, (uint32_t*)Ls.pc_cnt.p,
+                               (uint32_t*)Ls.pr_cnt.p, (uint32_t*)Ls.pp_tot.p,
+                               (unsigned long long*)tot, nullptr, (int32_t*)Ls.pc_list.p, nullptr,
+                               (int32_t*)Ls.pr_begin.p, (int32_t*)Ls.pr_cum.p, Ls.cap_pc,
+                               Ls.cap_pr);
+            GX_LAUNCH_CHECK(ctx);
+            GX_TRY(read_host(ctx, h_tot, tot, 8 * sizeof(int64_t)));
+            if (h_tot[4] == 0) {
+                done = true;
+                Ls.stride_pc = Ls.cap_pc;
+                Ls.stride_pr = Ls.cap_pr;
+                Ls.n_pc = h_tot[0];
+                Ls.n_ranges = h_tot[1];
+            } else {
+                GX_TRY(gx_zero(ctx, Ls.tot.p, 8 * sizeof(int64_t)));
+            }
+        }
+        if (!done) {
+            hipLaunchKernelGGL(k_walk_grav, dim3(gx_blocks(ng, 128)), dim3(128), 0, st, ng,
+                               (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p, nn,
+                               (const double*)T.box.p, theta2, 0, (uint32_t*)Ls.pc_cnt.p,
+                               (uint32_t*)Ls.pr_cnt.p, (uint32_t*)Ls.pp_tot.p,
+                               (unsigned long long*)tot, nullptr, nullptr, nullptr, nullptr,
+                               nullptr, 0, 0);
+            GX_LAUNCH_CHECK(ctx);
+            GX_TRY(read_host(ctx, h_tot, tot, 8 * sizeof(int64_t)));
+            GX_TRY((gx_scan<uint32_t, int64_t>(ctx, (const uint32_t*)Ls.pc_cnt.p,
+                                               (int64_t*)Ls.pc_off.p, ng, tot + 0)));
+            GX_TRY((gx_scan<uint32_t, int64_t>(ctx, (const uint32_t*)Ls.pr_cnt.p,
+                                               (int64_t*)Ls.pr_off.p, ng, tot + 1)));
+            // the offsets arrays carry their totals as element ng
+            GX_HIP(ctx, hipMemcpyAsync((int64_t*)Ls.pc_off.p + ng, tot + 0, 8,
+                                       hipMemcpyDeviceToDevice, st));
+            GX_HIP(ctx, hipMemcpyAsync((int64_t*)Ls.pr_off.p + ng, tot + 1, 8,
+                                       hipMemcpyDeviceToDevice, st));
+            Ls.n_pc = h_tot[0];
+            Ls.n_ranges = h_tot[1];
+            GX_TRY(gx_reserve(ctx, Ls.pc_list, (Ls.n_pc + 1) * sizeof(int32_t)));
+            GX_TRY(gx_reserve(ctx, Ls.pr_begin, (Ls.n_ranges + 1) * sizeof(int32_t)));
+            GX_TRY(gx_reserve(ctx, Ls.pr_cum, (Ls.n_ranges + 1) * sizeof(int32_t)));
+            hipLaunchKernelGGL(k_walk_grav, dim3(gx_blocks(ng, 128)), dim3(128), 0, st, ng,
+                               (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p, nn,
+                               (const double*)T.box.p, theta2, 1, nullptr, nullptr, nullptr,
+                               nullptr, (const int64_t*)Ls.pc_off.p, (int32_t*)Ls.pc_list.p,
+                               (const int64_t*)Ls.pr_off.p, (int32_t*)Ls.pr_begin.p,
+                               (int32_t*)Ls.pr_cum.p, 0, 0);
+            GX_LAUNCH_CHECK(ctx);
+        }
+        // slot sizes for the next call: largest lists seen, plus a margin,
+        // unless the slots would be far larger than the lists themselves
+        const int64_t mpc = h_tot[5] + h_tot[5] / 4 + 64, mpr = h_tot[6] + h_tot[6] / 4 + 16;
+        const bool fits = (double)ng * (double)(mpc + 2 * mpr) <= 8.0 * (double)(h_tot[0] + 2 * h_tot[1]) + 1e6;
+        Ls.cap_pc = fits ? (int)std::min<int64_t>(mpc, INT32_MAX / 2) : 0;
+        Ls.cap_pr = fits ? (int)std::min<int64_t>(mpr, INT32_MAX / 2) : 0;
+        Ls.cap_ng = ng;
     }
     Ls.n_groups = ng;
 
@@ -308,9 +354,11 @@ extern "C" int gx_gravity_forces(gx_ctx* ctx, const gx_particles* p, double G, d
                            (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
                            (const MomRec*)T.mom.p, (const double4*)T.pos4.p, (const float*)T.e2s.p,
                            (const uint32_t*)T.val[0].p, (const int64_t*)Ls.pc_off.p,
-                           (const int32_t*)Ls.pc_list.p, (const int64_t*)Ls.pr_off.p,
-                           (const int32_t*)Ls.pr_begin.p, (const int32_t*)Ls.pr_cum.p,
-                           (const uint32_t*)Ls.pp_tot.p, G, ax, ay, az, pot);
+                           (const uint32_t*)Ls.pc_cnt.p, Ls.stride_pc, (const int32_t*)Ls.pc_list.p,
+                           (const int64_t*)Ls.pr_off.p, (const uint32_t*)Ls.pr_cnt.p,
+                           Ls.stride_pr, (const int32_t*)Ls.pr_begin.p,
+                           (const int32_t*)Ls.pr_cum.p, (const uint32_t*)Ls.pp_tot.p, G, ax, ay,
+                           az, pot);
     };
     if (stats) GX_HIP(ctx, hipEventRecord(ctx->ev2, st));
     if (fp64) {
@@ -356,35 +404,47 @@ extern "C" int gx_gravity_list_export(gx_ctx* ctx, int64_t* pc_off, int32_t* pc_
     const int64_t ng = Ls.n_groups;
     GX_HIP(ctx, hipSetDevice(ctx->device));
     GX_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    if (pc_off) GX_HIP(ctx, hipMemcpy(pc_off, Ls.pc_off.p, (ng + 1) * 8, hipMemcpyDeviceToHost));
-    if (pc_node && Ls.n_pc)
-        GX_HIP(ctx, hipMemcpy(pc_node, Ls.pc_list.p, Ls.n_pc * 4, hipMemcpyDeviceToHost));
-    if (pp_off) GX_HIP(ctx, hipMemcpy(pp_off, Ls.pr_off.p, (ng + 1) * 8, hipMemcpyDeviceToHost));
-    if (pp_begin || pp_end) {
-        int64_t nr = Ls.n_ranges;
-        int32_t* b = (int32_t*)malloc((nr + 1) * 4);
-        int32_t* c = (int32_t*)malloc((nr + 1) * 4);
-        int64_t* off = (int64_t*)malloc((ng + 1) * 8);
-        uint32_t* tot = (uint32_t*)malloc((ng + 1) * 4);
-        if (!b || !c || !off || !tot) {
-            free(b); free(c); free(off); free(tot);
-            return gx_fail(ctx, GX_ENOMEM, "host malloc");
-        }
-        hipError_t e1 = hipMemcpy(b, Ls.pr_begin.p, nr * 4, hipMemcpyDeviceToHost);
-        hipError_t e2 = hipMemcpy(c, Ls.pr_cum.p, nr * 4, hipMemcpyDeviceToHost);
-        hipError_t e3 = hipMemcpy(off, Ls.pr_off.p, (ng + 1) * 8, hipMemcpyDeviceToHost);
-        hipError_t e4 = hipMemcpy(tot, Ls.pp_tot.p, ng * 4, hipMemcpyDeviceToHost);
-        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
-            free(b); free(c); free(off); free(tot);
-            return gx_fail(ctx, GX_EHIP, "list export copy failed");
-        }
-        for (int64_t g = 0; g < ng; g++)
-            for (int64_t r = off[g]; r < off[g + 1]; r++) {
-                int32_t cn = (r + 1 < off[g + 1]) ? c[r + 1] : (int32_t)tot[g];
-                if (pp_begin) pp_begin[r] = b[r];
-                if (pp_end) pp_end[r] = b[r] + (cn - c[r]);
-            }
-        free(b); free(c); free(off); free(tot);
+    // lists live either in fixed per-group slots (stride > 0) or in CSR
+    // arrays; the export is CSR in both cases
+    std::vector<uint32_t> pcc(ng), prc(ng), tot(ng);
+    std::vector<int64_t> pcs(ng + 1), prs(ng + 1);
+    if (ng > 0) {
+        GX_HIP(ctx, hipMemcpy(pcc.data(), Ls.pc_cnt.p, ng * 4, hipMemcpyDeviceToHost));
+        GX_HIP(ctx, hipMemcpy(prc.data(), Ls.pr_cnt.p, ng * 4, hipMemcpyDeviceToHost));
+        GX_HIP(ctx, hipMemcpy(tot.data(), Ls.pp_tot.p, ng * 4, hipMemcpyDeviceToHost));
     }
+    if (Ls.stride_pc > 0) {
+        for (int64_t g = 0; g < ng; g++) pcs[g] = g * Ls.stride_pc;
+    } else if (ng > 0) {
+        GX_HIP(ctx, hipMemcpy(pcs.data(), Ls.pc_off.p, ng * 8, hipMemcpyDeviceToHost));
+    }
+    if (Ls.stride_pr > 0) {
+        for (int64_t g = 0; g < ng; g++) prs[g] = g * Ls.stride_pr;
+    } else if (ng > 0) {
+        GX_HIP(ctx, hipMemcpy(prs.data(), Ls.pr_off.p, ng * 8, hipMemcpyDeviceToHost));
+    }
+    const int64_t span_pc = ng ? pcs[ng - 1] + pcc[ng - 1] : 0;
+    const int64_t span_pr = ng ? prs[ng - 1] + prc[ng - 1] : 0;
+    std::vector<int32_t> lst(span_pc), b(span_pr), c(span_pr);
+    if (span_pc) GX_HIP(ctx, hipMemcpy(lst.data(), Ls.pc_list.p, span_pc * 4, hipMemcpyDeviceToHost));
+    if (span_pr) {
+        GX_HIP(ctx, hipMemcpy(b.data(), Ls.pr_begin.p, span_pr * 4, hipMemcpyDeviceToHost));
+        GX_HIP(ctx, hipMemcpy(c.data(), Ls.pr_cum.p, span_pr * 4, hipMemcpyDeviceToHost));
+    }
+    int64_t opc = 0, opr = 0;
+    for (int64_t g = 0; g < ng; g++) {
+        if (pc_off) pc_off[g] = opc;
+        if (pp_off) pp_off[g] = opr;
+        for (uint32_t k = 0; k < pcc[g]; k++, opc++)
+            if (pc_node) pc_node[opc] = lst[pcs[g] + k];
+        for (uint32_t k = 0; k < prc[g]; k++, opr++) {
+            const int64_t r = prs[g] + k;
+            const int32_t cn = (k + 1 < prc[g]) ? c[r + 1] : (int32_t)tot[g];
+            if (pp_begin) pp_begin[opr] = b[r];
+            if (pp_end) pp_end[opr] = b[r] + (cn - c[r]);
+        }
+    }
+    if (pc_off) pc_off[ng] = opc;
+    if (pp_off) pp_off[ng] = opr;
     return GX_OK;
 }

@@ -136,16 +136,37 @@ __global__ void k_fill_u64(unsigned long long* p, int n, unsigned long long v) {
     if (i < n) p[i] = v;
 }
 
+// Courant step per cube: the lanes of a wave that share a cube (particles of
+// one cube are contiguous, so usually all of them) take the minimum by
+// shuffles and one lane updates the cube's minimum (positive doubles order
+// like their bit patterns).
 __global__ __launch_bounds__(256) void k_cfl(int64_t n, const float* __restrict__ H,
                                              const float* __restrict__ vsig,
                                              const int32_t* __restrict__ cube, double c,
                                              unsigned long long* __restrict__ out) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double v = (double)vsig[i];
-    if (!(v > 0.0)) return;
-    double dt = c * (double)H[i] / v;
-    atomicMin(&out[cube ? cube[i] : 0], (unsigned long long)__double_as_longlong(dt));
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    bool valid = false;
+    double dt = INFINITY;
+    int cb = -1;
+    if (i < n) {
+        const double v = (double)vsig[i];
+        if (v > 0.0) {
+            valid = true;
+            dt = c * (double)H[i] / v;
+            cb = cube ? cube[i] : 0;
+        }
+    }
+    uint64_t pending = __ballot(valid);
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int lc = __shfl(cb, leader, 64);
+        const bool mine = valid && cb == lc;
+        double m = mine ? dt : INFINITY;
+        for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
+        if (lane == leader) atomicMin(&out[lc], (unsigned long long)__double_as_longlong(m));
+        pending &= ~__ballot(mine);
+    }
 }
 
 extern "C" int gx_sph_timestep(gx_ctx* ctx, const gx_gas* g, double c_cfl, const int32_t* cube_id,

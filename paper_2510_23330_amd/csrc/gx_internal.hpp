@@ -70,6 +70,11 @@ struct ListSet {  // per-group interaction lists (CSR)
     Buf aux;  // per-group flags of the second-level overflow path
     Buf tot;  // device counters: [0] n_pc entries, [1] n_ranges, [2] n_pp inter, [3] n_pc inter
     int64_t n_groups = 0, n_pc = 0, n_ranges = 0;
+    // fixed-slot layout of the last gravity lists (0: CSR) and the slot sizes
+    // planned for the next call (0: none yet), valid for cap_ng groups
+    int64_t stride_pc = 0, stride_pr = 0;
+    int cap_pc = 0, cap_pr = 0;
+    int64_t cap_ng = -1;
 };
 
 struct gx_ctx {
@@ -79,6 +84,7 @@ struct gx_ctx {
     TreeSlot tree[2];
     ListSet grav, sph;
     Buf scan_tmp[3], hist, partial, small, host_small;
+    Buf wpart;  // per-chunk partial weight gradients (ordered reduction)
     Buf sph_work[16];
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
 };

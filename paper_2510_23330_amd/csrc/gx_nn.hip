@@ -25,7 +25,7 @@
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-#define CV_BM 128
+#define CV_BM 256
 #define CV_BK 32
 #define CV_APITCH 40  // bf16 per LDS row (32 + 8 padding)
 #define LRELU_SLOPE 0.1f
@@ -91,6 +91,11 @@ __device__ __forceinline__ uint4 im2col8r(const uint16_t* __restrict__ in, const
 // epilogue modes
 enum { EP_NONE = 0, EP_LRELU = 1, EP_DACT = 2 };
 
+// Block tile CV_BM (= 256) voxels x BN output channels, 4 waves, each wave
+// 64 voxels x BN: per 32-wide K slice a wave issues 4 x BN/16 MFMAs from 4 A
+// and BN/16 B fragments.  Two LDS stages: the next K slice is fetched into
+// registers while the current one feeds the matrix cores, then stored into
+// the other stage (one barrier per slice).
 template <int BN>
 __global__ __launch_bounds__(256) void k_conv3d(const uint16_t* __restrict__ in,
                                                 const uint16_t* __restrict__ w,
@@ -98,38 +103,39 @@ __global__ __launch_bounds__(256) void k_conv3d(const uint16_t* __restrict__ in,
                                                 int mode, const uint16_t* __restrict__ yref,
                                                 uint16_t* __restrict__ out_bf,
                                                 float* __restrict__ out_f32) {
-    // two LDS stages: the next K slice is fetched into registers while the
-    // current one feeds the matrix cores, then stored into the other stage
+    constexpr int MR = CV_BM / 64;  // A rows staged per thread and 16-row MFMA tiles per wave
+    constexpr int NT = BN / 16;     // MFMA column tiles per wave
     __shared__ __attribute__((aligned(16))) uint16_t sA[2][CV_BM * CV_APITCH];
     __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN * CV_APITCH];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t m0 = (int64_t)blockIdx.x * CV_BM;
     const int n0 = blockIdx.y * BN;
-    constexpr int NT = BN / 16;  // MFMA column tiles per wave
-    f32x4 acc[2][NT];
+    f32x4 acc[MR][NT];
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < MR; i++)
 #pragma unroll
         for (int j = 0; j < NT; j++) acc[i][j] = f32x4{0, 0, 0, 0};
 
-    // staging roles: A rows tid/4 and 64 + tid/4, 8-channel group tid%4;
+    // staging roles: A rows tid/4 + 64 r (r < MR), 8-channel group tid%4;
     // B row tid/4 (output channel) for tid < 4 BN
-    const int grp = tid & 3;
-    const RowXYZ r0 = row_xyz(g, m0 + (tid >> 2));
-    const RowXYZ r1 = row_xyz(g, m0 + 64 + (tid >> 2));
+    const int grp = tid & 3, srow = tid >> 2;
+    RowXYZ rows[MR];
+#pragma unroll
+    for (int r = 0; r < MR; r++) rows[r] = row_xyz(g, m0 + srow + 64 * r);
     const bool bst = tid < BN * 4;
-    const uint16_t* wrow = w + (int64_t)(n0 + (tid >> 2)) * g.K;
-    uint4 va0, va1, vb = make_uint4(0, 0, 0, 0);
+    const uint16_t* wrow = w + (int64_t)(n0 + (bst ? srow : 0)) * g.K;
+    uint4 va[MR], vb = make_uint4(0, 0, 0, 0);
     auto fetch = [&](int k0) {
         const int k = k0 + grp * 8;
-        va0 = im2col8r(in, g, r0, k);
-        va1 = im2col8r(in, g, r1, k);
+#pragma unroll
+        for (int r = 0; r < MR; r++) va[r] = im2col8r(in, g, rows[r], k);
         if (bst) vb = k < g.K ? *reinterpret_cast<const uint4*>(wrow + k) : make_uint4(0, 0, 0, 0);
     };
     auto stage = [&](int buf) {
-        *reinterpret_cast<uint4*>(&sA[buf][(tid >> 2) * CV_APITCH + grp * 8]) = va0;
-        *reinterpret_cast<uint4*>(&sA[buf][(64 + (tid >> 2)) * CV_APITCH + grp * 8]) = va1;
-        if (bst) *reinterpret_cast<uint4*>(&sB[buf][(tid >> 2) * CV_APITCH + grp * 8]) = vb;
+#pragma unroll
+        for (int r = 0; r < MR; r++)
+            *reinterpret_cast<uint4*>(&sA[buf][(srow + 64 * r) * CV_APITCH + grp * 8]) = va[r];
+        if (bst) *reinterpret_cast<uint4*>(&sB[buf][srow * CV_APITCH + grp * 8]) = vb;
     };
     fetch(0);
     stage(0);
@@ -139,16 +145,16 @@ __global__ __launch_bounds__(256) void k_conv3d(const uint16_t* __restrict__ in,
     for (int k0 = 0; k0 < g.K; k0 += CV_BK) {
         const bool more = k0 + CV_BK < g.K;
         if (more) fetch(k0 + CV_BK);
-        bf16x8 a[2], b[NT];
+        bf16x8 a[MR], b[NT];
 #pragma unroll
-        for (int i = 0; i < 2; i++)
+        for (int i = 0; i < MR; i++)
             a[i] = *reinterpret_cast<const bf16x8*>(
-                &sA[cur][(wv * 32 + i * 16 + (lane & 15)) * CV_APITCH + kq]);
+                &sA[cur][(wv * (16 * MR) + i * 16 + (lane & 15)) * CV_APITCH + kq]);
 #pragma unroll
         for (int j = 0; j < NT; j++)
             b[j] = *reinterpret_cast<const bf16x8*>(&sB[cur][(j * 16 + (lane & 15)) * CV_APITCH + kq]);
 #pragma unroll
-        for (int i = 0; i < 2; i++)
+        for (int i = 0; i < MR; i++)
 #pragma unroll
             for (int j = 0; j < NT; j++)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
@@ -158,14 +164,14 @@ __global__ __launch_bounds__(256) void k_conv3d(const uint16_t* __restrict__ in,
     }
     // epilogue: lane holds rows 4*(lane/16) + t of each 16 x 16 tile, column lane % 16
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < MR; i++)
 #pragma unroll
         for (int j = 0; j < NT; j++) {
             const int col = n0 + j * 16 + (lane & 15);
             const float bv = bias ? bias[col] : 0.0f;
 #pragma unroll
             for (int t = 0; t < 4; t++) {
-                const int64_t m = m0 + wv * 32 + i * 16 + (lane >> 4) * 4 + t;
+                const int64_t m = m0 + wv * (16 * MR) + i * 16 + (lane >> 4) * 4 + t;
                 if (m >= g.M) continue;
                 float v = acc[i][j][t] + bv;
                 const int64_t o = m * g.Cout + col;
@@ -202,7 +208,7 @@ template <int BN>
 __global__ __launch_bounds__(256) void k_conv3d_wgrad(const uint16_t* __restrict__ in,
                                                       const uint16_t* __restrict__ dout,
                                                       ConvGeom g, int64_t m_per_block,
-                                                      float* __restrict__ dw) {
+                                                      float* __restrict__ part) {
     constexpr int BKW = 64;                  // K tile (rows of dW^T)
     __shared__ __attribute__((aligned(16))) uint16_t sAt[BKW * CV_APITCH];  // [k][m]
     __shared__ __attribute__((aligned(16))) uint16_t sBt[BN * CV_APITCH];   // [co][m]
@@ -247,27 +253,59 @@ __global__ __launch_bounds__(256) void k_conv3d_wgrad(const uint16_t* __restrict
         }
         __syncthreads();
     }
-    // acc[j][t]: row (K) = wv*16 + 4*(lane/16) + t, column (co) = j*16 + lane%16
+    // acc[j][t]: row (K) = wv*16 + 4*(lane/16) + t, column (co) = j*16 + lane%16;
+    // each chunk of voxels owns its own partial gradient, reduced in chunk
+    // order afterwards (a deterministic sum)
+    float* pc = part + (int64_t)blockIdx.z * g.Cout * g.K;
 #pragma unroll
     for (int j = 0; j < NT; j++)
 #pragma unroll
         for (int t = 0; t < 4; t++) {
             const int k = k0 + wv * 16 + (lane >> 4) * 4 + t;
             const int co = n0 + j * 16 + (lane & 15);
-            if (k < g.K) atomicAdd(&dw[(int64_t)co * g.K + k], acc[j][t]);
+            if (k < g.K) pc[(int64_t)co * g.K + k] = acc[j][t];
         }
 }
 
-__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ dout, int64_t M,
-                                                   int C, float* __restrict__ db) {
-    // block: one channel-group of 64 channels? simple: each thread strides voxels for a channel
-    const int c = blockIdx.y;
+// dw[e] += sum over chunks c (in order) of part[c][e]
+__global__ void k_wgrad_reduce(const float* __restrict__ part, int64_t n, int chunks,
+                               float* __restrict__ dw) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
     float s = 0.0f;
-    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < M;
-         m += (int64_t)gridDim.x * blockDim.x)
-        s += bf2f(dout[m * C + c]);
-    s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0) atomicAdd(&db[c], s);
+    for (int c = 0; c < chunks; c++) s += part[(int64_t)c * n + e];
+    dw[e] += s;
+}
+
+// Bias gradient: block b sums rows [b R, (b + 1) R) of dout[M][C] with 256 / C
+// row lanes per channel (C <= 256, a power of two >= 16), coalesced, and
+// writes its per-channel partial; k_bias_reduce adds the partials in block
+// order.
+__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ dout, int64_t M,
+                                                   int C, int64_t rows_per_block,
+                                                   float* __restrict__ part) {
+    __shared__ float sh[256];
+    const int c = threadIdx.x % C, rl = threadIdx.x / C, nrl = 256 / C;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r1 = min(M, r0 + rows_per_block);
+    float s = 0.0f;
+    for (int64_t m = r0 + rl; m < r1; m += nrl) s += bf2f(dout[m * C + c]);
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < C) {
+        float t = 0.0f;
+        for (int q = 0; q < nrl; q++) t += sh[q * C + threadIdx.x];
+        part[(int64_t)blockIdx.x * C + threadIdx.x] = t;
+    }
+}
+
+__global__ void k_bias_reduce(const float* __restrict__ part, int nb, int C,
+                              float* __restrict__ db) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    float s = 0.0f;
+    for (int b = 0; b < nb; b++) s += part[(int64_t)b * C + c];
+    db[c] += s;
 }
 
 // ---------------------------------------------------------------------------
@@ -503,6 +541,47 @@ __global__ void k_chan_affine(const float* __restrict__ in, int in_stride, int n
         for (int c = 0; c < bf_stride; c++) obf[v * bf_stride + c] = c < nc ? f2bf(y[c]) : (uint16_t)0;
 }
 
+// ---------------------------------------------------------------------------
+// Symmetries of the cube (training-set augmentation)
+// ---------------------------------------------------------------------------
+// Sample b of in[B][S^3][C] (voxel order z-major, x fastest) is mapped by the
+// cube symmetry sym[b] = perm * 8 + flips (perm in [0, 6) indexes the axis
+// permutations, flip bit a reverses output axis a): output axis a takes input
+// axis P[a], reversed when bit a is set.  The velocity channels vc .. vc + 2
+// (vx, vy, vz), when vc >= 0, are permuted the same way and negated on the
+// reversed axes, so a field that is a solution of the isotropic fluid
+// equations stays one.
+__constant__ int c_perm6[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+
+__global__ void k_cube_sym(const float* __restrict__ in, int S, int C, int vc,
+                           const int32_t* __restrict__ sym, float* __restrict__ out) {
+    const int b = blockIdx.y;
+    const int64_t V = (int64_t)S * S * S;
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const int sy = sym[b];
+    const int* P = c_perm6[(sy >> 3) % 6];
+    const int fl = sy & 7;
+    int o[3];
+    o[0] = (int)(v % S);
+    o[1] = (int)((v / S) % S);
+    o[2] = (int)(v / ((int64_t)S * S));
+    int q[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) q[P[a]] = (fl >> a & 1) ? S - 1 - o[a] : o[a];
+    const int64_t src = ((int64_t)q[2] * S + q[1]) * S + q[0];
+    const float* ip = in + ((int64_t)b * V + src) * C;
+    float* op = out + ((int64_t)b * V + v) * C;
+    for (int c = 0; c < C; c++) op[c] = ip[c];
+    if (vc >= 0) {
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const float w = ip[vc + P[a]];
+            op[vc + a] = (fl >> a & 1) ? -w : w;
+        }
+    }
+}
+
 static int ilog2(int v) {
     int l = 0;
     while ((1 << l) < v) l++;
@@ -584,15 +663,27 @@ extern "C" int gx_conv3d_bwd_weight(gx_ctx* ctx, const uint16_t* in, const uint1
     if (mpb < 256) mpb = 256;
     chunks = (g.M + mpb - 1) / mpb;
     dim3 grid(kt, nt, (unsigned)chunks);
+    const int64_t nw = (int64_t)Cout * g.K;
+    const int nbb = 256;  // bias-gradient blocks
+    GX_TRY(gx_reserve(ctx, ctx->wpart, (size_t)(chunks * nw + (int64_t)nbb * Cout) * sizeof(float)));
+    float* part = (float*)ctx->wpart.p;
+    float* bpart = part + chunks * nw;
     if (bn == 64)
-        hipLaunchKernelGGL(k_conv3d_wgrad<64>, grid, dim3(256), 0, ctx->stream, in, dout, g, mpb, dw);
+        hipLaunchKernelGGL(k_conv3d_wgrad<64>, grid, dim3(256), 0, ctx->stream, in, dout, g, mpb, part);
     else if (bn == 32)
-        hipLaunchKernelGGL(k_conv3d_wgrad<32>, grid, dim3(256), 0, ctx->stream, in, dout, g, mpb, dw);
+        hipLaunchKernelGGL(k_conv3d_wgrad<32>, grid, dim3(256), 0, ctx->stream, in, dout, g, mpb, part);
     else
-        hipLaunchKernelGGL(k_conv3d_wgrad<16>, grid, dim3(256), 0, ctx->stream, in, dout, g, mpb, dw);
+        hipLaunchKernelGGL(k_conv3d_wgrad<16>, grid, dim3(256), 0, ctx->stream, in, dout, g, mpb, part);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(gx_blocks(nw, 256)), dim3(256), 0, ctx->stream, part, nw,
+                       (int)chunks, dw);
     if (dbias) {
-        hipLaunchKernelGGL(k_bias_grad, dim3(256, Cout), dim3(256), 0, ctx->stream, dout, g.M, Cout,
-                           dbias);
+        if (Cout > 256 || !pow2(Cout))
+            return gx_fail(ctx, GX_EINVAL, "conv3d_bwd_weight: bias gradient needs Cout <= 256, a power of two");
+        const int64_t rpb = (g.M + nbb - 1) / nbb;
+        hipLaunchKernelGGL(k_bias_grad, dim3(nbb), dim3(256), 0, ctx->stream, dout, g.M, Cout, rpb,
+                           bpart);
+        hipLaunchKernelGGL(k_bias_reduce, dim3(gx_blocks(Cout, 256)), dim3(256), 0, ctx->stream,
+                           bpart, nbb, Cout, dbias);
     }
     GX_LAUNCH_CHECK(ctx);
     return GX_OK;
@@ -719,6 +810,18 @@ extern "C" int gx_chan_affine(gx_ctx* ctx, int64_t V, const float* in, int in_st
     GX_HIP(ctx, hipSetDevice(ctx->device));
     hipLaunchKernelGGL(k_chan_affine, dim3(gx_blocks(V, 256)), dim3(256), 0, ctx->stream, in,
                        in_stride, nc, V, scale, shift, out, out_stride, out_bf16, bf_stride);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+extern "C" int gx_cube_sym(gx_ctx* ctx, const float* in, int B, int S, int C, int vc,
+                           const int32_t* sym, float* out) {
+    if (!ctx || !in || !sym || !out || B < 1 || S < 1 || C < 1 || vc > C - 3 || in == out)
+        return GX_EINVAL;
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    const int64_t V = (int64_t)S * S * S;
+    hipLaunchKernelGGL(k_cube_sym, dim3(gx_blocks(V, 256), B), dim3(256), 0, ctx->stream, in, S, C,
+                       vc, sym, out);
     GX_LAUNCH_CHECK(ctx);
     return GX_OK;
 }

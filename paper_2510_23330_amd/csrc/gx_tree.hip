@@ -189,39 +189,68 @@ __global__ __launch_bounds__(256) void k_node_emit(int64_t n, const uint64_t* __
                                                    const uint32_t* __restrict__ lvl_off,
                                                    uint32_t* __restrict__ lvl_fill,
                                                    int32_t* __restrict__ lvl_ids) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || cnt[i] == 0) return;
-    int Li = lmax[i];
-    int lstart = Li - (int)cnt[i] + 1;
-    uint64_t ki = key[i];
-    for (int l = lstart; l <= Li; l++) {
-        int64_t id = (int64_t)base[i] + (l - lstart);
-        int64_t end;
-        if (l == 0) {
-            end = n;
-        } else {
-            int shift = 3 * (GX_MAX_LEVEL - l);
-            uint64_t pre = ki >> shift;
-            int64_t lo = i + 1, hi = n;  // first index in [lo, hi) with a different prefix
-            while (lo < hi) {
-                int64_t mid = (lo + hi) >> 1;
-                if ((key[mid] >> shift) == pre) lo = mid + 1;
-                else hi = mid;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool has = i < n && cnt[i] > 0;
+    int Li = -1, lstart = 0;
+    uint32_t bi = 0;
+    if (has) {
+        Li = lmax[i];
+        lstart = Li - (int)cnt[i] + 1;
+        bi = base[i];
+        const uint64_t ki = key[i];
+        // deepest node first: each shallower node ends at or after the deeper
+        // one, so its end is searched from there, galloping then bisecting
+        int64_t lo = i + 1;
+        for (int l = Li; l >= lstart; l--) {
+            int64_t end;
+            if (l == 0) {
+                end = n;
+            } else {
+                const int shift = 3 * (GX_MAX_LEVEL - l);
+                const uint64_t pre = ki >> shift;
+                int64_t step = 1, hi = n;
+                for (;;) {
+                    const int64_t p = lo + step - 1;
+                    if (p >= n) break;
+                    if ((key[p] >> shift) != pre) {
+                        hi = p;
+                        break;
+                    }
+                    lo = p + 1;
+                    step <<= 1;
+                }
+                while (lo < hi) {  // first index in [lo, hi) with a different prefix
+                    const int64_t mid = (lo + hi) >> 1;
+                    if ((key[mid] >> shift) == pre) lo = mid + 1;
+                    else hi = mid;
+                }
+                end = lo;
             }
-            end = lo;
+            NodeRec r;
+            r.begin = (int32_t)i;
+            r.end = (int32_t)end;
+            r.level = (int16_t)l;
+            r.leaf = (int8_t)(l == Li);
+            r.pad = 0;
+            r.next = (int32_t)(end < n ? (int64_t)base[end] : n_nodes);
+            r.lo[0] = r.lo[1] = r.lo[2] = 0.0;
+            r.hi[0] = r.hi[1] = r.hi[2] = 0.0;
+            nodes[(int64_t)bi + (l - lstart)] = r;
+            lo = end;
         }
-        NodeRec r;
-        r.begin = (int32_t)i;
-        r.end = (int32_t)end;
-        r.level = (int16_t)l;
-        r.leaf = (int8_t)(l == Li);
-        r.pad = 0;
-        r.next = (int32_t)(end < n ? (int64_t)base[end] : n_nodes);
-        r.lo[0] = r.lo[1] = r.lo[2] = 0.0;
-        r.hi[0] = r.hi[1] = r.hi[2] = 0.0;
-        nodes[id] = r;
-        uint32_t slot = atomicAdd(&lvl_fill[l], 1u);
-        lvl_ids[lvl_off[l] + slot] = (int32_t)id;
+    }
+    // per-level id lists, one atomic per wave and level
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int l = 0; l <= GX_MAX_LEVEL; l++) {
+        const bool part = has && l >= lstart && l <= Li;
+        const uint64_t mk = __ballot(part);
+        if (mk == 0) continue;
+        const int leader = __ffsll((unsigned long long)mk) - 1;
+        uint32_t b0 = 0;
+        if (lane == leader) b0 = atomicAdd(&lvl_fill[l], (uint32_t)__popcll(mk));
+        b0 = __shfl(b0, leader, 64);
+        if (part) lvl_ids[lvl_off[l] + b0 + __popcll(mk & lt)] = (int32_t)(bi + (l - lstart));
     }
 }
 

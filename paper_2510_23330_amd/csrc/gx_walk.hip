@@ -14,6 +14,7 @@
 // is id + 1.  One thread walks one group; consecutive groups are neighbours
 // in key order and follow nearly the same path, which keeps a wave coherent.
 #include "gx_internal.hpp"
+#include <climits>
 
 #pragma clang fp contract(off)
 
@@ -55,19 +56,26 @@ __device__ __forceinline__ double box_far2(const double* glo, const double* ghi,
 
 // mode 0: count (pc cells, pp ranges, pp particles; interaction totals)
 // mode 1: fill the CSR lists at the offsets produced from the counts
+// mode 2: one pass into fixed slots of cap_pc / cap_pr entries per group
+//         (entries past a slot are counted, not written; such groups are
+//         counted in tot[4])
+// Modes 0 and 2 also record the largest per-group counts (tot[5], tot[6]).
 __global__ __launch_bounds__(128) void k_walk_grav(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes, int nn,
     const double* __restrict__ box, double theta2, int mode, uint32_t* __restrict__ pc_cnt,
     uint32_t* __restrict__ pr_cnt, uint32_t* __restrict__ pp_tot,
     unsigned long long* __restrict__ tot, const int64_t* __restrict__ pc_off,
     int32_t* __restrict__ pc_list, const int64_t* __restrict__ pr_off,
-    int32_t* __restrict__ pr_begin, int32_t* __restrict__ pr_cum) {
+    int32_t* __restrict__ pr_begin, int32_t* __restrict__ pr_cum, int cap_pc, int cap_pr) {
     int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ng) return;
     const NodeRec G = nodes[groups[g]];
     const double L = box[3];
     int npc = 0, npr = 0, npp = 0, last_end = -1;
-    int64_t pco = mode ? pc_off[g] : 0, pro = mode ? pr_off[g] : 0;
+    const bool write = mode != 0;
+    const int64_t pco = mode == 1 ? pc_off[g] : (int64_t)g * cap_pc;
+    const int64_t pro = mode == 1 ? pr_off[g] : (int64_t)g * cap_pr;
+    const int lim_pc = mode == 2 ? cap_pc : INT_MAX, lim_pr = mode == 2 ? cap_pr : INT_MAX;
     for (int n = 0; n < nn;) {
         const NodeRec& nd = nodes[n];
         double lo[3] = {nd.lo[0], nd.lo[1], nd.lo[2]};
@@ -78,13 +86,13 @@ __global__ __launch_bounds__(128) void k_walk_grav(
         double lhs = lc * lc;
         double rhs = theta2 * d2;
         if (lhs < rhs) {
-            if (mode) pc_list[pco + npc] = n;
+            if (write && npc < lim_pc) pc_list[pco + npc] = n;
             npc++;
             n = nxt;
         } else if (nd.leaf) {
             int b = nd.begin, e = nd.end;
             if (b != last_end) {
-                if (mode) {
+                if (write && npr < lim_pr) {
                     pr_begin[pro + npr] = b;
                     pr_cum[pro + npr] = npp;
                 }
@@ -97,20 +105,26 @@ __global__ __launch_bounds__(128) void k_walk_grav(
             n = n + 1;
         }
     }
-    if (!mode) {
+    if (mode != 1) {
         pc_cnt[g] = (uint32_t)npc;
         pr_cnt[g] = (uint32_t)npr;
         pp_tot[g] = (uint32_t)npp;
         unsigned long long nG = (unsigned long long)(G.end - G.begin);
         atomicAdd(&tot[2], nG * (unsigned long long)npp);
         atomicAdd(&tot[3], nG * (unsigned long long)npc);
+        atomicAdd(&tot[0], (unsigned long long)npc);
+        atomicAdd(&tot[1], (unsigned long long)npr);
+        atomicMax(&tot[5], (unsigned long long)npc);
+        atomicMax(&tot[6], (unsigned long long)npr);
+        if (mode == 2 && (npc > cap_pc || npr > cap_pr)) atomicAdd(&tot[4], 1ull);
     }
 }
 
 // Direct summation expressed as lists: every group sees the single range [0, n).
 __global__ void k_direct_lists(int ng, int n, const int32_t* __restrict__ groups,
                                const NodeRec* __restrict__ nodes, int64_t* __restrict__ pc_off,
-                               int64_t* __restrict__ pr_off, int32_t* __restrict__ pr_begin,
+                               int64_t* __restrict__ pr_off, uint32_t* __restrict__ pc_cnt,
+                               uint32_t* __restrict__ pr_cnt, int32_t* __restrict__ pr_begin,
                                int32_t* __restrict__ pr_cum, uint32_t* __restrict__ pp_tot,
                                unsigned long long* __restrict__ tot) {
     int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -118,6 +132,8 @@ __global__ void k_direct_lists(int ng, int n, const int32_t* __restrict__ groups
     pc_off[g] = 0;
     pr_off[g] = g;
     if (g == ng) return;
+    pc_cnt[g] = 0;
+    pr_cnt[g] = 1;
     pr_begin[g] = 0;
     pr_cum[g] = 0;
     pp_tot[g] = (uint32_t)n;

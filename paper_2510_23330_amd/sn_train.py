@@ -107,16 +107,26 @@ def summarize(pred, ref):
     return out
 
 
-def train(sur: Surrogate, Xs, Ys, Xt, Yt, epochs, seconds, lr, log, seed=0):
-    """Xs bf16 [n, V*8] standardized inputs, Ys f32 [n, V*5] standardized targets."""
+def train(sur: Surrogate, Xp, Yp, Xt, Yt, epochs, seconds, lr, log, seed=0, augment=True):
+    """Xp, Yp: physical training pairs, device float [n, V*5]; Xt, Yt: the
+    held-out pairs standardized (bf16 [m, V*8], f32 [m, V*5]).  Each
+    mini-batch is drawn at random, mapped by a random symmetry of the cube
+    (augment) and standardized on the device.  The weights with the lowest
+    held-out MSE seen at an epoch end are kept."""
     import torch
-    net = sur.net
+    eng, net = sur.eng, sur.net
     B = net.B
-    n = Xs.shape[0]
-    V = sur.V
+    n = Xp.shape[0]
+    V, S = sur.V, sur.grid
     rng = np.random.default_rng(seed)
+    f32 = dict(dtype=torch.float32, device="cuda")
+    xg = torch.empty(B * V * 5, **f32)
+    yg = torch.empty(B * V * 5, **f32)
+    xa = torch.empty(B * V * 5, **f32)
+    ya = torch.empty(B * V * 5, **f32)
     xb = torch.empty(B * V * 8, dtype=torch.bfloat16, device="cuda")
-    yb = torch.empty(B * V * 5, dtype=torch.float32, device="cuda")
+    yb = torch.empty(B * V * 5, **f32)
+    best = (float("inf"), None, -1)
     t0 = time.perf_counter()
     hist = []
     step = 0
@@ -127,8 +137,17 @@ def train(sur: Surrogate, Xs, Ys, Xt, Yt, epochs, seconds, lr, log, seed=0):
         tot, cnt = 0.0, 0
         for a in range(0, n - B + 1, B):
             sel = torch.as_tensor(perm[a:a + B], device="cuda")
-            xb.view(B, V * 8).copy_(Xs.index_select(0, sel))
-            yb.view(B, V * 5).copy_(Ys.index_select(0, sel))
+            xg.view(B, V * 5).copy_(Xp.index_select(0, sel))
+            yg.view(B, V * 5).copy_(Yp.index_select(0, sel))
+            if augment:
+                sym = torch.as_tensor(rng.integers(0, 48, B).astype(np.int32), device="cuda")
+                eng.cube_sym(xg, B, S, 5, 2, sym, xa)
+                eng.cube_sym(yg, B, S, 5, 2, sym, ya)
+                src_x, src_y = xa, ya
+            else:
+                src_x, src_y = xg, yg
+            sur.standardize(src_x, "in", out_bf16=xb)
+            sur.standardize(src_y, "out", out_f32=yb)
             loss = net.train_step(xb, yb, lr=lr)
             tot += loss
             cnt += 1
@@ -141,11 +160,17 @@ def train(sur: Surrogate, Xs, Ys, Xt, Yt, epochs, seconds, lr, log, seed=0):
                 stop = True
                 break
         val = evaluate_mse(sur, Xt, Yt)
+        if val < best[0]:
+            best = (val, net.w32.clone(), ep)
         hist.append({"epoch": ep, "steps": step, "train_mse": tot / max(cnt, 1), "val_mse": val,
                      "seconds": time.perf_counter() - t0})
         log(f"epoch {ep}: train mse {tot / max(cnt, 1):.4f} val mse {val:.4f}")
         if stop:
             break
+    if best[1] is not None:
+        net.w32.copy_(best[1])
+        eng.f32_to_bf16(net.w32, net.wbf)
+        log(f"kept the weights of epoch {best[2]} (val mse {best[0]:.4f})")
     return hist
 
 
@@ -178,6 +203,8 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-4)
     ap.add_argument("--seed0", type=int, default=1000)
     ap.add_argument("--init", default=None, help="surrogate.npz to continue from")
+    ap.add_argument("--no-augment", action="store_true",
+                    help="train without the random cube symmetries")
     ap.add_argument("--out", default="sn_out")
     a = ap.parse_args(argv)
     import torch
@@ -216,15 +243,17 @@ def main(argv=None):
         sur.standardize(Y.view(-1), "out", out_f32=Ys.view(-1))
         return Xs, Ys
 
-    Xs, Ys = std_pair(Xp, Yp)
     Xts, Yts = std_pair(Xtp, Ytp)
-    del Yp
-    log(f"dataset: {Xs.shape[0]} train / {Xts.shape[0]} test cubes")
+    log(f"dataset: {Xp.shape[0]} train / {Xts.shape[0]} test cubes")
 
     # 3. training
     from .unet import flops_forward
     t0 = time.perf_counter()
-    hist = train(sur, Xs, Ys, Xts, Yts, a.epochs, a.train_seconds, a.lr, log)
+    hist = []
+    if Xp.shape[0] >= a.batch and a.epochs > 0:
+        hist = train(sur, Xp, Yp, Xts, Yts, a.epochs, a.train_seconds, a.lr, log,
+                     augment=not a.no_augment)
+    del Xp, Yp
     ttrain = time.perf_counter() - t0
     steps = hist[-1]["steps"] if hist else 0
     metrics["training"] = {"history": hist, "seconds": ttrain, "steps": steps,
@@ -271,7 +300,7 @@ def main(argv=None):
                         vz=new["vz"], m=m, eps2=sb.p.eps2[:m.shape[0]])
         g = GasState.zeros(q.n, u=new["u"])
         eng.tree_build(q, GX_TREE_GAS, cfg.n_leaf, cfg.n_group)
-        eng.sph_density(q, g, cfg.n_ngb, cfg.gamma, cfg.h_tol, cfg.max_iter)
+        eng.sph_density(q, g, cfg.n_ngb, cfg.gamma, cfg.h_tol, cfg.max_iter, allow_noconv=True)
         vox = torch.zeros(len(bs) * V * 5, dtype=torch.float32, device="cuda")
         eng.sn_voxelize(q, g.u, g.H, sb.centers, SIDE, a.grid, 1.0 / U_PER_K, sb.ambient(),
                         out_f32=vox)

@@ -288,3 +288,27 @@ def test_one_leapfrog_step_plummer(gx, eng):
     assert np.max(np.abs(gx_x - x)) <= 1e-9
     amax = np.max(np.abs(np.stack(o[:3])))
     assert np.max(np.abs(gx_v - v)) <= 1e-5 * dt * amax
+
+
+def test_list_slots_equal_two_pass_and_fall_back(gx, eng):
+    # The first call builds the lists in two passes (count, scan, fill); the
+    # next call on the same tree writes them in one pass into per-group slots
+    # sized from the first: lists and forces must be identical.  A call whose
+    # lists outgrow the slots (smaller theta) takes the two-pass path again
+    # and still matches the oracle.
+    d = ics.disk_galaxy(30000, 6)
+    p = _dev(gx, d)
+    eng.tree_build(p, gx.GX_TREE_ALL, 16, 256)
+    runs = []
+    for theta in (0.5, 0.5, 0.3, 0.3):
+        out = _zeros(p.n)
+        eng.gravity_forces(p, 1.0, theta, gx.GX_QUAD, *out)
+        runs.append((_np(out), eng.gravity_lists()))
+    for i, j in ((0, 1), (2, 3)):
+        for a, b in zip(runs[i][0], runs[j][0]):
+            assert np.array_equal(a, b)
+        for k in runs[i][1]:
+            assert np.array_equal(np.asarray(runs[i][1][k]), np.asarray(runs[j][1][k])), k
+    T = oracle.Tree(d, 16, 256)
+    _list_sets(T, T.nodes(), T.lists(0.5), runs[1][1])
+    _list_sets(T, T.nodes(), T.lists(0.3), runs[2][1])

@@ -229,8 +229,10 @@ def test_training_trajectory_matches_oracle(gx, eng):
 def test_unet_loss_decreases(gx, eng):
     # Training by the project's own kernels on a fixed pair of samples.  An
     # independent FP32 PyTorch CPU run of the same network, initialisation,
-    # data and optimiser reaches 0.26x the initial loss after 150 steps; the
-    # BF16 path must do at least as well within a margin.
+    # data and optimiser (Adam, lr 1e-3) reaches 0.20x the initial loss after
+    # 150 steps; the BF16 path must reach 0.3x.  (The weight-gradient sums
+    # use atomics, so runs differ in rounding; at lr 3e-3 some runs leave the
+    # stable regime.)
     import torch
     from paper_2510_23330_amd.unet import UNet
     S, B = 16, 2
@@ -241,6 +243,57 @@ def test_unet_loss_decreases(gx, eng):
     tgt = np.tanh(x[..., :5] * 0.7 + 0.3 * np.roll(x[..., :5], 1, axis=1)).astype(np.float32)
     xt = _bf(x)
     tt = torch.as_tensor(tgt.ravel(), device="cuda")
-    losses = [net.train_step(xt, tt, lr=3e-3) for _ in range(150)]
+    losses = [net.train_step(xt, tt, lr=1e-3) for _ in range(150)]
+    print("loss", np.round(losses[::10], 4))
     assert losses[-1] < 0.3 * losses[0]
     assert losses[-1] < min(losses[:100])
+
+
+def test_cube_symmetries(gx, eng):
+    # The 48 symmetries of the cube used to augment training pairs: a scalar
+    # field that depends only on the distance to the centre and the radial
+    # velocity field (an explosion) are invariant under every one; a field
+    # equal to the input x coordinate and a uniform x velocity land on the
+    # axis that the permutation sends x to, reversed by its flip; two equal
+    # flips cancel.
+    import torch
+    S, C = 6, 5
+    c = (S - 1) / 2.0
+    z, y, x = np.meshgrid(*(np.arange(S, dtype=np.float64),) * 3, indexing="ij")
+    rad = np.zeros((S, S, S, C), np.float32)
+    rad[..., 0] = np.sqrt((x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2)
+    rad[..., 1] = 1.0
+    rad[..., 2], rad[..., 3], rad[..., 4] = x - c, y - c, z - c
+    lin = np.zeros((S, S, S, C), np.float32)
+    lin[..., 0] = x
+    lin[..., 2] = 1.0
+    syms = np.arange(48, dtype=np.int32)
+    B = syms.size
+    for field, invariant in ((rad, True), (lin, False)):
+        inp = torch.as_tensor(np.broadcast_to(field, (B,) + field.shape).copy().ravel(), device="cuda")
+        out = torch.empty_like(inp)
+        eng.cube_sym(inp, B, S, C, 2, torch.as_tensor(syms, device="cuda"), out)
+        o = out.cpu().numpy().reshape(B, S, S, S, C)
+        perms = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+        for sidx in range(B):
+            if invariant:
+                assert np.array_equal(o[sidx], field), sidx
+                continue
+            P, fl = perms[sidx >> 3], sidx & 7
+            a = P.index(0)                       # output axis that carries input x
+            coord = (x, y, z)[a]
+            exp = (S - 1 - coord) if (fl >> a) & 1 else coord
+            assert np.array_equal(o[sidx][..., 0], exp.astype(np.float32)), sidx
+            v = np.zeros(3)
+            v[a] = -1.0 if (fl >> a) & 1 else 1.0
+            for k in range(3):
+                assert np.all(o[sidx][..., 2 + k] == v[k]), (sidx, k)
+    # flips only: applying the same element twice is the identity
+    rng = np.random.default_rng(0)
+    f = rng.normal(size=(8, S, S, S, C)).astype(np.float32)
+    t = torch.as_tensor(f.ravel(), device="cuda")
+    sym = torch.arange(8, dtype=torch.int32, device="cuda")
+    once, twice = torch.empty_like(t), torch.empty_like(t)
+    eng.cube_sym(t, 8, S, C, 2, sym, once)
+    eng.cube_sym(once, 8, S, C, 2, sym, twice)
+    assert torch.equal(twice, t)
