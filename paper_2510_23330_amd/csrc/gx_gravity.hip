@@ -29,6 +29,12 @@ __global__ __launch_bounds__(128) void k_walk_grav(
     unsigned long long* __restrict__ tot, const int64_t* __restrict__ pc_off,
     int32_t* __restrict__ pc_list, const int64_t* __restrict__ pr_off,
     int32_t* __restrict__ pr_begin, int32_t* __restrict__ pr_cum, int cap_pc, int cap_pr);
+__global__ __launch_bounds__(64) void k_walk_grav_wave(
+    int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes,
+    const int32_t* __restrict__ child, const double* __restrict__ box, double theta2,
+    uint32_t* __restrict__ pc_cnt, uint32_t* __restrict__ pr_cnt, uint32_t* __restrict__ pp_tot,
+    unsigned long long* __restrict__ tot, int32_t* __restrict__ pc_list,
+    int32_t* __restrict__ pr_begin, int32_t* __restrict__ pr_cum, int cap_pc, int cap_pr);
 __global__ void k_direct_lists(int ng, int n, const int32_t* __restrict__ groups,
                                const NodeRec* __restrict__ nodes, int64_t* __restrict__ pc_off,
                                int64_t* __restrict__ pr_off, uint32_t* __restrict__ pc_cnt,
@@ -280,6 +286,7 @@ extern "C" int gx_gravity_forces(gx_ctx* ctx, const gx_particles* p, double G, d
     } else {
         const double theta2 = theta * theta;
         bool done = false;
+        int64_t seen_pc = 0, seen_pr = 0;  // largest per-group list sizes seen in this call
         // one pass into per-group slots sized from the largest lists of the
         // previous call; a list that does not fit sends the call to the exact
         // two-pass (count, scan, fill) construction
@@ -287,15 +294,17 @@ extern "C" int gx_gravity_forces(gx_ctx* ctx, const gx_particles* p, double G, d
             GX_TRY(gx_reserve(ctx, Ls.pc_list, (size_t)ng * Ls.cap_pc * sizeof(int32_t)));
             GX_TRY(gx_reserve(ctx, Ls.pr_begin, (size_t)ng * Ls.cap_pr * sizeof(int32_t)));
             GX_TRY(gx_reserve(ctx, Ls.pr_cum, (size_t)ng * Ls.cap_pr * sizeof(int32_t)));
-            hipLaunchKernelGGL(k_walk_grav, dim3(gx_blocks(ng, 128)), dim3(128), 0, st, ng,
-                               (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p, nn,
-                               (const double*)T.box.p, theta2, 2, (uint32_t*)Ls.pc_cnt.p,
-                               (uint32_t*)Ls.pr_cnt.p, (uint32_t*)Ls.pp_tot.p,
-                               (unsigned long long*)tot, nullptr, (int32_t*)Ls.pc_list.p, nullptr,
-                               (int32_t*)Ls.pr_begin.p, (int32_t*)Ls.pr_cum.p, Ls.cap_pc,
-                               Ls.cap_pr);
+            hipLaunchKernelGGL(k_walk_grav_wave, dim3(xcd_grid(ng)), dim3(64), 0, st, ng,
+                               (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
+                               (const int32_t*)T.child.p, (const double*)T.box.p, theta2,
+                               (uint32_t*)Ls.pc_cnt.p, (uint32_t*)Ls.pr_cnt.p,
+                               (uint32_t*)Ls.pp_tot.p, (unsigned long long*)tot,
+                               (int32_t*)Ls.pc_list.p, (int32_t*)Ls.pr_begin.p,
+                               (int32_t*)Ls.pr_cum.p, Ls.cap_pc, Ls.cap_pr);
             GX_LAUNCH_CHECK(ctx);
             GX_TRY(read_host(ctx, h_tot, tot, 8 * sizeof(int64_t)));
+            seen_pc = h_tot[5];
+            seen_pr = h_tot[6];
             if (h_tot[4] == 0) {
                 done = true;
                 Ls.stride_pc = Ls.cap_pc;
@@ -339,7 +348,11 @@ extern "C" int gx_gravity_forces(gx_ctx* ctx, const gx_particles* p, double G, d
         }
         // slot sizes for the next call: largest lists seen, plus a margin,
         // unless the slots would be far larger than the lists themselves
-        const int64_t mpc = h_tot[5] + h_tot[5] / 4 + 64, mpr = h_tot[6] + h_tot[6] / 4 + 16;
+        // (the one-pass walk does not merge contiguous leaves, so its range
+        // counts can exceed the two-pass ones: keep the larger)
+        seen_pc = std::max<int64_t>(seen_pc, h_tot[5]);
+        seen_pr = std::max<int64_t>(seen_pr, h_tot[6]);
+        const int64_t mpc = seen_pc + seen_pc / 4 + 64, mpr = seen_pr + seen_pr / 4 + 16;
         const bool fits = (double)ng * (double)(mpc + 2 * mpr) <= 8.0 * (double)(h_tot[0] + 2 * h_tot[1]) + 1e6;
         Ls.cap_pc = fits ? (int)std::min<int64_t>(mpc, INT32_MAX / 2) : 0;
         Ls.cap_pr = fits ? (int)std::min<int64_t>(mpr, INT32_MAX / 2) : 0;

@@ -45,47 +45,52 @@ struct ConvGeom {
     int lgC;    // log2(Cin): the GEMM's K channel count is a power of two
 };
 
-// Voxel coordinates of implicit-GEMM row m (one decomposition per row, reused
-// for every K slice).
-struct RowXYZ {
+// Implicit-GEMM row m: its voxel index and a 27-bit mask of the taps whose
+// neighbour lies inside the volume (bit (dz+1)*9 + (dy+1)*3 + (dx+1); bit 0
+// alone for 1^3 kernels; 0 for rows past M).  Decomposed once per row.
+struct RowTap {
     int64_t m;
-    int x, y, z;
-    bool ok;
+    uint32_t mask;
 };
 
-__device__ __forceinline__ RowXYZ row_xyz(const ConvGeom& g, int64_t m) {
-    RowXYZ r{m, 0, 0, 0, m < g.M};
-    if (r.ok) {
-        const int S = g.S;
-        int64_t t = m / S;
-        r.x = (int)(m - t * S);
-        const int64_t t2 = t / S;
-        r.y = (int)(t - t2 * S);
-        r.z = (int)(t2 % S);
+__device__ __forceinline__ RowTap row_taps(const ConvGeom& g, int64_t m) {
+    RowTap r{m, 0u};
+    if (m >= g.M) return r;
+    if (g.kvol == 1) {
+        r.mask = 1u;
+        return r;
     }
+    const uint32_t S = (uint32_t)g.S;
+    const uint32_t mm = (uint32_t)m;  // M < 2^31 (checked on the host)
+    const uint32_t t = mm / S, t2 = t / S;
+    const uint32_t x = mm - t * S, y = t - t2 * S, z = t2 % S;
+    const uint32_t vx = (x > 0 ? 1u : 0u) | 2u | (x + 1 < S ? 4u : 0u);
+    const uint32_t vy = (y > 0 ? 1u : 0u) | 2u | (y + 1 < S ? 4u : 0u);
+    const uint32_t vz = (z > 0 ? 1u : 0u) | 2u | (z + 1 < S ? 4u : 0u);
+    uint32_t mask = 0u;
+#pragma unroll
+    for (int dz = 0; dz < 3; dz++)
+#pragma unroll
+        for (int dy = 0; dy < 3; dy++)
+            if ((vz >> dz & 1u) && (vy >> dy & 1u)) mask |= vx << (dz * 9 + dy * 3);
+    r.mask = mask;
     return r;
 }
 
-// 8 consecutive K entries (one tap, 8 channels) of im2col row r.
-__device__ __forceinline__ uint4 im2col8r(const uint16_t* __restrict__ in, const ConvGeom& g,
-                                          const RowXYZ& r, int k) {
-    uint4 z = make_uint4(0, 0, 0, 0);
-    if (!r.ok || k >= g.K) return z;
-    const int tap = k >> g.lgC, ci = k & (g.Cin - 1);
-    int dx = 0, dy = 0, dz = 0;
-    if (g.kvol == 27) {
-        dz = tap / 9;
-        const int rr = tap - dz * 9;
-        dy = rr / 3;
-        dx = rr - dy * 3 - 1;
-        dy -= 1;
-        dz -= 1;
-    }
-    const int S = g.S;
-    const int X = r.x + dx, Y = r.y + dy, Z = r.z + dz;
-    if (X < 0 || X >= S || Y < 0 || Y >= S || Z < 0 || Z >= S) return z;
-    const int64_t v = r.m + ((int64_t)dz * S + dy) * S + dx;
-    return *reinterpret_cast<const uint4*>(in + v * g.Cin + ci);
+// Voxel-index offset of tap t: ((dz * S) + dy) * S + dx.
+__device__ __forceinline__ int64_t tap_offset(const ConvGeom& g, int tap) {
+    if (g.kvol == 1) return 0;
+    const int dz = tap / 9, rr = tap - dz * 9, dy = rr / 3, dx = rr - dy * 3;
+    return ((int64_t)(dz - 1) * g.S + (dy - 1)) * g.S + (dx - 1);
+}
+
+// 8 consecutive K entries (one tap, 8 channels) of im2col row r, given the
+// slice's tap, channel and voxel offset.
+__device__ __forceinline__ uint4 im2col8t(const uint16_t* __restrict__ in, const ConvGeom& g,
+                                          const RowTap& r, bool kin, int tap, int ci,
+                                          int64_t off) {
+    if (!kin || !(r.mask >> tap & 1u)) return make_uint4(0, 0, 0, 0);
+    return *reinterpret_cast<const uint4*>(in + (r.m + off) * g.Cin + ci);
 }
 
 // epilogue modes
@@ -119,17 +124,20 @@ __global__ __launch_bounds__(256) void k_conv3d(const uint16_t* __restrict__ in,
     // staging roles: A rows tid/4 + 64 r (r < MR), 8-channel group tid%4;
     // B row tid/4 (output channel) for tid < 4 BN
     const int grp = tid & 3, srow = tid >> 2;
-    RowXYZ rows[MR];
+    RowTap rows[MR];
 #pragma unroll
-    for (int r = 0; r < MR; r++) rows[r] = row_xyz(g, m0 + srow + 64 * r);
+    for (int r = 0; r < MR; r++) rows[r] = row_taps(g, m0 + srow + 64 * r);
     const bool bst = tid < BN * 4;
     const uint16_t* wrow = w + (int64_t)(n0 + (bst ? srow : 0)) * g.K;
     uint4 va[MR], vb = make_uint4(0, 0, 0, 0);
     auto fetch = [&](int k0) {
         const int k = k0 + grp * 8;
+        const bool kin = k < g.K;
+        const int tap = k >> g.lgC, ci = k & (g.Cin - 1);
+        const int64_t off = tap_offset(g, tap);
 #pragma unroll
-        for (int r = 0; r < MR; r++) va[r] = im2col8r(in, g, rows[r], k);
-        if (bst) vb = k < g.K ? *reinterpret_cast<const uint4*>(wrow + k) : make_uint4(0, 0, 0, 0);
+        for (int r = 0; r < MR; r++) va[r] = im2col8t(in, g, rows[r], kin, tap, ci, off);
+        if (bst) vb = kin ? *reinterpret_cast<const uint4*>(wrow + k) : make_uint4(0, 0, 0, 0);
     };
     auto stage = [&](int buf) {
 #pragma unroll
@@ -218,6 +226,11 @@ __global__ __launch_bounds__(256) void k_conv3d_wgrad(const uint16_t* __restrict
     const int64_t mb = (int64_t)blockIdx.z * m_per_block;
     const int64_t me = min(g.M, mb + m_per_block);
     constexpr int NT = BN / 16;
+    // this thread's K columns (8 of one tap) are the same for every voxel
+    const int kw = k0 + (tid & 7) * 8;
+    const bool kin = kw < g.K;
+    const int tap = kin ? (kw >> g.lgC) : 0, ci = kw & (g.Cin - 1);
+    const int64_t off = tap_offset(g, tap);
     // wave wv owns K rows [wv * 16, +16) x all BN columns
     f32x4 acc[NT];
 #pragma unroll
@@ -228,7 +241,7 @@ __global__ __launch_bounds__(256) void k_conv3d_wgrad(const uint16_t* __restrict
             const int mrow = tid >> 3, grp = tid & 7;
             const int64_t m = m0 + mrow;
             uint4 v = make_uint4(0, 0, 0, 0);
-            if (m < me) v = im2col8r(in, g, row_xyz(g, m), k0 + grp * 8);
+            if (m < me) v = im2col8t(in, g, row_taps(g, m), kin, tap, ci, off);
             const uint16_t* h = reinterpret_cast<const uint16_t*>(&v);
 #pragma unroll
             for (int q = 0; q < 8; q++) sAt[(grp * 8 + q) * CV_APITCH + mrow] = h[q];
@@ -598,6 +611,8 @@ static int check_conv(gx_ctx* ctx, int B, int S, int Cin, int Cout, int ksize, i
                        "conv3d: need B, S >= 1, Cin % 8 == 0, Cout % 16 == 0, ksize 1 or 3");
     if (!pow2(kch))
         return gx_fail(ctx, GX_EINVAL, "conv3d: the reduced channel count must be a power of two");
+    if ((int64_t)B * S * S * S >= ((int64_t)1 << 31))
+        return gx_fail(ctx, GX_EINVAL, "conv3d: B S^3 must stay below 2^31 voxels");
     return GX_OK;
 }
 

@@ -49,6 +49,7 @@ __global__ __launch_bounds__(64) void k_walk_sph_wave(
     int32_t* __restrict__ pr_cum, uint8_t* __restrict__ sovf);
 
 #define SPH_THREADS 64
+#define SPH_DT 256         // threads of the density and force kernels (4 waves per group)
 #define SPH_CAP 2048       // candidates kept in LDS by the density kernel
 #define SPH_TILE 256       // force kernel source tile
 #define SPH_RANGES 1024    // capacity of a block's candidate range list (single-pass walk)
@@ -67,10 +68,9 @@ static int work(gx_ctx* ctx, int k, size_t bytes, void** p) {
     return GX_OK;
 }
 
-// Kernel-size seed: H64 when positive and finite, else from the smallest tree
-// node holding the particle and at least n_ngb particles, using the node's
-// geometric volume (which over-estimates the occupied volume, so the seed
-// errs large and the first candidate list already covers the root).
+// Kernel-size seed: H64 when positive and finite, else from the mean density
+// of the smallest tree node holding the particle and at least n_ngb
+// particles (its mass over the volume of its tight bounding box).
 __global__ __launch_bounds__(256) void k_sph_seed(int64_t n, const NodeRec* __restrict__ nodes,
                                                   const MomRec* __restrict__ mom,
                                                   const double4* __restrict__ pos4,
@@ -100,8 +100,15 @@ __global__ __launch_bounds__(256) void k_sph_seed(int64_t n, const NodeRec* __re
         if (nxt < 0) break;
         node = nxt;
     }
-    const double side = ldexp(box[3], -nodes[node].level);
-    const double rho = mom[node].M / (side * side * side);
+    // volume of the node's tight bounding box (a thin disk fills only a slab
+    // of its cubic cell), guarded against flat boxes
+    const NodeRec& nd = nodes[node];
+    double vol = 1.0;
+    for (int d = 0; d < 3; d++) {
+        const double w = nd.hi[d] - nd.lo[d];
+        vol *= w > 0.0 ? w : 1e-30;
+    }
+    const double rho = mom[node].M / vol;
     Hs[s] = (float)cbrt(3.0 * (double)n_ngb * pos4[s].w / (4.0 * M_PI * rho));
 }
 
@@ -164,7 +171,13 @@ __device__ __forceinline__ void expand_chunk(const GroupList& L, int npp, int ch
     }
 }
 
-__global__ __launch_bounds__(SPH_THREADS) void k_sph_density(
+// Kernel size and density: one 256-thread workgroup per group; the group's
+// candidates sit once in LDS and are shared by its four waves.  The threads
+// form 256 / pad slices (pad >= nG lanes each, every receiver once per
+// slice); a slice sums its share of the candidates, the shares are combined
+// by shuffles inside a wave and through LDS across waves (fixed order), and
+// every copy of a receiver then takes the same safeguarded Newton step.
+__global__ __launch_bounds__(SPH_DT) void k_sph_density(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes,
     const double4* __restrict__ pos4, const uint32_t* __restrict__ perm,
     const uint8_t* __restrict__ active, ListView L, float* __restrict__ rad, float n_ngb, float tol,
@@ -176,10 +189,11 @@ __global__ __launch_bounds__(SPH_THREADS) void k_sph_density(
     if (g >= ng) return;
     if (active && !active[g]) return;
     __shared__ float4 cand[SPH_CAP];
-    const int lane = threadIdx.x;
+    __shared__ float2 red[SPH_DT / 64][64];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const NodeRec B = nodes[groups[g]];
     const int nG = B.end - B.begin;
-    const int pad = slice_pad(nG), nsl = 64 / pad, il = lane % pad, sl = lane / pad;
+    const int pad = slice_pad(nG), nsl = SPH_DT / pad, il = tid % pad, sl = tid / pad;
     const double cx = (B.lo[0] + B.hi[0]) * 0.5;
     const double cy = (B.lo[1] + B.hi[1]) * 0.5;
     const double cz = (B.lo[2] + B.hi[2]) * 0.5;
@@ -187,7 +201,7 @@ __global__ __launch_bounds__(SPH_THREADS) void k_sph_density(
     const int npp = GL.npp;
     const float Rlim = rad[g];
     const bool in_lds = npp <= SPH_CAP;
-    if (in_lds) expand_chunk(GL, npp, 0, npp, pos4, cx, cy, cz, cand, lane, SPH_THREADS);
+    if (in_lds) expand_chunk(GL, npp, 0, npp, pos4, cx, cy, cz, cand, tid, SPH_DT);
     __syncthreads();
 
     int nflag = 0, nfail = 0, worst_it = 0;
@@ -214,7 +228,7 @@ __global__ __launch_bounds__(SPH_THREADS) void k_sph_density(
                 const int che = min(npp, ch + SPH_CAP);
                 if (!in_lds) {
                     __syncthreads();
-                    expand_chunk(GL, npp, ch, che, pos4, cx, cy, cz, cand, lane, SPH_THREADS);
+                    expand_chunk(GL, npp, ch, che, pos4, cx, cy, cz, cand, tid, SPH_DT);
                     __syncthreads();
                 }
                 const int cnt = che - ch;
@@ -236,8 +250,19 @@ __global__ __launch_bounds__(SPH_THREADS) void k_sph_density(
                     }
                 }
             }
+            // slices of this wave, then the four waves in order
             s0 = slice_sum(s0, pad);
             s1 = slice_sum(s1, pad);
+            if (lane < pad) red[wv][lane] = make_float2(s0, s1);
+            __syncthreads();
+            s0 = 0.0f;
+            s1 = 0.0f;
+#pragma unroll
+            for (int w = 0; w < SPH_DT / 64; w++) {
+                const float2 r = red[w][il];
+                s0 += r.x;
+                s1 += r.y;
+            }
             if (!done) {
                 it++;
                 S0 = s0;
@@ -262,7 +287,7 @@ __global__ __launch_bounds__(SPH_THREADS) void k_sph_density(
                     H = Hn;
                 }
             }
-            if (__ballot(!done) == 0ull) break;
+            if (!__syncthreads_or(done ? 0 : 1)) break;
         }
         if (act && sl == 0) {
             Hs[s] = H;
@@ -283,18 +308,20 @@ __global__ __launch_bounds__(SPH_THREADS) void k_sph_density(
             }
         }
     }
-    nflag = (int)wave_sum((unsigned)nflag);
-    nfail = (int)wave_sum((unsigned)nfail);
-    worst_it = wave_max(worst_it);
-    hmax = wave_max(hmax);
-    if (lane == 0) {
-        flags[g] = nflag ? 1u : 0u;
-        atomicMax(&stat[1], (unsigned long long)worst_it);
-        if (nflag) {
-            rad[g] = hmax * SPH_MARGIN;
-            atomicAdd(&stat[3], 1ull);
-        } else {  // counted once, in the group's final round
-            atomicAdd(&stat[0], (unsigned long long)nfail);
+    if (wv == 0) {  // slice 0 (the written copies) lies in wave 0
+        nflag = (int)wave_sum((unsigned)nflag);
+        nfail = (int)wave_sum((unsigned)nfail);
+        worst_it = wave_max(worst_it);
+        hmax = wave_max(hmax);
+        if (lane == 0) {
+            flags[g] = nflag ? 1u : 0u;
+            atomicMax(&stat[1], (unsigned long long)worst_it);
+            if (nflag) {
+                rad[g] = hmax * SPH_MARGIN;
+                atomicAdd(&stat[3], 1ull);
+            } else {  // counted once, in the group's final round
+                atomicAdd(&stat[0], (unsigned long long)nfail);
+            }
         }
     }
 }
@@ -368,7 +395,7 @@ __global__ __launch_bounds__(64) void k_group_hmax(int ng, const int32_t* __rest
     if (g < ng) rad[g] = mom[groups[g]].hmax;
 }
 
-__global__ __launch_bounds__(SPH_THREADS) void k_sph_force(
+__global__ __launch_bounds__(SPH_DT) void k_sph_force(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes,
     const double4* __restrict__ pos4, const uint32_t* __restrict__ perm,
     const double4* __restrict__ sv, const float4* __restrict__ ss, ListView L, float alpha,
@@ -380,10 +407,12 @@ __global__ __launch_bounds__(SPH_THREADS) void k_sph_force(
         tvz[SPH_TILE], tm[SPH_TILE], thi[SPH_TILE], th2[SPH_TILE], tcw[SPH_TILE], trho[SPH_TILE],
         tA[SPH_TILE], tc[SPH_TILE];
     __shared__ int32_t jidx[SPH_TILE];
-    const int lane = threadIdx.x;
+    __shared__ double redd[4][SPH_DT / 64][64];
+    __shared__ float redv[SPH_DT / 64][64];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const NodeRec B = nodes[groups[g]];
     const int nG = B.end - B.begin;
-    const int pad = slice_pad(nG), nsl = 64 / pad, il = lane % pad, sl = lane / pad;
+    const int pad = slice_pad(nG), nsl = SPH_DT / pad, il = tid % pad, sl = tid / pad;
     const double cx = (B.lo[0] + B.hi[0]) * 0.5;
     const double cy = (B.lo[1] + B.hi[1]) * 0.5;
     const double cz = (B.lo[2] + B.hi[2]) * 0.5;
@@ -429,11 +458,11 @@ __global__ __launch_bounds__(SPH_THREADS) void k_sph_force(
                 const int cn = (r + 1 < r1) ? GL.cum[r + 1] : npp;
                 const int b = GL.begin[r];
                 const int lo = max(c, t0), hi = min(cn, t0 + tn);
-                for (int k = lo + lane; k < hi; k += SPH_THREADS) jidx[k - t0] = b + (k - c);
+                for (int k = lo + tid; k < hi; k += SPH_DT) jidx[k - t0] = b + (k - c);
             }
             while (rr < r1 && ((rr + 1 < r1) ? GL.cum[rr + 1] : npp) <= t0 + tn) rr++;
             __syncthreads();
-            for (int e = lane; e < tn; e += SPH_THREADS) {
+            for (int e = tid; e < tn; e += SPH_DT) {
                 const int j = jidx[e];
                 const double4 p = pos4[j];
                 const double4 v = sv[j];
@@ -497,12 +526,30 @@ __global__ __launch_bounds__(SPH_THREADS) void k_sph_force(
                 DU += (double)fu;
             }
         }
+        // slices of each wave by shuffles, then the four waves in order
         AX = slice_sum(AX, pad);
         AY = slice_sum(AY, pad);
         AZ = slice_sum(AZ, pad);
         DU = slice_sum(DU, pad);
         for (int o = pad; o < 64; o <<= 1) vs = fmaxf(vs, __shfl_xor(vs, o, 64));
+        __syncthreads();
+        if (lane < pad) {
+            redd[0][wv][lane] = AX;
+            redd[1][wv][lane] = AY;
+            redd[2][wv][lane] = AZ;
+            redd[3][wv][lane] = DU;
+            redv[wv][lane] = vs;
+        }
+        __syncthreads();
         if (act && sl == 0) {
+            AX = AY = AZ = DU = 0.0;
+            for (int w = 0; w < SPH_DT / 64; w++) {
+                AX += redd[0][w][il];
+                AY += redd[1][w][il];
+                AZ += redd[2][w][il];
+                DU += redd[3][w][il];
+                vs = fmaxf(vs, redv[w][il]);
+            }
             const uint32_t o = perm[s];
             ax[o] += AX;
             ay[o] += AY;
@@ -514,7 +561,7 @@ __global__ __launch_bounds__(SPH_THREADS) void k_sph_force(
     nin = wave_sum(nin);
     if (lane == 0) {
         atomicAdd(&stat[2], nin);
-        atomicAdd(&stat[4], (unsigned long long)nG * (unsigned long long)npp);
+        if (wv == 0) atomicAdd(&stat[4], (unsigned long long)nG * (unsigned long long)npp);
     }
 }
 
@@ -662,7 +709,7 @@ extern "C" int gx_sph_density(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, 
         GX_TRY(gx_sph_walk(ctx, T, Ls, nb, (const int32_t*)T.groups.p, nullptr, rad, 0, act, &view,
                            &list_pairs));
         if (stats) GX_HIP(ctx, hipEventRecord(ctx->ev2, st));
-        hipLaunchKernelGGL(k_sph_density, dim3(xcd_grid(nb)), dim3(SPH_THREADS), 0, st, nb,
+        hipLaunchKernelGGL(k_sph_density, dim3(xcd_grid(nb)), dim3(SPH_DT), 0, st, nb,
                            (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
                            (const double4*)T.pos4.p,
                            (const uint32_t*)T.val[0].p, act, view, rad, (float)n_ngb, (float)tol,
@@ -748,7 +795,7 @@ extern "C" int gx_sph_forces(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, d
     GX_TRY(gx_sph_walk(ctx, T, Ls, nb, (const int32_t*)T.groups.p, nullptr, rad, 1, nullptr, &view,
                        &list_pairs));
     if (stats) GX_HIP(ctx, hipEventRecord(ctx->ev2, st));
-    hipLaunchKernelGGL(k_sph_force, dim3(xcd_grid(nb)), dim3(SPH_THREADS), 0, st, nb,
+    hipLaunchKernelGGL(k_sph_force, dim3(xcd_grid(nb)), dim3(SPH_DT), 0, st, nb,
                        (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
                        (const double4*)T.pos4.p,
                        (const uint32_t*)T.val[0].p, sv, ss, view, (float)alpha, ax, ay, az,

@@ -120,6 +120,111 @@ __global__ __launch_bounds__(128) void k_walk_grav(
     }
 }
 
+// Wave-cooperative gravity walk into per-group slots (the one-pass mode of
+// k_walk_grav): one wavefront per group, an LDS stack of pending nodes; each
+// step pops up to 64 nodes, one per lane, applies the opening criterion in
+// the same IEEE sequence, appends accepted cells and opened leaves to the
+// slots by ballot compaction and pushes the children of opened internal
+// nodes.  Lists come out in a different order than the stackless walk's (the
+// same sets).  Slot or stack overflow is counted in tot[4] (the caller then
+// builds the lists in two passes).
+#define GWALK_STACK 4096
+__global__ __launch_bounds__(64) void k_walk_grav_wave(
+    int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes,
+    const int32_t* __restrict__ child, const double* __restrict__ box, double theta2,
+    uint32_t* __restrict__ pc_cnt, uint32_t* __restrict__ pr_cnt, uint32_t* __restrict__ pp_tot,
+    unsigned long long* __restrict__ tot, int32_t* __restrict__ pc_list,
+    int32_t* __restrict__ pr_begin, int32_t* __restrict__ pr_cum, int cap_pc, int cap_pr) {
+    const int g = xcd_remap(blockIdx.x, ng);
+    if (g >= ng) return;
+    const int lane = threadIdx.x;
+    __shared__ int32_t stk[GWALK_STACK];
+    const NodeRec G = nodes[groups[g]];
+    const double L = box[3];
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t pco = (int64_t)g * cap_pc, pro = (int64_t)g * cap_pr;
+    if (lane == 0) stk[0] = 0;
+    int sp = 1, npc = 0, npr = 0, npp = 0, over = 0;
+    __syncthreads();
+    while (sp > 0 && !over) {
+        const int take = sp < 64 ? sp : 64;
+        const int b0 = sp - take;
+        int n = -1;
+        if (lane < take) n = stk[b0 + lane];
+        __syncthreads();
+        sp = b0;
+        bool acc = false, leaf = false, open = false;
+        int b = 0, e = 0;
+        if (n >= 0) {
+            const NodeRec& nd = nodes[n];
+            double lo[3] = {nd.lo[0], nd.lo[1], nd.lo[2]};
+            double hi[3] = {nd.hi[0], nd.hi[1], nd.hi[2]};
+            double d2 = box_dist2(G.lo, G.hi, lo, hi);
+            double lc = ldexp(L, -(int)nd.level);
+            double lhs = lc * lc;
+            double rhs = theta2 * d2;
+            acc = lhs < rhs;
+            leaf = !acc && nd.leaf;
+            open = !acc && !nd.leaf;
+            b = nd.begin;
+            e = nd.end;
+        }
+        // accepted cells
+        const uint64_t am = __ballot(acc);
+        if (acc) {
+            const int pos = npc + __popcll(am & lt);
+            if (pos < cap_pc) pc_list[pco + pos] = n;
+        }
+        npc += __popcll(am);
+        // opened leaves: particle ranges
+        const uint64_t lm = __ballot(leaf);
+        const int sz = leaf ? e - b : 0;
+        const int incl = wave_incl_scan(sz);
+        if (leaf) {
+            const int pos = npr + __popcll(lm & lt);
+            if (pos < cap_pr) {
+                pr_begin[pro + pos] = b;
+                pr_cum[pro + pos] = npp + incl - sz;
+            }
+        }
+        npr += __popcll(lm);
+        npp += __shfl(incl, 63, 64);
+        // opened internal nodes: children onto the stack
+        int nch = 0;
+        int32_t ch[8];
+        if (open) {
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                ch[k] = child[8 * (int64_t)n + k];
+                nch += ch[k] >= 0;
+            }
+        }
+        const int cincl = wave_incl_scan(nch);
+        const int ctot = __shfl(cincl, 63, 64);
+        if (sp + ctot > GWALK_STACK) {
+            over = 1;
+        } else {
+            const int coff = sp + cincl - nch;
+            for (int k = 0; k < nch; k++) stk[coff + k] = ch[k];
+            sp += ctot;
+        }
+        __syncthreads();
+    }
+    if (lane == 0) {
+        pc_cnt[g] = (uint32_t)npc;
+        pr_cnt[g] = (uint32_t)npr;
+        pp_tot[g] = (uint32_t)npp;
+        const unsigned long long nG = (unsigned long long)(G.end - G.begin);
+        atomicAdd(&tot[2], nG * (unsigned long long)npp);
+        atomicAdd(&tot[3], nG * (unsigned long long)npc);
+        atomicAdd(&tot[0], (unsigned long long)npc);
+        atomicAdd(&tot[1], (unsigned long long)npr);
+        atomicMax(&tot[5], (unsigned long long)npc);
+        atomicMax(&tot[6], (unsigned long long)npr);
+        if (over || npc > cap_pc || npr > cap_pr) atomicAdd(&tot[4], 1ull);
+    }
+}
+
 // Direct summation expressed as lists: every group sees the single range [0, n).
 __global__ void k_direct_lists(int ng, int n, const int32_t* __restrict__ groups,
                                const NodeRec* __restrict__ nodes, int64_t* __restrict__ pc_off,

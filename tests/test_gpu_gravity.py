@@ -291,11 +291,12 @@ def test_one_leapfrog_step_plummer(gx, eng):
 
 
 def test_list_slots_equal_two_pass_and_fall_back(gx, eng):
-    # The first call builds the lists in two passes (count, scan, fill); the
-    # next call on the same tree writes them in one pass into per-group slots
-    # sized from the first: lists and forces must be identical.  A call whose
-    # lists outgrow the slots (smaller theta) takes the two-pass path again
-    # and still matches the oracle.
+    # The first call builds the lists in two passes (count, scan, fill) with
+    # the stackless walk; the next call on the same tree builds them in one
+    # wave-cooperative pass into per-group slots sized from the first: the
+    # same lists as sets (in another order), so the same forces up to FP32
+    # summation order.  A call whose lists outgrow the slots (smaller theta)
+    # takes the two-pass path again; every call matches the oracle's lists.
     d = ics.disk_galaxy(30000, 6)
     p = _dev(gx, d)
     eng.tree_build(p, gx.GX_TREE_ALL, 16, 256)
@@ -304,11 +305,11 @@ def test_list_slots_equal_two_pass_and_fall_back(gx, eng):
         out = _zeros(p.n)
         eng.gravity_forces(p, 1.0, theta, gx.GX_QUAD, *out)
         runs.append((_np(out), eng.gravity_lists()))
-    for i, j in ((0, 1), (2, 3)):
-        for a, b in zip(runs[i][0], runs[j][0]):
-            assert np.array_equal(a, b)
-        for k in runs[i][1]:
-            assert np.array_equal(np.asarray(runs[i][1][k]), np.asarray(runs[j][1][k])), k
     T = oracle.Tree(d, 16, 256)
-    _list_sets(T, T.nodes(), T.lists(0.5), runs[1][1])
-    _list_sets(T, T.nodes(), T.lists(0.3), runs[2][1])
+    for k, theta in enumerate((0.5, 0.5, 0.3, 0.3)):
+        _list_sets(T, T.nodes(), T.lists(theta), runs[k][1])
+    for i, j in ((0, 1), (2, 3)):
+        a, b = runs[i][0], runs[j][0]
+        err = _relerr(b[:3], a[:3])
+        assert np.percentile(err, 99) <= 1e-6 and err.max() <= 1e-5
+        assert np.max(np.abs(b[3] - a[3]) / np.abs(a[3])) <= 1e-6
