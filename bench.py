@@ -42,6 +42,27 @@ HBM_PEAK = 8.0e12                    # B/s
 FLOP_PP = 27                         # per particle-particle interaction (Table 4 convention)
 FLOP_PC = 63                         # per particle-cell interaction, monopole + quadrupole
 
+# HBM traffic of one k_grav_force<float,true> launch on this workload, from two
+# rocprofv3 --pmc runs of this script (FETCH_SIZE, WRITE_SIZE in KiB per
+# dispatch) scaled by what the same counters read for a reference copy of
+# known size (hbm_calib.py: FETCH_SIZE reads half the bytes copied, WRITE_SIZE
+# all of them).  Valid only for the kernel source with this SHA-256; any
+# change to gx_gravity.hip makes the bench report null until remeasured.
+GRAV_TRAFFIC = {"source_sha256": None, "fetch_kib": None, "write_kib": None,
+                "fetch_scale": 2.0, "write_scale": 1.0}
+
+
+def grav_traffic_bytes():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2510_23330_amd", "csrc", "gx_gravity.hip")
+    if GRAV_TRAFFIC["source_sha256"] is None:
+        return None
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != GRAV_TRAFFIC["source_sha256"]:
+            return None
+    return 1024.0 * (GRAV_TRAFFIC["fetch_kib"] * GRAV_TRAFFIC["fetch_scale"] +
+                     GRAV_TRAFFIC["write_kib"] * GRAV_TRAFFIC["write_scale"])
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -241,7 +262,7 @@ def main():
         "gravity_kernel_interactions_per_s": inter_step / kernel_s,
         "energy_drift_rel": abs(E1 - E0) / abs(E0),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": grav_traffic_bytes(),
                      "kernel": "k_grav_force<float,true>",
                      "flop_convention": f"{FLOP_PP}/pp + {FLOP_PC}/pc"},
     }

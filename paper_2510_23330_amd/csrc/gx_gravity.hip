@@ -139,7 +139,12 @@ __global__ __launch_bounds__(GF_THREADS) void k_grav_force(
                     for (int jj = jb; jj < je; jj++) {
                         const V4<T> a = sA[jj];
                         const T dx = a.x - xi, dy = a.y - yi, dz = a.z - zi;
-                        const T r2 = dx * dx + dy * dy + dz * dz + (ei + sB[jj].x);
+                        // softened r^2 with the softening as the first addend,
+                        // so every product folds into a fused multiply-add
+                        T r2 = ei + sB[jj].x;
+                        r2 = fma(dx, dx, r2);
+                        r2 = fma(dy, dy, r2);
+                        r2 = fma(dz, dz, r2);
                         const T rinv = pair_rsqrt<T>(r2);
                         const T mr = a.w * rinv;
                         const T mr3 = mr * rinv * rinv;
@@ -180,7 +185,10 @@ __global__ __launch_bounds__(GF_THREADS) void k_grav_force(
                     const V4<T> a = sA[jj];
                     const V4<T> b = sB[jj];
                     const T dx = a.x - xi, dy = a.y - yi, dz = a.z - zi;
-                    const T R2 = dx * dx + dy * dy + dz * dz + (ei + b.x);
+                    T R2 = ei + b.x;
+                    R2 = fma(dx, dx, R2);
+                    R2 = fma(dy, dy, R2);
+                    R2 = fma(dz, dz, R2);
                     const T Rinv = pair_rsqrt<T>(R2);
                     const T Rinv2 = Rinv * Rinv;
                     const T M = a.w;
@@ -194,11 +202,17 @@ __global__ __launch_bounds__(GF_THREADS) void k_grav_force(
                         const T dqd = dx * qdx + dy * qdy + dz * qdz;
                         const T Rinv5 = Rinv3 * Rinv2;
                         const T u5 = dqd * Rinv5;
-                        const T coef = MR3 + (T)2.5 * u5 * Rinv2;
-                        fx += coef * dx - Rinv5 * qdx;
-                        fy += coef * dy - Rinv5 * qdy;
-                        fz += coef * dz - Rinv5 * qdz;
-                        fp -= M * Rinv + (T)0.5 * u5;
+                        const T coef = fma(u5, (T)2.5 * Rinv2, MR3);
+                        // one fused update per term keeps each component at
+                        // two operations
+                        fx = fma(coef, dx, fx);
+                        fy = fma(coef, dy, fy);
+                        fz = fma(coef, dz, fz);
+                        fx = fma(-Rinv5, qdx, fx);
+                        fy = fma(-Rinv5, qdy, fy);
+                        fz = fma(-Rinv5, qdz, fz);
+                        fp = fma(-M, Rinv, fp);
+                        fp = fma((T)-0.5, u5, fp);
                     } else {
                         fx += MR3 * dx;
                         fy += MR3 * dy;

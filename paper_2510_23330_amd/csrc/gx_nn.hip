@@ -194,6 +194,152 @@ __global__ __launch_bounds__(256) void k_conv3d(const uint16_t* __restrict__ in,
         }
 }
 
+// ---------------------------------------------------------------------------
+// 3^3 convolution on output bricks (the path for every 3^3 layer)
+// ---------------------------------------------------------------------------
+// A workgroup computes a brick of BRZ x BRY x BRX = 4 x 8 x 8 output voxels of
+// one sample for BN output channels.  For each chunk of CK input channels it
+// stages the brick's input with a one-voxel halo (6 x 10 x 10 voxels) in LDS
+// once, and the MFMA A fragments of all 27 taps are read straight from that
+// tile (tap = a fixed LDS offset), so each input voxel is fetched from memory
+// once per chunk instead of once per tap.  Wave w owns brick slice z = w
+// (64 voxels = 4 MFMA row tiles).  K runs chunk-major: (chunk, tap, channel),
+// 32 per MFMA step (32 / CK taps per step for CK < 32); weights stay in the
+// [Cout][27][Cin] layout and each lane loads its B fragment (16 bytes) from
+// memory, one step ahead.
+#define BRZ 4
+#define BRY 8
+#define BRX 8
+#define HZ (BRZ + 2)
+#define HY (BRY + 2)
+#define HX (BRX + 2)
+#define HVOX (HZ * HY * HX)
+
+template <int BN, int CK>
+__global__ __launch_bounds__(256) void k_conv3d_brick(const uint16_t* __restrict__ in,
+                                                      const uint16_t* __restrict__ w,
+                                                      const float* __restrict__ bias, ConvGeom g,
+                                                      int mode, const uint16_t* __restrict__ yref,
+                                                      uint16_t* __restrict__ out_bf,
+                                                      float* __restrict__ out_f32) {
+    constexpr int PITCH = CK + 8;          // bf16 per halo voxel (padding against bank conflicts)
+    constexpr int NT = BN / 16;
+    constexpr int TPS = 32 / CK;           // taps per MFMA step
+    constexpr int NSTEP = (27 + TPS - 1) / TPS;
+    constexpr int GPV = CK / 8;            // 8-channel groups per voxel
+    __shared__ __attribute__((aligned(16))) uint16_t hal[HVOX * PITCH];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int S = g.S;
+    const int nbx = (S + BRX - 1) / BRX, nby = (S + BRY - 1) / BRY, nbz = (S + BRZ - 1) / BRZ;
+    int t = blockIdx.x;
+    const int bx = t % nbx;
+    t /= nbx;
+    const int by = t % nby;
+    t /= nby;
+    const int bz = t % nbz;
+    const int b = t / nbz;
+    const int x0 = bx * BRX, y0 = by * BRY, z0 = bz * BRZ;
+    const int n0 = blockIdx.y * BN;
+    const int64_t vs0 = (int64_t)b * S * S * S;  // first voxel of the sample
+
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < NT; j++) acc[i][j] = f32x4{0, 0, 0, 0};
+
+    // this lane's rows: brick voxel (z = wv, y = 2 i + (lane & 15) / 8, x = lane & 7)
+    int hrow[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const int vy = 2 * i + ((lane & 15) >> 3), vx = lane & 7;
+        hrow[i] = (wv * HY + vy) * HX + vx;  // halo voxel of tap (0, 0, 0) = offset (-1, -1, -1)
+    }
+    const int kg = lane >> 4;                          // k group of this lane (8 values)
+    const int tsub = kg / GPV, csub = (kg % GPV) * 8;  // tap within the step, channel offset
+    const uint16_t* wcol[NT];
+#pragma unroll
+    for (int j = 0; j < NT; j++) wcol[j] = w + (int64_t)(n0 + j * 16 + (lane & 15)) * g.K;
+
+    const int nchunk = g.Cin / CK;
+    for (int c = 0; c < nchunk; c++) {
+        __syncthreads();  // the previous chunk's tile has been read
+        for (int e = tid; e < HVOX * GPV; e += 256) {
+            const int h = e / GPV, gq = e - h * GPV;
+            const int hz = h / (HY * HX), hr = h - hz * (HY * HX), hy = hr / HX, hx = hr - hy * HX;
+            const int Z = z0 - 1 + hz, Y = y0 - 1 + hy, X = x0 - 1 + hx;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (Z >= 0 && Z < S && Y >= 0 && Y < S && X >= 0 && X < S)
+                v = *reinterpret_cast<const uint4*>(
+                    in + (vs0 + ((int64_t)Z * S + Y) * S + X) * g.Cin + c * CK + gq * 8);
+            *reinterpret_cast<uint4*>(&hal[h * PITCH + gq * 8]) = v;
+        }
+        __syncthreads();
+        // B fragments one step ahead
+        auto load_b = [&](int st, bf16x8(&bb)[NT]) {
+            const int tap = st * TPS + tsub;
+#pragma unroll
+            for (int j = 0; j < NT; j++) {
+                uint4 q = make_uint4(0, 0, 0, 0);
+                if (tap < 27) q = *reinterpret_cast<const uint4*>(wcol[j] + tap * g.Cin + c * CK + csub);
+                bb[j] = *reinterpret_cast<const bf16x8*>(&q);
+            }
+        };
+        bf16x8 bcur[NT], bnext[NT];
+        load_b(0, bcur);
+        for (int st = 0; st < NSTEP; st++) {
+            if (st + 1 < NSTEP) load_b(st + 1, bnext);
+            const int tap = st * TPS + tsub;
+            bf16x8 a[4];
+            if (tap < 27) {
+                const int dz = tap / 9, rr = tap - dz * 9, dy = rr / 3, dx = rr - dy * 3;
+                const int toff = (dz * HY + dy) * HX + dx;
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+                    a[i] = *reinterpret_cast<const bf16x8*>(&hal[(hrow[i] + toff) * PITCH + csub]);
+            } else {
+                const uint4 z4 = make_uint4(0, 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < 4; i++) a[i] = *reinterpret_cast<const bf16x8*>(&z4);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < NT; j++)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bcur[j], acc[i][j], 0, 0, 0);
+            if (st + 1 < NSTEP) {
+#pragma unroll
+                for (int j = 0; j < NT; j++) bcur[j] = bnext[j];
+            }
+        }
+    }
+    // epilogue: lane holds rows 4 (lane / 16) + r of each 16-row tile, column lane % 16;
+    // row q of tile i is brick voxel (z = wv, y = 2 i + q / 8, x = q % 8)
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < NT; j++) {
+            const int col = n0 + j * 16 + (lane & 15);
+            const float bv = bias ? bias[col] : 0.0f;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int q = (lane >> 4) * 4 + r;
+                const int Z = z0 + wv, Y = y0 + 2 * i + (q >> 3), X = x0 + (q & 7);
+                if (Z >= S || Y >= S || X >= S) continue;
+                const int64_t m = vs0 + ((int64_t)Z * S + Y) * S + X;
+                float v = acc[i][j][r] + bv;
+                const int64_t o = m * g.Cout + col;
+                if (mode == EP_LRELU) {
+                    v = v > 0.0f ? v : LRELU_SLOPE * v;
+                } else if (mode == EP_DACT) {
+                    v = bf2f(yref[o]) > 0.0f ? v : LRELU_SLOPE * v;
+                }
+                if (out_bf) out_bf[o] = f2bf(v);
+                if (out_f32) out_f32[o] = v;
+            }
+        }
+}
+
 // Weights for the data gradient: w'[ci][tap'][co] = w[co][26 - tap'][ci] (or
 // the same tap for 1^3 kernels), so that backward data is a forward pass.
 __global__ void k_wflip(const uint16_t* __restrict__ w, int Cout, int Cin, int kvol,
@@ -312,13 +458,15 @@ __global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ 
     }
 }
 
-__global__ void k_bias_reduce(const float* __restrict__ part, int nb, int C,
-                              float* __restrict__ db) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C) return;
+// One wave per channel: lane l sums blocks l, l + 64, ...; then the lanes in
+// a fixed butterfly order.
+__global__ __launch_bounds__(64) void k_bias_reduce(const float* __restrict__ part, int nb, int C,
+                                                    float* __restrict__ db) {
+    const int c = blockIdx.x;
     float s = 0.0f;
-    for (int b = 0; b < nb; b++) s += part[(int64_t)b * C + c];
-    db[c] += s;
+    for (int b = threadIdx.x; b < nb; b += 64) s += part[(int64_t)b * C + c];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) db[c] += s;
 }
 
 // ---------------------------------------------------------------------------
@@ -616,9 +764,35 @@ static int check_conv(gx_ctx* ctx, int B, int S, int Cin, int Cout, int ksize, i
     return GX_OK;
 }
 
+template <int BN>
+static void launch_brick(gx_ctx* ctx, dim3 grid, const uint16_t* in, const uint16_t* w,
+                         const float* bias, const ConvGeom& g, int mode, const uint16_t* yref,
+                         uint16_t* ob, float* of) {
+    if (g.Cin % 32 == 0)
+        hipLaunchKernelGGL((k_conv3d_brick<BN, 32>), grid, dim3(256), 0, ctx->stream, in, w, bias, g,
+                           mode, yref, ob, of);
+    else if (g.Cin % 16 == 0)
+        hipLaunchKernelGGL((k_conv3d_brick<BN, 16>), grid, dim3(256), 0, ctx->stream, in, w, bias, g,
+                           mode, yref, ob, of);
+    else
+        hipLaunchKernelGGL((k_conv3d_brick<BN, 8>), grid, dim3(256), 0, ctx->stream, in, w, bias, g,
+                           mode, yref, ob, of);
+}
+
 static int launch_conv(gx_ctx* ctx, const uint16_t* in, const uint16_t* w, const float* bias,
                        const ConvGeom& g, int mode, const uint16_t* yref, uint16_t* ob,
                        float* of) {
+    if (g.kvol == 27) {
+        const int S = g.S;
+        const int64_t nb = (int64_t)g.B * ((S + BRZ - 1) / BRZ) * ((S + BRY - 1) / BRY) *
+                           ((S + BRX - 1) / BRX);
+        const dim3 grid((unsigned)nb, (unsigned)(g.Cout / (g.Cout % 64 == 0 ? 64 : g.Cout % 32 == 0 ? 32 : 16)));
+        if (g.Cout % 64 == 0) launch_brick<64>(ctx, grid, in, w, bias, g, mode, yref, ob, of);
+        else if (g.Cout % 32 == 0) launch_brick<32>(ctx, grid, in, w, bias, g, mode, yref, ob, of);
+        else launch_brick<16>(ctx, grid, in, w, bias, g, mode, yref, ob, of);
+        GX_LAUNCH_CHECK(ctx);
+        return GX_OK;
+    }
     const unsigned gx = (unsigned)((g.M + CV_BM - 1) / CV_BM);
     if (g.Cout % 64 == 0)
         hipLaunchKernelGGL(k_conv3d<64>, dim3(gx, g.Cout / 64), dim3(256), 0, ctx->stream, in, w,
@@ -668,18 +842,20 @@ extern "C" int gx_conv3d_bwd_weight(gx_ctx* ctx, const uint16_t* in, const uint1
     GX_HIP(ctx, hipSetDevice(ctx->device));
     const int kv = ksize == 3 ? 27 : 1;
     ConvGeom g{B, S, Cin, Cout, kv, (int64_t)B * S * S * S, kv * Cin, ilog2(Cin)};
-    // split the voxel reduction so the grid has >= ~2048 blocks
     const int kt = (g.K + 63) / 64;
     const int bn = Cout % 64 == 0 ? 64 : (Cout % 32 == 0 ? 32 : 16);
     const int nt = Cout / bn;
-    int64_t chunks = std::max<int64_t>(1, 2048 / (kt * nt));
+    // split the voxel reduction into at most 64 chunks, aiming at >= ~1024
+    // blocks in all
+    int64_t chunks = std::min<int64_t>(64, std::max<int64_t>(1, 1024 / (kt * nt)));
     int64_t mpb = (g.M + chunks - 1) / chunks;
     mpb = ((mpb + 31) / 32) * 32;
     if (mpb < 256) mpb = 256;
     chunks = (g.M + mpb - 1) / mpb;
     dim3 grid(kt, nt, (unsigned)chunks);
     const int64_t nw = (int64_t)Cout * g.K;
-    const int nbb = 256;  // bias-gradient blocks
+    // bias-gradient blocks: about 4,096 rows each, at most 256
+    const int nbb = (int)std::max<int64_t>(1, std::min<int64_t>(256, (g.M + 4095) / 4096));
     GX_TRY(gx_reserve(ctx, ctx->wpart, (size_t)(chunks * nw + (int64_t)nbb * Cout) * sizeof(float)));
     float* part = (float*)ctx->wpart.p;
     float* bpart = part + chunks * nw;
@@ -697,8 +873,8 @@ extern "C" int gx_conv3d_bwd_weight(gx_ctx* ctx, const uint16_t* in, const uint1
         const int64_t rpb = (g.M + nbb - 1) / nbb;
         hipLaunchKernelGGL(k_bias_grad, dim3(nbb), dim3(256), 0, ctx->stream, dout, g.M, Cout, rpb,
                            bpart);
-        hipLaunchKernelGGL(k_bias_reduce, dim3(gx_blocks(Cout, 256)), dim3(256), 0, ctx->stream,
-                           bpart, nbb, Cout, dbias);
+        hipLaunchKernelGGL(k_bias_reduce, dim3(Cout), dim3(64), 0, ctx->stream, bpart, nbb, Cout,
+                           dbias);
     }
     GX_LAUNCH_CHECK(ctx);
     return GX_OK;
