@@ -41,7 +41,7 @@ class Pending:
 class SNCoupling:
     def __init__(self, step, surrogate: Surrogate, n_sites: int = 64, delay: int = 50,
                  side_pc: float = 60.0, seed: int = 5, r_max: float = 15.0, z_max: float = 0.3,
-                 valid_sigma: float = 8.0, cfg: SPHConfig = SPHConfig()):
+                 valid_sigma: float = 8.0, cfg: SPHConfig = SPHConfig(), star_type: int = 1):
         import torch
         self.torch = torch
         self.step, self.sur = step, surrogate
@@ -50,13 +50,16 @@ class SNCoupling:
         self.seed, self.cfg = seed, cfg
         self.valid_sigma = valid_sigma
         p, o = step.p, step.gas_offset
-        # candidate sites: disk stars (type 0 slice [0, gas_offset) minus the halo)
+        # candidate sites: stars (particle type star_type; the synthetic sets
+        # use 0 dark matter, 1 stars, 2 gas) in the disk, R < r_max, |z| < z_max
         x = p.x[:o].cpu().numpy()
         y = p.y[:o].cpu().numpy()
         z = p.z[:o].cpu().numpy()
-        ptype = p.type[:o].cpu().numpy() if p.type is not None else np.zeros(o, np.uint8)
+        ptype = p.type[:o].cpu().numpy() if p.type is not None else np.full(o, star_type, np.uint8)
         R = np.sqrt(x * x + y * y)
-        self.cand = np.nonzero((ptype == 0) & (R < r_max) & (np.abs(z) < z_max))[0]
+        self.cand = np.nonzero((ptype == star_type) & (R < r_max) & (np.abs(z) < z_max))[0]
+        if self.cand.size == 0:
+            raise ValueError("no star particles inside the SN site region")
         g = int(math.ceil(n_sites ** (1.0 / 3.0)))
         lat = np.array([((k % g), (k // g) % g, k // (g * g)) for k in range(n_sites)],
                        np.float64) * 1000.0

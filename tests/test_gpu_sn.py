@@ -233,6 +233,10 @@ def test_coupling_replaces_by_id(gx, eng):
     sur.mean_out.copy_(mean_out)
     side_pc = 600.0
     cp = SNCoupling(st, sur, n_sites=16, delay=1, side_pc=side_pc, seed=11)
+    # sites are disk stars
+    assert np.all(d["type"][cp.cand] == ics.T_STAR)
+    R = np.hypot(d["x"][cp.cand], d["y"][cp.cand])
+    assert np.all(R < 15.0) and np.all(np.abs(d["z"][cp.cand]) < 0.3)
     centers = cp.sites(0).cpu().numpy()
     gx_, gy, gz = (a.cpu().numpy() for a in (st.gas.x, st.gas.y, st.gas.z))
     gvx, gvy, gvz = (a.cpu().numpy() for a in (st.gas.vx, st.gas.vy, st.gas.vz))
