@@ -378,6 +378,16 @@ int gx_sn_replace(gx_ctx* ctx, int64_t n, const int64_t* id, int64_t id_cap, dou
 int gx_conv3d_fwd(gx_ctx* ctx, const uint16_t* in, int B, int S, int Cin, const uint16_t* w,
                   const float* bias, int ksize, int Cout, int act, uint16_t* out_bf16,
                   float* out_f32);
+/* 3^3 convolution (as gx_conv3d_fwd) of an input assembled on the fly:
+ * channels [0, c1) from `in` ([B][..][c1]) and [c1, Cin) from `in2`
+ * ([B][..][Cin - c1]; NULL: all Cin channels from `in`, c1 = Cin); with
+ * upsample = 1 both sources hold (S/2)^3 voxels and are read with nearest x2
+ * upsampling.  Equals gx_upsample2 / gx_concat followed by gx_conv3d_fwd
+ * without materialising their outputs (the U-Net's up-path convolutions at
+ * inference).  c1 a multiple of 8; S even when upsampling. */
+int gx_conv3d_fwd_fused(gx_ctx* ctx, const uint16_t* in, int c1, const uint16_t* in2, int upsample,
+                        int B, int S, int Cin, const uint16_t* w, const float* bias, int Cout,
+                        int act, uint16_t* out_bf16, float* out_f32);
 /* din = dL/din from dout = dL/dout ([B][S^3][Cout]) for the layer of weights w
  * ([Cout][kvol][Cin]); when y_in (the layer input, itself the LeakyReLU output
  * of the previous layer) is given, din is multiplied by that activation's

@@ -358,6 +358,14 @@ class Engine:
                                            ksize, Cout, int(act), _ptr(out_bf16, torch.bfloat16),
                                            _ptr(out_f32, torch.float32)))
 
+    def conv3d_fwd_fused(self, x, c1, x2, upsample, B, S, Cin, w, bias, Cout, act, out_bf16=None,
+                         out_f32=None):
+        torch = _torch()
+        self._check(self.lib.gx_conv3d_fwd_fused(
+            self.ctx, _ptr(x, torch.bfloat16), int(c1), _ptr(x2, torch.bfloat16), int(upsample), B,
+            S, Cin, _ptr(w, torch.bfloat16), _ptr(bias, torch.float32), Cout, int(act),
+            _ptr(out_bf16, torch.bfloat16), _ptr(out_f32, torch.float32)))
+
     def conv3d_bwd_data(self, dout, B, S, Cin, w, ksize, Cout, y_in, din):
         torch = _torch()
         self._check(self.lib.gx_conv3d_bwd_data(self.ctx, _ptr(dout, torch.bfloat16), B, S, Cin,

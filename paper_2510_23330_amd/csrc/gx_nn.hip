@@ -215,13 +215,22 @@ __global__ __launch_bounds__(256) void k_conv3d(const uint16_t* __restrict__ in,
 #define HX (BRX + 2)
 #define HVOX (HZ * HY * HX)
 
+// The convolution's input may be assembled on the fly: channels [0, c1) from
+// `in` and [c1, Cin) from `in2` (a channel concatenation), each read at half
+// resolution when `up` is set (nearest x2 upsampling of an (S/2)^3 grid).
+struct ConvSrc {
+    const uint16_t* in2;
+    int c1;  // channels taken from the first source (Cin when in2 is null)
+    int up;  // 1: sources hold (S/2)^3 voxels
+};
+
 template <int BN, int CK>
 __global__ __launch_bounds__(256) void k_conv3d_brick(const uint16_t* __restrict__ in,
                                                       const uint16_t* __restrict__ w,
                                                       const float* __restrict__ bias, ConvGeom g,
                                                       int mode, const uint16_t* __restrict__ yref,
                                                       uint16_t* __restrict__ out_bf,
-                                                      float* __restrict__ out_f32) {
+                                                      float* __restrict__ out_f32, ConvSrc src) {
     constexpr int PITCH = CK + 8;          // bf16 per halo voxel (padding against bank conflicts)
     constexpr int NT = BN / 16;
     constexpr int TPS = 32 / CK;           // taps per MFMA step
@@ -262,16 +271,29 @@ __global__ __launch_bounds__(256) void k_conv3d_brick(const uint16_t* __restrict
     for (int j = 0; j < NT; j++) wcol[j] = w + (int64_t)(n0 + j * 16 + (lane & 15)) * g.K;
 
     const int nchunk = g.Cin / CK;
+    const int Ss = src.up ? S / 2 : S;             // source grid
+    const int64_t ss0 = (int64_t)b * Ss * Ss * Ss;  // first source voxel of the sample
     for (int c = 0; c < nchunk; c++) {
+        // this chunk's source tensor, its channel stride and offset
+        const bool second = src.in2 && c * CK >= src.c1;
+        const uint16_t* sp = second ? src.in2 : in;
+        const int sc = second ? g.Cin - src.c1 : src.c1;
+        const int co = second ? c * CK - src.c1 : c * CK;
         __syncthreads();  // the previous chunk's tile has been read
         for (int e = tid; e < HVOX * GPV; e += 256) {
             const int h = e / GPV, gq = e - h * GPV;
             const int hz = h / (HY * HX), hr = h - hz * (HY * HX), hy = hr / HX, hx = hr - hy * HX;
-            const int Z = z0 - 1 + hz, Y = y0 - 1 + hy, X = x0 - 1 + hx;
+            int Z = z0 - 1 + hz, Y = y0 - 1 + hy, X = x0 - 1 + hx;
             uint4 v = make_uint4(0, 0, 0, 0);
-            if (Z >= 0 && Z < S && Y >= 0 && Y < S && X >= 0 && X < S)
+            if (Z >= 0 && Z < S && Y >= 0 && Y < S && X >= 0 && X < S) {
+                if (src.up) {
+                    Z >>= 1;
+                    Y >>= 1;
+                    X >>= 1;
+                }
                 v = *reinterpret_cast<const uint4*>(
-                    in + (vs0 + ((int64_t)Z * S + Y) * S + X) * g.Cin + c * CK + gq * 8);
+                    sp + (ss0 + ((int64_t)Z * Ss + Y) * Ss + X) * sc + co + gq * 8);
+            }
             *reinterpret_cast<uint4*>(&hal[h * PITCH + gq * 8]) = v;
         }
         __syncthreads();
@@ -767,29 +789,33 @@ static int check_conv(gx_ctx* ctx, int B, int S, int Cin, int Cout, int ksize, i
 template <int BN>
 static void launch_brick(gx_ctx* ctx, dim3 grid, const uint16_t* in, const uint16_t* w,
                          const float* bias, const ConvGeom& g, int mode, const uint16_t* yref,
-                         uint16_t* ob, float* of) {
-    if (g.Cin % 32 == 0)
+                         uint16_t* ob, float* of, const ConvSrc& src) {
+    // chunk width: the largest of 32, 16, 8 dividing both sources' channel counts
+    const int c2 = g.Cin - src.c1;
+    auto fits = [&](int ck) { return g.Cin % ck == 0 && src.c1 % ck == 0 && c2 % ck == 0; };
+    if (fits(32))
         hipLaunchKernelGGL((k_conv3d_brick<BN, 32>), grid, dim3(256), 0, ctx->stream, in, w, bias, g,
-                           mode, yref, ob, of);
-    else if (g.Cin % 16 == 0)
+                           mode, yref, ob, of, src);
+    else if (fits(16))
         hipLaunchKernelGGL((k_conv3d_brick<BN, 16>), grid, dim3(256), 0, ctx->stream, in, w, bias, g,
-                           mode, yref, ob, of);
+                           mode, yref, ob, of, src);
     else
         hipLaunchKernelGGL((k_conv3d_brick<BN, 8>), grid, dim3(256), 0, ctx->stream, in, w, bias, g,
-                           mode, yref, ob, of);
+                           mode, yref, ob, of, src);
 }
 
 static int launch_conv(gx_ctx* ctx, const uint16_t* in, const uint16_t* w, const float* bias,
                        const ConvGeom& g, int mode, const uint16_t* yref, uint16_t* ob,
-                       float* of) {
+                       float* of, ConvSrc src = ConvSrc{nullptr, -1, 0}) {
+    if (src.c1 < 0) src.c1 = g.Cin;
     if (g.kvol == 27) {
         const int S = g.S;
         const int64_t nb = (int64_t)g.B * ((S + BRZ - 1) / BRZ) * ((S + BRY - 1) / BRY) *
                            ((S + BRX - 1) / BRX);
         const dim3 grid((unsigned)nb, (unsigned)(g.Cout / (g.Cout % 64 == 0 ? 64 : g.Cout % 32 == 0 ? 32 : 16)));
-        if (g.Cout % 64 == 0) launch_brick<64>(ctx, grid, in, w, bias, g, mode, yref, ob, of);
-        else if (g.Cout % 32 == 0) launch_brick<32>(ctx, grid, in, w, bias, g, mode, yref, ob, of);
-        else launch_brick<16>(ctx, grid, in, w, bias, g, mode, yref, ob, of);
+        if (g.Cout % 64 == 0) launch_brick<64>(ctx, grid, in, w, bias, g, mode, yref, ob, of, src);
+        else if (g.Cout % 32 == 0) launch_brick<32>(ctx, grid, in, w, bias, g, mode, yref, ob, of, src);
+        else launch_brick<16>(ctx, grid, in, w, bias, g, mode, yref, ob, of, src);
         GX_LAUNCH_CHECK(ctx);
         return GX_OK;
     }
@@ -816,6 +842,22 @@ extern "C" int gx_conv3d_fwd(gx_ctx* ctx, const uint16_t* in, int B, int S, int 
     const int kv = ksize == 3 ? 27 : 1;
     ConvGeom g{B, S, Cin, Cout, kv, (int64_t)B * S * S * S, kv * Cin, ilog2(Cin)};
     return launch_conv(ctx, in, w, bias, g, act ? EP_LRELU : EP_NONE, nullptr, out_bf16, out_f32);
+}
+
+extern "C" int gx_conv3d_fwd_fused(gx_ctx* ctx, const uint16_t* in, int c1, const uint16_t* in2,
+                                   int upsample, int B, int S, int Cin, const uint16_t* w,
+                                   const float* bias, int Cout, int act, uint16_t* out_bf16,
+                                   float* out_f32) {
+    if (!ctx || !in || !w || (!out_bf16 && !out_f32)) return GX_EINVAL;
+    GX_TRY(check_conv(ctx, B, S, Cin, Cout, 3, Cin));
+    if (in2 ? (c1 < 8 || c1 % 8 || c1 >= Cin) : (c1 != Cin))
+        return gx_fail(ctx, GX_EINVAL, "conv3d_fwd_fused: c1 must split Cin in multiples of 8");
+    if (upsample && (S % 2 || S < 2))
+        return gx_fail(ctx, GX_EINVAL, "conv3d_fwd_fused: upsampling needs an even S");
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    ConvGeom g{B, S, Cin, Cout, 27, (int64_t)B * S * S * S, 27 * Cin, ilog2(Cin)};
+    return launch_conv(ctx, in, w, bias, g, act ? EP_LRELU : EP_NONE, nullptr, out_bf16, out_f32,
+                       ConvSrc{in2, in2 ? c1 : Cin, upsample ? 1 : 0});
 }
 
 extern "C" int gx_conv3d_bwd_data(gx_ctx* ctx, const uint16_t* dout, int B, int S, int Cin,

@@ -134,9 +134,10 @@ class UNet:
                 A[f"p{l}"] = torch.zeros(B * (s // 2) ** 3 * ch[l], **bf)
         for l in range(self.levels - 2, -1, -1):
             s = S // 2 ** l
-            A[f"up{l}"] = torch.zeros(B * s ** 3 * ch[l + 1], **bf)
+            if self.train_mode:  # inference reads them through the fused convolution
+                A[f"up{l}"] = torch.zeros(B * s ** 3 * ch[l + 1], **bf)
+                A[f"c{l}"] = torch.zeros(B * s ** 3 * 2 * ch[l], **bf)
             A[f"u{l}c"] = torch.zeros(B * s ** 3 * ch[l], **bf)
-            A[f"c{l}"] = torch.zeros(B * s ** 3 * 2 * ch[l], **bf)
             A[f"d{l}a"] = torch.zeros(B * s ** 3 * ch[l], **bf)
             A[f"d{l}b"] = torch.zeros(B * s ** 3 * ch[l], **bf)
         self.pred = torch.zeros(B * S ** 3 * COUT_PAD, dtype=torch.float32, device=self.device)
@@ -161,6 +162,11 @@ class UNet:
         self.eng.conv3d_fwd(x, self.Bcur, S, ly.cin, self._w(ly), self._b(ly), ly.ksize, ly.cout,
                             ly.act, out_bf16=out_bf, out_f32=out_f32)
 
+    def _conv_fused(self, name, x, c1, x2, up, S, out_bf):
+        ly = self.by[name]
+        self.eng.conv3d_fwd_fused(x, c1, x2, up, self.Bcur, S, ly.cin, self._w(ly), self._b(ly),
+                                  ly.cout, ly.act, out_bf16=out_bf)
+
     # ---- forward ----------------------------------------------------------------
     def forward(self, x):
         """x: bf16 [B * S^3 * 8] standardized input; returns fp32 [B * S^3 * 16]."""
@@ -176,10 +182,15 @@ class UNet:
         h = A[f"e{self.levels - 1}b"]
         for l in range(self.levels - 2, -1, -1):
             s = S // 2 ** l
-            self.eng.upsample2(h, B, s // 2, ch[l + 1], A[f"up{l}"])
-            self._conv(f"u{l}c", A[f"up{l}"], s, A[f"u{l}c"])
-            self.eng.concat(A[f"u{l}c"], ch[l], A[f"e{l}b"], ch[l], B * s ** 3, A[f"c{l}"])
-            self._conv(f"d{l}a", A[f"c{l}"], s, A[f"d{l}a"])
+            if self.train_mode:
+                # the backward pass needs the upsampled and concatenated inputs
+                self.eng.upsample2(h, B, s // 2, ch[l + 1], A[f"up{l}"])
+                self._conv(f"u{l}c", A[f"up{l}"], s, A[f"u{l}c"])
+                self.eng.concat(A[f"u{l}c"], ch[l], A[f"e{l}b"], ch[l], B * s ** 3, A[f"c{l}"])
+                self._conv(f"d{l}a", A[f"c{l}"], s, A[f"d{l}a"])
+            else:
+                self._conv_fused(f"u{l}c", h, ch[l + 1], None, 1, s, A[f"u{l}c"])
+                self._conv_fused(f"d{l}a", A[f"u{l}c"], ch[l], A[f"e{l}b"], 0, s, A[f"d{l}a"])
             self._conv(f"d{l}b", A[f"d{l}a"], s, A[f"d{l}b"])
             h = A[f"d{l}b"]
         self._conv("head", h, S, out_f32=self.pred)

@@ -297,3 +297,62 @@ def test_cube_symmetries(gx, eng):
     eng.cube_sym(t, 8, S, C, 2, sym, once)
     eng.cube_sym(once, 8, S, C, 2, sym, twice)
     assert torch.equal(twice, t)
+
+
+@pytest.mark.parametrize("case,Ca,Cb", [("upsample", 32, 0), ("concat", 32, 32), ("concat", 16, 16),
+                                        ("both", 32, 32)])
+def test_conv_fused_inputs_equal_materialized(gx, eng, case, Ca, Cb):
+    # Convolving an input assembled on the fly (nearest x2 upsampling and/or a
+    # channel concatenation) gives what upsample2 / concat followed by the
+    # plain convolution gives: bit for bit when both reduce the channels in
+    # the same chunks.
+    import torch
+    rng = np.random.default_rng(21)
+    B, S, Cout = 2, 10, 32
+    up = case in ("upsample", "both")
+    Sin = S // 2 if up else S
+    a = _bf(oracle.bf16_round(rng.normal(size=(B, Sin, Sin, Sin, Ca))))
+    b = _bf(oracle.bf16_round(rng.normal(size=(B, Sin, Sin, Sin, Cb)))) if case != "upsample" else None
+    Cin = Ca + (Cb if b is not None else 0)
+    w = _bf(oracle.bf16_round(rng.normal(scale=0.1, size=(Cout, 27, Cin))))
+    bias = torch.as_tensor(rng.normal(size=Cout).astype(np.float32), device="cuda")
+    # materialized reference
+    V = B * S ** 3
+    if b is not None:
+        cat = torch.zeros(B * Sin ** 3 * Cin, dtype=torch.bfloat16, device="cuda")
+        eng.concat(a, Ca, b, Cb, B * Sin ** 3, cat)
+    else:
+        cat = a
+    if up:
+        full = torch.zeros(V * Cin, dtype=torch.bfloat16, device="cuda")
+        eng.upsample2(cat, B, Sin, Cin, full)
+    else:
+        full = cat
+    ref = torch.zeros(V * Cout, dtype=torch.float32, device="cuda")
+    eng.conv3d_fwd(full, B, S, Cin, w, bias, 3, Cout, 1, out_f32=ref)
+    got = torch.zeros_like(ref)
+    eng.conv3d_fwd_fused(a, Ca if b is not None else Cin, b, int(up), B, S, Cin, w, bias, Cout, 1,
+                         out_f32=got)
+    if Ca % 32 == 0 and Cb % 32 == 0:
+        assert torch.equal(got, ref)
+    else:
+        # 16-channel sources are reduced in 16-channel chunks (another FP32
+        # summation order than the 32-channel chunks of the plain call)
+        r = ref.cpu().numpy()
+        assert np.max(np.abs(got.cpu().numpy() - r)) <= 1e-5 * np.sqrt(np.mean(r ** 2))
+
+
+def test_unet_inference_equals_training_forward(gx, eng):
+    # The inference-mode network (fused up-path inputs, no saved tensors) and
+    # the training-mode network compute the same prediction bit for bit
+    # (channel counts multiples of 32: the same reduction chunks).
+    import torch
+    from paper_2510_23330_amd.unet import UNet
+    S, B = 16, 2
+    tr = UNet(eng, S=S, batch=B, base=32, levels=3, seed=5)
+    inf = UNet(eng, S=S, batch=B, base=32, levels=3, seed=5, train=False)
+    rng = np.random.default_rng(6)
+    x = np.zeros((B, S, S, S, 8), np.float32)
+    x[..., :5] = rng.normal(size=(B, S, S, S, 5))
+    xt = _bf(x)
+    assert torch.equal(tr.forward(xt).clone(), inf.forward(xt))

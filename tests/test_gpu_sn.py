@@ -285,3 +285,53 @@ def test_coupling_replaces_by_id(gx, eng):
         assert np.allclose(VX[k], 1.0) and np.allclose(VY[k], 2.0) and np.allclose(VZ[k], 3.0)
         assert np.allclose(U[k - go], 1e4 * ics.U_PER_K, rtol=1e-5)
     sur_eng.close()
+
+
+def test_ambient_gather_unframe(gx, eng):
+    # Region hand-over helpers: the ambient state is the members' mean density
+    # and mass-weighted temperature and velocity; packing into the box frame
+    # and unpacking (no drift) returns the positions; with a drift the shift
+    # is the bulk velocity times the delay.
+    import torch
+    d = _field(50_000, 31, box=100.0)
+    d["u"] = np.random.default_rng(32).uniform(1.0, 5.0, 50_000)
+    p = gx.ParticleSet.from_numpy(d)
+    rng = np.random.default_rng(33)
+    centers = rng.uniform(-60, 60, (6, 3))
+    side = 40.0
+    off, idx, tot = eng.sn_extract(p, _t(centers), side / 2, 50_000)
+    u = _t(d["u"])
+    amb = eng.sn_ambient(p, u, off, idx, side, 48.46).cpu().numpy().reshape(-1, 5)
+    offh, idxh = off.cpu().numpy(), idx.cpu().numpy()
+    for c in range(6):
+        mem = idxh[offh[c]:offh[c + 1]]
+        m = d["m"][mem]
+        assert amb[c, 0] == pytest.approx(math.log10(m.sum() / side ** 3), abs=1e-6)
+        assert amb[c, 1] == pytest.approx(math.log10(np.sum(m * d["u"][mem]) / m.sum() * 48.46), abs=1e-6)
+        for k, v in enumerate(("vx", "vy", "vz")):
+            assert amb[c, 2 + k] == pytest.approx(np.sum(m * d[v][mem]) / m.sum(), abs=1e-5)
+    n_max = int(np.diff(offh).max())
+    dst = _t(np.arange(18, dtype=np.float64).reshape(6, 3) * 1000.0)
+    box = {k: torch.empty(tot, dtype=torch.float64, device="cuda")
+           for k in ("x", "y", "z", "vx", "vy", "vz", "m", "u")}
+    box["H"] = torch.empty(tot, dtype=torch.float32, device="cuda")
+    eng.sn_gather(p, u, None, off, idx, n_max, _t(centers), dst, 1000.0, box)
+    bx = box["x"].cpu().numpy()
+    dsth = dst.cpu().numpy()
+    for c in range(6):
+        sl = slice(offh[c], offh[c + 1])
+        mem = idxh[sl]
+        assert np.allclose(bx[sl], (d["x"][mem] - centers[c, 0]) * 1000.0 + dsth[c, 0], rtol=0, atol=1e-6)
+        assert np.array_equal(box["m"].cpu().numpy()[sl], d["m"][mem])
+        assert np.all(box["H"].cpu().numpy()[sl] == -1.0)
+    x, y, z = box["x"].clone(), box["y"].clone(), box["z"].clone()
+    eng.sn_unframe(off, n_max, dst, _t(centers), None, 0.0, 1000.0, x, y, z)
+    assert np.allclose(x.cpu().numpy(), d["x"][idxh], rtol=0, atol=1e-9)
+    assert np.allclose(z.cpu().numpy(), d["z"][idxh], rtol=0, atol=1e-9)
+    ambt = torch.as_tensor(amb.ravel(), device="cuda")
+    x2 = box["x"].clone()
+    eng.sn_unframe(off, n_max, dst, _t(centers), ambt, 2.0, 1000.0, x2, box["y"].clone(), box["z"].clone())
+    shift = x2.cpu().numpy() - x.cpu().numpy()
+    for c in range(6):
+        sl = slice(offh[c], offh[c + 1])
+        assert np.allclose(shift[sl], 2.0 * amb[c, 2], rtol=1e-6, atol=1e-9)
