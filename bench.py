@@ -204,6 +204,7 @@ def main():
     grav_ms, grav_kernel_ms, dens_ms, hydro_ms, tree_ms = [], [], [], [], []
     n_pp = n_pc = n_sph = 0
     energies = []
+    walk_diag = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for k in range(args.steps):
@@ -217,6 +218,7 @@ def main():
         dens_ms.append(st["density"]["ms"])
         hydro_ms.append(st["hydro"]["ms"])
         tree_ms.append(st["tree_all"]["ms"] + st["tree_gas"]["ms"])
+        walk_diag.append((st["gravity"]["n_rewalk"], st["gravity"]["n_iter_max"]))
         n_pp += st["gravity"]["n_pp"]
         n_pc += st["gravity"]["n_pc"]
         n_sph += st["density"]["n_sph_list"] + st["hydro"]["n_sph_list"]
@@ -261,6 +263,8 @@ def main():
         "sn_coupling": None if coupling is None else dict(coupling.stats, sites_per_step=args.sn_sites,
                                                           delay_steps=50),
         "gravity_kernel_interactions_per_s": inter_step / kernel_s,
+        "gravity_lists": {"two_pass_steps": int(sum(w[0] for w in walk_diag)),
+                          "max_walk_stack": int(max(w[1] for w in walk_diag))},
         "energy_drift_rel": abs(E1 - E0) / abs(E0),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": grav_traffic_bytes(),

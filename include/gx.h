@@ -68,9 +68,11 @@ typedef struct {
     int64_t n_sph_ngb;   /* SPH pairs inside the kernel support */
     int64_t n_groups;    /* receiving groups */
     int64_t n_nodes;     /* tree nodes */
-    int64_t n_iter_max;  /* largest kernel-size iteration count */
+    int64_t n_iter_max;  /* largest kernel-size iteration count (SPH density);
+                            deepest stack of the one-pass list walk (gravity) */
     int64_t n_noconv;    /* receivers whose kernel size did not converge */
-    int64_t n_rewalk;    /* groups whose SPH list had to be rebuilt */
+    int64_t n_rewalk;    /* re-walk rounds of the SPH density list (SPH density);
+                            1 when the gravity lists took the two-pass path */
     double ms;           /* wall time of the call on the stream, milliseconds */
     double ms_kernel;    /* time of the call's pairwise kernel alone (HIP events), ms */
 } gx_stats;

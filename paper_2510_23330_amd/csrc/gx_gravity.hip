@@ -33,8 +33,14 @@ __global__ __launch_bounds__(64) void k_walk_grav_wave(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes,
     const int32_t* __restrict__ child, const double* __restrict__ box, double theta2,
     uint32_t* __restrict__ pc_cnt, uint32_t* __restrict__ pr_cnt, uint32_t* __restrict__ pp_tot,
-    unsigned long long* __restrict__ tot, int32_t* __restrict__ pc_list,
-    int32_t* __restrict__ pr_begin, int32_t* __restrict__ pr_cum, int cap_pc, int cap_pr);
+    int32_t* __restrict__ pc_list, int32_t* __restrict__ pr_begin, int32_t* __restrict__ pr_cum,
+    int cap_pc, int cap_pr, uint8_t* __restrict__ gflag, int32_t* __restrict__ gdepth);
+__global__ __launch_bounds__(256) void k_group_totals(
+    int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ recv,
+    const NodeRec* __restrict__ nodes, const uint32_t* __restrict__ c0,
+    const uint32_t* __restrict__ c1, const uint32_t* __restrict__ pp,
+    const uint8_t* __restrict__ flag, const int32_t* __restrict__ depth,
+    unsigned long long* __restrict__ tot);
 __global__ void k_direct_lists(int ng, int n, const int32_t* __restrict__ groups,
                                const NodeRec* __restrict__ nodes, int64_t* __restrict__ pc_off,
                                int64_t* __restrict__ pr_off, uint32_t* __restrict__ pc_cnt,
@@ -301,6 +307,8 @@ extern "C" int gx_gravity_forces(gx_ctx* ctx, const gx_particles* p, double G, d
         const double theta2 = theta * theta;
         bool done = false;
         int64_t seen_pc = 0, seen_pr = 0;  // largest per-group list sizes seen in this call
+        Ls.last_two_pass = 1;
+        Ls.last_stack = 0;
         // one pass into per-group slots sized from the largest lists of the
         // previous call; a list that does not fit sends the call to the exact
         // two-pass (count, scan, fill) construction
@@ -308,19 +316,29 @@ extern "C" int gx_gravity_forces(gx_ctx* ctx, const gx_particles* p, double G, d
             GX_TRY(gx_reserve(ctx, Ls.pc_list, (size_t)ng * Ls.cap_pc * sizeof(int32_t)));
             GX_TRY(gx_reserve(ctx, Ls.pr_begin, (size_t)ng * Ls.cap_pr * sizeof(int32_t)));
             GX_TRY(gx_reserve(ctx, Ls.pr_cum, (size_t)ng * Ls.cap_pr * sizeof(int32_t)));
+            GX_TRY(gx_reserve(ctx, Ls.aux, (size_t)ng * (1 + sizeof(int32_t)) + 64));
+            uint8_t* gflag = (uint8_t*)Ls.aux.p;
+            int32_t* gdepth = (int32_t*)((uint8_t*)Ls.aux.p + (((size_t)ng + 15) & ~(size_t)15));
             hipLaunchKernelGGL(k_walk_grav_wave, dim3(xcd_grid(ng)), dim3(64), 0, st, ng,
                                (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
                                (const int32_t*)T.child.p, (const double*)T.box.p, theta2,
                                (uint32_t*)Ls.pc_cnt.p, (uint32_t*)Ls.pr_cnt.p,
-                               (uint32_t*)Ls.pp_tot.p, (unsigned long long*)tot,
-                               (int32_t*)Ls.pc_list.p, (int32_t*)Ls.pr_begin.p,
-                               (int32_t*)Ls.pr_cum.p, Ls.cap_pc, Ls.cap_pr);
+                               (uint32_t*)Ls.pp_tot.p, (int32_t*)Ls.pc_list.p,
+                               (int32_t*)Ls.pr_begin.p, (int32_t*)Ls.pr_cum.p, Ls.cap_pc,
+                               Ls.cap_pr, gflag, gdepth);
+            hipLaunchKernelGGL(k_group_totals, dim3(gx_blocks(ng, 256)), dim3(256), 0, st, ng,
+                               (const int32_t*)T.groups.p, nullptr, (const NodeRec*)T.nodes.p,
+                               (const uint32_t*)Ls.pc_cnt.p, (const uint32_t*)Ls.pr_cnt.p,
+                               (const uint32_t*)Ls.pp_tot.p, gflag, gdepth,
+                               (unsigned long long*)tot);
             GX_LAUNCH_CHECK(ctx);
             GX_TRY(read_host(ctx, h_tot, tot, 8 * sizeof(int64_t)));
             seen_pc = h_tot[5];
             seen_pr = h_tot[6];
+            Ls.last_stack = h_tot[7];
             if (h_tot[4] == 0) {
                 done = true;
+                Ls.last_two_pass = 0;
                 Ls.stride_pc = Ls.cap_pc;
                 Ls.stride_pr = Ls.cap_pr;
                 Ls.n_pc = h_tot[0];
@@ -411,6 +429,10 @@ extern "C" int gx_gravity_forces(gx_ctx* ctx, const gx_particles* p, double G, d
         stats->n_pc = h_tot[3];
         stats->n_groups = ng;
         stats->n_nodes = nn;
+        // list construction: n_rewalk = 1 when it took the two-pass path,
+        // n_iter_max = deepest walk stack of the one-pass walk (0: not run)
+        stats->n_rewalk = Ls.last_two_pass;
+        stats->n_iter_max = Ls.last_stack;
     }
     return GX_OK;
 }

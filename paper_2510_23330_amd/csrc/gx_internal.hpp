@@ -75,6 +75,7 @@ struct ListSet {  // per-group interaction lists (CSR)
     int64_t stride_pc = 0, stride_pr = 0;
     int cap_pc = 0, cap_pr = 0;
     int64_t cap_ng = -1;
+    int64_t last_two_pass = 1, last_stack = 0;  // diagnostics of the last construction
 };
 
 struct gx_ctx {

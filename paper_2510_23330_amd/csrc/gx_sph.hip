@@ -39,6 +39,12 @@ __global__ __launch_bounds__(64) void k_walk_sph_bfs(
     uint32_t* __restrict__ pr_cnt, uint32_t* __restrict__ pp_tot,
     unsigned long long* __restrict__ tot, int32_t* __restrict__ pr_begin,
     int32_t* __restrict__ pr_cum, uint8_t* __restrict__ ovf);
+__global__ __launch_bounds__(256) void k_group_totals(
+    int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ recv,
+    const NodeRec* __restrict__ nodes, const uint32_t* __restrict__ c0,
+    const uint32_t* __restrict__ c1, const uint32_t* __restrict__ pp,
+    const uint8_t* __restrict__ flag, const int32_t* __restrict__ depth,
+    unsigned long long* __restrict__ tot);
 __global__ __launch_bounds__(64) void k_walk_sph_wave(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ recv,
     const NodeRec* __restrict__ nodes, const int32_t* __restrict__ child,
@@ -558,10 +564,15 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_force(
             vsig_out[o] = vs;
         }
     }
+    __shared__ unsigned long long nsh[SPH_DT / 64];
     nin = wave_sum(nin);
-    if (lane == 0) {
-        atomicAdd(&stat[2], nin);
-        if (wv == 0) atomicAdd(&stat[4], (unsigned long long)nG * (unsigned long long)npp);
+    if (lane == 0) nsh[wv] = nin;
+    __syncthreads();
+    if (tid == 0) {  // one update of the shared counters per group
+        unsigned long long t = 0;
+        for (int w = 0; w < SPH_DT / 64; w++) t += nsh[w];
+        atomicAdd(&stat[2], t);
+        atomicAdd(&stat[4], (unsigned long long)nG * (unsigned long long)npp);
     }
 }
 
@@ -595,6 +606,9 @@ int gx_sph_walk(gx_ctx* ctx, TreeSlot& T, ListSet& Ls, int ng, const int32_t* gr
                        (const NodeRec*)T.nodes.p, (const int32_t*)T.child.p, (const MomRec*)T.mom.p, rad, use_hmax, active,
                        SPH_RANGES, cnt, ptot, (unsigned long long*)tot, (int32_t*)Ls.pr_begin.p,
                        (int32_t*)Ls.pr_cum.p, ovf);
+    hipLaunchKernelGGL(k_group_totals, dim3(gx_blocks(ng, 256)), dim3(256), 0, st, ng, groups, recv,
+                       (const NodeRec*)T.nodes.p, nullptr, cnt, ptot, ovf, nullptr,
+                       (unsigned long long*)tot);
     GX_LAUNCH_CHECK(ctx);
     int64_t h[16];
     GX_HIP(ctx, hipMemcpyAsync(h, tot, 16 * sizeof(int64_t), hipMemcpyDeviceToHost, st));

@@ -126,15 +126,16 @@ __global__ __launch_bounds__(128) void k_walk_grav(
 // the same IEEE sequence, appends accepted cells and opened leaves to the
 // slots by ballot compaction and pushes the children of opened internal
 // nodes.  Lists come out in a different order than the stackless walk's (the
-// same sets).  Slot or stack overflow is counted in tot[4] (the caller then
-// builds the lists in two passes).
+// same sets).  Per group it writes the list sizes, an overflow flag (slot or
+// stack) and the deepest stack; k_group_totals then forms the totals (the
+// caller builds the lists in two passes when any group overflowed).
 #define GWALK_STACK 4096
 __global__ __launch_bounds__(64) void k_walk_grav_wave(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes,
     const int32_t* __restrict__ child, const double* __restrict__ box, double theta2,
     uint32_t* __restrict__ pc_cnt, uint32_t* __restrict__ pr_cnt, uint32_t* __restrict__ pp_tot,
-    unsigned long long* __restrict__ tot, int32_t* __restrict__ pc_list,
-    int32_t* __restrict__ pr_begin, int32_t* __restrict__ pr_cum, int cap_pc, int cap_pr) {
+    int32_t* __restrict__ pc_list, int32_t* __restrict__ pr_begin, int32_t* __restrict__ pr_cum,
+    int cap_pc, int cap_pr, uint8_t* __restrict__ gflag, int32_t* __restrict__ gdepth) {
     const int g = xcd_remap(blockIdx.x, ng);
     if (g >= ng) return;
     const int lane = threadIdx.x;
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(64) void k_walk_grav_wave(
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t pco = (int64_t)g * cap_pc, pro = (int64_t)g * cap_pr;
     if (lane == 0) stk[0] = 0;
-    int sp = 1, npc = 0, npr = 0, npp = 0, over = 0;
+    int sp = 1, npc = 0, npr = 0, npp = 0, over = 0, spmax = 1;
     __syncthreads();
     while (sp > 0 && !over) {
         const int take = sp < 64 ? sp : 64;
@@ -207,21 +208,68 @@ __global__ __launch_bounds__(64) void k_walk_grav_wave(
             const int coff = sp + cincl - nch;
             for (int k = 0; k < nch; k++) stk[coff + k] = ch[k];
             sp += ctot;
+            spmax = sp > spmax ? sp : spmax;
         }
         __syncthreads();
     }
     if (lane == 0) {
+        // per-group results only; k_group_totals forms the sums (one shared
+        // counter update per block instead of several per group)
         pc_cnt[g] = (uint32_t)npc;
         pr_cnt[g] = (uint32_t)npr;
         pp_tot[g] = (uint32_t)npp;
+        gflag[g] = (over || npc > cap_pc || npr > cap_pr) ? 1 : 0;
+        gdepth[g] = over ? GWALK_STACK + 1 : spmax;
+    }
+}
+
+// Totals of a set of per-group lists: tot[0] += sum c0, tot[1] += sum c1,
+// tot[2] += sum nG pp, tot[3] += sum nG c0, tot[4] += sum flag, and maxima
+// tot[5] = max c0, tot[6] = max c1, tot[7] = max depth (any input may be
+// NULL).  nG = receiver size (groups[g] of nodes, or recv[g]).
+__global__ __launch_bounds__(256) void k_group_totals(
+    int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ recv,
+    const NodeRec* __restrict__ nodes, const uint32_t* __restrict__ c0,
+    const uint32_t* __restrict__ c1, const uint32_t* __restrict__ pp,
+    const uint8_t* __restrict__ flag, const int32_t* __restrict__ depth,
+    unsigned long long* __restrict__ tot) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long s[5] = {0, 0, 0, 0, 0}, m[3] = {0, 0, 0};
+    if (g < ng) {
+        const NodeRec& G = recv ? recv[g] : nodes[groups[g]];
         const unsigned long long nG = (unsigned long long)(G.end - G.begin);
-        atomicAdd(&tot[2], nG * (unsigned long long)npp);
-        atomicAdd(&tot[3], nG * (unsigned long long)npc);
-        atomicAdd(&tot[0], (unsigned long long)npc);
-        atomicAdd(&tot[1], (unsigned long long)npr);
-        atomicMax(&tot[5], (unsigned long long)npc);
-        atomicMax(&tot[6], (unsigned long long)npr);
-        if (over || npc > cap_pc || npr > cap_pr) atomicAdd(&tot[4], 1ull);
+        const unsigned long long a = c0 ? c0[g] : 0, b = c1 ? c1[g] : 0, q = pp ? pp[g] : 0;
+        s[0] = a;
+        s[1] = b;
+        s[2] = nG * q;
+        s[3] = nG * a;
+        s[4] = flag ? flag[g] : 0;
+        m[0] = a;
+        m[1] = b;
+        m[2] = depth ? (unsigned long long)depth[g] : 0;
+    }
+    __shared__ unsigned long long sh[4][8];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 5; k++) {
+        const unsigned long long t = wave_sum(s[k]);
+        if (lane == 0) sh[wv][k] = t;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const unsigned long long t = wave_max(m[k]);
+        if (lane == 0) sh[wv][5 + k] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        const int k = threadIdx.x;
+        unsigned long long v = sh[0][k];
+        for (int w = 1; w < 4; w++) v = k < 5 ? v + sh[w][k] : (sh[w][k] > v ? sh[w][k] : v);
+        if (k < 5) {
+            if (v) atomicAdd(&tot[k], v);
+        } else {
+            atomicMax(&tot[k], v);
+        }
     }
 }
 
@@ -322,8 +370,8 @@ __global__ __launch_bounds__(128) void k_walk_sph(
 // intersecting internal nodes push their children (from the child table)
 // onto the next frontier in LDS.  Ranges come out level by level, not in key
 // order; consumers only rely on the running offsets.  A frontier or slot
-// overflow is reported in tot[4] (the caller then falls back to the
-// thread-per-group CSR walk).
+// overflow sets the group's ovf flag (the caller then builds that group's
+// list with the depth-first walks).
 #define BFS_FMAX 2048
 __global__ __launch_bounds__(64) void k_walk_sph_bfs(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ recv,
@@ -412,17 +460,11 @@ __global__ __launch_bounds__(64) void k_walk_sph_bfs(
         cnt = ncnt;
         cur ^= 1;
     }
-    if (lane == 0) {
+    if (lane == 0) {  // totals: k_group_totals over pr_cnt, pp_tot and ovf
         const bool bad = over || nout > cap;
         ovf[g] = bad ? 1 : 0;
         pr_cnt[g] = bad ? 0u : (uint32_t)nout;
         pp_tot[g] = bad ? 0u : (uint32_t)npp;
-        if (bad) {
-            atomicAdd(&tot[4], 1ull);
-        } else {
-            atomicAdd(&tot[2], (unsigned long long)(G.end - G.begin) * (unsigned long long)npp);
-            atomicAdd(&tot[1], (unsigned long long)nout);
-        }
     }
 }
 
