@@ -156,7 +156,13 @@ __global__ __launch_bounds__(64) void k_walk_grav_wave(
         sp = b0;
         bool acc = false, leaf = false, open = false;
         int b = 0, e = 0;
+        int4 cq0 = make_int4(-1, -1, -1, -1), cq1 = cq0;
         if (n >= 0) {
+            // the child row is fetched with the node record (not after the
+            // opening test) so the two loads overlap
+            const int4* cp = reinterpret_cast<const int4*>(child + 8 * (int64_t)n);
+            cq0 = cp[0];
+            cq1 = cp[1];
             const NodeRec& nd = nodes[n];
             double lo[3] = {nd.lo[0], nd.lo[1], nd.lo[2]};
             double hi[3] = {nd.hi[0], nd.hi[1], nd.hi[2]};
@@ -192,13 +198,10 @@ __global__ __launch_bounds__(64) void k_walk_grav_wave(
         npp += __shfl(incl, 63, 64);
         // opened internal nodes: children onto the stack
         int nch = 0;
-        int32_t ch[8];
+        const int32_t ch[8] = {cq0.x, cq0.y, cq0.z, cq0.w, cq1.x, cq1.y, cq1.z, cq1.w};
         if (open) {
 #pragma unroll
-            for (int k = 0; k < 8; k++) {
-                ch[k] = child[8 * (int64_t)n + k];
-                nch += ch[k] >= 0;
-            }
+            for (int k = 0; k < 8; k++) nch += ch[k] >= 0;
         }
         const int cincl = wave_incl_scan(nch);
         const int ctot = __shfl(cincl, 63, 64);
@@ -405,8 +408,12 @@ __global__ __launch_bounds__(64) void k_walk_sph_bfs(
             const int idx = base + lane;
             bool inter = false, leaf = false;
             int n = -1, b = 0, e = 0;
+            int4 cq0 = make_int4(-1, -1, -1, -1), cq1 = cq0;
             if (idx < cnt) {
                 n = fr[cur][idx];
+                const int4* cp = reinterpret_cast<const int4*>(child + 8 * (int64_t)n);
+                cq0 = cp[0];
+                cq1 = cp[1];
                 const NodeRec& nd = nodes[n];
                 double lo[3] = {nd.lo[0], nd.lo[1], nd.lo[2]};
                 double hi[3] = {nd.hi[0], nd.hi[1], nd.hi[2]};
@@ -437,13 +444,10 @@ __global__ __launch_bounds__(64) void k_walk_sph_bfs(
             npp += __shfl(incl, 63, 64);
             // open internal nodes
             int nch = 0;
-            int32_t ch[8];
+            const int32_t ch[8] = {cq0.x, cq0.y, cq0.z, cq0.w, cq1.x, cq1.y, cq1.z, cq1.w};
             if (inter && !leaf) {
 #pragma unroll
-                for (int k = 0; k < 8; k++) {
-                    ch[k] = child[8 * (int64_t)n + k];
-                    nch += ch[k] >= 0;
-                }
+                for (int k = 0; k < 8; k++) nch += ch[k] >= 0;
             }
             const int cincl = wave_incl_scan(nch);
             const int coff = ncnt + cincl - nch;
@@ -515,7 +519,11 @@ __global__ __launch_bounds__(64) void k_walk_sph_wave(
         sp = b0;
         bool inter = false, leaf = false;
         int b = 0, e = 0;
+        int4 cq0 = make_int4(-1, -1, -1, -1), cq1 = cq0;
         if (n >= 0) {
+            const int4* cp = reinterpret_cast<const int4*>(child + 8 * (int64_t)n);
+            cq0 = cp[0];
+            cq1 = cp[1];
             const NodeRec& nd = nodes[n];
             double lo[3] = {nd.lo[0], nd.lo[1], nd.lo[2]};
             double hi[3] = {nd.hi[0], nd.hi[1], nd.hi[2]};
@@ -542,13 +550,10 @@ __global__ __launch_bounds__(64) void k_walk_sph_wave(
         nout += __popcll(em);
         npp += __shfl(incl, 63, 64);
         int nch = 0;
-        int32_t ch[8];
+        const int32_t ch[8] = {cq0.x, cq0.y, cq0.z, cq0.w, cq1.x, cq1.y, cq1.z, cq1.w};
         if (inter && !leaf) {
 #pragma unroll
-            for (int k = 0; k < 8; k++) {
-                ch[k] = child[8 * (int64_t)n + k];
-                nch += ch[k] >= 0;
-            }
+            for (int k = 0; k < 8; k++) nch += ch[k] >= 0;
         }
         const int cincl = wave_incl_scan(nch);
         const int ctot = __shfl(cincl, 63, 64);
