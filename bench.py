@@ -48,8 +48,8 @@ FLOP_PC = 63                         # per particle-cell interaction, monopole +
 # known size (hbm_calib.py: FETCH_SIZE reads half the bytes copied, WRITE_SIZE
 # all of them).  Valid only for the kernel source with this SHA-256; any
 # change to gx_gravity.hip makes the bench report null until remeasured.
-GRAV_TRAFFIC = {"source_sha256": "9e4e64d9fbd0436098543b955de8dccd3038bd57bbf5da38418ebee55995c732",
-                "fetch_kib": 4231431.0, "write_kib": 2004637.375,
+GRAV_TRAFFIC = {"source_sha256": "50fc688e0d0613a2daee320263c644c1817ca54ed45e4bad78e112a8c6ef1fd9",
+                "fetch_kib": 4235088.6875, "write_kib": 2004601.53125,
                 "fetch_scale": 2.0, "write_scale": 1.0}
 
 

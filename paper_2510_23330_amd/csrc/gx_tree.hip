@@ -240,18 +240,24 @@ __global__ __launch_bounds__(256) void k_node_emit(int64_t n, const uint64_t* __
             lo = end;
         }
     }
-    // per-level id lists, one atomic per wave and level
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int l = 0; l <= GX_MAX_LEVEL; l++) {
-        const bool part = has && l >= lstart && l <= Li;
-        const uint64_t mk = __ballot(part);
-        if (mk == 0) continue;
-        const int leader = __ffsll((unsigned long long)mk) - 1;
-        uint32_t b0 = 0;
-        if (lane == leader) b0 = atomicAdd(&lvl_fill[l], (uint32_t)__popcll(mk));
-        b0 = __shfl(b0, leader, 64);
-        if (part) lvl_ids[lvl_off[l] + b0 + __popcll(mk & lt)] = (int32_t)(bi + (l - lstart));
+    // per-level id lists: slots counted in LDS per workgroup, then one global
+    // counter update per workgroup and level (the level counters are shared
+    // by the whole grid, so per-wave or per-node updates would serialise)
+    __shared__ uint32_t lcnt[GX_MAX_LEVEL + 1], lbase[GX_MAX_LEVEL + 1];
+    if (threadIdx.x <= GX_MAX_LEVEL) lcnt[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t slot[GX_MAX_LEVEL + 1];
+    if (has)
+        for (int l = lstart; l <= Li; l++) slot[l] = atomicAdd(&lcnt[l], 1u);
+    __syncthreads();
+    if (threadIdx.x <= GX_MAX_LEVEL) {
+        const uint32_t c = lcnt[threadIdx.x];
+        lbase[threadIdx.x] = c ? atomicAdd(&lvl_fill[threadIdx.x], c) : 0u;
     }
+    __syncthreads();
+    if (has)
+        for (int l = lstart; l <= Li; l++)
+            lvl_ids[lvl_off[l] + lbase[l] + slot[l]] = (int32_t)(bi + (l - lstart));
 }
 
 // Parent of every node and the (up to 8) children of every internal node in
