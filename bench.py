@@ -41,6 +41,8 @@ PEAK_FP32 = 157.3e12                 # MI355X FP32 vector, FLOP/s
 HBM_PEAK = 8.0e12                    # B/s
 FLOP_PP = 27                         # per particle-particle interaction (Table 4 convention)
 FLOP_PC = 63                         # per particle-cell interaction, monopole + quadrupole
+FLOP_DENS = 73                       # per SPH density candidate pair evaluation (Table 4)
+FLOP_FORCE = 101                     # per SPH force candidate pair (Table 4)
 
 # HBM traffic of one k_grav_force<float,true> launch on this workload, from two
 # rocprofv3 --pmc runs of this script (FETCH_SIZE, WRITE_SIZE in KiB per
@@ -203,6 +205,8 @@ def main():
     per = []
     grav_ms, grav_kernel_ms, dens_ms, hydro_ms, tree_ms = [], [], [], [], []
     n_pp = n_pc = n_sph = 0
+    dens_k_ms, hydro_k_ms, dens_it = [], [], []
+    n_dens_eval = n_force_list = n_force_ngb = 0
     energies = []
     walk_diag = []
     torch.cuda.synchronize()
@@ -222,6 +226,12 @@ def main():
         n_pp += st["gravity"]["n_pp"]
         n_pc += st["gravity"]["n_pc"]
         n_sph += st["density"]["n_sph_list"] + st["hydro"]["n_sph_list"]
+        dens_k_ms.append(st["density"]["ms_kernel"])
+        hydro_k_ms.append(st["hydro"]["ms_kernel"])
+        dens_it.append(st["density"]["n_iter_max"])
+        n_dens_eval += st["density"]["n_sph_list"]
+        n_force_list += st["hydro"]["n_sph_list"]
+        n_force_ngb += st["hydro"]["n_sph_ngb"]
         log(f"[bench] step {k}: {per[-1] * 1e3:.1f} ms")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
@@ -263,6 +273,16 @@ def main():
         "sn_coupling": None if coupling is None else dict(coupling.stats, sites_per_step=args.sn_sites,
                                                           delay_steps=50),
         "gravity_kernel_interactions_per_s": inter_step / kernel_s,
+        "sph": {"density_pair_evals_per_step": n_dens_eval / args.steps,
+                "density_kernel_ms": float(np.mean(dens_k_ms)),
+                "density_tflops_73": FLOP_DENS * n_dens_eval / args.steps
+                / (float(np.mean(dens_k_ms)) / 1e3) / 1e12,
+                "density_max_iterations": int(max(dens_it)),
+                "force_list_pairs_per_step": n_force_list / args.steps,
+                "force_ngb_pairs_per_step": n_force_ngb / args.steps,
+                "force_kernel_ms": float(np.mean(hydro_k_ms)),
+                "force_tflops_101": FLOP_FORCE * n_force_list / args.steps
+                / (float(np.mean(hydro_k_ms)) / 1e3) / 1e12},
         "gravity_lists": {"two_pass_steps": int(sum(w[0] for w in walk_diag)),
                           "max_walk_stack": int(max(w[1] for w in walk_diag))},
         "energy_drift_rel": abs(E1 - E0) / abs(E0),

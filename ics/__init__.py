@@ -135,6 +135,30 @@ def lattice(nside: int = 24, spacing: float = 1.0, jitter: float = 0.0,
                  u=np.full(n, u))
 
 
+def slab_and_sparse(n_slab: int = 12000, n_sparse: int = 24, seed: int = 11,
+                    height: float = 0.5, thickness: float = 0.02, sigma: float = 0.05):
+    """Dense gas slab with a few sparse particles above and below it.
+
+    n_slab particles uniform in [0, 1]^2 x [-thickness/2, thickness/2];
+    n_sparse particles uniform in [0, 1]^2 at z = +-height (half on each
+    side).  The sparse particles' kernels reach into the slab, so the
+    candidate lists of their groups cover most of it.  Equal masses,
+    Gaussian velocities of standard deviation sigma, unit internal energy.
+    """
+    rng = _rng(seed)
+    xs = rng.uniform(0.0, 1.0, (2, n_slab))
+    zs = rng.uniform(-0.5 * thickness, 0.5 * thickness, n_slab)
+    xp = rng.uniform(0.0, 1.0, (2, n_sparse))
+    zp = np.where(np.arange(n_sparse) % 2 == 0, height, -height)
+    x = np.concatenate([xs[0], xp[0]])
+    y = np.concatenate([xs[1], xp[1]])
+    z = np.concatenate([zs, zp])
+    n = x.size
+    v = rng.normal(0.0, sigma, (3, n))
+    return _pack(x, y, z, v[0], v[1], v[2], np.full(n, 1.0 / n),
+                 np.full(n, 1e-6), np.full(n, T_GAS), u=np.full(n, 1.0))
+
+
 def _cyl_disk(rng, n, rd, zd, rmax):
     R = rng.gamma(2.0, rd, n)
     bad = R > rmax

@@ -64,7 +64,8 @@ enum {
 typedef struct {
     int64_t n_pp;        /* particle-particle interactions (self pairs included) */
     int64_t n_pc;        /* particle-cell interactions */
-    int64_t n_sph_list;  /* SPH candidate pairs evaluated (list length x receivers) */
+    int64_t n_sph_list;  /* SPH candidate pairs evaluated: list length x receivers, and
+                            for the density summed over all kernel-size passes */
     int64_t n_sph_ngb;   /* SPH pairs inside the kernel support */
     int64_t n_groups;    /* receiving groups */
     int64_t n_nodes;     /* tree nodes */

@@ -239,6 +239,67 @@ struct GroupList {
     }
 };
 
+// First range of a group list that overlaps list position ch: the last range
+// whose running offset is <= ch (offsets increase strictly), by bisection.
+__device__ __forceinline__ int64_t first_range(const GroupList& L, int ch) {
+    int64_t lo = L.r0, hi = L.r1 - 1;
+    if (hi < lo) return lo;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (L.cum[mid] <= ch) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Particle slot of every position ch .. che-1 of a group's candidate list,
+// computed by the whole block (every thread must call it; it synchronises).
+// The ranges touching the chunk are read in parallel, one thread per range:
+// each marks its first position with its range number and records its slot
+// offset; a block-wide running maximum then carries the range number to every
+// position it covers.  On return slot[k - ch] holds the particle slot of list
+// position k.  LDS scratch: slot and roff hold che - ch ints, wtot one int
+// per wave of the block.
+__device__ __forceinline__ void list_slots(const GroupList& L, int npp, int ch, int che,
+                                           int* slot, int* roff, int* wtot, int tid,
+                                           int nthreads) {
+    const int n = che - ch;
+    for (int i = tid; i < n; i += nthreads) slot[i] = -1;
+    __syncthreads();
+    const int64_t ra = first_range(L, ch);
+    for (int64_t r = ra + tid; r < L.r1; r += nthreads) {
+        const int c = L.cum[r];
+        if (c >= che) break;  // later ranges of this thread start later still
+        const int rl = (int)(r - ra);
+        if (rl < n) {  // non-empty ranges: at most one per position
+            roff[rl] = L.begin[r] - c;
+            atomicMax(&slot[max(c, ch) - ch], rl);
+        }
+    }
+    __syncthreads();
+    // running maximum: contiguous segments per thread, then across lanes and waves
+    const int per = (n + nthreads - 1) / nthreads;
+    const int b0 = min(n, tid * per), b1 = min(n, b0 + per);
+    int run = -1;
+    for (int i = b0; i < b1; i++) run = max(run, slot[i]);
+    const int lane = tid & 63, wv = tid >> 6;
+    int v = run;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o, 64);
+        if (lane >= o) v = max(v, t);
+    }
+    if (lane == 63) wtot[wv] = v;
+    __syncthreads();
+    int cur = __shfl_up(v, 1, 64);
+    if (lane == 0) cur = -1;
+    for (int w = 0; w < wv; w++) cur = max(cur, wtot[w]);
+    for (int i = b0; i < b1; i++) {
+        cur = max(cur, slot[i]);
+        slot[i] = ch + i + roff[cur];
+    }
+    __syncthreads();
+}
+
 // Build candidate lists for ng receivers (tree groups `groups`, or boxes
 // `recv` when non-null) on a tree slot: leaves within max(rad[g], node hmax
 // when use_hmax) of the receiver box.

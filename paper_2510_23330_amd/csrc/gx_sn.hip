@@ -394,7 +394,7 @@ __global__ __launch_bounds__(64) void k_voxelize(
     if (g >= nbv) return;
     __shared__ float tx[VOX_TILE], ty[VOX_TILE], tz[VOX_TILE], tm[VOX_TILE], th[VOX_TILE],
         tT[VOX_TILE], tvx[VOX_TILE], tvy[VOX_TILE], tvz[VOX_TILE];
-    __shared__ int32_t jidx[VOX_TILE];
+    __shared__ int jidx[VOX_TILE], jroff[VOX_TILE], wtot[1];
     const int lane = threadIdx.x;
     const NodeRec B = recv[g];
     const double cx = (B.lo[0] + B.hi[0]) * 0.5, cy = (B.lo[1] + B.hi[1]) * 0.5,
@@ -406,20 +406,10 @@ __global__ __launch_bounds__(64) void k_voxelize(
     const GroupList GL(L, g);
     const int npp = GL.npp;
     float sr = 0, sw = 0, stt = 0, svx = 0, svy = 0, svz = 0;
-    int64_t rr = GL.r0;
     for (int t0 = 0; t0 < npp; t0 += VOX_TILE) {
         const int tn = min(VOX_TILE, npp - t0);
         __syncthreads();
-        for (int64_t r = rr; r < GL.r1; r++) {
-            const int c = GL.cum[r];
-            if (c >= t0 + tn) break;
-            const int cn = (r + 1 < GL.r1) ? GL.cum[r + 1] : npp;
-            const int b = GL.begin[r];
-            const int lo = max(c, t0), hi = min(cn, t0 + tn);
-            for (int q = lo + lane; q < hi; q += 64) jidx[q - t0] = b + (q - c);
-        }
-        while (rr < GL.r1 && ((rr + 1 < GL.r1) ? GL.cum[rr + 1] : npp) <= t0 + tn) rr++;
-        __syncthreads();
+        list_slots(GL, npp, t0, t0 + tn, jidx, jroff, wtot, lane, 64);
         for (int e = lane; e < tn; e += 64) {
             const int j = jidx[e];
             const double4 p = pos4[j];

@@ -57,16 +57,24 @@ __global__ __launch_bounds__(64) void k_walk_sph_wave(
 #define SPH_THREADS 64
 #define SPH_DT 256         // threads of the density and force kernels (4 waves per group)
 #define SPH_CAP 2048       // candidates kept in LDS by the density kernel
-#define SPH_TILE 256       // force kernel source tile
+#define SPH_TILE 256       // force kernel source tile (<= 256: hit lists hold 8-bit indices)
 #define SPH_RANGES 1024    // capacity of a block's candidate range list (single-pass walk)
 #define SPH_MARGIN 1.15f   // density search radius = margin x largest kernel size
+#define SPH_HCAP 32        // per-lane hit list entries (density; candidate indices)
+#define SPH_FCAP 32        // per-lane hit list entries (force; tile indices)
+#define SPH_KAPPA 1.02f    // density hit lists hold candidates within kappa x kernel size
 
 // 495 / (32 pi), (4 pi / 3) * 495 / (32 pi) = 495 / 24, 1155 / (4 pi)
 #define WC4_NORM 4.9238032806262495f
 #define NEFF_C 20.625f
 #define GRADW_C 91.91197457030109f
 
-enum { W_H = 0, W_RAD, W_ACT, W_FLAG, W_VEL, W_SPH, W_STAT };
+enum {
+    W_H = 0, W_RAD, W_ACT, W_FLAG, W_VEL, W_SPH, W_STAT,
+    // long-list groups: chunk counts, item offsets, group list, items, Newton
+    // state per slot, partial sums, finished flags
+    W_HV, W_HOFF, W_HLIST, W_ITEM, W_HST, W_PART, W_PARTV, W_GD
+};
 
 static int work(gx_ctx* ctx, int k, size_t bytes, void** p) {
     GX_TRY(gx_reserve(ctx, ctx->sph_work[k], bytes));
@@ -143,59 +151,177 @@ __device__ __forceinline__ T slice_sum(T v, int pad) {
     return v;
 }
 
-// First range of a group list that overlaps candidate position ch: the last
-// range whose running offset is <= ch (offsets increase strictly), found by
-// bisection so that expanding one chunk of a long list costs O(log R) plus
-// the ranges the chunk touches.
-__device__ __forceinline__ int64_t first_range(const GroupList& L, int ch) {
-    int64_t lo = L.r0, hi = L.r1 - 1;
-    if (hi < lo) return lo;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        if (L.cum[mid] <= ch) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
+// Candidates ch .. che-1 of a group's list into LDS as FP32 positions
+// relative to the group centre and masses (whole block; synchronises).
 __device__ __forceinline__ void expand_chunk(const GroupList& L, int npp, int ch, int che,
                                              const double4* __restrict__ pos4, double cx,
                                              double cy, double cz, float4* __restrict__ cand,
-                                             int tid, int nthreads) {
-    for (int64_t r = first_range(L, ch); r < L.r1; r++) {
-        const int c = L.cum[r];
-        const int cn = (r + 1 < L.r1) ? L.cum[r + 1] : npp;
-        if (cn <= ch) continue;
-        if (c >= che) break;
-        const int b = L.begin[r];
-        const int lo = max(c, ch), hi = min(cn, che);
-        for (int k = lo + tid; k < hi; k += nthreads) {
-            const double4 p = pos4[b + (k - c)];
-            cand[k - ch] = make_float4((float)(p.x - cx), (float)(p.y - cy), (float)(p.z - cz),
-                                       (float)p.w);
+                                             int* slot, int* roff, int* wtot, int tid,
+                                             int nthreads) {
+    list_slots(L, npp, ch, che, slot, roff, wtot, tid, nthreads);
+    for (int k = tid; k < che - ch; k += nthreads) {
+        const double4 p = pos4[slot[k]];
+        cand[k] = make_float4((float)(p.x - cx), (float)(p.y - cy), (float)(p.z - cz),
+                              (float)p.w);
+    }
+}
+
+// Kernel sums s0 = sum m W-shape and s1 = sum m q^2 (1 + 5q) (1 - q)^5 over
+// the candidates of one lane's hit list, in list order.
+__device__ __forceinline__ void dens_hits(const uint16_t (*hl)[SPH_DT], int nh, int tid,
+                                          const float4* __restrict__ cand, float xi, float yi,
+                                          float zi, float Hinv2, float& s0, float& s1) {
+    for (int j = 0; j < nh; j++) {
+        const float4 c = cand[hl[j][tid]];
+        const float dx = c.x - xi, dy = c.y - yi, dz = c.z - zi;
+        const float q2 = (dx * dx + dy * dy + dz * dz) * Hinv2;
+        if (q2 < 1.0f) {
+            const float q = __builtin_amdgcn_sqrtf(q2);
+            const float t = 1.0f - q;
+            const float t2 = t * t;
+            const float t5 = t2 * t2 * t;
+            const float poly = 1.0f + q * (6.0f + q * (35.0f / 3.0f));
+            s0 += c.w * t5 * t * poly;
+            s1 += c.w * q2 * (1.0f + 5.0f * q) * t5;
         }
     }
 }
 
-// Kernel size and density: one 256-thread workgroup per group; the group's
-// candidates sit once in LDS and are shared by its four waves.  The threads
-// form 256 / pad slices (pad >= nG lanes each, every receiver once per
-// slice); a slice sums its share of the candidates, the shares are combined
-// by shuffles inside a wave and through LDS across waves (fixed order), and
-// every copy of a receiver then takes the same safeguarded Newton step.
+// One lane's pass over candidates sl, sl + nsl, ... of cand[0, n): those
+// within sqrt(lim) go to its hit list (flushed into the sums whenever some
+// lane of the wave is near capacity).  Returns true when a flush happened,
+// i.e. the list left behind is not complete.  Every lane of the wave runs
+// the same number of steps.
+__device__ __forceinline__ bool dens_scan(uint16_t (*hl)[SPH_DT], int& nh, int tid, int sl, int nsl,
+                                          int n, bool act, const float4* __restrict__ cand,
+                                          float xi, float yi, float zi, float lim, float Hinv2,
+                                          float& s0, float& s1) {
+    nh = 0;
+    bool flushed = false;
+    const int nst = (n + nsl - 1) / nsl;
+    for (int m = 0; m < nst; m += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int k = sl + (m + u) * nsl;
+            const float4 c = cand[min(k, n - 1)];
+            const float dx = c.x - xi, dy = c.y - yi, dz = c.z - zi;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            hl[nh][tid] = (uint16_t)k;  // kept only if counted
+            nh += (act && k < n && r2 < lim) ? 1 : 0;
+        }
+        if (__ballot(nh > SPH_HCAP - 4)) {  // wave-uniform flush
+            dens_hits(hl, nh, tid, cand, xi, yi, zi, Hinv2, s0, s1);
+            nh = 0;
+            flushed = true;
+        }
+    }
+    return flushed;
+}
+
+// One safeguarded Newton step on N_eff(H) = n_ngb from the kernel sums at H:
+// the bracket [lo, hi] shrinks to H's side, the Newton iterate is kept when
+// inside it, else bisection (or doubling while no upper bound exists).
+// Done on |N_eff - n_ngb| <= tol, at max_iter evaluations, or when the next
+// kernel size exceeds the list radius Rlim (over: the list must be redone).
+__device__ __forceinline__ void newton_step(float s0, float s1, float mi, float n_ngb, float tol,
+                                            int max_iter, float Rlim, float& H, float& lo,
+                                            float& hi, float& S0, int& it, bool& done, bool& conv,
+                                            bool& over) {
+    it++;
+    S0 = s0;
+    const float neff = NEFF_C * s0 / mi;
+    const float f = neff - n_ngb;
+    if (fabsf(f) <= tol) {
+        done = true;
+        conv = true;
+    } else if (it >= max_iter) {
+        done = true;
+    } else {
+        const float dn = NEFF_C * (56.0f / 3.0f) * s1 / (mi * H);
+        if (f < 0.0f) lo = H;
+        else hi = H;
+        float Hn = dn > 0.0f ? H - f / dn : NAN;
+        if (!(Hn > lo && Hn < hi)) Hn = (hi < INFINITY) ? 0.5f * (lo + hi) : 2.0f * H;
+        if (Hn > Rlim) {
+            done = true;
+            over = true;
+        }
+        H = Hn;
+    }
+}
+
+// Outputs of a converged (or capped) receiver in sorted slot s.
+__device__ __forceinline__ void dens_write(int s, float H, float S0, const uint32_t* __restrict__ perm,
+                                           const double* __restrict__ u, float gamma,
+                                           double* __restrict__ H64, float* __restrict__ Hout,
+                                           float* __restrict__ rho_out, float* __restrict__ P_out,
+                                           float* __restrict__ cs_out) {
+    const uint32_t o = perm[s];
+    const float rho = WC4_NORM / (H * H * H) * S0;
+    const double uu = u[o];
+    H64[o] = (double)H;
+    Hout[o] = H;
+    rho_out[o] = rho;
+    if (P_out) P_out[o] = (float)((double)(gamma - 1.0f) * (double)rho * uu);
+    if (cs_out) cs_out[o] = (float)sqrt((double)gamma * (gamma - 1.0f) * uu);
+}
+
+// Per-group results: the list-redo flag and radius, iteration maximum and
+// non-converged count, evaluated pairs (one update of each shared counter).
+__device__ __forceinline__ void dens_group_stats(int g, int nflag, int nfail, int worst_it,
+                                                 float hmax, unsigned long long evals,
+                                                 uint32_t* __restrict__ flags,
+                                                 float* __restrict__ rad,
+                                                 unsigned long long* __restrict__ stat) {
+    flags[g] = nflag ? 1u : 0u;
+    atomicMax(&stat[1], (unsigned long long)worst_it);
+    atomicAdd(&stat[5], evals);
+    if (nflag) {
+        rad[g] = hmax * SPH_MARGIN;
+        atomicAdd(&stat[3], 1ull);
+    } else {  // counted once, in the group's final round
+        atomicAdd(&stat[0], (unsigned long long)nfail);
+    }
+}
+
+// Kernel size and density: one 256-thread workgroup per group whose
+// candidate list fits in LDS (longer lists are marked in hv and take the
+// chunked path below).  The group's candidates sit once in LDS and are
+// shared by its four waves.  The threads form 256 / pad slices (pad >= nG
+// lanes each, every receiver once per slice); slice sl takes candidates sl,
+// sl + nsl, ...  A lane tests its candidates against kappa x its kernel size
+// and appends the ones inside to a hit list in LDS, then evaluates the kernel
+// on the list only; a complete list is reused by later Newton passes while
+// the kernel size stays within kappa x the size it was built for.  The
+// slices' sums are combined by shuffles inside a wave and through LDS across
+// waves (fixed order), and every copy of a receiver then takes the same
+// safeguarded Newton step.
 __global__ __launch_bounds__(SPH_DT) void k_sph_density(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes,
     const double4* __restrict__ pos4, const uint32_t* __restrict__ perm,
     const uint8_t* __restrict__ active, ListView L, float* __restrict__ rad, float n_ngb, float tol,
-    int max_iter, float* __restrict__ Hs, uint32_t* __restrict__ flags,
+    int max_iter, float* __restrict__ Hs, uint32_t* __restrict__ flags, uint32_t* __restrict__ hv,
     unsigned long long* __restrict__ stat, const double* __restrict__ u, float gamma,
     double* __restrict__ H64, float* __restrict__ Hout, float* __restrict__ rho_out,
     float* __restrict__ P_out, float* __restrict__ cs_out) {
     const int g = xcd_remap(blockIdx.x, ng);
     if (g >= ng) return;
     if (active && !active[g]) return;
+    const GroupList GL(L, g);
+    const int npp = GL.npp;
+    if (npp > SPH_CAP) {  // long list: chunked over several workgroups
+        if (threadIdx.x == 0) hv[g] = (uint32_t)((npp + SPH_CAP - 1) / SPH_CAP);
+        return;
+    }
     __shared__ float4 cand[SPH_CAP];
     __shared__ float2 red[SPH_DT / 64][64];
+    // hit lists; the list expansion uses the same space (slot + range
+    // offsets) before the lists are built
+    __shared__ __align__(16) uint16_t hl[SPH_HCAP][SPH_DT];
+    __shared__ int wtot[SPH_DT / 64];
+    static_assert(sizeof(hl) >= 2 * SPH_CAP * sizeof(int), "expansion scratch");
+    int* const xslot = reinterpret_cast<int*>(&hl[0][0]);
+    int* const xroff = xslot + SPH_CAP;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const NodeRec B = nodes[groups[g]];
     const int nG = B.end - B.begin;
@@ -203,15 +329,13 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density(
     const double cx = (B.lo[0] + B.hi[0]) * 0.5;
     const double cy = (B.lo[1] + B.hi[1]) * 0.5;
     const double cz = (B.lo[2] + B.hi[2]) * 0.5;
-    const GroupList GL(L, g);
-    const int npp = GL.npp;
     const float Rlim = rad[g];
-    const bool in_lds = npp <= SPH_CAP;
-    if (in_lds) expand_chunk(GL, npp, 0, npp, pos4, cx, cy, cz, cand, tid, SPH_DT);
+    expand_chunk(GL, npp, 0, npp, pos4, cx, cy, cz, cand, xslot, xroff, wtot, tid, SPH_DT);
     __syncthreads();
 
     int nflag = 0, nfail = 0, worst_it = 0;
     float hmax = 0.0f;
+    unsigned long long evals = 0;  // receiver x candidate evaluations, all passes
     for (int ic = 0; ic < nG; ic += pad) {
         const int s = B.begin + ic + il;
         const bool act = ic + il < nG;
@@ -227,35 +351,22 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density(
         float lo = 0.0f, hi = INFINITY, S0 = 0.0f;
         bool done = !act, conv = false, over = false;
         int it = 0;
+        const unsigned long long pass_evals = (unsigned long long)min(pad, nG - ic) * npp;
+        float Hb = 0.0f;    // kernel size this lane's hit list was built for
+        int nh = 0;         // entries in this lane's hit list
+        bool have = false;  // every lane of the block holds a complete list
         for (;;) {
+            evals += pass_evals;
             const float Hinv = 1.0f / H, Hinv2 = Hinv * Hinv;
             float s0 = 0.0f, s1 = 0.0f;
-            for (int ch = 0; ch < npp; ch += SPH_CAP) {
-                const int che = min(npp, ch + SPH_CAP);
-                if (!in_lds) {
-                    __syncthreads();
-                    expand_chunk(GL, npp, ch, che, pos4, cx, cy, cz, cand, tid, SPH_DT);
-                    __syncthreads();
-                }
-                const int cnt = che - ch;
-                const int per = (cnt + nsl - 1) / nsl;
-                const int kb = sl * per, ke = min(cnt, kb + per);
-#pragma unroll 4
-                for (int k = kb; k < ke; k++) {
-                    const float4 c = cand[k];
-                    const float dx = c.x - xi, dy = c.y - yi, dz = c.z - zi;
-                    const float q2 = (dx * dx + dy * dy + dz * dz) * Hinv2;
-                    if (q2 < 1.0f) {
-                        const float q = __builtin_sqrtf(q2);
-                        const float t = 1.0f - q;
-                        const float t2 = t * t;
-                        const float t5 = t2 * t2 * t;
-                        const float poly = 1.0f + q * (6.0f + q * (35.0f / 3.0f));
-                        s0 += c.w * t5 * t * poly;
-                        s1 += c.w * q2 * (1.0f + 5.0f * q) * t5;
-                    }
-                }
+            const bool stale = __syncthreads_or(act && H > SPH_KAPPA * Hb);
+            if (!have || stale) {
+                Hb = H;
+                const bool flushed = dens_scan(hl, nh, tid, sl, nsl, npp, act, cand, xi, yi, zi,
+                                               (SPH_KAPPA * SPH_KAPPA) * H * H, Hinv2, s0, s1);
+                have = !__syncthreads_or(flushed);
             }
+            dens_hits(hl, nh, tid, cand, xi, yi, zi, Hinv2, s0, s1);
             // slices of this wave, then the four waves in order
             s0 = slice_sum(s0, pad);
             s1 = slice_sum(s1, pad);
@@ -269,30 +380,9 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density(
                 s0 += r.x;
                 s1 += r.y;
             }
-            if (!done) {
-                it++;
-                S0 = s0;
-                const float neff = NEFF_C * s0 / mi;
-                const float f = neff - n_ngb;
-                if (fabsf(f) <= tol) {
-                    done = true;
-                    conv = true;
-                } else if (it >= max_iter) {
-                    done = true;
-                } else {
-                    const float dn = NEFF_C * (56.0f / 3.0f) * s1 / (mi * H);
-                    if (f < 0.0f) lo = H;
-                    else hi = H;
-                    float Hn = dn > 0.0f ? H - f / dn : NAN;
-                    if (!(Hn > lo && Hn < hi)) Hn = (hi < INFINITY) ? 0.5f * (lo + hi) : 2.0f * H;
-                    if (Hn > Rlim) {
-                        // the list only covers kernel sizes up to Rlim: redo with a larger list
-                        done = true;
-                        over = true;
-                    }
-                    H = Hn;
-                }
-            }
+            if (!done)
+                newton_step(s0, s1, mi, n_ngb, tol, max_iter, Rlim, H, lo, hi, S0, it, done, conv,
+                            over);
             if (!__syncthreads_or(done ? 0 : 1)) break;
         }
         if (act && sl == 0) {
@@ -303,14 +393,7 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density(
                 nflag++;
             } else {
                 if (!conv) nfail++;
-                const uint32_t o = perm[s];
-                const float rho = WC4_NORM / (H * H * H) * S0;
-                const double uu = u[o];
-                H64[o] = (double)H;
-                Hout[o] = H;
-                rho_out[o] = rho;
-                if (P_out) P_out[o] = (float)((double)(gamma - 1.0f) * (double)rho * uu);
-                if (cs_out) cs_out[o] = (float)sqrt((double)gamma * (gamma - 1.0f) * uu);
+                dens_write(s, H, S0, perm, u, gamma, H64, Hout, rho_out, P_out, cs_out);
             }
         }
     }
@@ -319,16 +402,187 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density(
         nfail = (int)wave_sum((unsigned)nfail);
         worst_it = wave_max(worst_it);
         hmax = wave_max(hmax);
-        if (lane == 0) {
-            flags[g] = nflag ? 1u : 0u;
-            atomicMax(&stat[1], (unsigned long long)worst_it);
-            if (nflag) {
-                rad[g] = hmax * SPH_MARGIN;
-                atomicAdd(&stat[3], 1ull);
-            } else {  // counted once, in the group's final round
-                atomicAdd(&stat[0], (unsigned long long)nfail);
-            }
+        if (lane == 0) dens_group_stats(g, nflag, nfail, worst_it, hmax, evals, flags, rad, stat);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Long candidate lists: work items (group, chunk of SPH_CAP candidates)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_long_items(int ng, const uint32_t* __restrict__ hv,
+                                                    const int64_t* __restrict__ hoff,
+                                                    int2* __restrict__ items,
+                                                    int32_t* __restrict__ hlist,
+                                                    uint32_t* __restrict__ nh_ctr) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ng || hv[g] == 0) return;
+    hlist[atomicAdd(nh_ctr, 1u)] = g;
+    for (uint32_t c = 0; c < hv[g]; c++) items[hoff[g] + c] = make_int2(g, (int)c);
+}
+
+// Newton state of the receivers of long-list groups, per sorted slot:
+// {lo, hi, S0, it | done << 8 | conv << 9 | over << 10}.
+// Launched over at least as many blocks as there are long groups (nh[0]).
+__global__ __launch_bounds__(64) void k_long_init(const uint32_t* __restrict__ nh,
+                                                  const int32_t* __restrict__ hlist,
+                                                  const int32_t* __restrict__ groups,
+                                                  const NodeRec* __restrict__ nodes,
+                                                  float4* __restrict__ hst,
+                                                  uint8_t* __restrict__ gdone) {
+    if (blockIdx.x >= nh[0]) return;
+    const int g = hlist[blockIdx.x];
+    const NodeRec B = nodes[groups[g]];
+    const int il = threadIdx.x;
+    if (il == 0) gdone[g] = 0;
+    if (il < B.end - B.begin) hst[B.begin + il] = make_float4(0.0f, INFINITY, 0.0f, 0.0f);
+}
+
+// Partial kernel sums of one chunk of a long list at the receivers' current
+// kernel sizes (skipping finished receivers): same lanes, slices and hit
+// lists as k_sph_density, sums combined over slices and waves in a fixed
+// order and stored per (item, receiver).
+__global__ __launch_bounds__(SPH_DT) void k_sph_density_part(
+    const int2* __restrict__ items, const int32_t* __restrict__ groups,
+    const NodeRec* __restrict__ nodes, const double4* __restrict__ pos4, ListView L,
+    const float* __restrict__ Hs, const float4* __restrict__ hst,
+    const uint8_t* __restrict__ gdone, float2* __restrict__ part) {
+    const int2 item = items[blockIdx.x];
+    const int g = item.x;
+    if (gdone[g]) return;
+    __shared__ float4 cand[SPH_CAP];
+    __shared__ float2 red[SPH_DT / 64][64];
+    __shared__ __align__(16) uint16_t hl[SPH_HCAP][SPH_DT];
+    __shared__ int wtot[SPH_DT / 64];
+    int* const xslot = reinterpret_cast<int*>(&hl[0][0]);
+    int* const xroff = xslot + SPH_CAP;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const NodeRec B = nodes[groups[g]];
+    const int nG = B.end - B.begin;
+    const int pad = slice_pad(nG), nsl = SPH_DT / pad, il = tid % pad, sl = tid / pad;
+    const double cx = (B.lo[0] + B.hi[0]) * 0.5;
+    const double cy = (B.lo[1] + B.hi[1]) * 0.5;
+    const double cz = (B.lo[2] + B.hi[2]) * 0.5;
+    const GroupList GL(L, g);
+    const int npp = GL.npp;
+    const int ch = item.y * SPH_CAP, che = min(npp, ch + SPH_CAP);
+    expand_chunk(GL, npp, ch, che, pos4, cx, cy, cz, cand, xslot, xroff, wtot, tid, SPH_DT);
+    __syncthreads();
+    const int s = B.begin + il;
+    bool act = il < nG;
+    float xi = 0, yi = 0, zi = 0, H = 1.0f;
+    if (act) {
+        act = (__float_as_uint(hst[s].w) & 0x100u) == 0;  // not finished
+        const double4 p = pos4[s];
+        xi = (float)(p.x - cx);
+        yi = (float)(p.y - cy);
+        zi = (float)(p.z - cz);
+        H = Hs[s];
+    }
+    const float Hinv = 1.0f / H, Hinv2 = Hinv * Hinv;
+    float s0 = 0.0f, s1 = 0.0f;
+    int nh;
+    dens_scan(hl, nh, tid, sl, nsl, che - ch, act, cand, xi, yi, zi, H * H, Hinv2, s0, s1);
+    dens_hits(hl, nh, tid, cand, xi, yi, zi, Hinv2, s0, s1);
+    s0 = slice_sum(s0, pad);
+    s1 = slice_sum(s1, pad);
+    if (lane < pad) red[wv][lane] = make_float2(s0, s1);
+    __syncthreads();
+    if (tid < pad && il < nG) {
+        s0 = 0.0f;
+        s1 = 0.0f;
+#pragma unroll
+        for (int w = 0; w < SPH_DT / 64; w++) {
+            const float2 r = red[w][il];
+            s0 += r.x;
+            s1 += r.y;
         }
+        part[(int64_t)blockIdx.x * 64 + il] = make_float2(s0, s1);
+    }
+}
+
+// Newton step for the receivers of one long-list group (one wave): chunk
+// sums added in chunk order, then the step of k_sph_density; a group whose
+// receivers are all done writes its outputs and statistics.
+__global__ __launch_bounds__(64) void k_sph_density_long_step(
+    const uint32_t* __restrict__ nh, const int32_t* __restrict__ hlist,
+    const int32_t* __restrict__ groups,
+    const NodeRec* __restrict__ nodes, const double4* __restrict__ pos4, ListView L,
+    const uint32_t* __restrict__ hv, const int64_t* __restrict__ hoff,
+    const float2* __restrict__ part, float* __restrict__ rad, float n_ngb, float tol, int max_iter,
+    float* __restrict__ Hs, float4* __restrict__ hst, uint8_t* __restrict__ gdone,
+    uint32_t* __restrict__ flags, uint32_t* __restrict__ pending,
+    unsigned long long* __restrict__ stat, const uint32_t* __restrict__ perm,
+    const double* __restrict__ u, float gamma, double* __restrict__ H64,
+    float* __restrict__ Hout, float* __restrict__ rho_out, float* __restrict__ P_out,
+    float* __restrict__ cs_out) {
+    if (blockIdx.x >= nh[0]) return;
+    const int g = hlist[blockIdx.x];
+    if (gdone[g]) return;
+    const NodeRec B = nodes[groups[g]];
+    const int nG = B.end - B.begin;
+    const int il = threadIdx.x;
+    const bool act = il < nG;
+    const int s = B.begin + il;
+    const float Rlim = rad[g];
+    float H = 1.0f, lo = 0.0f, hi = INFINITY, S0 = 0.0f;
+    int it = 0;
+    bool done = true, conv = false, over = false;
+    if (act) {
+        const float4 st = hst[s];
+        const uint32_t bits = __float_as_uint(st.w);
+        lo = st.x;
+        hi = st.y;
+        S0 = st.z;
+        it = (int)(bits & 0xffu);
+        done = bits & 0x100u;
+        conv = bits & 0x200u;
+        over = bits & 0x400u;
+        H = Hs[s];
+        if (!done) {
+            float s0 = 0.0f, s1 = 0.0f;
+            const int64_t i0 = hoff[g];
+            for (uint32_t c = 0; c < hv[g]; c++) {
+                const float2 p = part[(i0 + c) * 64 + il];
+                s0 += p.x;
+                s1 += p.y;
+            }
+            const float mi = (float)pos4[s].w;
+            newton_step(s0, s1, mi, n_ngb, tol, max_iter, Rlim, H, lo, hi, S0, it, done, conv,
+                        over);
+            Hs[s] = H;
+            hst[s] = make_float4(lo, hi, S0,
+                                 __uint_as_float((uint32_t)it | (done ? 0x100u : 0u) |
+                                                 (conv ? 0x200u : 0u) | (over ? 0x400u : 0u)));
+        }
+    }
+    const bool all_done = __ballot(!done) == 0;
+    if (il == 0) {
+        const GroupList GL(L, g);
+        atomicAdd(&stat[5], (unsigned long long)nG * (unsigned long long)GL.npp);
+    }
+    if (!all_done) {
+        if (il == 0) atomicAdd(pending, 1u);
+        return;
+    }
+    int nflag = 0, nfail = 0, worst_it = 0;
+    float hmax = 0.0f;
+    if (act) {
+        hmax = H;
+        worst_it = it;
+        if (over) {
+            nflag = 1;
+        } else {
+            if (!conv) nfail = 1;
+            dens_write(s, H, S0, perm, u, gamma, H64, Hout, rho_out, P_out, cs_out);
+        }
+    }
+    nflag = (int)wave_sum((unsigned)nflag);
+    nfail = (int)wave_sum((unsigned)nfail);
+    worst_it = wave_max(worst_it);
+    hmax = wave_max(hmax);
+    if (il == 0) {
+        dens_group_stats(g, nflag, nfail, worst_it, hmax, 0ull, flags, rad, stat);
+        gdone[g] = 1;
     }
 }
 
@@ -401,18 +655,96 @@ __global__ __launch_bounds__(64) void k_group_hmax(int ng, const int32_t* __rest
     if (g < ng) rad[g] = mom[groups[g]].hmax;
 }
 
+static_assert(SPH_TILE <= 256, "force hit lists store 8-bit tile indices");
+static_assert(SPH_CAP <= 65536, "density hit lists store 16-bit candidate indices");
+
+// Pair terms of one lane's force hit list (tile indices, list order).
+struct ForceRecv {
+    float x, y, z, vx, vy, vz, Hinv, cw, rho, A, c;
+};
+
+__device__ __forceinline__ void force_hits(const uint8_t (*fl)[SPH_DT], int nh, int tid,
+                                           const float4* __restrict__ t0,
+                                           const float4* __restrict__ t1,
+                                           const float4* __restrict__ t2,
+                                           const float* __restrict__ tc, const ForceRecv& R,
+                                           float alpha, float& fx, float& fy, float& fz,
+                                           float& fu, float& vs) {
+    for (int j = 0; j < nh; j++) {
+        const int k = fl[j][tid];
+        const float4 a = t0[k];  // x, y, z, H^2
+        const float4 b = t1[k];  // vx, vy, vz, m
+        const float4 d = t2[k];  // 1/H, gradient constant, rho, A
+        const float cj = tc[k];
+        const float dx = a.x - R.x, dy = a.y - R.y, dz = a.z - R.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float rinv = __builtin_amdgcn_rsqf(r2);
+        const float r = r2 * rinv;
+        const float qi = r * R.Hinv, qj = r * d.x;
+        // (1 - q)^5 vanishes at the support edge: clamping t at 0 gives the
+        // same terms as a branch on q < 1
+        const float ti = fmaxf(1.0f - qi, 0.0f), tj = fmaxf(1.0f - qj, 0.0f);
+        const float ti2 = ti * ti, tj2 = tj * tj;
+        const float gi = R.cw * (1.0f + 5.0f * qi) * ti2 * ti2 * ti;
+        const float gj = d.y * (1.0f + 5.0f * qj) * tj2 * tj2 * tj;
+        const float dvx = b.x - R.vx, dvy = b.y - R.vy, dvz = b.z - R.vz;
+        const float vr = dvx * dx + dvy * dy + dvz * dz;
+        const float w = vr * rinv;
+        const float sig = R.c + cj - 3.0f * fminf(w, 0.0f);
+        const float Pi = w < 0.0f ? -alpha * sig * w / (R.rho + d.z) : 0.0f;
+        const float gbar = 0.5f * (gi + gj);
+        const float f = b.w * (R.A * gi + d.w * gj + Pi * gbar);
+        fx += f * dx;
+        fy += f * dy;
+        fz += f * dz;
+        fu += b.w * (R.A * gi + 0.5f * Pi * gbar) * vr;
+        vs = fmaxf(vs, sig);
+    }
+}
+
+// Hydro force: one 256-thread workgroup per group, candidates staged in LDS
+// tiles of SPH_TILE.  Lanes form slices as in the density kernel (slice sl
+// takes tile entries sl, sl + nsl, ...).  A lane tests its entries for
+// r < max(H_i, H_j), appends the pairs inside to a hit list in LDS (flushed
+// whenever some lane of the wave is near capacity) and evaluates the pair
+// terms on the list only.  FP32 sums per tile, FP64 across tiles, slices
+// combined by shuffles and across waves through LDS in a fixed order.
+//
+// PART = false: one workgroup per group over its whole list, results added
+// to the outputs; groups with lists longer than SPH_CAP are only marked in
+// hv (chunk counts).  PART = true: one workgroup per work item (group, chunk
+// of SPH_CAP candidates), FP64 partial sums and the chunk's largest signal
+// velocity stored per (item, receiver) for k_sph_force_long_sum.
+template <bool PART>
 __global__ __launch_bounds__(SPH_DT) void k_sph_force(
-    int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes,
-    const double4* __restrict__ pos4, const uint32_t* __restrict__ perm,
-    const double4* __restrict__ sv, const float4* __restrict__ ss, ListView L, float alpha,
-    double* __restrict__ ax, double* __restrict__ ay, double* __restrict__ az,
-    double* __restrict__ dudt, float* __restrict__ vsig_out, unsigned long long* __restrict__ stat) {
-    const int g = xcd_remap(blockIdx.x, ng);
-    if (g >= ng) return;
-    __shared__ float tx[SPH_TILE], ty[SPH_TILE], tz[SPH_TILE], tvx[SPH_TILE], tvy[SPH_TILE],
-        tvz[SPH_TILE], tm[SPH_TILE], thi[SPH_TILE], th2[SPH_TILE], tcw[SPH_TILE], trho[SPH_TILE],
-        tA[SPH_TILE], tc[SPH_TILE];
-    __shared__ int32_t jidx[SPH_TILE];
+    int ng, const int2* __restrict__ items, const int32_t* __restrict__ groups,
+    const NodeRec* __restrict__ nodes, const double4* __restrict__ pos4,
+    const uint32_t* __restrict__ perm, const double4* __restrict__ sv,
+    const float4* __restrict__ ss, ListView L, float alpha, double* __restrict__ ax,
+    double* __restrict__ ay, double* __restrict__ az, double* __restrict__ dudt,
+    float* __restrict__ vsig_out, uint32_t* __restrict__ hv, double4* __restrict__ partd,
+    float* __restrict__ partv, unsigned long long* __restrict__ stat) {
+    int g, pb;
+    if (PART) {
+        const int2 it = items[blockIdx.x];
+        g = it.x;
+        pb = it.y * SPH_CAP;
+    } else {
+        g = xcd_remap(blockIdx.x, ng);
+        if (g >= ng) return;
+        pb = 0;
+    }
+    const GroupList GL(L, g);
+    const int npp = GL.npp;
+    if (!PART && npp > SPH_CAP) {
+        if (threadIdx.x == 0) hv[g] = (uint32_t)((npp + SPH_CAP - 1) / SPH_CAP);
+        return;
+    }
+    const int pe = PART ? min(npp, pb + SPH_CAP) : npp;
+    __shared__ float4 t0[SPH_TILE], t1[SPH_TILE], t2[SPH_TILE];
+    __shared__ float tc[SPH_TILE];
+    __shared__ int jidx[SPH_TILE], jroff[SPH_TILE], wtot[SPH_DT / 64];
+    __shared__ uint8_t fl[SPH_FCAP][SPH_DT];
     __shared__ double redd[4][SPH_DT / 64][64];
     __shared__ float redv[SPH_DT / 64][64];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -423,114 +755,78 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_force(
     const double cy = (B.lo[1] + B.hi[1]) * 0.5;
     const double cz = (B.lo[2] + B.hi[2]) * 0.5;
     const double4 vref = sv[B.begin];
-    const GroupList GL(L, g);
-    const int npp = GL.npp;
-    const int64_t r0 = GL.r0, r1 = GL.r1;
     unsigned long long nin = 0;
 
     for (int ic = 0; ic < nG; ic += pad) {
         const int s = B.begin + ic + il;
         const bool act = ic + il < nG;
-        float xi = 0, yi = 0, zi = 0, vxi = 0, vyi = 0, vzi = 0;
-        float Hi = 1, Hinv = 1, cwi = 0, rhoi = 1, Ai = 0, ci = 0;
+        ForceRecv R = {0, 0, 0, 0, 0, 0, 1, 0, 1, 0, 0};
+        float Hi = 1;
         if (act) {
             const double4 p = pos4[s];
-            xi = (float)(p.x - cx);
-            yi = (float)(p.y - cy);
-            zi = (float)(p.z - cz);
+            R.x = (float)(p.x - cx);
+            R.y = (float)(p.y - cy);
+            R.z = (float)(p.z - cz);
             const double4 v = sv[s];
-            vxi = (float)(v.x - vref.x);
-            vyi = (float)(v.y - vref.y);
-            vzi = (float)(v.z - vref.z);
+            R.vx = (float)(v.x - vref.x);
+            R.vy = (float)(v.y - vref.y);
+            R.vz = (float)(v.z - vref.z);
             const float4 q = ss[s];
             Hi = q.x;
-            Hinv = 1.0f / Hi;
-            const float h2 = Hinv * Hinv;
-            cwi = -GRADW_C * h2 * h2 * Hinv;
-            rhoi = q.y;
-            Ai = q.z;
-            ci = q.w;
+            R.Hinv = 1.0f / Hi;
+            const float h2 = R.Hinv * R.Hinv;
+            R.cw = -GRADW_C * h2 * h2 * R.Hinv;
+            R.rho = q.y;
+            R.A = q.z;
+            R.c = q.w;
         }
         const float Hi2 = Hi * Hi;
         double AX = 0, AY = 0, AZ = 0, DU = 0;
-        float vs = ci;
-        int64_t rr = r0;  // first range that may overlap the current tile
-        for (int t0 = 0; t0 < npp; t0 += SPH_TILE) {
-            const int tn = min(SPH_TILE, npp - t0);
+        float vs = R.c;
+        for (int tb = pb; tb < pe; tb += SPH_TILE) {
+            const int tn = min(SPH_TILE, pe - tb);
             __syncthreads();
-            for (int64_t r = rr; r < r1; r++) {
-                const int c = GL.cum[r];
-                if (c >= t0 + tn) break;
-                const int cn = (r + 1 < r1) ? GL.cum[r + 1] : npp;
-                const int b = GL.begin[r];
-                const int lo = max(c, t0), hi = min(cn, t0 + tn);
-                for (int k = lo + tid; k < hi; k += SPH_DT) jidx[k - t0] = b + (k - c);
-            }
-            while (rr < r1 && ((rr + 1 < r1) ? GL.cum[rr + 1] : npp) <= t0 + tn) rr++;
-            __syncthreads();
+            list_slots(GL, npp, tb, tb + tn, jidx, jroff, wtot, tid, SPH_DT);
             for (int e = tid; e < tn; e += SPH_DT) {
                 const int j = jidx[e];
                 const double4 p = pos4[j];
                 const double4 v = sv[j];
                 const float4 q = ss[j];
-                tx[e] = (float)(p.x - cx);
-                ty[e] = (float)(p.y - cy);
-                tz[e] = (float)(p.z - cz);
-                tvx[e] = (float)(v.x - vref.x);
-                tvy[e] = (float)(v.y - vref.y);
-                tvz[e] = (float)(v.z - vref.z);
-                tm[e] = (float)p.w;
                 const float hinv = 1.0f / q.x;
                 const float h2 = hinv * hinv;
-                thi[e] = hinv;
-                th2[e] = q.x * q.x;
-                tcw[e] = -GRADW_C * h2 * h2 * hinv;
-                trho[e] = q.y;
-                tA[e] = q.z;
+                t0[e] = make_float4((float)(p.x - cx), (float)(p.y - cy), (float)(p.z - cz),
+                                    q.x * q.x);
+                t1[e] = make_float4((float)(v.x - vref.x), (float)(v.y - vref.y),
+                                    (float)(v.z - vref.z), (float)p.w);
+                t2[e] = make_float4(hinv, -GRADW_C * h2 * h2 * hinv, q.y, q.z);
                 tc[e] = q.w;
             }
             __syncthreads();
-            if (act) {
-                float fx = 0, fy = 0, fz = 0, fu = 0;
-                const int per = (tn + nsl - 1) / nsl;
-                const int kb = sl * per, ke = min(tn, kb + per);
-                for (int k = kb; k < ke; k++) {
-                    const float dx = tx[k] - xi, dy = ty[k] - yi, dz = tz[k] - zi;
+            float fx = 0, fy = 0, fz = 0, fu = 0;
+            const int nst = (tn + nsl - 1) / nsl;
+            int nh = 0;
+            for (int m = 0; m < nst; m += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int k = sl + (m + u) * nsl;
+                    const float4 a = t0[min(k, tn - 1)];
+                    const float dx = a.x - R.x, dy = a.y - R.y, dz = a.z - R.z;
                     const float r2 = dx * dx + dy * dy + dz * dz;
-                    const bool inside = (r2 < Hi2 || r2 < th2[k]) && r2 > 0.0f;
-                    if (inside) {
-                        const float rinv = __builtin_amdgcn_rsqf(r2);
-                        const float r = r2 * rinv;
-                        const float qi = r * Hinv, qj = r * thi[k];
-                        float gi = 0.0f, gj = 0.0f;
-                        if (qi < 1.0f) {
-                            const float t = 1.0f - qi, t2 = t * t;
-                            gi = cwi * (1.0f + 5.0f * qi) * t2 * t2 * t;
-                        }
-                        if (qj < 1.0f) {
-                            const float t = 1.0f - qj, t2 = t * t;
-                            gj = tcw[k] * (1.0f + 5.0f * qj) * t2 * t2 * t;
-                        }
-                        const float dvx = tvx[k] - vxi, dvy = tvy[k] - vyi, dvz = tvz[k] - vzi;
-                        const float vr = dvx * dx + dvy * dy + dvz * dz;
-                        const float w = vr * rinv;
-                        const float sig = ci + tc[k] - 3.0f * fminf(w, 0.0f);
-                        const float Pi = w < 0.0f ? -alpha * sig * w / (rhoi + trho[k]) : 0.0f;
-                        const float gbar = 0.5f * (gi + gj);
-                        const float f = tm[k] * (Ai * gi + tA[k] * gj + Pi * gbar);
-                        fx += f * dx;
-                        fy += f * dy;
-                        fz += f * dz;
-                        fu += tm[k] * (Ai * gi + 0.5f * Pi * gbar) * vr;
-                        vs = fmaxf(vs, sig);
-                        nin++;
-                    }
+                    fl[nh][tid] = (uint8_t)k;  // kept only if counted
+                    nh += (act && k < tn && (r2 < Hi2 || r2 < a.w) && r2 > 0.0f) ? 1 : 0;
                 }
-                AX += (double)fx;
-                AY += (double)fy;
-                AZ += (double)fz;
-                DU += (double)fu;
+                if (__ballot(nh > SPH_FCAP - 4)) {  // wave-uniform flush
+                    nin += nh;
+                    force_hits(fl, nh, tid, t0, t1, t2, tc, R, alpha, fx, fy, fz, fu, vs);
+                    nh = 0;
+                }
             }
+            nin += nh;
+            force_hits(fl, nh, tid, t0, t1, t2, tc, R, alpha, fx, fy, fz, fu, vs);
+            AX += (double)fx;
+            AY += (double)fy;
+            AZ += (double)fz;
+            DU += (double)fu;
         }
         // slices of each wave by shuffles, then the four waves in order
         AX = slice_sum(AX, pad);
@@ -556,12 +852,18 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_force(
                 DU += redd[3][w][il];
                 vs = fmaxf(vs, redv[w][il]);
             }
-            const uint32_t o = perm[s];
-            ax[o] += AX;
-            ay[o] += AY;
-            az[o] += AZ;
-            dudt[o] = DU;
-            vsig_out[o] = vs;
+            if (PART) {
+                const int64_t q = (int64_t)blockIdx.x * 64 + ic + il;
+                partd[q] = make_double4(AX, AY, AZ, DU);
+                partv[q] = vs;
+            } else {
+                const uint32_t o = perm[s];
+                ax[o] += AX;
+                ay[o] += AY;
+                az[o] += AZ;
+                dudt[o] = DU;
+                vsig_out[o] = vs;
+            }
         }
     }
     __shared__ unsigned long long nsh[SPH_DT / 64];
@@ -572,8 +874,42 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_force(
         unsigned long long t = 0;
         for (int w = 0; w < SPH_DT / 64; w++) t += nsh[w];
         atomicAdd(&stat[2], t);
-        atomicAdd(&stat[4], (unsigned long long)nG * (unsigned long long)npp);
+        atomicAdd(&stat[4], (unsigned long long)nG * (unsigned long long)(pe - pb));
     }
+}
+
+// Receivers of one long-list group (one wave): chunk partials added in chunk
+// order, results added to the outputs as in k_sph_force.
+__global__ __launch_bounds__(64) void k_sph_force_long_sum(
+    const uint32_t* __restrict__ nh, const int32_t* __restrict__ hlist,
+    const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes,
+    const uint32_t* __restrict__ hv, const int64_t* __restrict__ hoff,
+    const double4* __restrict__ partd, const float* __restrict__ partv,
+    const uint32_t* __restrict__ perm, double* __restrict__ ax, double* __restrict__ ay,
+    double* __restrict__ az, double* __restrict__ dudt, float* __restrict__ vsig_out) {
+    if (blockIdx.x >= nh[0]) return;
+    const int g = hlist[blockIdx.x];
+    const NodeRec B = nodes[groups[g]];
+    const int il = threadIdx.x;
+    if (il >= B.end - B.begin) return;
+    double AX = 0, AY = 0, AZ = 0, DU = 0;
+    float vs = 0.0f;
+    const int64_t i0 = hoff[g];
+    for (uint32_t c = 0; c < hv[g]; c++) {
+        const int64_t q = (i0 + c) * 64 + il;
+        const double4 p = partd[q];
+        AX += p.x;
+        AY += p.y;
+        AZ += p.z;
+        DU += p.w;
+        vs = fmaxf(vs, partv[q]);
+    }
+    const uint32_t o = perm[B.begin + il];
+    ax[o] += AX;
+    ay[o] += AY;
+    az[o] += AZ;
+    dudt[o] = DU;
+    vsig_out[o] = vs;
 }
 
 // ---------------------------------------------------------------------------
@@ -677,6 +1013,78 @@ __global__ void k_flags_to_active(int nb, const uint32_t* __restrict__ flags,
     if (g < nb) active[g] = flags[g] ? 1 : 0;
 }
 
+// Work items of the groups marked in hv (chunk counts): item offsets hoff,
+// items (group, chunk), group list hlist with its count in ctr[0].  Returns
+// the number of items in *ni (0: nothing to do).
+static int long_items(gx_ctx* ctx, int nb, const uint32_t* hv, int64_t** hoff, int2** items,
+                      int32_t** hlist, uint32_t** ctr, int64_t* ni) {
+    hipStream_t st = ctx->stream;
+    GX_TRY(work(ctx, W_HOFF, (size_t)(nb + 1) * sizeof(int64_t), (void**)hoff));
+    GX_TRY(work(ctx, W_HLIST, (size_t)(nb + 4) * sizeof(int32_t), (void**)hlist));
+    *ctr = (uint32_t*)(*hlist + nb);
+    GX_TRY((gx_scan<uint32_t, int64_t>(ctx, hv, *hoff, nb, *hoff + nb)));
+    GX_HIP(ctx, hipMemcpyAsync(ni, *hoff + nb, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    GX_HIP(ctx, hipStreamSynchronize(st));
+    if (*ni == 0) return GX_OK;
+    GX_TRY(work(ctx, W_ITEM, (size_t)*ni * sizeof(int2), (void**)items));
+    GX_TRY(gx_zero(ctx, *ctr, 4 * sizeof(uint32_t)));
+    hipLaunchKernelGGL(k_long_items, dim3(gx_blocks(nb, 256)), dim3(256), 0, st, nb, hv, *hoff,
+                       *items, *hlist, *ctr);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+// Groups whose candidate lists exceed SPH_CAP: chunk sums over many
+// workgroups, then one Newton step per receiver, until every receiver is
+// done (at most max_iter passes).
+static int density_long(gx_ctx* ctx, TreeSlot& T, const ListView& view, int nb, float* rad,
+                        float n_ngb, float tol, int max_iter, float* Hs, uint32_t* flags,
+                        const uint32_t* hv, unsigned long long* stat, gx_gas* gs, float gamma) {
+    hipStream_t st = ctx->stream;
+    int64_t *hoff, ni = 0;
+    int2* items;
+    int32_t* hlist;
+    uint32_t* ctr;
+    GX_TRY(long_items(ctx, nb, hv, &hoff, &items, &hlist, &ctr, &ni));
+    if (ni == 0) return GX_OK;
+    if (ni > INT32_MAX / 64) return gx_fail(ctx, GX_EINVAL, "sph_density: too many list chunks");
+    float4* hst;
+    float2* part;
+    uint8_t* gdone;
+    GX_TRY(work(ctx, W_HST, (size_t)T.n * sizeof(float4), (void**)&hst));
+    GX_TRY(work(ctx, W_PART, (size_t)ni * 64 * sizeof(float2), (void**)&part));
+    GX_TRY(work(ctx, W_GD, (size_t)nb + 16, (void**)&gdone));
+    // the group kernels run over ni blocks (>= the group count) and read the count on device
+    hipLaunchKernelGGL(k_long_init, dim3((unsigned)ni), dim3(64), 0, st, (const uint32_t*)ctr,
+                       (const int32_t*)hlist, (const int32_t*)T.groups.p,
+                       (const NodeRec*)T.nodes.p, hst, gdone);
+    GX_LAUNCH_CHECK(ctx);
+    uint32_t pending = 0;
+    int pass = 0;
+    for (; pass < max_iter; pass++) {
+        GX_TRY(gx_zero(ctx, ctr + 1, sizeof(uint32_t)));
+        hipLaunchKernelGGL(k_sph_density_part, dim3((unsigned)ni), dim3(SPH_DT), 0, st,
+                           (const int2*)items, (const int32_t*)T.groups.p,
+                           (const NodeRec*)T.nodes.p, (const double4*)T.pos4.p, view,
+                           (const float*)Hs, (const float4*)hst, (const uint8_t*)gdone, part);
+        hipLaunchKernelGGL(k_sph_density_long_step, dim3((unsigned)ni), dim3(64), 0, st,
+                           (const uint32_t*)ctr, (const int32_t*)hlist,
+                           (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
+                           (const double4*)T.pos4.p, view, hv, (const int64_t*)hoff,
+                           (const float2*)part, rad, n_ngb, tol, max_iter, Hs, hst, gdone, flags,
+                           ctr + 1, stat, (const uint32_t*)T.val[0].p, gs->u, gamma, gs->H64,
+                           gs->H, gs->rho, gs->P, gs->cs);
+        GX_LAUNCH_CHECK(ctx);
+        GX_HIP(ctx, hipMemcpyAsync(&pending, ctr + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        GX_HIP(ctx, hipStreamSynchronize(st));
+        if (pending == 0) break;
+    }
+    if (pending != 0)
+        return gx_fail(ctx, GX_EHIP, "sph_density: long-list receivers unfinished after %d passes",
+                       pass);
+    return GX_OK;
+}
+
 extern "C" int gx_sph_density(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, double n_ngb,
                               double gamma, double tol, int max_iter, gx_stats* stats) {
     if (!ctx || !gas || !gs) return GX_EINVAL;
@@ -706,6 +1114,8 @@ extern "C" int gx_sph_density(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, 
     GX_TRY(work(ctx, W_FLAG, nb * sizeof(uint32_t), (void**)&flags));
     GX_TRY(work(ctx, W_STAT, 16 * sizeof(unsigned long long), (void**)&stat));
     GX_TRY(gx_zero(ctx, stat, 16 * sizeof(unsigned long long)));
+    uint32_t* hv;
+    GX_TRY(work(ctx, W_HV, (size_t)(nb + 1) * sizeof(uint32_t), (void**)&hv));
     hipLaunchKernelGGL(k_sph_seed, dim3(gx_blocks(n, 256)), dim3(256), 0, st, n,
                        (const NodeRec*)T.nodes.p, (const MomRec*)T.mom.p, (const double4*)T.pos4.p,
                        (const uint32_t*)T.val[0].p, gs->H64, (float)n_ngb, (const double*)T.box.p,
@@ -723,13 +1133,16 @@ extern "C" int gx_sph_density(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, 
         GX_TRY(gx_sph_walk(ctx, T, Ls, nb, (const int32_t*)T.groups.p, nullptr, rad, 0, act, &view,
                            &list_pairs));
         if (stats) GX_HIP(ctx, hipEventRecord(ctx->ev2, st));
+        GX_TRY(gx_zero(ctx, hv, (size_t)nb * sizeof(uint32_t)));
         hipLaunchKernelGGL(k_sph_density, dim3(xcd_grid(nb)), dim3(SPH_DT), 0, st, nb,
                            (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
                            (const double4*)T.pos4.p,
                            (const uint32_t*)T.val[0].p, act, view, rad, (float)n_ngb, (float)tol,
-                           max_iter, Hs, flags, stat, gs->u, (float)gamma, gs->H64, gs->H, gs->rho,
-                           gs->P, gs->cs);
+                           max_iter, Hs, flags, hv, stat, gs->u, (float)gamma, gs->H64, gs->H,
+                           gs->rho, gs->P, gs->cs);
         GX_LAUNCH_CHECK(ctx);
+        GX_TRY(density_long(ctx, T, view, nb, rad, (float)n_ngb, (float)tol, max_iter, Hs, flags,
+                            hv, stat, gs, (float)gamma));
         if (stats) GX_HIP(ctx, hipEventRecord(ctx->ev3, st));
         GX_HIP(ctx, hipMemcpyAsync(h_stat, stat, 8 * sizeof(unsigned long long),
                                    hipMemcpyDeviceToHost, st));
@@ -758,7 +1171,7 @@ extern "C" int gx_sph_density(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, 
         stats->ms_kernel = kernel_ms;
         stats->n_noconv = (int64_t)h_stat[0];
         stats->n_iter_max = (int64_t)h_stat[1];
-        stats->n_sph_list = list_pairs;
+        stats->n_sph_list = (int64_t)h_stat[5];
         stats->n_rewalk = rounds - 1;
         stats->n_groups = nb;
         stats->n_nodes = T.n_nodes;
@@ -809,12 +1222,42 @@ extern "C" int gx_sph_forces(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, d
     GX_TRY(gx_sph_walk(ctx, T, Ls, nb, (const int32_t*)T.groups.p, nullptr, rad, 1, nullptr, &view,
                        &list_pairs));
     if (stats) GX_HIP(ctx, hipEventRecord(ctx->ev2, st));
-    hipLaunchKernelGGL(k_sph_force, dim3(xcd_grid(nb)), dim3(SPH_DT), 0, st, nb,
-                       (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
-                       (const double4*)T.pos4.p,
+    uint32_t* hv;
+    GX_TRY(work(ctx, W_HV, (size_t)(nb + 1) * sizeof(uint32_t), (void**)&hv));
+    GX_TRY(gx_zero(ctx, hv, (size_t)nb * sizeof(uint32_t)));
+    hipLaunchKernelGGL(k_sph_force<false>, dim3(xcd_grid(nb)), dim3(SPH_DT), 0, st, nb,
+                       (const int2*)nullptr, (const int32_t*)T.groups.p,
+                       (const NodeRec*)T.nodes.p, (const double4*)T.pos4.p,
                        (const uint32_t*)T.val[0].p, sv, ss, view, (float)alpha, ax, ay, az,
-                       gs->dudt, gs->vsig, stat);
+                       gs->dudt, gs->vsig, hv, (double4*)nullptr, (float*)nullptr, stat);
     GX_LAUNCH_CHECK(ctx);
+    {  // groups with long lists: chunks over many workgroups, then ordered sums
+        int64_t *hoff, ni = 0;
+        int2* items;
+        int32_t* hlist;
+        uint32_t* ctr;
+        GX_TRY(long_items(ctx, nb, hv, &hoff, &items, &hlist, &ctr, &ni));
+        if (ni > 0) {
+            if (ni > INT32_MAX / 64)
+                return gx_fail(ctx, GX_EINVAL, "sph_forces: too many list chunks");
+            double4* partd;
+            float* partv;
+            GX_TRY(work(ctx, W_PART, (size_t)ni * 64 * sizeof(double4), (void**)&partd));
+            GX_TRY(work(ctx, W_PARTV, (size_t)ni * 64 * sizeof(float), (void**)&partv));
+            hipLaunchKernelGGL(k_sph_force<true>, dim3((unsigned)ni), dim3(SPH_DT), 0, st, nb,
+                               (const int2*)items, (const int32_t*)T.groups.p,
+                               (const NodeRec*)T.nodes.p, (const double4*)T.pos4.p,
+                               (const uint32_t*)T.val[0].p, sv, ss, view, (float)alpha, ax, ay,
+                               az, gs->dudt, gs->vsig, hv, partd, partv, stat);
+            hipLaunchKernelGGL(k_sph_force_long_sum, dim3((unsigned)ni), dim3(64), 0, st,
+                               (const uint32_t*)ctr, (const int32_t*)hlist,
+                               (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
+                               (const uint32_t*)hv, (const int64_t*)hoff, (const double4*)partd,
+                               (const float*)partv, (const uint32_t*)T.val[0].p, ax, ay, az,
+                               gs->dudt, gs->vsig);
+            GX_LAUNCH_CHECK(ctx);
+        }
+    }
     if (stats) GX_HIP(ctx, hipEventRecord(ctx->ev3, st));
     if (stats) {
         GX_HIP(ctx, hipEventRecord(ctx->ev1, st));

@@ -43,12 +43,17 @@ def _density(gx, eng, d, n_group=64, n_leaf=8, H_guess=None):
     return p, g, st
 
 
-@pytest.mark.parametrize("case", ["sphere", "lattice", "disk_gas"])
+# "slab": sparse particles whose kernels reach into a dense slab give groups
+# with candidate lists far longer than one workgroup holds, which take the
+# chunked path (partial sums over many workgroups).
+@pytest.mark.parametrize("case", ["sphere", "lattice", "disk_gas", "slab"])
 def test_density_matches_oracle(gx, eng, case):
     if case == "sphere":
         d = ics.gas_sphere(8192, 2)
     elif case == "lattice":
         d = ics.lattice(20, jitter=0.05)
+    elif case == "slab":
+        d = ics.slab_and_sparse()
     else:
         d = ics.gas_view(ics.disk_galaxy(200_000, 3))
     p, g, st = _density(gx, eng, d)
@@ -87,10 +92,12 @@ def _force(gx, eng, d, Ho, rho_o, alpha=1.0):
     return [a.cpu().numpy() for a in acc], g.dudt.cpu().numpy(), g.vsig.cpu().numpy(), st
 
 
-@pytest.mark.parametrize("case", ["sphere", "disk_gas", "converging"])
+@pytest.mark.parametrize("case", ["sphere", "disk_gas", "converging", "slab"])
 def test_force_matches_oracle(gx, eng, case):
     if case == "sphere":
         d = ics.gas_sphere(8192, 2)
+    elif case == "slab":
+        d = ics.slab_and_sparse()
     elif case == "disk_gas":
         d = ics.gas_view(ics.disk_galaxy(200_000, 3))
     else:
