@@ -122,14 +122,17 @@ __global__ __launch_bounds__(128) void k_walk_grav(
 
 // Wave-cooperative gravity walk into per-group slots (the one-pass mode of
 // k_walk_grav): one wavefront per group, an LDS stack of pending nodes; each
-// step pops up to 64 nodes, one per lane, applies the opening criterion in
-// the same IEEE sequence, appends accepted cells and opened leaves to the
-// slots by ballot compaction and pushes the children of opened internal
-// nodes.  Lists come out in a different order than the stackless walk's (the
-// same sets).  Per group it writes the list sizes, an overflow flag (slot or
-// stack) and the deepest stack; k_group_totals then forms the totals (the
-// caller builds the lists in two passes when any group overflowed).
+// step pops up to GWALK_WK x 64 nodes (GWALK_WK per lane, so that as many
+// node records are in flight per round trip to memory), applies the opening
+// criterion in the same IEEE sequence, appends accepted cells and opened
+// leaves to the slots by ballot compaction and pushes the children of opened
+// internal nodes.  Lists come out in a different order than the stackless
+// walk's (the same sets).  Per group it writes the list sizes, an overflow
+// flag (slot or stack) and the deepest stack; k_group_totals then forms the
+// totals (the caller builds the lists in two passes when any group
+// overflowed).
 #define GWALK_STACK 4096
+#define GWALK_WK 2
 __global__ __launch_bounds__(64) void k_walk_grav_wave(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes,
     const int32_t* __restrict__ child, const double* __restrict__ box, double theta2,
@@ -148,68 +151,91 @@ __global__ __launch_bounds__(64) void k_walk_grav_wave(
     int sp = 1, npc = 0, npr = 0, npp = 0, over = 0, spmax = 1;
     __syncthreads();
     while (sp > 0 && !over) {
-        const int take = sp < 64 ? sp : 64;
+        const int take = sp < 64 * GWALK_WK ? sp : 64 * GWALK_WK;
         const int b0 = sp - take;
-        int n = -1;
-        if (lane < take) n = stk[b0 + lane];
+        int n[GWALK_WK];
+#pragma unroll
+        for (int w = 0; w < GWALK_WK; w++) {
+            const int q = lane + 64 * w;
+            n[w] = q < take ? stk[b0 + q] : -1;
+        }
         __syncthreads();
         sp = b0;
-        bool acc = false, leaf = false, open = false;
-        int b = 0, e = 0;
-        int4 cq0 = make_int4(-1, -1, -1, -1), cq1 = cq0;
-        if (n >= 0) {
-            // the child row is fetched with the node record (not after the
-            // opening test) so the two loads overlap
-            const int4* cp = reinterpret_cast<const int4*>(child + 8 * (int64_t)n);
-            cq0 = cp[0];
-            cq1 = cp[1];
-            const NodeRec& nd = nodes[n];
-            double lo[3] = {nd.lo[0], nd.lo[1], nd.lo[2]};
-            double hi[3] = {nd.hi[0], nd.hi[1], nd.hi[2]};
-            double d2 = box_dist2(G.lo, G.hi, lo, hi);
-            double lc = ldexp(L, -(int)nd.level);
-            double lhs = lc * lc;
-            double rhs = theta2 * d2;
-            acc = lhs < rhs;
-            leaf = !acc && nd.leaf;
-            open = !acc && !nd.leaf;
-            b = nd.begin;
-            e = nd.end;
-        }
-        // accepted cells
-        const uint64_t am = __ballot(acc);
-        if (acc) {
-            const int pos = npc + __popcll(am & lt);
-            if (pos < cap_pc) pc_list[pco + pos] = n;
-        }
-        npc += __popcll(am);
-        // opened leaves: particle ranges
-        const uint64_t lm = __ballot(leaf);
-        const int sz = leaf ? e - b : 0;
-        const int incl = wave_incl_scan(sz);
-        if (leaf) {
-            const int pos = npr + __popcll(lm & lt);
-            if (pos < cap_pr) {
-                pr_begin[pro + pos] = b;
-                pr_cum[pro + pos] = npp + incl - sz;
+        // all loads of this step first: child rows and node records
+        int4 cq[GWALK_WK][2];
+        NodeRec rec[GWALK_WK];
+#pragma unroll
+        for (int w = 0; w < GWALK_WK; w++) {
+            cq[w][0] = cq[w][1] = make_int4(-1, -1, -1, -1);
+            if (n[w] >= 0) {
+                const int4* cp = reinterpret_cast<const int4*>(child + 8 * (int64_t)n[w]);
+                cq[w][0] = cp[0];
+                cq[w][1] = cp[1];
+                rec[w] = nodes[n[w]];
             }
         }
-        npr += __popcll(lm);
-        npp += __shfl(incl, 63, 64);
-        // opened internal nodes: children onto the stack
         int nch = 0;
-        const int32_t ch[8] = {cq0.x, cq0.y, cq0.z, cq0.w, cq1.x, cq1.y, cq1.z, cq1.w};
-        if (open) {
 #pragma unroll
-            for (int k = 0; k < 8; k++) nch += ch[k] >= 0;
+        for (int w = 0; w < GWALK_WK; w++) {
+            bool acc = false, leaf = false, open = false;
+            int b = 0, e = 0;
+            if (n[w] >= 0) {
+                const NodeRec& nd = rec[w];
+                double lo[3] = {nd.lo[0], nd.lo[1], nd.lo[2]};
+                double hi[3] = {nd.hi[0], nd.hi[1], nd.hi[2]};
+                double d2 = box_dist2(G.lo, G.hi, lo, hi);
+                double lc = ldexp(L, -(int)nd.level);
+                double lhs = lc * lc;
+                double rhs = theta2 * d2;
+                acc = lhs < rhs;
+                leaf = !acc && nd.leaf;
+                open = !acc && !nd.leaf;
+                b = nd.begin;
+                e = nd.end;
+            }
+            // accepted cells
+            const uint64_t am = __ballot(acc);
+            if (acc) {
+                const int pos = npc + __popcll(am & lt);
+                if (pos < cap_pc) pc_list[pco + pos] = n[w];
+            }
+            npc += __popcll(am);
+            // opened leaves: particle ranges
+            const uint64_t lm = __ballot(leaf);
+            const int sz = leaf ? e - b : 0;
+            const int incl = wave_incl_scan(sz);
+            if (leaf) {
+                const int pos = npr + __popcll(lm & lt);
+                if (pos < cap_pr) {
+                    pr_begin[pro + pos] = b;
+                    pr_cum[pro + pos] = npp + incl - sz;
+                }
+            }
+            npr += __popcll(lm);
+            npp += __shfl(incl, 63, 64);
+            if (!open) {
+                cq[w][0] = cq[w][1] = make_int4(-1, -1, -1, -1);
+            } else {
+                nch += (cq[w][0].x >= 0) + (cq[w][0].y >= 0) + (cq[w][0].z >= 0) +
+                       (cq[w][0].w >= 0) + (cq[w][1].x >= 0) + (cq[w][1].y >= 0) +
+                       (cq[w][1].z >= 0) + (cq[w][1].w >= 0);
+            }
         }
+        // children of opened internal nodes onto the stack (lane order, then w)
         const int cincl = wave_incl_scan(nch);
         const int ctot = __shfl(cincl, 63, 64);
         if (sp + ctot > GWALK_STACK) {
             over = 1;
         } else {
-            const int coff = sp + cincl - nch;
-            for (int k = 0; k < nch; k++) stk[coff + k] = ch[k];
+            int coff = sp + cincl - nch;
+#pragma unroll
+            for (int w = 0; w < GWALK_WK; w++) {
+                const int32_t ch[8] = {cq[w][0].x, cq[w][0].y, cq[w][0].z, cq[w][0].w,
+                                       cq[w][1].x, cq[w][1].y, cq[w][1].z, cq[w][1].w};
+#pragma unroll
+                for (int k = 0; k < 8; k++)
+                    if (ch[k] >= 0) stk[coff++] = ch[k];
+            }
             sp += ctot;
             spmax = sp > spmax ? sp : spmax;
         }
