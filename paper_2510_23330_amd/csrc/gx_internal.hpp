@@ -86,6 +86,7 @@ struct gx_ctx {
     ListSet grav, sph;
     Buf scan_tmp[3], hist, partial, small, host_small;
     Buf wpart;  // per-chunk partial weight gradients (ordered reduction)
+    Buf wrel;   // 3^3 weights re-laid out chunk-major for the slab convolution
     Buf sph_work[16];
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
 };

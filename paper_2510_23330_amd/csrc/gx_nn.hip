@@ -362,6 +362,170 @@ __global__ __launch_bounds__(256) void k_conv3d_brick(const uint16_t* __restrict
         }
 }
 
+// ---------------------------------------------------------------------------
+// 3^3 convolution on output slabs with weights staged in LDS
+// ---------------------------------------------------------------------------
+// A workgroup computes SBZ x SBY x SBX = 8 x 4 x 16 output voxels of one
+// sample for BN output channels; wave w owns z slices 2w and 2w + 1, i.e.
+// eight 16-row MFMA tiles, each one x-row of 16 voxels.  The reduction runs
+// over chunks of 8 input channels: per chunk the slab's input with a
+// one-voxel halo (10 x 6 x 18 voxels x 8 channels) and the chunk's weights
+// for all 27 taps and BN outputs (27 x BN x 8) are staged in LDS once for the
+// four waves, then 7 MFMA steps cover K = 27 taps x 8 channels (4 taps per
+// step, lane group kg takes tap 4 st + kg; the 28th tap slot is zero).  16
+// consecutive voxels or output channels of 16 bytes each fill all 64 LDS
+// banks once, so both operand reads are conflict-free without padding.  The
+// weights come re-laid out as [Cin / 8][27][Cout][8] (k_wrelayout) so that
+// each chunk's slice is read with whole-line loads.
+#define SBZ 8
+#define SBY 4
+#define SBX 16
+#define SHZ (SBZ + 2)
+#define SHY (SBY + 2)
+#define SHX (SBX + 2)
+#define SHVOX (SHZ * SHY * SHX)
+
+__global__ void k_wrelayout(const uint16_t* __restrict__ w, int Cout, int Cin,
+                            uint16_t* __restrict__ wr) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // one 8-channel piece
+    const int ncg = Cin / 8;
+    const int64_t n = (int64_t)Cout * 27 * ncg;
+    if (e >= n) return;
+    const int cg = (int)(e % ncg);
+    const int64_t t = e / ncg;
+    const int tap = (int)(t % 27);
+    const int co = (int)(t / 27);
+    *reinterpret_cast<uint4*>(wr + (((int64_t)cg * 27 + tap) * Cout + co) * 8) =
+        *reinterpret_cast<const uint4*>(w + ((int64_t)co * 27 + tap) * Cin + cg * 8);
+}
+
+template <int BN>
+__global__ __launch_bounds__(256, 2) void k_conv3d_slab(const uint16_t* __restrict__ in,
+                                                        const uint16_t* __restrict__ wr,
+                                                        const float* __restrict__ bias, ConvGeom g,
+                                                        int mode, const uint16_t* __restrict__ yref,
+                                                        uint16_t* __restrict__ out_bf,
+                                                        float* __restrict__ out_f32, ConvSrc src) {
+    constexpr int NT = BN / 16;
+    constexpr int NSTEP = 7;  // ceil(27 / 4)
+    __shared__ __attribute__((aligned(16))) uint16_t hal[SHVOX * 8];
+    __shared__ __attribute__((aligned(16))) uint16_t wsh[27 * BN * 8];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int S = g.S;
+    const int nbx = (S + SBX - 1) / SBX, nby = (S + SBY - 1) / SBY, nbz = (S + SBZ - 1) / SBZ;
+    int t = blockIdx.x;
+    const int bx = t % nbx;
+    t /= nbx;
+    const int by = t % nby;
+    t /= nby;
+    const int bz = t % nbz;
+    const int b = t / nbz;
+    const int x0 = bx * SBX, y0 = by * SBY, z0 = bz * SBZ;
+    const int n0 = blockIdx.y * BN;
+    const int64_t vs0 = (int64_t)b * S * S * S;
+
+    f32x4 acc[8][NT];
+#pragma unroll
+    for (int r = 0; r < 8; r++)
+#pragma unroll
+        for (int j = 0; j < NT; j++) acc[r][j] = f32x4{0, 0, 0, 0};
+
+    // row tile r of this wave: z slice 2 wv + r / 4, y row r % 4, x = lane & 15
+    int hrow[8];
+#pragma unroll
+    for (int r = 0; r < 8; r++) hrow[r] = ((2 * wv + (r >> 2)) * SHY + (r & 3)) * SHX + (lane & 15);
+    const int kg = lane >> 4;  // tap slot of this lane within a step
+
+    const int nchunk = g.Cin / 8;
+    const int Ss = src.up ? S / 2 : S;
+    const int64_t ss0 = (int64_t)b * Ss * Ss * Ss;
+    for (int c = 0; c < nchunk; c++) {
+        const bool second = src.in2 && c * 8 >= src.c1;
+        const uint16_t* sp = second ? src.in2 : in;
+        const int sc = second ? g.Cin - src.c1 : src.c1;
+        const int co = second ? c * 8 - src.c1 : c * 8;
+        __syncthreads();  // the previous chunk's tiles have been read
+        for (int h = tid; h < SHVOX; h += 256) {
+            const int hz = h / (SHY * SHX), hr = h - hz * (SHY * SHX), hy = hr / SHX,
+                      hx = hr - hy * SHX;
+            int Z = z0 - 1 + hz, Y = y0 - 1 + hy, X = x0 - 1 + hx;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (Z >= 0 && Z < S && Y >= 0 && Y < S && X >= 0 && X < S) {
+                if (src.up) {
+                    Z >>= 1;
+                    Y >>= 1;
+                    X >>= 1;
+                }
+                v = *reinterpret_cast<const uint4*>(sp + (ss0 + ((int64_t)Z * Ss + Y) * Ss + X) * sc +
+                                                    co);
+            }
+            *reinterpret_cast<uint4*>(&hal[h * 8]) = v;
+        }
+        {
+            const uint16_t* wc = wr + (int64_t)c * 27 * g.Cout * 8;
+            for (int e = tid; e < 27 * BN; e += 256) {
+                const int tap = e / BN, n = e - tap * BN;
+                *reinterpret_cast<uint4*>(&wsh[e * 8]) =
+                    *reinterpret_cast<const uint4*>(wc + ((int64_t)tap * g.Cout + n0 + n) * 8);
+            }
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int st = 0; st < NSTEP; st++) {
+            const int tap = st * 4 + kg;
+            bf16x8 a[8], bb[NT];
+            if (tap < 27) {
+                const int dz = tap / 9, rr = tap - dz * 9, dy = rr / 3, dx = rr - dy * 3;
+                const int toff = (dz * SHY + dy) * SHX + dx;
+#pragma unroll
+                for (int r = 0; r < 8; r++)
+                    a[r] = *reinterpret_cast<const bf16x8*>(&hal[(hrow[r] + toff) * 8]);
+#pragma unroll
+                for (int j = 0; j < NT; j++)
+                    bb[j] = *reinterpret_cast<const bf16x8*>(&wsh[(tap * BN + j * 16 + (lane & 15)) * 8]);
+            } else {
+                const uint4 z4 = make_uint4(0, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 8; r++) a[r] = *reinterpret_cast<const bf16x8*>(&z4);
+#pragma unroll
+                for (int j = 0; j < NT; j++) bb[j] = *reinterpret_cast<const bf16x8*>(&z4);
+            }
+#pragma unroll
+            for (int r = 0; r < 8; r++)
+#pragma unroll
+                for (int j = 0; j < NT; j++)
+                    acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], bb[j], acc[r][j], 0, 0, 0);
+        }
+    }
+    // epilogue: lane holds rows 4 (lane / 16) + q of each tile, column lane % 16;
+    // row x of tile r is voxel (z0 + 2 wv + r / 4, y0 + r % 4, x0 + x)
+#pragma unroll
+    for (int r = 0; r < 8; r++) {
+        const int Z = z0 + 2 * wv + (r >> 2), Y = y0 + (r & 3);
+        if (Z >= S || Y >= S) continue;
+#pragma unroll
+        for (int j = 0; j < NT; j++) {
+            const int col = n0 + j * 16 + (lane & 15);
+            const float bv = bias ? bias[col] : 0.0f;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int X = x0 + (lane >> 4) * 4 + q;
+                if (X >= S) continue;
+                const int64_t m = vs0 + ((int64_t)Z * S + Y) * S + X;
+                float v = acc[r][j][q] + bv;
+                const int64_t o = m * g.Cout + col;
+                if (mode == EP_LRELU) {
+                    v = v > 0.0f ? v : LRELU_SLOPE * v;
+                } else if (mode == EP_DACT) {
+                    v = bf2f(yref[o]) > 0.0f ? v : LRELU_SLOPE * v;
+                }
+                if (out_bf) out_bf[o] = f2bf(v);
+                if (out_f32) out_f32[o] = v;
+            }
+        }
+    }
+}
+
 // Weights for the data gradient: w'[ci][tap'][co] = w[co][26 - tap'][ci] (or
 // the same tap for 1^3 kernels), so that backward data is a forward pass.
 __global__ void k_wflip(const uint16_t* __restrict__ w, int Cout, int Cin, int kvol,
@@ -808,6 +972,27 @@ static int launch_conv(gx_ctx* ctx, const uint16_t* in, const uint16_t* w, const
                        const ConvGeom& g, int mode, const uint16_t* yref, uint16_t* ob,
                        float* of, ConvSrc src = ConvSrc{nullptr, -1, 0}) {
     if (src.c1 < 0) src.c1 = g.Cin;
+    if (g.kvol == 27 && g.Cout % 32 == 0 && g.Cin % 8 == 0 && src.c1 % 8 == 0) {
+        // weights staged in LDS: re-laid out chunk-major first
+        const int64_t pieces = (int64_t)g.Cout * 27 * (g.Cin / 8);
+        GX_TRY(gx_reserve(ctx, ctx->wrel, (size_t)pieces * 16));
+        uint16_t* wr = (uint16_t*)ctx->wrel.p;
+        hipLaunchKernelGGL(k_wrelayout, dim3(gx_blocks(pieces, 256)), dim3(256), 0, ctx->stream, w,
+                           g.Cout, g.Cin, wr);
+        const int S = g.S;
+        const int64_t nb = (int64_t)g.B * ((S + SBZ - 1) / SBZ) * ((S + SBY - 1) / SBY) *
+                           ((S + SBX - 1) / SBX);
+        if (g.Cout % 64 == 0)
+            hipLaunchKernelGGL(k_conv3d_slab<64>, dim3((unsigned)nb, (unsigned)(g.Cout / 64)),
+                               dim3(256), 0, ctx->stream, in, (const uint16_t*)wr, bias, g, mode,
+                               yref, ob, of, src);
+        else
+            hipLaunchKernelGGL(k_conv3d_slab<32>, dim3((unsigned)nb, (unsigned)(g.Cout / 32)),
+                               dim3(256), 0, ctx->stream, in, (const uint16_t*)wr, bias, g, mode,
+                               yref, ob, of, src);
+        GX_LAUNCH_CHECK(ctx);
+        return GX_OK;
+    }
     if (g.kvol == 27) {
         const int S = g.S;
         const int64_t nb = (int64_t)g.B * ((S + BRZ - 1) / BRZ) * ((S + BRY - 1) / BRY) *

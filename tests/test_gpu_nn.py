@@ -39,8 +39,11 @@ def _close(got, ref, rel=2 ** -8, rms_frac=1e-4):
     return np.all(np.abs(got - ref) <= rel * np.abs(ref) + rms_frac * rms)
 
 
+# 3^3 shapes cover grids smaller than one output slab (S = 2, 4, 6), several
+# slabs per axis (S = 20) and one- to eight-chunk reductions.
 @pytest.mark.parametrize("B,S,Cin,Cout,k", [(2, 8, 8, 16, 3), (1, 8, 32, 32, 3), (2, 6, 32, 64, 3),
-                                             (1, 8, 64, 128, 3), (2, 8, 32, 16, 1), (1, 5, 16, 48, 3)])
+                                             (1, 8, 64, 128, 3), (2, 8, 32, 16, 1), (1, 5, 16, 48, 3),
+                                             (2, 4, 16, 32, 3), (2, 2, 32, 64, 3), (1, 20, 8, 32, 3)])
 def test_conv_fwd(gx, eng, B, S, Cin, Cout, k):
     import torch
     rng = np.random.default_rng(B * 100 + S + Cin + Cout + k)
@@ -61,7 +64,8 @@ def test_conv_fwd(gx, eng, B, S, Cin, Cout, k):
     assert _close(_np(out), oracle.lrelu(ref), rel=1e-5)
 
 
-@pytest.mark.parametrize("B,S,Cin,Cout,k", [(2, 8, 16, 32, 3), (1, 8, 64, 32, 3), (2, 6, 32, 16, 1)])
+@pytest.mark.parametrize("B,S,Cin,Cout,k", [(2, 8, 16, 32, 3), (1, 8, 64, 32, 3), (2, 6, 32, 16, 1),
+                                             (2, 4, 32, 32, 3), (2, 2, 64, 32, 3)])
 def test_conv_bwd_data(gx, eng, B, S, Cin, Cout, k):
     import torch
     rng = np.random.default_rng(7 + Cin)
@@ -148,12 +152,22 @@ def test_unet_forward_backward_matches_oracle(gx, eng):
     net.backward(xt, net.dpred)
     dpred = np.zeros_like(pr)
     dpred[..., :5] = 2 * (got[..., :5] - target) / target.size
-    g = ounet.backward(th_gpu, x, A, rb(dpred), base, levels, rb=rb)
+    dp_gpu = _np(net.dpred).reshape(pr.shape)
+    assert np.allclose(dp_gpu, rb(dpred), rtol=2 ** -7, atol=1e-12)
+    # The backward pass is checked on the network's own BF16 activations and
+    # output gradient: an activation whose FP32 sum lands next to a BF16
+    # rounding boundary can round the other way than the FP64 oracle's, and
+    # the randomly initialised layers amplify such a flip downstream (to a
+    # few 1e-3 of an activation), which would otherwise dominate the
+    # comparison.  What remains are the backward kernels' own FP32 sums and
+    # BF16 gradient roundings.
+    Ag = {k: _np(v).reshape(A[k].shape) for k, v in net.acts.items()}
+    g = ounet.backward(th_gpu, x, Ag, dp_gpu, base, levels, rb=rb)
     gg = net.grad.cpu().numpy().astype(np.float64)
     for name, d in tab.items():
         sl = slice(*d["w"])
         e = np.linalg.norm(gg[sl] - g[sl]) / (np.linalg.norm(g[sl]) + 1e-30)
-        assert e < 3e-2, (name, e)
+        assert e < 1e-2, (name, e)
 
 
 def test_adam_matches_oracle(gx, eng):
