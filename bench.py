@@ -118,7 +118,7 @@ def sn_region_leg(eng, n_cubes, infer_batch, seed0=5000):
     seeds = list(range(seed0, seed0 + n_cubes))
     x, y, info = generate(eng, seeds)
     plain_s = info["seconds"]
-    sur = Surrogate(eng, batch=32, seed=0, train=False)
+    sur = Surrogate(eng, batch=64, seed=0, train=False)
     sb = SNBatch(eng, ics.sn_batch(seeds))
     sb.voxelize()
     sur.regions(sb.p, sb.g, sb.centers, cap=sb.n)         # warm-up
@@ -174,7 +174,7 @@ def main():
         from paper_2510_23330_amd.coupling import SNCoupling
         from paper_2510_23330_amd.sn import Surrogate
         sur_eng = gx.Engine(0)
-        coupling = SNCoupling(sim, Surrogate(sur_eng, batch=32, seed=0, train=False),
+        coupling = SNCoupling(sim, Surrogate(sur_eng, batch=64, seed=0, train=False),
                               n_sites=args.sn_sites, delay=50)
     torch.cuda.synchronize()
     log("[bench] set-up done; initial forces (cold kernel sizes) ...")

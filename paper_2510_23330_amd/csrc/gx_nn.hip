@@ -439,18 +439,38 @@ __global__ __launch_bounds__(256, 2) void k_conv3d_slab(const uint16_t* __restri
     const int nchunk = g.Cin / 8;
     const int Ss = src.up ? S / 2 : S;
     const int64_t ss0 = (int64_t)b * Ss * Ss * Ss;
-    for (int c = 0; c < nchunk; c++) {
+    // A chunk's tiles are fetched into registers one chunk ahead (their loads
+    // run under the previous chunk's MFMAs) and committed to LDS between two
+    // barriers.
+    // (the 64-output variant fetches only the halo ahead: its accumulators
+    // leave no room for the weights as well)
+    constexpr bool PFW = BN <= 32;
+    constexpr int NHV = (SHVOX + 255) / 256, NWV = PFW ? (27 * BN + 255) / 256 : 1;
+    uint4 ph[NHV], pw[NWV];
+    auto fetch_w = [&](int c) {
+        const uint16_t* wc = wr + (int64_t)c * 27 * g.Cout * 8;
+#pragma unroll
+        for (int u = 0; u < NWV; u++) {
+            const int e = tid + 256 * u;
+            const int tap = e / BN, n = e - tap * BN;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (e < 27 * BN) v = *reinterpret_cast<const uint4*>(wc + ((int64_t)tap * g.Cout + n0 + n) * 8);
+            pw[u] = v;
+        }
+    };
+    auto fetch = [&](int c) {
         const bool second = src.in2 && c * 8 >= src.c1;
         const uint16_t* sp = second ? src.in2 : in;
         const int sc = second ? g.Cin - src.c1 : src.c1;
         const int co = second ? c * 8 - src.c1 : c * 8;
-        __syncthreads();  // the previous chunk's tiles have been read
-        for (int h = tid; h < SHVOX; h += 256) {
+#pragma unroll
+        for (int u = 0; u < NHV; u++) {
+            const int h = tid + 256 * u;
             const int hz = h / (SHY * SHX), hr = h - hz * (SHY * SHX), hy = hr / SHX,
                       hx = hr - hy * SHX;
             int Z = z0 - 1 + hz, Y = y0 - 1 + hy, X = x0 - 1 + hx;
             uint4 v = make_uint4(0, 0, 0, 0);
-            if (Z >= 0 && Z < S && Y >= 0 && Y < S && X >= 0 && X < S) {
+            if (h < SHVOX && Z >= 0 && Z < S && Y >= 0 && Y < S && X >= 0 && X < S) {
                 if (src.up) {
                     Z >>= 1;
                     Y >>= 1;
@@ -459,9 +479,25 @@ __global__ __launch_bounds__(256, 2) void k_conv3d_slab(const uint16_t* __restri
                 v = *reinterpret_cast<const uint4*>(sp + (ss0 + ((int64_t)Z * Ss + Y) * Ss + X) * sc +
                                                     co);
             }
-            *reinterpret_cast<uint4*>(&hal[h * 8]) = v;
+            ph[u] = v;
         }
-        {
+        if (PFW) fetch_w(c);
+    };
+    fetch(0);
+    for (int c = 0; c < nchunk; c++) {
+        __syncthreads();  // the previous chunk's tiles have been read
+#pragma unroll
+        for (int u = 0; u < NHV; u++) {
+            const int h = tid + 256 * u;
+            if (h < SHVOX) *reinterpret_cast<uint4*>(&hal[h * 8]) = ph[u];
+        }
+        if (PFW) {
+#pragma unroll
+            for (int u = 0; u < NWV; u++) {
+                const int e = tid + 256 * u;
+                if (e < 27 * BN) *reinterpret_cast<uint4*>(&wsh[e * 8]) = pw[u];
+            }
+        } else {
             const uint16_t* wc = wr + (int64_t)c * 27 * g.Cout * 8;
             for (int e = tid; e < 27 * BN; e += 256) {
                 const int tap = e / BN, n = e - tap * BN;
@@ -470,6 +506,8 @@ __global__ __launch_bounds__(256, 2) void k_conv3d_slab(const uint16_t* __restri
             }
         }
         __syncthreads();
+        if (c + 1 < nchunk) fetch(c + 1);
+        __builtin_amdgcn_sched_barrier(0);  // issue the next chunk's loads before the MFMAs
 #pragma unroll 1
         for (int st = 0; st < NSTEP; st++) {
             const int tap = st * 4 + kg;
