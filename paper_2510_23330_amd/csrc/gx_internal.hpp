@@ -87,7 +87,7 @@ struct gx_ctx {
     Buf scan_tmp[3], hist, partial, small, host_small;
     Buf wpart;  // per-chunk partial weight gradients (ordered reduction)
     Buf wrel;   // 3^3 weights re-laid out chunk-major for the slab convolution
-    Buf sph_work[16];
+    Buf sph_work[24];
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
 };
 

@@ -537,21 +537,59 @@ extern "C" int gx_sn_voxelize(gx_ctx* ctx, const gx_particles* gas, const double
 // uniform each), position uniform inside the voxel (three more uniforms),
 // temperature and velocity of that voxel.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_cdf(const float* __restrict__ pred, int nvox,
-                                             double* __restrict__ cdf) {
-    const int c = blockIdx.x;
+// Inclusive prefix sums of the voxel weights 10^(log10 rho) of every cube, in
+// three passes with a fixed order: tiles of CDF_TILE voxels (8 consecutive
+// per thread, then across the block), the tile totals of each cube, and the
+// tile offsets added back.
+#define CDF_TILE 2048
+__global__ __launch_bounds__(256) void k_cdf_tiles(const float* __restrict__ pred, int nvox,
+                                                   double* __restrict__ cdf,
+                                                   double* __restrict__ ttot) {
+    const int c = blockIdx.y, t = blockIdx.x;
+    const int ntile = (nvox + CDF_TILE - 1) / CDF_TILE;
     const float* p = pred + (int64_t)c * nvox * 5;
     double* out = cdf + (int64_t)c * nvox;
     __shared__ double sh[4];
+    const int v0 = t * CDF_TILE + threadIdx.x * 8;
+    double w[8], run = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+        const int v = v0 + q;
+        run += v < nvox ? pow(10.0, (double)p[(int64_t)v * 5]) : 0.0;
+        w[q] = run;
+    }
+    double tot;
+    const double ex = block_excl_scan256<double>(run, sh, &tot);
+#pragma unroll
+    for (int q = 0; q < 8; q++)
+        if (v0 + q < nvox) out[v0 + q] = ex + w[q];
+    if (threadIdx.x == 0) ttot[(int64_t)c * ntile + t] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_cdf_offsets(int nvox, double* __restrict__ ttot) {
+    const int c = blockIdx.x;
+    const int ntile = (nvox + CDF_TILE - 1) / CDF_TILE;
+    double* tt = ttot + (int64_t)c * ntile;
+    __shared__ double sh[4];
     double carry = 0.0;
-    for (int b = 0; b < nvox; b += 256) {
-        const int v = b + threadIdx.x;
-        const double w = v < nvox ? pow(10.0, (double)p[(int64_t)v * 5]) : 0.0;
+    for (int b = 0; b < ntile; b += 256) {
+        const int t = b + threadIdx.x;
+        const double w = t < ntile ? tt[t] : 0.0;
         double tot;
         const double ex = block_excl_scan256<double>(w, sh, &tot);
-        if (v < nvox) out[v] = carry + ex + w;  // inclusive
+        __syncthreads();
+        if (t < ntile) tt[t] = carry + ex;  // exclusive offset of tile t
         carry += tot;
     }
+}
+
+__global__ __launch_bounds__(256) void k_cdf_add(int nvox, const double* __restrict__ ttot,
+                                                 double* __restrict__ cdf) {
+    const int c = blockIdx.y, t = blockIdx.x;
+    const int ntile = (nvox + CDF_TILE - 1) / CDF_TILE;
+    const double off = ttot[(int64_t)c * ntile + t];
+    double* out = cdf + (int64_t)c * nvox;
+    for (int v = t * CDF_TILE + threadIdx.x; v < min(nvox, (t + 1) * CDF_TILE); v += 256) out[v] += off;
 }
 
 __global__ __launch_bounds__(256) void k_resample(
@@ -596,9 +634,15 @@ extern "C" int gx_sn_resample(gx_ctx* ctx, const float* pred, int k, int grid, d
         return GX_EINVAL;
     GX_HIP(ctx, hipSetDevice(ctx->device));
     const int nvox = grid * grid * grid;
+    const int ntile = (nvox + CDF_TILE - 1) / CDF_TILE;
     GX_TRY(gx_reserve(ctx, ctx->sph_work[11], (size_t)k * nvox * sizeof(double)));
+    GX_TRY(gx_reserve(ctx, ctx->sph_work[7], (size_t)k * ntile * sizeof(double)));
     double* cdf = (double*)ctx->sph_work[11].p;
-    hipLaunchKernelGGL(k_cdf, dim3(k), dim3(256), 0, ctx->stream, pred, nvox, cdf);
+    double* ttot = (double*)ctx->sph_work[7].p;
+    hipLaunchKernelGGL(k_cdf_tiles, dim3(ntile, k), dim3(256), 0, ctx->stream, pred, nvox, cdf, ttot);
+    hipLaunchKernelGGL(k_cdf_offsets, dim3(k), dim3(256), 0, ctx->stream, nvox, ttot);
+    hipLaunchKernelGGL(k_cdf_add, dim3(ntile, k), dim3(256), 0, ctx->stream, nvox,
+                       (const double*)ttot, cdf);
     const unsigned gxb = (unsigned)std::max<int64_t>(1, (n_out_max + 255) / 256);
     hipLaunchKernelGGL(k_resample, dim3(gxb, k), dim3(256), 0, ctx->stream, k, grid, 0.5 * side,
                        centers, out_off, pred, cdf, uniforms, T_to_u, x, y, z, vx, vy, vz, u);

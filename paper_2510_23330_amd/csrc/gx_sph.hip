@@ -69,12 +69,14 @@ __global__ __launch_bounds__(64) void k_walk_sph_wave(
 #define NEFF_C 20.625f
 #define GRADW_C 91.91197457030109f
 
+// Work slots of the SPH calls (slots 8 - 12 belong to the SN calls).
 enum {
     W_H = 0, W_RAD, W_ACT, W_FLAG, W_VEL, W_SPH, W_STAT,
     // long-list groups: chunk counts, item offsets, group list, items, Newton
     // state per slot, partial sums, finished flags
-    W_HV, W_HOFF, W_HLIST, W_ITEM, W_HST, W_PART, W_PARTV, W_GD
+    W_HV = 13, W_HOFF, W_HLIST, W_ITEM, W_HST, W_PART, W_PARTV, W_GD
 };
+static_assert(W_GD < 24, "work slots");
 
 static int work(gx_ctx* ctx, int k, size_t bytes, void** p) {
     GX_TRY(gx_reserve(ctx, ctx->sph_work[k], bytes));
