@@ -93,9 +93,10 @@ __global__ __launch_bounds__(GF_THREADS) void k_grav_force(
     const double cx = (gn.lo[0] + gn.hi[0]) * 0.5;
     const double cy = (gn.lo[1] + gn.hi[1]) * 0.5;
     const double cz = (gn.lo[2] + gn.hi[2]) * 0.5;
-    // slices: pad lanes hold the receivers once; 256 / pad slices split each tile
-    int pad = 32;
-    while (pad < nG && pad < GF_THREADS) pad <<= 1;
+    // slices: pad = nG lanes hold the receivers once and floor(256 / nG)
+    // slices split each tile, so at most nG - 1 lanes of the block idle (the
+    // slices are combined through LDS, any width works)
+    const int pad = nG < 1 ? 1 : nG;
     const int nsl = GF_THREADS / pad, il = tid % pad, sl = tid / pad;
     const int npp = (int)pp_tot[g];
     // list of this group: fixed slots (stride > 0) or CSR offsets
