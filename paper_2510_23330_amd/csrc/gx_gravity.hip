@@ -129,15 +129,27 @@ __global__ __launch_bounds__(GF_THREADS) void k_grav_force(
                 for (int k = lo; k < hi; k++) jidx[k - ch] = b + (k - c);
             }
             __syncthreads();
+            // each thread's source of the next tile is read into registers
+            // while the current tile is evaluated
+            V4<T> npa{};
+            T npe = 0;
+            auto fetch_src = [&](int t) {
+                if (t < che) {
+                    const int j = jidx[t - ch];
+                    const double4 p = pos4[j];
+                    npa = V4<T>{(T)(p.x - cx), (T)(p.y - cy), (T)(p.z - cz), (T)p.w};
+                    npe = (T)e2s[j];
+                }
+            };
+            fetch_src(ch + tid);
             for (int t0 = ch; t0 < che; t0 += GF_TILE) {
                 const int tn = min(GF_TILE, che - t0);
                 if (tid < tn) {
-                    const int j = jidx[t0 - ch + tid];
-                    const double4 p = pos4[j];
-                    sA[tid] = V4<T>{(T)(p.x - cx), (T)(p.y - cy), (T)(p.z - cz), (T)p.w};
-                    sB[tid].x = (T)e2s[j];
+                    sA[tid] = npa;
+                    sB[tid].x = npe;
                 }
                 __syncthreads();
+                fetch_src(t0 + GF_TILE + tid);
                 if (act) {
                     T fx = 0, fy = 0, fz = 0, fp = 0;
                     const int per = (tn + nsl - 1) / nsl;
@@ -170,19 +182,31 @@ __global__ __launch_bounds__(GF_THREADS) void k_grav_force(
         }
 
         // ---- particle-cell part: accepted cells -----------------------------
+        // each thread's record of the next tile is read into registers while
+        // the current tile is evaluated
+        V4<T> na{}, nb{}, nc{};
+        auto fetch_cell = [&](int64_t t) {
+            if (t < c1) {
+                const MomRec mr = mom[pc_list[t]];
+                na = V4<T>{(T)(mr.cx - cx), (T)(mr.cy - cy), (T)(mr.cz - cz), (T)mr.M};
+                nb = V4<T>{(T)mr.e2, (T)mr.q[0], (T)mr.q[1], (T)mr.q[2]};
+                nc = V4<T>{(T)mr.q[3], (T)mr.q[4], (T)mr.q[5], (T)0};
+            }
+        };
+        fetch_cell(c0 + tid);
         for (int64_t t0 = c0; t0 < c1; t0 += GF_TILE) {
             const int tn = (int)min((int64_t)GF_TILE, c1 - t0);
             if (tid < tn) {
-                const MomRec mr = mom[pc_list[t0 + tid]];
-                sA[tid] = V4<T>{(T)(mr.cx - cx), (T)(mr.cy - cy), (T)(mr.cz - cz), (T)mr.M};
+                sA[tid] = na;
                 if (QUAD) {
-                    sB[tid] = V4<T>{(T)mr.e2, (T)mr.q[0], (T)mr.q[1], (T)mr.q[2]};
-                    sC[tid] = V4<T>{(T)mr.q[3], (T)mr.q[4], (T)mr.q[5], (T)0};
+                    sB[tid] = nb;
+                    sC[tid] = nc;
                 } else {
-                    sB[tid].x = (T)mr.e2;
+                    sB[tid].x = nb.x;
                 }
             }
             __syncthreads();
+            fetch_cell(t0 + GF_TILE + tid);
             if (act) {
                 T fx = 0, fy = 0, fz = 0, fp = 0;
                 const int per = (tn + nsl - 1) / nsl;
