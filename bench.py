@@ -50,8 +50,8 @@ FLOP_FORCE = 101                     # per SPH force candidate pair (Table 4)
 # known size (hbm_calib.py: FETCH_SIZE reads half the bytes copied, WRITE_SIZE
 # all of them).  Valid only for the kernel source with this SHA-256; any
 # change to gx_gravity.hip makes the bench report null until remeasured.
-GRAV_TRAFFIC = {"source_sha256": "50fc688e0d0613a2daee320263c644c1817ca54ed45e4bad78e112a8c6ef1fd9",
-                "fetch_kib": 4235088.6875, "write_kib": 2004601.53125,
+GRAV_TRAFFIC = {"source_sha256": "ef8d9680b32478b4a20967e7c22c98c122aef1a12845c1e52e9e6654a8379443",
+                "fetch_kib": 4224040.0625, "write_kib": 2004640.03125,
                 "fetch_scale": 2.0, "write_scale": 1.0}
 
 
