@@ -93,10 +93,11 @@ __global__ __launch_bounds__(GF_THREADS) void k_grav_force(
     const double cx = (gn.lo[0] + gn.hi[0]) * 0.5;
     const double cy = (gn.lo[1] + gn.hi[1]) * 0.5;
     const double cz = (gn.lo[2] + gn.hi[2]) * 0.5;
-    // slices: pad = nG lanes hold the receivers once and floor(256 / nG)
-    // slices split each tile, so at most nG - 1 lanes of the block idle (the
-    // slices are combined through LDS, any width works)
-    const int pad = nG < 1 ? 1 : nG;
+    // slices: pad = min(nG, 256) lanes hold the receivers once and
+    // floor(256 / pad) slices split each tile, so fewer than pad lanes of the
+    // block idle (the slices are combined through LDS, any width works);
+    // groups above 256 take several passes over their receivers
+    const int pad = nG < 1 ? 1 : (nG < GF_THREADS ? nG : GF_THREADS);
     const int nsl = GF_THREADS / pad, il = tid % pad, sl = tid / pad;
     const int npp = (int)pp_tot[g];
     // list of this group: fixed slots (stride > 0) or CSR offsets

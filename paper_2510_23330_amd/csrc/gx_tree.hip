@@ -60,17 +60,25 @@ __global__ __launch_bounds__(256) void k_box_partial(int64_t n, const double* __
     }
 }
 
-__global__ void k_box_final(const double* __restrict__ part, int nb, double* __restrict__ box) {
-    if (threadIdx.x != 0) return;
+// One wave: lane-strided partial minima/maxima, then across the wave (exact
+// in any order).
+__global__ __launch_bounds__(64) void k_box_final(const double* __restrict__ part, int nb,
+                                                  double* __restrict__ box) {
     double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     double emin = INFINITY;
-    for (int b = 0; b < nb; b++) {
+    for (int b = threadIdx.x; b < nb; b += 64) {
         for (int d = 0; d < 3; d++) {
             mn[d] = fmin(mn[d], part[b * 8 + d]);
             mx[d] = fmax(mx[d], part[b * 8 + 3 + d]);
         }
         emin = fmin(emin, part[b * 8 + 6]);
     }
+    for (int d = 0; d < 3; d++) {
+        mn[d] = wave_min(mn[d]);
+        mx[d] = wave_max(mx[d]);
+    }
+    emin = wave_min(emin);
+    if (threadIdx.x != 0) return;
     double ext = 0.0;
     for (int d = 0; d < 3; d++) {
         double e = mx[d] - mn[d];

@@ -151,18 +151,20 @@ def test_direct_fp64_mode_matches_oracle(gx, eng):
     assert np.max(np.abs(pot - o[3]) / np.abs(o[3])) <= 1e-12
 
 
-@pytest.mark.parametrize("quad", [True, False])
-def test_tree_fp32_vs_oracle_tree(gx, eng, quad):
+# n_group 600: groups above one 256-lane block (several receiver passes);
+# n_group 16: many receiver slices per block.
+@pytest.mark.parametrize("quad,ngr", [(True, 256), (False, 256), (True, 600), (True, 16)])
+def test_tree_fp32_vs_oracle_tree(gx, eng, quad, ngr):
     # Same lists on both sides: only FP32 rounding separates them.
     d = ics.disk_galaxy(60000, 6)
     G = ics.G_KPC
     p = _dev(gx, d)
-    eng.tree_build(p, gx.GX_TREE_ALL, 16, 256)
+    eng.tree_build(p, gx.GX_TREE_ALL, 16, ngr)
     out = _zeros(p.n)
     flags = gx.GX_QUAD if quad else 0
     st = eng.gravity_forces(p, G, 0.5, flags, *out)
     ax, ay, az, pot = _np(out)
-    t = oracle.Tree(d, 16, 256).gravity(G, 0.5, quad)
+    t = oracle.Tree(d, 16, ngr).gravity(G, 0.5, quad)
     err = _relerr((ax, ay, az), t[:3])
     assert np.percentile(err, 99) <= 1e-5
     assert np.max(np.abs(pot - t[3]) / np.abs(t[3])) <= 1e-5
