@@ -311,10 +311,14 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density(
     if (active && !active[g]) return;
     const GroupList GL(L, g);
     const int npp = GL.npp;
-    if (npp > SPH_CAP) {  // long list: chunked over several workgroups
+    const NodeRec B = nodes[groups[g]];
+    const int nG = B.end - B.begin;
+    if (npp > SPH_CAP && nG <= 64) {  // long list: chunked over several workgroups
         if (threadIdx.x == 0) hv[g] = (uint32_t)((npp + SPH_CAP - 1) / SPH_CAP);
         return;
     }
+    // (a long list of a group above 64 receivers is evaluated here chunk by chunk)
+    const bool in_lds = npp <= SPH_CAP;
     __shared__ float4 cand[SPH_CAP];
     __shared__ float2 red[SPH_DT / 64][64];
     // hit lists; the list expansion uses the same space (slot + range
@@ -325,14 +329,12 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density(
     int* const xslot = reinterpret_cast<int*>(&hl[0][0]);
     int* const xroff = xslot + SPH_CAP;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const NodeRec B = nodes[groups[g]];
-    const int nG = B.end - B.begin;
     const int pad = slice_pad(nG), nsl = SPH_DT / pad, il = tid % pad, sl = tid / pad;
     const double cx = (B.lo[0] + B.hi[0]) * 0.5;
     const double cy = (B.lo[1] + B.hi[1]) * 0.5;
     const double cz = (B.lo[2] + B.hi[2]) * 0.5;
     const float Rlim = rad[g];
-    expand_chunk(GL, npp, 0, npp, pos4, cx, cy, cz, cand, xslot, xroff, wtot, tid, SPH_DT);
+    if (in_lds) expand_chunk(GL, npp, 0, npp, pos4, cx, cy, cz, cand, xslot, xroff, wtot, tid, SPH_DT);
     __syncthreads();
 
     int nflag = 0, nfail = 0, worst_it = 0;
@@ -361,14 +363,28 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density(
             evals += pass_evals;
             const float Hinv = 1.0f / H, Hinv2 = Hinv * Hinv;
             float s0 = 0.0f, s1 = 0.0f;
-            const bool stale = __syncthreads_or(act && H > SPH_KAPPA * Hb);
-            if (!have || stale) {
-                Hb = H;
-                const bool flushed = dens_scan(hl, nh, tid, sl, nsl, npp, act, cand, xi, yi, zi,
-                                               (SPH_KAPPA * SPH_KAPPA) * H * H, Hinv2, s0, s1);
-                have = !__syncthreads_or(flushed);
+            if (in_lds) {
+                const bool stale = __syncthreads_or(act && H > SPH_KAPPA * Hb);
+                if (!have || stale) {
+                    Hb = H;
+                    const bool flushed = dens_scan(hl, nh, tid, sl, nsl, npp, act, cand, xi, yi,
+                                                   zi, (SPH_KAPPA * SPH_KAPPA) * H * H, Hinv2, s0,
+                                                   s1);
+                    have = !__syncthreads_or(flushed);
+                }
+                dens_hits(hl, nh, tid, cand, xi, yi, zi, Hinv2, s0, s1);
+            } else {
+                for (int ch = 0; ch < npp; ch += SPH_CAP) {
+                    const int che = min(npp, ch + SPH_CAP);
+                    __syncthreads();
+                    expand_chunk(GL, npp, ch, che, pos4, cx, cy, cz, cand, xslot, xroff, wtot,
+                                 tid, SPH_DT);
+                    __syncthreads();
+                    dens_scan(hl, nh, tid, sl, nsl, che - ch, act, cand, xi, yi, zi, H * H, Hinv2,
+                              s0, s1);
+                    dens_hits(hl, nh, tid, cand, xi, yi, zi, Hinv2, s0, s1);
+                }
             }
-            dens_hits(hl, nh, tid, cand, xi, yi, zi, Hinv2, s0, s1);
             // slices of this wave, then the four waves in order
             s0 = slice_sum(s0, pad);
             s1 = slice_sum(s1, pad);
@@ -738,7 +754,7 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_force(
     }
     const GroupList GL(L, g);
     const int npp = GL.npp;
-    if (!PART && npp > SPH_CAP) {
+    if (!PART && npp > SPH_CAP && nodes[groups[g]].end - nodes[groups[g]].begin <= 64) {
         if (threadIdx.x == 0) hv[g] = (uint32_t)((npp + SPH_CAP - 1) / SPH_CAP);
         return;
     }

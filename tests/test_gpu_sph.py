@@ -46,17 +46,24 @@ def _density(gx, eng, d, n_group=64, n_leaf=8, H_guess=None):
 # "slab": sparse particles whose kernels reach into a dense slab give groups
 # with candidate lists far longer than one workgroup holds, which take the
 # chunked path (partial sums over many workgroups).
-@pytest.mark.parametrize("case", ["sphere", "lattice", "disk_gas", "slab"])
+# "slab128": a denser sparse layer and groups of up to 128 receivers; groups
+# above 64 receivers with long lists are evaluated chunk by chunk inside one
+# workgroup instead.
+@pytest.mark.parametrize("case", ["sphere", "lattice", "disk_gas", "slab", "slab128"])
 def test_density_matches_oracle(gx, eng, case):
+    ngr = 64
     if case == "sphere":
         d = ics.gas_sphere(8192, 2)
     elif case == "lattice":
         d = ics.lattice(20, jitter=0.05)
     elif case == "slab":
         d = ics.slab_and_sparse()
+    elif case == "slab128":
+        d = ics.slab_and_sparse(n_slab=20000, n_sparse=2400, height=0.12)
+        ngr = 128
     else:
         d = ics.gas_view(ics.disk_galaxy(200_000, 3))
-    p, g, st = _density(gx, eng, d)
+    p, g, st = _density(gx, eng, d, n_group=ngr)
     assert st["n_noconv"] == 0
     Ho, rho_o, it, nf, S = oracle.sph_density(d, 64.0, 1e-10, 200, with_slope=True)
     assert nf == 0
@@ -80,24 +87,27 @@ def test_density_warm_start_iterations(gx, eng):
     assert st["n_rewalk"] == 0
 
 
-def _force(gx, eng, d, Ho, rho_o, alpha=1.0):
+def _force(gx, eng, d, Ho, rho_o, alpha=1.0, n_group=64):
     import torch
     p = gx.ParticleSet.from_numpy(d)
     g = gx.GasState.zeros(p.n, u=d["u"])
     g.H.copy_(torch.as_tensor(Ho.astype(np.float32), device="cuda"))
     g.rho.copy_(torch.as_tensor(rho_o.astype(np.float32), device="cuda"))
-    eng.tree_build(p, gx.GX_TREE_GAS, 8, 64)
+    eng.tree_build(p, gx.GX_TREE_GAS, 8, n_group)
     acc = [torch.zeros(p.n, dtype=torch.float64, device="cuda") for _ in range(3)]
     st = eng.sph_forces(p, g, *acc, gamma=GAMMA, alpha=alpha)
     return [a.cpu().numpy() for a in acc], g.dudt.cpu().numpy(), g.vsig.cpu().numpy(), st
 
 
-@pytest.mark.parametrize("case", ["sphere", "disk_gas", "converging", "slab"])
+@pytest.mark.parametrize("case", ["sphere", "disk_gas", "converging", "slab", "slab128"])
 def test_force_matches_oracle(gx, eng, case):
+    ngr = 128 if case == "slab128" else 64
     if case == "sphere":
         d = ics.gas_sphere(8192, 2)
     elif case == "slab":
         d = ics.slab_and_sparse()
+    elif case == "slab128":
+        d = ics.slab_and_sparse(n_slab=20000, n_sparse=2400, height=0.12)
     elif case == "disk_gas":
         d = ics.gas_view(ics.disk_galaxy(200_000, 3))
     else:
@@ -108,7 +118,7 @@ def test_force_matches_oracle(gx, eng, case):
     # the GPU consumes FP32 H and rho: give the oracle the same rounded values
     Hf = Ho.astype(np.float32).astype(np.float64)
     rf = rho_o.astype(np.float32).astype(np.float64)
-    a, du, vs, st = _force(gx, eng, d, Hf, rf)
+    a, du, vs, st = _force(gx, eng, d, Hf, rf, n_group=ngr)
     ox, oy, oz, odu, ovs = oracle.sph_force(d, Hf, rf, GAMMA, 1.0)
     rms = np.sqrt(np.mean(ox ** 2 + oy ** 2 + oz ** 2))
     err = np.sqrt((a[0] - ox) ** 2 + (a[1] - oy) ** 2 + (a[2] - oz) ** 2)
