@@ -5,9 +5,12 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
+#include <climits>
+#include <cstddef>
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <type_traits>
 
 #include "gx.h"
 
@@ -28,6 +31,9 @@ struct alignas(64) NodeRec {
     int8_t leaf;
     int8_t pad;
 };
+static_assert(sizeof(NodeRec) == 64 && offsetof(NodeRec, begin) == 52 &&
+              offsetof(NodeRec, level) == 60 && offsetof(NodeRec, leaf) == 62,
+              "walk kernels unpack NodeRec from four 16-byte words");
 
 // Multipole record read by the force kernel: FP64 centre of mass and mass,
 // FP32 traceless quadrupole (xx, yy, zz, xy, xz, yz) and mean eps^2.
@@ -131,15 +137,50 @@ int gx_radix_sort(gx_ctx* ctx, TreeSlot& T, int64_t n, int key_bits);
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int gx_lane() { return (int)__lane_id(); }
 
+// Inclusive scan over the wave (all 64 lanes active).  32-bit integers use
+// DPP moves (row shifts by 1, 2, 4, 8 inside each 16-lane row, then the
+// broadcasts of lane 15 to rows 1 and 3 and of lane 31 to rows 2 and 3): VALU
+// cross-lane reads with no LDS round trip.  Other types shuffle.
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v) {
+    if constexpr (std::is_integral<T>::value && sizeof(T) == 4) {
+        unsigned x = (unsigned)v;
+        x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);
+        x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);
+        x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);
+        x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);
+        x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);
+        x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);
+        return (T)x;
+    } else {
 #pragma unroll
-    for (int o = 1; o < GX_WAVE; o <<= 1) {
-        T t = __shfl_up(v, o, GX_WAVE);
-        if (gx_lane() >= o) v += t;
+        for (int o = 1; o < GX_WAVE; o <<= 1) {
+            T t = __shfl_up(v, o, GX_WAVE);
+            if (gx_lane() >= o) v += t;
+        }
+        return v;
     }
+}
+
+// Inclusive running maximum over the wave (all lanes active), by the same
+// DPP moves as wave_incl_scan; lanes with no source keep INT_MIN.
+__device__ __forceinline__ int wave_incl_max(int v) {
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x111, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x112, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x114, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x118, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x142, 0xa, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x143, 0xc, 0xf, false));
     return v;
 }
+
+// v of the next lower lane (DPP wave shift right by one); lane 0 gets fill.
+__device__ __forceinline__ int wave_prev(int v, int fill) {
+    return __builtin_amdgcn_update_dpp(fill, v, 0x138, 0xf, 0xf, false);
+}
+
+// Value of a 32-bit integer in lane 63 (wave-uniform result).
+__device__ __forceinline__ int wave_last(int v) { return __builtin_amdgcn_readlane(v, GX_WAVE - 1); }
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -284,15 +325,10 @@ __device__ __forceinline__ void list_slots(const GroupList& L, int npp, int ch, 
     int run = -1;
     for (int i = b0; i < b1; i++) run = max(run, slot[i]);
     const int lane = tid & 63, wv = tid >> 6;
-    int v = run;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(v, o, 64);
-        if (lane >= o) v = max(v, t);
-    }
+    const int v = wave_incl_max(run);
     if (lane == 63) wtot[wv] = v;
     __syncthreads();
-    int cur = __shfl_up(v, 1, 64);
-    if (lane == 0) cur = -1;
+    int cur = wave_prev(v, -1);
     for (int w = 0; w < wv; w++) cur = max(cur, wtot[w]);
     for (int i = b0; i < b1; i++) {
         cur = max(cur, slot[i]);

@@ -18,6 +18,11 @@
 
 #pragma clang fp contract(off)
 
+// FP64 value from its low and high 32-bit words (little-endian record words)
+__device__ __forceinline__ double dword2(unsigned lo, unsigned hi) {
+    return __hiloint2double((int)hi, (int)lo);
+}
+
 __device__ __forceinline__ double box_dist2(const double* glo, const double* ghi, const double* lo,
                                             const double* hi) {
     double s = 0.0;
@@ -161,17 +166,22 @@ __global__ __launch_bounds__(64) void k_walk_grav_wave(
         }
         __syncthreads();
         sp = b0;
-        // all loads of this step first: child rows and node records
+        // all loads of this step first, as whole 16-byte words into their own
+        // registers (child rows and the 64-byte node records; narrower field
+        // loads let the scheduler chain the nodes' loads one after another)
         int4 cq[GWALK_WK][2];
-        NodeRec rec[GWALK_WK];
+        uint4 rq[GWALK_WK][4];
 #pragma unroll
         for (int w = 0; w < GWALK_WK; w++) {
             cq[w][0] = cq[w][1] = make_int4(-1, -1, -1, -1);
+            rq[w][0] = rq[w][1] = rq[w][2] = rq[w][3] = make_uint4(0, 0, 0, 0);
             if (n[w] >= 0) {
                 const int4* cp = reinterpret_cast<const int4*>(child + 8 * (int64_t)n[w]);
+                const uint4* np = reinterpret_cast<const uint4*>(nodes + n[w]);
                 cq[w][0] = cp[0];
                 cq[w][1] = cp[1];
-                rec[w] = nodes[n[w]];
+#pragma unroll
+                for (int q = 0; q < 4; q++) rq[w][q] = np[q];
             }
         }
         int nch = 0;
@@ -180,18 +190,21 @@ __global__ __launch_bounds__(64) void k_walk_grav_wave(
             bool acc = false, leaf = false, open = false;
             int b = 0, e = 0;
             if (n[w] >= 0) {
-                const NodeRec& nd = rec[w];
-                double lo[3] = {nd.lo[0], nd.lo[1], nd.lo[2]};
-                double hi[3] = {nd.hi[0], nd.hi[1], nd.hi[2]};
+                // NodeRec: lo[3], hi[3] (FP64), next, begin, end, level (16 bit), leaf (8 bit)
+                const uint4* r = rq[w];
+                double lo[3] = {dword2(r[0].x, r[0].y), dword2(r[0].z, r[0].w), dword2(r[1].x, r[1].y)};
+                double hi[3] = {dword2(r[1].z, r[1].w), dword2(r[2].x, r[2].y), dword2(r[2].z, r[2].w)};
+                const int level = (int)(int16_t)(r[3].w & 0xffffu);
+                const bool isleaf = ((r[3].w >> 16) & 0xffu) != 0;
                 double d2 = box_dist2(G.lo, G.hi, lo, hi);
-                double lc = ldexp(L, -(int)nd.level);
+                double lc = ldexp(L, -level);
                 double lhs = lc * lc;
                 double rhs = theta2 * d2;
                 acc = lhs < rhs;
-                leaf = !acc && nd.leaf;
-                open = !acc && !nd.leaf;
-                b = nd.begin;
-                e = nd.end;
+                leaf = !acc && isleaf;
+                open = !acc && !isleaf;
+                b = (int)r[3].y;
+                e = (int)r[3].z;
             }
             // accepted cells
             const uint64_t am = __ballot(acc);
@@ -212,7 +225,7 @@ __global__ __launch_bounds__(64) void k_walk_grav_wave(
                 }
             }
             npr += __popcll(lm);
-            npp += __shfl(incl, 63, 64);
+            npp += wave_last(incl);
             if (!open) {
                 cq[w][0] = cq[w][1] = make_int4(-1, -1, -1, -1);
             } else {
@@ -223,7 +236,7 @@ __global__ __launch_bounds__(64) void k_walk_grav_wave(
         }
         // children of opened internal nodes onto the stack (lane order, then w)
         const int cincl = wave_incl_scan(nch);
-        const int ctot = __shfl(cincl, 63, 64);
+        const int ctot = wave_last(cincl);
         if (sp + ctot > GWALK_STACK) {
             over = 1;
         } else {
@@ -467,7 +480,7 @@ __global__ __launch_bounds__(64) void k_walk_sph_bfs(
                 }
             }
             nout += __popcll(em);
-            npp += __shfl(incl, 63, 64);
+            npp += wave_last(incl);
             // open internal nodes
             int nch = 0;
             const int32_t ch[8] = {cq0.x, cq0.y, cq0.z, cq0.w, cq1.x, cq1.y, cq1.z, cq1.w};
@@ -480,7 +493,7 @@ __global__ __launch_bounds__(64) void k_walk_sph_bfs(
             for (int k = 0; k < nch; k++) {
                 if (coff + k < BFS_FMAX) fr[cur ^ 1][coff + k] = ch[k];
             }
-            ncnt += __shfl(cincl, 63, 64);
+            ncnt += wave_last(cincl);
         }
         __syncthreads();
         if (ncnt > BFS_FMAX) {
@@ -574,7 +587,7 @@ __global__ __launch_bounds__(64) void k_walk_sph_wave(
             pr_cum[pos] = npp + incl - sz;
         }
         nout += __popcll(em);
-        npp += __shfl(incl, 63, 64);
+        npp += wave_last(incl);
         int nch = 0;
         const int32_t ch[8] = {cq0.x, cq0.y, cq0.z, cq0.w, cq1.x, cq1.y, cq1.z, cq1.w};
         if (inter && !leaf) {
@@ -582,7 +595,7 @@ __global__ __launch_bounds__(64) void k_walk_sph_wave(
             for (int k = 0; k < 8; k++) nch += ch[k] >= 0;
         }
         const int cincl = wave_incl_scan(nch);
-        const int ctot = __shfl(cincl, 63, 64);
+        const int ctot = wave_last(cincl);
         if (sp + ctot > WDFS_STACK) {
             over = 1;
         } else {
