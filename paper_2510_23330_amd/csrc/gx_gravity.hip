@@ -30,11 +30,12 @@ __global__ __launch_bounds__(128) void k_walk_grav(
     int32_t* __restrict__ pc_list, const int64_t* __restrict__ pr_off,
     int32_t* __restrict__ pr_begin, int32_t* __restrict__ pr_cum, int cap_pc, int cap_pr);
 __global__ __launch_bounds__(64) void k_walk_grav_wave(
-    int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes,
-    const int32_t* __restrict__ child, const double* __restrict__ box, double theta2,
-    uint32_t* __restrict__ pc_cnt, uint32_t* __restrict__ pr_cnt, uint32_t* __restrict__ pp_tot,
-    int32_t* __restrict__ pc_list, int32_t* __restrict__ pr_begin, int32_t* __restrict__ pr_cum,
-    int cap_pc, int cap_pr, uint8_t* __restrict__ gflag, int32_t* __restrict__ gdepth);
+    int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes, int64_t nn,
+    const double* __restrict__ wbox, const int4* __restrict__ wrec,
+    const double* __restrict__ box, double theta2, uint32_t* __restrict__ pc_cnt,
+    uint32_t* __restrict__ pr_cnt, uint32_t* __restrict__ pp_tot, int32_t* __restrict__ pc_list,
+    int32_t* __restrict__ pr_begin, int32_t* __restrict__ pr_cum, int cap_pc, int cap_pr,
+    uint8_t* __restrict__ gflag, int32_t* __restrict__ gdepth);
 __global__ __launch_bounds__(256) void k_group_totals(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ recv,
     const NodeRec* __restrict__ nodes, const uint32_t* __restrict__ c0,
@@ -345,9 +346,11 @@ extern "C" int gx_gravity_forces(gx_ctx* ctx, const gx_particles* p, double G, d
             GX_TRY(gx_reserve(ctx, Ls.aux, (size_t)ng * (1 + sizeof(int32_t)) + 64));
             uint8_t* gflag = (uint8_t*)Ls.aux.p;
             int32_t* gdepth = (int32_t*)((uint8_t*)Ls.aux.p + (((size_t)ng + 15) & ~(size_t)15));
+            GX_TRY(gx_walk_tree(ctx, T));
             hipLaunchKernelGGL(k_walk_grav_wave, dim3(xcd_grid(ng)), dim3(64), 0, st, ng,
                                (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
-                               (const int32_t*)T.child.p, (const double*)T.box.p, theta2,
+                               (int64_t)T.n_nodes, (const double*)T.wbox.p,
+                               (const int4*)T.wrec.p, (const double*)T.box.p, theta2,
                                (uint32_t*)Ls.pc_cnt.p, (uint32_t*)Ls.pr_cnt.p,
                                (uint32_t*)Ls.pp_tot.p, (int32_t*)Ls.pc_list.p,
                                (int32_t*)Ls.pr_begin.p, (int32_t*)Ls.pr_cum.p, Ls.cap_pc,

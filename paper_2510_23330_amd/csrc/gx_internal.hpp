@@ -6,7 +6,6 @@
 
 #include <cstdarg>
 #include <climits>
-#include <cstddef>
 #include <cstdint>
 #include <cstdio>
 #include <string>
@@ -29,11 +28,9 @@ struct alignas(64) NodeRec {
     int32_t end;
     int16_t level;
     int8_t leaf;
-    int8_t pad;
+    int8_t nchild;  // number of children (internal nodes; set with the child rows)
 };
-static_assert(sizeof(NodeRec) == 64 && offsetof(NodeRec, begin) == 52 &&
-              offsetof(NodeRec, level) == 60 && offsetof(NodeRec, leaf) == 62,
-              "walk kernels unpack NodeRec from four 16-byte words");
+static_assert(sizeof(NodeRec) == 64, "one node record per 64-byte line");
 
 // Multipole record read by the force kernel: FP64 centre of mass and mass,
 // FP32 traceless quadrupole (xx, yy, zz, xy, xz, yz) and mean eps^2.
@@ -64,6 +61,12 @@ struct TreeSlot {
     Buf groups;          // int32 node id of each group (pre-order)
     Buf blocks;          // NodeRec per SPH receiver block (64 consecutive sorted slots)
     Buf box;             // double[8]: x0, y0, z0, L, 2^21/L, min eps^2
+    // gravity walk copy of the tree in level order (children of a node are
+    // consecutive): sort buffers, six FP64 box arrays (lo x y z, hi x y z, each
+    // n_nodes long) and one int4 per node {pre-order id, level | leaf << 16 |
+    // nchild << 24, first child (internal) or particle begin (leaf), end}
+    Buf wkey[2], wval[2], wbox, wrec;
+    int walk_ready = 0;
     int64_t n_nodes = 0, n_groups = 0, n_blocks = 0;
     int64_t lvl_hist[GX_MAX_LEVEL + 1] = {};
     int32_t* perm() const { return (int32_t*)val[0].p; }
@@ -131,6 +134,10 @@ int gx_scan(gx_ctx* ctx, const TI* in, TO* out, int64_t n, TO* total);
 
 // Stable LSD radix sort of (u64 key, u32 value) pairs; result in slot 0.
 int gx_radix_sort(gx_ctx* ctx, TreeSlot& T, int64_t n, int key_bits);
+// The same on caller buffers key[0..1], val[0..1] (input in slot 0).
+int gx_radix_sort_bufs(gx_ctx* ctx, Buf* key, Buf* val, int64_t n, int key_bits);
+// Level-order walk arrays of a built tree (kept until the next build).
+int gx_walk_tree(gx_ctx* ctx, TreeSlot& T);
 
 // ---------------------------------------------------------------------------
 // Device helpers

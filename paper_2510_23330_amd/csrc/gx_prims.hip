@@ -93,7 +93,8 @@ extern "C" int gx_destroy(gx_ctx* ctx) {
     for (auto& T : ctx->tree) {
         for (auto* b : {&T.key[0], &T.key[1], &T.val[0], &T.val[1], &T.pos4, &T.e2s, &T.win,
                         &T.cnt, &T.lmax, &T.nodes, &T.mom, &T.q64, &T.parent, &T.child, &T.lvl_ids,
-                        &T.lvl_fill, &T.flag, &T.groups, &T.blocks, &T.box})
+                        &T.lvl_fill, &T.flag, &T.groups, &T.blocks, &T.box, &T.wkey[0], &T.wkey[1],
+                        &T.wval[0], &T.wval[1], &T.wbox, &T.wrec})
             free_buf(*b);
     }
     for (auto* L : {&ctx->grav, &ctx->sph})
@@ -286,6 +287,10 @@ __global__ void k_iota(uint32_t* v, int64_t n) {
 }
 
 int gx_radix_sort(gx_ctx* ctx, TreeSlot& T, int64_t n, int key_bits) {
+    return gx_radix_sort_bufs(ctx, T.key, T.val, n, key_bits);
+}
+
+int gx_radix_sort_bufs(gx_ctx* ctx, Buf* key, Buf* val, int64_t n, int key_bits) {
     int nblk = (int)((n + RS_TILE - 1) / RS_TILE);
     int64_t nh = (int64_t)256 * nblk;
     GX_TRY(gx_reserve(ctx, ctx->hist, nh * sizeof(uint32_t)));
@@ -294,10 +299,10 @@ int gx_radix_sort(gx_ctx* ctx, TreeSlot& T, int64_t n, int key_bits) {
     int cur = 0;
     for (int p = 0; p < npass; p++) {
         int shift = 8 * p;
-        uint64_t* kin = (uint64_t*)T.key[cur].p;
-        uint32_t* vin = (uint32_t*)T.val[cur].p;
-        uint64_t* kout = (uint64_t*)T.key[cur ^ 1].p;
-        uint32_t* vout = (uint32_t*)T.val[cur ^ 1].p;
+        uint64_t* kin = (uint64_t*)key[cur].p;
+        uint32_t* vin = (uint32_t*)val[cur].p;
+        uint64_t* kout = (uint64_t*)key[cur ^ 1].p;
+        uint32_t* vout = (uint32_t*)val[cur ^ 1].p;
         hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(256), 0, ctx->stream, kin, n, shift, hist, nblk);
         GX_TRY((gx_scan<uint32_t, uint32_t>(ctx, hist, hist, nh, nullptr)));
         hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(256), 0, ctx->stream, kin, vin, kout, vout,
@@ -306,8 +311,8 @@ int gx_radix_sort(gx_ctx* ctx, TreeSlot& T, int64_t n, int key_bits) {
         cur ^= 1;
     }
     if (cur != 0) {  // leave the result in slot 0
-        std::swap(T.key[0], T.key[1]);
-        std::swap(T.val[0], T.val[1]);
+        std::swap(key[0], key[1]);
+        std::swap(val[0], val[1]);
     }
     return GX_OK;
 }

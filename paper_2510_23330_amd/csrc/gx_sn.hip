@@ -378,7 +378,7 @@ __global__ void k_vox_blocks(int k, int grid, double half, const double* __restr
     r.end = 64;
     r.level = -1;
     r.leaf = 0;
-    r.pad = 0;
+    r.nchild = 0;
     recv[e] = r;
     rad[e] = 0.0f;
 }

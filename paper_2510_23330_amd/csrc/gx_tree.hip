@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256) void k_node_emit(int64_t n, const uint64_t* __
             r.end = (int32_t)end;
             r.level = (int16_t)l;
             r.leaf = (int8_t)(l == Li);
-            r.pad = 0;
+            r.nchild = 0;
             r.next = (int32_t)(end < n ? (int64_t)base[end] : n_nodes);
             r.lo[0] = r.lo[1] = r.lo[2] = 0.0;
             r.hi[0] = r.hi[1] = r.hi[2] = 0.0;
@@ -269,8 +269,8 @@ __global__ __launch_bounds__(256) void k_node_emit(int64_t n, const uint64_t* __
 }
 
 // Parent of every node and the (up to 8) children of every internal node in
-// key order, -1 padded (child[8 p + k]).
-__global__ __launch_bounds__(256) void k_node_parent(int64_t nn, const NodeRec* __restrict__ nodes,
+// key order, -1 padded (child[8 p + k]); their number goes to nodes[p].nchild.
+__global__ __launch_bounds__(256) void k_node_parent(int64_t nn, NodeRec* __restrict__ nodes,
                                                      int32_t* __restrict__ parent,
                                                      int32_t* __restrict__ child) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -284,6 +284,7 @@ __global__ __launch_bounds__(256) void k_node_parent(int64_t nn, const NodeRec* 
             child[8 * p + k++] = c;
         }
     }
+    nodes[p].nchild = (int8_t)k;
     for (; k < 8; k++) child[8 * p + k] = -1;
 }
 
@@ -426,7 +427,7 @@ __global__ __launch_bounds__(64) void k_blocks(int64_t n, const double4* __restr
         r.next = -1;
         r.level = -1;
         r.leaf = 0;
-        r.pad = 0;
+        r.nchild = 0;
         blk[b] = r;
     }
 }
@@ -461,6 +462,7 @@ extern "C" int gx_tree_build(gx_ctx* ctx, const gx_particles* p, int which, int 
     }
     TreeSlot& T = ctx->tree[which];
     T.built = 0;
+    T.walk_ready = 0;
     const int64_t n = p->n;
     hipStream_t st = ctx->stream;
 
@@ -542,7 +544,7 @@ extern "C" int gx_tree_build(gx_ctx* ctx, const gx_particles* p, int which, int 
                        (const int8_t*)T.lmax.p, nn, (NodeRec*)T.nodes.p, lvl_aux, lvl_hist,
                        (int32_t*)T.lvl_ids.p);
     hipLaunchKernelGGL(k_node_parent, dim3(gx_blocks(nn, 256)), dim3(256), 0, st, nn,
-                       (const NodeRec*)T.nodes.p, (int32_t*)T.parent.p, (int32_t*)T.child.p);
+                       (NodeRec*)T.nodes.p, (int32_t*)T.parent.p, (int32_t*)T.child.p);
     GX_LAUNCH_CHECK(ctx);
     for (int l = GX_MAX_LEVEL; l >= 0; l--) {
         int c = (int)T.lvl_hist[l];

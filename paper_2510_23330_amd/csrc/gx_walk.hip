@@ -18,20 +18,14 @@
 
 #pragma clang fp contract(off)
 
-// FP64 value from its low and high 32-bit words (little-endian record words)
-__device__ __forceinline__ double dword2(unsigned lo, unsigned hi) {
-    return __hiloint2double((int)hi, (int)lo);
-}
-
 __device__ __forceinline__ double box_dist2(const double* glo, const double* ghi, const double* lo,
                                             const double* hi) {
     double s = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-        double t1 = lo[d] - ghi[d];
-        double t2 = glo[d] - hi[d];
-        double t = t1 > t2 ? t1 : t2;
-        t = t < 0.0 ? 0.0 : t;
+        // max(0, lo - ghi, glo - hi); fmax gives the same square as the
+        // compare-and-select form (boxes hold no NaN; a -0 squares to +0)
+        const double t = fmax(fmax(lo[d] - ghi[d], glo[d] - hi[d]), 0.0);
         double tt = t * t;
         s = s + tt;
     }
@@ -125,25 +119,97 @@ __global__ __launch_bounds__(128) void k_walk_grav(
     }
 }
 
+// Level-order copy of the tree for the gravity walk.  Sorting the nodes by
+// level (stable, so each level keeps pre-order) makes the children of every
+// node consecutive, and the children of consecutive nodes follow one another.
+// The walk then needs only a node's first child and child count, and the
+// nodes one wavefront pops together (children of consecutively popped nodes)
+// sit side by side in the arrays: a 64-lane load of one field touches a few
+// cache lines instead of one line per lane.
+__global__ __launch_bounds__(256) void k_lvl_keys(int64_t nn, const NodeRec* __restrict__ nodes,
+                                                  uint64_t* __restrict__ key,
+                                                  uint32_t* __restrict__ val) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nn) return;
+    key[i] = (uint64_t)(uint16_t)nodes[i].level;
+    val[i] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(256) void k_lvl_pos(int64_t nn, const uint32_t* __restrict__ order,
+                                                 int32_t* __restrict__ pos) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nn) return;
+    pos[order[i]] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(256) void k_walk_arrays(int64_t nn, const uint32_t* __restrict__ order,
+                                                     const int32_t* __restrict__ pos,
+                                                     const NodeRec* __restrict__ nodes,
+                                                     double* __restrict__ wbox,
+                                                     int4* __restrict__ wrec) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nn) return;
+    const int32_t p = (int32_t)order[i];
+    const NodeRec nd = nodes[p];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        wbox[d * nn + i] = nd.lo[d];
+        wbox[(3 + d) * nn + i] = nd.hi[d];
+    }
+    const uint32_t meta = (uint32_t)(uint16_t)nd.level | ((uint32_t)(uint8_t)nd.leaf << 16) |
+                          ((uint32_t)(uint8_t)nd.nchild << 24);
+    // the first child of an internal node follows it in pre-order
+    const int32_t a = nd.leaf ? nd.begin : (nd.nchild > 0 ? pos[p + 1] : 0);
+    wrec[i] = make_int4(p, (int32_t)meta, a, nd.end);
+}
+
+int gx_walk_tree(gx_ctx* ctx, TreeSlot& T) {
+    if (T.walk_ready) return GX_OK;
+    const int64_t nn = T.n_nodes;
+    if (nn <= 0 || nn >= ((int64_t)1 << 31) / 8)
+        return gx_fail(ctx, GX_EINVAL, "walk arrays: %lld nodes", (long long)nn);
+    hipStream_t st = ctx->stream;
+    for (int k = 0; k < 2; k++) {
+        GX_TRY(gx_reserve(ctx, T.wkey[k], nn * sizeof(uint64_t)));
+        GX_TRY(gx_reserve(ctx, T.wval[k], nn * sizeof(uint32_t)));
+    }
+    GX_TRY(gx_reserve(ctx, T.wbox, 6 * nn * sizeof(double)));
+    GX_TRY(gx_reserve(ctx, T.wrec, nn * sizeof(int4)));
+    hipLaunchKernelGGL(k_lvl_keys, dim3(gx_blocks(nn, 256)), dim3(256), 0, st, nn,
+                       (const NodeRec*)T.nodes.p, (uint64_t*)T.wkey[0].p, (uint32_t*)T.wval[0].p);
+    GX_LAUNCH_CHECK(ctx);
+    GX_TRY(gx_radix_sort_bufs(ctx, T.wkey, T.wval, nn, 8));  // levels < 256: one pass
+    hipLaunchKernelGGL(k_lvl_pos, dim3(gx_blocks(nn, 256)), dim3(256), 0, st, nn,
+                       (const uint32_t*)T.wval[0].p, (int32_t*)T.wval[1].p);
+    hipLaunchKernelGGL(k_walk_arrays, dim3(gx_blocks(nn, 256)), dim3(256), 0, st, nn,
+                       (const uint32_t*)T.wval[0].p, (const int32_t*)T.wval[1].p,
+                       (const NodeRec*)T.nodes.p, (double*)T.wbox.p, (int4*)T.wrec.p);
+    GX_LAUNCH_CHECK(ctx);
+    T.walk_ready = 1;
+    return GX_OK;
+}
+
 // Wave-cooperative gravity walk into per-group slots (the one-pass mode of
-// k_walk_grav): one wavefront per group, an LDS stack of pending nodes; each
-// step pops up to GWALK_WK x 64 nodes (GWALK_WK per lane, so that as many
-// node records are in flight per round trip to memory), applies the opening
-// criterion in the same IEEE sequence, appends accepted cells and opened
-// leaves to the slots by ballot compaction and pushes the children of opened
-// internal nodes.  Lists come out in a different order than the stackless
-// walk's (the same sets).  Per group it writes the list sizes, an overflow
-// flag (slot or stack) and the deepest stack; k_group_totals then forms the
-// totals (the caller builds the lists in two passes when any group
-// overflowed).
+// k_walk_grav) over the level-order arrays: one wavefront per group, an LDS
+// stack of pending level-order positions; each step pops up to GWALK_WK x 64
+// nodes (GWALK_WK per lane, so that as many node reads are in flight per
+// round trip to memory), applies the opening criterion in the same IEEE
+// sequence, appends accepted cells (by pre-order id) and opened leaves to the
+// slots by ballot compaction and pushes the children of opened internal
+// nodes in the order the nodes were popped.  Lists come out in a different
+// order than the stackless walk's (the same sets).  Per group it writes the
+// list sizes, an overflow flag (slot or stack) and the deepest stack;
+// k_group_totals then forms the totals (the caller builds the lists in two
+// passes when any group overflowed).
 #define GWALK_STACK 4096
 #define GWALK_WK 2
 __global__ __launch_bounds__(64) void k_walk_grav_wave(
-    int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes,
-    const int32_t* __restrict__ child, const double* __restrict__ box, double theta2,
-    uint32_t* __restrict__ pc_cnt, uint32_t* __restrict__ pr_cnt, uint32_t* __restrict__ pp_tot,
-    int32_t* __restrict__ pc_list, int32_t* __restrict__ pr_begin, int32_t* __restrict__ pr_cum,
-    int cap_pc, int cap_pr, uint8_t* __restrict__ gflag, int32_t* __restrict__ gdepth) {
+    int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes, int64_t nn,
+    const double* __restrict__ wbox, const int4* __restrict__ wrec,
+    const double* __restrict__ box, double theta2, uint32_t* __restrict__ pc_cnt,
+    uint32_t* __restrict__ pr_cnt, uint32_t* __restrict__ pp_tot, int32_t* __restrict__ pc_list,
+    int32_t* __restrict__ pr_begin, int32_t* __restrict__ pr_cum, int cap_pc, int cap_pr,
+    uint8_t* __restrict__ gflag, int32_t* __restrict__ gdepth) {
     const int g = xcd_remap(blockIdx.x, ng);
     if (g >= ng) return;
     const int lane = threadIdx.x;
@@ -152,7 +218,7 @@ __global__ __launch_bounds__(64) void k_walk_grav_wave(
     const double L = box[3];
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t pco = (int64_t)g * cap_pc, pro = (int64_t)g * cap_pr;
-    if (lane == 0) stk[0] = 0;
+    if (lane == 0) stk[0] = 0;  // the root is alone on level 0
     int sp = 1, npc = 0, npr = 0, npp = 0, over = 0, spmax = 1;
     __syncthreads();
     while (sp > 0 && !over) {
@@ -166,51 +232,46 @@ __global__ __launch_bounds__(64) void k_walk_grav_wave(
         }
         __syncthreads();
         sp = b0;
-        // all loads of this step first, as whole 16-byte words into their own
-        // registers (child rows and the 64-byte node records; narrower field
-        // loads let the scheduler chain the nodes' loads one after another)
-        int4 cq[GWALK_WK][2];
-        uint4 rq[GWALK_WK][4];
+        // all loads of this step first; a row no lane uses is skipped, idle
+        // lanes of a used row read the root and discard it
+        double lo[GWALK_WK][3], hi[GWALK_WK][3];
+        int4 rec[GWALK_WK];
 #pragma unroll
         for (int w = 0; w < GWALK_WK; w++) {
-            cq[w][0] = cq[w][1] = make_int4(-1, -1, -1, -1);
-            rq[w][0] = rq[w][1] = rq[w][2] = rq[w][3] = make_uint4(0, 0, 0, 0);
-            if (n[w] >= 0) {
-                const int4* cp = reinterpret_cast<const int4*>(child + 8 * (int64_t)n[w]);
-                const uint4* np = reinterpret_cast<const uint4*>(nodes + n[w]);
-                cq[w][0] = cp[0];
-                cq[w][1] = cp[1];
+            if (64 * w >= take) {  // wave-uniform
+                rec[w] = make_int4(0, 0, 0, 0);
 #pragma unroll
-                for (int q = 0; q < 4; q++) rq[w][q] = np[q];
+                for (int d = 0; d < 3; d++) lo[w][d] = hi[w][d] = 0.0;
+                continue;
             }
+            const int64_t i = n[w] >= 0 ? n[w] : 0;
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                lo[w][d] = wbox[d * nn + i];
+                hi[w][d] = wbox[(3 + d) * nn + i];
+            }
+            rec[w] = wrec[i];
         }
-        int nch = 0;
+        int nch[GWALK_WK], first[GWALK_WK];
 #pragma unroll
         for (int w = 0; w < GWALK_WK; w++) {
-            bool acc = false, leaf = false, open = false;
-            int b = 0, e = 0;
-            if (n[w] >= 0) {
-                // NodeRec: lo[3], hi[3] (FP64), next, begin, end, level (16 bit), leaf (8 bit)
-                const uint4* r = rq[w];
-                double lo[3] = {dword2(r[0].x, r[0].y), dword2(r[0].z, r[0].w), dword2(r[1].x, r[1].y)};
-                double hi[3] = {dword2(r[1].z, r[1].w), dword2(r[2].x, r[2].y), dword2(r[2].z, r[2].w)};
-                const int level = (int)(int16_t)(r[3].w & 0xffffu);
-                const bool isleaf = ((r[3].w >> 16) & 0xffu) != 0;
-                double d2 = box_dist2(G.lo, G.hi, lo, hi);
-                double lc = ldexp(L, -level);
-                double lhs = lc * lc;
-                double rhs = theta2 * d2;
-                acc = lhs < rhs;
-                leaf = !acc && isleaf;
-                open = !acc && !isleaf;
-                b = (int)r[3].y;
-                e = (int)r[3].z;
-            }
-            // accepted cells
+            const uint32_t meta = (uint32_t)rec[w].y;
+            const int level = (int)(int16_t)(meta & 0xffffu);
+            const bool isleaf = ((meta >> 16) & 0xffu) != 0;
+            const double d2 = box_dist2(G.lo, G.hi, lo[w], hi[w]);
+            const double lc = ldexp(L, -level);
+            const double lhs = lc * lc;
+            const double rhs = theta2 * d2;
+            const bool live = n[w] >= 0;
+            const bool acc = live && lhs < rhs;
+            const bool leaf = live && !acc && isleaf;
+            const bool open = live && !acc && !isleaf;
+            const int b = rec[w].z, e = rec[w].w;
+            // accepted cells (pre-order ids)
             const uint64_t am = __ballot(acc);
             if (acc) {
                 const int pos = npc + __popcll(am & lt);
-                if (pos < cap_pc) pc_list[pco + pos] = n[w];
+                if (pos < cap_pc) pc_list[pco + pos] = rec[w].x;
             }
             npc += __popcll(am);
             // opened leaves: particle ranges
@@ -226,29 +287,27 @@ __global__ __launch_bounds__(64) void k_walk_grav_wave(
             }
             npr += __popcll(lm);
             npp += wave_last(incl);
-            if (!open) {
-                cq[w][0] = cq[w][1] = make_int4(-1, -1, -1, -1);
-            } else {
-                nch += (cq[w][0].x >= 0) + (cq[w][0].y >= 0) + (cq[w][0].z >= 0) +
-                       (cq[w][0].w >= 0) + (cq[w][1].x >= 0) + (cq[w][1].y >= 0) +
-                       (cq[w][1].z >= 0) + (cq[w][1].w >= 0);
-            }
+            nch[w] = open ? (int)(meta >> 24) : 0;
+            first[w] = b;
         }
-        // children of opened internal nodes onto the stack (lane order, then w)
-        const int cincl = wave_incl_scan(nch);
-        const int ctot = wave_last(cincl);
+        // children of opened internal nodes onto the stack in the order the
+        // nodes were popped (w = 0 rows, then w = 1): a node's children are
+        // the consecutive positions first .. first + nchild - 1
+        int coff[GWALK_WK], ctot = 0;
+#pragma unroll
+        for (int w = 0; w < GWALK_WK; w++) {
+            const int ci = wave_incl_scan(nch[w]);
+            coff[w] = sp + ctot + ci - nch[w];
+            ctot += wave_last(ci);
+        }
         if (sp + ctot > GWALK_STACK) {
             over = 1;
         } else {
-            int coff = sp + cincl - nch;
 #pragma unroll
-            for (int w = 0; w < GWALK_WK; w++) {
-                const int32_t ch[8] = {cq[w][0].x, cq[w][0].y, cq[w][0].z, cq[w][0].w,
-                                       cq[w][1].x, cq[w][1].y, cq[w][1].z, cq[w][1].w};
+            for (int w = 0; w < GWALK_WK; w++)
 #pragma unroll
                 for (int k = 0; k < 8; k++)
-                    if (ch[k] >= 0) stk[coff++] = ch[k];
-            }
+                    if (k < nch[w]) stk[coff[w] + k] = first[w] + k;
             sp += ctot;
             spmax = sp > spmax ? sp : spmax;
         }
