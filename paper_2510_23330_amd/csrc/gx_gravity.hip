@@ -29,13 +29,13 @@ __global__ __launch_bounds__(128) void k_walk_grav(
     unsigned long long* __restrict__ tot, const int64_t* __restrict__ pc_off,
     int32_t* __restrict__ pc_list, const int64_t* __restrict__ pr_off,
     int32_t* __restrict__ pr_begin, int32_t* __restrict__ pr_cum, int cap_pc, int cap_pr);
-__global__ __launch_bounds__(64) void k_walk_grav_wave(
-    int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes, int64_t nn,
-    const double* __restrict__ wbox, const int4* __restrict__ wrec,
-    const double* __restrict__ box, double theta2, uint32_t* __restrict__ pc_cnt,
-    uint32_t* __restrict__ pr_cnt, uint32_t* __restrict__ pp_tot, int32_t* __restrict__ pc_list,
-    int32_t* __restrict__ pr_begin, int32_t* __restrict__ pr_cum, int cap_pc, int cap_pr,
-    uint8_t* __restrict__ gflag, int32_t* __restrict__ gdepth);
+// One-pass wave walk over the level-order arrays (launched in the walk's own
+// source file): small_stack picks the 8 KB stack, else 16 KB.
+int gx_walk_grav_wave(gx_ctx* ctx, TreeSlot& T, int ng, double theta2, bool small_stack,
+                      uint32_t* pc_cnt, uint32_t* pr_cnt, uint32_t* pp_tot, int32_t* pc_list,
+                      int32_t* pr_begin, int32_t* pr_cum, int cap_pc, int cap_pr,
+                      uint8_t* gflag, int32_t* gdepth);
+int gx_walk_stack_small();
 __global__ __launch_bounds__(256) void k_group_totals(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ recv,
     const NodeRec* __restrict__ nodes, const uint32_t* __restrict__ c0,
@@ -346,34 +346,41 @@ extern "C" int gx_gravity_forces(gx_ctx* ctx, const gx_particles* p, double G, d
             GX_TRY(gx_reserve(ctx, Ls.aux, (size_t)ng * (1 + sizeof(int32_t)) + 64));
             uint8_t* gflag = (uint8_t*)Ls.aux.p;
             int32_t* gdepth = (int32_t*)((uint8_t*)Ls.aux.p + (((size_t)ng + 15) & ~(size_t)15));
-            GX_TRY(gx_walk_tree(ctx, T));
-            hipLaunchKernelGGL(k_walk_grav_wave, dim3(xcd_grid(ng)), dim3(64), 0, st, ng,
-                               (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
-                               (int64_t)T.n_nodes, (const double*)T.wbox.p,
-                               (const int4*)T.wrec.p, (const double*)T.box.p, theta2,
-                               (uint32_t*)Ls.pc_cnt.p, (uint32_t*)Ls.pr_cnt.p,
-                               (uint32_t*)Ls.pp_tot.p, (int32_t*)Ls.pc_list.p,
-                               (int32_t*)Ls.pr_begin.p, (int32_t*)Ls.pr_cum.p, Ls.cap_pc,
-                               Ls.cap_pr, gflag, gdepth);
-            hipLaunchKernelGGL(k_group_totals, dim3(gx_blocks(ng, 256)), dim3(256), 0, st, ng,
-                               (const int32_t*)T.groups.p, nullptr, (const NodeRec*)T.nodes.p,
-                               (const uint32_t*)Ls.pc_cnt.p, (const uint32_t*)Ls.pr_cnt.p,
-                               (const uint32_t*)Ls.pp_tot.p, gflag, gdepth,
-                               (unsigned long long*)tot);
-            GX_LAUNCH_CHECK(ctx);
-            GX_TRY(read_host(ctx, h_tot, tot, 8 * sizeof(int64_t)));
-            seen_pc = h_tot[5];
-            seen_pr = h_tot[6];
-            Ls.last_stack = h_tot[7];
-            if (h_tot[4] == 0) {
-                done = true;
-                Ls.last_two_pass = 0;
-                Ls.stride_pc = Ls.cap_pc;
-                Ls.stride_pr = Ls.cap_pr;
-                Ls.n_pc = h_tot[0];
-                Ls.n_ranges = h_tot[1];
-            } else {
-                GX_TRY(gx_zero(ctx, Ls.tot.p, 8 * sizeof(int64_t)));
+            // the small stack when the previous call's deepest stack fits with an
+            // eighth to spare; a small-stack walk that overflows only its stack
+            // is repeated once with the large one
+            const int64_t s_small = gx_walk_stack_small();
+            bool small = Ls.last_stack > 0 && Ls.last_stack + Ls.last_stack / 8 <= s_small;
+            for (int attempt = 0; attempt < 2 && !done; attempt++) {
+                GX_TRY(gx_walk_grav_wave(ctx, T, ng, theta2, small, (uint32_t*)Ls.pc_cnt.p,
+                                         (uint32_t*)Ls.pr_cnt.p, (uint32_t*)Ls.pp_tot.p,
+                                         (int32_t*)Ls.pc_list.p, (int32_t*)Ls.pr_begin.p,
+                                         (int32_t*)Ls.pr_cum.p, Ls.cap_pc, Ls.cap_pr, gflag,
+                                         gdepth));
+                hipLaunchKernelGGL(k_group_totals, dim3(gx_blocks(ng, 256)), dim3(256), 0, st, ng,
+                                   (const int32_t*)T.groups.p, nullptr, (const NodeRec*)T.nodes.p,
+                                   (const uint32_t*)Ls.pc_cnt.p, (const uint32_t*)Ls.pr_cnt.p,
+                                   (const uint32_t*)Ls.pp_tot.p, gflag, gdepth,
+                                   (unsigned long long*)tot);
+                GX_LAUNCH_CHECK(ctx);
+                GX_TRY(read_host(ctx, h_tot, tot, 8 * sizeof(int64_t)));
+                seen_pc = std::max<int64_t>(seen_pc, h_tot[5]);
+                seen_pr = std::max<int64_t>(seen_pr, h_tot[6]);
+                Ls.last_stack = h_tot[7];
+                if (h_tot[4] == 0) {
+                    done = true;
+                    Ls.last_two_pass = 0;
+                    Ls.stride_pc = Ls.cap_pc;
+                    Ls.stride_pr = Ls.cap_pr;
+                    Ls.n_pc = h_tot[0];
+                    Ls.n_ranges = h_tot[1];
+                } else {
+                    GX_TRY(gx_zero(ctx, Ls.tot.p, 8 * sizeof(int64_t)));
+                    const bool stack_only = h_tot[7] > s_small && h_tot[5] <= Ls.cap_pc &&
+                                            h_tot[6] <= Ls.cap_pr;
+                    if (!(small && stack_only)) break;
+                    small = false;
+                }
             }
         }
         if (!done) {

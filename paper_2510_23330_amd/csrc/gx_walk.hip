@@ -201,8 +201,13 @@ int gx_walk_tree(gx_ctx* ctx, TreeSlot& T) {
 // list sizes, an overflow flag (slot or stack) and the deepest stack;
 // k_group_totals then forms the totals (the caller builds the lists in two
 // passes when any group overflowed).
-#define GWALK_STACK 4096
+// The stack is sized per launch: GWALK_STACK_S entries (8 KB of LDS, about
+// twenty wavefronts per CU: the walk is latency-bound once its loads are
+// coalesced) or GWALK_STACK_L (16 KB) for deeper walks.
+#define GWALK_STACK_S 2048
+#define GWALK_STACK_L 4096
 #define GWALK_WK 2
+template <int GWALK_STACK>
 __global__ __launch_bounds__(64) void k_walk_grav_wave(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes, int64_t nn,
     const double* __restrict__ wbox, const int4* __restrict__ wrec,
@@ -323,6 +328,23 @@ __global__ __launch_bounds__(64) void k_walk_grav_wave(
         gdepth[g] = over ? GWALK_STACK + 1 : spmax;
     }
 }
+
+int gx_walk_grav_wave(gx_ctx* ctx, TreeSlot& T, int ng, double theta2, bool small_stack,
+                      uint32_t* pc_cnt, uint32_t* pr_cnt, uint32_t* pp_tot, int32_t* pc_list,
+                      int32_t* pr_begin, int32_t* pr_cum, int cap_pc, int cap_pr,
+                      uint8_t* gflag, int32_t* gdepth) {
+    GX_TRY(gx_walk_tree(ctx, T));
+    auto kern = small_stack ? k_walk_grav_wave<GWALK_STACK_S> : k_walk_grav_wave<GWALK_STACK_L>;
+    hipLaunchKernelGGL(kern, dim3(xcd_grid(ng)), dim3(64), 0, ctx->stream, ng,
+                       (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p, (int64_t)T.n_nodes,
+                       (const double*)T.wbox.p, (const int4*)T.wrec.p, (const double*)T.box.p,
+                       theta2, pc_cnt, pr_cnt, pp_tot, pc_list, pr_begin, pr_cum, cap_pc, cap_pr,
+                       gflag, gdepth);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+int gx_walk_stack_small() { return GWALK_STACK_S; }
 
 // Totals of a set of per-group lists: tot[0] += sum c0, tot[1] += sum c1,
 // tot[2] += sum nG pp, tot[3] += sum nG c0, tot[4] += sum flag, and maxima
