@@ -400,7 +400,7 @@ __global__ void k_wrelayout(const uint16_t* __restrict__ w, int Cout, int Cin,
 }
 
 template <int BN>
-__global__ __launch_bounds__(256, 2) void k_conv3d_slab(const uint16_t* __restrict__ in,
+__global__ __launch_bounds__(256, BN == 32 ? 3 : 2) void k_conv3d_slab(const uint16_t* __restrict__ in,
                                                         const uint16_t* __restrict__ wr,
                                                         const float* __restrict__ bias, ConvGeom g,
                                                         int mode, const uint16_t* __restrict__ yref,
@@ -430,10 +430,9 @@ __global__ __launch_bounds__(256, 2) void k_conv3d_slab(const uint16_t* __restri
 #pragma unroll
         for (int j = 0; j < NT; j++) acc[r][j] = f32x4{0, 0, 0, 0};
 
-    // row tile r of this wave: z slice 2 wv + r / 4, y row r % 4, x = lane & 15
-    int hrow[8];
-#pragma unroll
-    for (int r = 0; r < 8; r++) hrow[r] = ((2 * wv + (r >> 2)) * SHY + (r & 3)) * SHX + (lane & 15);
+    // row tile r of this wave: z slice 2 wv + r / 4, y row r % 4, x = lane & 15;
+    // its halo voxel is hbase plus a constant per r (an immediate LDS offset)
+    const int hbase = 2 * wv * SHY * SHX + (lane & 15);
     const int kg = lane >> 4;  // tap slot of this lane within a step
 
     const int nchunk = g.Cin / 8;
@@ -515,9 +514,10 @@ __global__ __launch_bounds__(256, 2) void k_conv3d_slab(const uint16_t* __restri
             if (tap < 27) {
                 const int dz = tap / 9, rr = tap - dz * 9, dy = rr / 3, dx = rr - dy * 3;
                 const int toff = (dz * SHY + dy) * SHX + dx;
+                const uint16_t* hp = &hal[(hbase + toff) * 8];
 #pragma unroll
                 for (int r = 0; r < 8; r++)
-                    a[r] = *reinterpret_cast<const bf16x8*>(&hal[(hrow[r] + toff) * 8]);
+                    a[r] = *reinterpret_cast<const bf16x8*>(hp + ((r >> 2) * SHY + (r & 3)) * SHX * 8);
 #pragma unroll
                 for (int j = 0; j < NT; j++)
                     bb[j] = *reinterpret_cast<const bf16x8*>(&wsh[(tap * BN + j * 16 + (lane & 15)) * 8]);
