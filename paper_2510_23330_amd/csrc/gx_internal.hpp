@@ -65,8 +65,12 @@ struct TreeSlot {
     // consecutive): sort buffers, six FP64 box arrays (lo x y z, hi x y z, each
     // n_nodes long) and one int4 per node {pre-order id, level | leaf << 16 |
     // nchild << 24, first child (internal) or particle begin (leaf), end}
-    Buf wkey[2], wval[2], wbox, wrec;
+    // The SPH walks use wsph, one int4 per node {particle begin, end, first
+    // child, level | leaf << 16 | nchild << 24}, and whmax, the node kernel
+    // sizes in level order (gathered again when hmax_ver moves on).
+    Buf wkey[2], wval[2], wbox, wrec, wsph, whmax;
     int walk_ready = 0;
+    int64_t hmax_ver = 0, whmax_ver = -1;
     int64_t n_nodes = 0, n_groups = 0, n_blocks = 0;
     int64_t lvl_hist[GX_MAX_LEVEL + 1] = {};
     int32_t* perm() const { return (int32_t*)val[0].p; }
@@ -138,6 +142,8 @@ int gx_radix_sort(gx_ctx* ctx, TreeSlot& T, int64_t n, int key_bits);
 int gx_radix_sort_bufs(gx_ctx* ctx, Buf* key, Buf* val, int64_t n, int key_bits);
 // Level-order walk arrays of a built tree (kept until the next build).
 int gx_walk_tree(gx_ctx* ctx, TreeSlot& T);
+// The same plus the level-order node kernel sizes for SPH walks with use_hmax.
+int gx_walk_tree_sph(gx_ctx* ctx, TreeSlot& T, int use_hmax);
 
 // ---------------------------------------------------------------------------
 // Device helpers

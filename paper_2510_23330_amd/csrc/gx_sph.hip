@@ -34,7 +34,8 @@ __global__ __launch_bounds__(128) void k_walk_sph(
     int32_t* __restrict__ pr_cum);
 __global__ __launch_bounds__(64) void k_walk_sph_bfs(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ recv,
-    const NodeRec* __restrict__ nodes, const int32_t* __restrict__ child, const MomRec* __restrict__ mom,
+    const NodeRec* __restrict__ nodes, int64_t nn, const double* __restrict__ wbox,
+    const int4* __restrict__ wsph, const float* __restrict__ whmax,
     const float* __restrict__ radius, int use_hmax, const uint8_t* __restrict__ active, int cap,
     uint32_t* __restrict__ pr_cnt, uint32_t* __restrict__ pp_tot,
     unsigned long long* __restrict__ tot, int32_t* __restrict__ pr_begin,
@@ -47,8 +48,9 @@ __global__ __launch_bounds__(256) void k_group_totals(
     unsigned long long* __restrict__ tot);
 __global__ __launch_bounds__(64) void k_walk_sph_wave(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ recv,
-    const NodeRec* __restrict__ nodes, const int32_t* __restrict__ child,
-    const MomRec* __restrict__ mom, const float* __restrict__ radius, int use_hmax,
+    const NodeRec* __restrict__ nodes, int64_t nn, const double* __restrict__ wbox,
+    const int4* __restrict__ wsph, const float* __restrict__ whmax,
+    const float* __restrict__ radius, int use_hmax,
     const uint8_t* __restrict__ active, int mode, uint32_t* __restrict__ pr_cnt,
     uint32_t* __restrict__ pp_tot, unsigned long long* __restrict__ tot,
     const int64_t* __restrict__ pr_off, int32_t* __restrict__ pr_begin,
@@ -663,6 +665,7 @@ int gx_sph_node_hmax(gx_ctx* ctx, TreeSlot& T, const float4* ss) {
                            (MomRec*)T.mom.p, ss);
     }
     GX_LAUNCH_CHECK(ctx);
+    T.hmax_ver++;
     return GX_OK;
 }
 
@@ -956,10 +959,14 @@ int gx_sph_walk(gx_ctx* ctx, TreeSlot& T, ListSet& Ls, int ng, const int32_t* gr
     uint32_t* ptot2 = ptot + ng + 1;
     uint8_t* ovf = (uint8_t*)Ls.pc_cnt.p;
     GX_TRY(gx_zero(ctx, tot, 16 * sizeof(int64_t)));
+    GX_TRY(gx_walk_tree_sph(ctx, T, use_hmax));
+    const double* wbox = (const double*)T.wbox.p;
+    const int4* wsph = (const int4*)T.wsph.p;
+    const float* whmax = (const float*)T.whmax.p;
     hipLaunchKernelGGL(k_walk_sph_bfs, dim3(xcd_grid(ng)), dim3(64), 0, st, ng, groups, recv,
-                       (const NodeRec*)T.nodes.p, (const int32_t*)T.child.p, (const MomRec*)T.mom.p, rad, use_hmax, active,
-                       SPH_RANGES, cnt, ptot, (unsigned long long*)tot, (int32_t*)Ls.pr_begin.p,
-                       (int32_t*)Ls.pr_cum.p, ovf);
+                       (const NodeRec*)T.nodes.p, (int64_t)nn, wbox, wsph, whmax, rad, use_hmax,
+                       active, SPH_RANGES, cnt, ptot, (unsigned long long*)tot,
+                       (int32_t*)Ls.pr_begin.p, (int32_t*)Ls.pr_cum.p, ovf);
     hipLaunchKernelGGL(k_group_totals, dim3(gx_blocks(ng, 256)), dim3(256), 0, st, ng, groups, recv,
                        (const NodeRec*)T.nodes.p, nullptr, cnt, ptot, ovf, nullptr,
                        (unsigned long long*)tot);
@@ -977,11 +984,10 @@ int gx_sph_walk(gx_ctx* ctx, TreeSlot& T, ListSet& Ls, int ng, const int32_t* gr
         GX_TRY(gx_reserve(ctx, Ls.aux, ng + 16));
         uint8_t* sovf = (uint8_t*)Ls.aux.p;
         const NodeRec* nodes = (const NodeRec*)T.nodes.p;
-        const int32_t* child = (const int32_t*)T.child.p;
         const MomRec* mom = (const MomRec*)T.mom.p;
         hipLaunchKernelGGL(k_walk_sph_wave, dim3(xcd_grid(ng)), dim3(64), 0, st, ng, groups, recv,
-                           nodes, child, mom, rad, use_hmax, ovf, 0, cnt2, ptot2,
-                           (unsigned long long*)tot, nullptr, nullptr, nullptr, sovf);
+                           nodes, (int64_t)nn, wbox, wsph, whmax, rad, use_hmax, ovf, 0, cnt2,
+                           ptot2, (unsigned long long*)tot, nullptr, nullptr, nullptr, sovf);
         GX_LAUNCH_CHECK(ctx);
         GX_HIP(ctx, hipMemcpyAsync(h, tot, 16 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
         GX_HIP(ctx, hipStreamSynchronize(st));
@@ -999,8 +1005,8 @@ int gx_sph_walk(gx_ctx* ctx, TreeSlot& T, ListSet& Ls, int ng, const int32_t* gr
         GX_TRY(gx_reserve(ctx, Ls.pc_off, (nr + 1) * sizeof(int32_t)));
         GX_TRY(gx_reserve(ctx, Ls.pc_list, (nr + 1) * sizeof(int32_t)));
         hipLaunchKernelGGL(k_walk_sph_wave, dim3(xcd_grid(ng)), dim3(64), 0, st, ng, groups, recv,
-                           nodes, child, mom, rad, use_hmax, ovf, 1, nullptr, nullptr, nullptr,
-                           (const int64_t*)Ls.pr_off.p, (int32_t*)Ls.pc_off.p,
+                           nodes, (int64_t)nn, wbox, wsph, whmax, rad, use_hmax, ovf, 1, nullptr,
+                           nullptr, nullptr, (const int64_t*)Ls.pr_off.p, (int32_t*)Ls.pc_off.p,
                            (int32_t*)Ls.pc_list.p, sovf);
         GX_LAUNCH_CHECK(ctx);
         if (deep) {

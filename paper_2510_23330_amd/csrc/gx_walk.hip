@@ -146,7 +146,8 @@ __global__ __launch_bounds__(256) void k_walk_arrays(int64_t nn, const uint32_t*
                                                      const int32_t* __restrict__ pos,
                                                      const NodeRec* __restrict__ nodes,
                                                      double* __restrict__ wbox,
-                                                     int4* __restrict__ wrec) {
+                                                     int4* __restrict__ wrec,
+                                                     int4* __restrict__ wsph) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nn) return;
     const int32_t p = (int32_t)order[i];
@@ -159,8 +160,17 @@ __global__ __launch_bounds__(256) void k_walk_arrays(int64_t nn, const uint32_t*
     const uint32_t meta = (uint32_t)(uint16_t)nd.level | ((uint32_t)(uint8_t)nd.leaf << 16) |
                           ((uint32_t)(uint8_t)nd.nchild << 24);
     // the first child of an internal node follows it in pre-order
-    const int32_t a = nd.leaf ? nd.begin : (nd.nchild > 0 ? pos[p + 1] : 0);
-    wrec[i] = make_int4(p, (int32_t)meta, a, nd.end);
+    const int32_t first = nd.nchild > 0 ? pos[p + 1] : 0;
+    wrec[i] = make_int4(p, (int32_t)meta, nd.leaf ? nd.begin : first, nd.end);
+    wsph[i] = make_int4(nd.begin, nd.end, first, (int32_t)meta);
+}
+
+__global__ __launch_bounds__(256) void k_walk_hmax(int64_t nn, const uint32_t* __restrict__ order,
+                                                   const MomRec* __restrict__ mom,
+                                                   float* __restrict__ whmax) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nn) return;
+    whmax[i] = mom[order[i]].hmax;
 }
 
 int gx_walk_tree(gx_ctx* ctx, TreeSlot& T) {
@@ -175,6 +185,8 @@ int gx_walk_tree(gx_ctx* ctx, TreeSlot& T) {
     }
     GX_TRY(gx_reserve(ctx, T.wbox, 6 * nn * sizeof(double)));
     GX_TRY(gx_reserve(ctx, T.wrec, nn * sizeof(int4)));
+    GX_TRY(gx_reserve(ctx, T.wsph, nn * sizeof(int4)));
+    GX_TRY(gx_reserve(ctx, T.whmax, nn * sizeof(float)));
     hipLaunchKernelGGL(k_lvl_keys, dim3(gx_blocks(nn, 256)), dim3(256), 0, st, nn,
                        (const NodeRec*)T.nodes.p, (uint64_t*)T.wkey[0].p, (uint32_t*)T.wval[0].p);
     GX_LAUNCH_CHECK(ctx);
@@ -183,9 +195,26 @@ int gx_walk_tree(gx_ctx* ctx, TreeSlot& T) {
                        (const uint32_t*)T.wval[0].p, (int32_t*)T.wval[1].p);
     hipLaunchKernelGGL(k_walk_arrays, dim3(gx_blocks(nn, 256)), dim3(256), 0, st, nn,
                        (const uint32_t*)T.wval[0].p, (const int32_t*)T.wval[1].p,
-                       (const NodeRec*)T.nodes.p, (double*)T.wbox.p, (int4*)T.wrec.p);
+                       (const NodeRec*)T.nodes.p, (double*)T.wbox.p, (int4*)T.wrec.p,
+                       (int4*)T.wsph.p);
     GX_LAUNCH_CHECK(ctx);
     T.walk_ready = 1;
+    T.whmax_ver = -1;
+    return GX_OK;
+}
+
+// Level-order walk arrays plus, when use_hmax, the node kernel sizes in level
+// order as of the last gx_sph_node_hmax.
+int gx_walk_tree_sph(gx_ctx* ctx, TreeSlot& T, int use_hmax) {
+    GX_TRY(gx_walk_tree(ctx, T));
+    if (use_hmax && T.whmax_ver != T.hmax_ver) {
+        const int64_t nn = T.n_nodes;
+        hipLaunchKernelGGL(k_walk_hmax, dim3(gx_blocks(nn, 256)), dim3(256), 0, ctx->stream, nn,
+                           (const uint32_t*)T.wval[0].p, (const MomRec*)T.mom.p,
+                           (float*)T.whmax.p);
+        GX_LAUNCH_CHECK(ctx);
+        T.whmax_ver = T.hmax_ver;
+    }
     return GX_OK;
 }
 
@@ -498,7 +527,8 @@ __global__ __launch_bounds__(128) void k_walk_sph(
 #define BFS_FMAX 2048
 __global__ __launch_bounds__(64) void k_walk_sph_bfs(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ recv,
-    const NodeRec* __restrict__ nodes, const int32_t* __restrict__ child, const MomRec* __restrict__ mom,
+    const NodeRec* __restrict__ nodes, int64_t nn, const double* __restrict__ wbox,
+    const int4* __restrict__ wsph, const float* __restrict__ whmax,
     const float* __restrict__ radius, int use_hmax, const uint8_t* __restrict__ active, int cap,
     uint32_t* __restrict__ pr_cnt, uint32_t* __restrict__ pp_tot,
     unsigned long long* __restrict__ tot, int32_t* __restrict__ pr_begin,
@@ -527,26 +557,29 @@ __global__ __launch_bounds__(64) void k_walk_sph_bfs(
         for (int base = 0; base < cnt; base += 64) {
             const int idx = base + lane;
             bool inter = false, leaf = false;
-            int n = -1, b = 0, e = 0;
-            int4 cq0 = make_int4(-1, -1, -1, -1), cq1 = cq0;
+            int b = 0, e = 0, first = 0, nchild = 0;
             if (idx < cnt) {
-                n = fr[cur][idx];
-                const int4* cp = reinterpret_cast<const int4*>(child + 8 * (int64_t)n);
-                cq0 = cp[0];
-                cq1 = cp[1];
-                const NodeRec& nd = nodes[n];
-                double lo[3] = {nd.lo[0], nd.lo[1], nd.lo[2]};
-                double hi[3] = {nd.hi[0], nd.hi[1], nd.hi[2]};
+                const int64_t n = fr[cur][idx];  // level-order position
+                double lo[3], hi[3];
+#pragma unroll
+                for (int d = 0; d < 3; d++) {
+                    lo[d] = wbox[d * nn + n];
+                    hi[d] = wbox[(3 + d) * nn + n];
+                }
+                const int4 r = wsph[n];
                 const double d2 = box_dist2(G.lo, G.hi, lo, hi);
                 double R = RG;
                 if (use_hmax) {
-                    const double hm = (double)mom[n].hmax;
+                    const double hm = (double)whmax[n];
                     R = hm > R ? hm : R;
                 }
                 inter = d2 < R * R;
-                leaf = nd.leaf || (inter && box_far2(G.lo, G.hi, lo, hi) < RG * RG);
-                b = nd.begin;
-                e = nd.end;
+                const bool isleaf = (((uint32_t)r.w >> 16) & 0xffu) != 0;
+                leaf = isleaf || (inter && box_far2(G.lo, G.hi, lo, hi) < RG * RG);
+                b = r.x;
+                e = r.y;
+                first = r.z;
+                nchild = (int)((uint32_t)r.w >> 24);
             }
             // emit leaves (and wholly covered nodes)
             const bool emit = inter && leaf;
@@ -562,17 +595,12 @@ __global__ __launch_bounds__(64) void k_walk_sph_bfs(
             }
             nout += __popcll(em);
             npp += wave_last(incl);
-            // open internal nodes
-            int nch = 0;
-            const int32_t ch[8] = {cq0.x, cq0.y, cq0.z, cq0.w, cq1.x, cq1.y, cq1.z, cq1.w};
-            if (inter && !leaf) {
-#pragma unroll
-                for (int k = 0; k < 8; k++) nch += ch[k] >= 0;
-            }
+            // open internal nodes: children are first .. first + nchild - 1
+            const int nch = (inter && !leaf) ? nchild : 0;
             const int cincl = wave_incl_scan(nch);
             const int coff = ncnt + cincl - nch;
             for (int k = 0; k < nch; k++) {
-                if (coff + k < BFS_FMAX) fr[cur ^ 1][coff + k] = ch[k];
+                if (coff + k < BFS_FMAX) fr[cur ^ 1][coff + k] = first + k;
             }
             ncnt += wave_last(cincl);
         }
@@ -605,8 +633,9 @@ __global__ __launch_bounds__(64) void k_walk_sph_bfs(
 #define WDFS_STACK 8192
 __global__ __launch_bounds__(64) void k_walk_sph_wave(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ recv,
-    const NodeRec* __restrict__ nodes, const int32_t* __restrict__ child,
-    const MomRec* __restrict__ mom, const float* __restrict__ radius, int use_hmax,
+    const NodeRec* __restrict__ nodes, int64_t nn, const double* __restrict__ wbox,
+    const int4* __restrict__ wsph, const float* __restrict__ whmax,
+    const float* __restrict__ radius, int use_hmax,
     const uint8_t* __restrict__ active, int mode, uint32_t* __restrict__ pr_cnt,
     uint32_t* __restrict__ pp_tot, unsigned long long* __restrict__ tot,
     const int64_t* __restrict__ pr_off, int32_t* __restrict__ pr_begin,
@@ -638,25 +667,28 @@ __global__ __launch_bounds__(64) void k_walk_sph_wave(
         __syncthreads();  // every lane has read its node before pushes reuse the slots
         sp = b0;
         bool inter = false, leaf = false;
-        int b = 0, e = 0;
-        int4 cq0 = make_int4(-1, -1, -1, -1), cq1 = cq0;
-        if (n >= 0) {
-            const int4* cp = reinterpret_cast<const int4*>(child + 8 * (int64_t)n);
-            cq0 = cp[0];
-            cq1 = cp[1];
-            const NodeRec& nd = nodes[n];
-            double lo[3] = {nd.lo[0], nd.lo[1], nd.lo[2]};
-            double hi[3] = {nd.hi[0], nd.hi[1], nd.hi[2]};
+        int b = 0, e = 0, first = 0, nchild = 0;
+        if (n >= 0) {  // level-order position
+            double lo[3], hi[3];
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                lo[d] = wbox[d * nn + n];
+                hi[d] = wbox[(3 + d) * nn + n];
+            }
+            const int4 r = wsph[n];
             const double d2 = box_dist2(G.lo, G.hi, lo, hi);
             double R = RG;
             if (use_hmax) {
-                const double hm = (double)mom[n].hmax;
+                const double hm = (double)whmax[n];
                 R = hm > R ? hm : R;
             }
             inter = d2 < R * R;
-            leaf = nd.leaf || (inter && box_far2(G.lo, G.hi, lo, hi) < RG * RG);
-            b = nd.begin;
-            e = nd.end;
+            const bool isleaf = (((uint32_t)r.w >> 16) & 0xffu) != 0;
+            leaf = isleaf || (inter && box_far2(G.lo, G.hi, lo, hi) < RG * RG);
+            b = r.x;
+            e = r.y;
+            first = r.z;
+            nchild = (int)((uint32_t)r.w >> 24);
         }
         const bool emit = inter && leaf;
         const uint64_t em = __ballot(emit);
@@ -669,19 +701,14 @@ __global__ __launch_bounds__(64) void k_walk_sph_wave(
         }
         nout += __popcll(em);
         npp += wave_last(incl);
-        int nch = 0;
-        const int32_t ch[8] = {cq0.x, cq0.y, cq0.z, cq0.w, cq1.x, cq1.y, cq1.z, cq1.w};
-        if (inter && !leaf) {
-#pragma unroll
-            for (int k = 0; k < 8; k++) nch += ch[k] >= 0;
-        }
+        const int nch = (inter && !leaf) ? nchild : 0;  // children first .. first + nch - 1
         const int cincl = wave_incl_scan(nch);
         const int ctot = wave_last(cincl);
         if (sp + ctot > WDFS_STACK) {
             over = 1;
         } else {
             const int coff = sp + cincl - nch;
-            for (int k = 0; k < nch; k++) stk[coff + k] = ch[k];
+            for (int k = 0; k < nch; k++) stk[coff + k] = first + k;
             sp += ctot;
         }
         __syncthreads();
