@@ -334,6 +334,7 @@ extern "C" int gx_gravity_forces(gx_ctx* ctx, const gx_particles* p, double G, d
         const double theta2 = theta * theta;
         bool done = false;
         int64_t seen_pc = 0, seen_pr = 0;  // largest per-group list sizes seen in this call
+        const int64_t prev_stack = Ls.last_stack;  // deepest stack of the previous call
         Ls.last_two_pass = 1;
         Ls.last_stack = 0;
         // one pass into per-group slots sized from the largest lists of the
@@ -350,7 +351,7 @@ extern "C" int gx_gravity_forces(gx_ctx* ctx, const gx_particles* p, double G, d
             // eighth to spare; a small-stack walk that overflows only its stack
             // is repeated once with the large one
             const int64_t s_small = gx_walk_stack_small();
-            bool small = Ls.last_stack > 0 && Ls.last_stack + Ls.last_stack / 8 <= s_small;
+            bool small = prev_stack > 0 && prev_stack + prev_stack / 8 <= s_small;
             for (int attempt = 0; attempt < 2 && !done; attempt++) {
                 GX_TRY(gx_walk_grav_wave(ctx, T, ng, theta2, small, (uint32_t*)Ls.pc_cnt.p,
                                          (uint32_t*)Ls.pr_cnt.p, (uint32_t*)Ls.pp_tot.p,
