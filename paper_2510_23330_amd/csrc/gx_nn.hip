@@ -413,7 +413,11 @@ __global__ __launch_bounds__(256, BN == 32 ? 3 : 2) void k_conv3d_slab(const uin
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int S = g.S;
     const int nbx = (S + SBX - 1) / SBX, nby = (S + SBY - 1) / SBY, nbz = (S + SBZ - 1) / SBZ;
-    int t = blockIdx.x;
+    // each XCD takes a contiguous run of slabs, so neighbours that share halo
+    // planes run on one L2 (the grid is padded to a multiple of 8)
+    const int nslab = g.B * nbz * nby * nbx;
+    int t = xcd_remap(blockIdx.x, nslab);
+    if (t >= nslab) return;
     const int bx = t % nbx;
     t /= nbx;
     const int by = t % nby;
@@ -1021,11 +1025,11 @@ static int launch_conv(gx_ctx* ctx, const uint16_t* in, const uint16_t* w, const
         const int64_t nb = (int64_t)g.B * ((S + SBZ - 1) / SBZ) * ((S + SBY - 1) / SBY) *
                            ((S + SBX - 1) / SBX);
         if (g.Cout % 64 == 0)
-            hipLaunchKernelGGL(k_conv3d_slab<64>, dim3((unsigned)nb, (unsigned)(g.Cout / 64)),
+            hipLaunchKernelGGL(k_conv3d_slab<64>, dim3(xcd_grid(nb), (unsigned)(g.Cout / 64)),
                                dim3(256), 0, ctx->stream, in, (const uint16_t*)wr, bias, g, mode,
                                yref, ob, of, src);
         else
-            hipLaunchKernelGGL(k_conv3d_slab<32>, dim3((unsigned)nb, (unsigned)(g.Cout / 32)),
+            hipLaunchKernelGGL(k_conv3d_slab<32>, dim3(xcd_grid(nb), (unsigned)(g.Cout / 32)),
                                dim3(256), 0, ctx->stream, in, (const uint16_t*)wr, bias, g, mode,
                                yref, ob, of, src);
         GX_LAUNCH_CHECK(ctx);
