@@ -409,7 +409,8 @@ __global__ __launch_bounds__(256, BN == 32 ? 3 : 2) void k_conv3d_slab(const uin
     constexpr int NT = BN / 16;
     constexpr int NSTEP = 7;  // ceil(27 / 4)
     __shared__ __attribute__((aligned(16))) uint16_t hal[SHVOX * 8];
-    __shared__ __attribute__((aligned(16))) uint16_t wsh[27 * BN * 8];
+    // 27 taps of weights plus a zero row for the padding tap slot
+    __shared__ __attribute__((aligned(16))) uint16_t wsh[28 * BN * 8];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int S = g.S;
     const int nbx = (S + SBX - 1) / SBX, nby = (S + SBY - 1) / SBY, nbz = (S + SBZ - 1) / SBZ;
@@ -486,6 +487,7 @@ __global__ __launch_bounds__(256, BN == 32 ? 3 : 2) void k_conv3d_slab(const uin
         }
         if (PFW) fetch_w(c);
     };
+    if (tid < BN) *reinterpret_cast<uint4*>(&wsh[(27 * BN + tid) * 8]) = make_uint4(0, 0, 0, 0);
     fetch(0);
     for (int c = 0; c < nchunk; c++) {
         __syncthreads();  // the previous chunk's tiles have been read
@@ -513,25 +515,20 @@ __global__ __launch_bounds__(256, BN == 32 ? 3 : 2) void k_conv3d_slab(const uin
         __builtin_amdgcn_sched_barrier(0);  // issue the next chunk's loads before the MFMAs
 #pragma unroll 1
         for (int st = 0; st < NSTEP; st++) {
+            // the padding slot (tap 27) multiplies the tap-26 window (in
+            // bounds, finite) by the zero weight row: an exact zero
             const int tap = st * 4 + kg;
+            const int ta = tap < 27 ? tap : 26;
+            const int dz = ta / 9, rr = ta - dz * 9, dy = rr / 3, dx = rr - dy * 3;
+            const int toff = (dz * SHY + dy) * SHX + dx;
+            const uint16_t* hp = &hal[(hbase + toff) * 8];
             bf16x8 a[8], bb[NT];
-            if (tap < 27) {
-                const int dz = tap / 9, rr = tap - dz * 9, dy = rr / 3, dx = rr - dy * 3;
-                const int toff = (dz * SHY + dy) * SHX + dx;
-                const uint16_t* hp = &hal[(hbase + toff) * 8];
 #pragma unroll
-                for (int r = 0; r < 8; r++)
-                    a[r] = *reinterpret_cast<const bf16x8*>(hp + ((r >> 2) * SHY + (r & 3)) * SHX * 8);
+            for (int r = 0; r < 8; r++)
+                a[r] = *reinterpret_cast<const bf16x8*>(hp + ((r >> 2) * SHY + (r & 3)) * SHX * 8);
 #pragma unroll
-                for (int j = 0; j < NT; j++)
-                    bb[j] = *reinterpret_cast<const bf16x8*>(&wsh[(tap * BN + j * 16 + (lane & 15)) * 8]);
-            } else {
-                const uint4 z4 = make_uint4(0, 0, 0, 0);
-#pragma unroll
-                for (int r = 0; r < 8; r++) a[r] = *reinterpret_cast<const bf16x8*>(&z4);
-#pragma unroll
-                for (int j = 0; j < NT; j++) bb[j] = *reinterpret_cast<const bf16x8*>(&z4);
-            }
+            for (int j = 0; j < NT; j++)
+                bb[j] = *reinterpret_cast<const bf16x8*>(&wsh[(tap * BN + j * 16 + (lane & 15)) * 8]);
 #pragma unroll
             for (int r = 0; r < 8; r++)
 #pragma unroll
