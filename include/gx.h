@@ -356,6 +356,18 @@ int gx_sn_resample(gx_ctx* ctx, const float* pred, int k, int grid, double side,
                    double* vx, double* vy, double* vz, double* u);
 
 /*
+ * gx_sn_check -- trust check of a prediction before replacement (an addition
+ * to Sec. 3.2 step 4: a region whose prediction leaves the training targets'
+ * range keeps the plain integrator).  ok[c] = 1 when every value of cube c is
+ * finite and lo[ch] <= value <= hi[ch] for its channel ch (compared in FP32).
+ * pred   device float [k][grid^3][5] physical channels
+ * lo, hi host double [5]
+ * ok     host uint8 [k] (output).  Synchronises.  k = 0 is a no-op.
+ */
+int gx_sn_check(gx_ctx* ctx, const float* pred, int k, int grid, const double* lo,
+                const double* hi, uint8_t* ok);
+
+/*
  * gx_sn_replace -- replace particles by ID (Sec. 3.2 step 4).  id: device
  * int64 [n] ids of the main arrays (each in [0, id_cap)); new particles with
  * ids new_id[m] overwrite position and velocity; u (device, index i - u_offset

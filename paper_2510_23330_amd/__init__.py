@@ -339,6 +339,19 @@ class Engine:
             _ptr(uniforms, torch.float32), float(T_to_u), *(_ptr(t, torch.float64) for t in
                                                               (x, y, z, vx, vy, vz, u))))
 
+    def sn_check(self, pred, k, grid, lo, hi):
+        """Per-cube trust flags (numpy bool [k]) of a prediction: every value
+        finite and inside [lo, hi] of its channel (lo, hi: 5 floats)."""
+        torch = _torch()
+        lo_h = np.ascontiguousarray(np.asarray(lo, dtype=np.float64).reshape(5))
+        hi_h = np.ascontiguousarray(np.asarray(hi, dtype=np.float64).reshape(5))
+        ok = np.zeros(max(int(k), 1), dtype=np.uint8)
+        self._check(self.lib.gx_sn_check(
+            self.ctx, _ptr(pred, torch.float32), int(k), int(grid),
+            lo_h.ctypes.data_as(C.c_void_p), hi_h.ctypes.data_as(C.c_void_p),
+            ok.ctypes.data_as(C.c_void_p)))
+        return ok[:int(k)].astype(bool)
+
     def sn_replace(self, id, id_cap, x, y, z, vx, vy, vz, u, u_offset, H64, new_id, nx, ny, nz, nvx,
                    nvy, nvz, nu):
         torch = _torch()

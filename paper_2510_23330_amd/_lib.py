@@ -73,6 +73,7 @@ SIGNATURES = {
     "gx_sn_voxelize": (I32, [P, C.POINTER(GxParticles), P, P, P, I32, D, I32, D, P, P, P, P,
                              I32, P]),
     "gx_sn_resample": (I32, [P, P, I32, I32, D, P, P, I64, P, D, P, P, P, P, P, P, P]),
+    "gx_sn_check": (I32, [P, P, I32, I32, P, P, P]),
     "gx_sn_replace": (I32, [P, I64, P, I64, P, P, P, P, P, P, P, I64, P, I64, P, P, P, P, P, P, P,
                             P, C.POINTER(I64)]),
     "gx_conv3d_fwd": (I32, [P, P, I32, I32, I32, P, P, I32, I32, I32, P, P]),

@@ -76,14 +76,13 @@ class SNCoupling:
         return torch.stack([p.x[s], p.y[s], p.z[s]], dim=1).contiguous()
 
     def _valid(self, pred, K):
-        """Per-region check that every predicted channel stays within
-        valid_sigma standard deviations of the training targets."""
-        torch, sur = self.torch, self.sur
-        v = pred.view(K, -1, 5)
-        lo = (sur.mean_out - self.valid_sigma * sur.std_out).view(1, 5)
-        hi = (sur.mean_out + self.valid_sigma * sur.std_out).view(1, 5)
-        ok = (torch.isfinite(v).all(dim=1) & (v.amin(dim=1) >= lo) & (v.amax(dim=1) <= hi)).all(dim=1)
-        return ok.cpu().numpy()
+        """Per-region check (gx_sn_check) that every predicted channel stays
+        within valid_sigma standard deviations of the training targets."""
+        sur = self.sur
+        mo = sur.mean_out.cpu().numpy().astype(np.float64)
+        so = sur.std_out.cpu().numpy().astype(np.float64)
+        return self.eng.sn_check(pred, K, sur.grid, mo - self.valid_sigma * so,
+                                 mo + self.valid_sigma * so)
 
     def launch(self, step_index: int):
         """Hand this step's regions to the surrogate; queue their replacement."""
@@ -96,8 +95,8 @@ class SNCoupling:
         self.stats["regions"] += K
         if tot == 0:
             return
-        counts = (off[1:] - off[:-1])
-        n_max = int(counts.max().item())
+        offh = off.cpu().numpy()
+        n_max = int((offh[1:] - offh[:-1]).max())
         f64 = dict(dtype=torch.float64, device=dev)
         box = {a: torch.empty(tot, **f64) for a in ("x", "y", "z", "vx", "vy", "vz", "m", "u")}
         box["H"] = torch.empty(tot, dtype=torch.float32, device=dev)
@@ -127,7 +126,6 @@ class SNCoupling:
         ids = st.p.id[st.gas_offset:].index_select(0, idx.long())
         if not ok.all():
             # fallback: drop the regions the network cannot be trusted on
-            offh = off.cpu().numpy()
             keep = np.concatenate([np.arange(offh[c], offh[c + 1]) for c in range(K) if ok[c]]
                                   or [np.zeros(0, np.int64)])
             kt = torch.as_tensor(keep, dtype=torch.long, device=dev)

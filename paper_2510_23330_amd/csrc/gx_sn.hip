@@ -5,6 +5,7 @@
 // predicted grid (as many as went in, so mass is conserved), and replace
 // particles by ID.
 #include "gx_internal.hpp"
+#include <vector>
 
 #include <cmath>
 
@@ -647,6 +648,60 @@ extern "C" int gx_sn_resample(gx_ctx* ctx, const float* pred, int k, int grid, d
     hipLaunchKernelGGL(k_resample, dim3(gxb, k), dim3(256), 0, ctx->stream, k, grid, 0.5 * side,
                        centers, out_off, pred, cdf, uniforms, T_to_u, x, y, z, vx, vy, vz, u);
     GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Trust check of a prediction before replacement.
+// ---------------------------------------------------------------------------
+struct SnBounds {
+    float lo[5], hi[5];
+};
+
+// Grid (blocks per region, k): region c is marked in bad[c] when any value of
+// its [grid^3][5] block is not finite or outside [lo[ch], hi[ch]].
+__global__ __launch_bounds__(256) void k_sn_check(const float* __restrict__ pred, int per,
+                                                  SnBounds bd, uint32_t* __restrict__ bad) {
+    const float* p = pred + (int64_t)blockIdx.y * per;
+    bool good = true;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < per; e += gridDim.x * blockDim.x) {
+        const float v = p[e];
+        const int ch = e % 5;
+        float lo = bd.lo[0], hi = bd.hi[0];
+#pragma unroll
+        for (int q = 1; q < 5; q++)
+            if (ch == q) {
+                lo = bd.lo[q];
+                hi = bd.hi[q];
+            }
+        good = good && isfinite(v) && v >= lo && v <= hi;
+    }
+    if (!__syncthreads_and(good ? 1 : 0) && threadIdx.x == 0) atomicOr(&bad[blockIdx.y], 1u);
+}
+
+extern "C" int gx_sn_check(gx_ctx* ctx, const float* pred, int k, int grid, const double* lo,
+                           const double* hi, uint8_t* ok) {
+    if (!ctx || k < 0 || grid < 1 || !lo || !hi || (k > 0 && (!pred || !ok))) return GX_EINVAL;
+    const int64_t per = (int64_t)grid * grid * grid * 5;
+    if (per > INT32_MAX) return gx_fail(ctx, GX_EINVAL, "sn_check: grid %d too large", grid);
+    if (k == 0) return GX_OK;
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    SnBounds bd;
+    for (int q = 0; q < 5; q++) {
+        bd.lo[q] = (float)lo[q];
+        bd.hi[q] = (float)hi[q];
+    }
+    GX_TRY(gx_reserve(ctx, ctx->sph_work[21], (size_t)k * sizeof(uint32_t)));
+    uint32_t* bad = (uint32_t*)ctx->sph_work[21].p;
+    GX_TRY(gx_zero(ctx, bad, (size_t)k * sizeof(uint32_t)));
+    const unsigned nbx = (unsigned)std::min<int64_t>(64, (per + 255) / 256);
+    hipLaunchKernelGGL(k_sn_check, dim3(nbx, k), dim3(256), 0, ctx->stream, pred, (int)per, bd, bad);
+    GX_LAUNCH_CHECK(ctx);
+    std::vector<uint32_t> h(k);
+    GX_HIP(ctx, hipMemcpyAsync(h.data(), bad, (size_t)k * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    GX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (int c = 0; c < k; c++) ok[c] = h[c] ? 0 : 1;
     return GX_OK;
 }
 

@@ -335,3 +335,32 @@ def test_ambient_gather_unframe(gx, eng):
     for c in range(6):
         sl = slice(offh[c], offh[c + 1])
         assert np.allclose(shift[sl], 2.0 * amb[c, 2], rtol=1e-6, atol=1e-9)
+
+
+def test_trust_check_flags(gx, eng):
+    """gx_sn_check against its definition (every value finite and inside the
+    channel's [lo, hi]) on cubes with one planted fault each, values exactly
+    on the bounds, and an empty call."""
+    import torch
+    grid, k = 12, 7
+    rng = np.random.default_rng(21)
+    lo = np.array([-1.0, 0.0, -2.0, -3.0, 1.0])
+    hi = np.array([1.0, 5.0, 2.0, 3.0, 2.0])
+    v = rng.uniform(lo, hi, size=(k, grid ** 3, 5)).astype(np.float32)
+    v[1, 10, 0] = np.float32(lo[0])           # on the bound: passes
+    v[1, 11, 4] = np.float32(hi[4])
+    v[2, 5, 1] = np.float32(hi[1]) * 1.001    # above
+    v[3, grid ** 3 - 1, 2] = -2.5             # below, last voxel
+    v[4, 7, 3] = np.nan
+    v[5, 0, 4] = np.inf
+    flat = v.reshape(-1).copy()
+    pred = torch.as_tensor(flat, device="cuda")
+    ok = eng.sn_check(pred, k, grid, lo, hi)
+    lo32, hi32 = lo.astype(np.float32), hi.astype(np.float32)
+    ref = np.array([np.all(np.isfinite(v[c]) & (v[c] >= lo32) & (v[c] <= hi32)) for c in range(k)])
+    assert ref.tolist() == [True, True, False, False, False, False, True]
+    assert ok.tolist() == ref.tolist()
+    # a second call on the same context starts from clear flags
+    ok2 = eng.sn_check(pred[: 2 * grid ** 3 * 5], 2, grid, lo, hi)
+    assert ok2.tolist() == [True, True]
+    assert eng.sn_check(pred, 0, grid, lo, hi).tolist() == []
