@@ -50,8 +50,8 @@ FLOP_FORCE = 101                     # per SPH force candidate pair (Table 4)
 # known size (hbm_calib.py: FETCH_SIZE reads half the bytes copied, WRITE_SIZE
 # all of them).  Valid only for the kernel source with this SHA-256; any
 # change to gx_gravity.hip makes the bench report null until remeasured.
-GRAV_TRAFFIC = {"source_sha256": "ef8d9680b32478b4a20967e7c22c98c122aef1a12845c1e52e9e6654a8379443",
-                "fetch_kib": 4224040.0625, "write_kib": 2004640.03125,
+GRAV_TRAFFIC = {"source_sha256": "bdd50057ecdf11bfa44a453e0d5b3a66ea58246aa72137dd388b8a15cf41dfb1",
+                "fetch_kib": 3961765.5625, "write_kib": 2004873.03125,
                 "fetch_scale": 2.0, "write_scale": 1.0}
 
 
