@@ -524,7 +524,10 @@ __global__ __launch_bounds__(128) void k_walk_sph(
 // order; consumers only rely on the running offsets.  A frontier or slot
 // overflow sets the group's ovf flag (the caller then builds that group's
 // list with the depth-first walks).
-#define BFS_FMAX 2048
+// 512 entries (4 KB of LDS for both frontiers, many wavefronts per CU): a
+// wider frontier sends fewer groups to the depth-first walk but runs far
+// fewer walks at once, which measured slower on the 16M disk.
+#define BFS_FMAX 512
 __global__ __launch_bounds__(64) void k_walk_sph_bfs(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ recv,
     const NodeRec* __restrict__ nodes, int64_t nn, const double* __restrict__ wbox,
@@ -630,7 +633,7 @@ __global__ __launch_bounds__(64) void k_walk_sph_bfs(
 // writes them at pr_off[g] in the same order.  A group whose stack would
 // overflow is flagged in sovf (and counted in tot[5]); the caller walks those
 // with the thread-level walk instead.
-#define WDFS_STACK 8192
+#define WDFS_STACK 4096  // 16 KB of LDS
 __global__ __launch_bounds__(64) void k_walk_sph_wave(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ recv,
     const NodeRec* __restrict__ nodes, int64_t nn, const double* __restrict__ wbox,
