@@ -210,7 +210,9 @@ template int gx_scan<uint32_t, int64_t>(gx_ctx*, const uint32_t*, int64_t*, int6
 // a scatter in which each block ranks its tile stably: items are taken in
 // rounds of 256 (round-major, then thread order), ranked within each wave by
 // ballot matching on the 8 digit bits, and across waves and rounds through
-// per-digit counters in LDS.
+// per-digit counters in LDS; the ranked tile is laid out in digit order in
+// LDS and written out from there, so neighbouring threads write neighbouring
+// places of one digit's range.
 // ---------------------------------------------------------------------------
 #define RS_ITEMS 16
 #define RS_TILE (256 * RS_ITEMS)
@@ -238,34 +240,43 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint64_t* __restrict__
     __shared__ uint32_t running[256];
     __shared__ uint32_t wcnt[2][4][256];
     __shared__ uint32_t boff[256];
+    __shared__ uint32_t dstart[256];
+    __shared__ uint32_t sh4[4];
+    __shared__ uint64_t sk[RS_TILE];
+    __shared__ uint32_t sv[RS_TILE];
     const int t = threadIdx.x, w = t / GX_WAVE, lane = gx_lane();
     running[t] = 0;
     boff[t] = off[(int64_t)t * nblk + blockIdx.x];
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    // 1. rank every item of the tile among the tile's items with its digit
+    //    (rounds of 256 in index order; within a round by wave, then lane)
+    uint64_t kk[RS_ITEMS];
+    uint32_t vv[RS_ITEMS], lr[RS_ITEMS];  // lr: digit << 16 | rank in the tile, ~0u when empty
+#pragma unroll
     for (int r = 0; r < RS_ITEMS; r++) {
         uint32_t(*wc)[256] = wcnt[r & 1];
 #pragma unroll
         for (int k = 0; k < 4; k++) wc[k][t] = 0;
         __syncthreads();
-        int64_t i = base + r * 256 + t;
-        bool valid = i < n;
-        uint64_t k = valid ? kin[i] : 0;
-        uint32_t v = valid ? vin[i] : 0;
-        uint32_t d = (uint32_t)(k >> shift) & 255u;
+        const int64_t i = base + r * 256 + t;
+        const bool valid = i < n;
+        const uint64_t k = valid ? kin[i] : 0;
+        const uint32_t v = valid ? vin[i] : 0;
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; b++) {
-            bool bit = (d >> b) & 1u;
-            uint64_t bb = __ballot(bit);
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
             peers &= bit ? bb : ~bb;
         }
-        uint32_t rank = (uint32_t)__popcll(peers & lt);
+        const uint32_t rank = (uint32_t)__popcll(peers & lt);
         if (valid && (peers >> lane) == 1ull) wc[w][d] = (uint32_t)__popcll(peers);  // last peer
         __syncthreads();
         {
-            uint32_t c0 = wc[0][t], c1 = wc[1][t], c2 = wc[2][t], c3 = wc[3][t];
-            uint32_t run = running[t];
+            const uint32_t c0 = wc[0][t], c1 = wc[1][t], c2 = wc[2][t], c3 = wc[3][t];
+            const uint32_t run = running[t];
             wc[0][t] = run;
             wc[1][t] = run + c0;
             wc[2][t] = run + c0 + c1;
@@ -273,11 +284,33 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint64_t* __restrict__
             running[t] = run + c0 + c1 + c2 + c3;
         }
         __syncthreads();
-        if (valid) {
-            uint32_t pos = boff[d] + wc[w][d] + rank;
-            kout[pos] = k;
-            vout[pos] = v;
+        kk[r] = k;
+        vv[r] = v;
+        lr[r] = valid ? ((d << 16) | (wc[w][d] + rank)) : ~0u;
+    }
+    // 2. the tile in digit order in LDS (running[] now holds the tile's
+    //    digit histogram; its exclusive scan gives each digit's first slot)
+    uint32_t tot;
+    dstart[t] = block_excl_scan256<uint32_t>(running[t], sh4, &tot);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; r++) {
+        if (lr[r] != ~0u) {
+            const uint32_t p = dstart[lr[r] >> 16] + (lr[r] & 0xffffu);
+            sk[p] = kk[r];
+            sv[p] = vv[r];
         }
+    }
+    __syncthreads();
+    // 3. out in slot order: consecutive threads write consecutive places of
+    //    one digit's output range
+    const int cnt = (int)(n - base < RS_TILE ? n - base : RS_TILE);
+    for (int j = t; j < cnt; j += 256) {
+        const uint64_t k = sk[j];
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        const uint32_t pos = boff[d] + (uint32_t)j - dstart[d];
+        kout[pos] = k;
+        vout[pos] = sv[j];
     }
 }
 
