@@ -403,6 +403,13 @@ int gx_conv3d_fwd(gx_ctx* ctx, const uint16_t* in, int B, int S, int Cin, const 
 int gx_conv3d_fwd_fused(gx_ctx* ctx, const uint16_t* in, int c1, const uint16_t* in2, int upsample,
                         int B, int S, int Cin, const uint16_t* w, const float* bias, int Cout,
                         int act, uint16_t* out_bf16, float* out_f32);
+/* 3^3 convolution (as gx_conv3d_fwd, bf16 output) that also writes the 2^3
+ * average pooling of that output, pool_bf16 [B][(S/2)^3][Cout]: equals
+ * gx_conv3d_fwd followed by gx_avgpool2, bit for bit (the U-Net's encoder
+ * convolutions before each pooling).  S even. */
+int gx_conv3d_fwd_pool(gx_ctx* ctx, const uint16_t* in, int B, int S, int Cin, const uint16_t* w,
+                       const float* bias, int Cout, int act, uint16_t* out_bf16,
+                       uint16_t* pool_bf16);
 /* din = dL/din from dout = dL/dout ([B][S^3][Cout]) for the layer of weights w
  * ([Cout][kvol][Cin]); when y_in (the layer input, itself the LeakyReLU output
  * of the previous layer) is given, din is multiplied by that activation's

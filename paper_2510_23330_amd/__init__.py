@@ -379,6 +379,13 @@ class Engine:
             S, Cin, _ptr(w, torch.bfloat16), _ptr(bias, torch.float32), Cout, int(act),
             _ptr(out_bf16, torch.bfloat16), _ptr(out_f32, torch.float32)))
 
+    def conv3d_fwd_pool(self, x, B, S, Cin, w, bias, Cout, act, out_bf16, pool_bf16):
+        torch = _torch()
+        self._check(self.lib.gx_conv3d_fwd_pool(
+            self.ctx, _ptr(x, torch.bfloat16), B, S, Cin, _ptr(w, torch.bfloat16),
+            _ptr(bias, torch.float32), Cout, int(act), _ptr(out_bf16, torch.bfloat16),
+            _ptr(pool_bf16, torch.bfloat16)))
+
     def conv3d_bwd_data(self, dout, B, S, Cin, w, ksize, Cout, y_in, din):
         torch = _torch()
         self._check(self.lib.gx_conv3d_bwd_data(self.ctx, _ptr(dout, torch.bfloat16), B, S, Cin,

@@ -222,6 +222,7 @@ struct ConvSrc {
     const uint16_t* in2;
     int c1;  // channels taken from the first source (Cin when in2 is null)
     int up;  // 1: sources hold (S/2)^3 voxels
+    uint16_t* pool = nullptr;  // slab kernel: 2^3 average of the bf16 output ([B][(S/2)^3][Cout])
 };
 
 template <int BN, int CK>
@@ -560,6 +561,39 @@ __global__ __launch_bounds__(256, BN == 32 ? 3 : 2) void k_conv3d_slab(const uin
                 }
                 if (out_bf) out_bf[o] = f2bf(v);
                 if (out_f32) out_f32[o] = v;
+            }
+        }
+    }
+    if (src.pool) {
+        // 2^3 average pooling of the bf16 outputs: a lane holds all eight
+        // voxels of its blocks (z pair: tiles r and r + 4, y pair: tiles r and
+        // r + 1, x pair: q and q + 1); summed in the order of k_avgpool2
+        const int So = S / 2, Z = z0 + 2 * wv;
+        if (Z < S) {
+#pragma unroll
+            for (int yp = 0; yp < 2; yp++) {
+                const int Y = y0 + 2 * yp;
+                if (Y >= S) continue;
+#pragma unroll
+                for (int j = 0; j < NT; j++) {
+                    const int col = n0 + j * 16 + (lane & 15);
+                    const float bv = bias ? bias[col] : 0.0f;
+#pragma unroll
+                    for (int qp = 0; qp < 2; qp++) {
+                        const int X = x0 + (lane >> 4) * 4 + 2 * qp;
+                        if (X >= S) continue;
+                        float sum = 0.0f;
+#pragma unroll
+                        for (int d = 0; d < 8; d++) {
+                            const int r = (d >> 2) * 4 + 2 * yp + ((d >> 1) & 1);
+                            float v = acc[r][j][2 * qp + (d & 1)] + bv;
+                            if (mode == EP_LRELU) v = v > 0.0f ? v : LRELU_SLOPE * v;
+                            sum += bf2f(f2bf(v));
+                        }
+                        const int64_t po = (((int64_t)b * So + Z / 2) * So + Y / 2) * So + X / 2;
+                        src.pool[po * g.Cout + col] = f2bf(0.125f * sum);
+                    }
+                }
             }
         }
     }
@@ -1066,6 +1100,28 @@ extern "C" int gx_conv3d_fwd(gx_ctx* ctx, const uint16_t* in, int B, int S, int 
     const int kv = ksize == 3 ? 27 : 1;
     ConvGeom g{B, S, Cin, Cout, kv, (int64_t)B * S * S * S, kv * Cin, ilog2(Cin)};
     return launch_conv(ctx, in, w, bias, g, act ? EP_LRELU : EP_NONE, nullptr, out_bf16, out_f32);
+}
+
+extern "C" int gx_conv3d_fwd_pool(gx_ctx* ctx, const uint16_t* in, int B, int S, int Cin,
+                                  const uint16_t* w, const float* bias, int Cout, int act,
+                                  uint16_t* out_bf16, uint16_t* pool_bf16) {
+    if (!ctx || !in || !w || !out_bf16 || !pool_bf16) return GX_EINVAL;
+    GX_TRY(check_conv(ctx, B, S, Cin, Cout, 3, Cin));
+    if (S % 2 || S < 2) return gx_fail(ctx, GX_EINVAL, "conv3d_fwd_pool: S must be even");
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    ConvGeom g{B, S, Cin, Cout, 27, (int64_t)B * S * S * S, 27 * Cin, ilog2(Cin)};
+    const int mode = act ? EP_LRELU : EP_NONE;
+    if (Cout % 32 == 0 && Cin % 8 == 0) {  // slab kernel: pooled in its epilogue
+        ConvSrc src{nullptr, Cin, 0};
+        src.pool = pool_bf16;
+        return launch_conv(ctx, in, w, bias, g, mode, nullptr, out_bf16, nullptr, src);
+    }
+    GX_TRY(launch_conv(ctx, in, w, bias, g, mode, nullptr, out_bf16, nullptr));
+    const int64_t n = (int64_t)B * S * S * S * Cout / 8;
+    hipLaunchKernelGGL(k_avgpool2, dim3(gx_blocks(n, 256)), dim3(256), 0, ctx->stream,
+                       (const uint16_t*)out_bf16, B, S, Cout, pool_bf16);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
 }
 
 extern "C" int gx_conv3d_fwd_fused(gx_ctx* ctx, const uint16_t* in, int c1, const uint16_t* in2,

@@ -175,10 +175,13 @@ class UNet:
         for l in range(self.levels):
             s = S // 2 ** l
             self._conv(f"e{l}a", h, s, A[f"e{l}a"])
-            self._conv(f"e{l}b", A[f"e{l}a"], s, A[f"e{l}b"])
-            if l < self.levels - 1:
-                self.eng.avgpool2(A[f"e{l}b"], B, s, ch[l], A[f"p{l}"])
+            if l < self.levels - 1:  # the pooled copy comes from the same launch
+                ly = self.by[f"e{l}b"]
+                self.eng.conv3d_fwd_pool(A[f"e{l}a"], B, s, ly.cin, self._w(ly), self._b(ly),
+                                         ly.cout, ly.act, A[f"e{l}b"], A[f"p{l}"])
                 h = A[f"p{l}"]
+            else:
+                self._conv(f"e{l}b", A[f"e{l}a"], s, A[f"e{l}b"])
         h = A[f"e{self.levels - 1}b"]
         for l in range(self.levels - 2, -1, -1):
             s = S // 2 ** l

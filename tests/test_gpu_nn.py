@@ -370,3 +370,27 @@ def test_unet_inference_equals_training_forward(gx, eng):
     x[..., :5] = rng.normal(size=(B, S, S, S, 5))
     xt = _bf(x)
     assert torch.equal(tr.forward(xt).clone(), inf.forward(xt))
+
+
+@pytest.mark.parametrize("B,S,Cin,Cout", [(2, 16, 8, 32), (1, 12, 32, 64), (2, 10, 16, 128),
+                                          (1, 8, 16, 16)])
+def test_conv_pool_equals_conv_then_pool(gx, eng, B, S, Cin, Cout):
+    # The pooled copy written by the convolution (in the slab kernel's
+    # epilogue for outputs a multiple of 32; by a second launch otherwise)
+    # equals gx_avgpool2 of the convolution's output, bit for bit; S = 10 and
+    # 12 leave partial slabs, Cout = 128 takes two column blocks.
+    import torch
+    rng = np.random.default_rng(5)
+    x = _bf(oracle.bf16_round(rng.normal(size=(B, S, S, S, Cin))))
+    w = _bf(oracle.bf16_round(rng.normal(scale=0.1, size=(Cout, 27, Cin))))
+    bias = torch.as_tensor(rng.normal(size=Cout).astype(np.float32), device="cuda")
+    V = B * S ** 3
+    ref = torch.zeros(V * Cout, dtype=torch.bfloat16, device="cuda")
+    eng.conv3d_fwd(x, B, S, Cin, w, bias, 3, Cout, 1, out_bf16=ref)
+    refp = torch.zeros(V * Cout // 8, dtype=torch.bfloat16, device="cuda")
+    eng.avgpool2(ref, B, S, Cout, refp)
+    out = torch.zeros_like(ref)
+    pool = torch.full_like(refp, float("nan"))
+    eng.conv3d_fwd_pool(x, B, S, Cin, w, bias, Cout, 1, out, pool)
+    assert torch.equal(out, ref)
+    assert torch.equal(pool.view(torch.int16), refp.view(torch.int16))
