@@ -403,6 +403,14 @@ int gx_conv3d_fwd(gx_ctx* ctx, const uint16_t* in, int B, int S, int Cin, const 
 int gx_conv3d_fwd_fused(gx_ctx* ctx, const uint16_t* in, int c1, const uint16_t* in2, int upsample,
                         int B, int S, int Cin, const uint16_t* w, const float* bias, int Cout,
                         int act, uint16_t* out_bf16, float* out_f32);
+/* 1^3 convolution (the network head) whose first nc of its Cout outputs are
+ * written as out[v * out_stride + c] = fmaf(value, scale[c], shift[c]) (scale,
+ * shift device float [nc]); the other outputs are not stored.  Equals
+ * gx_conv3d_fwd (ksize 1, FP32 output) followed by gx_chan_affine with
+ * in_stride Cout, bit for bit. */
+int gx_conv_head(gx_ctx* ctx, const uint16_t* in, int B, int S, int Cin, const uint16_t* w,
+                 const float* bias, int Cout, int nc, const float* scale, const float* shift,
+                 float* out, int out_stride);
 /* 3^3 convolution (as gx_conv3d_fwd, bf16 output) that also writes the 2^3
  * average pooling of that output, pool_bf16 [B][(S/2)^3][Cout]: equals
  * gx_conv3d_fwd followed by gx_avgpool2, bit for bit (the U-Net's encoder

@@ -379,6 +379,13 @@ class Engine:
             S, Cin, _ptr(w, torch.bfloat16), _ptr(bias, torch.float32), Cout, int(act),
             _ptr(out_bf16, torch.bfloat16), _ptr(out_f32, torch.float32)))
 
+    def conv_head(self, x, B, S, Cin, w, bias, Cout, nc, scale, shift, out, out_stride):
+        torch = _torch()
+        self._check(self.lib.gx_conv_head(
+            self.ctx, _ptr(x, torch.bfloat16), B, S, Cin, _ptr(w, torch.bfloat16),
+            _ptr(bias, torch.float32), Cout, int(nc), _ptr(scale, torch.float32),
+            _ptr(shift, torch.float32), _ptr(out, torch.float32), int(out_stride)))
+
     def conv3d_fwd_pool(self, x, B, S, Cin, w, bias, Cout, act, out_bf16, pool_bf16):
         torch = _torch()
         self._check(self.lib.gx_conv3d_fwd_pool(

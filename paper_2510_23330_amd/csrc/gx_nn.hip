@@ -96,6 +96,15 @@ __device__ __forceinline__ uint4 im2col8t(const uint16_t* __restrict__ in, const
 // epilogue modes
 enum { EP_NONE = 0, EP_LRELU = 1, EP_DACT = 2 };
 
+// Optional per-channel affine output of the generic kernel: when scale is set,
+// output channels col < nc go to out_f32[m * stride + col] as
+// fmaf(value, scale[col], shift[col]) and the others are dropped.
+struct ConvAffine {
+    const float* scale = nullptr;
+    const float* shift = nullptr;
+    int nc = 0, stride = 0;
+};
+
 // Block tile CV_BM (= 256) voxels x BN output channels, 4 waves, each wave
 // 64 voxels x BN: per 32-wide K slice a wave issues 4 x BN/16 MFMAs from 4 A
 // and BN/16 B fragments.  Two LDS stages: the next K slice is fetched into
@@ -107,7 +116,7 @@ __global__ __launch_bounds__(256) void k_conv3d(const uint16_t* __restrict__ in,
                                                 const float* __restrict__ bias, ConvGeom g,
                                                 int mode, const uint16_t* __restrict__ yref,
                                                 uint16_t* __restrict__ out_bf,
-                                                float* __restrict__ out_f32) {
+                                                float* __restrict__ out_f32, ConvAffine aff) {
     constexpr int MR = CV_BM / 64;  // A rows staged per thread and 16-row MFMA tiles per wave
     constexpr int NT = BN / 16;     // MFMA column tiles per wave
     __shared__ __attribute__((aligned(16))) uint16_t sA[2][CV_BM * CV_APITCH];
@@ -187,6 +196,10 @@ __global__ __launch_bounds__(256) void k_conv3d(const uint16_t* __restrict__ in,
                     v = v > 0.0f ? v : LRELU_SLOPE * v;
                 } else if (mode == EP_DACT) {
                     v = bf2f(yref[o]) > 0.0f ? v : LRELU_SLOPE * v;
+                }
+                if (aff.scale) {
+                    if (col < aff.nc) out_f32[m * aff.stride + col] = fmaf(v, aff.scale[col], aff.shift[col]);
+                    continue;
                 }
                 if (out_bf) out_bf[o] = f2bf(v);
                 if (out_f32) out_f32[o] = v;
@@ -1043,7 +1056,8 @@ static void launch_brick(gx_ctx* ctx, dim3 grid, const uint16_t* in, const uint1
 
 static int launch_conv(gx_ctx* ctx, const uint16_t* in, const uint16_t* w, const float* bias,
                        const ConvGeom& g, int mode, const uint16_t* yref, uint16_t* ob,
-                       float* of, ConvSrc src = ConvSrc{nullptr, -1, 0}) {
+                       float* of, ConvSrc src = ConvSrc{nullptr, -1, 0},
+                       ConvAffine aff = ConvAffine{}) {
     if (src.c1 < 0) src.c1 = g.Cin;
     if (g.kvol == 27 && g.Cout % 32 == 0 && g.Cin % 8 == 0 && src.c1 % 8 == 0) {
         // weights staged in LDS: re-laid out chunk-major first
@@ -1080,13 +1094,13 @@ static int launch_conv(gx_ctx* ctx, const uint16_t* in, const uint16_t* w, const
     const unsigned gx = (unsigned)((g.M + CV_BM - 1) / CV_BM);
     if (g.Cout % 64 == 0)
         hipLaunchKernelGGL(k_conv3d<64>, dim3(gx, g.Cout / 64), dim3(256), 0, ctx->stream, in, w,
-                           bias, g, mode, yref, ob, of);
+                           bias, g, mode, yref, ob, of, aff);
     else if (g.Cout % 32 == 0)
         hipLaunchKernelGGL(k_conv3d<32>, dim3(gx, g.Cout / 32), dim3(256), 0, ctx->stream, in, w,
-                           bias, g, mode, yref, ob, of);
+                           bias, g, mode, yref, ob, of, aff);
     else
         hipLaunchKernelGGL(k_conv3d<16>, dim3(gx, g.Cout / 16), dim3(256), 0, ctx->stream, in, w,
-                           bias, g, mode, yref, ob, of);
+                           bias, g, mode, yref, ob, of, aff);
     GX_LAUNCH_CHECK(ctx);
     return GX_OK;
 }
@@ -1100,6 +1114,23 @@ extern "C" int gx_conv3d_fwd(gx_ctx* ctx, const uint16_t* in, int B, int S, int 
     const int kv = ksize == 3 ? 27 : 1;
     ConvGeom g{B, S, Cin, Cout, kv, (int64_t)B * S * S * S, kv * Cin, ilog2(Cin)};
     return launch_conv(ctx, in, w, bias, g, act ? EP_LRELU : EP_NONE, nullptr, out_bf16, out_f32);
+}
+
+extern "C" int gx_conv_head(gx_ctx* ctx, const uint16_t* in, int B, int S, int Cin,
+                            const uint16_t* w, const float* bias, int Cout, int nc,
+                            const float* scale, const float* shift, float* out, int out_stride) {
+    if (!ctx || !in || !w || !scale || !shift || !out || nc < 1 || nc > Cout || out_stride < nc)
+        return GX_EINVAL;
+    GX_TRY(check_conv(ctx, B, S, Cin, Cout, 1, Cin));
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    ConvGeom g{B, S, Cin, Cout, 1, (int64_t)B * S * S * S, Cin, ilog2(Cin)};
+    ConvAffine aff;
+    aff.scale = scale;
+    aff.shift = shift;
+    aff.nc = nc;
+    aff.stride = out_stride;
+    return launch_conv(ctx, in, w, bias, g, EP_NONE, nullptr, nullptr, out, ConvSrc{nullptr, -1, 0},
+                       aff);
 }
 
 extern "C" int gx_conv3d_fwd_pool(gx_ctx* ctx, const uint16_t* in, int B, int S, int Cin,

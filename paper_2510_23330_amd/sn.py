@@ -222,9 +222,8 @@ class Surrogate:
         for a in range(0, K, B):
             b = min(B, K - a)
             net.Bcur = b
-            pred = net.forward(x_bf16[a * V * 8:(a + b) * V * 8])
-            self.eng.chan_affine(pred[:b * V * 16], 16, 5, self.std_out, self.mean_out,
-                                 out=out_f32[a * V * 5:(a + b) * V * 5], out_stride=5)
+            net.forward(x_bf16[a * V * 8:(a + b) * V * 8], out_phys=out_f32[a * V * 5:(a + b) * V * 5],
+                        scale=self.std_out, shift=self.mean_out)
         net.Bcur = B
         return out_f32
 

@@ -168,8 +168,10 @@ class UNet:
                                   ly.cout, ly.act, out_bf16=out_bf)
 
     # ---- forward ----------------------------------------------------------------
-    def forward(self, x):
-        """x: bf16 [B * S^3 * 8] standardized input; returns fp32 [B * S^3 * 16]."""
+    def forward(self, x, out_phys=None, scale=None, shift=None):
+        """x: bf16 [B * S^3 * 8] standardized input; returns fp32 [B * S^3 * 16].
+        With out_phys (fp32 [B * S^3 * 5]) the head writes the first five
+        outputs mapped by scale * y + shift there instead, and returns it."""
         A, S, ch, B = self.acts, self.S, self.ch, self.Bcur
         h = x
         for l in range(self.levels):
@@ -196,6 +198,11 @@ class UNet:
                 self._conv_fused(f"d{l}a", A[f"u{l}c"], ch[l], A[f"e{l}b"], 0, s, A[f"d{l}a"])
             self._conv(f"d{l}b", A[f"d{l}a"], s, A[f"d{l}b"])
             h = A[f"d{l}b"]
+        if out_phys is not None:
+            ly = self.by["head"]
+            self.eng.conv_head(h, B, S, ly.cin, self._w(ly), self._b(ly), ly.cout, N_CHAN, scale,
+                               shift, out_phys, N_CHAN)
+            return out_phys
         self._conv("head", h, S, out_f32=self.pred)
         return self.pred
 

@@ -394,3 +394,25 @@ def test_conv_pool_equals_conv_then_pool(gx, eng, B, S, Cin, Cout):
     eng.conv3d_fwd_pool(x, B, S, Cin, w, bias, Cout, 1, out, pool)
     assert torch.equal(out, ref)
     assert torch.equal(pool.view(torch.int16), refp.view(torch.int16))
+
+
+@pytest.mark.parametrize("B,S,Cin,Cout,nc", [(2, 9, 32, 16, 5), (1, 16, 32, 32, 7)])
+def test_conv_head_equals_conv_then_affine(gx, eng, B, S, Cin, Cout, nc):
+    # The head convolution writing scale * y + shift for its first nc outputs
+    # equals the 1^3 convolution followed by gx_chan_affine, bit for bit
+    # (S = 9 leaves a partial 256-voxel block).
+    import torch
+    rng = np.random.default_rng(8)
+    x = _bf(oracle.bf16_round(rng.normal(size=(B, S, S, S, Cin))))
+    w = _bf(oracle.bf16_round(rng.normal(scale=0.2, size=(Cout, 1, Cin))))
+    bias = torch.as_tensor(rng.normal(size=Cout).astype(np.float32), device="cuda")
+    scale = torch.as_tensor(rng.uniform(0.5, 2.0, nc).astype(np.float32), device="cuda")
+    shift = torch.as_tensor(rng.normal(size=nc).astype(np.float32), device="cuda")
+    V = B * S ** 3
+    full = torch.zeros(V * Cout, dtype=torch.float32, device="cuda")
+    eng.conv3d_fwd(x, B, S, Cin, w, bias, 1, Cout, 0, out_f32=full)
+    ref = torch.zeros(V * nc, dtype=torch.float32, device="cuda")
+    eng.chan_affine(full, Cout, nc, scale, shift, out=ref, out_stride=nc)
+    got = torch.full_like(ref, float("nan"))
+    eng.conv_head(x, B, S, Cin, w, bias, Cout, nc, scale, shift, got, nc)
+    assert torch.equal(got, ref)
