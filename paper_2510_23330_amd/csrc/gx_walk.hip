@@ -247,6 +247,9 @@ __global__ __launch_bounds__(64) void k_walk_grav_wave(
     const int g = xcd_remap(blockIdx.x, ng);
     if (g >= ng) return;
     const int lane = threadIdx.x;
+    const char* bx[6];
+#pragma unroll
+    for (int d = 0; d < 6; d++) bx[d] = reinterpret_cast<const char*>(wbox + d * nn);
     __shared__ int32_t stk[GWALK_STACK];
     const NodeRec G = nodes[groups[g]];
     const double L = box[3];
@@ -278,13 +281,16 @@ __global__ __launch_bounds__(64) void k_walk_grav_wave(
                 for (int d = 0; d < 3; d++) lo[w][d] = hi[w][d] = 0.0;
                 continue;
             }
-            const int64_t i = n[w] >= 0 ? n[w] : 0;
+            // 32-bit byte offsets from per-array bases (loads with a scalar
+            // base address; the arrays are below 2 GB, checked at build)
+            const uint32_t i = n[w] >= 0 ? (uint32_t)n[w] : 0u;
+            const uint32_t o8 = i * 8u;
 #pragma unroll
             for (int d = 0; d < 3; d++) {
-                lo[w][d] = wbox[d * nn + i];
-                hi[w][d] = wbox[(3 + d) * nn + i];
+                lo[w][d] = *reinterpret_cast<const double*>(bx[d] + o8);
+                hi[w][d] = *reinterpret_cast<const double*>(bx[3 + d] + o8);
             }
-            rec[w] = wrec[i];
+            rec[w] = *reinterpret_cast<const int4*>(reinterpret_cast<const char*>(wrec) + 2u * o8);
         }
         int nch[GWALK_WK], first[GWALK_WK];
 #pragma unroll
