@@ -413,8 +413,11 @@ __global__ void k_wrelayout(const uint16_t* __restrict__ w, int Cout, int Cin,
         *reinterpret_cast<const uint4*>(w + ((int64_t)co * 27 + tap) * Cin + cg * 8);
 }
 
-template <int BN>
-__global__ __launch_bounds__(256, BN == 32 ? 3 : 2) void k_conv3d_slab(const uint16_t* __restrict__ in,
+// RT row tiles per wave: 8 (wave w owns z slices 2w, 2w + 1; 8-slice slabs)
+// or 4 (one z slice per wave; 4-slice slabs, half the accumulators, so the
+// 64-output variant also runs three workgroups per CU).
+template <int BN, int RT>
+__global__ __launch_bounds__(256, (BN == 32 || RT == 4) ? 3 : 2) void k_conv3d_slab(const uint16_t* __restrict__ in,
                                                         const uint16_t* __restrict__ wr,
                                                         const float* __restrict__ bias, ConvGeom g,
                                                         int mode, const uint16_t* __restrict__ yref,
@@ -422,12 +425,14 @@ __global__ __launch_bounds__(256, BN == 32 ? 3 : 2) void k_conv3d_slab(const uin
                                                         float* __restrict__ out_f32, ConvSrc src) {
     constexpr int NT = BN / 16;
     constexpr int NSTEP = 7;  // ceil(27 / 4)
-    __shared__ __attribute__((aligned(16))) uint16_t hal[SHVOX * 8];
+    constexpr int ZW = RT / 4;                 // z slices per wave
+    constexpr int BZ = 4 * ZW, HVOX_ = (BZ + 2) * SHY * SHX;  // slab depth, halo voxels
+    __shared__ __attribute__((aligned(16))) uint16_t hal[HVOX_ * 8];
     // 27 taps of weights plus a zero row for the padding tap slot
     __shared__ __attribute__((aligned(16))) uint16_t wsh[28 * BN * 8];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int S = g.S;
-    const int nbx = (S + SBX - 1) / SBX, nby = (S + SBY - 1) / SBY, nbz = (S + SBZ - 1) / SBZ;
+    const int nbx = (S + SBX - 1) / SBX, nby = (S + SBY - 1) / SBY, nbz = (S + BZ - 1) / BZ;
     // each XCD takes a contiguous run of slabs, so neighbours that share halo
     // planes run on one L2 (the grid is padded to a multiple of 8)
     const int nslab = g.B * nbz * nby * nbx;
@@ -439,19 +444,19 @@ __global__ __launch_bounds__(256, BN == 32 ? 3 : 2) void k_conv3d_slab(const uin
     t /= nby;
     const int bz = t % nbz;
     const int b = t / nbz;
-    const int x0 = bx * SBX, y0 = by * SBY, z0 = bz * SBZ;
+    const int x0 = bx * SBX, y0 = by * SBY, z0 = bz * BZ;
     const int n0 = blockIdx.y * BN;
     const int64_t vs0 = (int64_t)b * S * S * S;
 
-    f32x4 acc[8][NT];
+    f32x4 acc[RT][NT];
 #pragma unroll
-    for (int r = 0; r < 8; r++)
+    for (int r = 0; r < RT; r++)
 #pragma unroll
         for (int j = 0; j < NT; j++) acc[r][j] = f32x4{0, 0, 0, 0};
 
-    // row tile r of this wave: z slice 2 wv + r / 4, y row r % 4, x = lane & 15;
+    // row tile r of this wave: z slice ZW wv + r / 4, y row r % 4, x = lane & 15;
     // its halo voxel is hbase plus a constant per r (an immediate LDS offset)
-    const int hbase = 2 * wv * SHY * SHX + (lane & 15);
+    const int hbase = ZW * wv * SHY * SHX + (lane & 15);
     const int kg = lane >> 4;  // tap slot of this lane within a step
 
     const int nchunk = g.Cin / 8;
@@ -460,10 +465,10 @@ __global__ __launch_bounds__(256, BN == 32 ? 3 : 2) void k_conv3d_slab(const uin
     // A chunk's tiles are fetched into registers one chunk ahead (their loads
     // run under the previous chunk's MFMAs) and committed to LDS between two
     // barriers.
-    // (the 64-output variant fetches only the halo ahead: its accumulators
-    // leave no room for the weights as well)
-    constexpr bool PFW = BN <= 32;
-    constexpr int NHV = (SHVOX + 255) / 256, NWV = PFW ? (27 * BN + 255) / 256 : 1;
+    // (with 8 row tiles the 64-output variant fetches only the halo ahead: its
+    // accumulators leave no room for the weights as well)
+    constexpr bool PFW = BN * RT <= 256;
+    constexpr int NHV = (HVOX_ + 255) / 256, NWV = PFW ? (27 * BN + 255) / 256 : 1;
     uint4 ph[NHV], pw[NWV];
     auto fetch_w = [&](int c) {
         const uint16_t* wc = wr + (int64_t)c * 27 * g.Cout * 8;
@@ -488,7 +493,7 @@ __global__ __launch_bounds__(256, BN == 32 ? 3 : 2) void k_conv3d_slab(const uin
                       hx = hr - hy * SHX;
             int Z = z0 - 1 + hz, Y = y0 - 1 + hy, X = x0 - 1 + hx;
             uint4 v = make_uint4(0, 0, 0, 0);
-            if (h < SHVOX && Z >= 0 && Z < S && Y >= 0 && Y < S && X >= 0 && X < S) {
+            if (h < HVOX_ && Z >= 0 && Z < S && Y >= 0 && Y < S && X >= 0 && X < S) {
                 if (src.up) {
                     Z >>= 1;
                     Y >>= 1;
@@ -508,7 +513,7 @@ __global__ __launch_bounds__(256, BN == 32 ? 3 : 2) void k_conv3d_slab(const uin
 #pragma unroll
         for (int u = 0; u < NHV; u++) {
             const int h = tid + 256 * u;
-            if (h < SHVOX) *reinterpret_cast<uint4*>(&hal[h * 8]) = ph[u];
+            if (h < HVOX_) *reinterpret_cast<uint4*>(&hal[h * 8]) = ph[u];
         }
         if (PFW) {
 #pragma unroll
@@ -538,13 +543,13 @@ __global__ __launch_bounds__(256, BN == 32 ? 3 : 2) void k_conv3d_slab(const uin
             const uint16_t* hp = &hal[(hbase + toff) * 8];
             bf16x8 a[8], bb[NT];
 #pragma unroll
-            for (int r = 0; r < 8; r++)
+            for (int r = 0; r < RT; r++)
                 a[r] = *reinterpret_cast<const bf16x8*>(hp + ((r >> 2) * SHY + (r & 3)) * SHX * 8);
 #pragma unroll
             for (int j = 0; j < NT; j++)
                 bb[j] = *reinterpret_cast<const bf16x8*>(&wsh[(tap * BN + j * 16 + (lane & 15)) * 8]);
 #pragma unroll
-            for (int r = 0; r < 8; r++)
+            for (int r = 0; r < RT; r++)
 #pragma unroll
                 for (int j = 0; j < NT; j++)
                     acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], bb[j], acc[r][j], 0, 0, 0);
@@ -553,8 +558,8 @@ __global__ __launch_bounds__(256, BN == 32 ? 3 : 2) void k_conv3d_slab(const uin
     // epilogue: lane holds rows 4 (lane / 16) + q of each tile, column lane % 16;
     // row x of tile r is voxel (z0 + 2 wv + r / 4, y0 + r % 4, x0 + x)
 #pragma unroll
-    for (int r = 0; r < 8; r++) {
-        const int Z = z0 + 2 * wv + (r >> 2), Y = y0 + (r & 3);
+    for (int r = 0; r < RT; r++) {
+        const int Z = z0 + ZW * wv + (r >> 2), Y = y0 + (r & 3);
         if (Z >= S || Y >= S) continue;
 #pragma unroll
         for (int j = 0; j < NT; j++) {
@@ -577,6 +582,7 @@ __global__ __launch_bounds__(256, BN == 32 ? 3 : 2) void k_conv3d_slab(const uin
             }
         }
     }
+    if constexpr (RT == 8)
     if (src.pool) {
         // 2^3 average pooling of the bf16 outputs: a lane holds all eight
         // voxels of its blocks (z pair: tiles r and r + 4, y pair: tiles r and
@@ -1069,12 +1075,18 @@ static int launch_conv(gx_ctx* ctx, const uint16_t* in, const uint16_t* w, const
         const int S = g.S;
         const int64_t nb = (int64_t)g.B * ((S + SBZ - 1) / SBZ) * ((S + SBY - 1) / SBY) *
                            ((S + SBX - 1) / SBX);
-        if (g.Cout % 64 == 0)
-            hipLaunchKernelGGL(k_conv3d_slab<64>, dim3(xcd_grid(nb), (unsigned)(g.Cout / 64)),
+        const int64_t nb4 = (int64_t)g.B * ((S + 3) / 4) * ((S + SBY - 1) / SBY) *
+                            ((S + SBX - 1) / SBX);
+        if (g.Cout % 64 == 0 && !src.pool)  // one z slice per wave (pooling needs z pairs)
+            hipLaunchKernelGGL((k_conv3d_slab<64, 4>), dim3(xcd_grid(nb4), (unsigned)(g.Cout / 64)),
                                dim3(256), 0, ctx->stream, in, (const uint16_t*)wr, bias, g, mode,
                                yref, ob, of, src);
-        else
-            hipLaunchKernelGGL(k_conv3d_slab<32>, dim3(xcd_grid(nb), (unsigned)(g.Cout / 32)),
+        else if (g.Cout % 64 == 0)
+            hipLaunchKernelGGL((k_conv3d_slab<64, 8>), dim3(xcd_grid(nb), (unsigned)(g.Cout / 64)),
+                               dim3(256), 0, ctx->stream, in, (const uint16_t*)wr, bias, g, mode,
+                               yref, ob, of, src);
+        else  // (one z slice per wave measured slower for 32 outputs)
+            hipLaunchKernelGGL((k_conv3d_slab<32, 8>), dim3(xcd_grid(nb), (unsigned)(g.Cout / 32)),
                                dim3(256), 0, ctx->stream, in, (const uint16_t*)wr, bias, g, mode,
                                yref, ob, of, src);
         GX_LAUNCH_CHECK(ctx);

@@ -43,7 +43,8 @@ def _close(got, ref, rel=2 ** -8, rms_frac=1e-4):
 # slabs per axis (S = 20) and one- to eight-chunk reductions.
 @pytest.mark.parametrize("B,S,Cin,Cout,k", [(2, 8, 8, 16, 3), (1, 8, 32, 32, 3), (2, 6, 32, 64, 3),
                                              (1, 8, 64, 128, 3), (2, 8, 32, 16, 1), (1, 5, 16, 48, 3),
-                                             (2, 4, 16, 32, 3), (2, 2, 32, 64, 3), (1, 20, 8, 32, 3)])
+                                             (2, 4, 16, 32, 3), (2, 2, 32, 64, 3), (1, 20, 8, 32, 3),
+                                             (1, 10, 16, 64, 3)])
 def test_conv_fwd(gx, eng, B, S, Cin, Cout, k):
     import torch
     rng = np.random.default_rng(B * 100 + S + Cin + Cout + k)
