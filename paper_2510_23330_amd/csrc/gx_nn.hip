@@ -427,9 +427,12 @@ __global__ __launch_bounds__(256, (BN == 32 || RT == 4) ? 3 : 2) void k_conv3d_s
     constexpr int NSTEP = 7;  // ceil(27 / 4)
     constexpr int ZW = RT / 4;                 // z slices per wave
     constexpr int BZ = 4 * ZW, HVOX_ = (BZ + 2) * SHY * SHX;  // slab depth, halo voxels
-    __shared__ __attribute__((aligned(16))) uint16_t hal[HVOX_ * 8];
-    // 27 taps of weights plus a zero row for the padding tap slot
-    __shared__ __attribute__((aligned(16))) uint16_t wsh[28 * BN * 8];
+    // one LDS block: the halo tile, then 27 taps of weights plus a zero row for
+    // the padding tap slot; after the last chunk it stages the output
+    constexpr int HAL_N = HVOX_ * 8, WSH_N = 28 * BN * 8;
+    __shared__ __attribute__((aligned(16))) uint16_t smem[HAL_N + WSH_N];
+    uint16_t* const hal = smem;
+    uint16_t* const wsh = smem + HAL_N;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int S = g.S;
     const int nbx = (S + SBX - 1) / SBX, nby = (S + SBY - 1) / SBY, nbz = (S + BZ - 1) / BZ;
@@ -556,7 +559,49 @@ __global__ __launch_bounds__(256, (BN == 32 || RT == 4) ? 3 : 2) void k_conv3d_s
         }
     }
     // epilogue: lane holds rows 4 (lane / 16) + q of each tile, column lane % 16;
-    // row x of tile r is voxel (z0 + 2 wv + r / 4, y0 + r % 4, x0 + x)
+    // row x of tile r is voxel (z0 + ZW wv + r / 4, y0 + r % 4, x0 + x).
+    // A bf16-only output is staged through LDS (voxel-major rows padded by 8
+    // values, so the four lane groups write different banks) and stored as
+    // whole 16-byte pieces, 8 channels of one voxel per lane: consecutive
+    // lanes write consecutive memory instead of 2-byte values 64 bytes apart.
+    if (out_bf && !out_f32 && mode != EP_DACT) {
+        constexpr int RH = RT / 2, BNP = BN + 8, NCH = BN / 8;
+        static_assert(4 * RH * 16 * BNP <= HAL_N + WSH_N, "output staging fits the tiles' LDS");
+        static_assert((RH * 16 * NCH) % 64 == 0, "whole pieces per lane");
+        uint16_t* const st = smem + wv * (RH * 16 * BNP);
+        __syncthreads();  // every wave is done with the halo and weight tiles
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+#pragma unroll
+            for (int rr = 0; rr < RH; rr++) {
+#pragma unroll
+                for (int j = 0; j < NT; j++) {
+                    const int cl = j * 16 + (lane & 15);
+                    const float bv = bias ? bias[n0 + cl] : 0.0f;
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        float v = acc[h * RH + rr][j][q] + bv;
+                        if (mode == EP_LRELU) v = v > 0.0f ? v : LRELU_SLOPE * v;
+                        st[(rr * 16 + (lane >> 4) * 4 + q) * BNP + cl] = f2bf(v);
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < RH * 16 * NCH / 64; u++) {
+                const int kk = lane + 64 * u;
+                const int vv = kk / NCH, c8 = kk - vv * NCH;
+                const int r = h * RH + (vv >> 4);
+                const int Z = z0 + ZW * wv + (r >> 2), Y = y0 + (r & 3), X = x0 + (vv & 15);
+                if (Z < S && Y < S && X < S) {
+                    const int64_t m = vs0 + ((int64_t)Z * S + Y) * S + X;
+                    *reinterpret_cast<uint4*>(&out_bf[m * g.Cout + n0 + c8 * 8]) =
+                        *reinterpret_cast<const uint4*>(&st[vv * BNP + c8 * 8]);
+                }
+            }
+            if (h == 0) __syncthreads();  // pieces read before the second half is staged
+        }
+    } else
 #pragma unroll
     for (int r = 0; r < RT; r++) {
         const int Z = z0 + ZW * wv + (r >> 2), Y = y0 + (r & 3);

@@ -63,6 +63,15 @@ def test_conv_fwd(gx, eng, B, S, Cin, Cout, k):
     eng.conv3d_fwd(_bf(x), B, S, Cin, _bf(w), torch.as_tensor(b, dtype=torch.float32, device="cuda"),
                    k, Cout, 1, out_f32=out)
     assert _close(_np(out), oracle.lrelu(ref), rel=1e-5)
+    # a bf16-only output (staged through LDS and stored in 16-byte pieces by
+    # the slab kernel) equals the bf16 rounding of the same values, bit for bit
+    bias_t = torch.as_tensor(b, dtype=torch.float32, device="cuda")
+    only = torch.full_like(outb, float("nan"))
+    eng.conv3d_fwd(_bf(x), B, S, Cin, _bf(w), bias_t, k, Cout, 0, out_bf16=only)
+    assert torch.equal(only.view(torch.int16), outb.view(torch.int16))
+    only_act = torch.full_like(outb, float("nan"))
+    eng.conv3d_fwd(_bf(x), B, S, Cin, _bf(w), bias_t, k, Cout, 1, out_bf16=only_act)
+    assert torch.equal(only_act.view(torch.int16), out.to(torch.bfloat16).view(torch.int16))
 
 
 @pytest.mark.parametrize("B,S,Cin,Cout,k", [(2, 8, 16, 32, 3), (1, 8, 64, 32, 3), (2, 6, 32, 16, 1),
