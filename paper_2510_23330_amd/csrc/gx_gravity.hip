@@ -4,13 +4,13 @@
 // group's box centre in FP64 and rounded to FP32; pair terms are summed in
 // FP32 over one LDS tile (<= 256 sources) and tiles are combined in FP64.
 //
-// Work layout (CDNA4, wave64): one workgroup of 256 threads per group.  A
+// Work layout (CDNA4, wave64): one workgroup of 512 threads per group.  A
 // group holds nG <= n_group receivers; the workgroup is split into
-// 256 / pad slices (pad = 64, 128 or 256 >= nG), each slice holding every
+// floor(512 / nG) slices of exactly nG lanes, each slice holding every
 // receiver once (one per lane) and taking its own share of each source
 // tile, so small groups still fill the lanes; the slices' partial sums are
-// combined through LDS at the end.  Every wave lies inside one slice, so all
-// lanes of a wave read the same source from LDS (a broadcast).  Sources are
+// combined through LDS at the end.  A wave reads at most two sources per LDS
+// instruction (one per slice it touches: LDS broadcasts).  Sources are
 // staged cooperatively: opened-leaf particle ranges are expanded into an
 // index chunk in LDS, then each thread loads one source, converts it to
 // group-relative FP32 and stores it into structure-of-arrays LDS tiles.
@@ -49,7 +49,10 @@ __global__ void k_direct_lists(int ng, int n, const int32_t* __restrict__ groups
                                int32_t* __restrict__ pr_cum, uint32_t* __restrict__ pp_tot,
                                unsigned long long* __restrict__ tot);
 
-#define GF_THREADS 256
+// 512 threads per group: more slices per tile, so fewer lanes of the waves
+// that issue sit idle when a group's size is not a multiple of 64 (e.g. 130
+// receivers: 3 slices over 7 waves instead of 1 slice over 3 waves per tile)
+#define GF_THREADS 512
 #define GF_TILE 256
 #define GF_CH 2048
 
@@ -70,7 +73,10 @@ struct alignas(4 * sizeof(T)) V4 {
 };
 
 template <typename T, bool QUAD>
-__global__ __launch_bounds__(GF_THREADS) void k_grav_force(
+// FP32: at most 80 VGPRs (six wavefronts per SIMD); left free, the compiler
+// takes 116 registers and four wavefronts, which measured ~7 % slower
+__global__ __launch_bounds__(GF_THREADS)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1))) void k_grav_force(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ nodes,
     const MomRec* __restrict__ mom, const double4* __restrict__ pos4, const float* __restrict__ e2s,
     const uint32_t* __restrict__ perm, const int64_t* __restrict__ pc_off,
@@ -94,10 +100,10 @@ __global__ __launch_bounds__(GF_THREADS) void k_grav_force(
     const double cx = (gn.lo[0] + gn.hi[0]) * 0.5;
     const double cy = (gn.lo[1] + gn.hi[1]) * 0.5;
     const double cz = (gn.lo[2] + gn.hi[2]) * 0.5;
-    // slices: pad = min(nG, 256) lanes hold the receivers once and
-    // floor(256 / pad) slices split each tile, so fewer than pad lanes of the
-    // block idle (the slices are combined through LDS, any width works);
-    // groups above 256 take several passes over their receivers
+    // slices: pad = min(nG, GF_THREADS) lanes hold the receivers once and
+    // floor(GF_THREADS / pad) slices split each tile, so fewer than pad lanes
+    // of the block idle (the slices are combined through LDS, any width
+    // works); larger groups take several passes over their receivers
     const int pad = nG < 1 ? 1 : (nG < GF_THREADS ? nG : GF_THREADS);
     const int nsl = GF_THREADS / pad, il = tid % pad, sl = tid / pad;
     const int npp = (int)pp_tot[g];
@@ -136,7 +142,7 @@ __global__ __launch_bounds__(GF_THREADS) void k_grav_force(
             V4<T> npa{};
             T npe = 0;
             auto fetch_src = [&](int t) {
-                if (t < che) {
+                if (tid < GF_TILE && t < che) {
                     const int j = jidx[t - ch];
                     const double4 p = pos4[j];
                     npa = V4<T>{(T)(p.x - cx), (T)(p.y - cy), (T)(p.z - cz), (T)p.w};
@@ -188,7 +194,7 @@ __global__ __launch_bounds__(GF_THREADS) void k_grav_force(
         // the current tile is evaluated
         V4<T> na{}, nb{}, nc{};
         auto fetch_cell = [&](int64_t t) {
-            if (t < c1) {
+            if (tid < GF_TILE && t < c1) {
                 const MomRec mr = mom[pc_list[t]];
                 na = V4<T>{(T)(mr.cx - cx), (T)(mr.cy - cy), (T)(mr.cz - cz), (T)mr.M};
                 nb = V4<T>{(T)mr.e2, (T)mr.q[0], (T)mr.q[1], (T)mr.q[2]};
