@@ -179,7 +179,34 @@ __global__ __launch_bounds__(256) void k_conv3d(const uint16_t* __restrict__ in,
         __syncthreads();
         cur ^= 1;
     }
-    // epilogue: lane holds rows 4*(lane/16) + t of each 16 x 16 tile, column lane % 16
+    // epilogue: lane holds rows 4*(lane/16) + t of each 16 x 16 tile, column lane % 16.
+    // A dense affine output (stride == nc, the network head) is staged in LDS
+    // and written as one contiguous run per block in 16-byte pieces.
+    if (aff.scale && aff.stride == aff.nc && BN == 16 && n0 == 0) {
+        float* const st = reinterpret_cast<float*>(&sA[0][0]);  // CV_BM * nc floats
+        static_assert(sizeof(sA) >= CV_BM * 16 * sizeof(float), "staging fits");
+        const int nc = aff.nc;
+        __syncthreads();  // every wave is done with the tiles
+#pragma unroll
+        for (int i = 0; i < MR; i++) {
+            const int col = lane & 15;
+            const float bv = bias ? bias[col] : 0.0f;
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                const int ml = wv * (16 * MR) + i * 16 + (lane >> 4) * 4 + t;
+                if (col < nc) st[ml * nc + col] = fmaf(acc[i][0][t] + bv, aff.scale[col], aff.shift[col]);
+            }
+        }
+        __syncthreads();
+        const int nv = (int)min((int64_t)CV_BM, g.M - m0);
+        const int nf = nv * nc;
+        float* const dst = out_f32 + m0 * nc;  // 16-byte aligned: CV_BM * nc * 4 is a multiple of 16
+        const int n4 = nf / 4;
+        for (int e = tid; e < n4; e += 256)
+            *reinterpret_cast<float4*>(dst + 4 * e) = *reinterpret_cast<const float4*>(st + 4 * e);
+        for (int e = 4 * n4 + tid; e < nf; e += 256) dst[e] = st[e];
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < MR; i++)
 #pragma unroll
