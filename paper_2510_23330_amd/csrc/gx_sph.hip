@@ -3,12 +3,13 @@
 // kernels of Table 4), Wendland C4 kernel, on the gas tree slot.
 //
 // Receivers: the gas tree's groups (maximal nodes of at most n_group
-// particles; compact boxes keep candidate lists short).  One wavefront per
-// group.  Groups are usually smaller than 64, so the wave is cut into
-// 64 / pad slices (pad = 16, 32 or 64 >= group size): every slice holds each
-// receiver once and takes its own share of the candidates; cross-slice sums
-// are butterfly shuffles, which give every lane of a receiver bit-identical
-// totals.  Each group's candidate list -- particles of every gas-tree leaf
+// particles; compact boxes keep candidate lists short).  One 256-thread
+// workgroup per group.  Groups are usually smaller than 64, so the workgroup
+// is cut into floor(256 / pad) slices of pad = min(group size, 64) lanes:
+// every slice holds each receiver once and takes its own share of the
+// candidates; the slices' partial sums go through LDS and are added in slice
+// order, which gives every lane of a receiver bit-identical totals.  Each
+// group's candidate list -- particles of every gas-tree leaf
 // whose box comes within the search radius of the group box -- is built by
 // the wave-cooperative breadth-first walk in gx_walk.hip, in one pass into a
 // fixed-capacity slot per group.
@@ -142,18 +143,10 @@ __global__ __launch_bounds__(64) void k_group_radius(int ng, const int32_t* __re
     if (threadIdx.x == 0) rad[g] = h * scale;
 }
 
-__device__ __forceinline__ int slice_pad(int nG) {
-    int pad = 16;
-    while (pad < nG && pad < 64) pad <<= 1;
-    return pad;
-}
-
-// Sum over the slices of a wave (lanes il, il + pad, ...): butterfly shuffles.
-template <typename T>
-__device__ __forceinline__ T slice_sum(T v, int pad) {
-    for (int o = pad; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+// Lanes per receiver slice: exactly the group's size (at most 64, larger
+// groups take several passes); floor(SPH_DT / pad) slices share the
+// candidates, so only SPH_DT mod pad lanes of the block idle.
+__device__ __forceinline__ int slice_pad(int nG) { return nG < 1 ? 1 : (nG < 64 ? nG : 64); }
 
 // Candidates ch .. che-1 of a group's list into LDS as FP32 positions
 // relative to the group centre and masses (whole block; synchronises).
@@ -322,7 +315,7 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density(
     // (a long list of a group above 64 receivers is evaluated here chunk by chunk)
     const bool in_lds = npp <= SPH_CAP;
     __shared__ float4 cand[SPH_CAP];
-    __shared__ float2 red[SPH_DT / 64][64];
+    __shared__ float2 red[SPH_DT];
     // hit lists; the list expansion uses the same space (slot + range
     // offsets) before the lists are built
     __shared__ __align__(16) uint16_t hl[SPH_HCAP][SPH_DT];
@@ -344,7 +337,7 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density(
     unsigned long long evals = 0;  // receiver x candidate evaluations, all passes
     for (int ic = 0; ic < nG; ic += pad) {
         const int s = B.begin + ic + il;
-        const bool act = ic + il < nG;
+        const bool act = sl < nsl && ic + il < nG;
         float xi = 0, yi = 0, zi = 0, mi = 1, H = 1.0f;
         if (act) {
             const double4 p = pos4[s];
@@ -387,16 +380,14 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density(
                     dens_hits(hl, nh, tid, cand, xi, yi, zi, Hinv2, s0, s1);
                 }
             }
-            // slices of this wave, then the four waves in order
-            s0 = slice_sum(s0, pad);
-            s1 = slice_sum(s1, pad);
-            if (lane < pad) red[wv][lane] = make_float2(s0, s1);
+            // the slices' partial sums, added in slice order (every copy of
+            // a receiver gets the same sums)
+            red[tid] = make_float2(s0, s1);
             __syncthreads();
             s0 = 0.0f;
             s1 = 0.0f;
-#pragma unroll
-            for (int w = 0; w < SPH_DT / 64; w++) {
-                const float2 r = red[w][il];
+            for (int q = 0; q < nsl; q++) {
+                const float2 r = red[q * pad + il];
                 s0 += r.x;
                 s1 += r.y;
             }
@@ -470,7 +461,7 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density_part(
     const int g = item.x;
     if (gdone[g]) return;
     __shared__ float4 cand[SPH_CAP];
-    __shared__ float2 red[SPH_DT / 64][64];
+    __shared__ float2 red[SPH_DT];
     __shared__ __align__(16) uint16_t hl[SPH_HCAP][SPH_DT];
     __shared__ int wtot[SPH_DT / 64];
     int* const xslot = reinterpret_cast<int*>(&hl[0][0]);
@@ -488,7 +479,7 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density_part(
     expand_chunk(GL, npp, ch, che, pos4, cx, cy, cz, cand, xslot, xroff, wtot, tid, SPH_DT);
     __syncthreads();
     const int s = B.begin + il;
-    bool act = il < nG;
+    bool act = sl < nsl && il < nG;
     float xi = 0, yi = 0, zi = 0, H = 1.0f;
     if (act) {
         act = (__float_as_uint(hst[s].w) & 0x100u) == 0;  // not finished
@@ -503,16 +494,13 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density_part(
     int nh;
     dens_scan(hl, nh, tid, sl, nsl, che - ch, act, cand, xi, yi, zi, H * H, Hinv2, s0, s1);
     dens_hits(hl, nh, tid, cand, xi, yi, zi, Hinv2, s0, s1);
-    s0 = slice_sum(s0, pad);
-    s1 = slice_sum(s1, pad);
-    if (lane < pad) red[wv][lane] = make_float2(s0, s1);
+    red[tid] = make_float2(s0, s1);
     __syncthreads();
-    if (tid < pad && il < nG) {
+    if (sl == 0 && il < nG) {  // the slices' partial sums in slice order
         s0 = 0.0f;
         s1 = 0.0f;
-#pragma unroll
-        for (int w = 0; w < SPH_DT / 64; w++) {
-            const float2 r = red[w][il];
+        for (int q = 0; q < nsl; q++) {
+            const float2 r = red[q * pad + il];
             s0 += r.x;
             s1 += r.y;
         }
@@ -766,8 +754,8 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_force(
     __shared__ float tc[SPH_TILE];
     __shared__ int jidx[SPH_TILE], jroff[SPH_TILE], wtot[SPH_DT / 64];
     __shared__ uint8_t fl[SPH_FCAP][SPH_DT];
-    __shared__ double redd[4][SPH_DT / 64][64];
-    __shared__ float redv[SPH_DT / 64][64];
+    __shared__ double redd[4][SPH_DT];
+    __shared__ float redv[SPH_DT];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const NodeRec B = nodes[groups[g]];
     const int nG = B.end - B.begin;
@@ -780,7 +768,7 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_force(
 
     for (int ic = 0; ic < nG; ic += pad) {
         const int s = B.begin + ic + il;
-        const bool act = ic + il < nG;
+        const bool act = sl < nsl && ic + il < nG;
         ForceRecv R = {0, 0, 0, 0, 0, 0, 1, 0, 1, 0, 0};
         float Hi = 1;
         if (act) {
@@ -849,29 +837,22 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_force(
             AZ += (double)fz;
             DU += (double)fu;
         }
-        // slices of each wave by shuffles, then the four waves in order
-        AX = slice_sum(AX, pad);
-        AY = slice_sum(AY, pad);
-        AZ = slice_sum(AZ, pad);
-        DU = slice_sum(DU, pad);
-        for (int o = pad; o < 64; o <<= 1) vs = fmaxf(vs, __shfl_xor(vs, o, 64));
+        // the slices' partial sums, added in slice order
         __syncthreads();
-        if (lane < pad) {
-            redd[0][wv][lane] = AX;
-            redd[1][wv][lane] = AY;
-            redd[2][wv][lane] = AZ;
-            redd[3][wv][lane] = DU;
-            redv[wv][lane] = vs;
-        }
+        redd[0][tid] = AX;
+        redd[1][tid] = AY;
+        redd[2][tid] = AZ;
+        redd[3][tid] = DU;
+        redv[tid] = vs;
         __syncthreads();
         if (act && sl == 0) {
             AX = AY = AZ = DU = 0.0;
-            for (int w = 0; w < SPH_DT / 64; w++) {
-                AX += redd[0][w][il];
-                AY += redd[1][w][il];
-                AZ += redd[2][w][il];
-                DU += redd[3][w][il];
-                vs = fmaxf(vs, redv[w][il]);
+            for (int q = 0; q < nsl; q++) {
+                AX += redd[0][q * pad + il];
+                AY += redd[1][q * pad + il];
+                AZ += redd[2][q * pad + il];
+                DU += redd[3][q * pad + il];
+                vs = fmaxf(vs, redv[q * pad + il]);
             }
             if (PART) {
                 const int64_t q = (int64_t)blockIdx.x * 64 + ic + il;
