@@ -50,8 +50,8 @@ FLOP_FORCE = 101                     # per SPH force candidate pair (Table 4)
 # known size (hbm_calib.py: FETCH_SIZE reads half the bytes copied, WRITE_SIZE
 # all of them).  Valid only for the kernel source with this SHA-256; any
 # change to gx_gravity.hip makes the bench report null until remeasured.
-GRAV_TRAFFIC = {"source_sha256": "bf0ed82a75544d8addd64275e07a2e3549202ae604ad52a327176b9ce1518cf8",
-                "fetch_kib": 4067149.125, "write_kib": 2853701.90625,
+GRAV_TRAFFIC = {"source_sha256": "a3d3eb3e96b0f3b25b0277057df50d3442b69ec67b795f182ff062edd99fd8f4",
+                "fetch_kib": 4065408.25, "write_kib": 2853768.21875,
                 "fetch_scale": 2.0, "write_scale": 1.0}
 
 

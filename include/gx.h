@@ -160,6 +160,10 @@ int gx_tree_build(gx_ctx* ctx, const gx_particles* p, int which, int n_leaf, int
  * flags      GX_QUAD | GX_DIRECT | GX_PREC_FP64
  * ax..pot    device FP64 outputs [n], overwritten, original order
  * stats      optional host: n_pp, n_pc, n_groups, ms (synchronises)
+ * The environment variable GX_WALK_SMALL_STACK = n > 0, read by each call,
+ * limits the list walk's small stack to min(n, 2048) entries and has the
+ * one-pass list construction try it first: a test hook for the retry with
+ * the large stack (the lists and forces do not change, only the work done).
  */
 int gx_gravity_forces(gx_ctx* ctx, const gx_particles* p, double G, double theta, int flags,
                       double* ax, double* ay, double* az, double* pot, gx_stats* stats);

@@ -35,7 +35,8 @@ int gx_walk_grav_wave(gx_ctx* ctx, TreeSlot& T, int ng, double theta2, bool smal
                       uint32_t* pc_cnt, uint32_t* pr_cnt, uint32_t* pp_tot, int32_t* pc_list,
                       int32_t* pr_begin, int32_t* pr_cum, int cap_pc, int cap_pr,
                       uint8_t* gflag, int32_t* gdepth);
-int gx_walk_stack_small();
+// Entries of the small walk stack (the context's limit when one is set).
+int gx_walk_stack_small(const gx_ctx* ctx);
 __global__ __launch_bounds__(256) void k_group_totals(
     int ng, const int32_t* __restrict__ groups, const NodeRec* __restrict__ recv,
     const NodeRec* __restrict__ nodes, const uint32_t* __restrict__ c0,
@@ -356,8 +357,11 @@ extern "C" int gx_gravity_forces(gx_ctx* ctx, const gx_particles* p, double G, d
             // the small stack when the previous call's deepest stack fits with an
             // eighth to spare; a small-stack walk that overflows only its stack
             // is repeated once with the large one
-            const int64_t s_small = gx_walk_stack_small();
-            bool small = prev_stack > 0 && prev_stack + prev_stack / 8 <= s_small;
+            const char* lim = std::getenv("GX_WALK_SMALL_STACK");
+            ctx->walk_small_cap = lim ? std::max(0, std::atoi(lim)) : 0;
+            const int64_t s_small = gx_walk_stack_small(ctx);
+            bool small = ctx->walk_small_cap > 0 ||
+                         (prev_stack > 0 && prev_stack + prev_stack / 8 <= s_small);
             for (int attempt = 0; attempt < 2 && !done; attempt++) {
                 GX_TRY(gx_walk_grav_wave(ctx, T, ng, theta2, small, (uint32_t*)Ls.pc_cnt.p,
                                          (uint32_t*)Ls.pr_cnt.p, (uint32_t*)Ls.pp_tot.p,

@@ -8,6 +8,7 @@
 #include <climits>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <string>
 #include <type_traits>
 
@@ -101,6 +102,11 @@ struct gx_ctx {
     Buf wpart;  // per-chunk partial weight gradients (ordered reduction)
     Buf wrel;   // 3^3 weights re-laid out chunk-major for the slab convolution
     Buf sph_work[24];
+    // > 0: the gravity walk's small stack holds only this many entries and is
+    // tried first (environment variable GX_WALK_SMALL_STACK, read by each
+    // gravity call), so that its overflow and the retry with the large stack
+    // can be exercised on small workloads
+    int walk_small_cap = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
 };
 

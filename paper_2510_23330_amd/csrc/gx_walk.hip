@@ -243,7 +243,8 @@ __global__ __launch_bounds__(64) void k_walk_grav_wave(
     const double* __restrict__ box, double theta2, uint32_t* __restrict__ pc_cnt,
     uint32_t* __restrict__ pr_cnt, uint32_t* __restrict__ pp_tot, int32_t* __restrict__ pc_list,
     int32_t* __restrict__ pr_begin, int32_t* __restrict__ pr_cum, int cap_pc, int cap_pr,
-    uint8_t* __restrict__ gflag, int32_t* __restrict__ gdepth) {
+    uint8_t* __restrict__ gflag, int32_t* __restrict__ gdepth, int scap) {
+    // scap: entries of stk in use, 1 <= scap <= GWALK_STACK
     const int g = xcd_remap(blockIdx.x, ng);
     if (g >= ng) return;
     const int lane = threadIdx.x;
@@ -340,7 +341,7 @@ __global__ __launch_bounds__(64) void k_walk_grav_wave(
             coff[w] = sp + ctot + ci - nch[w];
             ctot += wave_last(ci);
         }
-        if (sp + ctot > GWALK_STACK) {
+        if (sp + ctot > scap) {
             over = 1;
         } else {
 #pragma unroll
@@ -360,8 +361,13 @@ __global__ __launch_bounds__(64) void k_walk_grav_wave(
         pr_cnt[g] = (uint32_t)npr;
         pp_tot[g] = (uint32_t)npp;
         gflag[g] = (over || npc > cap_pc || npr > cap_pr) ? 1 : 0;
-        gdepth[g] = over ? GWALK_STACK + 1 : spmax;
+        gdepth[g] = over ? scap + 1 : spmax;
     }
+}
+
+int gx_walk_stack_small(const gx_ctx* ctx) {
+    const int c = ctx->walk_small_cap;
+    return (c > 0 && c < GWALK_STACK_S) ? c : GWALK_STACK_S;
 }
 
 int gx_walk_grav_wave(gx_ctx* ctx, TreeSlot& T, int ng, double theta2, bool small_stack,
@@ -370,16 +376,15 @@ int gx_walk_grav_wave(gx_ctx* ctx, TreeSlot& T, int ng, double theta2, bool smal
                       uint8_t* gflag, int32_t* gdepth) {
     GX_TRY(gx_walk_tree(ctx, T));
     auto kern = small_stack ? k_walk_grav_wave<GWALK_STACK_S> : k_walk_grav_wave<GWALK_STACK_L>;
+    const int scap = small_stack ? gx_walk_stack_small(ctx) : GWALK_STACK_L;
     hipLaunchKernelGGL(kern, dim3(xcd_grid(ng)), dim3(64), 0, ctx->stream, ng,
                        (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p, (int64_t)T.n_nodes,
                        (const double*)T.wbox.p, (const int4*)T.wrec.p, (const double*)T.box.p,
                        theta2, pc_cnt, pr_cnt, pp_tot, pc_list, pr_begin, pr_cum, cap_pc, cap_pr,
-                       gflag, gdepth);
+                       gflag, gdepth, scap);
     GX_LAUNCH_CHECK(ctx);
     return GX_OK;
 }
-
-int gx_walk_stack_small() { return GWALK_STACK_S; }
 
 // Totals of a set of per-group lists: tot[0] += sum c0, tot[1] += sum c1,
 // tot[2] += sum nG pp, tot[3] += sum nG c0, tot[4] += sum flag, and maxima
