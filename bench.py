@@ -48,15 +48,19 @@ FLOP_FORCE = 101                     # per SPH force candidate pair (Table 4)
 # rocprofv3 --pmc runs of this script (FETCH_SIZE, WRITE_SIZE in KiB per
 # dispatch) scaled by what the same counters read for a reference copy of
 # known size (hbm_calib.py: FETCH_SIZE reads half the bytes copied, WRITE_SIZE
-# all of them).  Valid only for the kernel source with this SHA-256; any
-# change to gx_gravity.hip makes the bench report null until remeasured.
+# all of them).  Valid only for the kernel source with this SHA-256 and the
+# particle order named (the outputs are scattered to the caller's order); any
+# change to gx_gravity.hip, or the other order, makes the bench report null.
 GRAV_TRAFFIC = {"source_sha256": "a3d3eb3e96b0f3b25b0277057df50d3442b69ec67b795f182ff062edd99fd8f4",
-                "fetch_kib": 4065408.25, "write_kib": 2853768.21875,
+                "particle_order": "morton",
+                "fetch_kib": 3676699.3125, "write_kib": 2289833.4375,
                 "fetch_scale": 2.0, "write_scale": 1.0}
 
 
-def grav_traffic_bytes():
+def grav_traffic_bytes(order):
     import hashlib
+    if order != GRAV_TRAFFIC["particle_order"]:
+        return None
     src = os.path.join(ROOT, "paper_2510_23330_amd", "csrc", "gx_gravity.hip")
     if GRAV_TRAFFIC["source_sha256"] is None:
         return None
@@ -82,7 +86,37 @@ def parse():
     ap.add_argument("--sn-cubes", type=int, default=64,
                     help="SN cubes of the plain-SPH vs surrogate region comparison (0 skips)")
     ap.add_argument("--sn-infer-batch", type=int, default=256)
+    ap.add_argument("--ic-order", choices=("morton", "generated"), default="morton",
+                    help="particle array order: Morton order of a 1024^3 grid per block "
+                         "(default) or the generator's order")
     return ap.parse_args()
+
+
+def morton_order(d):
+    """Reorder the particle arrays of ``d`` in place into the Morton order of a
+    1024^3 grid over their bounding box, separately for the collisionless
+    block and the gas block (which stays last).  N-body codes keep their
+    particle arrays in a space-filling-curve order; the library gathers its
+    sorted copies from, and writes its outputs to, the caller's order, so
+    with this order those accesses touch neighbouring memory.  Particle ids
+    travel with the particles; the physics does not depend on the order."""
+    n, go = len(d["x"]), int(d["gas_offset"])
+    q = []
+    for c in ("x", "y", "z"):
+        a = d[c]
+        lo, hi = a.min(), a.max()
+        v = np.clip(((a - lo) * (1024.0 / max(hi - lo, 1e-300))).astype(np.int64), 0, 1023)
+        w = np.zeros(n, np.int64)
+        for b in range(10):  # spread the 10 bits three apart
+            w |= ((v >> b) & 1) << (3 * b)
+        q.append(w)
+    key = (q[0] << 2) | (q[1] << 1) | q[2]
+    idx = np.concatenate([np.argsort(key[:go], kind="stable"),
+                          go + np.argsort(key[go:], kind="stable")])
+    for k, v in list(d.items()):
+        if isinstance(v, np.ndarray) and len(v) == n:
+            d[k] = v[idx]
+    d["u_gas"] = d["u_gas"][idx[go:] - go]
 
 
 def log(*a):
@@ -161,7 +195,10 @@ def main():
 
     t0 = time.perf_counter()
     d = ics.disk_galaxy(args.n, args.seed)
-    log(f"[bench] generated {args.n} particles in {time.perf_counter() - t0:.1f} s")
+    if args.ic_order == "morton":
+        morton_order(d)
+    log(f"[bench] generated {args.n} particles ({args.ic_order} order) in "
+        f"{time.perf_counter() - t0:.1f} s")
     eng = gx.Engine(0)
     p = gx.ParticleSet.from_numpy(d)
     u = torch.as_tensor(d["u_gas"], device="cuda")
@@ -260,7 +297,7 @@ def main():
                                "theta 0.5 + quadrupole, n_leaf 16, groups <= 256; SPH Wendland C4, "
                                "64 neighbours, groups <= 64; dt 2000 yr; 64 SN regions per step "
                                "to the surrogate",
-                   "n_particles": args.n, "seed": args.seed},
+                   "n_particles": args.n, "seed": args.seed, "particle_order": args.ic_order},
         "s_per_step": ms_step / 1e3,
         "grav_interactions_per_step": inter_step,
         "grav_pp_per_step": n_pp / args.steps,
@@ -287,7 +324,7 @@ def main():
                           "max_walk_stack": int(max(w[1] for w in walk_diag))},
         "energy_drift_rel": abs(E1 - E0) / abs(E0),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": grav_traffic_bytes(),
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": grav_traffic_bytes(args.ic_order),
                      "kernel": "k_grav_force<float,true>",
                      "flop_convention": f"{FLOP_PP}/pp + {FLOP_PC}/pc"},
     }
