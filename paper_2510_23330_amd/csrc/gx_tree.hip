@@ -304,6 +304,9 @@ __global__ __launch_bounds__(256) void k_moments_level(int cnt, const int32_t* _
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     double q[6] = {0, 0, 0, 0, 0, 0};
     if (nd.leaf) {
+        // unrolled so that several particle loads are in flight at once (the
+        // sums still run in particle order)
+#pragma unroll 4
         for (int s = nd.begin; s < nd.end; s++) {
             double4 p = pos4[s];
             M += p.w;
@@ -317,6 +320,7 @@ __global__ __launch_bounds__(256) void k_moments_level(int cnt, const int32_t* _
         cx /= M;
         cy /= M;
         cz /= M;
+#pragma unroll 4
         for (int s = nd.begin; s < nd.end; s++) {
             double4 p = pos4[s];
             double dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
