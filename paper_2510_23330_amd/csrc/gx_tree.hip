@@ -333,23 +333,35 @@ __global__ __launch_bounds__(256) void k_moments_level(int cnt, const int32_t* _
             q[5] += p.w * 3 * dy * dz;
         }
     } else {
-        for (int c = id + 1; c < nd.next; c = nodes[c].next) {
-            MomRec mc = mom[c];
-            M += mc.M;
-            cx += mc.M * mc.cx;
-            cy += mc.M * mc.cy;
-            cz += mc.M * mc.cz;
-            e2 += mc.M * (double)mc.e2;
-            NodeRec nc = nodes[c];
-            for (int d = 0; d < 3; d++) {
-                lo[d] = fmin(lo[d], nc.lo[d]);
-                hi[d] = fmax(hi[d], nc.hi[d]);
+        // at most eight children, linked by their next fields; the first pass
+        // keeps their positions so the second needs no link chasing
+        int cid[8];
+        int c = id + 1;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            cid[j] = c;
+            if (c < nd.next) {
+                MomRec mc = mom[c];
+                M += mc.M;
+                cx += mc.M * mc.cx;
+                cy += mc.M * mc.cy;
+                cz += mc.M * mc.cz;
+                e2 += mc.M * (double)mc.e2;
+                NodeRec nc = nodes[c];
+                for (int d = 0; d < 3; d++) {
+                    lo[d] = fmin(lo[d], nc.lo[d]);
+                    hi[d] = fmax(hi[d], nc.hi[d]);
+                }
+                c = nc.next;
             }
         }
         cx /= M;
         cy /= M;
         cz /= M;
-        for (int c = id + 1; c < nd.next; c = nodes[c].next) {
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const int c = cid[j];
+            if (c >= nd.next) continue;
             MomRec mc = mom[c];
             const double* qc = &q64[6 * (int64_t)c];
             double dx = mc.cx - cx, dy = mc.cy - cy, dz = mc.cz - cz;
