@@ -17,6 +17,17 @@ sph_force          hydro force (Table 3/4).
 kick_drift         second-order leapfrog, half kick / drift / half kick
                    (Sec. 3.2), positions and velocities in FP64 (Sec. 4.3).
 energy             total energy audit in FP64.
+eos                ideal-gas pressure and sound speed.
+conv3d*, voxelize  the surrogate's convolutions and particle-to-grid mapping
+                   (Sec. 3.3); the network composition is in ``oracle.unet``.
+sn                 (module) the supernova-region steps of Sec. 3.2: box
+                   extraction, injection, ambient state, inverse-CDF
+                   resampling, trust check, replacement by ID.
+
+Every function is pinned by the CPU tests to something other than itself:
+closed forms, brute force, invariants, hand-computed cases (the opening
+criterion at its boundary, the cell softening through its expansion, a
+head-on viscous pair), finite differences and statistical tests.
 """
 from __future__ import annotations
 
