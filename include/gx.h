@@ -372,6 +372,25 @@ int gx_sn_check(gx_ctx* ctx, const float* pred, int k, int grid, const double* l
                 const double* hi, uint8_t* ok);
 
 /*
+ * gx_sn_check_noalloc -- gx_sn_check for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  It allocates nothing, does not synchronise, and writes
+ * the flags to device memory; the outcome per region is that of gx_sn_check.
+ * pred    device float [k][grid^3][5] physical channels
+ * lo, hi  host double [5] (read during the call)
+ * ok_dev  device uint8 [k] (output: 1 = trusted)
+ * Its scratch (one 32-bit flag per region) is a static device array of
+ * GX_NOALLOC_MAX_REGIONS entries that each device keeps for the life of the
+ * process; gx_create takes its address.  k > GX_NOALLOC_MAX_REGIONS returns
+ * GX_EINVAL with a message.  Every call on one device shares that array, so
+ * calls that overlap on one device (two streams, two host threads) race;
+ * calls in stream order do not.  k = 0 is a no-op.
+ */
+#define GX_NOALLOC_MAX_REGIONS 16384
+int gx_sn_check_noalloc(gx_ctx* ctx, const float* pred, int k, int grid, const double* lo,
+                        const double* hi, uint8_t* ok_dev);
+
+/*
  * gx_sn_replace -- replace particles by ID (Sec. 3.2 step 4).  id: device
  * int64 [n] ids of the main arrays (each in [0, id_cap)); new particles with
  * ids new_id[m] overwrite position and velocity; u (device, index i - u_offset

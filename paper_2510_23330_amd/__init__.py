@@ -352,6 +352,18 @@ class Engine:
             ok.ctypes.data_as(C.c_void_p)))
         return ok[:int(k)].astype(bool)
 
+    def sn_check_noalloc(self, pred, k, grid, lo, hi, ok_dev):
+        """gx_sn_check without allocation or synchronisation: flags written to
+        the device uint8 tensor ok_dev [k] (1 = trusted)."""
+        torch = _torch()
+        lo_h = np.ascontiguousarray(np.asarray(lo, dtype=np.float64).reshape(5))
+        hi_h = np.ascontiguousarray(np.asarray(hi, dtype=np.float64).reshape(5))
+        self._check(self.lib.gx_sn_check_noalloc(
+            self.ctx, _ptr(pred, torch.float32), int(k), int(grid),
+            lo_h.ctypes.data_as(C.c_void_p), hi_h.ctypes.data_as(C.c_void_p),
+            _ptr(ok_dev, torch.uint8)))
+        return ok_dev
+
     def sn_replace(self, id, id_cap, x, y, z, vx, vy, vz, u, u_offset, H64, new_id, nx, ny, nz, nvx,
                    nvy, nvz, nu):
         torch = _torch()

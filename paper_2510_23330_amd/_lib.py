@@ -19,6 +19,7 @@ D = C.c_double
 GX_OK, GX_EINVAL, GX_ENOMEM, GX_EHIP, GX_ENOTBUILT, GX_ESTALE, GX_ENOCONV = 0, -1, -2, -3, -4, -5, -6
 GX_TREE_ALL, GX_TREE_GAS = 0, 1
 GX_QUAD, GX_DIRECT, GX_PREC_FP64 = 1, 2, 4
+GX_NOALLOC_MAX_REGIONS = 16384
 
 STATUS_NAMES = {0: "GX_OK", -1: "GX_EINVAL", -2: "GX_ENOMEM", -3: "GX_EHIP", -4: "GX_ENOTBUILT",
                 -5: "GX_ESTALE", -6: "GX_ENOCONV"}
@@ -74,6 +75,7 @@ SIGNATURES = {
                              I32, P]),
     "gx_sn_resample": (I32, [P, P, I32, I32, D, P, P, I64, P, D, P, P, P, P, P, P, P]),
     "gx_sn_check": (I32, [P, P, I32, I32, P, P, P]),
+    "gx_sn_check_noalloc": (I32, [P, P, I32, I32, P, P, P]),
     "gx_sn_replace": (I32, [P, I64, P, I64, P, P, P, P, P, P, P, I64, P, I64, P, P, P, P, P, P, P,
                             P, C.POINTER(I64)]),
     "gx_conv3d_fwd": (I32, [P, P, I32, I32, I32, P, P, I32, I32, I32, P, P]),

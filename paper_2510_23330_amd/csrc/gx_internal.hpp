@@ -117,6 +117,9 @@ int gx_fail(gx_ctx* ctx, int code, const char* fmt, ...);
 int gx_reserve(gx_ctx* ctx, Buf& b, size_t bytes);
 // Zero `bytes` (rounded up to 4) of device memory on the context stream.
 int gx_zero(gx_ctx* ctx, void* p, size_t bytes);
+// Takes, once per device (device current), the device address of the static
+// scratch of the no-allocation entry point (gx_sn.hip); called by gx_create.
+int gx_noalloc_setup(gx_ctx* ctx);
 
 #define GX_HIP(ctx, call)                                                               \
     do {                                                                                \

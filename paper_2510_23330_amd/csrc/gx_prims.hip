@@ -82,6 +82,14 @@ extern "C" int gx_create(gx_ctx** out, int device, void* hip_stream) {
         delete c;
         return GX_EHIP;
     }
+    if (gx_noalloc_setup(c) != GX_OK) {
+        (void)hipEventDestroy(c->ev0);
+        (void)hipEventDestroy(c->ev1);
+        (void)hipEventDestroy(c->ev2);
+        (void)hipEventDestroy(c->ev3);
+        delete c;
+        return GX_EHIP;
+    }
     *out = c;
     return GX_OK;
 }

@@ -5,6 +5,8 @@
 // predicted grid (as many as went in, so mass is conserved), and replace
 // particles by ID.
 #include "gx_internal.hpp"
+
+#include <mutex>
 #include <vector>
 
 #include <cmath>
@@ -702,6 +704,74 @@ extern "C" int gx_sn_check(gx_ctx* ctx, const float* pred, int k, int grid, cons
                                ctx->stream));
     GX_HIP(ctx, hipStreamSynchronize(ctx->stream));
     for (int c = 0; c < k; c++) ok[c] = h[c] ? 0 : 1;
+    return GX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Trust check without allocation (gx_sn_check_noalloc), for callers that
+// cannot allocate device memory.  Its scratch, one flag word per region, is
+// the static device array `scratch` below: every device the library runs on
+// holds its own copy until the process ends.  In host code `scratch` names a
+// host-side stand-in, not device memory, so its device address is taken once
+// per device by gx_noalloc_setup (called from gx_create with the device
+// current) and only that address is handed to kernels.
+// ---------------------------------------------------------------------------
+#define GX_NOALLOC_MAX_DEVICES 64
+static __device__ __align__(256) uint32_t scratch[GX_NOALLOC_MAX_REGIONS];
+static void* g_scratch_dev[GX_NOALLOC_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+int gx_noalloc_setup(gx_ctx* ctx) {
+    if (ctx->device < 0 || ctx->device >= GX_NOALLOC_MAX_DEVICES)
+        return gx_fail(ctx, GX_EINVAL, "device %d beyond the static scratch table", ctx->device);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_dev[ctx->device]) return GX_OK;
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return gx_fail(ctx, GX_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", ctx->device,
+                       hipGetErrorString(e));
+    }
+    g_scratch_dev[ctx->device] = p;
+    return GX_OK;
+}
+
+__global__ void k_flags_clear(uint32_t* __restrict__ bad, int k) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < k) bad[c] = 0u;
+}
+
+__global__ void k_flags_to_ok(const uint32_t* __restrict__ bad, int k, uint8_t* __restrict__ ok) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < k) ok[c] = bad[c] ? 0 : 1;
+}
+
+extern "C" int gx_sn_check_noalloc(gx_ctx* ctx, const float* pred, int k, int grid,
+                                   const double* lo, const double* hi, uint8_t* ok_dev) {
+    if (!ctx || k < 0 || grid < 1 || !lo || !hi || (k > 0 && (!pred || !ok_dev))) return GX_EINVAL;
+    if (k > GX_NOALLOC_MAX_REGIONS)
+        return gx_fail(ctx, GX_EINVAL,
+                       "sn_check_noalloc: %d regions exceed the static scratch of %d regions", k,
+                       GX_NOALLOC_MAX_REGIONS);
+    const int64_t per = (int64_t)grid * grid * grid * 5;
+    if (per > INT32_MAX) return gx_fail(ctx, GX_EINVAL, "sn_check_noalloc: grid %d too large", grid);
+    if (k == 0) return GX_OK;
+    uint32_t* bad = (uint32_t*)g_scratch_dev[ctx->device];
+    if (!bad) return gx_fail(ctx, GX_EINVAL, "sn_check_noalloc: no scratch address for device %d",
+                             ctx->device);
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    SnBounds bd;
+    for (int q = 0; q < 5; q++) {
+        bd.lo[q] = (float)lo[q];
+        bd.hi[q] = (float)hi[q];
+    }
+    hipLaunchKernelGGL(k_flags_clear, dim3(gx_blocks(k, 256)), dim3(256), 0, ctx->stream, bad, k);
+    const unsigned nbx = (unsigned)std::min<int64_t>(64, (per + 255) / 256);
+    hipLaunchKernelGGL(k_sn_check, dim3(nbx, k), dim3(256), 0, ctx->stream, pred, (int)per, bd, bad);
+    hipLaunchKernelGGL(k_flags_to_ok, dim3(gx_blocks(k, 256)), dim3(256), 0, ctx->stream,
+                       (const uint32_t*)bad, k, ok_dev);
+    GX_LAUNCH_CHECK(ctx);
     return GX_OK;
 }
 
