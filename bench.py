@@ -92,33 +92,6 @@ def parse():
     return ap.parse_args()
 
 
-def morton_order(d):
-    """Reorder the particle arrays of ``d`` in place into the Morton order of a
-    1024^3 grid over their bounding box, separately for the collisionless
-    block and the gas block (which stays last).  N-body codes keep their
-    particle arrays in a space-filling-curve order; the library gathers its
-    sorted copies from, and writes its outputs to, the caller's order, so
-    with this order those accesses touch neighbouring memory.  Particle ids
-    travel with the particles; the physics does not depend on the order."""
-    n, go = len(d["x"]), int(d["gas_offset"])
-    q = []
-    for c in ("x", "y", "z"):
-        a = d[c]
-        lo, hi = a.min(), a.max()
-        v = np.clip(((a - lo) * (1024.0 / max(hi - lo, 1e-300))).astype(np.int64), 0, 1023)
-        w = np.zeros(n, np.int64)
-        for b in range(10):  # spread the 10 bits three apart
-            w |= ((v >> b) & 1) << (3 * b)
-        q.append(w)
-    key = (q[0] << 2) | (q[1] << 1) | q[2]
-    idx = np.concatenate([np.argsort(key[:go], kind="stable"),
-                          go + np.argsort(key[go:], kind="stable")])
-    for k, v in list(d.items()):
-        if isinstance(v, np.ndarray) and len(v) == n:
-            d[k] = v[idx]
-    d["u_gas"] = d["u_gas"][idx[go:] - go]
-
-
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -196,7 +169,7 @@ def main():
     t0 = time.perf_counter()
     d = ics.disk_galaxy(args.n, args.seed)
     if args.ic_order == "morton":
-        morton_order(d)
+        ics.spatial_order(d)
     log(f"[bench] generated {args.n} particles ({args.ic_order} order) in "
         f"{time.perf_counter() - t0:.1f} s")
     eng = gx.Engine(0)

@@ -245,6 +245,33 @@ def disk_galaxy(n_total: int = 1_000_000, seed: int = 3, frac_star: float = 0.5,
     return out
 
 
+def spatial_order(d: dict) -> dict:
+    """Reorder the particle arrays of a ``disk_galaxy`` dict, in place, along
+    a space-filling curve: the Morton order of a 1024^3 grid over the
+    bounding box, separately for the collisionless block and the gas block
+    (which stays last).  N-body codes keep their arrays in such an order; it
+    is an input layout (ids travel with the particles) and takes no part in
+    any tree: the library sorts by its own keys whatever the input order."""
+    n, go = len(d["x"]), int(d["gas_offset"])
+    q = []
+    for c in ("x", "y", "z"):
+        a = d[c]
+        lo, hi = a.min(), a.max()
+        v = np.clip(((a - lo) * (1024.0 / max(hi - lo, 1e-300))).astype(np.int64), 0, 1023)
+        w = np.zeros(n, np.int64)
+        for b in range(10):  # spread the 10 bits three apart
+            w |= ((v >> b) & 1) << (3 * b)
+        q.append(w)
+    key = (q[0] << 2) | (q[1] << 1) | q[2]
+    idx = np.concatenate([np.argsort(key[:go], kind="stable"),
+                          go + np.argsort(key[go:], kind="stable")])
+    for k, v in list(d.items()):
+        if isinstance(v, np.ndarray) and len(v) == n:
+            d[k] = v[idx]
+    d["u_gas"] = d["u_gas"][idx[go:] - go]
+    return d
+
+
 def gas_view(p: dict) -> dict:
     """Gas-only slice (contiguous tail) of a ``disk_galaxy`` dict."""
     o = int(p["gas_offset"])

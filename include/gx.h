@@ -111,6 +111,12 @@ int gx_set_stream(gx_ctx* ctx, void* hip_stream);
 const char* gx_last_error(const gx_ctx* ctx);
 /* Library build string (architecture and compile options); static storage. */
 const char* gx_version(void);
+/* Test hook of the gravity list walk: entries > 0 limits its small LDS stack
+ * to min(entries, 2048) and has the one-pass list construction try it first,
+ * so that a stack overflow and the retry with the large stack happen on small
+ * workloads (lists and forces do not change, only the work done); 0 restores
+ * the normal choice.  Kept by the context until changed. */
+int gx_set_walk_stack_limit(gx_ctx* ctx, int entries);
 
 /*
  * gx_tree_build -- Barnes-Hut octree over Morton-sorted particles (Sec. 3.4)
@@ -160,10 +166,6 @@ int gx_tree_build(gx_ctx* ctx, const gx_particles* p, int which, int n_leaf, int
  * flags      GX_QUAD | GX_DIRECT | GX_PREC_FP64
  * ax..pot    device FP64 outputs [n], overwritten, original order
  * stats      optional host: n_pp, n_pc, n_groups, ms (synchronises)
- * The environment variable GX_WALK_SMALL_STACK = n > 0, read by each call,
- * limits the list walk's small stack to min(n, 2048) entries and has the
- * one-pass list construction try it first: a test hook for the retry with
- * the large stack (the lists and forces do not change, only the work done).
  */
 int gx_gravity_forces(gx_ctx* ctx, const gx_particles* p, double G, double theta, int flags,
                       double* ax, double* ay, double* az, double* pot, gx_stats* stats);
@@ -397,6 +399,8 @@ int gx_sn_check_noalloc(gx_ctx* ctx, const float* pred, int k, int grid, const d
  * for main index i >= u_offset) and H64 (same indexing; set to -1 so the next
  * kernel-size solve reseeds) may be NULL.  n_missing (host, may be NULL)
  * counts new ids absent from the main set.  Synchronises when n_missing.
+ * An ID listed more than once among the new particles takes the values of
+ * its last entry (deterministic).
  */
 int gx_sn_replace(gx_ctx* ctx, int64_t n, const int64_t* id, int64_t id_cap, double* x, double* y,
                   double* z, double* vx, double* vy, double* vz, double* u, int64_t u_offset,
@@ -497,6 +501,69 @@ int gx_f32_to_bf16(gx_ctx* ctx, const float* x, int64_t n, uint16_t* y);
  * NULL: no addition / no derivative); gradient routing at skip connections. */
 int gx_grad_combine(gx_ctx* ctx, int64_t n, const uint16_t* a, const uint16_t* b, const uint16_t* y,
                     uint16_t* out);
+
+/* ---- the whole network (Sec. 3.3) ----------------------------------------
+ * The U-Net as one call per pass, the layer sequence run inside the library
+ * over the blocks above.  Per level l < levels (channels base * 2^l): two 3^3
+ * convolutions (zero padding 1, bias, LeakyReLU 0.1); 2^3 average pooling
+ * down; nearest x2 upsampling followed by a 3^3 convolution up; the skip
+ * joined by channel concatenation (upsampled path first); a linear 1^3 head
+ * with cout outputs.  Layer order e0a e0b ... e{L-1}a e{L-1}b, then for
+ * l = L-2 .. 0: u{l}c d{l}a d{l}b, then head; the flat parameter array holds
+ * every layer's weights [Cout][kvol][Cin] in that order, then every bias.
+ */
+typedef struct {
+    int levels;              /* 2..6 */
+    int base;                /* channels of level 0, a multiple of 16 */
+    int cin;                 /* input channels (physical ones zero padded), multiple of 8 */
+    int cout;                /* head outputs, multiple of 16 */
+    const uint16_t* w_bf16;  /* device bf16 [n_params]: the weights are read from here */
+    const float* w_f32;      /* device fp32 [n_params]: the biases are read from here */
+} gx_unet;
+
+/* Parameter and layer counts of a network description (no device work). */
+int gx_unet_sizes(int levels, int base, int cin, int cout, int64_t* n_params, int64_t* n_layers);
+/* Layer `index` of that description: name (e.g. "d0a"), channels, kernel size
+ * and offsets of its weights and bias in the flat parameter array. */
+int gx_unet_layer(int levels, int base, int cin, int cout, int index, char* name, int name_cap,
+                  int* cin_out, int* cout_out, int* ksize, int64_t* w_off, int64_t* b_off);
+/*
+ * gx_unet_forward -- one forward pass of B samples of S^3 voxels.
+ * in        device bf16 [B][S^3][cin] (standardised channels)
+ * save      1: keep every activation in the context for gx_unet_backward (the
+ *           upsampled and concatenated inputs are materialised); 0: inference,
+ *           the up-path convolutions read them on the fly (same results)
+ * out_f32   device fp32 [B][S^3][cout] head output, or NULL
+ * out_phys  device fp32 [B][S^3][nc]: the first nc head outputs mapped by
+ *           out = y * scale[c] + shift[c] (scale, shift device fp32 [nc]),
+ *           or NULL.  At least one output.
+ * S must be divisible by 2^(levels - 1).  Activations are library scratch.
+ */
+int gx_unet_forward(gx_ctx* ctx, const gx_unet* net, const uint16_t* in, int B, int S, int save,
+                    float* out_f32, int nc, const float* scale, const float* shift,
+                    float* out_phys);
+/*
+ * gx_unet_backward -- parameter gradients of the last saving forward pass
+ * (same network, B and S; GX_ESTALE otherwise).
+ * in    the forward input; dout device bf16 [B][S^3][cout] = dL/d(head output)
+ * grad  device fp32 [n_params], ACCUMULATED (zero it first)
+ */
+int gx_unet_backward(gx_ctx* ctx, const gx_unet* net, const uint16_t* in, int B, int S,
+                     const uint16_t* dout, float* grad);
+/* Copy a tensor written by the last forward pass (gradient = 0: the
+ * activation `name`, e.g. "e1b", "p0", "u0c", "d0a", and with save = 1 also
+ * "up0", "c0") or by the backward pass after it (gradient = 1: the gradient
+ * of that activation's pre-activation, or "skip{l}") to device bf16 dst (cap
+ * elements), stream ordered; *count gets its element count (dst may be NULL
+ * to ask only for it).  Inspection for tests. */
+int gx_unet_saved(gx_ctx* ctx, const char* name, int gradient, uint16_t* dst, int64_t cap,
+                  int64_t* count);
+/* Standardisation of the network's channels from FP64 sums (gx_chan_stats
+ * over count rows): mean = s / count, std = max(sqrt(max(s2 / count -
+ * mean^2, 0)), min_std), scale = 1 / std, shift = -mean / std (device fp32
+ * [nc] each, any may be NULL). */
+int gx_chan_moments(gx_ctx* ctx, const double* sums, int nc, double count, double min_std,
+                    float* mean, float* std_out, float* scale, float* shift);
 
 #ifdef __cplusplus
 }

@@ -166,6 +166,10 @@ class Engine:
             raise GxError(rc, msg)
         return rc
 
+    def set_walk_stack_limit(self, entries: int):
+        """Test hook: limit the gravity walk's small stack (0 restores it)."""
+        self._check(self.lib.gx_set_walk_stack_limit(self.ctx, int(entries)))
+
     def set_stream(self, stream):
         self._stream = stream
         self._check(self.lib.gx_set_stream(self.ctx, C.c_void_p(stream.cuda_stream)))
@@ -478,10 +482,78 @@ class Engine:
             _ptr(shift, torch.float32), _ptr(out, torch.float32), int(out_stride or nc),
             _ptr(out_bf16, torch.bfloat16), int(bf_stride or nc)))
 
+    def chan_moments(self, sums, nc, count, min_std, mean=None, std=None, scale=None,
+                     shift=None):
+        """Mean, floored standard deviation and the standardising affine map
+        (scale = 1/std, shift = -mean/std) from FP64 channel sums."""
+        torch = _torch()
+        f = lambda t: _ptr(t, torch.float32)
+        self._check(self.lib.gx_chan_moments(self.ctx, _ptr(sums, torch.float64), int(nc),
+                                             float(count), float(min_std), f(mean), f(std),
+                                             f(scale), f(shift)))
+
+    # ---- whole network -------------------------------------------------------
+    def _unet_desc(self, levels, base, cin, cout, w_bf16, w_f32):
+        torch = _torch()
+        return _lib.GxUNet(int(levels), int(base), int(cin), int(cout),
+                           _ptr(w_bf16, torch.bfloat16), _ptr(w_f32, torch.float32))
+
+    def unet_forward(self, desc, x, B, S, save, out_f32=None, nc=0, scale=None, shift=None,
+                     out_phys=None):
+        torch = _torch()
+        self._check(self.lib.gx_unet_forward(
+            self.ctx, C.byref(desc), _ptr(x, torch.bfloat16), int(B), int(S), int(bool(save)),
+            _ptr(out_f32, torch.float32), int(nc), _ptr(scale, torch.float32),
+            _ptr(shift, torch.float32), _ptr(out_phys, torch.float32)))
+
+    def unet_backward(self, desc, x, B, S, dout, grad):
+        torch = _torch()
+        self._check(self.lib.gx_unet_backward(self.ctx, C.byref(desc), _ptr(x, torch.bfloat16),
+                                              int(B), int(S), _ptr(dout, torch.bfloat16),
+                                              _ptr(grad, torch.float32)))
+
+    def unet_saved(self, name: str, gradient: bool = False):
+        """Copy of a tensor kept by the last saving forward pass (bf16, flat)."""
+        torch = _torch()
+        cnt = C.c_int64(0)
+        self._check(self.lib.gx_unet_saved(self.ctx, name.encode(), int(gradient), None, 0,
+                                           C.byref(cnt)))
+        out = torch.empty(cnt.value, dtype=torch.bfloat16, device=f"cuda:{self.device}")
+        self._check(self.lib.gx_unet_saved(self.ctx, name.encode(), int(gradient),
+                                           _ptr(out, torch.bfloat16), cnt.value, C.byref(cnt)))
+        return out
+
     def f32_to_bf16(self, x, y):
         torch = _torch()
         self._check(self.lib.gx_f32_to_bf16(self.ctx, _ptr(x, torch.float32), int(x.numel()),
                                             _ptr(y, torch.bfloat16)))
+
+
+def unet_sizes(levels, base, cin, cout):
+    """(n_params, n_layers) of a network description."""
+    lib = _lib.load()
+    n, k = C.c_int64(0), C.c_int64(0)
+    rc = lib.gx_unet_sizes(int(levels), int(base), int(cin), int(cout), C.byref(n), C.byref(k))
+    if rc:
+        raise GxError(rc, "bad network description")
+    return n.value, k.value
+
+
+def unet_layers(levels, base, cin, cout):
+    """Per layer: (name, cin, cout, ksize, w_off, b_off), in the library's order."""
+    lib = _lib.load()
+    _, nl = unet_sizes(levels, base, cin, cout)
+    out = []
+    for i in range(nl):
+        name = C.create_string_buffer(16)
+        ci, co, ks = C.c_int(0), C.c_int(0), C.c_int(0)
+        wo, bo = C.c_int64(0), C.c_int64(0)
+        rc = lib.gx_unet_layer(int(levels), int(base), int(cin), int(cout), i, name, 16,
+                               C.byref(ci), C.byref(co), C.byref(ks), C.byref(wo), C.byref(bo))
+        if rc:
+            raise GxError(rc, "bad layer index")
+        out.append((name.value.decode(), ci.value, co.value, ks.value, wo.value, bo.value))
+    return out
 
 
 def version() -> str:

@@ -44,6 +44,11 @@ class GxGas(C.Structure):
                 ("vsig", P), ("n", I64)]
 
 
+class GxUNet(C.Structure):
+    _fields_ = [("levels", I32), ("base", I32), ("cin", I32), ("cout", I32), ("w_bf16", P),
+                ("w_f32", P)]
+
+
 # name -> (restype, argtypes), mirroring include/gx.h
 SIGNATURES = {
     "gx_create": (I32, [C.POINTER(P), I32, P]),
@@ -51,6 +56,7 @@ SIGNATURES = {
     "gx_set_stream": (I32, [P, P]),
     "gx_last_error": (C.c_char_p, [P]),
     "gx_version": (C.c_char_p, []),
+    "gx_set_walk_stack_limit": (I32, [P, I32]),
     "gx_tree_build": (I32, [P, C.POINTER(GxParticles), I32, I32, I32, P, C.POINTER(GxStats)]),
     "gx_gravity_forces": (I32, [P, C.POINTER(GxParticles), D, D, I32, P, P, P, P,
                                 C.POINTER(GxStats)]),
@@ -94,6 +100,13 @@ SIGNATURES = {
     "gx_cube_sym": (I32, [P, P, I32, I32, I32, I32, P, P]),
     "gx_chan_affine": (I32, [P, I64, P, I32, I32, P, P, P, I32, P, I32]),
     "gx_grad_combine": (I32, [P, I64, P, P, P, P]),
+    "gx_unet_sizes": (I32, [I32, I32, I32, I32, C.POINTER(I64), C.POINTER(I64)]),
+    "gx_unet_layer": (I32, [I32, I32, I32, I32, I32, C.c_char_p, I32, C.POINTER(I32),
+                            C.POINTER(I32), C.POINTER(I32), C.POINTER(I64), C.POINTER(I64)]),
+    "gx_unet_forward": (I32, [P, C.POINTER(GxUNet), P, I32, I32, I32, P, I32, P, P, P]),
+    "gx_unet_backward": (I32, [P, C.POINTER(GxUNet), P, I32, I32, P, P]),
+    "gx_unet_saved": (I32, [P, C.c_char_p, I32, P, I64, C.POINTER(I64)]),
+    "gx_chan_moments": (I32, [P, P, I32, D, D, P, P, P, P]),
 }
 
 _lib = None

@@ -29,6 +29,7 @@ SOURCES = {
     "gx_sph.hip": [],
     "gx_sn.hip": [],
     "gx_nn.hip": [],
+    "gx_unet.hip": [],
 }
 ARCH = os.environ.get("GX_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INC, "-I", CSRC,

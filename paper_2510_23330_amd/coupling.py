@@ -69,10 +69,28 @@ class SNCoupling:
                       "particles_replaced": 0, "missing_ids": 0}
 
     def sites(self, step_index: int):
+        """This step's SN sites: candidate stars in a seeded random order,
+        each kept unless its box would overlap the box of a site already kept
+        (so every gas particle belongs to at most one region), until K."""
         rng = np.random.default_rng(self.seed + step_index)
-        sel = rng.choice(self.cand, size=min(self.K, self.cand.size), replace=False)
+        order = rng.permutation(self.cand)
         torch, p = self.torch, self.step.p
-        s = torch.as_tensor(np.sort(sel), device=p.x.device)
+        side = self.side / PC_PER_KPC
+        kept = np.zeros((0, 3))
+        chosen = []
+        for a in range(0, order.size, 4096):
+            idx = torch.as_tensor(order[a:a + 4096], device=p.x.device)
+            pos = torch.stack([p.x[idx], p.y[idx], p.z[idx]], dim=1).cpu().numpy()
+            for j in range(pos.shape[0]):
+                if kept.shape[0] and np.any(np.all(np.abs(kept - pos[j]) < side, axis=1)):
+                    continue
+                kept = np.vstack([kept, pos[j]])
+                chosen.append(order[a + j])
+                if len(chosen) == self.K:
+                    break
+            if len(chosen) == self.K:
+                break
+        s = torch.as_tensor(np.sort(np.asarray(chosen, np.int64)), device=p.x.device)
         return torch.stack([p.x[s], p.y[s], p.z[s]], dim=1).contiguous()
 
     def _valid(self, pred, K):

@@ -357,8 +357,6 @@ extern "C" int gx_gravity_forces(gx_ctx* ctx, const gx_particles* p, double G, d
             // the small stack when the previous call's deepest stack fits with an
             // eighth to spare; a small-stack walk that overflows only its stack
             // is repeated once with the large one
-            const char* lim = std::getenv("GX_WALK_SMALL_STACK");
-            ctx->walk_small_cap = lim ? std::max(0, std::atoi(lim)) : 0;
             const int64_t s_small = gx_walk_stack_small(ctx);
             bool small = ctx->walk_small_cap > 0 ||
                          (prev_stack > 0 && prev_stack + prev_stack / 8 <= s_small);

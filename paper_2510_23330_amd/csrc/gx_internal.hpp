@@ -92,6 +92,8 @@ struct ListSet {  // per-group interaction lists (CSR)
     int64_t last_two_pass = 1, last_stack = 0;  // diagnostics of the last construction
 };
 
+struct gx_unet_state;  // saved U-Net activations and gradients (gx_unet.hip)
+
 struct gx_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -103,10 +105,10 @@ struct gx_ctx {
     Buf wrel;   // 3^3 weights re-laid out chunk-major for the slab convolution
     Buf sph_work[24];
     // > 0: the gravity walk's small stack holds only this many entries and is
-    // tried first (environment variable GX_WALK_SMALL_STACK, read by each
-    // gravity call), so that its overflow and the retry with the large stack
-    // can be exercised on small workloads
+    // tried first (set by gx_set_walk_stack_limit), so that its overflow and
+    // the retry with the large stack can be exercised on small workloads
     int walk_small_cap = 0;
+    gx_unet_state* unet = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
 };
 
@@ -120,6 +122,8 @@ int gx_zero(gx_ctx* ctx, void* p, size_t bytes);
 // Takes, once per device (device current), the device address of the static
 // scratch of the no-allocation entry point (gx_sn.hip); called by gx_create.
 int gx_noalloc_setup(gx_ctx* ctx);
+// Releases the U-Net activations held by a context (gx_unet.hip).
+void gx_unet_free(gx_ctx* ctx);
 
 #define GX_HIP(ctx, call)                                                               \
     do {                                                                                \

@@ -19,7 +19,8 @@
 // activation derivative of a stored layer output, and writes bf16 or fp32.
 // Backward data is the same kernel on weights with flipped taps and swapped
 // channel roles; backward weight reduces im2col^T x dOut over voxel chunks
-// (transposed through LDS) into FP32 with atomics.
+// (transposed through LDS) into per-chunk FP32 partial gradients, which a
+// second kernel adds in chunk order (deterministic).
 #include "gx_internal.hpp"
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));

@@ -111,6 +111,7 @@ extern "C" int gx_destroy(gx_ctx* ctx) {
             free_buf(*b);
     for (auto& b : ctx->scan_tmp) free_buf(b);
     for (auto& b : ctx->sph_work) free_buf(b);
+    gx_unet_free(ctx);
     free_buf(ctx->hist);
     free_buf(ctx->partial);
     free_buf(ctx->small);
@@ -126,6 +127,12 @@ extern "C" int gx_destroy(gx_ctx* ctx) {
 extern "C" int gx_set_stream(gx_ctx* ctx, void* hip_stream) {
     if (!ctx) return GX_EINVAL;
     ctx->stream = (hipStream_t)hip_stream;
+    return GX_OK;
+}
+
+extern "C" int gx_set_walk_stack_limit(gx_ctx* ctx, int entries) {
+    if (!ctx || entries < 0) return GX_EINVAL;
+    ctx->walk_small_cap = entries;
     return GX_OK;
 }
 

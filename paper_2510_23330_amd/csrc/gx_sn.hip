@@ -180,7 +180,7 @@ __global__ __launch_bounds__(256) void k_sn_inject(const double* __restrict__ x,
         uint32_t ntie;
         const uint32_t ex = block_excl_scan256<uint32_t>(is_tie, sh, &ntie);
         const bool chosen = j < e && (d < t || (is_tie && tie_seen + (int)ex < ties_needed));
-        if (chosen) u[idx[j]] += du;
+        if (chosen) atomicAdd(&u[idx[j]], du);  // boxes may share a chosen particle
         tie_seen += (int)ntie;
     }
 }
@@ -789,6 +789,19 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
+// A main index targeted by several new particles (an ID listed twice) takes
+// the last of them: each new particle claims its target with atomicMax of its
+// list position, and only the winner writes.
+__global__ void k_replace_claim(int64_t m, const int64_t* __restrict__ nid,
+                                const int32_t* __restrict__ map, int64_t id_cap,
+                                int32_t* __restrict__ win) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    const int64_t id = nid[k];
+    const int32_t i = (id >= 0 && id < id_cap) ? map[id] : -1;
+    if (i >= 0) atomicMax(&win[i], (int32_t)k);
+}
+
 __global__ void k_replace(int64_t m, const int64_t* __restrict__ nid, const double* __restrict__ nx,
                           const double* __restrict__ ny, const double* __restrict__ nz,
                           const double* __restrict__ nvx, const double* __restrict__ nvy,
@@ -796,7 +809,8 @@ __global__ void k_replace(int64_t m, const int64_t* __restrict__ nid, const doub
                           const int32_t* __restrict__ map, int64_t id_cap, double* __restrict__ x,
                           double* __restrict__ y, double* __restrict__ z, double* __restrict__ vx,
                           double* __restrict__ vy, double* __restrict__ vz, double* __restrict__ u,
-                          int64_t u_off, double* __restrict__ H64, unsigned long long* missing) {
+                          int64_t u_off, double* __restrict__ H64,
+                          const int32_t* __restrict__ win, unsigned long long* missing) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= m) return;
     const int64_t id = nid[k];
@@ -805,6 +819,7 @@ __global__ void k_replace(int64_t m, const int64_t* __restrict__ nid, const doub
         atomicAdd(missing, 1ull);
         return;
     }
+    if (win[i] != (int32_t)k) return;  // a later entry with the same ID wins
     x[i] = nx[k];
     y[i] = ny[k];
     z[i] = nz[k];
@@ -827,17 +842,25 @@ extern "C" int gx_sn_replace(gx_ctx* ctx, int64_t n, const int64_t* id, int64_t 
         return GX_EINVAL;
     GX_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
+    if (m > INT32_MAX || n > INT32_MAX)
+        return gx_fail(ctx, GX_EINVAL, "sn_replace: more than 2^31 - 1 particles");
     GX_TRY(gx_reserve(ctx, ctx->sph_work[12], id_cap * sizeof(int32_t)));
+    GX_TRY(gx_reserve(ctx, ctx->sph_work[22], std::max<int64_t>(n, 1) * sizeof(int32_t)));
     GX_TRY(gx_reserve(ctx, ctx->small, 64));
     int32_t* map = (int32_t*)ctx->sph_work[12].p;
+    int32_t* win = (int32_t*)ctx->sph_work[22].p;
     unsigned long long* miss = (unsigned long long*)ctx->small.p;
     GX_TRY(gx_zero(ctx, miss, 8));
     hipLaunchKernelGGL(k_fill_i32, dim3(gx_blocks(id_cap, 256)), dim3(256), 0, st, map, id_cap, -1);
     hipLaunchKernelGGL(k_id_map, dim3(gx_blocks(n, 256)), dim3(256), 0, st, n, id, id_cap, map);
-    if (m > 0)
+    if (m > 0) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(gx_blocks(n, 256)), dim3(256), 0, st, win, n, -1);
+        hipLaunchKernelGGL(k_replace_claim, dim3(gx_blocks(m, 256)), dim3(256), 0, st, m, new_id,
+                           (const int32_t*)map, id_cap, win);
         hipLaunchKernelGGL(k_replace, dim3(gx_blocks(m, 256)), dim3(256), 0, st, m, new_id, nx, ny, nz,
                            nvx, nvy, nvz, nu, map, id_cap, x, y, z, vx, vy, vz, u, u_offset, H64,
-                           miss);
+                           (const int32_t*)win, miss);
+    }
     GX_LAUNCH_CHECK(ctx);
     if (n_missing) {
         unsigned long long h = 0;

@@ -57,16 +57,15 @@ class SNBatch:
         self.steps = 0
         self.noconv = 0          # kernel-size solves that hit the iteration cap
         self.u_floor = cfg.t_floor * U_PER_K
+        # ambient state of each cube before the explosion (mean density, mass-
+        # weighted temperature and bulk velocity of its gas): the value of
+        # voxels no particle kernel reaches, at every later voxelization too
+        off, idx, _ = eng.sn_extract(self.p, self.centers, SIDE / 2, self.n)
+        self._amb = eng.sn_ambient(self.p, self.g.u, off, idx, SIDE, 1.0 / U_PER_K)
 
     def ambient(self):
-        """Per-cube ambient (log10 rho, log10 T, 0, 0, 0) for empty voxels."""
-        K = self.K
-        counts = np.diff(self.off)
-        rho = counts * self.b["m"][self.off[:-1]] / SIDE ** 3
-        amb = np.zeros((K, 5), np.float32)
-        amb[:, 0] = np.log10(rho)
-        amb[:, 1] = np.log10(self.b["T_amb"])
-        return self.torch.as_tensor(amb, device=self.p.x.device)
+        """Per-cube ambient (log10 rho, log10 T, vx, vy, vz), device float [K * 5]."""
+        return self._amb
 
     def inject(self, k_inj: int = 32, energy: float = E_SN):
         """1e51 erg of thermal energy into the k_inj particles nearest each centre."""
@@ -188,31 +187,30 @@ class Surrogate:
         self.net = UNet(eng, S=grid, batch=batch, base=base, levels=levels, seed=seed, device=device,
                         train=train)
         f = dict(dtype=torch.float32, device=device)
+        # channel mean and standard deviation of the training inputs and
+        # targets, and the standardising maps x -> x * scale + shift
         self.mean_in, self.std_in = torch.zeros(5, **f), torch.ones(5, **f)
         self.mean_out, self.std_out = torch.zeros(5, **f), torch.ones(5, **f)
+        self.scale_in, self.shift_in = torch.ones(5, **f), torch.zeros(5, **f)
+        self.scale_out, self.shift_out = torch.ones(5, **f), torch.zeros(5, **f)
         self.V = grid ** 3
 
-    # ---- statistics -----------------------------------------------------------
-    @staticmethod
-    def _moments(sums, count):
-        s = sums.double().cpu().numpy()
-        nc = s.size // 2
-        mean = s[:nc] / count
-        var = np.maximum(s[nc:] / count - mean ** 2, 0.0)
-        return mean, np.sqrt(var)
+    STATS = ("mean_in", "std_in", "scale_in", "shift_in", "mean_out", "std_out", "scale_out",
+             "shift_out")
 
+    # ---- statistics -----------------------------------------------------------
     def set_stats(self, sums_in, sums_out, count, min_std: float = 1e-3):
-        torch = self.torch
-        mi, si = self._moments(sums_in, count)
-        mo, so = self._moments(sums_out, count)
-        for dst, v in ((self.mean_in, mi), (self.std_in, np.maximum(si, min_std)),
-                       (self.mean_out, mo), (self.std_out, np.maximum(so, min_std))):
-            dst.copy_(torch.as_tensor(v, dtype=torch.float32))
+        """Channel moments from FP64 sums (gx_chan_stats over count rows)."""
+        self.eng.chan_moments(sums_in, 5, count, min_std, self.mean_in, self.std_in,
+                              self.scale_in, self.shift_in)
+        self.eng.chan_moments(sums_out, 5, count, min_std, self.mean_out, self.std_out,
+                              self.scale_out, self.shift_out)
 
     def standardize(self, x_f32, which="in", out_f32=None, out_bf16=None):
         """(x - mean) / std per channel of physical [.., 5] rows."""
-        mean, std = (self.mean_in, self.std_in) if which == "in" else (self.mean_out, self.std_out)
-        self.eng.chan_affine(x_f32, 5, 5, 1.0 / std, -mean / std, out=out_f32, out_stride=5,
+        scale, shift = (self.scale_in, self.shift_in) if which == "in" else \
+            (self.scale_out, self.shift_out)
+        self.eng.chan_affine(x_f32, 5, 5, scale, shift, out=out_f32, out_stride=5,
                              out_bf16=out_bf16, bf_stride=8)
 
     # ---- inference ------------------------------------------------------------
@@ -262,8 +260,7 @@ class Surrogate:
         d = self.net.state_dict()
         extra = {"m": d["m"], "v": d["v"]} if moments else {}
         np.savez(path, w32=d["w32"], t=d["t"], **extra,
-                 mean_in=self.mean_in.cpu().numpy(), std_in=self.std_in.cpu().numpy(),
-                 mean_out=self.mean_out.cpu().numpy(), std_out=self.std_out.cpu().numpy())
+                 **{k: getattr(self, k).cpu().numpy() for k in self.STATS})
 
     def load(self, path):
         d = np.load(path)
@@ -271,5 +268,5 @@ class Surrogate:
         self.net.load_state_dict({"w32": d["w32"], "m": d["m"] if "m" in d else z,
                                   "v": d["v"] if "v" in d else z,
                                   "t": int(d["t"]) if "m" in d else 0})
-        for k in ("mean_in", "std_in", "mean_out", "std_out"):
+        for k in self.STATS:
             getattr(self, k).copy_(self.torch.as_tensor(d[k]))

@@ -49,3 +49,24 @@ def test_version_and_invalid_args_without_gpu():
     # null out-pointer is rejected before any device call
     assert lib.gx_create(None, 0, None) == _lib.GX_EINVAL
     assert lib.gx_destroy(None) == _lib.GX_EINVAL
+
+
+def test_unet_layer_table_matches_oracle():
+    # the library's layer order and flat parameter offsets (host-only calls)
+    # are the oracle network's
+    from paper_2510_23330_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libgx.so not built")
+    import paper_2510_23330_amd as gx
+    from oracle import unet as ounet
+    for base, levels in ((32, 4), (16, 3), (16, 2)):
+        tab, n, _ = ounet.layer_table(base, levels)
+        assert gx.unet_sizes(levels, base, 8, 16) == (n, len(tab))
+        got = gx.unet_layers(levels, base, 8, 16)
+        assert [g[0] for g in got] == list(tab)
+        for name, ci, co, k, wo, bo in got:
+            d = tab[name]
+            assert (ci, co, k, wo, bo) == (d["cin"], d["cout"], d["k"], d["w"][0], d["b"][0])
+    lib = _lib.load()
+    n = ctypes.c_int64(0)
+    assert lib.gx_unet_sizes(1, 32, 8, 16, ctypes.byref(n), None) == _lib.GX_EINVAL

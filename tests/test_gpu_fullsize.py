@@ -4,11 +4,13 @@ theta 0.5 with quadrupoles; gas tree n_leaf 8, groups <= 64, 64 neighbours).
 
 The oracle cannot evaluate 16M particles whole, so outputs are compared on a
 seeded sample it computes one by one: tree gravity for 48 receiving groups
-(against the FP64 oracle tree, the same lists by construction) and kernel
-size + density for 256 gas particles (against the FP64 Newton solve).  The
-hydro force, whose oracle needs every neighbour's kernel size, is checked at
-this size through what holds at any size: pairwise antisymmetry gives zero
-total momentum change and zero total energy change.
+(against the FP64 oracle tree, the same lists by construction), kernel size
++ density for 256 gas particles (against the FP64 Newton solve), and the
+hydro force for 256 gas receivers (the oracle fed the GPU's own kernel sizes
+and densities, so only the force arithmetic differs), plus what holds at any
+size: pairwise antisymmetry gives zero total momentum and energy change.
+Both the generator's particle order and the space-filling-curve order the
+benchmark times are run.
 """
 import numpy as np
 import pytest
@@ -21,9 +23,12 @@ N = 16_000_000
 GAMMA = 5.0 / 3.0
 
 
-@pytest.fixture(scope="module")
-def disk():
-    return ics.disk_galaxy(N, 4)
+@pytest.fixture(scope="module", params=["generated", "spatial"])
+def disk(request):
+    d = ics.disk_galaxy(N, 4)
+    if request.param == "spatial":
+        ics.spatial_order(d)
+    return d
 
 
 def test_fullsize_tree_gravity_sampled(gx, disk):
@@ -88,5 +93,18 @@ def test_fullsize_sph_density_sampled_and_force_invariants(gx, disk):
         work = m * (v[0] * a[0] + v[1] * a[1] + v[2] * a[2])
         scale = np.sum(np.abs(work)) + np.sum(np.abs(m * du))
         assert abs(np.sum(work) + np.sum(m * du)) <= 1e-5 * scale
+        # sampled receivers against the oracle's force on the GPU's H and rho
+        Hf = g.H.cpu().numpy().astype(np.float64)
+        rf = g.rho.cpu().numpy().astype(np.float64)
+        idx2 = ics.sample_indices(n, 256, 29)
+        ox, oy, oz, odu, ovs = oracle.sph_force(gas, Hf, rf, GAMMA, 1.0, idx=idx2)
+        rms = np.sqrt(np.mean(ox ** 2 + oy ** 2 + oz ** 2))
+        err = np.sqrt((a[0][idx2] - ox) ** 2 + (a[1][idx2] - oy) ** 2 + (a[2][idx2] - oz) ** 2)
+        an = np.sqrt(ox ** 2 + oy ** 2 + oz ** 2)
+        print(f"1.6M gas force, 256 receivers: max |da|/rms {err.max() / rms:.2e}, "
+              f"median |da|/|a| {np.median(err / an):.2e}")
+        assert np.max(err) <= 1e-4 * rms
+        assert np.max(np.abs(du[idx2] - odu)) <= 1e-4 * np.sqrt(np.mean(odu ** 2))
+        assert np.allclose(g.vsig.cpu().numpy()[idx2], ovs, rtol=1e-5)
     finally:
         eng.close()

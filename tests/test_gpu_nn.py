@@ -254,9 +254,8 @@ def test_unet_loss_decreases(gx, eng):
     # Training by the project's own kernels on a fixed pair of samples.  An
     # independent FP32 PyTorch CPU run of the same network, initialisation,
     # data and optimiser (Adam, lr 1e-3) reaches 0.20x the initial loss after
-    # 150 steps; the BF16 path must reach 0.3x.  (The weight-gradient sums
-    # use atomics, so runs differ in rounding; at lr 3e-3 some runs leave the
-    # stable regime.)
+    # 150 steps; the BF16 path must reach 0.3x.  (At lr 3e-3 the BF16 run
+    # leaves the stable regime.)
     import torch
     from paper_2510_23330_amd.unet import UNet
     S, B = 16, 2
