@@ -10,8 +10,9 @@ kernel size + density, hydro force, second half kick, FP64 energy audit.
 
 Each step also hands 64 supernova regions (60 pc boxes around seeded disk
 stars) to the surrogate -- extract, voxelize, U-Net inference, resample --
-and replaces returned regions by particle ID 50 steps later (the network is
-randomly initialised here: only its cost is measured).
+and replaces returned regions by particle ID 50 steps later (with the trained
+weights when their file exists, else a random initialisation whose
+predictions all fail the trust check and fall back).
 
 Prints ONE JSON line.  ``value`` = gravity interactions (particle-particle +
 particle-cell) per second of whole-step wall time.  ``roofline`` reports the
@@ -19,8 +20,11 @@ dominant kernel (pairwise gravity) against the FP32 vector peak, timed live
 with HIP events on the library's stream.  ``sn_region`` compares, for 64 SN
 cubes of 1 Msun particles, the plain small-timestep SPH to 0.1 Myr with the
 surrogate path on the same cubes, and the network's inference throughput at
-batch 256.  ``cpu_baseline`` times the FP64 oracle's tree gravity on a
-seeded sample of the same workload's groups.
+batch 256.  ``galaxy_0p1Myr`` compares 0.1 Myr of the disk with the
+surrogate (50 global steps) against a shared step held to the SN regions'
+Courant step.  ``force_error`` gives the relative force error against the
+FP64 oracle's direct sum (16M, 1M, Plummer).  ``cpu_baseline`` times the FP64
+oracle's tree gravity on a seeded sample of the same workload's groups.
 """
 from __future__ import annotations
 
@@ -47,13 +51,13 @@ FLOP_FORCE = 101                     # per SPH force candidate pair (Table 4)
 # HBM traffic of one k_grav_force<float,true> launch on this workload, from two
 # rocprofv3 --pmc runs of this script (FETCH_SIZE, WRITE_SIZE in KiB per
 # dispatch) scaled by what the same counters read for a reference copy of
-# known size (hbm_calib.py: FETCH_SIZE reads half the bytes copied, WRITE_SIZE
+# known size (hbm_calib.py beside this script: FETCH_SIZE reads half the bytes copied, WRITE_SIZE
 # all of them).  Valid only for the kernel source with this SHA-256 and the
 # particle order named (the outputs are scattered to the caller's order); any
 # change to gx_gravity.hip, or the other order, makes the bench report null.
-GRAV_TRAFFIC = {"source_sha256": "a3d3eb3e96b0f3b25b0277057df50d3442b69ec67b795f182ff062edd99fd8f4",
+GRAV_TRAFFIC = {"source_sha256": "1349b22688d7ca533d65c1ce4b223cb86c2e54ab19a9ade1d4b11260bc5f02d7",
                 "particle_order": "morton",
-                "fetch_kib": 3676699.3125, "write_kib": 2289833.4375,
+                "fetch_kib": 3679386.875, "write_kib": 2310470.25,
                 "fetch_scale": 2.0, "write_scale": 1.0}
 
 
@@ -86,6 +90,10 @@ def parse():
     ap.add_argument("--sn-cubes", type=int, default=64,
                     help="SN cubes of the plain-SPH vs surrogate region comparison (0 skips)")
     ap.add_argument("--sn-infer-batch", type=int, default=256)
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2510_23330_amd", "weights",
+                                                      "sn_unet_5ch.npz"),
+                    help="trained surrogate weights (random initialisation when absent)")
+    ap.add_argument("--no-force-error", action="store_true")
     ap.add_argument("--ic-order", choices=("morton", "generated"), default="morton",
                     help="particle array order: Morton order of a 1024^3 grid per block "
                          "(default) or the generator's order")
@@ -94,6 +102,72 @@ def parse():
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _err_stats(a, ref):
+    """Relative force error |a - ref| / |ref| per receiver: n, median, p99, max,
+    and the fraction of force nulls (|ref| below 1e-3 of the median |ref|)."""
+    an = np.sqrt(ref[0] ** 2 + ref[1] ** 2 + ref[2] ** 2)
+    e = np.sqrt((a[0] - ref[0]) ** 2 + (a[1] - ref[1]) ** 2 + (a[2] - ref[2]) ** 2) / an
+    return {"n": int(e.size), "median": float(np.median(e)), "p99": float(np.percentile(e, 99)),
+            "max": float(e.max()), "null_frac": float(np.mean(an < 1e-3 * np.median(an)))}
+
+
+def force_errors(eng, sim, n_recv=256, seed=31):
+    """Relative force error against the FP64 oracle's direct sum (Eq. 1 over
+    every source): the benchmark's 16M particles in their state after the
+    timed steps (tree gravity, the timed configuration), the 1M disk (tree),
+    and the 8,192-particle Plummer sphere (direct sum in FP32)."""
+    import torch
+    import ics
+    import oracle
+    import paper_2510_23330_amd as gx
+    G = ics.G_KPC
+    out = {}
+    p = sim.p
+    n = p.n
+    acc = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(4)]
+    eng.tree_build(p, gx.GX_TREE_ALL, 16, 256)
+    eng.gravity_forces(p, G, 0.5, gx.GX_QUAD, *acc)
+    host = {k: getattr(p, k).cpu().numpy() for k in ("x", "y", "z", "m")}
+    host["eps2"] = p.eps2.cpu().numpy()
+    idx = ics.sample_indices(n, n_recv, seed)
+    ref = oracle.direct_gravity(host, G, idx)
+    out["disk16M_tree_vs_fp64_direct"] = dict(
+        _err_stats([a.cpu().numpy()[idx] for a in acc[:3]], ref[:3]),
+        receivers=f"{len(idx)} seeded of {n}")
+    del acc, host
+    d1 = ics.disk_galaxy(1_000_000, 3)
+    p1 = gx.ParticleSet.from_numpy(d1)
+    acc = [torch.zeros(p1.n, dtype=torch.float64, device="cuda") for _ in range(4)]
+    eng.tree_build(p1, gx.GX_TREE_ALL, 16, 256)
+    eng.gravity_forces(p1, G, 0.5, gx.GX_QUAD, *acc)
+    idx = ics.sample_indices(p1.n, 1000, 17)
+    ref = oracle.direct_gravity(d1, G, idx)
+    out["disk1M_tree_vs_fp64_direct"] = dict(
+        _err_stats([a.cpu().numpy()[idx] for a in acc[:3]], ref[:3]),
+        receivers=f"{len(idx)} seeded of {p1.n}")
+    d0 = ics.plummer(8192, 1)
+    p0 = gx.ParticleSet.from_numpy(d0)
+    acc = [torch.zeros(p0.n, dtype=torch.float64, device="cuda") for _ in range(4)]
+    eng.tree_build(p0, gx.GX_TREE_ALL, 16, 256)
+    eng.gravity_forces(p0, 1.0, 0.5, gx.GX_DIRECT, *acc)
+    ref = oracle.direct_gravity(d0, 1.0)
+    out["plummer8k_direct_fp32_vs_fp64"] = dict(
+        _err_stats([a.cpu().numpy() for a in acc[:3]], ref[:3]), receivers="all 8192")
+    out["targets_p99"] = {"tree": 1e-3, "direct": 1e-5}
+    return out
 
 
 def cpu_baseline(d, n_groups_sample, seed):
@@ -109,50 +183,92 @@ def cpu_baseline(d, n_groups_sample, seed):
     inter = r[4] + r[5]
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": inter / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": (f"FP64 oracle tree gravity (theta 0.5, quadrupole) for {len(gsel)} of "
                        f"{T.n_groups} groups of the 16M disk ({inter:.3e} interactions in "
                        f"{dt:.2f} s; oracle tree build {build_s:.1f} s not included)")}
 
 
-def sn_region_leg(eng, n_cubes, infer_batch, seed0=5000):
-    """Per SN region: plain small-dt SPH to 0.1 Myr vs the surrogate path
-    (extract, ambient, gas tree, voxelize, infer, resample) on the same cubes,
-    plus network inference throughput at the stated batch."""
+def load_surrogate(eng, batch, weights):
+    """The network for inference: the trained weights when the file exists,
+    else a random initialisation (then only its cost is meaningful)."""
+    from paper_2510_23330_amd.sn import Surrogate
+    sur = Surrogate(eng, batch=batch, seed=0, train=False)
+    if weights and os.path.exists(weights):
+        sur.load(weights)
+        return sur, os.path.relpath(weights, ROOT)
+    return sur, None
+
+
+def _abs_err_stats(pred, ref):
+    d = np.abs(pred - ref)
+    return {"median": float(np.median(d)), "p90": float(np.percentile(d, 90))}
+
+
+def sn_region_leg(eng, n_cubes, infer_batch, weights, seed0=5000):
+    """Per SN region: plain small-dt SPH to 0.1 Myr against the surrogate path
+    (extract, ambient, gas tree, voxelize, infer, resample) on the same cubes.
+    Plain SPH runs twice: with one shared Courant step for all cubes (what a
+    galaxy with a shared global step must take) and with each cube on its own
+    Courant step (the fair cost per region).  With trained weights the
+    surrogate's per-voxel error against the per-cube plain SPH is reported,
+    beside persistence (no change).  Plus inference throughput at the stated
+    batch."""
     import torch
     import ics
-    from paper_2510_23330_amd.sn import GRID, SNBatch, Surrogate, generate
+    from paper_2510_23330_amd.sn import GRID, SNBatch, generate
     from paper_2510_23330_amd.unet import flops_forward
     seeds = list(range(seed0, seed0 + n_cubes))
-    x, y, info = generate(eng, seeds)
-    plain_s = info["seconds"]
-    sur = Surrogate(eng, batch=64, seed=0, train=False)
+    _, _, info_sh = generate(eng, seeds)
+    x0, y, info = generate(eng, seeds, per_cube=True)
+    cube_steps = np.asarray(info["cube_steps"])
+    sur, wfile = load_surrogate(eng, 64, weights)
     sb = SNBatch(eng, ics.sn_batch(seeds))
     sb.voxelize()
     sur.regions(sb.p, sb.g, sb.centers, cap=sb.n)         # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sur.regions(sb.p, sb.g, sb.centers, cap=sb.n)
+    off, idx, new, pred = sur.regions(sb.p, sb.g, sb.centers, cap=sb.n)
     torch.cuda.synchronize()
     sur_s = time.perf_counter() - t0
+    res = {"regions": n_cubes, "particles": info["n_particles"],
+           "plain_sph_shared_step": {"steps": info_sh["steps"], "s": info_sh["seconds"],
+                                     "ms_per_region": info_sh["seconds"] / n_cubes * 1e3},
+           "plain_sph_per_cube_step": {"steps_min": int(cube_steps.min()),
+                                       "steps_median": float(np.median(cube_steps)),
+                                       "steps_max": int(cube_steps.max()),
+                                       "s": info["seconds"],
+                                       "ms_per_region": info["seconds"] / n_cubes * 1e3},
+           "surrogate_s": sur_s, "surrogate_ms_per_region": sur_s / n_cubes * 1e3,
+           "speedup_vs_per_cube": info["seconds"] / sur_s,
+           "speedup_vs_shared_step": info_sh["seconds"] / sur_s,
+           "weights": wfile or "random init (timing only)"}
+    if wfile:
+        V = GRID ** 3
+        P = pred.view(n_cubes, V, 5).cpu().numpy().astype(np.float64)
+        Y = y.view(n_cubes, V, 5).cpu().numpy().astype(np.float64)
+        X = x0.view(n_cubes, V, 5).cpu().numpy().astype(np.float64)
+        res["error_vs_plain_sph"] = {
+            "surrogate": {"dlog_rho": _abs_err_stats(P[..., 0], Y[..., 0]),
+                          "dlog_T": _abs_err_stats(P[..., 1], Y[..., 1])},
+            "persistence": {"dlog_rho": _abs_err_stats(X[..., 0], Y[..., 0]),
+                            "dlog_T": _abs_err_stats(X[..., 1], Y[..., 1])},
+            "unit": "dex per voxel (64^3 voxels x regions)"}
     # inference throughput at infer_batch regions (chunks of the network's batch)
     V = GRID ** 3
     xin = torch.zeros(infer_batch * V * 8, dtype=torch.bfloat16, device="cuda")
-    pred = torch.empty(infer_batch * V * 5, dtype=torch.float32, device="cuda")
+    pr = torch.empty(infer_batch * V * 5, dtype=torch.float32, device="cuda")
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    sur.infer(xin[:32 * V * 8], 32, pred)
+    sur.infer(xin[:32 * V * 8], 32, pr)
     ev0.record()
-    sur.infer(xin, infer_batch, pred)
+    sur.infer(xin, infer_batch, pr)
     ev1.record()
     torch.cuda.synchronize()
     inf_s = ev0.elapsed_time(ev1) / 1e3
     fl = flops_forward(GRID) * infer_batch
-    return {"regions": n_cubes, "particles": info["n_particles"], "plain_sph_steps": info["steps"],
-            "plain_sph_s": plain_s, "surrogate_s": sur_s, "speedup": plain_s / sur_s,
-            "plain_sph_ms_per_region": plain_s / n_cubes * 1e3,
-            "surrogate_ms_per_region": sur_s / n_cubes * 1e3,
-            "infer_batch": infer_batch, "infer_s": inf_s,
-            "infer_tflops": fl / inf_s / 1e12, "infer_frac_bf16_peak": fl / inf_s / 2.5e15,
-            "weights": "random init (timing only; accuracy comes from the trained network)"}
+    res.update({"infer_batch": infer_batch, "infer_s": inf_s, "infer_tflops": fl / inf_s / 1e12,
+                "infer_frac_bf16_peak": fl / inf_s / 2.5e15})
+    return res
 
 
 def main():
@@ -182,10 +298,9 @@ def main():
     coupling = None
     if args.sn_sites > 0:
         from paper_2510_23330_amd.coupling import SNCoupling
-        from paper_2510_23330_amd.sn import Surrogate
         sur_eng = gx.Engine(0)
-        coupling = SNCoupling(sim, Surrogate(sur_eng, batch=64, seed=0, train=False),
-                              n_sites=args.sn_sites, delay=50)
+        sur, wfile = load_surrogate(sur_eng, 64, args.weights)
+        coupling = SNCoupling(sim, sur, n_sites=args.sn_sites, delay=50)
     torch.cuda.synchronize()
     log("[bench] set-up done; initial forces (cold kernel sizes) ...")
     t0 = time.perf_counter()
@@ -216,7 +331,7 @@ def main():
     grav_ms, grav_kernel_ms, dens_ms, hydro_ms, tree_ms = [], [], [], [], []
     n_pp = n_pc = n_sph = 0
     dens_k_ms, hydro_k_ms, dens_it = [], [], []
-    n_dens_eval = n_force_list = n_force_ngb = 0
+    n_dens_eval = n_dens_ngb = n_force_list = n_force_ngb = 0
     energies = []
     walk_diag = []
     torch.cuda.synchronize()
@@ -240,6 +355,7 @@ def main():
         hydro_k_ms.append(st["hydro"]["ms_kernel"])
         dens_it.append(st["density"]["n_iter_max"])
         n_dens_eval += st["density"]["n_sph_list"]
+        n_dens_ngb += st["density"]["n_sph_ngb"]
         n_force_list += st["hydro"]["n_sph_list"]
         n_force_ngb += st["hydro"]["n_sph_ngb"]
         log(f"[bench] step {k}: {per[-1] * 1e3:.1f} ms")
@@ -280,19 +396,28 @@ def main():
                      "gravity_kernel": float(np.mean(grav_kernel_ms)),
                      "sph_density": float(np.mean(dens_ms)), "sph_force": float(np.mean(hydro_ms)),
                      "sn_surrogate": float(np.mean(sn_ms)) if sn_ms else None},
-        "sn_coupling": None if coupling is None else dict(coupling.stats, sites_per_step=args.sn_sites,
-                                                          delay_steps=50),
+        "sn_coupling": None if coupling is None else dict(
+            coupling.stats, sites_per_step=args.sn_sites, delay_steps=50,
+            weights=wfile or "random init (timing only; every region falls back)"),
         "gravity_kernel_interactions_per_s": inter_step / kernel_s,
         "sph": {"density_pair_evals_per_step": n_dens_eval / args.steps,
+                "density_ngb_evals_per_step": n_dens_ngb / args.steps,
                 "density_kernel_ms": float(np.mean(dens_k_ms)),
                 "density_tflops_73": FLOP_DENS * n_dens_eval / args.steps
+                / (float(np.mean(dens_k_ms)) / 1e3) / 1e12,
+                "density_tflops_73_ngb": FLOP_DENS * n_dens_ngb / args.steps
                 / (float(np.mean(dens_k_ms)) / 1e3) / 1e12,
                 "density_max_iterations": int(max(dens_it)),
                 "force_list_pairs_per_step": n_force_list / args.steps,
                 "force_ngb_pairs_per_step": n_force_ngb / args.steps,
                 "force_kernel_ms": float(np.mean(hydro_k_ms)),
                 "force_tflops_101": FLOP_FORCE * n_force_list / args.steps
-                / (float(np.mean(hydro_k_ms)) / 1e3) / 1e12},
+                / (float(np.mean(hydro_k_ms)) / 1e3) / 1e12,
+                "force_tflops_101_ngb": FLOP_FORCE * n_force_ngb / args.steps
+                / (float(np.mean(hydro_k_ms)) / 1e3) / 1e12,
+                "convention": "list: every candidate pair evaluated (Table 4 convention); ngb: "
+                              "only pairs inside the kernel supports (density: summed over the "
+                              "kernel-size passes)"},
         "gravity_lists": {"two_pass_steps": int(sum(w[0] for w in walk_diag)),
                           "max_walk_stack": int(max(w[1] for w in walk_diag))},
         "energy_drift_rel": abs(E1 - E0) / abs(E0),
@@ -301,10 +426,28 @@ def main():
                      "kernel": "k_grav_force<float,true>",
                      "flop_convention": f"{FLOP_PP}/pp + {FLOP_PC}/pc"},
     }
+    if not args.no_force_error:
+        t0 = time.perf_counter()
+        out["force_error"] = force_errors(eng, sim)
+        log(f"[bench] force errors {time.perf_counter() - t0:.1f} s")
     if args.sn_cubes > 0:
         t0 = time.perf_counter()
-        out["sn_region"] = sn_region_leg(eng, args.sn_cubes, args.sn_infer_batch)
+        out["sn_region"] = sn_region_leg(eng, args.sn_cubes, args.sn_infer_batch, args.weights)
         log(f"[bench] SN region leg {time.perf_counter() - t0:.1f} s")
+        if sn_ms:
+            # 0.1 Myr of the disk with 64 SNe per step: 50 global steps of
+            # 2,000 yr with the surrogate hand-over in each, against a shared
+            # step that the SN regions hold to their Courant step (the shared-
+            # step SPH of the 1 Msun cubes gives it) at the step cost without
+            # the surrogate
+            n_sh = out["sn_region"]["plain_sph_shared_step"]["steps"]
+            plain_step_s = (ms_step - float(np.mean(sn_ms))) / 1e3
+            out["galaxy_0p1Myr"] = {
+                "surrogate_s": 50 * ms_step / 1e3,
+                "plain_shared_step_s": n_sh * plain_step_s,
+                "speedup": n_sh * plain_step_s / (50 * ms_step / 1e3),
+                "global_steps": {"surrogate": 50, "plain": n_sh},
+                "dt_cfl_sn_yr": 0.1e6 / n_sh, "dt_global_yr": 2000.0}
     if not args.no_cpu and args.cpu_groups > 0:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(d, args.cpu_groups, 99)

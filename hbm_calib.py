@@ -3,7 +3,7 @@ the device a few times, so that the FETCH_SIZE / WRITE_SIZE counters of a
 profiler run can be scaled by what they read for exactly `bytes` read and
 `bytes` written per dispatch.
 
-    python -m paper_2510_23330_amd.hbm_calib --bytes 1073741824 --reps 3
+    python hbm_calib.py --bytes 1073741824 --reps 3
 """
 from __future__ import annotations
 

@@ -66,7 +66,9 @@ typedef struct {
     int64_t n_pc;        /* particle-cell interactions */
     int64_t n_sph_list;  /* SPH candidate pairs evaluated: list length x receivers, and
                             for the density summed over all kernel-size passes */
-    int64_t n_sph_ngb;   /* SPH pairs inside the kernel support */
+    int64_t n_sph_ngb;   /* SPH pairs inside the kernel support: force, pairs with
+                            r < max(H_i, H_j); density, evaluations with r < H_i
+                            summed over all kernel-size passes */
     int64_t n_groups;    /* receiving groups */
     int64_t n_nodes;     /* tree nodes */
     int64_t n_iter_max;  /* largest kernel-size iteration count (SPH density);
@@ -217,6 +219,20 @@ int gx_kick_drift(gx_ctx* ctx, int64_t n, double dt_kick, double dt_drift, doubl
                   double* z, double* vx, double* vy, double* vz, const double* ax,
                   const double* ay, const double* az, int64_t n_u, double* u, const double* dudt,
                   double u_floor, double* vpred_xyz, double* upred);
+
+/*
+ * gx_kick_drift_cubes -- gx_kick_drift for independent systems (SN cubes)
+ * that each take their own Courant step: particle i of cube c = cube_id[i]
+ * uses dt_kick = f_kick dt_cube[c] and dt_drift = f_drift dt_cube[c]
+ * (dt_cube device double [n_cubes], e.g. from gx_sph_timestep with cube_id;
+ * a cube with dt 0 stays put).  All n particles are gas: u, dudt, upred and
+ * vpred_xyz (layout of gx_kick_drift) cover all of them, or are NULL.
+ */
+int gx_kick_drift_cubes(gx_ctx* ctx, int64_t n, const int32_t* cube_id, const double* dt_cube,
+                        double f_kick, double f_drift, double* x, double* y, double* z, double* vx,
+                        double* vy, double* vz, const double* ax, const double* ay,
+                        const double* az, double* u, const double* dudt, double u_floor,
+                        double* vpred_xyz, double* upred);
 
 /*
  * gx_energy -- FP64 energy audit, deterministic two-level reduction:

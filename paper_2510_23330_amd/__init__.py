@@ -223,6 +223,16 @@ class Engine:
                                            n_u, _ptr(u), _ptr(dudt), float(u_floor), _ptr(vpred),
                                            _ptr(upred)))
 
+    def kick_drift_cubes(self, p: ParticleSet, cube_id, dt_cube, f_kick, f_drift, ax, ay, az,
+                         u=None, dudt=None, u_floor=0.0, vpred=None, upred=None):
+        """Half step of independent cubes, each with its own dt (device double [K])."""
+        torch = _torch()
+        self._check(self.lib.gx_kick_drift_cubes(
+            self.ctx, p.n, _ptr(cube_id, torch.int32), _ptr(dt_cube, torch.float64), float(f_kick),
+            float(f_drift), _ptr(p.x), _ptr(p.y), _ptr(p.z), _ptr(p.vx), _ptr(p.vy), _ptr(p.vz),
+            _ptr(ax), _ptr(ay), _ptr(az), _ptr(u), _ptr(dudt), float(u_floor), _ptr(vpred),
+            _ptr(upred)))
+
     def energy(self, p: ParticleSet, pot, m_gas=None, u=None):
         out = (C.c_double * 3)()
         n_gas = 0 if u is None else int(u.shape[0])

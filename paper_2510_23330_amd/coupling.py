@@ -73,22 +73,26 @@ class SNCoupling:
         each kept unless its box would overlap the box of a site already kept
         (so every gas particle belongs to at most one region), until K."""
         rng = np.random.default_rng(self.seed + step_index)
-        order = rng.permutation(self.cand)
         torch, p = self.torch, self.step.p
         side = self.side / PC_PER_KPC
         kept = np.zeros((0, 3))
-        chosen = []
-        for a in range(0, order.size, 4096):
-            idx = torch.as_tensor(order[a:a + 4096], device=p.x.device)
+        chosen, seen = [], set()
+        want = min(self.K, self.cand.size)
+        for _ in range(64):  # draws of 4K distinct candidates until K are kept
+            draw = rng.choice(self.cand, size=min(4 * self.K, self.cand.size), replace=False)
+            idx = torch.as_tensor(draw, device=p.x.device)
             pos = torch.stack([p.x[idx], p.y[idx], p.z[idx]], dim=1).cpu().numpy()
             for j in range(pos.shape[0]):
+                if draw[j] in seen:
+                    continue
+                seen.add(int(draw[j]))
                 if kept.shape[0] and np.any(np.all(np.abs(kept - pos[j]) < side, axis=1)):
                     continue
                 kept = np.vstack([kept, pos[j]])
-                chosen.append(order[a + j])
-                if len(chosen) == self.K:
+                chosen.append(draw[j])
+                if len(chosen) == want:
                     break
-            if len(chosen) == self.K:
+            if len(chosen) == want:
                 break
         s = torch.as_tensor(np.sort(np.asarray(chosen, np.int64)), device=p.x.device)
         return torch.stack([p.x[s], p.y[s], p.z[s]], dim=1).contiguous()

@@ -6,8 +6,11 @@
 
 #include <cstring>
 
+// With a cube table (cube != nullptr) particle i takes the step dt of its
+// cube: dtk = dtk * dt_cube[cube[i]], dtd = dtd * dt_cube[cube[i]].
 __global__ __launch_bounds__(256) void k_kick_drift(
-    int64_t n, double dtk, double dtd, double* __restrict__ x, double* __restrict__ y,
+    int64_t n, double dtk_, double dtd_, const int32_t* __restrict__ cube,
+    const double* __restrict__ dt_cube, double* __restrict__ x, double* __restrict__ y,
     double* __restrict__ z, double* __restrict__ vx, double* __restrict__ vy,
     double* __restrict__ vz, const double* __restrict__ ax, const double* __restrict__ ay,
     const double* __restrict__ az, int64_t n_u, double* __restrict__ u,
@@ -15,6 +18,12 @@ __global__ __launch_bounds__(256) void k_kick_drift(
     double* __restrict__ upred) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    double dtk = dtk_, dtd = dtd_;
+    if (cube) {
+        const double dc = dt_cube[cube[i]];
+        dtk *= dc;
+        dtd *= dc;
+    }
     const double a0 = ax[i], a1 = ay[i], a2 = az[i];
     const double v0 = vx[i] + a0 * dtk, v1 = vy[i] + a1 * dtk, v2 = vz[i] + a2 * dtk;
     vx[i] = v0;
@@ -55,8 +64,27 @@ extern "C" int gx_kick_drift(gx_ctx* ctx, int64_t n, double dt_kick, double dt_d
     if (n == 0) return GX_OK;
     GX_HIP(ctx, hipSetDevice(ctx->device));
     hipLaunchKernelGGL(k_kick_drift, dim3(gx_blocks(n, 256)), dim3(256), 0, ctx->stream, n, dt_kick,
-                       dt_drift, x, y, z, vx, vy, vz, ax, ay, az, u ? n_u : 0, u, dudt, u_floor,
-                       vpred_xyz, upred);
+                       dt_drift, nullptr, nullptr, x, y, z, vx, vy, vz, ax, ay, az, u ? n_u : 0, u,
+                       dudt, u_floor, vpred_xyz, upred);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+extern "C" int gx_kick_drift_cubes(gx_ctx* ctx, int64_t n, const int32_t* cube_id,
+                                   const double* dt_cube, double f_kick, double f_drift, double* x,
+                                   double* y, double* z, double* vx, double* vy, double* vz,
+                                   const double* ax, const double* ay, const double* az,
+                                   double* u, const double* dudt, double u_floor,
+                                   double* vpred_xyz, double* upred) {
+    if (!ctx) return GX_EINVAL;
+    if (n < 0 || !cube_id || !dt_cube || !x || !y || !z || !vx || !vy || !vz || !ax || !ay || !az)
+        return gx_fail(ctx, GX_EINVAL, "kick_drift_cubes: null pointer or n < 0");
+    if (u && !dudt) return gx_fail(ctx, GX_EINVAL, "kick_drift_cubes: u without dudt");
+    if (n == 0) return GX_OK;
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_kick_drift, dim3(gx_blocks(n, 256)), dim3(256), 0, ctx->stream, n, f_kick,
+                       f_drift, cube_id, dt_cube, x, y, z, vx, vy, vz, ax, ay, az, u ? n : 0, u, dudt,
+                       u_floor, vpred_xyz, upred);
     GX_LAUNCH_CHECK(ctx);
     return GX_OK;
 }

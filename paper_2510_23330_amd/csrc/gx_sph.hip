@@ -77,9 +77,11 @@ enum {
     W_H = 0, W_RAD, W_ACT, W_FLAG, W_VEL, W_SPH, W_STAT,
     // long-list groups: chunk counts, item offsets, group list, items, Newton
     // state per slot, partial sums, finished flags
-    W_HV = 13, W_HOFF, W_HLIST, W_ITEM, W_HST, W_PART, W_PARTV, W_GD
+    W_HV = 13, W_HOFF, W_HLIST, W_ITEM, W_HST, W_PART, W_PARTV, W_GD,
+    // per-group count of density evaluations inside the kernel support
+    W_NGB = 23
 };
-static_assert(W_GD < 24, "work slots");
+static_assert(W_GD < 21, "work slots");
 
 static int work(gx_ctx* ctx, int k, size_t bytes, void** p) {
     GX_TRY(gx_reserve(ctx, ctx->sph_work[k], bytes));
@@ -167,12 +169,14 @@ __device__ __forceinline__ void expand_chunk(const GroupList& L, int npp, int ch
 // the candidates of one lane's hit list, in list order.
 __device__ __forceinline__ void dens_hits(const uint16_t (*hl)[SPH_DT], int nh, int tid,
                                           const float4* __restrict__ cand, float xi, float yi,
-                                          float zi, float Hinv2, float& s0, float& s1) {
+                                          float zi, float Hinv2, float& s0, float& s1,
+                                          unsigned& nin) {
     for (int j = 0; j < nh; j++) {
         const float4 c = cand[hl[j][tid]];
         const float dx = c.x - xi, dy = c.y - yi, dz = c.z - zi;
         const float q2 = (dx * dx + dy * dy + dz * dz) * Hinv2;
         if (q2 < 1.0f) {
+            nin++;
             const float q = __builtin_amdgcn_sqrtf(q2);
             const float t = 1.0f - q;
             const float t2 = t * t;
@@ -192,7 +196,7 @@ __device__ __forceinline__ void dens_hits(const uint16_t (*hl)[SPH_DT], int nh, 
 __device__ __forceinline__ bool dens_scan(uint16_t (*hl)[SPH_DT], int& nh, int tid, int sl, int nsl,
                                           int n, bool act, const float4* __restrict__ cand,
                                           float xi, float yi, float zi, float lim, float Hinv2,
-                                          float& s0, float& s1) {
+                                          float& s0, float& s1, unsigned& nin) {
     nh = 0;
     bool flushed = false;
     const int nst = (n + nsl - 1) / nsl;
@@ -207,7 +211,7 @@ __device__ __forceinline__ bool dens_scan(uint16_t (*hl)[SPH_DT], int& nh, int t
             nh += (act && k < n && r2 < lim) ? 1 : 0;
         }
         if (__ballot(nh > SPH_HCAP - 4)) {  // wave-uniform flush
-            dens_hits(hl, nh, tid, cand, xi, yi, zi, Hinv2, s0, s1);
+            dens_hits(hl, nh, tid, cand, xi, yi, zi, Hinv2, s0, s1, nin);
             nh = 0;
             flushed = true;
         }
@@ -298,7 +302,8 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density(
     const double4* __restrict__ pos4, const uint32_t* __restrict__ perm,
     const uint8_t* __restrict__ active, ListView L, float* __restrict__ rad, float n_ngb, float tol,
     int max_iter, float* __restrict__ Hs, uint32_t* __restrict__ flags, uint32_t* __restrict__ hv,
-    unsigned long long* __restrict__ stat, const double* __restrict__ u, float gamma,
+    unsigned long long* __restrict__ stat, uint32_t* __restrict__ gngb,
+    const double* __restrict__ u, float gamma,
     double* __restrict__ H64, float* __restrict__ Hout, float* __restrict__ rho_out,
     float* __restrict__ P_out, float* __restrict__ cs_out) {
     const int g = xcd_remap(blockIdx.x, ng);
@@ -335,6 +340,7 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density(
     int nflag = 0, nfail = 0, worst_it = 0;
     float hmax = 0.0f;
     unsigned long long evals = 0;  // receiver x candidate evaluations, all passes
+    unsigned nin = 0;              // this lane's evaluations inside the kernel support
     for (int ic = 0; ic < nG; ic += pad) {
         const int s = B.begin + ic + il;
         const bool act = sl < nsl && ic + il < nG;
@@ -364,10 +370,10 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density(
                     Hb = H;
                     const bool flushed = dens_scan(hl, nh, tid, sl, nsl, npp, act, cand, xi, yi,
                                                    zi, (SPH_KAPPA * SPH_KAPPA) * H * H, Hinv2, s0,
-                                                   s1);
+                                                   s1, nin);
                     have = !__syncthreads_or(flushed);
                 }
-                dens_hits(hl, nh, tid, cand, xi, yi, zi, Hinv2, s0, s1);
+                dens_hits(hl, nh, tid, cand, xi, yi, zi, Hinv2, s0, s1, nin);
             } else {
                 for (int ch = 0; ch < npp; ch += SPH_CAP) {
                     const int che = min(npp, ch + SPH_CAP);
@@ -376,8 +382,8 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density(
                                  tid, SPH_DT);
                     __syncthreads();
                     dens_scan(hl, nh, tid, sl, nsl, che - ch, act, cand, xi, yi, zi, H * H, Hinv2,
-                              s0, s1);
-                    dens_hits(hl, nh, tid, cand, xi, yi, zi, Hinv2, s0, s1);
+                              s0, s1, nin);
+                    dens_hits(hl, nh, tid, cand, xi, yi, zi, Hinv2, s0, s1, nin);
                 }
             }
             // the slices' partial sums, added in slice order (every copy of
@@ -408,13 +414,34 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density(
             }
         }
     }
+    nin = wave_sum(nin);
+    if (lane == 0) wtot[wv] = (int)nin;
+    __syncthreads();
     if (wv == 0) {  // slice 0 (the written copies) lies in wave 0
         nflag = (int)wave_sum((unsigned)nflag);
         nfail = (int)wave_sum((unsigned)nfail);
         worst_it = wave_max(worst_it);
         hmax = wave_max(hmax);
-        if (lane == 0) dens_group_stats(g, nflag, nfail, worst_it, hmax, evals, flags, rad, stat);
+        if (lane == 0) {
+            dens_group_stats(g, nflag, nfail, worst_it, hmax, evals, flags, rad, stat);
+            unsigned tin = 0;
+            for (int w = 0; w < SPH_DT / 64; w++) tin += (unsigned)wtot[w];
+            gngb[g] += tin;  // one workgroup per group and round: no other writer
+        }
     }
+}
+
+// Sum of n counters into *out (one workgroup, fixed order per thread; the
+// statistics of a call, not on its critical path).
+__global__ __launch_bounds__(256) void k_sum_u32(const uint32_t* __restrict__ v, int n,
+                                                 unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long sh[4];
+    unsigned long long s = 0;
+    for (int i = threadIdx.x; i < n; i += 256) s += v[i];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -456,7 +483,8 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density_part(
     const int2* __restrict__ items, const int32_t* __restrict__ groups,
     const NodeRec* __restrict__ nodes, const double4* __restrict__ pos4, ListView L,
     const float* __restrict__ Hs, const float4* __restrict__ hst,
-    const uint8_t* __restrict__ gdone, float2* __restrict__ part) {
+    const uint8_t* __restrict__ gdone, float2* __restrict__ part,
+    uint32_t* __restrict__ gngb) {
     const int2 item = items[blockIdx.x];
     const int g = item.x;
     if (gdone[g]) return;
@@ -492,9 +520,12 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density_part(
     const float Hinv = 1.0f / H, Hinv2 = Hinv * Hinv;
     float s0 = 0.0f, s1 = 0.0f;
     int nh;
-    dens_scan(hl, nh, tid, sl, nsl, che - ch, act, cand, xi, yi, zi, H * H, Hinv2, s0, s1);
-    dens_hits(hl, nh, tid, cand, xi, yi, zi, Hinv2, s0, s1);
+    unsigned nin = 0;
+    dens_scan(hl, nh, tid, sl, nsl, che - ch, act, cand, xi, yi, zi, H * H, Hinv2, s0, s1, nin);
+    dens_hits(hl, nh, tid, cand, xi, yi, zi, Hinv2, s0, s1, nin);
     red[tid] = make_float2(s0, s1);
+    nin = wave_sum(nin);
+    if (lane == 0 && nin) atomicAdd(&gngb[g], nin);
     __syncthreads();
     if (sl == 0 && il < nG) {  // the slices' partial sums in slice order
         s0 = 0.0f;
@@ -1044,7 +1075,8 @@ static int long_items(gx_ctx* ctx, int nb, const uint32_t* hv, int64_t** hoff, i
 // done (at most max_iter passes).
 static int density_long(gx_ctx* ctx, TreeSlot& T, const ListView& view, int nb, float* rad,
                         float n_ngb, float tol, int max_iter, float* Hs, uint32_t* flags,
-                        const uint32_t* hv, unsigned long long* stat, gx_gas* gs, float gamma) {
+                        const uint32_t* hv, unsigned long long* stat, uint32_t* gngb, gx_gas* gs,
+                        float gamma) {
     hipStream_t st = ctx->stream;
     int64_t *hoff, ni = 0;
     int2* items;
@@ -1071,7 +1103,8 @@ static int density_long(gx_ctx* ctx, TreeSlot& T, const ListView& view, int nb, 
         hipLaunchKernelGGL(k_sph_density_part, dim3((unsigned)ni), dim3(SPH_DT), 0, st,
                            (const int2*)items, (const int32_t*)T.groups.p,
                            (const NodeRec*)T.nodes.p, (const double4*)T.pos4.p, view,
-                           (const float*)Hs, (const float4*)hst, (const uint8_t*)gdone, part);
+                           (const float*)Hs, (const float4*)hst, (const uint8_t*)gdone, part,
+                           gngb);
         hipLaunchKernelGGL(k_sph_density_long_step, dim3((unsigned)ni), dim3(64), 0, st,
                            (const uint32_t*)ctr, (const int32_t*)hlist,
                            (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
@@ -1121,6 +1154,9 @@ extern "C" int gx_sph_density(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, 
     GX_TRY(gx_zero(ctx, stat, 16 * sizeof(unsigned long long)));
     uint32_t* hv;
     GX_TRY(work(ctx, W_HV, (size_t)(nb + 1) * sizeof(uint32_t), (void**)&hv));
+    uint32_t* gngb;
+    GX_TRY(work(ctx, W_NGB, (size_t)(nb + 1) * sizeof(uint32_t), (void**)&gngb));
+    GX_TRY(gx_zero(ctx, gngb, (size_t)nb * sizeof(uint32_t)));
     hipLaunchKernelGGL(k_sph_seed, dim3(gx_blocks(n, 256)), dim3(256), 0, st, n,
                        (const NodeRec*)T.nodes.p, (const MomRec*)T.mom.p, (const double4*)T.pos4.p,
                        (const uint32_t*)T.val[0].p, gs->H64, (float)n_ngb, (const double*)T.box.p,
@@ -1143,11 +1179,11 @@ extern "C" int gx_sph_density(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, 
                            (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
                            (const double4*)T.pos4.p,
                            (const uint32_t*)T.val[0].p, act, view, rad, (float)n_ngb, (float)tol,
-                           max_iter, Hs, flags, hv, stat, gs->u, (float)gamma, gs->H64, gs->H,
+                           max_iter, Hs, flags, hv, stat, gngb, gs->u, (float)gamma, gs->H64, gs->H,
                            gs->rho, gs->P, gs->cs);
         GX_LAUNCH_CHECK(ctx);
         GX_TRY(density_long(ctx, T, view, nb, rad, (float)n_ngb, (float)tol, max_iter, Hs, flags,
-                            hv, stat, gs, (float)gamma));
+                            hv, stat, gngb, gs, (float)gamma));
         if (stats) GX_HIP(ctx, hipEventRecord(ctx->ev3, st));
         GX_HIP(ctx, hipMemcpyAsync(h_stat, stat, 8 * sizeof(unsigned long long),
                                    hipMemcpyDeviceToHost, st));
@@ -1169,7 +1205,12 @@ extern "C" int gx_sph_density(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, 
     }
     if (stats) {
         GX_HIP(ctx, hipEventRecord(ctx->ev1, st));
-        GX_HIP(ctx, hipEventSynchronize(ctx->ev1));
+        hipLaunchKernelGGL(k_sum_u32, dim3(1), dim3(256), 0, st, (const uint32_t*)gngb, nb,
+                           stat + 6);
+        GX_LAUNCH_CHECK(ctx);
+        GX_HIP(ctx, hipMemcpyAsync(h_stat + 6, stat + 6, sizeof(unsigned long long),
+                                   hipMemcpyDeviceToHost, st));
+        GX_HIP(ctx, hipStreamSynchronize(st));
         float ms = 0;
         GX_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
         stats->ms = ms;
@@ -1177,6 +1218,7 @@ extern "C" int gx_sph_density(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, 
         stats->n_noconv = (int64_t)h_stat[0];
         stats->n_iter_max = (int64_t)h_stat[1];
         stats->n_sph_list = (int64_t)h_stat[5];
+        stats->n_sph_ngb = (int64_t)h_stat[6];
         stats->n_rewalk = rounds - 1;
         stats->n_groups = nb;
         stats->n_nodes = T.n_nodes;
@@ -1229,6 +1271,9 @@ extern "C" int gx_sph_forces(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, d
     if (stats) GX_HIP(ctx, hipEventRecord(ctx->ev2, st));
     uint32_t* hv;
     GX_TRY(work(ctx, W_HV, (size_t)(nb + 1) * sizeof(uint32_t), (void**)&hv));
+    uint32_t* gngb;
+    GX_TRY(work(ctx, W_NGB, (size_t)(nb + 1) * sizeof(uint32_t), (void**)&gngb));
+    GX_TRY(gx_zero(ctx, gngb, (size_t)nb * sizeof(uint32_t)));
     GX_TRY(gx_zero(ctx, hv, (size_t)nb * sizeof(uint32_t)));
     hipLaunchKernelGGL(k_sph_force<false>, dim3(xcd_grid(nb)), dim3(SPH_DT), 0, st, nb,
                        (const int2*)nullptr, (const int32_t*)T.groups.p,

@@ -115,6 +115,87 @@ class SNBatch:
                 log(f"[sn] step {self.steps} t = {self.t / MYR * 1e3:.2f} kyr dt = {dt / MYR * 1e6:.1f} yr")
         return self.steps
 
+    # fields carried by the working set of run_cubes
+    _P_FIELDS = ("x", "y", "z", "vx", "vy", "vz", "m", "eps2")
+    _G_FIELDS = ("u", "dudt", "H64", "H", "rho", "P", "cs", "vsig")
+
+    def run_cubes(self, t_end: float, max_steps: int = 100000, log=None):
+        """KDK to t_end in which every cube takes its own Courant step: the
+        step of cube c is c_cfl min over its particles of H / v_sig
+        (gx_sph_timestep per cube), applied by gx_kick_drift_cubes, so a cube
+        is not held to the smallest step of the batch.  Cubes are independent
+        (no forces between them), so they share the force evaluations of one
+        working set; a cube that reaches t_end leaves it, its final state
+        written back to the batch's arrays.  Returns the per-cube step counts
+        (numpy int [K])."""
+        torch = self.torch
+        dev = self.p.x.device
+        K = self.K
+        off = np.asarray(self.off, np.int64)
+        t_c = np.zeros(K)
+        steps = np.zeros(K, np.int64)
+        if self.steps == 0:
+            self._forces(predicted=False)
+        full_p, full_g = self.p, self.g
+        full_a = (self.ax, self.ay, self.az)
+        active = np.arange(K)
+        keep = None           # particle indices of the working set in the full arrays
+        cid = torch.as_tensor(np.asarray(self.b["cube_id"], np.int32), device=dev)
+        dt_dev = torch.zeros(K, dtype=torch.float64, device=dev)
+        it = 0
+        while active.size and it < max_steps:
+            ka = active.size
+            self.eng.sph_timestep(self.g, self.cfg.c_cfl, dt_dev[:ka], cube_id=cid, n_cubes=ka)
+            dt = np.minimum(dt_dev[:ka].cpu().numpy(), t_end - t_c[active])
+            dt_dev[:ka].copy_(torch.as_tensor(dt, device=dev))
+            self.eng.kick_drift_cubes(self.p, cid, dt_dev[:ka], 0.5, 1.0, self.ax, self.ay, self.az,
+                                      u=self.g.u, dudt=self.g.dudt, u_floor=self.u_floor,
+                                      vpred=self.vpred, upred=self.upred)
+            self._forces(predicted=True)
+            self.eng.kick_drift_cubes(self.p, cid, dt_dev[:ka], 0.5, 0.0, self.ax, self.ay, self.az,
+                                      u=self.g.u, dudt=self.g.dudt, u_floor=self.u_floor)
+            t_c[active] += dt
+            steps[active] += 1
+            it += 1
+            self._guard()
+            done = t_c[active] >= t_end * (1 - 1e-12)
+            if done.any():
+                # write the working set back, then keep the unfinished cubes only
+                if keep is not None:
+                    for f in self._P_FIELDS:
+                        getattr(full_p, f).index_copy_(0, keep, getattr(self.p, f))
+                    for f in self._G_FIELDS:
+                        getattr(full_g, f).index_copy_(0, keep, getattr(self.g, f))
+                    for a, b in zip(full_a, (self.ax, self.ay, self.az)):
+                        a.index_copy_(0, keep, b)
+                active = active[~done]
+                if active.size == 0:
+                    break
+                idx = np.concatenate([np.arange(off[c], off[c + 1]) for c in active])
+                keep = torch.as_tensor(idx, device=dev)
+                self.p = ParticleSet(**{f: getattr(full_p, f).index_select(0, keep)
+                                        for f in self._P_FIELDS})
+                self.g = GasState(**{f: getattr(full_g, f).index_select(0, keep)
+                                     for f in self._G_FIELDS})
+                self.ax, self.ay, self.az = (a.index_select(0, keep) for a in full_a)
+                n = int(idx.size)
+                self.n = n
+                self.vpred = torch.zeros(3 * n, dtype=torch.float64, device=dev)
+                self.upred = torch.zeros(n, dtype=torch.float64, device=dev)
+                counts = off[active + 1] - off[active]
+                cid = torch.as_tensor(np.repeat(np.arange(active.size, dtype=np.int32), counts),
+                                      device=dev)
+            if log and it % 50 == 0:
+                log(f"[sn] iteration {it}: {active.size} cubes left")
+        self.p, self.g = full_p, full_g
+        self.ax, self.ay, self.az = full_a
+        self.n = full_p.n
+        self.vpred = torch.zeros(3 * self.n, dtype=torch.float64, device=dev)
+        self.upred = torch.zeros(self.n, dtype=torch.float64, device=dev)
+        self.t = t_end
+        self.steps += int(steps.max()) if K else 0
+        return steps
+
     def _guard(self, x_max: float = 1e7, u_max: float = 1e12):
         """Stop a run whose state left the representable range (a forced
         timestep far above the Courant limit can do that) before the next tree
@@ -148,7 +229,7 @@ class SNBatch:
 
 
 def generate(eng: Engine, seeds, t_end_myr: float = 0.1, log=None, cfg: SPHConfig = SPHConfig(),
-             dt_fixed_myr: float = None, keep=False, grid: int = GRID):
+             dt_fixed_myr: float = None, keep=False, grid: int = GRID, per_cube: bool = False):
     """One batch of training pairs: voxel grids just before the explosion and
     t_end after it, from plain small-dt SPH (or fixed steps of dt_fixed_myr).
     Returns (x, y, info) with x, y device float [K * 64^3 * 5] physical
@@ -161,13 +242,20 @@ def generate(eng: Engine, seeds, t_end_myr: float = 0.1, log=None, cfg: SPHConfi
     sb.torch.cuda.synchronize()
     t0 = time.perf_counter()
     sb.inject()
-    steps = sb.run(t_end_myr * MYR, log=log,
-                   dt_fixed=None if dt_fixed_myr is None else dt_fixed_myr * MYR)
+    cube_steps = None
+    if per_cube and dt_fixed_myr is None:
+        cube_steps = sb.run_cubes(t_end_myr * MYR, log=log)
+        steps = int(cube_steps.max())
+    else:
+        steps = sb.run(t_end_myr * MYR, log=log,
+                       dt_fixed=None if dt_fixed_myr is None else dt_fixed_myr * MYR)
     sb.torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     y = sb.voxelize(grid=grid)
     info = {"steps": steps, "seconds": wall, "n_particles": sb.n, "K": sb.K, "noconv": sb.noconv,
             "n_cm3": b["n_cm3"].tolist(), "T": b["T_amb"].tolist()}
+    if cube_steps is not None:
+        info["cube_steps"] = cube_steps.tolist()
     if keep:
         info["batch"] = sb
     return x, y, info
@@ -262,8 +350,24 @@ class Surrogate:
         np.savez(path, w32=d["w32"], t=d["t"], **extra,
                  **{k: getattr(self, k).cpu().numpy() for k in self.STATS})
 
+    def export(self, path):
+        """Inference weights: BF16 bits of every parameter (what the network
+        computes with) plus the FP32 biases, and the channel statistics."""
+        w = self.net.w32.cpu().numpy()
+        b0 = min(ly.b_off for ly in self.net.L)
+        bits = self.net.wbf.view(self.torch.int16).cpu().numpy().view(np.uint16)
+        np.savez_compressed(path, w_bf16=bits, bias_f32=w[b0:], b_off=np.int64(b0),
+                            levels=np.int64(self.net.levels), base=np.int64(self.net.base),
+                            **{k: getattr(self, k).cpu().numpy() for k in self.STATS})
+
     def load(self, path):
         d = np.load(path)
+        if "w_bf16" in d:  # an exported inference file
+            if int(d["levels"]) != self.net.levels or int(d["base"]) != self.net.base:
+                raise ValueError(f"{path}: network shape differs")
+            w = (d["w_bf16"].astype(np.uint32) << 16).view(np.float32).copy()
+            w[int(d["b_off"]):] = d["bias_f32"]
+            d = dict(d, w32=w)
         z = np.zeros_like(d["w32"])
         self.net.load_state_dict({"w32": d["w32"], "m": d["m"] if "m" in d else z,
                                   "v": d["v"] if "v" in d else z,

@@ -206,6 +206,8 @@ def main(argv=None):
     ap.add_argument("--no-augment", action="store_true",
                     help="train without the random cube symmetries")
     ap.add_argument("--out", default="sn_out")
+    ap.add_argument("--export", default=None,
+                    help="also write the inference weights (BF16) to this file")
     a = ap.parse_args(argv)
     import torch
     os.makedirs(a.out, exist_ok=True)
@@ -261,6 +263,8 @@ def main(argv=None):
                            "tflops_est": 3 * flops_forward(a.grid, a.base, a.levels) * steps * a.batch
                            / max(ttrain, 1e-9) / 1e12}
     sur.save(os.path.join(a.out, "surrogate.npz"))
+    if a.export:
+        sur.export(a.export)
 
     # 4. held-out evaluation (physical channels)
     n_t = Xtp.shape[0]

@@ -357,3 +357,66 @@ def test_trust_check_flags(gx, eng):
     ok2 = eng.sn_check(pred[: 2 * grid ** 3 * 5], 2, grid, lo, hi)
     assert ok2.tolist() == [True, True]
     assert eng.sn_check(pred, 0, grid, lo, hi).tolist() == []
+
+
+def test_kick_drift_cubes_matches_oracle_per_cube(gx, eng):
+    # each cube's particles take the oracle's leapfrog half step with that
+    # cube's dt (a cube with dt = 0 stays put)
+    import torch
+    rng = np.random.default_rng(51)
+    counts = np.array([700, 1, 0, 1300])
+    n = int(counts.sum())
+    cid = np.repeat(np.arange(4, dtype=np.int32), counts)
+    dt_c = np.array([0.01, 0.3, 0.2, 0.0])
+    x, v, a = (rng.normal(size=(3, n)) for _ in range(3))
+    u, du = rng.uniform(1, 2, n), rng.normal(size=n)
+    d = {"x": x[0], "y": x[1], "z": x[2], "vx": v[0], "vy": v[1], "vz": v[2], "m": np.ones(n)}
+    p = gx.ParticleSet.from_numpy(d)
+    A = [_t(a[k]) for k in range(3)]
+    ut = _t(u.copy())
+    vpred = torch.zeros(3 * n, dtype=torch.float64, device="cuda")
+    upred = torch.zeros(n, dtype=torch.float64, device="cuda")
+    eng.kick_drift_cubes(p, _t(cid), _t(dt_c), 0.5, 1.0, *A, u=ut, dudt=_t(du), vpred=vpred,
+                         upred=upred)
+    X = np.stack([t.cpu().numpy() for t in (p.x, p.y, p.z)])
+    Vv = np.stack([t.cpu().numpy() for t in (p.vx, p.vy, p.vz)])
+    for c in range(4):
+        sl = cid == c
+        if not sl.any():
+            continue
+        xo, vo, uo, vp, up = oracle.kick_drift(x[:, sl], v[:, sl], a[:, sl], 0.5 * dt_c[c], dt_c[c],
+                                               u=u[sl], dudt=du[sl])
+        # (the device may fuse a multiply-add: one rounding fewer)
+        close = lambda g, r: np.allclose(g, r, rtol=1e-14, atol=1e-15)
+        assert close(X[:, sl], xo) and close(Vv[:, sl], vo)
+        assert close(ut.cpu().numpy()[sl], uo)
+        assert close(vpred.cpu().numpy().reshape(3, n)[:, sl], vp)
+        assert close(upred.cpu().numpy()[sl], up)
+
+
+def test_per_cube_steps_match_single_cube_runs(gx, eng):
+    # Cubes are independent: run together with per-cube Courant steps, each
+    # takes the steps it takes alone (same count) and ends where it ends alone
+    # (up to FP32 sums over different tree groupings).
+    import torch
+    from paper_2510_23330_amd.sn import MYR, SNBatch
+    seeds = [7001, 7002, 7003]
+    t_end = 0.004 * MYR
+    b = ics.sn_batch(seeds, n_fixed=1500)
+    sb = SNBatch(eng, b)
+    sb.inject()
+    steps = sb.run_cubes(t_end)
+    X = sb.p.x.cpu().numpy()
+    U = sb.g.u.cpu().numpy()
+    off = b["offsets"]
+    for k, s in enumerate(seeds):
+        one = ics.sn_batch([s], n_fixed=1500)
+        so = SNBatch(eng, one)
+        so.inject()
+        n1 = so.run(t_end)
+        assert n1 == steps[k]
+        x1 = so.p.x.cpu().numpy() + b["centres"][k, 0] - one["centres"][0, 0]
+        sl = slice(off[k], off[k + 1])
+        assert np.allclose(X[sl], x1, rtol=0, atol=1e-6 * 60.0)
+        assert np.allclose(U[sl], so.g.u.cpu().numpy(), rtol=1e-4)
+    assert steps.min() >= 1
