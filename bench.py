@@ -94,6 +94,15 @@ def parse():
                                                       "sn_unet_5ch.npz"),
                     help="trained surrogate weights (random initialisation when absent)")
     ap.add_argument("--no-force-error", action="store_true")
+    ap.add_argument("--sn-mode", choices=("async", "sync"), default="async",
+                    help="surrogate hand-over on its own stream in a worker thread (default), "
+                         "or in series on the galaxy's stream")
+    ap.add_argument("--n-group", type=int, default=256, help="gravity group size n_g")
+    ap.add_argument("--n-leaf", type=int, default=16, help="gravity tree leaf size")
+    ap.add_argument("--sph-group", type=int, default=64, help="SPH group size")
+    ap.add_argument("--sph-leaf", type=int, default=8, help="gas tree leaf size")
+    ap.add_argument("--plain-steps", type=int, default=5,
+                    help="steps without the surrogate after the timed ones (step cost without it)")
     ap.add_argument("--ic-order", choices=("morton", "generated"), default="morton",
                     help="particle array order: Morton order of a 1024^3 grid per block "
                          "(default) or the generator's order")
@@ -292,15 +301,16 @@ def main():
     p = gx.ParticleSet.from_numpy(d)
     u = torch.as_tensor(d["u_gas"], device="cuda")
     cfg = StepConfig(G=ics.G_KPC, dt=2000.0 * YEAR_IN_KPC_TIME, theta=0.5, quad=True,
-                     n_leaf=16, n_group=256, sph_leaf=8, sph_group=64, n_ngb=64.0,
-                     u_floor=10.0 * ics.U_PER_K)
+                     n_leaf=args.n_leaf, n_group=args.n_group, sph_leaf=args.sph_leaf,
+                     sph_group=args.sph_group, n_ngb=64.0, u_floor=10.0 * ics.U_PER_K)
     sim = GalaxyStep(eng, p, int(d["gas_offset"]), u, cfg)
     coupling = None
     if args.sn_sites > 0:
         from paper_2510_23330_amd.coupling import SNCoupling
-        sur_eng = gx.Engine(0)
+        asyn = args.sn_mode == "async"
+        sur_eng = gx.Engine(0, stream=torch.cuda.Stream() if asyn else None)
         sur, wfile = load_surrogate(sur_eng, 64, args.weights)
-        coupling = SNCoupling(sim, sur, n_sites=args.sn_sites, delay=50)
+        coupling = SNCoupling(sim, sur, n_sites=args.sn_sites, delay=50, asynchronous=asyn)
     torch.cuda.synchronize()
     log("[bench] set-up done; initial forces (cold kernel sizes) ...")
     t0 = time.perf_counter()
@@ -311,6 +321,10 @@ def main():
 
     def sn_phase(i):
         if coupling is None:
+            return
+        if coupling.asynchronous:  # hand-over only; the work overlaps the next steps
+            coupling.apply_due(i)
+            coupling.launch(i)
             return
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -325,6 +339,9 @@ def main():
         sim.energy()
         log(f"[bench] warmup step {w} done")
     sn_ms.clear()
+    if coupling is not None:
+        coupling.drain()
+        coupling.sur_ms.clear()
     torch.cuda.synchronize()
 
     per = []
@@ -362,6 +379,45 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_step = elapsed / args.steps * 1e3
+    sn_async = None
+    applied_at_end = 0
+    if coupling is not None:
+        coupling.drain()
+        sur_ms = list(coupling.sur_ms)
+        # a run shorter than the 50-step delay has no result falling due while
+        # timed: apply the queued ones now, untimed, so that replacement by ID
+        # runs on what the network predicted for these regions
+        applied_at_end = len(coupling.queue)
+        coupling.apply_due(10 ** 9)
+        if coupling.asynchronous and args.plain_steps > 0:
+            # the same steps without the hand-over: what the surrogate adds
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.plain_steps):
+                sim.step()
+                sim.energy()
+            torch.cuda.synchronize()
+            ms_plain = (time.perf_counter() - t0) / args.plain_steps * 1e3
+            # and the hand-over alone, in series (nothing else on the GPU)
+            serial = []
+            for k in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                coupling.launch(10 ** 6 + k)
+                coupling.drain()
+                torch.cuda.synchronize()
+                serial.append((time.perf_counter() - t0) * 1e3)
+            added = ms_step - ms_plain
+            sn_async = {"handover_serial_ms": float(np.median(serial)),
+                        "step_ms_without_surrogate": ms_plain,
+                        "step_ms_added": added,
+                        "hidden_fraction": 1.0 - added / float(np.median(serial)),
+                        "surrogate_stream_ms_per_handover": float(np.mean(sur_ms)),
+                        "note": "surrogate on its own stream and host thread, started after the "
+                                "next gravity kernel; hidden fraction = 1 - (step with - step "
+                                "without) / the hand-over's cost in series"}
+            sn_ms[:] = []
+        coupling.close()
     inter_step = (n_pp + n_pc) / args.steps
     value = inter_step / (ms_step / 1e3)
     kernel_s = float(np.mean(grav_kernel_ms)) / 1e3
@@ -386,7 +442,9 @@ def main():
                                "theta 0.5 + quadrupole, n_leaf 16, groups <= 256; SPH Wendland C4, "
                                "64 neighbours, groups <= 64; dt 2000 yr; 64 SN regions per step "
                                "to the surrogate",
-                   "n_particles": args.n, "seed": args.seed, "particle_order": args.ic_order},
+                   "n_particles": args.n, "seed": args.seed, "particle_order": args.ic_order,
+                   "n_group": args.n_group, "n_leaf": args.n_leaf, "sph_group": args.sph_group,
+                   "sph_leaf": args.sph_leaf},
         "s_per_step": ms_step / 1e3,
         "grav_interactions_per_step": inter_step,
         "grav_pp_per_step": n_pp / args.steps,
@@ -397,8 +455,10 @@ def main():
                      "sph_density": float(np.mean(dens_ms)), "sph_force": float(np.mean(hydro_ms)),
                      "sn_surrogate": float(np.mean(sn_ms)) if sn_ms else None},
         "sn_coupling": None if coupling is None else dict(
-            coupling.stats, sites_per_step=args.sn_sites, delay_steps=50,
+            coupling.stats, sites_per_step=args.sn_sites, delay_steps=50, mode=args.sn_mode,
+            handovers_applied_after_timing=applied_at_end,
             weights=wfile or "random init (timing only; every region falls back)"),
+        "sn_async": sn_async,
         "gravity_kernel_interactions_per_s": inter_step / kernel_s,
         "sph": {"density_pair_evals_per_step": n_dens_eval / args.steps,
                 "density_ngb_evals_per_step": n_dens_ngb / args.steps,
@@ -434,14 +494,15 @@ def main():
         t0 = time.perf_counter()
         out["sn_region"] = sn_region_leg(eng, args.sn_cubes, args.sn_infer_batch, args.weights)
         log(f"[bench] SN region leg {time.perf_counter() - t0:.1f} s")
-        if sn_ms:
+        if sn_ms or sn_async:
             # 0.1 Myr of the disk with 64 SNe per step: 50 global steps of
             # 2,000 yr with the surrogate hand-over in each, against a shared
             # step that the SN regions hold to their Courant step (the shared-
             # step SPH of the 1 Msun cubes gives it) at the step cost without
             # the surrogate
             n_sh = out["sn_region"]["plain_sph_shared_step"]["steps"]
-            plain_step_s = (ms_step - float(np.mean(sn_ms))) / 1e3
+            plain_step_s = (sn_async["step_ms_without_surrogate"] if sn_async
+                            else ms_step - float(np.mean(sn_ms))) / 1e3
             out["galaxy_0p1Myr"] = {
                 "surrogate_s": 50 * ms_step / 1e3,
                 "plain_shared_step_s": n_sh * plain_step_s,

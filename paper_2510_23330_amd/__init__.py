@@ -170,6 +170,11 @@ class Engine:
         """Test hook: limit the gravity walk's small stack (0 restores it)."""
         self._check(self.lib.gx_set_walk_stack_limit(self.ctx, int(entries)))
 
+    @property
+    def stream(self):
+        """The torch stream this context enqueues on."""
+        return self._stream
+
     def set_stream(self, stream):
         self._stream = stream
         self._check(self.lib.gx_set_stream(self.ctx, C.c_void_p(stream.cuda_stream)))

@@ -3,45 +3,64 @@ are handed to the learned surrogate and their gas is replaced, by particle
 ID, after a delay of `delay` global steps (the paper's 0.1 Myr = 50 steps of
 2,000 yr), so the global step never shrinks for the explosions.
 
-Per call, for the K sites of this step (seeded uniform choice among disk
-stars): extract the gas in the (60 pc)^3 box around each site, pack it into
-the box's own frame in pc (`gx_sn_gather`), ambient state, gas tree and
-voxelization in that frame, U-Net inference, resampling of as many particles
-as entered, and transformation back to the galaxy frame drifted by the box's
-bulk velocity over the delay (`gx_sn_unframe`).  The result waits in a queue
-and is written over the particles with the same IDs (`gx_sn_replace`) when it
-falls due.  A region whose prediction leaves the range the network was
-trained on is not replaced: its gas stays with the plain integrator (the
-fallback), and the count is reported.
+Per hand-over, for the K sites of this step (seeded uniform choice among disk
+stars whose boxes do not overlap): extract the gas in the (60 pc)^3 box
+around each site, pack it into the box's own frame in pc (`gx_sn_gather`),
+ambient state, gas tree and voxelization in that frame, U-Net inference,
+resampling of as many particles as entered, and transformation back to the
+galaxy frame drifted by the box's bulk velocity over the delay
+(`gx_sn_unframe`).  The result waits in a queue and is written over the
+particles with the same IDs (`gx_sn_replace`) when it falls due.  A region
+whose prediction leaves the range the network was trained on is not
+replaced: its gas stays with the plain integrator (the fallback), and the
+count is reported.
 
-The surrogate runs on its own library context (its own gas-tree slot) on the
-same stream as the galaxy step; every arithmetic step runs in libgx.
+The surrogate has its own library context (its own gas-tree slot).  In the
+synchronous mode it runs on the galaxy's stream in the calling thread.  In
+the asynchronous mode -- the single-GPU counterpart of the paper's pool
+nodes, which work while the main nodes integrate -- the galaxy's stream
+copies the gas state at the hand-over into a snapshot, and a worker thread
+runs the pipeline on the snapshot on the surrogate's own stream (default
+priority) while the galaxy steps on, starting after the next step's gravity
+kernel (in the shadow of the latency-bound SPH and tree phases, not beside
+the compute-bound gravity kernel); the galaxy's stream waits for a result's
+completion event only when its replacement falls due.  Both modes
+compute the same replacements bit for bit: the same kernels on the same
+state, with the uniforms of the resampling drawn from a generator seeded by
+the step.  Every arithmetic step runs in libgx.
 """
 from __future__ import annotations
 
 import math
+import queue as _queue
+import threading
 from collections import deque
-from dataclasses import dataclass
+from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import GX_TREE_GAS, Engine, GasState, ParticleSet
+from . import GX_TREE_GAS, GasState, ParticleSet
 from .sn import U_PER_K, SPHConfig, Surrogate
 
 PC_PER_KPC = 1000.0
+_SNAP_F64 = ("x", "y", "z", "vx", "vy", "vz", "m", "u")
 
 
 @dataclass
 class Pending:
     due: int
-    ids: object        # device int64 [m] particle IDs to overwrite
-    new: dict          # device FP64 arrays x, y, z, vx, vy, vz, u (galaxy frame)
+    ids: object = None      # device int64 [m] particle IDs to overwrite
+    new: dict = None        # device FP64 arrays x, y, z, vx, vy, vz, u (galaxy frame)
+    done: object = None     # CUDA event on the surrogate's stream (asynchronous mode)
+    ready: threading.Event = field(default_factory=threading.Event)
+    error: BaseException = None
 
 
 class SNCoupling:
     def __init__(self, step, surrogate: Surrogate, n_sites: int = 64, delay: int = 50,
                  side_pc: float = 60.0, seed: int = 5, r_max: float = 15.0, z_max: float = 0.3,
-                 valid_sigma: float = 8.0, cfg: SPHConfig = SPHConfig(), star_type: int = 1):
+                 valid_sigma: float = 8.0, cfg: SPHConfig = SPHConfig(), star_type: int = 1,
+                 asynchronous: bool = False):
         import torch
         self.torch = torch
         self.step, self.sur = step, surrogate
@@ -67,7 +86,39 @@ class SNCoupling:
         self.queue = deque()
         self.stats = {"regions": 0, "replaced_regions": 0, "fallback_regions": 0,
                       "particles_replaced": 0, "missing_ids": 0}
+        self._lock = threading.Lock()
+        self.asynchronous = asynchronous
+        self.sur_ms = []          # surrogate pipeline time on its stream, per hand-over
+        if asynchronous:
+            self.main_stream = torch.cuda.current_stream(p.x.device)
+            self.sur_stream = surrogate.eng.stream
+            if self.sur_stream is None or self.sur_stream.cuda_stream == self.main_stream.cuda_stream:
+                raise ValueError("the asynchronous mode needs the surrogate engine on its own stream")
+            dev = p.x.device
+            ng = step.ng
+            # two snapshot slots: the galaxy writes one while the worker may
+            # still read the other
+            self._slots = [dict({a: torch.empty(ng, dtype=torch.float64, device=dev)
+                                 for a in _SNAP_F64},
+                                H=torch.empty(ng, dtype=torch.float32, device=dev),
+                                id=torch.empty(ng, dtype=torch.int64, device=dev),
+                                released=None, released_flag=threading.Event())
+                           for _ in range(2)]
+            for s in self._slots:
+                s["released_flag"].set()
+            self._next_slot = 0
+            # start gates: an event after each later gravity call; the work of
+            # a hand-over waits for the next one, so that it overlaps the
+            # latency-bound SPH and tree phases instead of the compute-bound
+            # gravity kernel
+            self._gates = []
+            self._gate_cv = threading.Condition()
+            step.after_gravity.append(self._publish_gate)
+            self._jobs = _queue.Queue()
+            self._worker = threading.Thread(target=self._work, name="sn-surrogate", daemon=True)
+            self._worker.start()
 
+    # ---- sites ----------------------------------------------------------------
     def sites(self, step_index: int):
         """This step's SN sites: candidate stars in a seeded random order,
         each kept unless its box would overlap the box of a site already kept
@@ -106,24 +157,36 @@ class SNCoupling:
         return self.eng.sn_check(pred, K, sur.grid, mo - self.valid_sigma * so,
                                  mo + self.valid_sigma * so)
 
-    def launch(self, step_index: int):
-        """Hand this step's regions to the surrogate; queue their replacement."""
+    # ---- the surrogate pipeline ----------------------------------------------------
+    def _pipeline(self, snap, centers, step_index, item, on_gathered=None):
+        """Regions of one hand-over from the gas state `snap` (dict of device
+        arrays x .. u, H, id over the gas), on the surrogate engine's stream;
+        fills item.ids / item.new.  on_gathered() is called once the snapshot
+        has been read for the last time (after the gather)."""
         torch, eng, st = self.torch, self.eng, self.step
-        gas, dev = st.gas, st.p.x.device
-        centers = self.sites(step_index)
+        dev = centers.device
         K = int(centers.shape[0])
+        gas = ParticleSet(x=snap["x"], y=snap["y"], z=snap["z"], vx=snap["vx"], vy=snap["vy"],
+                          vz=snap["vz"], m=snap["m"])
         half_kpc = 0.5 * self.side / PC_PER_KPC
         off, idx, tot = eng.sn_extract(gas, centers, half_kpc, gas.n)
-        self.stats["regions"] += K
+        f64 = dict(dtype=torch.float64, device=dev)
+        delta = {"regions": K, "replaced_regions": 0, "fallback_regions": 0}
         if tot == 0:
-            return
+            if on_gathered:
+                on_gathered()
+            item.ids = torch.zeros(0, dtype=torch.int64, device=dev)
+            item.new = {a: torch.zeros(0, **f64) for a in ("x", "y", "z", "vx", "vy", "vz", "u")}
+            return delta
         offh = off.cpu().numpy()
         n_max = int((offh[1:] - offh[:-1]).max())
-        f64 = dict(dtype=torch.float64, device=dev)
         box = {a: torch.empty(tot, **f64) for a in ("x", "y", "z", "vx", "vy", "vz", "m", "u")}
         box["H"] = torch.empty(tot, dtype=torch.float32, device=dev)
         lat = self.lattice[:K].contiguous()
-        eng.sn_gather(gas, st.g.u, st.g.H, off, idx, n_max, centers, lat, PC_PER_KPC, box)
+        eng.sn_gather(gas, snap["u"], snap["H"], off, idx, n_max, centers, lat, PC_PER_KPC, box)
+        ids = snap["id"].index_select(0, idx.long())
+        if on_gathered:
+            on_gathered()
         q = ParticleSet(x=box["x"], y=box["y"], z=box["z"], vx=box["vx"], vy=box["vy"],
                         vz=box["vz"], m=box["m"],
                         eps2=torch.zeros(tot, dtype=torch.float32, device=dev))
@@ -139,13 +202,14 @@ class SNCoupling:
         self.sur.infer(xin, K, pred)
         ok = self._valid(pred, K)
         new = {a: torch.empty(tot, **f64) for a in ("x", "y", "z", "vx", "vy", "vz", "u")}
-        uni = torch.rand(tot * 4, dtype=torch.float32, device=dev)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(1_000_003 * self.seed + step_index)
+        uni = torch.rand(tot * 4, dtype=torch.float32, device=dev, generator=gen)
         eng.sn_resample(pred, lat, self.sur.grid, self.side, off, n_max, uni, U_PER_K,
                         *(new[a] for a in ("x", "y", "z", "vx", "vy", "vz", "u")))
         delay_time = self.delay * st.cfg.dt
         eng.sn_unframe(off, n_max, lat, centers, amb, delay_time, PC_PER_KPC,
                        new["x"], new["y"], new["z"])
-        ids = st.p.id[st.gas_offset:].index_select(0, idx.long())
         if not ok.all():
             # fallback: drop the regions the network cannot be trusted on
             keep = np.concatenate([np.arange(offh[c], offh[c + 1]) for c in range(K) if ok[c]]
@@ -153,21 +217,130 @@ class SNCoupling:
             kt = torch.as_tensor(keep, dtype=torch.long, device=dev)
             ids = ids.index_select(0, kt)
             new = {a: v.index_select(0, kt) for a, v in new.items()}
-        self.stats["fallback_regions"] += int((~ok).sum())
-        self.stats["replaced_regions"] += int(ok.sum())
-        self.queue.append(Pending(step_index + self.delay, ids.contiguous(), new))
+        item.ids, item.new = ids.contiguous(), new
+        delta["fallback_regions"] = int((~ok).sum())
+        delta["replaced_regions"] = int(ok.sum())
+        return delta
+
+    def _count(self, delta):
+        with self._lock:
+            for k, v in delta.items():
+                self.stats[k] += v
+
+    # ---- hand-over and replacement ------------------------------------------
+    def launch(self, step_index: int):
+        """Hand this step's regions to the surrogate; queue their replacement."""
+        st = self.step
+        centers = self.sites(step_index)
+        item = Pending(step_index + self.delay)
+        if not self.asynchronous:
+            snap = {a: getattr(st.gas, a) for a in ("x", "y", "z", "vx", "vy", "vz", "m")}
+            snap.update(u=st.g.u, H=st.g.H, id=st.p.id[st.gas_offset:])
+            self._count(self._pipeline(snap, centers, step_index, item))
+            item.ready.set()
+        else:
+            torch = self.torch
+            slot = self._slots[self._next_slot]
+            self._next_slot ^= 1
+            # the worker must be done reading this slot (two hand-overs ago)
+            slot["released_flag"].wait()
+            if slot["released"] is not None:
+                self.main_stream.wait_event(slot["released"])
+            for a in ("x", "y", "z", "vx", "vy", "vz", "m"):
+                slot[a].copy_(getattr(st.gas, a))
+            slot["u"].copy_(st.g.u)
+            slot["H"].copy_(st.g.H)
+            slot["id"].copy_(st.p.id[st.gas_offset:])
+            taken = torch.cuda.Event()
+            taken.record(self.main_stream)
+            slot["released_flag"].clear()
+            with self._gate_cv:
+                need = len(self._gates) + 1
+            self._jobs.put((slot, taken, need, centers, step_index, item))
+        self.queue.append(item)
+
+    def _publish_gate(self):
+        ev = self.torch.cuda.Event()
+        ev.record(self.main_stream)
+        with self._gate_cv:
+            self._gates.append(ev)
+            self._gate_cv.notify_all()
+
+    def _gate(self, need):
+        with self._gate_cv:
+            while len(self._gates) < need:
+                self._gate_cv.wait()
+            return self._gates[need - 1]
+
+    def _work(self):
+        torch = self.torch
+        while True:
+            job = self._jobs.get()
+            if job is None:
+                return
+            slot, taken, need, centers, step_index, item = job
+            try:
+                gate = self._gate(need)
+                with torch.cuda.stream(self.sur_stream):
+                    self.sur_stream.wait_event(taken)
+                    self.sur_stream.wait_event(gate)
+                    t0 = torch.cuda.Event(enable_timing=True)
+                    t0.record(self.sur_stream)
+
+                    def gathered():
+                        ev = torch.cuda.Event()
+                        ev.record(self.sur_stream)
+                        slot["released"] = ev
+                        slot["released_flag"].set()
+
+                    delta = self._pipeline(slot, centers, step_index, item, on_gathered=gathered)
+                    t1 = torch.cuda.Event(enable_timing=True)
+                    t1.record(self.sur_stream)
+                    item.done = t1
+                    t1.synchronize()
+                    self.sur_ms.append(t0.elapsed_time(t1))
+                    self._count(delta)
+            except BaseException as e:  # handed to the main thread at apply time
+                item.error = e
+                slot["released"] = None
+                slot["released_flag"].set()
+            item.ready.set()
 
     def apply_due(self, step_index: int):
-        """Write every queued result that is due at this step."""
+        """Write every queued result that is due at this step (on the galaxy's
+        stream, with the galaxy's engine)."""
         st = self.step
         while self.queue and self.queue[0].due <= step_index:
             item = self.queue.popleft()
+            item.ready.wait()
+            if item.error is not None:
+                raise RuntimeError("surrogate hand-over failed") from item.error
+            if self.asynchronous and item.done is not None:
+                self.main_stream.wait_event(item.done)
+                for t in [item.ids, *item.new.values()]:
+                    t.record_stream(self.main_stream)
             m = int(item.ids.shape[0])
             if m == 0:
                 continue
             n = item.new
-            miss = self.eng.sn_replace(st.p.id, st.p.n, st.p.x, st.p.y, st.p.z, st.p.vx, st.p.vy,
-                                       st.p.vz, st.g.u, st.gas_offset, st.g.H64, item.ids,
-                                       n["x"], n["y"], n["z"], n["vx"], n["vy"], n["vz"], n["u"])
-            self.stats["particles_replaced"] += m - miss
-            self.stats["missing_ids"] += miss
+            miss = st.eng.sn_replace(st.p.id, st.p.n, st.p.x, st.p.y, st.p.z, st.p.vx, st.p.vy,
+                                     st.p.vz, st.g.u, st.gas_offset, st.g.H64, item.ids,
+                                     n["x"], n["y"], n["z"], n["vx"], n["vy"], n["vz"], n["u"])
+            with self._lock:
+                self.stats["particles_replaced"] += m - miss
+                self.stats["missing_ids"] += miss
+
+    def drain(self):
+        """Wait until every hand-over made so far has its result (opening the
+        start gate now for work still waiting for the next gravity call)."""
+        if self.asynchronous:
+            self._publish_gate()
+        for item in list(self.queue):
+            item.ready.wait()
+
+    def close(self):
+        if self.asynchronous and self._worker.is_alive():
+            self._publish_gate()
+            self._jobs.put(None)
+            self._worker.join()
+            self.step.after_gravity.remove(self._publish_gate)

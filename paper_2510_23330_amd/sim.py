@@ -49,6 +49,10 @@ class GalaxyStep:
 
     def __post_init__(self):
         import torch
+        # callables run right after each gravity call is enqueued (the
+        # asynchronous surrogate uses it to start in the shadow of the SPH
+        # and tree phases rather than beside the gravity kernel)
+        self.after_gravity = []
         n, o = self.p.n, self.gas_offset
         ng = n - o
         dev = self.p.x.device
@@ -71,6 +75,8 @@ class GalaxyStep:
         s["tree_all"] = self.eng.tree_build(self.p, GX_TREE_ALL, c.n_leaf, c.n_group)
         s["gravity"] = self.eng.gravity_forces(self.p, c.G, c.theta, GX_QUAD if c.quad else 0,
                                                self.ax, self.ay, self.az, self.pot)
+        for f in self.after_gravity:
+            f()
         if self.ng == 0:
             return
         s["tree_gas"] = self.eng.tree_build(self.gas, GX_TREE_GAS, c.sph_leaf, c.sph_group)

@@ -189,6 +189,37 @@ def evaluate_mse(sur: Surrogate, Xt, Yt):
     return tot / n
 
 
+def bench_training(a):
+    """Training throughput of the network alone (random standardized inputs
+    and targets; forward, MSE, backward, Adam per step)."""
+    import torch
+    from .unet import flops_forward
+    eng = Engine(0)
+    sur = Surrogate(eng, batch=a.batch, base=a.base, levels=a.levels, grid=a.grid, seed=1)
+    V = a.grid ** 3
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    xb = torch.zeros(a.batch * V * 8, dtype=torch.float32, device="cuda")
+    xb.view(-1, 8)[:, :5] = torch.randn(a.batch * V, 5, device="cuda", generator=g)
+    xb = xb.to(torch.bfloat16)
+    yb = torch.randn(a.batch * V * 5, device="cuda", generator=g)
+    for _ in range(3):
+        sur.net.train_step(xb, yb, lr=a.lr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.bench_steps):
+        sur.net.train_step(xb, yb, lr=a.lr)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.bench_steps
+    fl = 3 * flops_forward(a.grid, a.base, a.levels) * a.batch
+    out = {"batch": a.batch, "grid": a.grid, "ms_per_step": dt * 1e3,
+           "samples_per_s": a.batch / dt, "tflops_3x_forward": fl / dt / 1e12,
+           "frac_bf16_peak": fl / dt / 2.5e15}
+    print(json.dumps(out), flush=True)
+    eng.close()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--n-train", type=int, default=256)
@@ -208,8 +239,12 @@ def main(argv=None):
     ap.add_argument("--out", default="sn_out")
     ap.add_argument("--export", default=None,
                     help="also write the inference weights (BF16) to this file")
+    ap.add_argument("--bench-steps", type=int, default=0,
+                    help="only time this many training steps on random data and exit")
     a = ap.parse_args(argv)
     import torch
+    if a.bench_steps > 0:
+        return bench_training(a)
     os.makedirs(a.out, exist_ok=True)
     log = _log_fn(os.path.join(a.out, "log.txt"))
     eng = Engine(0)
