@@ -438,10 +438,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "disk galaxy 16M: 8e6 disk stars, 6.4e6 NFW halo, 1.6e6 gas disk; "
-                               "theta 0.5 + quadrupole, n_leaf 16, groups <= 256; SPH Wendland C4, "
-                               "64 neighbours, groups <= 64; dt 2000 yr; 64 SN regions per step "
-                               "to the surrogate",
+        "config": {"workload": f"disk galaxy {args.n / 1e6:g}M: 50 % disk stars, 40 % NFW halo, "
+                               f"10 % gas disk; theta 0.5 + quadrupole, n_leaf {args.n_leaf}, "
+                               f"groups <= {args.n_group}; SPH Wendland C4, 64 neighbours, gas "
+                               f"leaves {args.sph_leaf}, groups <= {args.sph_group}; dt 2000 yr; "
+                               f"{args.sn_sites} SN regions per step to the surrogate",
                    "n_particles": args.n, "seed": args.seed, "particle_order": args.ic_order,
                    "n_group": args.n_group, "n_leaf": args.n_leaf, "sph_group": args.sph_group,
                    "sph_leaf": args.sph_leaf},

@@ -19,6 +19,19 @@ resample   the grid-to-particle mapping of Sec. 3.3 read as exact sampling of
            the piecewise-constant density: the voxel by inverse CDF of
            10^(log10 rho_v), the position uniform inside it, T and v of that
            voxel, as many particles as entered (mass conserved).
+resample_gibbs
+           the same mapping by Gibbs sampling (the Markov-chain method Sec.
+           3.3 names): each particle's chain starts in the voxel of the
+           particle that entered, and each sweep redraws the x index from the
+           density along the line through the current (y, z), then y given
+           (x, z), then z given (x, y), each by the inverse CDF of the line's
+           weights 10^(log10 rho); then the position uniform inside the final
+           voxel and its T and v.
+encode8    the eight-cube input encoding of Sec. 3.3: log10 rho, log10 T, and
+           per velocity component a positive and a negative cube holding the
+           logarithm of the magnitude, log10(v0 + max(+-v, 0)) (the offset v0
+           keeps the logarithm finite where a cube is empty).
+decode8    its inverse, v = 10^(c+) - 10^(c-) (v0 cancels).
 check      trust flags of a prediction: every value finite and inside its
            channel's [lo, hi] (compared in FP32).
 replace    Sec. 3.2 step 4: the new state written over the particles with the
@@ -124,6 +137,90 @@ def resample(pred, centers, grid, side, counts, uniforms, T_to_u):
             out["voxel"].append(v)
             j += 1
     return {k: np.asarray(v) for k, v in out.items()}
+
+
+def line_draw(w, u):
+    """Inverse-CDF draw along one line of voxel weights w (FP64): the first
+    index whose inclusive prefix sum exceeds u * (the line's total), the
+    prefix sums taken in index order; the last index if none does."""
+    C = np.cumsum(np.asarray(w, np.float64))
+    k = int(np.searchsorted(C, float(u) * C[-1], side="right"))
+    return min(k, len(C) - 1)
+
+
+def resample_gibbs(pred, centers, grid, side, counts, start, sweeps, uniforms, T_to_u,
+                   sel=None):
+    """pred [K, grid^3, 5] physical channels (voxel order z-major, x fastest);
+    start [total, 3] positions of the particles that entered, in the frame of
+    `centers`; uniforms [total, 3 * sweeps + 3] in [0, 1): uniforms[j, 3s],
+    [3s + 1], [3s + 2] drive the x, y and z draws of sweep s, the last three
+    the position inside the final voxel.  The chain of particle j starts at
+    the voxel holding start[j] (indices clamped to the grid).  sel: the
+    particles to compute (default all).  Returns dict of x, y, z, vx, vy, vz,
+    u and the final voxel, for the particles of sel in order."""
+    pred = np.asarray(pred, np.float64)
+    K = pred.shape[0]
+    start = np.asarray(start, np.float64).reshape(-1, 3)
+    nu = 3 * sweeps + 3
+    uniforms = np.asarray(uniforms, np.float64).reshape(-1, nu)
+    centers = np.asarray(centers, np.float64).reshape(-1, 3)
+    counts = np.asarray(counts, np.int64)
+    off = np.concatenate([[0], np.cumsum(counts)])
+    total = int(off[-1])
+    sel = np.arange(total) if sel is None else np.asarray(sel, np.int64)
+    cube_of = np.searchsorted(off, sel, side="right") - 1
+    half = 0.5 * side
+    dv = side / grid
+    # weights rho_v per cube as [z, y, x] arrays
+    rho = [(10.0 ** pred[c, :, 0]).reshape(grid, grid, grid) for c in range(K)]
+    out = {k: [] for k in ("x", "y", "z", "vx", "vy", "vz", "u", "voxel")}
+    for j, c in zip(sel, cube_of):
+        lo = centers[c] - half
+        ijk = [min(max(int(np.floor((start[j, a] - lo[a]) / dv)), 0), grid - 1)
+               for a in range(3)]
+        X, Y, Z = ijk
+        r = rho[c]
+        for s in range(sweeps):
+            X = line_draw(r[Z, Y, :], uniforms[j, 3 * s])
+            Y = line_draw(r[Z, :, X], uniforms[j, 3 * s + 1])
+            Z = line_draw(r[:, Y, X], uniforms[j, 3 * s + 2])
+        v = (Z * grid + Y) * grid + X
+        ub = uniforms[j, 3 * sweeps:]
+        out["x"].append(lo[0] + (X + ub[0]) * dv)
+        out["y"].append(lo[1] + (Y + ub[1]) * dv)
+        out["z"].append(lo[2] + (Z + ub[2]) * dv)
+        out["vx"].append(pred[c, v, 2])
+        out["vy"].append(pred[c, v, 3])
+        out["vz"].append(pred[c, v, 4])
+        out["u"].append(10.0 ** pred[c, v, 1] * T_to_u)
+        out["voxel"].append(v)
+    return {k: np.asarray(v) for k, v in out.items()}
+
+
+def encode8(phys, v0):
+    """phys [..., 5] = (log10 rho, log10 T, vx, vy, vz) -> [..., 8] =
+    (log10 rho, log10 T, log10(v0 + max(vx, 0)), log10(v0 + max(-vx, 0)),
+    the same for vy, then vz)."""
+    phys = np.asarray(phys, np.float64)
+    out = np.empty(phys.shape[:-1] + (8,))
+    out[..., 0] = phys[..., 0]
+    out[..., 1] = phys[..., 1]
+    for a in range(3):
+        v = phys[..., 2 + a]
+        out[..., 2 + 2 * a] = np.log10(v0 + np.maximum(v, 0.0))
+        out[..., 3 + 2 * a] = np.log10(v0 + np.maximum(-v, 0.0))
+    return out
+
+
+def decode8(enc):
+    """[..., 8] -> [..., 5]: log10 rho, log10 T kept; v = 10^(c+) - 10^(c-)."""
+    enc = np.asarray(enc, np.float64)
+    out = np.empty(enc.shape[:-1] + (5,))
+    out[..., 0] = enc[..., 0]
+    out[..., 1] = enc[..., 1]
+    for a in range(3):
+        out[..., 2 + a] = 10.0 ** enc[..., 2 + 2 * a] - 10.0 ** enc[..., 3 + 2 * a]
+    return out
 
 
 def check(pred, lo, hi):
