@@ -97,6 +97,9 @@ def parse():
     ap.add_argument("--sn-mode", choices=("async", "sync"), default="async",
                     help="surrogate hand-over on its own stream in a worker thread (default), "
                          "or in series on the galaxy's stream")
+    ap.add_argument("--resampler", choices=("cdf", "gibbs"), default="cdf",
+                    help="grid-to-particle mapping of the surrogate: inverse CDF or Gibbs chains")
+    ap.add_argument("--sweeps", type=int, default=4, help="Gibbs sweeps per particle")
     ap.add_argument("--n-group", type=int, default=256, help="gravity group size n_g")
     ap.add_argument("--n-leaf", type=int, default=16, help="gravity tree leaf size")
     ap.add_argument("--sph-group", type=int, default=64, help="SPH group size")
@@ -198,12 +201,15 @@ def cpu_baseline(d, n_groups_sample, seed):
                        f"{dt:.2f} s; oracle tree build {build_s:.1f} s not included)")}
 
 
-def load_surrogate(eng, batch, weights):
+def load_surrogate(eng, batch, weights, resampler="cdf", sweeps=4):
     """The network for inference: the trained weights when the file exists,
     else a random initialisation (then only its cost is meaningful)."""
     from paper_2510_23330_amd.sn import Surrogate
-    sur = Surrogate(eng, batch=batch, seed=0, train=False)
-    if weights and os.path.exists(weights):
+    have = bool(weights) and os.path.exists(weights)
+    enc = Surrogate.file_encoding(weights) if have else "5ch"
+    sur = Surrogate(eng, batch=batch, seed=0, train=False, encoding=enc,
+                    resampler=resampler, sweeps=sweeps)
+    if have:
         sur.load(weights)
         return sur, os.path.relpath(weights, ROOT)
     return sur, None
@@ -214,7 +220,7 @@ def _abs_err_stats(pred, ref):
     return {"median": float(np.median(d)), "p90": float(np.percentile(d, 90))}
 
 
-def sn_region_leg(eng, n_cubes, infer_batch, weights, seed0=5000):
+def sn_region_leg(eng, n_cubes, infer_batch, weights, resampler="cdf", sweeps=4, seed0=5000):
     """Per SN region: plain small-dt SPH to 0.1 Myr against the surrogate path
     (extract, ambient, gas tree, voxelize, infer, resample) on the same cubes.
     Plain SPH runs twice: with one shared Courant step for all cubes (what a
@@ -231,7 +237,7 @@ def sn_region_leg(eng, n_cubes, infer_batch, weights, seed0=5000):
     _, _, info_sh = generate(eng, seeds)
     x0, y, info = generate(eng, seeds, per_cube=True)
     cube_steps = np.asarray(info["cube_steps"])
-    sur, wfile = load_surrogate(eng, 64, weights)
+    sur, wfile = load_surrogate(eng, 64, weights, resampler, sweeps)
     sb = SNBatch(eng, ics.sn_batch(seeds))
     sb.voxelize()
     sur.regions(sb.p, sb.g, sb.centers, cap=sb.n)         # warm-up
@@ -251,7 +257,9 @@ def sn_region_leg(eng, n_cubes, infer_batch, weights, seed0=5000):
            "surrogate_s": sur_s, "surrogate_ms_per_region": sur_s / n_cubes * 1e3,
            "speedup_vs_per_cube": info["seconds"] / sur_s,
            "speedup_vs_shared_step": info_sh["seconds"] / sur_s,
-           "weights": wfile or "random init (timing only)"}
+           "weights": wfile or "random init (timing only)",
+           "encoding": sur.encoding,
+           "resampler": sur.resampler + (f" ({sur.sweeps} sweeps)" if sur.resampler == "gibbs" else "")}
     if wfile:
         V = GRID ** 3
         P = pred.view(n_cubes, V, 5).cpu().numpy().astype(np.float64)
@@ -309,7 +317,7 @@ def main():
         from paper_2510_23330_amd.coupling import SNCoupling
         asyn = args.sn_mode == "async"
         sur_eng = gx.Engine(0, stream=torch.cuda.Stream() if asyn else None)
-        sur, wfile = load_surrogate(sur_eng, 64, args.weights)
+        sur, wfile = load_surrogate(sur_eng, 64, args.weights, args.resampler, args.sweeps)
         coupling = SNCoupling(sim, sur, n_sites=args.sn_sites, delay=50, asynchronous=asyn)
     torch.cuda.synchronize()
     log("[bench] set-up done; initial forces (cold kernel sizes) ...")
@@ -458,7 +466,8 @@ def main():
         "sn_coupling": None if coupling is None else dict(
             coupling.stats, sites_per_step=args.sn_sites, delay_steps=50, mode=args.sn_mode,
             handovers_applied_after_timing=applied_at_end,
-            weights=wfile or "random init (timing only; every region falls back)"),
+            weights=wfile or "random init (timing only; every region falls back)",
+            encoding=coupling.sur.encoding, resampler=coupling.sur.resampler),
         "sn_async": sn_async,
         "gravity_kernel_interactions_per_s": inter_step / kernel_s,
         "sph": {"density_pair_evals_per_step": n_dens_eval / args.steps,
@@ -493,7 +502,8 @@ def main():
         log(f"[bench] force errors {time.perf_counter() - t0:.1f} s")
     if args.sn_cubes > 0:
         t0 = time.perf_counter()
-        out["sn_region"] = sn_region_leg(eng, args.sn_cubes, args.sn_infer_batch, args.weights)
+        out["sn_region"] = sn_region_leg(eng, args.sn_cubes, args.sn_infer_batch, args.weights,
+                                         args.resampler, args.sweeps)
         log(f"[bench] SN region leg {time.perf_counter() - t0:.1f} s")
         if sn_ms or sn_async:
             # 0.1 Myr of the disk with 64 SNe per step: 50 global steps of

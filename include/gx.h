@@ -378,6 +378,46 @@ int gx_sn_resample(gx_ctx* ctx, const float* pred, int k, int grid, double side,
                    double* vx, double* vy, double* vz, double* u);
 
 /*
+ * gx_sn_resample_gibbs -- grid-to-particle mapping by Gibbs sampling, the
+ * Markov-chain method Sec. 3.3 names.  Particle j of cube c (CSR out_off,
+ * as in gx_sn_resample) runs a chain over voxel indices (X, Y, Z) that starts
+ * at the voxel holding (x0, y0, z0)[j] (floor((p - (centre - side/2)) /
+ * (side/grid)) per axis, clamped to the grid); each of `sweeps` sweeps draws
+ * X from the weights 10^(log10 rho) along the line through the current
+ * (Y, Z), then Y given (X, Z), then Z given (X, Y): the first index whose
+ * inclusive prefix sum (FP64, in index order) exceeds u * (the line total),
+ * the last index if none does.  The position is then uniform in the final
+ * voxel; T and velocity are that voxel's; u = T * T_to_u.  sweeps = 0 keeps
+ * the start voxel.
+ * pred        device float [k][grid^3][5] physical channels
+ * x0, y0, z0  device double [total] start positions, frame of `centers`
+ * uniforms    device float [total][3 * sweeps + 3] in [0, 1): entries 3s,
+ *             3s+1, 3s+2 drive the x, y, z draws of sweep s, the last three
+ *             the position inside the voxel
+ * outputs     device double [total]; n_out_max = largest per-cube count.
+ * Scratch: 3 k grid^3 doubles (the line sums) in the context.
+ */
+int gx_sn_resample_gibbs(gx_ctx* ctx, const float* pred, int k, int grid, double side,
+                         const double* centers, const int32_t* out_off, int64_t n_out_max,
+                         const double* x0, const double* y0, const double* z0, int sweeps,
+                         const float* uniforms, double T_to_u, double* x, double* y, double* z,
+                         double* vx, double* vy, double* vz, double* u);
+
+/*
+ * gx_sn_encode8 -- the eight input cubes of Sec. 3.3: from physical rows
+ * (log10 rho, log10 T, vx, vy, vz) of in_stride floats, out8 [V][8] =
+ * (log10 rho, log10 T, log10(v0 + max(vx, 0)), log10(v0 + max(-vx, 0)), the
+ * same for vy and vz).  The paper takes the logarithm of each sign's
+ * magnitude; the offset v0 > 0 (same unit as v) keeps it finite where a
+ * cube is empty.  FP64 arithmetic, FP32 storage.  Device pointers.
+ * gx_sn_decode8 -- the inverse on rows of in_stride >= 8 floats: out5 [V][5]
+ * with v = 10^(c+) - 10^(c-) per component (v0 cancels).
+ */
+int gx_sn_encode8(gx_ctx* ctx, int64_t V, const float* in5, int in_stride, double v0,
+                  float* out8);
+int gx_sn_decode8(gx_ctx* ctx, int64_t V, const float* in8, int in_stride, float* out5);
+
+/*
  * gx_sn_check -- trust check of a prediction before replacement (an addition
  * to Sec. 3.2 step 4: a region whose prediction leaves the training targets'
  * range keeps the plain integrator).  ok[c] = 1 when every value of cube c is

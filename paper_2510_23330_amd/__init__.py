@@ -358,6 +358,32 @@ class Engine:
             _ptr(uniforms, torch.float32), float(T_to_u), *(_ptr(t, torch.float64) for t in
                                                               (x, y, z, vx, vy, vz, u))))
 
+    def sn_resample_gibbs(self, pred, centers, grid, side, out_off, n_out_max, x0, y0, z0,
+                          sweeps, uniforms, T_to_u, x, y, z, vx, vy, vz, u):
+        """Gibbs resampling: chains start in the voxels of (x0, y0, z0);
+        uniforms float [total * (3 * sweeps + 3)]."""
+        torch = _torch()
+        self._check(self.lib.gx_sn_resample_gibbs(
+            self.ctx, _ptr(pred, torch.float32), int(centers.shape[0]), int(grid), float(side),
+            _ptr(centers, torch.float64), _ptr(out_off, torch.int32), int(n_out_max),
+            _ptr(x0, torch.float64), _ptr(y0, torch.float64), _ptr(z0, torch.float64),
+            int(sweeps), _ptr(uniforms, torch.float32), float(T_to_u),
+            *(_ptr(t, torch.float64) for t in (x, y, z, vx, vy, vz, u))))
+
+    def sn_encode8(self, in5, V, v0, out8, in_stride=5):
+        """Eight-cube encoding of V physical rows into out8 float [V * 8]."""
+        torch = _torch()
+        self._check(self.lib.gx_sn_encode8(self.ctx, int(V), _ptr(in5, torch.float32),
+                                           int(in_stride), float(v0), _ptr(out8, torch.float32)))
+        return out8
+
+    def sn_decode8(self, in8, V, out5, in_stride=8):
+        """Physical rows (log10 rho, log10 T, v) from eight-cube rows."""
+        torch = _torch()
+        self._check(self.lib.gx_sn_decode8(self.ctx, int(V), _ptr(in8, torch.float32),
+                                           int(in_stride), _ptr(out5, torch.float32)))
+        return out5
+
     def sn_check(self, pred, k, grid, lo, hi):
         """Per-cube trust flags (numpy bool [k]) of a prediction: every value
         finite and inside [lo, hi] of its channel (lo, hi: 5 floats)."""

@@ -81,6 +81,10 @@ SIGNATURES = {
     "gx_sn_voxelize": (I32, [P, C.POINTER(GxParticles), P, P, P, I32, D, I32, D, P, P, P, P,
                              I32, P]),
     "gx_sn_resample": (I32, [P, P, I32, I32, D, P, P, I64, P, D, P, P, P, P, P, P, P]),
+    "gx_sn_resample_gibbs": (I32, [P, P, I32, I32, D, P, P, I64, P, P, P, I32, P, D,
+                                   P, P, P, P, P, P, P]),
+    "gx_sn_encode8": (I32, [P, I64, P, I32, D, P]),
+    "gx_sn_decode8": (I32, [P, I64, P, I32, P]),
     "gx_sn_check": (I32, [P, P, I32, I32, P, P, P]),
     "gx_sn_check_noalloc": (I32, [P, P, I32, I32, P, P, P]),
     "gx_sn_replace": (I32, [P, I64, P, I64, P, P, P, P, P, P, P, I64, P, I64, P, P, P, P, P, P, P,

@@ -151,11 +151,8 @@ class SNCoupling:
     def _valid(self, pred, K):
         """Per-region check (gx_sn_check) that every predicted channel stays
         within valid_sigma standard deviations of the training targets."""
-        sur = self.sur
-        mo = sur.mean_out.cpu().numpy().astype(np.float64)
-        so = sur.std_out.cpu().numpy().astype(np.float64)
-        return self.eng.sn_check(pred, K, sur.grid, mo - self.valid_sigma * so,
-                                 mo + self.valid_sigma * so)
+        lo, hi = self.sur.check_bounds(self.valid_sigma)
+        return self.eng.sn_check(pred, K, self.sur.grid, lo, hi)
 
     # ---- the surrogate pipeline ----------------------------------------------------
     def _pipeline(self, snap, centers, step_index, item, on_gathered=None):
@@ -195,18 +192,17 @@ class SNCoupling:
         g = GasState.zeros(tot, u=box["u"], device=dev)
         g.H.copy_(box["H"])
         eng.tree_build(q, GX_TREE_GAS, self.cfg.n_leaf, self.cfg.n_group)
-        xin = torch.empty(K * self.sur.V * 8, dtype=torch.bfloat16, device=dev)
-        eng.sn_voxelize(q, g.u, g.H, lat, self.side, self.sur.grid, 1.0 / U_PER_K, amb,
-                        mean=self.sur.mean_in, std=self.sur.std_in, out_bf16=xin, cpad=8)
+        xin = self.sur.inputs(q, g, lat, self.side, amb, K)
         pred = torch.empty(K * self.sur.V * 5, dtype=torch.float32, device=dev)
         self.sur.infer(xin, K, pred)
         ok = self._valid(pred, K)
         new = {a: torch.empty(tot, **f64) for a in ("x", "y", "z", "vx", "vy", "vz", "u")}
         gen = torch.Generator(device=dev)
         gen.manual_seed(1_000_003 * self.seed + step_index)
-        uni = torch.rand(tot * 4, dtype=torch.float32, device=dev, generator=gen)
-        eng.sn_resample(pred, lat, self.sur.grid, self.side, off, n_max, uni, U_PER_K,
-                        *(new[a] for a in ("x", "y", "z", "vx", "vy", "vz", "u")))
+        uni = torch.rand(tot * self.sur.n_uniforms, dtype=torch.float32, device=dev,
+                         generator=gen)
+        self.sur.resample(pred, lat, self.side, off, n_max, uni, (box["x"], box["y"], box["z"]),
+                          new)
         delay_time = self.delay * st.cfg.dt
         eng.sn_unframe(off, n_max, lat, centers, amb, delay_time, PC_PER_KPC,
                        new["x"], new["y"], new["z"])

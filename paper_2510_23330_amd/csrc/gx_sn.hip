@@ -654,6 +654,194 @@ extern "C" int gx_sn_resample(gx_ctx* ctx, const float* pred, int k, int grid, d
 }
 
 // ---------------------------------------------------------------------------
+// Gibbs resampling: a Markov chain per particle over the voxel indices.  The
+// chain starts in the voxel of the particle that entered; each sweep redraws
+// the x index from the weights 10^(log10 rho) along the line through the
+// current (y, z), then y given (x, z), then z given (x, y).  Every line's
+// inclusive prefix sums are formed once per call, sequentially in index order
+// in FP64 (one thread per line), so each draw is a bisection of 64 entries
+// and takes the same decision as a sequential sum written out plainly.
+// ---------------------------------------------------------------------------
+// Line prefix sums along `axis` (0: x, stride 1; 1: y, stride grid; 2: z,
+// stride grid^2), stored at each voxel's own index.  Grid (lines / 256, k).
+__global__ __launch_bounds__(256) void k_line_cdf(const float* __restrict__ pred, int grid,
+                                                  int axis, double* __restrict__ cdf) {
+    const int c = blockIdx.y;
+    const int L = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g2 = grid * grid;
+    if (L >= g2) return;
+    const int64_t nvox = (int64_t)g2 * grid;
+    int base, stride;
+    if (axis == 0) {         // L = z * grid + y
+        base = L * grid;
+        stride = 1;
+    } else if (axis == 1) {  // L = z * grid + x
+        base = (L / grid) * g2 + (L % grid);
+        stride = grid;
+    } else {                 // L = y * grid + x
+        base = L;
+        stride = g2;
+    }
+    const float* p = pred + (int64_t)c * nvox * 5;
+    double* out = cdf + (int64_t)c * nvox;
+    double run = 0.0;
+    for (int i = 0; i < grid; i++) {
+        const int v = base + i * stride;
+        run += pow(10.0, (double)p[(int64_t)v * 5]);
+        out[v] = run;
+    }
+}
+
+// first index i of the line whose prefix sum exceeds u * (line total); the
+// last index when none does
+__device__ __forceinline__ int line_pick(const double* __restrict__ C, int base, int stride,
+                                         int grid, float u) {
+    const double target = (double)u * C[base + (grid - 1) * stride];
+    int lo = 0, hi = grid - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (C[base + mid * stride] > target) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_gibbs(
+    int grid, double half, double dv, const double* __restrict__ centers,
+    const int32_t* __restrict__ out_off, const float* __restrict__ pred,
+    const double* __restrict__ cx_, const double* __restrict__ cy_,
+    const double* __restrict__ cz_, const double* __restrict__ x0,
+    const double* __restrict__ y0, const double* __restrict__ z0, int sweeps,
+    const float* __restrict__ uni, double T_to_u, double* __restrict__ x,
+    double* __restrict__ y, double* __restrict__ z, double* __restrict__ vx,
+    double* __restrict__ vy, double* __restrict__ vz, double* __restrict__ u) {
+#pragma clang fp contract(off)
+    const int c = blockIdx.y;
+    const int b = out_off[c], e = out_off[c + 1];
+    const int j = b + blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= e) return;
+    const int g2 = grid * grid;
+    const int64_t nvox = (int64_t)g2 * grid;
+    const int64_t cb = (int64_t)c * nvox;
+    const double lx = centers[3 * c] - half, ly = centers[3 * c + 1] - half,
+                 lz = centers[3 * c + 2] - half;
+    // start voxel: floor((x0 - lo) / dv), clamped to the grid
+    auto cell = [&](double p, double lo) {
+        const double f = floor((p - lo) / dv);
+        return f < 0.0 ? 0 : (f > (double)(grid - 1) ? grid - 1 : (int)f);
+    };
+    int X = cell(x0[j], lx), Y = cell(y0[j], ly), Z = cell(z0[j], lz);
+    const int nu = 3 * sweeps + 3;
+    const float* U = uni + (int64_t)j * nu;
+    for (int s = 0; s < sweeps; s++) {
+        X = line_pick(cx_ + cb, (Z * grid + Y) * grid, 1, grid, U[3 * s]);
+        Y = line_pick(cy_ + cb, Z * g2 + X, grid, grid, U[3 * s + 1]);
+        Z = line_pick(cz_ + cb, Y * grid + X, g2, grid, U[3 * s + 2]);
+    }
+    const int v = (Z * grid + Y) * grid + X;
+    x[j] = lx + (X + (double)U[3 * sweeps]) * dv;
+    y[j] = ly + (Y + (double)U[3 * sweeps + 1]) * dv;
+    z[j] = lz + (Z + (double)U[3 * sweeps + 2]) * dv;
+    const float* p = pred + (cb + v) * 5;
+    u[j] = pow(10.0, (double)p[1]) * T_to_u;
+    vx[j] = p[2];
+    vy[j] = p[3];
+    vz[j] = p[4];
+}
+
+extern "C" int gx_sn_resample_gibbs(gx_ctx* ctx, const float* pred, int k, int grid, double side,
+                                    const double* centers, const int32_t* out_off,
+                                    int64_t n_out_max, const double* x0, const double* y0,
+                                    const double* z0, int sweeps, const float* uniforms,
+                                    double T_to_u, double* x, double* y, double* z, double* vx,
+                                    double* vy, double* vz, double* u) {
+    if (!ctx) return GX_EINVAL;
+    if (!pred || !centers || !out_off || !x0 || !y0 || !z0 || !uniforms || !x || !y || !z ||
+        !vx || !vy || !vz || !u)
+        return gx_fail(ctx, GX_EINVAL, "sn_resample_gibbs: null pointer");
+    if (k < 1 || grid < 1 || grid > 1024 || !(side > 0) || n_out_max < 0 || sweeps < 0 ||
+        sweeps > 1000)
+        return gx_fail(ctx, GX_EINVAL, "sn_resample_gibbs: need k >= 1, 1 <= grid <= 1024, "
+                                       "side > 0, n_out_max >= 0, 0 <= sweeps <= 1000");
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    const int64_t nvox = (int64_t)grid * grid * grid;
+    GX_TRY(gx_reserve(ctx, ctx->sph_work[11], (size_t)3 * k * nvox * sizeof(double)));
+    double* cdf = (double*)ctx->sph_work[11].p;
+    const int lines = grid * grid;
+    for (int a = 0; a < 3; a++)
+        hipLaunchKernelGGL(k_line_cdf, dim3((lines + 255) / 256, k), dim3(256), 0, ctx->stream,
+                           pred, grid, a, cdf + (int64_t)a * k * nvox);
+    const unsigned gxb = (unsigned)std::max<int64_t>(1, (n_out_max + 255) / 256);
+    hipLaunchKernelGGL(k_gibbs, dim3(gxb, k), dim3(256), 0, ctx->stream, grid, 0.5 * side,
+                       side / grid, centers, out_off, pred, (const double*)cdf,
+                       (const double*)(cdf + k * nvox), (const double*)(cdf + 2 * k * nvox), x0,
+                       y0, z0, sweeps, uniforms, T_to_u, x, y, z, vx, vy, vz, u);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Eight-cube encoding of the network's channels: log10 rho, log10 T, then per
+// velocity component log10(v0 + max(v, 0)) and log10(v0 + max(-v, 0)); the
+// inverse takes v = 10^(c+) - 10^(c-).  Formed in FP64, stored in FP32.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_encode8(int64_t V, const float* __restrict__ in,
+                                                 int in_stride, double v0,
+                                                 float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V) return;
+    const float* p = in + i * in_stride;
+    float* o = out + i * 8;
+    o[0] = p[0];
+    o[1] = p[1];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const double v = (double)p[2 + a];
+        o[2 + 2 * a] = (float)log10(v0 + fmax(v, 0.0));
+        o[3 + 2 * a] = (float)log10(v0 + fmax(-v, 0.0));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_decode8(int64_t V, const float* __restrict__ in,
+                                                 int in_stride, float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V) return;
+    const float* p = in + i * in_stride;
+    float* o = out + i * 5;
+    o[0] = p[0];
+    o[1] = p[1];
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+        o[2 + a] = (float)(pow(10.0, (double)p[2 + 2 * a]) - pow(10.0, (double)p[3 + 2 * a]));
+}
+
+extern "C" int gx_sn_encode8(gx_ctx* ctx, int64_t V, const float* in5, int in_stride, double v0,
+                             float* out8) {
+    if (!ctx) return GX_EINVAL;
+    if (V < 0 || !in5 || !out8 || in_stride < 5 || !(v0 > 0))
+        return gx_fail(ctx, GX_EINVAL, "sn_encode8: need V >= 0, in_stride >= 5, v0 > 0");
+    if (V == 0) return GX_OK;
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_encode8, dim3(gx_blocks(V, 256)), dim3(256), 0, ctx->stream, V, in5,
+                       in_stride, v0, out8);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+extern "C" int gx_sn_decode8(gx_ctx* ctx, int64_t V, const float* in8, int in_stride,
+                             float* out5) {
+    if (!ctx) return GX_EINVAL;
+    if (V < 0 || !in8 || !out5 || in_stride < 8)
+        return gx_fail(ctx, GX_EINVAL, "sn_decode8: need V >= 0, in_stride >= 8");
+    if (V == 0) return GX_OK;
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_decode8, dim3(gx_blocks(V, 256)), dim3(256), 0, ctx->stream, V, in8,
+                       in_stride, out5);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Trust check of a prediction before replacement.
 // ---------------------------------------------------------------------------
 struct SnBounds {

@@ -261,57 +261,168 @@ def generate(eng: Engine, seeds, t_end_myr: float = 0.1, log=None, cfg: SPHConfi
     return x, y, info
 
 
+ENCODINGS = ("5ch", "8cube")
+RESAMPLERS = ("cdf", "gibbs")
+V0_KMS = 1.0                 # offset inside the eight-cube velocity logarithms
+
+
 class Surrogate:
     """The learned replacement of a supernova region's plain SPH (Sec. 3.3):
     U-Net weights plus the channel statistics that standardise its inputs and
     targets.  Inputs are the voxelized state just before the explosion,
-    outputs the physical channels 0.1 Myr after it."""
+    outputs the state 0.1 Myr after it.
+
+    encoding "5ch": the network sees and predicts the five physical channels
+    (log10 rho, log10 T, vx, vy, vz); "8cube": the paper's eight cubes (log10
+    rho, log10 T, and per velocity component a positive and a negative cube
+    of log10(v0 + |v|)), decoded back to the five physical channels after the
+    network.  resampler "cdf": exact inverse-CDF draws of the voxels; "gibbs":
+    Gibbs chains of `sweeps` sweeps started at the entering particles' voxels."""
 
     def __init__(self, eng: Engine, batch: int = 4, base: int = 32, levels: int = 4,
-                 grid: int = GRID, seed: int = 0, device="cuda", train: bool = True):
+                 grid: int = GRID, seed: int = 0, device="cuda", train: bool = True,
+                 encoding: str = "5ch", resampler: str = "cdf", sweeps: int = 4):
         import torch
         from .unet import UNet
+        if encoding not in ENCODINGS or resampler not in RESAMPLERS:
+            raise ValueError(f"encoding in {ENCODINGS}, resampler in {RESAMPLERS}")
         self.torch, self.eng, self.grid, self.device = torch, eng, grid, device
+        self.encoding, self.resampler, self.sweeps = encoding, resampler, int(sweeps)
+        self.nc = 5 if encoding == "5ch" else 8
         self.net = UNet(eng, S=grid, batch=batch, base=base, levels=levels, seed=seed, device=device,
-                        train=train)
-        f = dict(dtype=torch.float32, device=device)
-        # channel mean and standard deviation of the training inputs and
-        # targets, and the standardising maps x -> x * scale + shift
-        self.mean_in, self.std_in = torch.zeros(5, **f), torch.ones(5, **f)
-        self.mean_out, self.std_out = torch.zeros(5, **f), torch.ones(5, **f)
-        self.scale_in, self.shift_in = torch.ones(5, **f), torch.zeros(5, **f)
-        self.scale_out, self.shift_out = torch.ones(5, **f), torch.zeros(5, **f)
+                        train=train, nc_in=self.nc, nc_out=self.nc)
+        self._alloc_stats()
         self.V = grid ** 3
 
     STATS = ("mean_in", "std_in", "scale_in", "shift_in", "mean_out", "std_out", "scale_out",
-             "shift_out")
+             "shift_out", "mean_phys", "std_phys")
+
+    def _alloc_stats(self):
+        torch = self.torch
+        f = dict(dtype=torch.float32, device=self.device)
+        nc = self.nc
+        # channel mean and standard deviation of the network's training inputs
+        # and targets (in its encoding), the standardising maps x -> x * scale
+        # + shift, and the physical targets' mean and deviation (trust check)
+        self.mean_in, self.std_in = torch.zeros(nc, **f), torch.ones(nc, **f)
+        self.mean_out, self.std_out = torch.zeros(nc, **f), torch.ones(nc, **f)
+        self.scale_in, self.shift_in = torch.ones(nc, **f), torch.zeros(nc, **f)
+        self.scale_out, self.shift_out = torch.ones(nc, **f), torch.zeros(nc, **f)
+        self.mean_phys, self.std_phys = torch.zeros(5, **f), torch.ones(5, **f)
+
+    @property
+    def n_uniforms(self):
+        """Uniform numbers the resampler takes per particle."""
+        return 4 if self.resampler == "cdf" else 3 * self.sweeps + 3
 
     # ---- statistics -----------------------------------------------------------
-    def set_stats(self, sums_in, sums_out, count, min_std: float = 1e-3):
-        """Channel moments from FP64 sums (gx_chan_stats over count rows)."""
-        self.eng.chan_moments(sums_in, 5, count, min_std, self.mean_in, self.std_in,
+    def encode(self, x_phys, V, out):
+        """Physical rows [V, 5] -> the network's channels [V, nc] (unstandardized)."""
+        if self.nc == 5:
+            out.copy_(x_phys[:V * 5])
+        else:
+            self.eng.sn_encode8(x_phys, V, V0_KMS, out)
+        return out
+
+    def channel_sums(self, X, sums, chunk: int = 64):
+        """Add FP64 channel sums of the network's encoding of physical rows
+        X (device float [n, V * 5]) into sums (device double [2 nc])."""
+        torch, V = self.torch, self.V
+        if self.nc == 5:
+            self.eng.chan_stats(X.reshape(-1), 5, 5, sums)
+            return sums
+        tmp = torch.empty(min(chunk, X.shape[0]) * V * self.nc, dtype=torch.float32,
+                          device=X.device)
+        for a in range(0, X.shape[0], chunk):
+            b = min(chunk, X.shape[0] - a)
+            enc = self.encode(X[a:a + b].reshape(-1), b * V, tmp[:b * V * self.nc])
+            self.eng.chan_stats(enc, self.nc, self.nc, sums)
+        return sums
+
+    def set_stats(self, sums_in, sums_out, count, sums_phys=None, min_std: float = 1e-3):
+        """Channel moments from FP64 sums (gx_chan_stats over count rows) of
+        the encoded inputs and targets and of the physical targets (the same
+        as the targets' for the five-channel encoding)."""
+        nc = self.nc
+        self.eng.chan_moments(sums_in, nc, count, min_std, self.mean_in, self.std_in,
                               self.scale_in, self.shift_in)
-        self.eng.chan_moments(sums_out, 5, count, min_std, self.mean_out, self.std_out,
+        self.eng.chan_moments(sums_out, nc, count, min_std, self.mean_out, self.std_out,
                               self.scale_out, self.shift_out)
+        if sums_phys is None:
+            if nc != 5:
+                raise ValueError("the eight-cube encoding needs the physical target sums")
+            self.mean_phys.copy_(self.mean_out)
+            self.std_phys.copy_(self.std_out)
+        else:
+            sc = self.torch.empty(5, dtype=self.torch.float32, device=self.device)
+            sh = self.torch.empty_like(sc)
+            self.eng.chan_moments(sums_phys, 5, count, min_std, self.mean_phys, self.std_phys,
+                                  sc, sh)
 
     def standardize(self, x_f32, which="in", out_f32=None, out_bf16=None):
-        """(x - mean) / std per channel of physical [.., 5] rows."""
+        """Physical [.., 5] rows -> the network's standardized channels:
+        out_f32 rows of nc floats, out_bf16 rows of 8 (channels nc.. zero)."""
         scale, shift = (self.scale_in, self.shift_in) if which == "in" else \
             (self.scale_out, self.shift_out)
-        self.eng.chan_affine(x_f32, 5, 5, scale, shift, out=out_f32, out_stride=5,
+        nc = self.nc
+        V = x_f32.numel() // 5
+        src = x_f32
+        if nc != 5:
+            src = self.encode(x_f32, V, self.torch.empty(V * nc, dtype=self.torch.float32,
+                                                         device=x_f32.device))
+        self.eng.chan_affine(src, nc, nc, scale, shift, out=out_f32, out_stride=nc,
                              out_bf16=out_bf16, bf_stride=8)
 
+    def check_bounds(self, sigma: float):
+        """Per physical channel [lo, hi] = mean +- sigma std of the training
+        targets (host FP64), for gx_sn_check."""
+        mo = self.mean_phys.cpu().numpy().astype(np.float64)
+        so = self.std_phys.cpu().numpy().astype(np.float64)
+        return mo - sigma * so, mo + sigma * so
+
     # ---- inference ------------------------------------------------------------
+    def inputs(self, p: ParticleSet, g: GasState, centers, side, amb, K):
+        """Standardized network input bf16 [K * V * 8] of K regions (gas tree
+        of p built by the caller)."""
+        torch = self.torch
+        dev = centers.device
+        xin = torch.empty(K * self.V * 8, dtype=torch.bfloat16, device=dev)
+        if self.nc == 5:
+            self.eng.sn_voxelize(p, g.u, g.H, centers, side, self.grid, 1.0 / U_PER_K, amb,
+                                 mean=self.mean_in, std=self.std_in, out_bf16=xin, cpad=8)
+        else:
+            phys = torch.empty(K * self.V * 5, dtype=torch.float32, device=dev)
+            self.eng.sn_voxelize(p, g.u, g.H, centers, side, self.grid, 1.0 / U_PER_K, amb,
+                                 out_f32=phys)
+            self.standardize(phys, "in", out_bf16=xin)
+        return xin
+
     def infer(self, x_bf16, K: int, out_f32):
         """x_bf16 [K * V * 8] standardized inputs -> out_f32 [K * V * 5] physical."""
-        net, V, B = self.net, self.V, self.net.B
+        net, V, B, nc = self.net, self.V, self.net.B, self.nc
+        tmp = None if nc == 5 else self.torch.empty(min(B, K) * V * nc, dtype=self.torch.float32,
+                                                    device=out_f32.device)
         for a in range(0, K, B):
             b = min(B, K - a)
             net.Bcur = b
-            net.forward(x_bf16[a * V * 8:(a + b) * V * 8], out_phys=out_f32[a * V * 5:(a + b) * V * 5],
+            dst = out_f32[a * V * 5:(a + b) * V * 5] if nc == 5 else tmp[:b * V * nc]
+            net.forward(x_bf16[a * V * 8:(a + b) * V * 8], out_phys=dst,
                         scale=self.std_out, shift=self.mean_out)
+            if nc != 5:
+                self.eng.sn_decode8(dst, b * V, out_f32[a * V * 5:(a + b) * V * 5])
         net.Bcur = B
         return out_f32
+
+    def resample(self, pred, centers, side, off, n_max, uniforms, start, out):
+        """Particles drawn from the predicted grids (CSR off by region): the
+        chosen resampler; start = (x, y, z) device FP64 positions of the
+        particles that entered (frame of centers; used by the Gibbs chains)."""
+        o = [out[k] for k in ("x", "y", "z", "vx", "vy", "vz", "u")]
+        if self.resampler == "cdf":
+            self.eng.sn_resample(pred, centers, self.grid, side, off, n_max, uniforms, U_PER_K, *o)
+        else:
+            self.eng.sn_resample_gibbs(pred, centers, self.grid, side, off, n_max, *start,
+                                       self.sweeps, uniforms, U_PER_K, *o)
 
     def regions(self, p: ParticleSet, g: GasState, centers, side: float = SIDE, cap: int = None,
                 cfg: SPHConfig = SPHConfig(), uniforms=None, build_tree=True):
@@ -326,9 +437,7 @@ class Surrogate:
         amb = eng.sn_ambient(p, g.u, off, idx, side, 1.0 / U_PER_K)
         if build_tree:
             eng.tree_build(p, GX_TREE_GAS, cfg.n_leaf, cfg.n_group)
-        xin = torch.empty(K * self.V * 8, dtype=torch.bfloat16, device=dev)
-        eng.sn_voxelize(p, g.u, g.H, centers, side, self.grid, 1.0 / U_PER_K, amb,
-                        mean=self.mean_in, std=self.std_in, out_bf16=xin, cpad=8)
+        xin = self.inputs(p, g, centers, side, amb, K)
         pred = torch.empty(K * self.V * 5, dtype=torch.float32, device=dev)
         self.infer(xin, K, pred)
         new = {k: torch.empty(max(tot, 1), dtype=torch.float64, device=dev)
@@ -336,32 +445,43 @@ class Surrogate:
         if tot > 0:
             n_max = int((off[1:] - off[:-1]).max().item())
             if uniforms is None:
-                uniforms = torch.rand(tot * 4, dtype=torch.float32, device=dev)
-            eng.sn_resample(pred, centers, self.grid, side, off, n_max, uniforms, U_PER_K,
-                            *(new[k] for k in ("x", "y", "z", "vx", "vy", "vz", "u")))
+                uniforms = torch.rand(tot * self.n_uniforms, dtype=torch.float32, device=dev)
+            li = idx.long()
+            start = tuple(a.index_select(0, li).contiguous() for a in (p.x, p.y, p.z))
+            self.resample(pred, centers, side, off, n_max, uniforms, start, new)
         return off, idx, {k: v[:tot] for k, v in new.items()}, pred
 
     # ---- persistence ----------------------------------------------------------
     def save(self, path, moments: bool = False):
-        """Weights (FP32 master copy) and channel statistics; Adam moments only
-        when asked (they triple the file)."""
+        """Weights (FP32 master copy), channel statistics and encoding; Adam
+        moments only when asked (they triple the file)."""
         d = self.net.state_dict()
         extra = {"m": d["m"], "v": d["v"]} if moments else {}
-        np.savez(path, w32=d["w32"], t=d["t"], **extra,
+        np.savez(path, w32=d["w32"], t=d["t"], encoding=np.str_(self.encoding), **extra,
                  **{k: getattr(self, k).cpu().numpy() for k in self.STATS})
 
     def export(self, path):
         """Inference weights: BF16 bits of every parameter (what the network
-        computes with) plus the FP32 biases, and the channel statistics."""
+        computes with) plus the FP32 biases, the channel statistics and the
+        encoding."""
         w = self.net.w32.cpu().numpy()
         b0 = min(ly.b_off for ly in self.net.L)
         bits = self.net.wbf.view(self.torch.int16).cpu().numpy().view(np.uint16)
         np.savez_compressed(path, w_bf16=bits, bias_f32=w[b0:], b_off=np.int64(b0),
                             levels=np.int64(self.net.levels), base=np.int64(self.net.base),
+                            encoding=np.str_(self.encoding),
                             **{k: getattr(self, k).cpu().numpy() for k in self.STATS})
+
+    @staticmethod
+    def file_encoding(path):
+        d = np.load(path)
+        return str(d["encoding"]) if "encoding" in d else "5ch"
 
     def load(self, path):
         d = np.load(path)
+        enc = str(d["encoding"]) if "encoding" in d else "5ch"
+        if enc != self.encoding:
+            raise ValueError(f"{path}: encoding {enc}, this surrogate uses {self.encoding}")
         if "w_bf16" in d:  # an exported inference file
             if int(d["levels"]) != self.net.levels or int(d["base"]) != self.net.base:
                 raise ValueError(f"{path}: network shape differs")
@@ -373,4 +493,10 @@ class Surrogate:
                                   "v": d["v"] if "v" in d else z,
                                   "t": int(d["t"]) if "m" in d else 0})
         for k in self.STATS:
-            getattr(self, k).copy_(self.torch.as_tensor(d[k]))
+            if k in d:
+                getattr(self, k).copy_(self.torch.as_tensor(d[k]))
+            elif k in ("mean_phys", "std_phys") and self.nc == 5:
+                # files written before the physical statistics were kept
+                getattr(self, k).copy_(self.torch.as_tensor(d[k.replace("phys", "out")]))
+            else:
+                raise ValueError(f"{path}: no {k}")

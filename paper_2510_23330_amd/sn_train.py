@@ -7,14 +7,16 @@
 1. Training pairs: K cubes per batch of plain small-timestep SPH (cube seeds
    sorted by particle count so one shared Courant step suits a batch), each
    voxelized to 64^3 x 5 channels before the explosion and 0.1 Myr after it.
-2. Channel statistics of the training inputs and targets (standardisation).
+2. Channel statistics of the training inputs and targets (standardisation)
+   in the network's encoding (--encoding: the five physical channels, or the
+   paper's eight cubes with the velocity components split by sign).
 3. Adam on the MSE of the standardized target channels, shuffled mini-batches,
    until the epoch count or the time budget is reached.
 4. Held-out cubes: the surrogate's prediction against plain SPH, against the
    pre-explosion state (persistence) and against plain SPH forced to the
    galaxy's 2,000 yr step; the resample -> density -> voxelize round trip of
-   the replacement particles; wall time of plain SPH vs the surrogate path
-   for the same regions.
+   the replacement particles for each resampler (inverse CDF, Gibbs); wall
+   time of plain SPH vs the surrogate path for the same regions.
 
 Writes metrics.json, the weights (surrogate.npz) and a log to --out.
 """
@@ -109,7 +111,8 @@ def summarize(pred, ref):
 
 def train(sur: Surrogate, Xp, Yp, Xt, Yt, epochs, seconds, lr, log, seed=0, augment=True):
     """Xp, Yp: physical training pairs, device float [n, V*5]; Xt, Yt: the
-    held-out pairs standardized (bf16 [m, V*8], f32 [m, V*5]).  Each
+    held-out pairs standardized (bf16 [m, V*8], f32 [m, V*nc]).  The cube
+    symmetries act on the physical channels, before the encoding.  Each
     mini-batch is drawn at random, mapped by a random symmetry of the cube
     (augment) and standardized on the device.  The weights with the lowest
     held-out MSE seen at an epoch end are kept."""
@@ -125,7 +128,7 @@ def train(sur: Surrogate, Xp, Yp, Xt, Yt, epochs, seconds, lr, log, seed=0, augm
     xa = torch.empty(B * V * 5, **f32)
     ya = torch.empty(B * V * 5, **f32)
     xb = torch.empty(B * V * 8, dtype=torch.bfloat16, device="cuda")
-    yb = torch.empty(B * V * 5, **f32)
+    yb = torch.empty(B * V * sur.nc, **f32)
     best = (float("inf"), None, -1)
     t0 = time.perf_counter()
     hist = []
@@ -184,7 +187,7 @@ def evaluate_mse(sur: Surrogate, Xt, Yt):
         b = min(B, n - a)
         net.Bcur = b
         pred = net.forward(Xt[a:a + b].reshape(-1))
-        tot += b * sur.eng.mse(pred, 16, Yt[a:a + b].reshape(-1), 5, b * V)
+        tot += b * sur.eng.mse(pred, 16, Yt[a:a + b].reshape(-1), sur.nc, b * V)
     net.Bcur = B
     return tot / n
 
@@ -195,14 +198,15 @@ def bench_training(a):
     import torch
     from .unet import flops_forward
     eng = Engine(0)
-    sur = Surrogate(eng, batch=a.batch, base=a.base, levels=a.levels, grid=a.grid, seed=1)
-    V = a.grid ** 3
+    sur = Surrogate(eng, batch=a.batch, base=a.base, levels=a.levels, grid=a.grid, seed=1,
+                    encoding=a.encoding)
+    V, nc = a.grid ** 3, sur.nc
     g = torch.Generator(device="cuda")
     g.manual_seed(7)
     xb = torch.zeros(a.batch * V * 8, dtype=torch.float32, device="cuda")
-    xb.view(-1, 8)[:, :5] = torch.randn(a.batch * V, 5, device="cuda", generator=g)
+    xb.view(-1, 8)[:, :nc] = torch.randn(a.batch * V, nc, device="cuda", generator=g)
     xb = xb.to(torch.bfloat16)
-    yb = torch.randn(a.batch * V * 5, device="cuda", generator=g)
+    yb = torch.randn(a.batch * V * nc, device="cuda", generator=g)
     for _ in range(3):
         sur.net.train_step(xb, yb, lr=a.lr)
     torch.cuda.synchronize()
@@ -212,7 +216,7 @@ def bench_training(a):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / a.bench_steps
     fl = 3 * flops_forward(a.grid, a.base, a.levels) * a.batch
-    out = {"batch": a.batch, "grid": a.grid, "ms_per_step": dt * 1e3,
+    out = {"batch": a.batch, "grid": a.grid, "encoding": a.encoding, "ms_per_step": dt * 1e3,
            "samples_per_s": a.batch / dt, "tflops_3x_forward": fl / dt / 1e12,
            "frac_bf16_peak": fl / dt / 2.5e15}
     print(json.dumps(out), flush=True)
@@ -239,6 +243,12 @@ def main(argv=None):
     ap.add_argument("--out", default="sn_out")
     ap.add_argument("--export", default=None,
                     help="also write the inference weights (BF16) to this file")
+    ap.add_argument("--encoding", choices=("5ch", "8cube"), default="5ch",
+                    help="network channels: five physical ones or the paper's eight cubes")
+    ap.add_argument("--resampler", choices=("cdf", "gibbs"), default="cdf")
+    ap.add_argument("--sweeps", type=int, default=4, help="Gibbs sweeps per particle")
+    ap.add_argument("--eval-resamplers", default="cdf,gibbs",
+                    help="resamplers compared in the held-out replacement check")
     ap.add_argument("--bench-steps", type=int, default=0,
                     help="only time this many training steps on random data and exit")
     a = ap.parse_args(argv)
@@ -261,21 +271,28 @@ def main(argv=None):
     metrics["test_plain_sph"] = tinfos
 
     # 2. statistics and standardized copies
-    sur = Surrogate(eng, batch=a.batch, base=a.base, levels=a.levels, grid=a.grid, seed=1)
+    sur = Surrogate(eng, batch=a.batch, base=a.base, levels=a.levels, grid=a.grid, seed=1,
+                    encoding=a.encoding, resampler=a.resampler, sweeps=a.sweeps)
+    nc = sur.nc
     if a.init:
         sur.load(a.init)
     else:
-        si = torch.zeros(10, dtype=torch.float64, device="cuda")
-        so = torch.zeros(10, dtype=torch.float64, device="cuda")
-        eng.chan_stats(Xp.view(-1), 5, 5, si)
-        eng.chan_stats(Yp.view(-1), 5, 5, so)
-        sur.set_stats(si, so, Xp.shape[0] * V)
+        si = torch.zeros(2 * nc, dtype=torch.float64, device="cuda")
+        so = torch.zeros(2 * nc, dtype=torch.float64, device="cuda")
+        sur.channel_sums(Xp, si)
+        sur.channel_sums(Yp, so)
+        sp = None
+        if nc != 5:
+            sp = torch.zeros(10, dtype=torch.float64, device="cuda")
+            eng.chan_stats(Yp.view(-1), 5, 5, sp)
+        sur.set_stats(si, so, Xp.shape[0] * V, sums_phys=sp)
     metrics["stats"] = {k: getattr(sur, k).cpu().tolist()
-                        for k in ("mean_in", "std_in", "mean_out", "std_out")}
+                        for k in ("mean_in", "std_in", "mean_out", "std_out", "mean_phys",
+                                  "std_phys")}
 
     def std_pair(X, Y):
         Xs = torch.empty((X.shape[0], V * 8), dtype=torch.bfloat16, device="cuda")
-        Ys = torch.empty_like(Y)
+        Ys = torch.empty((Y.shape[0], V * nc), dtype=torch.float32, device="cuda")
         sur.standardize(X.view(-1), "in", out_bf16=Xs.view(-1))
         sur.standardize(Y.view(-1), "out", out_f32=Ys.view(-1))
         return Xs, Ys
@@ -308,11 +325,11 @@ def main(argv=None):
     metrics["surrogate_vs_sph"] = summarize(pred, Ytp)
     metrics["persistence_vs_sph"] = summarize(Xtp, Ytp)
     # the same comparison in the standardized target channels the loss uses
-    pers = torch.empty_like(Xtp)
-    sur.standardize(Xtp.view(-1), "out", out_f32=pers.view(-1))
+    pers = torch.empty(n_t * V * nc, dtype=torch.float32, device="cuda")
+    sur.standardize(Xtp.view(-1), "out", out_f32=pers)
     metrics["mse_standardized"] = {
         "surrogate": evaluate_mse(sur, Xts, Yts),
-        "persistence": sur.eng.mse(pers.view(-1), 5, Yts.reshape(-1), 5, n_t * V)}
+        "persistence": sur.eng.mse(pers, nc, Yts.reshape(-1), nc, n_t * V)}
     del pers
     _, Yc, _, cinfos = generate_set(eng, test_seeds, a.per_batch, log, dt_fixed_myr=DT_GLOBAL_MYR,
                                     grid=a.grid)
@@ -320,39 +337,48 @@ def main(argv=None):
     metrics["coarse_dt_sph"] = cinfos
     del Yc
 
-    # replacement particles: resample, density, voxelize again; and timings
+    # replacement particles: resample, density, voxelize again; and timings,
+    # for each resampler compared
     import ics
     cfg = SPHConfig()
-    rt, plain_s, sur_s, nreg = [], 0.0, 0.0, 0
-    k = 0
-    for bs in batches_by_size(test_seeds, a.per_batch):
-        sb = SNBatch(eng, ics.sn_batch(bs), cfg)
-        sb.voxelize(grid=a.grid)            # kernel sizes of the pre-explosion state
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        off, idx, new, _ = sur.regions(sb.p, sb.g, sb.centers, cap=sb.n)
-        torch.cuda.synchronize()
-        sur_s += time.perf_counter() - t1
-        nreg += len(bs)
-        m = sb.p.m.index_select(0, idx.long())
-        q = ParticleSet(x=new["x"], y=new["y"], z=new["z"], vx=new["vx"], vy=new["vy"],
-                        vz=new["vz"], m=m, eps2=sb.p.eps2[:m.shape[0]])
-        g = GasState.zeros(q.n, u=new["u"])
-        eng.tree_build(q, GX_TREE_GAS, cfg.n_leaf, cfg.n_group)
-        eng.sph_density(q, g, cfg.n_ngb, cfg.gamma, cfg.h_tol, cfg.max_iter, allow_noconv=True)
-        vox = torch.zeros(len(bs) * V * 5, dtype=torch.float32, device="cuda")
-        eng.sn_voxelize(q, g.u, g.H, sb.centers, SIDE, a.grid, 1.0 / U_PER_K, sb.ambient(),
-                        out_f32=vox)
-        rt.append((vox, k, len(bs)))
-        k += len(bs)
-    # truth rows follow the same size-sorted order as generate_set produced
-    ref = torch.cat([Ytp[kk:kk + nb].reshape(-1) for _, kk, nb in rt])
-    metrics["replaced_particles_vs_sph"] = summarize(torch.cat([v for v, _, _ in rt]), ref)
+    metrics["replaced_particles_vs_sph"] = {}
+    metrics["timing_by_resampler"] = {}
     plain_s = sum(i["seconds"] for i in tinfos)
-    metrics["timing"] = {"regions": nreg, "plain_sph_s": plain_s, "surrogate_s": sur_s,
-                         "speedup": plain_s / max(sur_s, 1e-12),
-                         "plain_sph_s_per_64": plain_s / nreg * 64,
-                         "surrogate_s_per_64": sur_s / nreg * 64}
+    for rs in [r for r in a.eval_resamplers.split(",") if r]:
+        sur.resampler = rs
+        rt, sur_s, nreg = [], 0.0, 0
+        k = 0
+        for bs in batches_by_size(test_seeds, a.per_batch):
+            sb = SNBatch(eng, ics.sn_batch(bs), cfg)
+            sb.voxelize(grid=a.grid)            # kernel sizes of the pre-explosion state
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            off, idx, new, _ = sur.regions(sb.p, sb.g, sb.centers, cap=sb.n)
+            torch.cuda.synchronize()
+            sur_s += time.perf_counter() - t1
+            nreg += len(bs)
+            m = sb.p.m.index_select(0, idx.long())
+            q = ParticleSet(x=new["x"], y=new["y"], z=new["z"], vx=new["vx"], vy=new["vy"],
+                            vz=new["vz"], m=m, eps2=sb.p.eps2[:m.shape[0]])
+            g = GasState.zeros(q.n, u=new["u"])
+            eng.tree_build(q, GX_TREE_GAS, cfg.n_leaf, cfg.n_group)
+            eng.sph_density(q, g, cfg.n_ngb, cfg.gamma, cfg.h_tol, cfg.max_iter, allow_noconv=True)
+            vox = torch.zeros(len(bs) * V * 5, dtype=torch.float32, device="cuda")
+            eng.sn_voxelize(q, g.u, g.H, sb.centers, SIDE, a.grid, 1.0 / U_PER_K, sb.ambient(),
+                            out_f32=vox)
+            rt.append((vox, k, len(bs)))
+            k += len(bs)
+        # truth rows follow the same size-sorted order as generate_set produced
+        ref = torch.cat([Ytp[kk:kk + nb].reshape(-1) for _, kk, nb in rt])
+        metrics["replaced_particles_vs_sph"][rs] = summarize(torch.cat([v for v, _, _ in rt]), ref)
+        metrics["timing_by_resampler"][rs] = {
+            "regions": nreg, "plain_sph_s": plain_s, "surrogate_s": sur_s,
+            "speedup": plain_s / max(sur_s, 1e-12), "plain_sph_s_per_64": plain_s / nreg * 64,
+            "surrogate_s_per_64": sur_s / nreg * 64}
+        del rt, ref
+    sur.resampler = a.resampler
+    metrics["timing"] = metrics["timing_by_resampler"].get(
+        a.resampler, next(iter(metrics["timing_by_resampler"].values()), {}))
     log(json.dumps({k: metrics[k] for k in ("mse_standardized", "surrogate_vs_sph", "persistence_vs_sph",
                                              "coarse_dt_sph_vs_sph", "replaced_particles_vs_sph",
                                              "timing")}))

@@ -5,8 +5,9 @@ in the design notes): 4 levels with 32, 64, 128, 256 channels; two 3^3
 convolutions (zero padding 1, bias, LeakyReLU 0.1) per level on the way down
 and up; 2^3 average pooling down; nearest x2 upsampling followed by a 3^3
 convolution on the way up; skip connections by channel concatenation; a
-linear 1^3 head.  Inputs carry 5 physical channels padded to 8, outputs 5
-channels padded to 16 (FP32).  Activations and weights are BF16, every
+linear 1^3 head.  Inputs carry nc_in channels padded to 8 (5 physical
+channels, or the 8 cubes of the paper's encoding), outputs nc_out channels
+padded to 16 (FP32).  Activations and weights are BF16, every
 convolution accumulates in FP32; master weights and Adam moments are FP32.
 
 The layer sequence of each pass runs inside the library (gx_unet_forward,
@@ -23,7 +24,6 @@ import numpy as np
 
 CIN_PAD = 8
 COUT_PAD = 16
-N_CHAN = 5
 
 
 @dataclass
@@ -72,11 +72,15 @@ ACT_NAMES = ("e{l}a", "e{l}b", "p{l}", "up{l}", "u{l}c", "c{l}", "d{l}a", "d{l}b
 
 class UNet:
     def __init__(self, eng, S: int = 64, batch: int = 4, base: int = 32, levels: int = 4,
-                 seed: int = 0, device="cuda", train: bool = True):
+                 seed: int = 0, device="cuda", train: bool = True, nc_in: int = 5,
+                 nc_out: int = 5):
+        if not (1 <= nc_in <= CIN_PAD and 1 <= nc_out <= COUT_PAD):
+            raise ValueError("channel counts exceed the padded widths")
         import torch
         self.torch = torch
         self.eng = eng
         self.S, self.B, self.levels, self.base = S, batch, levels, base
+        self.nc_in, self.nc_out = nc_in, nc_out
         self.ch = [base * 2 ** l for l in range(levels)]
         self.L, n = layers(base, levels)
         self.by = {ly.name: ly for ly in self.L}
@@ -89,9 +93,9 @@ class UNet:
             ww = rng.uniform(-bound, bound, ly.n_w).reshape(ly.cout, ly.kvol, ly.cin)
             # padded input channels and padded head outputs carry nothing
             if ly.name == "e0a":
-                ww[:, :, N_CHAN:] = 0
+                ww[:, :, nc_in:] = 0
             if ly.name == "head":
-                ww[N_CHAN:] = 0
+                ww[nc_out:] = 0
             w[ly.w_off:ly.w_off + ly.n_w] = ww.ravel()
         f32 = dict(dtype=torch.float32, device=device)
         self.w32 = torch.as_tensor(w, **f32)
@@ -112,13 +116,13 @@ class UNet:
     # ---- forward ----------------------------------------------------------------
     def forward(self, x, out_phys=None, scale=None, shift=None):
         """x: bf16 [Bcur * S^3 * 8] standardized input; returns fp32 [Bcur * S^3 * 16].
-        With out_phys (fp32 [Bcur * S^3 * 5]) the head writes the first five
-        outputs mapped by scale * y + shift there instead, and returns it.  A
+        With out_phys (fp32 [Bcur * S^3 * nc_out]) the head writes the first
+        nc_out outputs mapped by scale * y + shift there instead, and returns it.  A
         training-mode network keeps its activations for backward()."""
         B, S = self.Bcur, self.S
         if out_phys is not None:
-            self.eng.unet_forward(self.desc, x, B, S, self.train_mode, None, N_CHAN, scale, shift,
-                                  out_phys)
+            self.eng.unet_forward(self.desc, x, B, S, self.train_mode, None, self.nc_out, scale,
+                                  shift, out_phys)
             return out_phys
         out = self.pred[:B * S ** 3 * COUT_PAD]
         self.eng.unet_forward(self.desc, x, B, S, self.train_mode, out_f32=out)
@@ -152,7 +156,7 @@ class UNet:
         pred = self.forward(x)
         V = self.Bcur * self.S ** 3
         dp = self.dpred[:V * COUT_PAD]
-        loss = self.eng.mse(pred, COUT_PAD, target, N_CHAN, V, dp)
+        loss = self.eng.mse(pred, COUT_PAD, target, self.nc_out, V, dp)
         self.zero_grad()
         self.backward(x, dp)
         self.adam(lr)

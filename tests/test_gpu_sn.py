@@ -229,6 +229,7 @@ def test_coupling_replaces_by_id(gx, eng):
     sur_eng.f32_to_bf16(sur.net.w32, sur.net.wbf)
     mean_out = torch.tensor([-1.0, 4.0, 1.0, 2.0, 3.0], device="cuda")
     sur.mean_out.copy_(mean_out)
+    sur.mean_phys.copy_(mean_out)
     side_pc = 600.0
     cp = SNCoupling(st, sur, n_sites=16, delay=1, side_pc=side_pc, seed=11)
     # sites are disk stars
@@ -422,7 +423,7 @@ def test_per_cube_steps_match_single_cube_runs(gx, eng):
     assert steps.min() >= 1
 
 
-def _coupled_run(gx, asynchronous, n_steps=4, delay=2):
+def _coupled_run(gx, asynchronous, n_steps=4, delay=2, encoding="5ch", resampler="cdf"):
     import torch
     from paper_2510_23330_amd.coupling import SNCoupling
     from paper_2510_23330_amd.sim import GalaxyStep, StepConfig
@@ -434,11 +435,16 @@ def _coupled_run(gx, asynchronous, n_steps=4, delay=2):
     st = GalaxyStep(eng, p, d["gas_offset"], u, StepConfig(G=ics.G_KPC, dt=2000.0 / 0.97779e9))
     st.initial_forces()
     sur_eng = gx.Engine(0, stream=torch.cuda.Stream() if asynchronous else None)
-    sur = Surrogate(sur_eng, batch=4, base=16, levels=3, grid=16, seed=0)
+    sur = Surrogate(sur_eng, batch=4, base=16, levels=3, grid=16, seed=0, encoding=encoding,
+                    resampler=resampler, sweeps=2)
     # zero weights: the network predicts its output mean, inside the trust range
     sur.net.w32.zero_()
     sur_eng.f32_to_bf16(sur.net.w32, sur.net.wbf)
-    sur.mean_out.copy_(torch.tensor([-1.0, 4.0, 1.0, 2.0, 3.0], device="cuda"))
+    phys = [-1.0, 4.0, 1.0, 2.0, 3.0]
+    mo = phys if encoding == "5ch" else \
+        [-1.0, 4.0, math.log10(2.0), 0.0, math.log10(3.0), 0.0, math.log10(4.0), 0.0]
+    sur.mean_out.copy_(torch.tensor(mo, device="cuda"))
+    sur.mean_phys.copy_(torch.tensor(phys, device="cuda"))
     cp = SNCoupling(st, sur, n_sites=8, delay=delay, side_pc=600.0, seed=11,
                     asynchronous=asynchronous)
     try:
@@ -463,6 +469,16 @@ def test_async_coupling_matches_sync(gx):
     # values, of the synchronous path.
     s_sync, c_sync = _coupled_run(gx, False)
     s_async, c_async = _coupled_run(gx, True)
+    assert c_sync["particles_replaced"] > 0 and c_sync == c_async
+    for k in s_sync:
+        assert np.array_equal(s_sync[k], s_async[k]), k
+
+
+def test_async_coupling_matches_sync_eight_cubes_gibbs(gx):
+    # the same with the eight-cube encoding and Gibbs resampling
+    kw = dict(encoding="8cube", resampler="gibbs")
+    s_sync, c_sync = _coupled_run(gx, False, **kw)
+    s_async, c_async = _coupled_run(gx, True, **kw)
     assert c_sync["particles_replaced"] > 0 and c_sync == c_async
     for k in s_sync:
         assert np.array_equal(s_sync[k], s_async[k]), k
