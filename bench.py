@@ -22,9 +22,10 @@ cubes of 1 Msun particles, the plain small-timestep SPH to 0.1 Myr with the
 surrogate path on the same cubes, and the network's inference throughput at
 batch 256.  ``galaxy_0p1Myr`` compares 0.1 Myr of the disk with the
 surrogate (50 global steps) against a shared step held to the SN regions'
-Courant step.  ``force_error`` gives the relative force error against the
-FP64 oracle's direct sum (16M, 1M, Plummer).  ``cpu_baseline`` times the FP64
-oracle's tree gravity on a seeded sample of the same workload's groups.
+Courant step.  The CPU-baseline leg (skipped by --no-cpu) is the only part
+that runs the FP64 oracle: ``cpu_baseline`` times its tree gravity on a
+seeded sample of the same workload's groups, and ``force_error`` gives the
+relative force error of the GPU against its direct sum (16M, 1M, Plummer).
 """
 from __future__ import annotations
 
@@ -84,7 +85,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--cpu-groups", type=int, default=1024,
                     help="groups in the oracle's timed sample (0 skips the CPU baseline)")
-    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the CPU-baseline leg (oracle timing and force errors)")
     ap.add_argument("--sn-sites", type=int, default=64,
                     help="SN regions handed to the surrogate per step (0: plain step only)")
     ap.add_argument("--sn-cubes", type=int, default=64,
@@ -93,7 +95,8 @@ def parse():
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2510_23330_amd", "weights",
                                                       "sn_unet_5ch.npz"),
                     help="trained surrogate weights (random initialisation when absent)")
-    ap.add_argument("--no-force-error", action="store_true")
+    ap.add_argument("--no-force-error", action="store_true",
+                    help="skip the force errors against the oracle's direct sum")
     ap.add_argument("--sn-mode", choices=("async", "sync"), default="async",
                     help="surrogate hand-over on its own stream in a worker thread (default), "
                          "or in series on the galaxy's stream")
@@ -180,6 +183,26 @@ def force_errors(eng, sim, n_recv=256, seed=31):
         _err_stats([a.cpu().numpy() for a in acc[:3]], ref[:3]), receivers="all 8192")
     out["targets_p99"] = {"tree": 1e-3, "direct": 1e-5}
     return out
+
+
+def cpu_baseline_leg(args, eng, sim, d):
+    """The benchmark's CPU-baseline leg, the only part of it that runs the
+    FP64 oracle: the oracle's tree gravity timed on the host cores
+    (``cpu_baseline``) and, unless --no-force-error, the oracle's FP64 direct
+    sum as the reference of the GPU forces (``force_error``).  --no-cpu skips
+    the leg."""
+    res = {"cpu_baseline": None}
+    if args.no_cpu:
+        return res
+    if not args.no_force_error:
+        t0 = time.perf_counter()
+        res["force_error"] = force_errors(eng, sim)
+        log(f"[bench] force errors {time.perf_counter() - t0:.1f} s")
+    if args.cpu_groups > 0:
+        t0 = time.perf_counter()
+        res["cpu_baseline"] = cpu_baseline(d, args.cpu_groups, 99)
+        log(f"[bench] cpu baseline {time.perf_counter() - t0:.1f} s")
+    return res
 
 
 def cpu_baseline(d, n_groups_sample, seed):
@@ -496,10 +519,6 @@ def main():
                      "kernel": "k_grav_force<float,true>",
                      "flop_convention": f"{FLOP_PP}/pp + {FLOP_PC}/pc"},
     }
-    if not args.no_force_error:
-        t0 = time.perf_counter()
-        out["force_error"] = force_errors(eng, sim)
-        log(f"[bench] force errors {time.perf_counter() - t0:.1f} s")
     if args.sn_cubes > 0:
         t0 = time.perf_counter()
         out["sn_region"] = sn_region_leg(eng, args.sn_cubes, args.sn_infer_batch, args.weights,
@@ -520,12 +539,7 @@ def main():
                 "speedup": n_sh * plain_step_s / (50 * ms_step / 1e3),
                 "global_steps": {"surrogate": 50, "plain": n_sh},
                 "dt_cfl_sn_yr": 0.1e6 / n_sh, "dt_global_yr": 2000.0}
-    if not args.no_cpu and args.cpu_groups > 0:
-        t0 = time.perf_counter()
-        out["cpu_baseline"] = cpu_baseline(d, args.cpu_groups, 99)
-        log(f"[bench] cpu baseline {time.perf_counter() - t0:.1f} s")
-    else:
-        out["cpu_baseline"] = None
+    out.update(cpu_baseline_leg(args, eng, sim, d))
     eng.close()
     print(json.dumps(out), flush=True)
 
