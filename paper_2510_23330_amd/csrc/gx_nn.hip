@@ -709,11 +709,16 @@ __global__ void k_wflip(const uint16_t* __restrict__ w, int Cout, int Cin, int k
 // Backward weight: dW[co][k] += sum_m dOut[m][co] * A[m][k] over a chunk of
 // voxels per block.  Tiles: 64 K entries x BN output channels, voxels in steps
 // of 32, both operands transposed into LDS so MFMA fragments are contiguous.
+// With bpart, the blocks of the first K tile also sum dOut over their voxels
+// (the bias gradient) from the transposed tile already in LDS: thread t adds
+// channel t % BN over its share of each step's voxels, and the shares are
+// combined in order at the end.
 template <int BN>
 __global__ __launch_bounds__(256) void k_conv3d_wgrad(const uint16_t* __restrict__ in,
                                                       const uint16_t* __restrict__ dout,
                                                       ConvGeom g, int64_t m_per_block,
-                                                      float* __restrict__ part) {
+                                                      float* __restrict__ part,
+                                                      float* __restrict__ bpart) {
     constexpr int BKW = 64;                  // K tile (rows of dW^T)
     __shared__ __attribute__((aligned(16))) uint16_t sAt[BKW * CV_APITCH];  // [k][m]
     __shared__ __attribute__((aligned(16))) uint16_t sBt[BN * CV_APITCH];   // [co][m]
@@ -732,6 +737,10 @@ __global__ __launch_bounds__(256) void k_conv3d_wgrad(const uint16_t* __restrict
     f32x4 acc[NT];
 #pragma unroll
     for (int j = 0; j < NT; j++) acc[j] = f32x4{0, 0, 0, 0};
+    const bool do_bias = bpart != nullptr && blockIdx.x == 0;
+    constexpr int BPARTS = 256 / BN, BSPAN = 32 / BPARTS;  // voxels per thread and step
+    const int bc = tid % BN, bq = tid / BN;
+    float bsum = 0.0f;
     for (int64_t m0 = mb; m0 < me; m0 += 32) {
         // A^T: 32 voxels x 64 K entries -> 256 loads of 8 K entries
         {
@@ -754,6 +763,11 @@ __global__ __launch_bounds__(256) void k_conv3d_wgrad(const uint16_t* __restrict
             for (int q = 0; q < 8; q++) sBt[(grp * 8 + q) * CV_APITCH + mrow] = h[q];
         }
         __syncthreads();
+        if (do_bias) {
+            const uint16_t* r = &sBt[bc * CV_APITCH + bq * BSPAN];
+#pragma unroll
+            for (int q = 0; q < BSPAN; q++) bsum += bf2f(r[q]);
+        }
         const int kq = (lane >> 4) * 8;
         const bf16x8 a = *reinterpret_cast<const bf16x8*>(&sAt[(wv * 16 + (lane & 15)) * CV_APITCH + kq]);
 #pragma unroll
@@ -775,6 +789,17 @@ __global__ __launch_bounds__(256) void k_conv3d_wgrad(const uint16_t* __restrict
             const int co = n0 + j * 16 + (lane & 15);
             if (k < g.K) pc[(int64_t)co * g.K + k] = acc[j][t];
         }
+    if (do_bias) {
+        // the loop ended on a barrier, so the A tile's LDS is free
+        float* sb = reinterpret_cast<float*>(sAt);
+        sb[tid] = bsum;
+        __syncthreads();
+        if (tid < BN) {
+            float s = 0.0f;
+            for (int q = 0; q < BPARTS; q++) s += sb[q * BN + tid];
+            bpart[(int64_t)blockIdx.z * g.Cout + n0 + tid] = s;
+        }
+    }
 }
 
 // dw[e] += sum over chunks c (in order) of part[c][e]
@@ -787,30 +812,9 @@ __global__ void k_wgrad_reduce(const float* __restrict__ part, int64_t n, int ch
     dw[e] += s;
 }
 
-// Bias gradient: block b sums rows [b R, (b + 1) R) of dout[M][C] with 256 / C
-// row lanes per channel (C <= 256, a power of two >= 16), coalesced, and
-// writes its per-channel partial; k_bias_reduce adds the partials in block
-// order.
-__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ dout, int64_t M,
-                                                   int C, int64_t rows_per_block,
-                                                   float* __restrict__ part) {
-    __shared__ float sh[256];
-    const int c = threadIdx.x % C, rl = threadIdx.x / C, nrl = 256 / C;
-    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
-    const int64_t r1 = min(M, r0 + rows_per_block);
-    float s = 0.0f;
-    for (int64_t m = r0 + rl; m < r1; m += nrl) s += bf2f(dout[m * C + c]);
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x < C) {
-        float t = 0.0f;
-        for (int q = 0; q < nrl; q++) t += sh[q * C + threadIdx.x];
-        part[(int64_t)blockIdx.x * C + threadIdx.x] = t;
-    }
-}
-
-// One wave per channel: lane l sums blocks l, l + 64, ...; then the lanes in
-// a fixed butterfly order.
+// Bias gradient from the per-chunk partials of k_conv3d_wgrad: one wave per
+// channel, lane l sums chunks l, l + 64, ...; then the lanes in a fixed
+// butterfly order.
 __global__ __launch_bounds__(64) void k_bias_reduce(const float* __restrict__ part, int nb, int C,
                                                     float* __restrict__ db) {
     const int c = blockIdx.x;
@@ -1292,28 +1296,23 @@ extern "C" int gx_conv3d_bwd_weight(gx_ctx* ctx, const uint16_t* in, const uint1
     chunks = (g.M + mpb - 1) / mpb;
     dim3 grid(kt, nt, (unsigned)chunks);
     const int64_t nw = (int64_t)Cout * g.K;
-    // bias-gradient blocks: about 4,096 rows each, at most 256
-    const int nbb = (int)std::max<int64_t>(1, std::min<int64_t>(256, (g.M + 4095) / 4096));
-    GX_TRY(gx_reserve(ctx, ctx->wpart, (size_t)(chunks * nw + (int64_t)nbb * Cout) * sizeof(float)));
+    GX_TRY(gx_reserve(ctx, ctx->wpart, (size_t)(chunks * nw + chunks * Cout) * sizeof(float)));
     float* part = (float*)ctx->wpart.p;
-    float* bpart = part + chunks * nw;
+    float* bpart = dbias ? part + chunks * nw : nullptr;
     if (bn == 64)
-        hipLaunchKernelGGL(k_conv3d_wgrad<64>, grid, dim3(256), 0, ctx->stream, in, dout, g, mpb, part);
+        hipLaunchKernelGGL(k_conv3d_wgrad<64>, grid, dim3(256), 0, ctx->stream, in, dout, g, mpb, part,
+                           bpart);
     else if (bn == 32)
-        hipLaunchKernelGGL(k_conv3d_wgrad<32>, grid, dim3(256), 0, ctx->stream, in, dout, g, mpb, part);
+        hipLaunchKernelGGL(k_conv3d_wgrad<32>, grid, dim3(256), 0, ctx->stream, in, dout, g, mpb, part,
+                           bpart);
     else
-        hipLaunchKernelGGL(k_conv3d_wgrad<16>, grid, dim3(256), 0, ctx->stream, in, dout, g, mpb, part);
+        hipLaunchKernelGGL(k_conv3d_wgrad<16>, grid, dim3(256), 0, ctx->stream, in, dout, g, mpb, part,
+                           bpart);
     hipLaunchKernelGGL(k_wgrad_reduce, dim3(gx_blocks(nw, 256)), dim3(256), 0, ctx->stream, part, nw,
                        (int)chunks, dw);
-    if (dbias) {
-        if (Cout > 256 || !pow2(Cout))
-            return gx_fail(ctx, GX_EINVAL, "conv3d_bwd_weight: bias gradient needs Cout <= 256, a power of two");
-        const int64_t rpb = (g.M + nbb - 1) / nbb;
-        hipLaunchKernelGGL(k_bias_grad, dim3(nbb), dim3(256), 0, ctx->stream, dout, g.M, Cout, rpb,
-                           bpart);
-        hipLaunchKernelGGL(k_bias_reduce, dim3(Cout), dim3(64), 0, ctx->stream, bpart, nbb, Cout,
-                           dbias);
-    }
+    if (dbias)
+        hipLaunchKernelGGL(k_bias_reduce, dim3(Cout), dim3(64), 0, ctx->stream, bpart, (int)chunks,
+                           Cout, dbias);
     GX_LAUNCH_CHECK(ctx);
     return GX_OK;
 }
