@@ -17,7 +17,12 @@
  *             are host pointers.
  * Streams     Work is enqueued on the context's stream (gx_create / gx_set_stream)
  *             and is asynchronous unless stated otherwise.  Calls that fill a
- *             host gx_stats* or a host output synchronise that stream.
+ *             host gx_stats* or a host output synchronise that stream, and so
+ *             do the calls whose next launches depend on device-computed sizes
+ *             or convergence: gx_tree_build (twice), gx_gravity_forces in tree
+ *             mode (once: the list totals), gx_sph_density (once per Newton
+ *             pass and list round), gx_sph_forces (list totals, long-list
+ *             chunk count); each says so below.
  * Errors      Every int-returning call returns GX_OK (0) or a negative gx_status.
  *             gx_last_error() gives a message for the last failure on a context.
  *             No C++ exception crosses this interface.  A context serves one host
@@ -144,7 +149,9 @@ int gx_set_walk_stack_limit(gx_ctx* ctx, int entries);
  * n_leaf    1..64; n_group n_leaf..4096
  * perm_out  optional device int32[n]: perm_out[s] = original index of sorted slot s
  * stats     optional host; n_nodes and n_groups filled.  This call always
- *           synchronises once (node and group counts size the next kernels).
+ *           synchronises twice: the node count and level histogram size the
+ *           node arrays and the per-level moment launches, the group count
+ *           sizes the group list.
  */
 int gx_tree_build(gx_ctx* ctx, const gx_particles* p, int which, int n_leaf, int n_group,
                   int32_t* perm_out, gx_stats* stats);
@@ -168,6 +175,10 @@ int gx_tree_build(gx_ctx* ctx, const gx_particles* p, int which, int n_leaf, int
  * flags      GX_QUAD | GX_DIRECT | GX_PREC_FP64
  * ax..pot    device FP64 outputs [n], overwritten, original order
  * stats      optional host: n_pp, n_pc, n_groups, ms (synchronises)
+ * In tree mode the call synchronises once before the pairwise kernel: the
+ * list totals tell whether every group's list fit its slot (else the exact
+ * two-pass construction runs, with a second synchronisation).  GX_DIRECT
+ * without stats does not synchronise.
  */
 int gx_gravity_forces(gx_ctx* ctx, const gx_particles* p, double G, double theta, int flags,
                       double* ax, double* ay, double* az, double* pot, gx_stats* stats);
@@ -185,6 +196,9 @@ int gx_gravity_forces(gx_ctx* ctx, const gx_particles* p, double G, double theta
  * Uses the GX_TREE_GAS slot built from `gas`.  g->H64 seeds the iteration when
  * positive; otherwise a seed comes from the group's mean density.
  * Returns GX_ENOCONV (outputs still written) if any receiver hit max_iter.
+ * Synchronises after the candidate walk (list totals), after each pass over
+ * long lists and after each round (whether any group must be walked again
+ * with a larger radius).
  */
 int gx_sph_density(gx_ctx* ctx, const gx_particles* gas, gx_gas* g, double n_ngb, double gamma,
                    double tol, int max_iter, gx_stats* stats);
@@ -200,6 +214,8 @@ int gx_sph_density(gx_ctx* ctx, const gx_particles* gas, gx_gas* g, double n_ngb
  * from gx_sph_density; velocities from gas->vx/vy/vz and u from g->u.
  * ax, ay, az   device FP64 [n]: the hydro acceleration is ADDED to them
  * g->dudt, g->vsig  overwritten
+ * Synchronises after the candidate walk (list totals) and after counting the
+ * long lists' chunks (their number sizes the chunked pass).
  */
 int gx_sph_forces(gx_ctx* ctx, const gx_particles* gas, gx_gas* g, double gamma, double alpha,
                   double* ax, double* ay, double* az, gx_stats* stats);
