@@ -103,6 +103,8 @@ struct gx_ctx {
     Buf scan_tmp[3], hist, partial, small, host_small;
     Buf wpart;  // per-chunk partial weight gradients (ordered reduction)
     Buf wrel;   // 3^3 weights re-laid out chunk-major for the slab convolution
+    Buf xcm, ycm;  // channel-major copies of a layer's input and output gradient
+    Buf wpart2;    // group sums of the weight-gradient partials
     Buf sph_work[24];
     // > 0: the gravity walk's small stack holds only this many entries and is
     // tried first (set by gx_set_walk_stack_limit), so that its overflow and

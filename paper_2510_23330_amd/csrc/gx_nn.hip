@@ -30,6 +30,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 #define CV_BK 32
 #define CV_APITCH 40  // bf16 per LDS row (32 + 8 padding)
 #define LRELU_SLOPE 0.1f
+#ifndef GX_WG_WAVES
+#define GX_WG_WAVES 4096  // waves the channel-major weight gradient aims at
+#endif
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -802,6 +805,181 @@ __global__ __launch_bounds__(256) void k_conv3d_wgrad(const uint16_t* __restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// Weight gradient from channel-major operands.  dW[co][tap][ci] = sum over
+// voxels m of dY[m][co] * X[m + d(tap)][ci]: a matrix product whose
+// reduction runs over voxels, so each MFMA operand fragment is 8 consecutive
+// voxels of one channel.  With the layer input and output gradient copied to
+// channel-major order ([b][c][v]) once per layer, such a fragment is one
+// aligned 16-byte load: the y and z tap offsets move it by whole rows, and
+// the x offsets of -1 and +1 come from the same 8 voxels and their left and
+// right neighbours by byte alignment.
+// ---------------------------------------------------------------------------
+// out[b][c][v] = in[b][v][c] (bf16), one block per 64 voxels of one sample.
+__global__ __launch_bounds__(256) void k_to_cmajor(const uint16_t* __restrict__ in, int64_t V,
+                                                   int C, uint16_t* __restrict__ out) {
+    __shared__ uint16_t t[256 * 66];
+    const int64_t v0 = (int64_t)blockIdx.x * 64;
+    const int64_t b = v0 / V, vv = v0 - b * V;
+    const int cg8 = C / 8;
+    for (int e = threadIdx.x; e < 64 * cg8; e += 256) {
+        const int vox = e / cg8, cg = e - vox * cg8;
+        const uint4 d = *reinterpret_cast<const uint4*>(in + (v0 + vox) * C + cg * 8);
+        const uint16_t* h = reinterpret_cast<const uint16_t*>(&d);
+#pragma unroll
+        for (int q = 0; q < 8; q++) t[(cg * 8 + q) * 66 + vox] = h[q];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < C * 8; e += 256) {
+        const int c = e >> 3, seg = e & 7;
+        uint4 d;
+        uint16_t* h = reinterpret_cast<uint16_t*>(&d);
+#pragma unroll
+        for (int q = 0; q < 8; q++) h[q] = t[c * 66 + seg * 8 + q];
+        *reinterpret_cast<uint4*>(out + (b * C + c) * V + vv + seg * 8) = d;
+    }
+}
+
+// One wave per task: 16 input channels (ci block), one z offset of the taps
+// (all 9 of its (y, x) offsets; the single tap of a 1^3 kernel), 32 output
+// channels (co block), over one chunk of voxels in steps of 32.  Per step
+// each lane loads its 8 voxels of two output-gradient channels and, per y
+// offset, 8 voxels of its input channel plus the two neighbours, and the wave
+// issues 2 MFMAs per tap.  Partial results per chunk, reduced in chunk order
+// afterwards; the tasks of the first ci block and z offset also sum the
+// output gradient for the bias.
+template <int KS>
+__global__ __launch_bounds__(256) void k_wgrad_cm(const uint16_t* __restrict__ xt,
+                                                  const uint16_t* __restrict__ yt, int B, int lgS,
+                                                  int Cin, int Cout, int64_t m_per_chunk,
+                                                  float* __restrict__ part,
+                                                  float* __restrict__ bpart) {
+    constexpr int NDZ = KS == 3 ? 3 : 1, NT = KS == 3 ? 9 : 1;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int S = 1 << lgS;
+    const int64_t V = (int64_t)1 << (3 * lgS), M = (int64_t)B * V;
+    const int ncib = (Cin + 15) / 16, ncob = (Cout + 31) / 32;
+    const int task = blockIdx.y * 4 + wv;
+    if (task >= ncib * NDZ * ncob) return;  // no barrier in this kernel
+    const int cib = task % ncib, dzi = (task / ncib) % NDZ, cob = task / (ncib * NDZ);
+    const int dz = KS == 3 ? dzi - 1 : 0;
+    const int ci = cib * 16 + (lane & 15);
+    const bool civ = ci < Cin;
+    const int coa = cob * 32 + (lane & 15), cob2 = coa + 16;
+    const bool cva = coa < Cout, cvb = cob2 < Cout;
+    const bool do_bias = bpart != nullptr && cib == 0 && dzi == 0;
+    f32x4 acc[NT][2];
+#pragma unroll
+    for (int t = 0; t < NT; t++) acc[t][0] = acc[t][1] = f32x4{0, 0, 0, 0};
+    float bsa = 0.0f, bsb = 0.0f;
+    const int64_t mb = (int64_t)blockIdx.x * m_per_chunk;
+    const int64_t me = min(M, mb + m_per_chunk);
+    for (int64_t m0 = mb; m0 < me; m0 += 32) {
+        // this lane's 8 voxels: one x-row segment
+        const int64_t m = m0 + (lane >> 4) * 8;
+        const int64_t b = m >> (3 * lgS), v = m & (V - 1);
+        const int x0 = (int)(v & (S - 1)), y = (int)((v >> lgS) & (S - 1)),
+                  z = (int)(v >> (2 * lgS));
+        const uint4 zero4 = make_uint4(0, 0, 0, 0);
+        const uint4 ua = cva ? *reinterpret_cast<const uint4*>(yt + (b * Cout + coa) * V + v) : zero4;
+        const uint4 ub = cvb ? *reinterpret_cast<const uint4*>(yt + (b * Cout + cob2) * V + v) : zero4;
+        if (do_bias) {
+            const uint16_t* ha = reinterpret_cast<const uint16_t*>(&ua);
+            const uint16_t* hb = reinterpret_cast<const uint16_t*>(&ub);
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                bsa += bf2f(ha[q]);
+                bsb += bf2f(hb[q]);
+            }
+        }
+        bf16x8 ya, yb;
+        __builtin_memcpy(&ya, &ua, 16);
+        __builtin_memcpy(&yb, &ub, 16);
+        const int zz = z + dz;
+        const bool zv = civ && zz >= 0 && zz < S;
+#pragma unroll
+        for (int dyi = 0; dyi < NDZ; dyi++) {
+            const int dy = KS == 3 ? dyi - 1 : 0;
+            const int yy = y + dy;
+            uint4 c0 = zero4;
+            uint32_t left = 0, right = 0;
+            if (zv && yy >= 0 && yy < S) {
+                const uint16_t* row = xt + (b * Cin + ci) * V + ((int64_t)zz << (2 * lgS)) +
+                                      ((int64_t)yy << lgS);
+                c0 = *reinterpret_cast<const uint4*>(row + x0);
+                if (KS == 3) {
+                    if (x0 > 0) left = row[x0 - 1];
+                    if (x0 + 8 < S) right = row[x0 + 8];
+                }
+            }
+            bf16x8 f0;
+            __builtin_memcpy(&f0, &c0, 16);
+            if (KS == 3) {
+                // x offset +1: (e1 .. e8); x offset -1: (e-1 .. e6)
+                const uint32_t a0 = __builtin_amdgcn_alignbyte(c0.y, c0.x, 2);
+                const uint32_t a1 = __builtin_amdgcn_alignbyte(c0.z, c0.y, 2);
+                const uint32_t a2 = __builtin_amdgcn_alignbyte(c0.w, c0.z, 2);
+                const uint32_t a3 = __builtin_amdgcn_alignbyte(right, c0.w, 2);
+                const uint32_t g0 = __builtin_amdgcn_alignbyte(c0.x, left << 16, 2);
+                const uint4 up = make_uint4(a0, a1, a2, a3), um = make_uint4(g0, a0, a1, a2);
+                bf16x8 fp, fm;
+                __builtin_memcpy(&fp, &up, 16);
+                __builtin_memcpy(&fm, &um, 16);
+                const int tb = dyi * 3;  // tap index within this z offset: dy * 3 + dx
+                acc[tb + 0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fm, ya, acc[tb + 0][0], 0, 0, 0);
+                acc[tb + 0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fm, yb, acc[tb + 0][1], 0, 0, 0);
+                acc[tb + 1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f0, ya, acc[tb + 1][0], 0, 0, 0);
+                acc[tb + 1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f0, yb, acc[tb + 1][1], 0, 0, 0);
+                acc[tb + 2][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fp, ya, acc[tb + 2][0], 0, 0, 0);
+                acc[tb + 2][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fp, yb, acc[tb + 2][1], 0, 0, 0);
+            } else {
+                acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f0, ya, acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f0, yb, acc[0][1], 0, 0, 0);
+            }
+        }
+    }
+    // acc[t][h][r]: ci = cib * 16 + 4 * (lane / 16) + r, co = cob * 32 + 16 h + lane % 16
+    const int K = (KS == 3 ? 27 : 1) * Cin;
+    float* pc = part + (int64_t)blockIdx.x * Cout * K;
+#pragma unroll
+    for (int t = 0; t < NT; t++) {
+        const int tap = dzi * 9 * (KS == 3 ? 1 : 0) + t;
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int co = cob * 32 + 16 * h + (lane & 15);
+            if (co >= Cout) continue;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int c = cib * 16 + 4 * (lane >> 4) + r;
+                if (c < Cin) pc[(int64_t)co * K + tap * Cin + c] = acc[t][h][r];
+            }
+        }
+    }
+    if (do_bias) {
+        // lanes l, l + 16, l + 32, l + 48 hold the same channels
+        bsa += __shfl_xor(bsa, 16, 64);
+        bsa += __shfl_xor(bsa, 32, 64);
+        bsb += __shfl_xor(bsb, 16, 64);
+        bsb += __shfl_xor(bsb, 32, 64);
+        if (lane < 16) {
+            if (cva) bpart[(int64_t)blockIdx.x * Cout + coa] = bsa;
+            if (cvb) bpart[(int64_t)blockIdx.x * Cout + cob2] = bsb;
+        }
+    }
+}
+
+// out[g][e] = sum over chunks c of group g (chunks gG .. gG + G - 1, in order)
+// of part[c][e]: the first of two ordered levels when there are many chunks
+__global__ void k_wgrad_group_sum(const float* __restrict__ part, int64_t n, int chunks, int G,
+                                  float* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int c0 = blockIdx.y * G, c1 = min(chunks, c0 + G);
+    float s = 0.0f;
+    for (int c = c0; c < c1; c++) s += part[(int64_t)c * n + e];
+    out[(int64_t)blockIdx.y * n + e] = s;
+}
+
 // dw[e] += sum over chunks c (in order) of part[c][e]
 __global__ void k_wgrad_reduce(const float* __restrict__ part, int64_t n, int chunks,
                                float* __restrict__ dw) {
@@ -1277,6 +1455,60 @@ extern "C" int gx_conv3d_bwd_data(gx_ctx* ctx, const uint16_t* dout, int B, int 
     return launch_conv(ctx, dout, wf, nullptr, g, y_in ? EP_DACT : EP_NONE, y_in, din, nullptr);
 }
 
+// Weight and bias gradients through channel-major copies (k_wgrad_cm): the
+// voxel range is split into chunks so that the tasks fill the device, each
+// chunk writes its partial gradient, and the partials are added in chunk order.
+static int wgrad_cmajor(gx_ctx* ctx, const uint16_t* in, const uint16_t* dout, const ConvGeom& g,
+                        float* dw, float* dbias) {
+    const int64_t V = (int64_t)g.S * g.S * g.S, M = g.M;
+    const int lgS = ilog2(g.S);
+    GX_TRY(gx_reserve(ctx, ctx->xcm, (size_t)M * g.Cin * sizeof(uint16_t)));
+    GX_TRY(gx_reserve(ctx, ctx->ycm, (size_t)M * g.Cout * sizeof(uint16_t)));
+    uint16_t* xt = (uint16_t*)ctx->xcm.p;
+    uint16_t* yt = (uint16_t*)ctx->ycm.p;
+    hipLaunchKernelGGL(k_to_cmajor, dim3((unsigned)(M / 64)), dim3(256), 0, ctx->stream, in, V,
+                       g.Cin, xt);
+    hipLaunchKernelGGL(k_to_cmajor, dim3((unsigned)(M / 64)), dim3(256), 0, ctx->stream, dout, V,
+                       g.Cout, yt);
+    const int ndz = g.kvol == 27 ? 3 : 1;
+    const int tasks = ((g.Cin + 15) / 16) * ndz * ((g.Cout + 31) / 32);
+    const int ty = (tasks + 3) / 4;
+    // chunks of whole 32-voxel steps, aiming at ~GX_WG_WAVES waves in all
+    int64_t chunks = std::min<int64_t>(4096, std::max<int64_t>(1, (GX_WG_WAVES + tasks - 1) / tasks));
+    int64_t mpc = (M + chunks - 1) / chunks;
+    mpc = std::max<int64_t>(32, ((mpc + 31) / 32) * 32);
+    chunks = (M + mpc - 1) / mpc;
+    const int64_t nw = (int64_t)g.Cout * g.K;
+    GX_TRY(gx_reserve(ctx, ctx->wpart, (size_t)(chunks * nw + chunks * g.Cout) * sizeof(float)));
+    float* part = (float*)ctx->wpart.p;
+    float* bpart = dbias ? part + chunks * nw : nullptr;
+    const dim3 grid((unsigned)chunks, (unsigned)ty);
+    if (g.kvol == 27)
+        hipLaunchKernelGGL(k_wgrad_cm<3>, grid, dim3(256), 0, ctx->stream, xt, yt, g.B, lgS, g.Cin,
+                           g.Cout, mpc, part, bpart);
+    else
+        hipLaunchKernelGGL(k_wgrad_cm<1>, grid, dim3(256), 0, ctx->stream, xt, yt, g.B, lgS, g.Cin,
+                           g.Cout, mpc, part, bpart);
+    if (chunks > 64) {
+        // two ordered levels: groups of 32 chunks, then the group sums
+        const int ngr = (int)((chunks + 31) / 32);
+        GX_TRY(gx_reserve(ctx, ctx->wpart2, (size_t)ngr * nw * sizeof(float)));
+        float* p2 = (float*)ctx->wpart2.p;
+        hipLaunchKernelGGL(k_wgrad_group_sum, dim3(gx_blocks(nw, 256), ngr), dim3(256), 0,
+                           ctx->stream, part, nw, (int)chunks, 32, p2);
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3(gx_blocks(nw, 256)), dim3(256), 0, ctx->stream, p2,
+                           nw, ngr, dw);
+    } else {
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3(gx_blocks(nw, 256)), dim3(256), 0, ctx->stream, part,
+                           nw, (int)chunks, dw);
+    }
+    if (dbias)
+        hipLaunchKernelGGL(k_bias_reduce, dim3(g.Cout), dim3(64), 0, ctx->stream, bpart, (int)chunks,
+                           g.Cout, dbias);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
 extern "C" int gx_conv3d_bwd_weight(gx_ctx* ctx, const uint16_t* in, const uint16_t* dout, int B,
                                     int S, int Cin, int ksize, int Cout, float* dw, float* dbias) {
     if (!ctx || !in || !dout || !dw) return GX_EINVAL;
@@ -1284,6 +1516,8 @@ extern "C" int gx_conv3d_bwd_weight(gx_ctx* ctx, const uint16_t* in, const uint1
     GX_HIP(ctx, hipSetDevice(ctx->device));
     const int kv = ksize == 3 ? 27 : 1;
     ConvGeom g{B, S, Cin, Cout, kv, (int64_t)B * S * S * S, kv * Cin, ilog2(Cin)};
+    if (pow2(S) && S >= 8 && Cin <= 256 && Cout <= 256)
+        return wgrad_cmajor(ctx, in, dout, g, dw, dbias);
     const int kt = (g.K + 63) / 64;
     const int bn = Cout % 64 == 0 ? 64 : (Cout % 32 == 0 ? 32 : 16);
     const int nt = Cout / bn;

@@ -115,6 +115,11 @@ extern "C" int gx_destroy(gx_ctx* ctx) {
     free_buf(ctx->hist);
     free_buf(ctx->partial);
     free_buf(ctx->small);
+    free_buf(ctx->wpart);
+    free_buf(ctx->wrel);
+    free_buf(ctx->xcm);
+    free_buf(ctx->ycm);
+    free_buf(ctx->wpart2);
     if (ctx->host_small.p) (void)hipHostFree(ctx->host_small.p);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);

@@ -92,8 +92,13 @@ def test_conv_bwd_data(gx, eng, B, S, Cin, Cout, k):
     assert _close(_np(din), ref2)
 
 
+# power-of-two grids of at least 8 take the channel-major kernel (including
+# half-filled 16-channel input blocks and 32-channel output blocks); other
+# grids the LDS-transposing one
 @pytest.mark.parametrize("B,S,Cin,Cout,k", [(2, 8, 8, 16, 3), (1, 8, 32, 64, 3), (2, 6, 32, 16, 1),
-                                             (1, 16, 16, 32, 3)])
+                                             (1, 16, 16, 32, 3), (1, 32, 64, 32, 3),
+                                             (1, 8, 256, 16, 1), (2, 12, 16, 48, 3),
+                                             (1, 16, 128, 256, 3)])
 def test_conv_bwd_weight(gx, eng, B, S, Cin, Cout, k):
     import torch
     rng = np.random.default_rng(11 + Cout)
