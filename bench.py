@@ -44,6 +44,7 @@ METRIC = "interactions/s & s/step at 16M particles; SN region: surrogate vs plai
 YEAR_IN_KPC_TIME = 1.0 / 0.97779e9  # time unit kpc/(km/s) = 0.97779 Gyr
 PEAK_FP32 = 157.3e12                 # MI355X FP32 vector, FLOP/s
 HBM_PEAK = 8.0e12                    # B/s
+TREE_BYTES_PER_PARTICLE = 330        # algorithmic bytes of one tree build per particle
 FLOP_PP = 27                         # per particle-particle interaction (Table 4 convention)
 FLOP_PC = 63                         # per particle-cell interaction, monopole + quadrupole
 FLOP_DENS = 73                       # per SPH density candidate pair evaluation (Table 4)
@@ -168,7 +169,7 @@ def force_errors(eng, sim, n_recv=256, seed=31):
     acc = [torch.zeros(p1.n, dtype=torch.float64, device="cuda") for _ in range(4)]
     eng.tree_build(p1, gx.GX_TREE_ALL, 16, 256)
     eng.gravity_forces(p1, G, 0.5, gx.GX_QUAD, *acc)
-    idx = ics.sample_indices(p1.n, 1000, 17)
+    idx = ics.sample_indices(p1.n, 16384, 17)
     ref = oracle.direct_gravity(d1, G, idx)
     out["disk1M_tree_vs_fp64_direct"] = dict(
         _err_stats([a.cpu().numpy()[idx] for a in acc[:3]], ref[:3]),
@@ -183,6 +184,25 @@ def force_errors(eng, sim, n_recv=256, seed=31):
         _err_stats([a.cpu().numpy() for a in acc[:3]], ref[:3]), receivers="all 8192")
     out["targets_p99"] = {"tree": 1e-3, "direct": 1e-5}
     return out
+
+
+def hbm_phases(n_part, n_gas, tree_ms, kd_ms):
+    """The HBM-bound phases against 8 TB/s with their algorithmic bytes: both
+    tree builds at ~330 B per particle (keys, 8 sort passes, permute, cells,
+    moments), and the four kick/drift calls of a step (stars 192 B, gas 272 B
+    per particle: positions, velocities, accelerations, u, du/dt, the
+    predictions)."""
+    n_star = n_part - n_gas
+    tree_b = TREE_BYTES_PER_PARTICLE * (n_part + n_gas)
+    kd_b = 192 * n_star + 272 * n_gas
+    return {
+        "tree_builds": {"bytes": tree_b, "ms": tree_ms, "GB_s": tree_b / tree_ms / 1e6,
+                        "frac": tree_b / (tree_ms / 1e3) / HBM_PEAK,
+                        "note": "a chain of small dependent kernels (sort passes, cells, one "
+                                "moment launch per level): launch- and latency-bound"},
+        "kick_drift": {"bytes": kd_b, "ms": kd_ms, "GB_s": kd_b / kd_ms / 1e6,
+                       "frac": kd_b / (kd_ms / 1e3) / HBM_PEAK},
+        "peak_GB_s": HBM_PEAK / 1e9}
 
 
 def cpu_baseline_leg(args, eng, sim, d):
@@ -201,8 +221,34 @@ def cpu_baseline_leg(args, eng, sim, d):
     if args.cpu_groups > 0:
         t0 = time.perf_counter()
         res["cpu_baseline"] = cpu_baseline(d, args.cpu_groups, 99)
+        res["cpu_baseline"]["one_thread_disk1M"] = oracle_one_thread_disk1M()
         log(f"[bench] cpu baseline {time.perf_counter() - t0:.1f} s")
     return res
+
+
+def oracle_one_thread_disk1M(n_groups=256, seed=98):
+    """The oracle's tree gravity on one host thread for a seeded sample of
+    the 1M disk's groups, in a child process started with OMP_NUM_THREADS=1
+    (it touches no GPU)."""
+    import subprocess
+    code = ("import time, ics, oracle\n"
+            "d = ics.disk_galaxy(1_000_000, 3)\n"
+            "T = oracle.Tree(d, 16, 256)\n"
+            f"g = ics.sample_indices(T.n_groups, {n_groups}, {seed})\n"
+            "t0 = time.perf_counter()\n"
+            "r = T.gravity_groups(g, ics.G_KPC, 0.5, True)\n"
+            "dt = time.perf_counter() - t0\n"
+            "print(r[4] + r[5], dt, T.n_groups)\n")
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True,
+                             text=True, timeout=600, check=True).stdout.split()
+    except (subprocess.SubprocessError, OSError) as e:
+        return {"error": str(e)[:200]}
+    inter, dt, ng = float(out[-3]), float(out[-2]), int(out[-1])
+    return {"value": inter / dt, "unit": "interactions/s", "cores": 1,
+            "sample": f"FP64 oracle tree gravity for {n_groups} of {ng} groups of the 1M disk "
+                      f"({inter:.3e} interactions in {dt:.2f} s)"}
 
 
 def cpu_baseline(d, n_groups_sample, seed):
@@ -334,7 +380,7 @@ def main():
     cfg = StepConfig(G=ics.G_KPC, dt=2000.0 * YEAR_IN_KPC_TIME, theta=0.5, quad=True,
                      n_leaf=args.n_leaf, n_group=args.n_group, sph_leaf=args.sph_leaf,
                      sph_group=args.sph_group, n_ngb=64.0, u_floor=10.0 * ics.U_PER_K)
-    sim = GalaxyStep(eng, p, int(d["gas_offset"]), u, cfg)
+    sim = GalaxyStep(eng, p, int(d["gas_offset"]), u, cfg, timing=True)
     coupling = None
     if args.sn_sites > 0:
         from paper_2510_23330_amd.coupling import SNCoupling
@@ -382,6 +428,7 @@ def main():
     n_dens_eval = n_dens_ngb = n_force_list = n_force_ngb = 0
     energies = []
     walk_diag = []
+    kd_ev, list_sizes = [], []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for k in range(args.steps):
@@ -396,6 +443,8 @@ def main():
         hydro_ms.append(st["hydro"]["ms"])
         tree_ms.append(st["tree_all"]["ms"] + st["tree_gas"]["ms"])
         walk_diag.append((st["gravity"]["n_rewalk"], st["gravity"]["n_iter_max"]))
+        kd_ev.append(st["kd_events"])
+        list_sizes.append(eng.gravity_list_sizes())
         n_pp += st["gravity"]["n_pp"]
         n_pc += st["gravity"]["n_pc"]
         n_sph += st["density"]["n_sph_list"] + st["hydro"]["n_sph_list"]
@@ -410,6 +459,8 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_step = elapsed / args.steps * 1e3
+    kd_ms = float(np.mean([e[0].elapsed_time(e[1]) + e[2].elapsed_time(e[3]) for e in kd_ev]))
+    walk_ms = float(np.mean(grav_ms) - np.mean(grav_kernel_ms))
     sn_async = None
     applied_at_end = 0
     if coupling is not None:
@@ -485,7 +536,9 @@ def main():
         "phase_ms": {"tree_builds": float(np.mean(tree_ms)), "gravity": float(np.mean(grav_ms)),
                      "gravity_kernel": float(np.mean(grav_kernel_ms)),
                      "sph_density": float(np.mean(dens_ms)), "sph_force": float(np.mean(hydro_ms)),
+                     "kick_drift": kd_ms,
                      "sn_surrogate": float(np.mean(sn_ms)) if sn_ms else None},
+        "ms_per_step_median": float(np.median(per)) * 1e3,
         "sn_coupling": None if coupling is None else dict(
             coupling.stats, sites_per_step=args.sn_sites, delay_steps=50, mode=args.sn_mode,
             handovers_applied_after_timing=applied_at_end,
@@ -512,7 +565,17 @@ def main():
                               "only pairs inside the kernel supports (density: summed over the "
                               "kernel-size passes)"},
         "gravity_lists": {"two_pass_steps": int(sum(w[0] for w in walk_diag)),
-                          "max_walk_stack": int(max(w[1] for w in walk_diag))},
+                          "max_walk_stack": int(max(w[1] for w in walk_diag)),
+                          "pc_entries_per_step": float(np.mean([l[1] for l in list_sizes])),
+                          "pp_ranges_per_step": float(np.mean([l[2] for l in list_sizes])),
+                          "walk_ms": walk_ms,
+                          "list_entries_per_s": float(np.mean([l[1] + l[2] for l in list_sizes]))
+                          / (walk_ms / 1e3),
+                          "note": "walk_ms = gravity call minus its pairwise kernel (the list "
+                                  "walk, the list totals and one host round trip); the walk is "
+                                  "latency-bound"},
+        "hbm_phases": hbm_phases(n_part=args.n, n_gas=sim.ng, tree_ms=float(np.mean(tree_ms)),
+                                 kd_ms=kd_ms),
         "energy_drift_rel": abs(E1 - E0) / abs(E0),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": grav_traffic_bytes(args.ic_order),

@@ -272,6 +272,13 @@ class Engine:
             "eps2bar", "lo", "hi", "groups"))))
         return o
 
+    def gravity_list_sizes(self):
+        """(groups, pc entries, pp ranges) of the last gravity call's lists
+        (host values kept by the context; no device access)."""
+        ng, npc, npr = C.c_int64(), C.c_int64(), C.c_int64()
+        self._check(self.lib.gx_gravity_list_sizes(self.ctx, C.byref(ng), C.byref(npc), C.byref(npr)))
+        return ng.value, npc.value, npr.value
+
     def gravity_lists(self):
         ng, npc, npr = C.c_int64(), C.c_int64(), C.c_int64()
         self._check(self.lib.gx_gravity_list_sizes(self.ctx, C.byref(ng), C.byref(npc), C.byref(npr)))

@@ -46,6 +46,8 @@ class GalaxyStep:
     u: object
     cfg: StepConfig
     stats: dict = field(default_factory=dict)
+    # record timing events around the kick/drift calls (stats["kd_events"])
+    timing: bool = False
 
     def __post_init__(self):
         import torch
@@ -97,9 +99,16 @@ class GalaxyStep:
     def initial_forces(self):
         self.forces(predicted=False)
 
+    def _event(self):
+        import torch
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(self.eng.stream or torch.cuda.current_stream())
+        return e
+
     def step(self):
         c, o, n = self.cfg, self.gas_offset, self.p.n
         dt = c.dt
+        ev = [self._event()] if self.timing else None
         # (1) half kick + (2) drift; gas also predicts v and u at the drifted positions
         if o > 0:
             self.eng.kick_drift(self.stars, dt / 2, dt, *self._acc(0, o))
@@ -107,14 +116,21 @@ class GalaxyStep:
             self.eng.kick_drift(self.gas, dt / 2, dt, *self._acc(o, n), u=self.g.u,
                                 dudt=self.g.dudt, u_floor=c.u_floor, vpred=self.vpred,
                                 upred=self.upred)
+        if ev:
+            ev.append(self._event())
         # (3) forces
         self.forces(predicted=True)
+        if ev:
+            ev.append(self._event())
         # (4) second half kick
         if o > 0:
             self.eng.kick_drift(self.stars, dt / 2, 0.0, *self._acc(0, o))
         if self.ng:
             self.eng.kick_drift(self.gas, dt / 2, 0.0, *self._acc(o, n), u=self.g.u,
                                 dudt=self.g.dudt, u_floor=c.u_floor)
+        if ev:
+            ev.append(self._event())
+            self.stats["kd_events"] = ev
         return self.stats
 
     def energy(self):
