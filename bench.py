@@ -57,9 +57,9 @@ FLOP_FORCE = 101                     # per SPH force candidate pair (Table 4)
 # all of them).  Valid only for the kernel source with this SHA-256 and the
 # particle order named (the outputs are scattered to the caller's order); any
 # change to gx_gravity.hip, or the other order, makes the bench report null.
-GRAV_TRAFFIC = {"source_sha256": "1349b22688d7ca533d65c1ce4b223cb86c2e54ab19a9ade1d4b11260bc5f02d7",
+GRAV_TRAFFIC = {"source_sha256": "f4017782473c36415ef613041e522fded6e7c05565c2d168b077cfb1a4884057",
                 "particle_order": "morton",
-                "fetch_kib": 3679386.875, "write_kib": 2310470.25,
+                "fetch_kib": 3512425.75, "write_kib": 1480535.15625,
                 "fetch_scale": 2.0, "write_scale": 1.0}
 
 

@@ -192,19 +192,22 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1))) void k_grav_force(
 
         // ---- particle-cell part: accepted cells -----------------------------
         // each thread's record of the next tile is read into registers while
-        // the current tile is evaluated
+        // the current tile is evaluated; entries are addressed from the
+        // group's (uniform) list start with 32-bit offsets
         V4<T> na{}, nb{}, nc{};
-        auto fetch_cell = [&](int64_t t) {
-            if (tid < GF_TILE && t < c1) {
-                const MomRec mr = mom[pc_list[t]];
+        const int32_t* __restrict__ plist = pc_list + c0;
+        const int ncell = (int)(c1 - c0);
+        auto fetch_cell = [&](int t) {
+            if (tid < GF_TILE && t < ncell) {
+                const MomRec mr = mom[plist[t]];
                 na = V4<T>{(T)(mr.cx - cx), (T)(mr.cy - cy), (T)(mr.cz - cz), (T)mr.M};
                 nb = V4<T>{(T)mr.e2, (T)mr.q[0], (T)mr.q[1], (T)mr.q[2]};
                 nc = V4<T>{(T)mr.q[3], (T)mr.q[4], (T)mr.q[5], (T)0};
             }
         };
-        fetch_cell(c0 + tid);
-        for (int64_t t0 = c0; t0 < c1; t0 += GF_TILE) {
-            const int tn = (int)min((int64_t)GF_TILE, c1 - t0);
+        fetch_cell(tid);
+        for (int t0 = 0; t0 < ncell; t0 += GF_TILE) {
+            const int tn = min(GF_TILE, ncell - t0);
             if (tid < tn) {
                 sA[tid] = na;
                 if (QUAD) {
