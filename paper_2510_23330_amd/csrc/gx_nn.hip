@@ -33,6 +33,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 #ifndef GX_WG_WAVES
 #define GX_WG_WAVES 4096  // waves the channel-major weight gradient aims at
 #endif
+#ifndef GX_WG_BLOCKS
+#define GX_WG_BLOCKS 512  // blocks the LDS-staged weight gradient aims at
+#endif
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -968,6 +971,150 @@ __global__ __launch_bounds__(256) void k_wgrad_cm(const uint16_t* __restrict__ x
     }
 }
 
+// The same product for grids of 32^3 and 64^3 with the operands staged in
+// LDS: a block of three waves (one per z offset of the taps) takes tiles of
+// 256 output voxels (R = 256 / S rows of one z plane) for one block of 16
+// input and 32 output channels.  Per tile it stages the input rows the 27
+// taps read (3 planes x (R + 2) rows x S voxels x 16 channels, from the
+// channel-major copy, rows padded by 8 zeros on each side so the x offsets
+// of -1 and +1 read zeros at the volume's edge) and the tile's output
+// gradient (32 channels x 256 voxels), then runs its 8 steps of 32 voxels
+// from LDS: per step and wave 3 x (one 16-byte read and two neighbours) and
+// two 16-byte gradient reads feed 18 MFMAs.  Each block takes a run of
+// consecutive tiles and writes one partial gradient.
+template <int LGS>
+__global__ __launch_bounds__(192) void k_wgrad_lds(const uint16_t* __restrict__ xt,
+                                                   const uint16_t* __restrict__ yt, int B, int Cin,
+                                                   int Cout, int tiles_per_block,
+                                                   float* __restrict__ part,
+                                                   float* __restrict__ bpart) {
+    constexpr int S = 1 << LGS, R = 256 / S, XP = S + 16, YP = 256 + 8;
+    constexpr int64_t V = (int64_t)S * S * S;
+    __shared__ __attribute__((aligned(16))) uint16_t sx[3][R + 2][16][XP];
+    __shared__ __attribute__((aligned(16))) uint16_t sy[32][YP];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int ncib = (Cin + 15) / 16;
+    const int cib = blockIdx.y % ncib, cob = blockIdx.y / ncib;
+    const int ntiles = B * S * (S / R);
+    const int t0 = blockIdx.x * tiles_per_block, t1 = min(ntiles, t0 + tiles_per_block);
+    // the pads of every staged row stay zero
+    for (int e = tid; e < 3 * (R + 2) * 16; e += 192) {
+        uint16_t* row = &sx[0][0][0][0] + (int64_t)e * XP;
+        *reinterpret_cast<uint4*>(row) = make_uint4(0, 0, 0, 0);
+        *reinterpret_cast<uint4*>(row + 8 + S) = make_uint4(0, 0, 0, 0);
+    }
+    const int cl = lane & 15;  // this lane's input channel (A rows) and output channel (B cols)
+    const int coa = cob * 32 + cl, cob2 = coa + 16;
+    const bool cva = coa < Cout, cvb = cob2 < Cout;
+    const bool do_bias = bpart != nullptr && cib == 0 && wv == 0;
+    f32x4 acc[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; t++) acc[t][0] = acc[t][1] = f32x4{0, 0, 0, 0};
+    float bsa = 0.0f, bsb = 0.0f;
+    for (int tile = t0; tile < t1; tile++) {
+        const int plane = tile / (S / R), y0 = (tile % (S / R)) * R;
+        const int b = plane >> LGS, z = plane & (S - 1);
+        __syncthreads();  // the previous tile's reads are done
+        // input rows: (plane p, row r, channel c, 8-voxel chunk k)
+        constexpr int XCH = 3 * (R + 2) * 16 * (S / 8);
+        for (int e = tid; e < XCH; e += 192) {
+            const int k = e % (S / 8);
+            const int c = (e / (S / 8)) % 16;
+            const int r = (e / (S / 8 * 16)) % (R + 2);
+            const int pz = e / (S / 8 * 16 * (R + 2));
+            const int zz = z + pz - 1, yy = y0 + r - 1, ci = cib * 16 + c;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (zz >= 0 && zz < S && yy >= 0 && yy < S && ci < Cin)
+                v = *reinterpret_cast<const uint4*>(
+                    xt + ((int64_t)b * Cin + ci) * V + ((int64_t)zz << (2 * LGS)) +
+                    ((int64_t)yy << LGS) + k * 8);
+            *reinterpret_cast<uint4*>(&sx[pz][r][c][8 + k * 8]) = v;
+        }
+        // output gradient of the tile: (channel c, 8-voxel chunk k)
+        const int64_t vb = ((int64_t)z << (2 * LGS)) + ((int64_t)y0 << LGS);
+        for (int e = tid; e < 32 * 32; e += 192) {
+            const int k = e & 31, c = e >> 5, co = cob * 32 + c;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (co < Cout)
+                v = *reinterpret_cast<const uint4*>(yt + ((int64_t)b * Cout + co) * V + vb + k * 8);
+            *reinterpret_cast<uint4*>(&sy[c][k * 8]) = v;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int st = 0; st < 8; st++) {
+            const int t = st * 32 + (lane >> 4) * 8;  // this lane's 8 voxels in the tile
+            const int r = t >> LGS, x0 = t & (S - 1);
+            uint4 ua = *reinterpret_cast<const uint4*>(&sy[cl][t]);
+            uint4 ub = *reinterpret_cast<const uint4*>(&sy[cl + 16][t]);
+            if (!cva) ua = make_uint4(0, 0, 0, 0);
+            if (!cvb) ub = make_uint4(0, 0, 0, 0);
+            if (do_bias) {
+                const uint16_t* ha = reinterpret_cast<const uint16_t*>(&ua);
+                const uint16_t* hb = reinterpret_cast<const uint16_t*>(&ub);
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    bsa += bf2f(ha[q]);
+                    bsb += bf2f(hb[q]);
+                }
+            }
+            bf16x8 ya, yb;
+            __builtin_memcpy(&ya, &ua, 16);
+            __builtin_memcpy(&yb, &ub, 16);
+#pragma unroll
+            for (int dyi = 0; dyi < 3; dyi++) {
+                const uint16_t* row = &sx[wv][r + dyi][cl][8];
+                const uint4 c0 = *reinterpret_cast<const uint4*>(row + x0);
+                const uint32_t left = row[x0 - 1], right = row[x0 + 8];
+                const uint32_t a0 = __builtin_amdgcn_alignbyte(c0.y, c0.x, 2);
+                const uint32_t a1 = __builtin_amdgcn_alignbyte(c0.z, c0.y, 2);
+                const uint32_t a2 = __builtin_amdgcn_alignbyte(c0.w, c0.z, 2);
+                const uint32_t a3 = __builtin_amdgcn_alignbyte(right, c0.w, 2);
+                const uint32_t g0 = __builtin_amdgcn_alignbyte(c0.x, left << 16, 2);
+                const uint4 up = make_uint4(a0, a1, a2, a3), um = make_uint4(g0, a0, a1, a2);
+                bf16x8 f0, fp, fm;
+                __builtin_memcpy(&f0, &c0, 16);
+                __builtin_memcpy(&fp, &up, 16);
+                __builtin_memcpy(&fm, &um, 16);
+                const int tb = dyi * 3;
+                acc[tb + 0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fm, ya, acc[tb + 0][0], 0, 0, 0);
+                acc[tb + 0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fm, yb, acc[tb + 0][1], 0, 0, 0);
+                acc[tb + 1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f0, ya, acc[tb + 1][0], 0, 0, 0);
+                acc[tb + 1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f0, yb, acc[tb + 1][1], 0, 0, 0);
+                acc[tb + 2][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fp, ya, acc[tb + 2][0], 0, 0, 0);
+                acc[tb + 2][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fp, yb, acc[tb + 2][1], 0, 0, 0);
+            }
+        }
+    }
+    // acc[t][h][r]: ci = cib * 16 + 4 * (lane / 16) + r, co = cob * 32 + 16 h + lane % 16,
+    // tap = wv * 9 + t
+    const int K = 27 * Cin;
+    float* pc = part + (int64_t)blockIdx.x * Cout * K;
+#pragma unroll
+    for (int t = 0; t < 9; t++) {
+        const int tap = wv * 9 + t;
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int co = cob * 32 + 16 * h + cl;
+            if (co >= Cout) continue;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int c = cib * 16 + 4 * (lane >> 4) + r;
+                if (c < Cin) pc[(int64_t)co * K + tap * Cin + c] = acc[t][h][r];
+            }
+        }
+    }
+    if (do_bias) {
+        bsa += __shfl_xor(bsa, 16, 64);
+        bsa += __shfl_xor(bsa, 32, 64);
+        bsb += __shfl_xor(bsb, 16, 64);
+        bsb += __shfl_xor(bsb, 32, 64);
+        if (lane < 16) {
+            if (cva) bpart[(int64_t)blockIdx.x * Cout + coa] = bsa;
+            if (cvb) bpart[(int64_t)blockIdx.x * Cout + cob2] = bsb;
+        }
+    }
+}
+
 // out[g][e] = sum over chunks c of group g (chunks gG .. gG + G - 1, in order)
 // of part[c][e]: the first of two ordered levels when there are many chunks
 __global__ void k_wgrad_group_sum(const float* __restrict__ part, int64_t n, int chunks, int G,
@@ -1455,6 +1602,55 @@ extern "C" int gx_conv3d_bwd_data(gx_ctx* ctx, const uint16_t* dout, int B, int 
     return launch_conv(ctx, dout, wf, nullptr, g, y_in ? EP_DACT : EP_NONE, y_in, din, nullptr);
 }
 
+// Sums the per-chunk partials (in chunk order; two ordered levels beyond 64
+// chunks) into dw and the bias partials into dbias.
+static int wgrad_reduce_chunks(gx_ctx* ctx, const float* part, const float* bpart, int64_t nw,
+                               int64_t chunks, int Cout, float* dw, float* dbias) {
+    if (chunks > 64) {
+        const int ngr = (int)((chunks + 31) / 32);
+        GX_TRY(gx_reserve(ctx, ctx->wpart2, (size_t)ngr * nw * sizeof(float)));
+        float* p2 = (float*)ctx->wpart2.p;
+        hipLaunchKernelGGL(k_wgrad_group_sum, dim3(gx_blocks(nw, 256), ngr), dim3(256), 0,
+                           ctx->stream, part, nw, (int)chunks, 32, p2);
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3(gx_blocks(nw, 256)), dim3(256), 0, ctx->stream, p2,
+                           nw, ngr, dw);
+    } else {
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3(gx_blocks(nw, 256)), dim3(256), 0, ctx->stream, part,
+                           nw, (int)chunks, dw);
+    }
+    if (dbias)
+        hipLaunchKernelGGL(k_bias_reduce, dim3(Cout), dim3(64), 0, ctx->stream, bpart, (int)chunks,
+                           Cout, dbias);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+// 3^3 weight gradient on 32^3 and 64^3 grids with LDS-staged operands
+// (k_wgrad_lds); xt, yt are the channel-major copies.
+static int wgrad_staged(gx_ctx* ctx, const uint16_t* xt, const uint16_t* yt, const ConvGeom& g,
+                        float* dw, float* dbias) {
+    const int ncib = (g.Cin + 15) / 16, ncob = (g.Cout + 31) / 32;
+    const int ntiles = (int)(g.M / 256);
+    // runs of consecutive tiles per block: about GX_WG_BLOCKS blocks in all
+    const int pairs = ncib * ncob;
+    int tpb = std::max(1, (int)((int64_t)ntiles * pairs / GX_WG_BLOCKS));
+    tpb = std::min(tpb, ntiles);
+    const int64_t chunks = (ntiles + tpb - 1) / tpb;
+    const int64_t nw = (int64_t)g.Cout * g.K;
+    GX_TRY(gx_reserve(ctx, ctx->wpart, (size_t)(chunks * nw + chunks * g.Cout) * sizeof(float)));
+    float* part = (float*)ctx->wpart.p;
+    float* bpart = dbias ? part + chunks * nw : nullptr;
+    const dim3 grid((unsigned)chunks, (unsigned)pairs);
+    if (g.S == 64)
+        hipLaunchKernelGGL(k_wgrad_lds<6>, grid, dim3(192), 0, ctx->stream, xt, yt, g.B, g.Cin,
+                           g.Cout, tpb, part, bpart);
+    else
+        hipLaunchKernelGGL(k_wgrad_lds<5>, grid, dim3(192), 0, ctx->stream, xt, yt, g.B, g.Cin,
+                           g.Cout, tpb, part, bpart);
+    GX_LAUNCH_CHECK(ctx);
+    return wgrad_reduce_chunks(ctx, part, bpart, nw, chunks, g.Cout, dw, dbias);
+}
+
 // Weight and bias gradients through channel-major copies (k_wgrad_cm): the
 // voxel range is split into chunks so that the tasks fill the device, each
 // chunk writes its partial gradient, and the partials are added in chunk order.
@@ -1470,6 +1666,8 @@ static int wgrad_cmajor(gx_ctx* ctx, const uint16_t* in, const uint16_t* dout, c
                        g.Cin, xt);
     hipLaunchKernelGGL(k_to_cmajor, dim3((unsigned)(M / 64)), dim3(256), 0, ctx->stream, dout, V,
                        g.Cout, yt);
+    if (g.kvol == 27 && (g.S == 32 || g.S == 64))
+        return wgrad_staged(ctx, xt, yt, g, dw, dbias);
     const int ndz = g.kvol == 27 ? 3 : 1;
     const int tasks = ((g.Cin + 15) / 16) * ndz * ((g.Cout + 31) / 32);
     const int ty = (tasks + 3) / 4;
@@ -1489,24 +1687,7 @@ static int wgrad_cmajor(gx_ctx* ctx, const uint16_t* in, const uint16_t* dout, c
     else
         hipLaunchKernelGGL(k_wgrad_cm<1>, grid, dim3(256), 0, ctx->stream, xt, yt, g.B, lgS, g.Cin,
                            g.Cout, mpc, part, bpart);
-    if (chunks > 64) {
-        // two ordered levels: groups of 32 chunks, then the group sums
-        const int ngr = (int)((chunks + 31) / 32);
-        GX_TRY(gx_reserve(ctx, ctx->wpart2, (size_t)ngr * nw * sizeof(float)));
-        float* p2 = (float*)ctx->wpart2.p;
-        hipLaunchKernelGGL(k_wgrad_group_sum, dim3(gx_blocks(nw, 256), ngr), dim3(256), 0,
-                           ctx->stream, part, nw, (int)chunks, 32, p2);
-        hipLaunchKernelGGL(k_wgrad_reduce, dim3(gx_blocks(nw, 256)), dim3(256), 0, ctx->stream, p2,
-                           nw, ngr, dw);
-    } else {
-        hipLaunchKernelGGL(k_wgrad_reduce, dim3(gx_blocks(nw, 256)), dim3(256), 0, ctx->stream, part,
-                           nw, (int)chunks, dw);
-    }
-    if (dbias)
-        hipLaunchKernelGGL(k_bias_reduce, dim3(g.Cout), dim3(64), 0, ctx->stream, bpart, (int)chunks,
-                           g.Cout, dbias);
-    GX_LAUNCH_CHECK(ctx);
-    return GX_OK;
+    return wgrad_reduce_chunks(ctx, part, bpart, nw, chunks, g.Cout, dw, dbias);
 }
 
 extern "C" int gx_conv3d_bwd_weight(gx_ctx* ctx, const uint16_t* in, const uint16_t* dout, int B,
