@@ -59,7 +59,11 @@ __global__ __launch_bounds__(64) void k_walk_sph_wave(
 
 #define SPH_THREADS 64
 #define SPH_DT 256         // threads of the density and force kernels (4 waves per group)
-#define SPH_CAP 2048       // candidates kept in LDS by the density kernel
+#define SPH_CAP 2048       // force kernel: candidates per workgroup of a chunked long list
+// density kernel: candidates kept in LDS, longer lists chunked over several
+// workgroups (1024 or 512, for more workgroups per CU, measured slower on the
+// 16M disk: 6.2 and 9.0 against 5.4 ms, as more groups take the chunked path)
+#define SPH_DCAP 2048
 #define SPH_TILE 256       // force kernel source tile (<= 256: hit lists hold 8-bit indices)
 #define SPH_RANGES 1024    // capacity of a block's candidate range list (single-pass walk)
 #define SPH_MARGIN 1.15f   // density search radius = margin x largest kernel size
@@ -313,21 +317,21 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density(
     const int npp = GL.npp;
     const NodeRec B = nodes[groups[g]];
     const int nG = B.end - B.begin;
-    if (npp > SPH_CAP && nG <= 64) {  // long list: chunked over several workgroups
-        if (threadIdx.x == 0) hv[g] = (uint32_t)((npp + SPH_CAP - 1) / SPH_CAP);
+    if (npp > SPH_DCAP && nG <= 64) {  // long list: chunked over several workgroups
+        if (threadIdx.x == 0) hv[g] = (uint32_t)((npp + SPH_DCAP - 1) / SPH_DCAP);
         return;
     }
     // (a long list of a group above 64 receivers is evaluated here chunk by chunk)
-    const bool in_lds = npp <= SPH_CAP;
-    __shared__ float4 cand[SPH_CAP];
+    const bool in_lds = npp <= SPH_DCAP;
+    __shared__ float4 cand[SPH_DCAP];
     __shared__ float2 red[SPH_DT];
     // hit lists; the list expansion uses the same space (slot + range
     // offsets) before the lists are built
     __shared__ __align__(16) uint16_t hl[SPH_HCAP][SPH_DT];
     __shared__ int wtot[SPH_DT / 64];
-    static_assert(sizeof(hl) >= 2 * SPH_CAP * sizeof(int), "expansion scratch");
+    static_assert(sizeof(hl) >= 2 * SPH_DCAP * sizeof(int), "expansion scratch");
     int* const xslot = reinterpret_cast<int*>(&hl[0][0]);
-    int* const xroff = xslot + SPH_CAP;
+    int* const xroff = xslot + SPH_DCAP;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int pad = slice_pad(nG), nsl = SPH_DT / pad, il = tid % pad, sl = tid / pad;
     const double cx = (B.lo[0] + B.hi[0]) * 0.5;
@@ -375,8 +379,8 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density(
                 }
                 dens_hits(hl, nh, tid, cand, xi, yi, zi, Hinv2, s0, s1, nin);
             } else {
-                for (int ch = 0; ch < npp; ch += SPH_CAP) {
-                    const int che = min(npp, ch + SPH_CAP);
+                for (int ch = 0; ch < npp; ch += SPH_DCAP) {
+                    const int che = min(npp, ch + SPH_DCAP);
                     __syncthreads();
                     expand_chunk(GL, npp, ch, che, pos4, cx, cy, cz, cand, xslot, xroff, wtot,
                                  tid, SPH_DT);
@@ -445,7 +449,7 @@ __global__ __launch_bounds__(256) void k_sum_u32(const uint32_t* __restrict__ v,
 }
 
 // ---------------------------------------------------------------------------
-// Long candidate lists: work items (group, chunk of SPH_CAP candidates)
+// Long candidate lists: work items (group, chunk of SPH_DCAP candidates)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_long_items(int ng, const uint32_t* __restrict__ hv,
                                                     const int64_t* __restrict__ hoff,
@@ -488,12 +492,12 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density_part(
     const int2 item = items[blockIdx.x];
     const int g = item.x;
     if (gdone[g]) return;
-    __shared__ float4 cand[SPH_CAP];
+    __shared__ float4 cand[SPH_DCAP];
     __shared__ float2 red[SPH_DT];
     __shared__ __align__(16) uint16_t hl[SPH_HCAP][SPH_DT];
     __shared__ int wtot[SPH_DT / 64];
     int* const xslot = reinterpret_cast<int*>(&hl[0][0]);
-    int* const xroff = xslot + SPH_CAP;
+    int* const xroff = xslot + SPH_DCAP;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const NodeRec B = nodes[groups[g]];
     const int nG = B.end - B.begin;
@@ -503,7 +507,7 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density_part(
     const double cz = (B.lo[2] + B.hi[2]) * 0.5;
     const GroupList GL(L, g);
     const int npp = GL.npp;
-    const int ch = item.y * SPH_CAP, che = min(npp, ch + SPH_CAP);
+    const int ch = item.y * SPH_DCAP, che = min(npp, ch + SPH_DCAP);
     expand_chunk(GL, npp, ch, che, pos4, cx, cy, cz, cand, xslot, xroff, wtot, tid, SPH_DT);
     __syncthreads();
     const int s = B.begin + il;
@@ -696,7 +700,7 @@ __global__ __launch_bounds__(64) void k_group_hmax(int ng, const int32_t* __rest
 }
 
 static_assert(SPH_TILE <= 256, "force hit lists store 8-bit tile indices");
-static_assert(SPH_CAP <= 65536, "density hit lists store 16-bit candidate indices");
+static_assert(SPH_DCAP <= 65536, "density hit lists store 16-bit candidate indices");
 
 // Pair terms of one lane's force hit list (tile indices, list order).
 struct ForceRecv {
@@ -756,7 +760,10 @@ __device__ __forceinline__ void force_hits(const uint8_t (*fl)[SPH_DT], int nh, 
 // of SPH_CAP candidates), FP64 partial sums and the chunk's largest signal
 // velocity stored per (item, receiver) for k_sph_force_long_sum.
 template <bool PART>
-__global__ __launch_bounds__(SPH_DT) void k_sph_force(
+// at most 96 VGPRs (five wavefronts per SIMD; the slice sums share the tile
+// storage so that five workgroups fit a CU's LDS): 3.05 against 3.2 ms on the
+// 16M disk at the compiler's free choice of 99 registers and four wavefronts
+__global__ __launch_bounds__(SPH_DT) __attribute__((amdgpu_waves_per_eu(5))) void k_sph_force(
     int ng, const int2* __restrict__ items, const int32_t* __restrict__ groups,
     const NodeRec* __restrict__ nodes, const double4* __restrict__ pos4,
     const uint32_t* __restrict__ perm, const double4* __restrict__ sv,
@@ -781,12 +788,21 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_force(
         return;
     }
     const int pe = PART ? min(npp, pb + SPH_CAP) : npp;
-    __shared__ float4 t0[SPH_TILE], t1[SPH_TILE], t2[SPH_TILE];
+    // source tiles; after a pass's last tile the same storage holds the
+    // slices' sums (FP64 accelerations and du/dt in tiles 0-1, the largest
+    // signal velocities in tile 2), between barriers
+    __shared__ float4 tb3[3][SPH_TILE];
     __shared__ float tc[SPH_TILE];
     __shared__ int jidx[SPH_TILE], jroff[SPH_TILE], wtot[SPH_DT / 64];
     __shared__ uint8_t fl[SPH_FCAP][SPH_DT];
-    __shared__ double redd[4][SPH_DT];
-    __shared__ float redv[SPH_DT];
+    static_assert(4 * SPH_DT * sizeof(double) <= 2 * SPH_TILE * sizeof(float4) &&
+                      SPH_DT * sizeof(float) <= SPH_TILE * sizeof(float4),
+                  "slice sums fit in the tile storage");
+    float4* const t0 = tb3[0];
+    float4* const t1 = tb3[1];
+    float4* const t2 = tb3[2];
+    double(*const redd)[SPH_DT] = reinterpret_cast<double(*)[SPH_DT]>(&tb3[0][0]);
+    float* const redv = reinterpret_cast<float*>(&tb3[2][0]);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const NodeRec B = nodes[groups[g]];
     const int nG = B.end - B.begin;
@@ -1070,7 +1086,7 @@ static int long_items(gx_ctx* ctx, int nb, const uint32_t* hv, int64_t** hoff, i
     return GX_OK;
 }
 
-// Groups whose candidate lists exceed SPH_CAP: chunk sums over many
+// Groups whose candidate lists exceed SPH_DCAP: chunk sums over many
 // workgroups, then one Newton step per receiver, until every receiver is
 // done (at most max_iter passes).
 static int density_long(gx_ctx* ctx, TreeSlot& T, const ListView& view, int nb, float* rad,
