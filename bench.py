@@ -98,6 +98,9 @@ def parse():
                     help="trained surrogate weights (random initialisation when absent)")
     ap.add_argument("--no-force-error", action="store_true",
                     help="skip the force errors against the oracle's direct sum")
+    ap.add_argument("--sph-stream", choices=("own", "shared"), default="own",
+                    help="gas tree, density and hydro force on a second context and stream "
+                         "beside the gravity kernel (default), or in series after it")
     ap.add_argument("--sn-mode", choices=("async", "sync"), default="async",
                     help="surrogate hand-over on its own stream in a worker thread (default), "
                          "or in series on the galaxy's stream")
@@ -380,7 +383,8 @@ def main():
     cfg = StepConfig(G=ics.G_KPC, dt=2000.0 * YEAR_IN_KPC_TIME, theta=0.5, quad=True,
                      n_leaf=args.n_leaf, n_group=args.n_group, sph_leaf=args.sph_leaf,
                      sph_group=args.sph_group, n_ngb=64.0, u_floor=10.0 * ics.U_PER_K)
-    sim = GalaxyStep(eng, p, int(d["gas_offset"]), u, cfg, timing=True)
+    hydro = gx.Engine(0, stream=torch.cuda.Stream()) if args.sph_stream == "own" else None
+    sim = GalaxyStep(eng, p, int(d["gas_offset"]), u, cfg, timing=True, hydro=hydro)
     coupling = None
     if args.sn_sites > 0:
         from paper_2510_23330_amd.coupling import SNCoupling
@@ -460,6 +464,32 @@ def main():
     elapsed = time.perf_counter() - t_start
     ms_step = elapsed / args.steps * 1e3
     kd_ms = float(np.mean([e[0].elapsed_time(e[1]) + e[2].elapsed_time(e[3]) for e in kd_ev]))
+    alone_ms = None
+    if hydro is not None:
+        # two untimed steps with the SPH after the gravity kernel instead of
+        # beside it (and no hand-over in flight): the pairwise kernel with the
+        # GPU to itself
+        if coupling is not None:
+            coupling.drain()
+        sim.concurrent = False
+        al = {"gk": [], "tree": [], "dk": [], "hk": [], "kd": []}
+        for _ in range(2):
+            st = sim.step()
+            al["gk"].append(st["gravity"]["ms_kernel"])
+            al["tree"].append(st["tree_all"]["ms"] + st["tree_gas"]["ms"])
+            al["dk"].append(st["density"]["ms_kernel"])
+            al["hk"].append(st["hydro"]["ms_kernel"])
+            al["kd"].append(st["kd_events"])
+        torch.cuda.synchronize()
+        al["kd"] = [e[0].elapsed_time(e[1]) + e[2].elapsed_time(e[3]) for e in al["kd"]]
+        sim.concurrent = True
+        al = {k: float(np.mean(v)) for k, v in al.items()}
+        alone_ms = al["gk"]
+    # kernel rates and HBM phases from the steps where each phase ran alone
+    dens_k = al["dk"] if alone_ms is not None else float(np.mean(dens_k_ms))
+    hydro_k = al["hk"] if alone_ms is not None else float(np.mean(hydro_k_ms))
+    tree_alone = al["tree"] if alone_ms is not None else float(np.mean(tree_ms))
+    kd_alone = al["kd"] if alone_ms is not None else kd_ms
     walk_ms = float(np.mean(grav_ms) - np.mean(grav_kernel_ms))
     sn_async = None
     applied_at_end = 0
@@ -527,7 +557,7 @@ def main():
                                f"{args.sn_sites} SN regions per step to the surrogate",
                    "n_particles": args.n, "seed": args.seed, "particle_order": args.ic_order,
                    "n_group": args.n_group, "n_leaf": args.n_leaf, "sph_group": args.sph_group,
-                   "sph_leaf": args.sph_leaf},
+                   "sph_leaf": args.sph_leaf, "sph_stream": args.sph_stream},
         "s_per_step": ms_step / 1e3,
         "grav_interactions_per_step": inter_step,
         "grav_pp_per_step": n_pp / args.steps,
@@ -539,6 +569,12 @@ def main():
                      "kick_drift": kd_ms,
                      "sn_surrogate": float(np.mean(sn_ms)) if sn_ms else None},
         "ms_per_step_median": float(np.median(per)) * 1e3,
+        "phase_ms_alone": None if alone_ms is None else {
+            "tree_builds": al["tree"], "gravity_kernel": al["gk"], "sph_density_kernel": al["dk"],
+            "sph_force_kernel": al["hk"], "kick_drift": al["kd"],
+            "note": "two untimed steps with the SPH after the gravity kernel, no hand-over in "
+                    "flight; in the timed steps the gas tree and SPH run beside the tree, walk "
+                    "and gravity of all particles, so phase_ms overlap"},
         "sn_coupling": None if coupling is None else dict(
             coupling.stats, sites_per_step=args.sn_sites, delay_steps=50, mode=args.sn_mode,
             handovers_applied_after_timing=applied_at_end,
@@ -548,22 +584,22 @@ def main():
         "gravity_kernel_interactions_per_s": inter_step / kernel_s,
         "sph": {"density_pair_evals_per_step": n_dens_eval / args.steps,
                 "density_ngb_evals_per_step": n_dens_ngb / args.steps,
-                "density_kernel_ms": float(np.mean(dens_k_ms)),
-                "density_tflops_73": FLOP_DENS * n_dens_eval / args.steps
-                / (float(np.mean(dens_k_ms)) / 1e3) / 1e12,
-                "density_tflops_73_ngb": FLOP_DENS * n_dens_ngb / args.steps
-                / (float(np.mean(dens_k_ms)) / 1e3) / 1e12,
+                "density_kernel_ms": dens_k,
+                "density_tflops_73": FLOP_DENS * n_dens_eval / args.steps / (dens_k / 1e3) / 1e12,
+                "density_tflops_73_ngb": FLOP_DENS * n_dens_ngb / args.steps / (dens_k / 1e3)
+                / 1e12,
                 "density_max_iterations": int(max(dens_it)),
                 "force_list_pairs_per_step": n_force_list / args.steps,
                 "force_ngb_pairs_per_step": n_force_ngb / args.steps,
-                "force_kernel_ms": float(np.mean(hydro_k_ms)),
-                "force_tflops_101": FLOP_FORCE * n_force_list / args.steps
-                / (float(np.mean(hydro_k_ms)) / 1e3) / 1e12,
-                "force_tflops_101_ngb": FLOP_FORCE * n_force_ngb / args.steps
-                / (float(np.mean(hydro_k_ms)) / 1e3) / 1e12,
+                "force_kernel_ms": hydro_k,
+                "force_tflops_101": FLOP_FORCE * n_force_list / args.steps / (hydro_k / 1e3)
+                / 1e12,
+                "force_tflops_101_ngb": FLOP_FORCE * n_force_ngb / args.steps / (hydro_k / 1e3)
+                / 1e12,
                 "convention": "list: every candidate pair evaluated (Table 4 convention); ngb: "
                               "only pairs inside the kernel supports (density: summed over the "
-                              "kernel-size passes)"},
+                              "kernel-size passes); kernel times from steps with the SPH alone "
+                              "on the GPU when it otherwise runs beside the gravity kernel"},
         "gravity_lists": {"two_pass_steps": int(sum(w[0] for w in walk_diag)),
                           "max_walk_stack": int(max(w[1] for w in walk_diag)),
                           "pc_entries_per_step": float(np.mean([l[1] for l in list_sizes])),
@@ -574,14 +610,22 @@ def main():
                           "note": "walk_ms = gravity call minus its pairwise kernel (the list "
                                   "walk, the list totals and one host round trip); the walk is "
                                   "latency-bound"},
-        "hbm_phases": hbm_phases(n_part=args.n, n_gas=sim.ng, tree_ms=float(np.mean(tree_ms)),
-                                 kd_ms=kd_ms),
+        "hbm_phases": hbm_phases(n_part=args.n, n_gas=sim.ng, tree_ms=tree_alone,
+                                 kd_ms=kd_alone),
         "energy_drift_rel": abs(E1 - E0) / abs(E0),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": grav_traffic_bytes(args.ic_order),
                      "kernel": "k_grav_force<float,true>",
                      "flop_convention": f"{FLOP_PP}/pp + {FLOP_PC}/pc"},
     }
+    if alone_ms is not None:
+        # the timed launches share the GPU with the SPH kernels of the hydro
+        # stream; the same FLOP over the kernel's time with the GPU to itself
+        out["roofline"]["concurrent_with"] = "gas tree, density and hydro force on a second stream"
+        out["roofline"]["alone"] = {"ms": alone_ms, "achieved": flops / (alone_ms / 1e3) / 1e12,
+                                    "frac": flops / (alone_ms / 1e3) / PEAK_FP32,
+                                    "steps": 2, "note": "untimed steps with the SPH after the "
+                                    "gravity kernel"}
     if args.sn_cubes > 0:
         t0 = time.perf_counter()
         out["sn_region"] = sn_region_leg(eng, args.sn_cubes, args.sn_infer_batch, args.weights,
@@ -603,6 +647,9 @@ def main():
                 "global_steps": {"surrogate": 50, "plain": n_sh},
                 "dt_cfl_sn_yr": 0.1e6 / n_sh, "dt_global_yr": 2000.0}
     out.update(cpu_baseline_leg(args, eng, sim, d))
+    sim.close()
+    if hydro is not None:
+        hydro.close()
     eng.close()
     print(json.dumps(out), flush=True)
 

@@ -237,6 +237,20 @@ int gx_kick_drift(gx_ctx* ctx, int64_t n, double dt_kick, double dt_drift, doubl
                   double u_floor, double* vpred_xyz, double* upred);
 
 /*
+ * gx_add_accel -- a += b, then b = 0, per component, for n particles (all
+ * six arrays device FP64 [n], a and b not overlapping).  The acceleration of a
+ * particle is the sum of its gravity and hydro terms (Sec. 3.2); this folds a
+ * set evaluated separately (e.g. gx_sph_forces, which adds into its outputs,
+ * run into a zeroed set on another context's stream beside the gravity
+ * kernel) into the total and leaves the set zeroed for the next evaluation.
+ * Each element is added once, so the total equals adding into a directly.
+ * Enqueued on the context's stream; errors: GX_EINVAL for a null pointer or
+ * n < 0.
+ */
+int gx_add_accel(gx_ctx* ctx, int64_t n, double* ax, double* ay, double* az, double* bx,
+                 double* by, double* bz);
+
+/*
  * gx_kick_drift_cubes -- gx_kick_drift for independent systems (SN cubes)
  * that each take their own Courant step: particle i of cube c = cube_id[i]
  * uses dt_kick = f_kick dt_cube[c] and dt_drift = f_drift dt_cube[c]

@@ -228,6 +228,16 @@ class Engine:
                                            n_u, _ptr(u), _ptr(dudt), float(u_floor), _ptr(vpred),
                                            _ptr(upred)))
 
+    def add_accel(self, ax, ay, az, bx, by, bz):
+        """a += b, then b = 0 (device double [n] each)."""
+        n = int(ax.shape[0])
+        for t in (ay, az, bx, by, bz):
+            if int(t.shape[0]) != n:
+                raise ValueError("add_accel: arrays of different lengths")
+        f64 = _torch().float64
+        self._check(self.lib.gx_add_accel(self.ctx, n, *(_ptr(t, f64) for t in (ax, ay, az, bx, by,
+                                                                               bz))))
+
     def kick_drift_cubes(self, p: ParticleSet, cube_id, dt_cube, f_kick, f_drift, ax, ay, az,
                          u=None, dudt=None, u_floor=0.0, vpred=None, upred=None):
         """Half step of independent cubes, each with its own dt (device double [K])."""

@@ -65,6 +65,7 @@ SIGNATURES = {
     "gx_sph_forces": (I32, [P, C.POINTER(GxParticles), C.POINTER(GxGas), D, D, P, P, P,
                             C.POINTER(GxStats)]),
     "gx_kick_drift": (I32, [P, I64, D, D, P, P, P, P, P, P, P, P, P, I64, P, P, D, P, P]),
+    "gx_add_accel": (I32, [P, I64, P, P, P, P, P, P]),
     "gx_kick_drift_cubes": (I32, [P, I64, P, P, D, D, P, P, P, P, P, P, P, P, P, P, P, D, P, P]),
     "gx_energy": (I32, [P, C.POINTER(GxParticles), P, I64, P, P, P]),
     "gx_sph_timestep": (I32, [P, C.POINTER(GxGas), D, P, I32, P]),

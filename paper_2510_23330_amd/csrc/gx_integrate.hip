@@ -70,6 +70,37 @@ extern "C" int gx_kick_drift(gx_ctx* ctx, int64_t n, double dt_kick, double dt_d
     return GX_OK;
 }
 
+__global__ __launch_bounds__(256) void k_add_accel(int64_t n, double* __restrict__ ax,
+                                                  double* __restrict__ ay,
+                                                  double* __restrict__ az,
+                                                  double* __restrict__ bx,
+                                                  double* __restrict__ by,
+                                                  double* __restrict__ bz) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        ax[i] += bx[i];
+        ay[i] += by[i];
+        az[i] += bz[i];
+        bx[i] = 0.0;
+        by[i] = 0.0;
+        bz[i] = 0.0;
+    }
+}
+
+extern "C" int gx_add_accel(gx_ctx* ctx, int64_t n, double* ax, double* ay, double* az,
+                            double* bx, double* by, double* bz) {
+    if (!ctx) return GX_EINVAL;
+    if (n < 0 || !ax || !ay || !az || !bx || !by || !bz)
+        return gx_fail(ctx, GX_EINVAL, "add_accel: null pointer or n < 0");
+    if (n == 0) return GX_OK;
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    const int64_t blocks = std::min<int64_t>(gx_blocks(n, 256), 4096);
+    hipLaunchKernelGGL(k_add_accel, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, n, ax, ay, az,
+                       bx, by, bz);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
 extern "C" int gx_kick_drift_cubes(gx_ctx* ctx, int64_t n, const int32_t* cube_id,
                                    const double* dt_cube, double f_kick, double f_drift, double* x,
                                    double* y, double* z, double* vx, double* vy, double* vz,

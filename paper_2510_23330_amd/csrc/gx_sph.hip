@@ -1332,7 +1332,11 @@ extern "C" int gx_sph_forces(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, d
         GX_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
         GX_HIP(ctx, hipEventElapsedTime(&msk, ctx->ev2, ctx->ev3));
         unsigned long long h[8];
-        GX_HIP(ctx, hipMemcpy(h, stat, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+        // on the context's stream: a plain copy would also wait for the
+        // legacy default stream, i.e. for other contexts' work
+        GX_HIP(ctx, hipMemcpyAsync(h, stat, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                   st));
+        GX_HIP(ctx, hipStreamSynchronize(st));
         stats->ms = ms;
         stats->ms_kernel = msk;
         stats->n_sph_ngb = (int64_t)h[2];

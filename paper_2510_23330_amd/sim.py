@@ -8,6 +8,8 @@ arithmetic step runs in libgx; this module only sequences the calls.
 """
 from __future__ import annotations
 
+import queue
+import threading
 from dataclasses import dataclass, field
 
 from . import GX_QUAD, GX_TREE_ALL, GX_TREE_GAS, Engine, GasState, ParticleSet
@@ -48,6 +50,12 @@ class GalaxyStep:
     stats: dict = field(default_factory=dict)
     # record timing events around the kick/drift calls (stats["kd_events"])
     timing: bool = False
+    # optional second engine on its own stream: the gas tree, kernel sizes,
+    # density and hydro force run there, issued by a worker thread, beside the
+    # tree, walk and gravity of all particles; the hydro accelerations go to a
+    # zeroed set that the galaxy's stream then adds to the gravity ones (and
+    # clears), so the step's results are the same as on one stream
+    hydro: object = None
 
     def __post_init__(self):
         import torch
@@ -67,22 +75,97 @@ class GalaxyStep:
         self.vpred = z64(3 * ng)
         self.upred = z64(ng)
         self.ng = ng
+        self._jobs = None
+        # with a hydro engine: SPH beside the gravity of all particles (True)
+        # or after it, on the same engines (False, e.g. to time the gravity
+        # kernel alone)
+        self.concurrent = True
+        if self.hydro is not None and ng > 0:
+            self.hax, self.hay, self.haz = z64(ng), z64(ng), z64(ng)
+            # library calls that read sizes back block their thread until
+            # their own stream is done, so each stream is driven by a thread
+            self._jobs = queue.Queue()
+            self._worker = threading.Thread(target=self._run_jobs, daemon=True)
+            self._worker.start()
+
+    def _run_jobs(self):
+        while True:
+            job = self._jobs.get()
+            if job is None:
+                return
+            fn, done = job
+            try:
+                fn()
+            except BaseException as e:  # re-raised by the calling thread
+                done["error"] = e
+            done["event"].set()
+
+    def close(self):
+        """Stop the hydro worker thread (if any)."""
+        if self._jobs is not None:
+            self._jobs.put(None)
+            self._worker.join()
+            self._jobs = None
 
     def _acc(self, a, b):
         return self.ax[a:b], self.ay[a:b], self.az[a:b]
 
+    def _record(self, eng):
+        import torch
+        e = torch.cuda.Event()
+        e.record(eng.stream)
+        return e
+
     def forces(self, predicted: bool = True):
-        """Gravity on all particles, then SPH on the gas (accelerations added)."""
+        """Gravity on all particles, then SPH on the gas (accelerations added).
+
+        With a hydro engine the SPH calls are issued by the worker thread on
+        the hydro engine's stream once this step's drift is done: the gas
+        tree, kernel sizes, density and hydro force run beside the tree, walk
+        and gravity kernel of all particles, the hydro force adding into the
+        zeroed set (hax, hay, haz); the galaxy's stream then waits for it and
+        adds the set to the gravity accelerations (clearing it)."""
         c, s = self.cfg, self.stats
+        if self._jobs is None:
+            s["tree_all"] = self.eng.tree_build(self.p, GX_TREE_ALL, c.n_leaf, c.n_group)
+            s["gravity"] = self.eng.gravity_forces(self.p, c.G, c.theta,
+                                                   GX_QUAD if c.quad else 0, self.ax, self.ay,
+                                                   self.az, self.pot)
+            for f in self.after_gravity:
+                f()
+            if self.ng:
+                self._sph(self.eng, predicted, self._acc(self.gas_offset, self.p.n))
+            return
+        he = self.hydro
+        done = {"event": threading.Event(), "error": None}
+
+        def submit(start):
+            def job():
+                he.stream.wait_event(start)
+                self._sph(he, predicted, (self.hax, self.hay, self.haz))
+                done["hydro_done"] = self._record(he)
+            self._jobs.put((job, done))
+
+        if self.concurrent:
+            submit(self._record(self.eng))  # from the end of the drift
         s["tree_all"] = self.eng.tree_build(self.p, GX_TREE_ALL, c.n_leaf, c.n_group)
         s["gravity"] = self.eng.gravity_forces(self.p, c.G, c.theta, GX_QUAD if c.quad else 0,
                                                self.ax, self.ay, self.az, self.pot)
+        if not self.concurrent:
+            submit(self._record(self.eng))  # from the end of the gravity kernel
         for f in self.after_gravity:
             f()
-        if self.ng == 0:
-            return
-        s["tree_gas"] = self.eng.tree_build(self.gas, GX_TREE_GAS, c.sph_leaf, c.sph_group)
-        ng = self.ng
+        done["event"].wait()
+        if done["error"] is not None:
+            raise RuntimeError("SPH on the hydro stream failed") from done["error"]
+        self.eng.stream.wait_event(done["hydro_done"])
+        self.eng.add_accel(*self._acc(self.gas_offset, self.p.n), self.hax, self.hay, self.haz)
+
+    def _sph(self, he, predicted, acc):
+        """Gas tree, kernel sizes, density and hydro force (added to acc), all
+        with engine he."""
+        c, s, ng = self.cfg, self.stats, self.ng
+        s["tree_gas"] = he.tree_build(self.gas, GX_TREE_GAS, c.sph_leaf, c.sph_group)
         if predicted:
             vel = (self.vpred[:ng], self.vpred[ng:2 * ng], self.vpred[2 * ng:])
             u = self.upred
@@ -91,10 +174,9 @@ class GalaxyStep:
         gas_view = self.gas if vel is None else ParticleSet(
             x=self.gas.x, y=self.gas.y, z=self.gas.z, vx=vel[0], vy=vel[1], vz=vel[2],
             m=self.gas.m, eps2=self.gas.eps2)
-        s["density"] = self.eng.sph_density(gas_view, self.g, c.n_ngb, c.gamma, c.h_tol,
-                                            c.max_iter, u=u)
-        s["hydro"] = self.eng.sph_forces(gas_view, self.g, *self._acc(self.gas_offset, self.p.n),
-                                         gamma=c.gamma, alpha=c.alpha, u=u)
+        s["density"] = he.sph_density(gas_view, self.g, c.n_ngb, c.gamma, c.h_tol, c.max_iter,
+                                      u=u)
+        s["hydro"] = he.sph_forces(gas_view, self.g, *acc, gamma=c.gamma, alpha=c.alpha, u=u)
 
     def initial_forces(self):
         self.forces(predicted=False)

@@ -171,3 +171,43 @@ def test_timestep_matches_oracle(gx, eng):
     for c in range(3):
         sel = np.arange(p.n) % 3 == c
         assert dt3[c].item() == pytest.approx(0.3 * np.min(Hf[sel] / ovs[sel]), rel=1e-5)
+
+
+def test_step_with_hydro_stream_matches_one_stream(gx, eng):
+    # Leapfrog steps of a disk galaxy with the gas tree, density and hydro
+    # force on a second context and stream, beside the gravity kernel (the
+    # hydro accelerations into a zeroed set, then added by gx_add_accel),
+    # leave the same state, bit for bit, as the same steps on one stream: the
+    # two streams run the same kernels on the same inputs, ordered by events.
+    # Each run starts from new contexts: a context's first gravity call builds
+    # its lists with the exact two-pass walk, later calls with the one-pass
+    # walk, whose lists hold the same cells in another order.
+    import torch
+    from paper_2510_23330_amd.sim import GalaxyStep, StepConfig
+    d = ics.disk_galaxy(300_000, seed=5)
+    out = []
+    for split in (False, True):
+        main = gx.Engine(0)
+        hydro = gx.Engine(0, stream=torch.cuda.Stream()) if split else None
+        p = gx.ParticleSet.from_numpy(d)
+        u = torch.as_tensor(d["u_gas"], device="cuda")
+        st = GalaxyStep(main, p, int(d["gas_offset"]), u,
+                        StepConfig(G=ics.G_KPC, dt=2000.0 / 0.97779e9), hydro=hydro)
+        st.initial_forces()
+        for _ in range(3):
+            st.step()
+        torch.cuda.synchronize()
+        out.append({k: t.cpu().numpy() for k, t in (
+            ("x", p.x), ("z", p.z), ("vx", p.vx), ("vz", p.vz), ("ax", st.ax), ("az", st.az),
+            ("pot", st.pot), ("u", st.g.u), ("H", st.g.H), ("rho", st.g.rho),
+            ("dudt", st.g.dudt), ("vsig", st.g.vsig))})
+        if split:  # the hydro set was added to the total and cleared
+            assert not any(bool(t.any()) for t in (st.hax, st.hay, st.haz))
+        st.close()
+        if hydro is not None:
+            hydro.close()
+        main.close()
+    assert st.stats["hydro"] is not None and st.ng > 0
+    for k in out[0]:
+        assert np.array_equal(out[0][k], out[1][k]), k
+    assert np.all(np.isfinite(out[1]["ax"]))
