@@ -104,6 +104,9 @@ def parse():
     ap.add_argument("--sn-mode", choices=("async", "sync"), default="async",
                     help="surrogate hand-over on its own stream in a worker thread (default), "
                          "or in series on the galaxy's stream")
+    ap.add_argument("--sn-start", choices=("after_gravity", "now"), default="after_gravity",
+                    help="asynchronous hand-over: start after the next gravity kernel (default) "
+                         "or as soon as the snapshot is taken")
     ap.add_argument("--resampler", choices=("cdf", "gibbs"), default="cdf",
                     help="grid-to-particle mapping of the surrogate: inverse CDF or Gibbs chains")
     ap.add_argument("--sweeps", type=int, default=4, help="Gibbs sweeps per particle")
@@ -391,7 +394,8 @@ def main():
         asyn = args.sn_mode == "async"
         sur_eng = gx.Engine(0, stream=torch.cuda.Stream() if asyn else None)
         sur, wfile = load_surrogate(sur_eng, 64, args.weights, args.resampler, args.sweeps)
-        coupling = SNCoupling(sim, sur, n_sites=args.sn_sites, delay=50, asynchronous=asyn)
+        coupling = SNCoupling(sim, sur, n_sites=args.sn_sites, delay=50, asynchronous=asyn,
+                              start=args.sn_start)
     torch.cuda.synchronize()
     log("[bench] set-up done; initial forces (cold kernel sizes) ...")
     t0 = time.perf_counter()
@@ -576,7 +580,7 @@ def main():
                     "flight; in the timed steps the gas tree and SPH run beside the tree, walk "
                     "and gravity of all particles, so phase_ms overlap"},
         "sn_coupling": None if coupling is None else dict(
-            coupling.stats, sites_per_step=args.sn_sites, delay_steps=50, mode=args.sn_mode,
+            coupling.stats, sites_per_step=args.sn_sites, delay_steps=50, mode=args.sn_mode, start=args.sn_start,
             handovers_applied_after_timing=applied_at_end,
             weights=wfile or "random init (timing only; every region falls back)",
             encoding=coupling.sur.encoding, resampler=coupling.sur.resampler),

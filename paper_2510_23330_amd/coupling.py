@@ -60,7 +60,7 @@ class SNCoupling:
     def __init__(self, step, surrogate: Surrogate, n_sites: int = 64, delay: int = 50,
                  side_pc: float = 60.0, seed: int = 5, r_max: float = 15.0, z_max: float = 0.3,
                  valid_sigma: float = 8.0, cfg: SPHConfig = SPHConfig(), star_type: int = 1,
-                 asynchronous: bool = False):
+                 asynchronous: bool = False, start: str = "after_gravity"):
         import torch
         self.torch = torch
         self.step, self.sur = step, surrogate
@@ -88,6 +88,12 @@ class SNCoupling:
                       "particles_replaced": 0, "missing_ids": 0}
         self._lock = threading.Lock()
         self.asynchronous = asynchronous
+        # asynchronous mode: a hand-over's work starts after the next gravity
+        # call's kernel ("after_gravity") or as soon as its snapshot is taken
+        # ("now")
+        if start not in ("after_gravity", "now"):
+            raise ValueError("start must be 'after_gravity' or 'now'")
+        self.start = start
         self.sur_ms = []          # surrogate pipeline time on its stream, per hand-over
         if asynchronous:
             self.main_stream = torch.cuda.current_stream(p.x.device)
@@ -276,10 +282,11 @@ class SNCoupling:
                 return
             slot, taken, need, centers, step_index, item = job
             try:
-                gate = self._gate(need)
+                gate = self._gate(need) if self.start == "after_gravity" else None
                 with torch.cuda.stream(self.sur_stream):
                     self.sur_stream.wait_event(taken)
-                    self.sur_stream.wait_event(gate)
+                    if gate is not None:
+                        self.sur_stream.wait_event(gate)
                     t0 = torch.cuda.Event(enable_timing=True)
                     t0.record(self.sur_stream)
 
