@@ -58,6 +58,7 @@ struct TreeSlot {
     Buf pos4;            // double4 {x, y, z, m} in sorted order
     Buf e2s;             // float eps^2 in sorted order
     Buf win, cnt, lmax;  // node-count construction scratch
+    Buf blkh;            // per-workgroup node counts per level [levels][workgroups], then bases
     Buf nodes, mom, q64, parent, child, lvl_ids, lvl_fill, flag;
     Buf groups;          // int32 node id of each group (pre-order)
     Buf blocks;          // NodeRec per SPH receiver block (64 consecutive sorted slots)

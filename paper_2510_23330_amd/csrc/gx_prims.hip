@@ -100,7 +100,7 @@ extern "C" int gx_destroy(gx_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     for (auto& T : ctx->tree) {
         for (auto* b : {&T.key[0], &T.key[1], &T.val[0], &T.val[1], &T.pos4, &T.e2s, &T.win,
-                        &T.cnt, &T.lmax, &T.nodes, &T.mom, &T.q64, &T.parent, &T.child, &T.lvl_ids,
+                        &T.cnt, &T.lmax, &T.blkh, &T.nodes, &T.mom, &T.q64, &T.parent, &T.child, &T.lvl_ids,
                         &T.lvl_fill, &T.flag, &T.groups, &T.blocks, &T.box, &T.wkey[0], &T.wkey[1],
                         &T.wval[0], &T.wval[1], &T.wbox, &T.wrec, &T.wsph, &T.whmax})
             free_buf(*b);

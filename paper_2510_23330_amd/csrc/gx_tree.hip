@@ -162,18 +162,96 @@ __global__ __launch_bounds__(256) void k_window(int64_t n, const uint64_t* __res
     w[j] = (int8_t)common_digits(key[j], key[j + n_leaf]);
 }
 
+// The nodes that start at particle i (deepest first: each shallower node
+// ends at or after the deeper one, so its end is searched from there,
+// galloping then bisecting), written at their pre-order slots, and their ids
+// appended to the per-level lists (slot = the workgroup's base + an LDS count).
+__device__ __forceinline__ void emit_nodes(int64_t i, int64_t n, const uint64_t* __restrict__ key,
+                                           const uint32_t* __restrict__ cnt,
+                                           const uint32_t* __restrict__ base,
+                                           const int8_t* __restrict__ lmax, int64_t n_nodes,
+                                           NodeRec* __restrict__ nodes, uint32_t* lcnt,
+                                           const uint32_t* lbase, int32_t* __restrict__ lvl_ids) {
+    const uint32_t c = cnt[i];
+    if (c == 0) return;
+    const int Li = lmax[i];
+    const int lstart = Li - (int)c + 1;
+    const uint32_t bi = base[i];
+    const uint64_t ki = key[i];
+    int64_t lo = i + 1;
+    for (int l = Li; l >= lstart; l--) {
+        int64_t end;
+        if (l == 0) {
+            end = n;
+        } else {
+            const int shift = 3 * (GX_MAX_LEVEL - l);
+            const uint64_t pre = ki >> shift;
+            int64_t step = 1, hi = n;
+            for (;;) {
+                const int64_t p = lo + step - 1;
+                if (p >= n) break;
+                if ((key[p] >> shift) != pre) {
+                    hi = p;
+                    break;
+                }
+                lo = p + 1;
+                step <<= 1;
+            }
+            while (lo < hi) {  // first index in [lo, hi) with a different prefix
+                const int64_t mid = (lo + hi) >> 1;
+                if ((key[mid] >> shift) == pre) lo = mid + 1;
+                else hi = mid;
+            }
+            end = lo;
+        }
+        NodeRec r;
+        r.begin = (int32_t)i;
+        r.end = (int32_t)end;
+        r.level = (int16_t)l;
+        r.leaf = (int8_t)(l == Li);
+        r.nchild = 0;
+        r.next = (int32_t)(end < n ? (int64_t)base[end] : n_nodes);
+        r.lo[0] = r.lo[1] = r.lo[2] = 0.0;
+        r.hi[0] = r.hi[1] = r.hi[2] = 0.0;
+        const int64_t id = (int64_t)bi + (l - lstart);
+        nodes[id] = r;
+        lvl_ids[lbase[l] + atomicAdd(&lcnt[l], 1u)] = (int32_t)id;
+        lo = end;
+    }
+}
+
+// The node-count and node-emit kernels give each workgroup one contiguous
+// range of particles (whole chunks of 256) and keep per-workgroup level counts
+// in LDS: the counts go to blkh[level][workgroup] (no global atomics, which
+// serialise when tens of thousands of workgroups update the same 22 level
+// counters), a per-level scan turns them into each workgroup's first slot in
+// the level's id list, and the emit kernel hands out slots inside its range
+// with LDS atomics (the order of ids within a level is immaterial: every
+// use of the lists treats the level's nodes independently).
+#define GX_TB_BLOCKS 2048
+static inline int tb_blocks(int64_t n) {
+    const int64_t chunks = (n + 255) / 256;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(chunks, GX_TB_BLOCKS));
+}
+// particles per workgroup (a multiple of 256) for nb workgroups
+__host__ __device__ inline int64_t tb_span(int64_t n, int nb) {
+    const int64_t chunks = (n + 255) / 256;
+    return ((chunks + nb - 1) / nb) * 256;
+}
+
 // Per particle: L_i (deepest level of a node containing i), the number of
-// nodes that start at i, and their level histogram.
+// nodes that start at i; per workgroup: the nodes of its range per level.
 __global__ __launch_bounds__(256) void k_node_count(int64_t n, const uint64_t* __restrict__ key,
                                                     const int8_t* __restrict__ w, int n_leaf,
                                                     uint32_t* __restrict__ cnt,
                                                     int8_t* __restrict__ lmax,
-                                                    uint32_t* __restrict__ lvl_hist) {
+                                                    uint32_t* __restrict__ blkh) {
     __shared__ uint32_t h[GX_MAX_LEVEL + 1];
     if (threadIdx.x <= GX_MAX_LEVEL) h[threadIdx.x] = 0;
     __syncthreads();
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
+    const int64_t span = tb_span(n, gridDim.x);
+    const int64_t r0 = (int64_t)blockIdx.x * span, r1 = r0 + span < n ? r0 + span : n;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
         int W = -1;
         int64_t j0 = i - n_leaf > 0 ? i - n_leaf : 0;
         int64_t j1 = i < n - 1 - n_leaf ? i : n - 1 - n_leaf;
@@ -186,7 +264,37 @@ __global__ __launch_bounds__(256) void k_node_count(int64_t n, const uint64_t* _
         for (int l = lstart; l <= Li; l++) atomicAdd(&h[l], 1u);
     }
     __syncthreads();
-    if (threadIdx.x <= GX_MAX_LEVEL && h[threadIdx.x]) atomicAdd(&lvl_hist[threadIdx.x], h[threadIdx.x]);
+    if (threadIdx.x <= GX_MAX_LEVEL) blkh[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+}
+
+// One workgroup per level: exclusive scan of the level's per-workgroup counts
+// (in place, in workgroup order) and the level's total.
+__global__ __launch_bounds__(256) void k_level_scan(int nb, uint32_t* __restrict__ blkh,
+                                                    uint32_t* __restrict__ lvl_hist) {
+    __shared__ uint32_t part[256];
+    uint32_t* row = blkh + (int64_t)blockIdx.x * nb;
+    const int per = (nb + 255) / 256;
+    const int b0 = threadIdx.x * per, b1 = min(nb, b0 + per);
+    uint32_t s = 0;
+    for (int b = b0; b < b1; b++) s += row[b];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int t = 0; t < 256; t++) {
+            const uint32_t v = part[t];
+            part[t] = acc;
+            acc += v;
+        }
+        lvl_hist[blockIdx.x] = acc;
+    }
+    __syncthreads();
+    uint32_t acc = part[threadIdx.x];
+    for (int b = b0; b < b1; b++) {
+        const uint32_t v = row[b];
+        row[b] = acc;
+        acc += v;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_node_emit(int64_t n, const uint64_t* __restrict__ key,
@@ -195,77 +303,18 @@ __global__ __launch_bounds__(256) void k_node_emit(int64_t n, const uint64_t* __
                                                    const int8_t* __restrict__ lmax, int64_t n_nodes,
                                                    NodeRec* __restrict__ nodes,
                                                    const uint32_t* __restrict__ lvl_off,
-                                                   uint32_t* __restrict__ lvl_fill,
+                                                   const uint32_t* __restrict__ blkh,
                                                    int32_t* __restrict__ lvl_ids) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    const bool has = i < n && cnt[i] > 0;
-    int Li = -1, lstart = 0;
-    uint32_t bi = 0;
-    if (has) {
-        Li = lmax[i];
-        lstart = Li - (int)cnt[i] + 1;
-        bi = base[i];
-        const uint64_t ki = key[i];
-        // deepest node first: each shallower node ends at or after the deeper
-        // one, so its end is searched from there, galloping then bisecting
-        int64_t lo = i + 1;
-        for (int l = Li; l >= lstart; l--) {
-            int64_t end;
-            if (l == 0) {
-                end = n;
-            } else {
-                const int shift = 3 * (GX_MAX_LEVEL - l);
-                const uint64_t pre = ki >> shift;
-                int64_t step = 1, hi = n;
-                for (;;) {
-                    const int64_t p = lo + step - 1;
-                    if (p >= n) break;
-                    if ((key[p] >> shift) != pre) {
-                        hi = p;
-                        break;
-                    }
-                    lo = p + 1;
-                    step <<= 1;
-                }
-                while (lo < hi) {  // first index in [lo, hi) with a different prefix
-                    const int64_t mid = (lo + hi) >> 1;
-                    if ((key[mid] >> shift) == pre) lo = mid + 1;
-                    else hi = mid;
-                }
-                end = lo;
-            }
-            NodeRec r;
-            r.begin = (int32_t)i;
-            r.end = (int32_t)end;
-            r.level = (int16_t)l;
-            r.leaf = (int8_t)(l == Li);
-            r.nchild = 0;
-            r.next = (int32_t)(end < n ? (int64_t)base[end] : n_nodes);
-            r.lo[0] = r.lo[1] = r.lo[2] = 0.0;
-            r.hi[0] = r.hi[1] = r.hi[2] = 0.0;
-            nodes[(int64_t)bi + (l - lstart)] = r;
-            lo = end;
-        }
-    }
-    // per-level id lists: slots counted in LDS per workgroup, then one global
-    // counter update per workgroup and level (the level counters are shared
-    // by the whole grid, so per-wave or per-node updates would serialise)
     __shared__ uint32_t lcnt[GX_MAX_LEVEL + 1], lbase[GX_MAX_LEVEL + 1];
-    if (threadIdx.x <= GX_MAX_LEVEL) lcnt[threadIdx.x] = 0;
-    __syncthreads();
-    uint32_t slot[GX_MAX_LEVEL + 1];
-    if (has)
-        for (int l = lstart; l <= Li; l++) slot[l] = atomicAdd(&lcnt[l], 1u);
-    __syncthreads();
     if (threadIdx.x <= GX_MAX_LEVEL) {
-        const uint32_t c = lcnt[threadIdx.x];
-        lbase[threadIdx.x] = c ? atomicAdd(&lvl_fill[threadIdx.x], c) : 0u;
+        lcnt[threadIdx.x] = 0;
+        lbase[threadIdx.x] = lvl_off[threadIdx.x] + blkh[(int64_t)threadIdx.x * gridDim.x + blockIdx.x];
     }
     __syncthreads();
-    if (has)
-        for (int l = lstart; l <= Li; l++)
-            lvl_ids[lvl_off[l] + lbase[l] + slot[l]] = (int32_t)(bi + (l - lstart));
+    const int64_t span = tb_span(n, gridDim.x);
+    const int64_t r0 = (int64_t)blockIdx.x * span, r1 = r0 + span < n ? r0 + span : n;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x)
+        emit_nodes(i, n, key, cnt, base, lmax, n_nodes, nodes, lcnt, lbase, lvl_ids);
 }
 
 // Parent of every node and the (up to 8) children of every internal node in
@@ -516,12 +565,16 @@ extern "C" int gx_tree_build(gx_ctx* ctx, const gx_particles* p, int which, int 
     uint32_t* cnt = (uint32_t*)T.cnt.p;
     uint32_t* base = cnt + (n + 1);
     uint32_t* lvl_hist = (uint32_t*)T.lvl_fill.p;  // [0..21] histogram, [22] n_nodes
-    uint32_t* lvl_aux = lvl_hist + 32;             // [0..21] offsets, then fill counters
+    uint32_t* lvl_aux = lvl_hist + 32;             // [0..21] level offsets
     GX_TRY(gx_zero(ctx, lvl_hist, 2 * 32 * sizeof(uint32_t)));
     hipLaunchKernelGGL(k_window, dim3(gx_blocks(n, 256)), dim3(256), 0, st, n, key, n_leaf,
                        (int8_t*)T.win.p);
-    hipLaunchKernelGGL(k_node_count, dim3(gx_blocks(n, 256)), dim3(256), 0, st, n, key,
-                       (const int8_t*)T.win.p, n_leaf, cnt, (int8_t*)T.lmax.p, lvl_hist);
+    const int tb = tb_blocks(n);
+    GX_TRY(gx_reserve(ctx, T.blkh, (size_t)(GX_MAX_LEVEL + 1) * tb * sizeof(uint32_t)));
+    uint32_t* blkh = (uint32_t*)T.blkh.p;
+    hipLaunchKernelGGL(k_node_count, dim3(tb), dim3(256), 0, st, n, key, (const int8_t*)T.win.p,
+                       n_leaf, cnt, (int8_t*)T.lmax.p, blkh);
+    hipLaunchKernelGGL(k_level_scan, dim3(GX_MAX_LEVEL + 1), dim3(256), 0, st, tb, blkh, lvl_hist);
     GX_LAUNCH_CHECK(ctx);
     GX_TRY((gx_scan<uint32_t, uint32_t>(ctx, cnt, base, n, lvl_hist + 22)));
 
@@ -553,12 +606,11 @@ extern "C" int gx_tree_build(gx_ctx* ctx, const gx_particles* p, int which, int 
     GX_TRY(gx_reserve(ctx, T.child, nn * 8 * sizeof(int32_t)));
     GX_TRY(gx_reserve(ctx, T.lvl_ids, nn * sizeof(int32_t)));
     GX_TRY(gx_reserve(ctx, T.flag, (nn + 1) * sizeof(uint32_t) * 2));
-    // level offsets to the device, fill counters zeroed
+    // level offsets to the device
     GX_HIP(ctx, hipMemcpyAsync(lvl_aux, lvl_off_h, 32 * sizeof(uint32_t), hipMemcpyHostToDevice, st));
-    GX_TRY(gx_zero(ctx, lvl_hist, 32 * sizeof(uint32_t)));
-    hipLaunchKernelGGL(k_node_emit, dim3(gx_blocks(n, 256)), dim3(256), 0, st, n, key, cnt, base,
-                       (const int8_t*)T.lmax.p, nn, (NodeRec*)T.nodes.p, lvl_aux, lvl_hist,
-                       (int32_t*)T.lvl_ids.p);
+    hipLaunchKernelGGL(k_node_emit, dim3(tb), dim3(256), 0, st, n, key, cnt, base,
+                       (const int8_t*)T.lmax.p, nn, (NodeRec*)T.nodes.p, lvl_aux,
+                       (const uint32_t*)blkh, (int32_t*)T.lvl_ids.p);
     hipLaunchKernelGGL(k_node_parent, dim3(gx_blocks(nn, 256)), dim3(256), 0, st, nn,
                        (NodeRec*)T.nodes.p, (int32_t*)T.parent.p, (int32_t*)T.child.p);
     GX_LAUNCH_CHECK(ctx);
