@@ -317,15 +317,17 @@ def test_list_slots_equal_two_pass_and_fall_back(gx, eng):
         assert np.max(np.abs(b[3] - a[3]) / np.abs(a[3])) <= 1e-6
 
 
-def test_walk_small_stack_overflow_retries_with_large_stack(gx):
+@pytest.mark.parametrize("limit", ["tiny", "half"])
+def test_walk_small_stack_overflow_retries_with_large_stack(gx, limit):
     # The first calls on a tree learn the list slot sizes (two-pass, then the
-    # one-pass walk).  With the walk's stack limited to 24 entries
-    # (gx_set_walk_stack_limit) the next call tries that small stack first:
-    # the walk overflows it (the kernel stops pushing and flags the groups)
-    # while the lists still fit their slots, so the call walks once more with
-    # the large stack and stays on the one-pass path, with the same lists in
-    # the same order as the call before it: the same forces bit for bit, and
-    # the oracle's lists as sets.
+    # one-pass walk).  With the walk's small stack limited
+    # (gx_set_walk_stack_limit) to 24 entries (every group overflows it) or to
+    # half the deepest stack of the previous call (only the deeper groups do),
+    # the next call tries that small stack first: the walk stops pushing in
+    # those groups and flags them while the lists still fit their slots, so
+    # the call walks once more with the large stack and stays on the one-pass
+    # path, with the same lists in the same order as the call before it: the
+    # same forces bit for bit, and the oracle's lists as sets.
     d = ics.disk_galaxy(30000, 6)
     e = gx.Engine(0)
     p = _dev(gx, d)
@@ -333,7 +335,8 @@ def test_walk_small_stack_overflow_retries_with_large_stack(gx):
     res = []
     for k in range(5):
         if k == 4:
-            e.set_walk_stack_limit(24)
+            cap = 24 if limit == "tiny" else res[3][1]["n_iter_max"] // 2
+            e.set_walk_stack_limit(cap)
         out = _zeros(p.n)
         st = e.gravity_forces(p, 1.0, 0.5, gx.GX_QUAD, *out)
         res.append((_np(out), st, e.gravity_lists()))
@@ -341,7 +344,7 @@ def test_walk_small_stack_overflow_retries_with_large_stack(gx):
     e.close()
     (a, sa, _), (b, sb, lb) = res[3], res[4]
     assert sa["n_rewalk"] == 0 and sb["n_rewalk"] == 0
-    assert sb["n_iter_max"] == sa["n_iter_max"] > 24
+    assert sb["n_iter_max"] == sa["n_iter_max"] > cap
     for u, v in zip(a, b):
         assert np.array_equal(u, v)
     T = oracle.Tree(d, 16, 256)
