@@ -1011,35 +1011,64 @@ __global__ __launch_bounds__(192) void k_wgrad_lds(const uint16_t* __restrict__ 
 #pragma unroll
     for (int t = 0; t < 9; t++) acc[t][0] = acc[t][1] = f32x4{0, 0, 0, 0};
     float bsa = 0.0f, bsb = 0.0f;
-    for (int tile = t0; tile < t1; tile++) {
+    // the next tile's input rows and output gradient are read into registers
+    // while the current tile's MFMAs run, and stored to LDS between barriers
+    constexpr int XCH = 3 * (R + 2) * 16 * (S / 8);  // 16-byte pieces of input rows
+    constexpr int NX = (XCH + 191) / 192, NY = (32 * 32 + 191) / 192;
+    uint4 px[NX], py[NY];
+    auto load_tile = [&](int tile) {
         const int plane = tile / (S / R), y0 = (tile % (S / R)) * R;
         const int b = plane >> LGS, z = plane & (S - 1);
-        __syncthreads();  // the previous tile's reads are done
-        // input rows: (plane p, row r, channel c, 8-voxel chunk k)
-        constexpr int XCH = 3 * (R + 2) * 16 * (S / 8);
-        for (int e = tid; e < XCH; e += 192) {
+#pragma unroll
+        for (int j = 0; j < NX; j++) {
+            const int e = tid + 192 * j;
             const int k = e % (S / 8);
             const int c = (e / (S / 8)) % 16;
             const int r = (e / (S / 8 * 16)) % (R + 2);
             const int pz = e / (S / 8 * 16 * (R + 2));
             const int zz = z + pz - 1, yy = y0 + r - 1, ci = cib * 16 + c;
             uint4 v = make_uint4(0, 0, 0, 0);
-            if (zz >= 0 && zz < S && yy >= 0 && yy < S && ci < Cin)
+            if (e < XCH && zz >= 0 && zz < S && yy >= 0 && yy < S && ci < Cin)
                 v = *reinterpret_cast<const uint4*>(
                     xt + ((int64_t)b * Cin + ci) * V + ((int64_t)zz << (2 * LGS)) +
                     ((int64_t)yy << LGS) + k * 8);
-            *reinterpret_cast<uint4*>(&sx[pz][r][c][8 + k * 8]) = v;
+            px[j] = v;
         }
-        // output gradient of the tile: (channel c, 8-voxel chunk k)
         const int64_t vb = ((int64_t)z << (2 * LGS)) + ((int64_t)y0 << LGS);
-        for (int e = tid; e < 32 * 32; e += 192) {
+#pragma unroll
+        for (int j = 0; j < NY; j++) {
+            const int e = tid + 192 * j;
             const int k = e & 31, c = e >> 5, co = cob * 32 + c;
             uint4 v = make_uint4(0, 0, 0, 0);
-            if (co < Cout)
+            if (e < 32 * 32 && co < Cout)
                 v = *reinterpret_cast<const uint4*>(yt + ((int64_t)b * Cout + co) * V + vb + k * 8);
-            *reinterpret_cast<uint4*>(&sy[c][k * 8]) = v;
+            py[j] = v;
         }
+    };
+    auto store_tile = [&]() {
+#pragma unroll
+        for (int j = 0; j < NX; j++) {
+            const int e = tid + 192 * j;
+            if (e < XCH) {
+                const int k = e % (S / 8);
+                const int c = (e / (S / 8)) % 16;
+                const int r = (e / (S / 8 * 16)) % (R + 2);
+                const int pz = e / (S / 8 * 16 * (R + 2));
+                *reinterpret_cast<uint4*>(&sx[pz][r][c][8 + k * 8]) = px[j];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NY; j++) {
+            const int e = tid + 192 * j;
+            if (e < 32 * 32) *reinterpret_cast<uint4*>(&sy[e >> 5][(e & 31) * 8]) = py[j];
+        }
+    };
+    if (t0 < t1) load_tile(t0);
+    for (int tile = t0; tile < t1; tile++) {
+        __syncthreads();  // the previous tile's reads are done
+        store_tile();
         __syncthreads();
+        if (tile + 1 < t1) load_tile(tile + 1);
 #pragma unroll 2
         for (int st = 0; st < 8; st++) {
             const int t = st * 32 + (lane >> 4) * 8;  // this lane's 8 voxels in the tile
