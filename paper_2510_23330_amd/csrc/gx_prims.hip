@@ -107,7 +107,7 @@ extern "C" int gx_destroy(gx_ctx* ctx) {
     }
     for (auto* L : {&ctx->grav, &ctx->sph})
         for (auto* b : {&L->pc_cnt, &L->pc_off, &L->pc_list, &L->pr_cnt, &L->pr_off, &L->pr_begin,
-                        &L->pr_cum, &L->pp_tot, &L->tot})
+                        &L->pr_cum, &L->pp_tot, &L->tot, &L->aux})
             free_buf(*b);
     for (auto& b : ctx->scan_tmp) free_buf(b);
     for (auto& b : ctx->sph_work) free_buf(b);
