@@ -971,8 +971,8 @@ __global__ __launch_bounds__(256) void k_wgrad_cm(const uint16_t* __restrict__ x
     }
 }
 
-// The same product for grids of 32^3 and 64^3 with the operands staged in
-// LDS: a block of three waves (one per z offset of the taps) takes tiles of
+// The same product for grids of 16^3, 32^3 and 64^3 with the operands staged
+// in LDS: a block of three waves (one per z offset of the taps) takes tiles of
 // 256 output voxels (R = 256 / S rows of one z plane) for one block of 16
 // input and 32 output channels.  Per tile it stages the input rows the 27
 // taps read (3 planes x (R + 2) rows x S voxels x 16 channels, from the
@@ -1654,7 +1654,7 @@ static int wgrad_reduce_chunks(gx_ctx* ctx, const float* part, const float* bpar
     return GX_OK;
 }
 
-// 3^3 weight gradient on 32^3 and 64^3 grids with LDS-staged operands
+// 3^3 weight gradient on 16^3, 32^3 and 64^3 grids with LDS-staged operands
 // (k_wgrad_lds); xt, yt are the channel-major copies.
 static int wgrad_staged(gx_ctx* ctx, const uint16_t* xt, const uint16_t* yt, const ConvGeom& g,
                         float* dw, float* dbias) {
@@ -1673,8 +1673,11 @@ static int wgrad_staged(gx_ctx* ctx, const uint16_t* xt, const uint16_t* yt, con
     if (g.S == 64)
         hipLaunchKernelGGL(k_wgrad_lds<6>, grid, dim3(192), 0, ctx->stream, xt, yt, g.B, g.Cin,
                            g.Cout, tpb, part, bpart);
-    else
+    else if (g.S == 32)
         hipLaunchKernelGGL(k_wgrad_lds<5>, grid, dim3(192), 0, ctx->stream, xt, yt, g.B, g.Cin,
+                           g.Cout, tpb, part, bpart);
+    else
+        hipLaunchKernelGGL(k_wgrad_lds<4>, grid, dim3(192), 0, ctx->stream, xt, yt, g.B, g.Cin,
                            g.Cout, tpb, part, bpart);
     GX_LAUNCH_CHECK(ctx);
     return wgrad_reduce_chunks(ctx, part, bpart, nw, chunks, g.Cout, dw, dbias);
@@ -1695,7 +1698,7 @@ static int wgrad_cmajor(gx_ctx* ctx, const uint16_t* in, const uint16_t* dout, c
                        g.Cin, xt);
     hipLaunchKernelGGL(k_to_cmajor, dim3((unsigned)(M / 64)), dim3(256), 0, ctx->stream, dout, V,
                        g.Cout, yt);
-    if (g.kvol == 27 && (g.S == 32 || g.S == 64))
+    if (g.kvol == 27 && (g.S == 16 || g.S == 32 || g.S == 64))
         return wgrad_staged(ctx, xt, yt, g, dw, dbias);
     const int ndz = g.kvol == 27 ? 3 : 1;
     const int tasks = ((g.Cin + 15) / 16) * ndz * ((g.Cout + 31) / 32);
