@@ -541,6 +541,17 @@ int gx_conv3d_bwd_data(gx_ctx* ctx, const uint16_t* dout, int B, int S, int Cin,
  * sum of dout (may be NULL).  Accumulates: zero them first. */
 int gx_conv3d_bwd_weight(gx_ctx* ctx, const uint16_t* in, const uint16_t* dout, int B, int S,
                          int Cin, int ksize, int Cout, float* dw, float* dbias);
+/* gx_conv3d_bwd_weight with the layer input described as gx_conv3d_fwd_fused
+ * takes it: channels 0 .. c1 - 1 from in ([B][V][c1]) and c1 .. Cin - 1 from
+ * in2 ([B][V][Cin - c1]; NULL: c1 = Cin), and with upsample = 1 both read at
+ * the nearest voxel of the (S/2)^3 grid, so that training needs no
+ * concatenated or upsampled copy of the U-Net's up-path inputs.  Equals
+ * gx_conv3d_bwd_weight on the materialised input, bit for bit.  Needs S a
+ * power of two >= 8, Cin and Cout <= 256, c1 a multiple of 8 (GX_EINVAL
+ * otherwise). */
+int gx_conv3d_bwd_weight_fused(gx_ctx* ctx, const uint16_t* in, int c1, const uint16_t* in2,
+                               int upsample, const uint16_t* dout, int B, int S, int Cin,
+                               int ksize, int Cout, float* dw, float* dbias);
 /* 2^3 average pooling of in [B][S^3][C] -> out [B][(S/2)^3][C]; backward = 1:
  * in is dL/dout at S/2 and out is dL/din at S. */
 int gx_avgpool2(gx_ctx* ctx, const uint16_t* in, int B, int S, int C, uint16_t* out, int backward);
@@ -638,10 +649,12 @@ int gx_unet_backward(gx_ctx* ctx, const gx_unet* net, const uint16_t* in, int B,
                      const uint16_t* dout, float* grad);
 /* Copy a tensor written by the last forward pass (gradient = 0: the
  * activation `name`, e.g. "e1b", "p0", "u0c", "d0a", and with save = 1 also
- * "up0", "c0") or by the backward pass after it (gradient = 1: the gradient
- * of that activation's pre-activation, or "skip{l}") to device bf16 dst (cap
- * elements), stream ordered; *count gets its element count (dst may be NULL
- * to ask only for it).  Inspection for tests. */
+ * the up path's upsampled and concatenated inputs "up0", "c0", formed again
+ * from the kept activations where the pass did not keep them) or by the
+ * backward pass after it (gradient = 1: the gradient of that activation's
+ * pre-activation, or "skip{l}") to device bf16 dst (cap elements), stream
+ * ordered; *count gets its element count (dst may be NULL to ask only for
+ * it).  Inspection for tests. */
 int gx_unet_saved(gx_ctx* ctx, const char* name, int gradient, uint16_t* dst, int64_t cap,
                   int64_t* count);
 /* Standardisation of the network's channels from FP64 sums (gx_chan_stats

@@ -481,6 +481,14 @@ class Engine:
                                                   Cout, _ptr(dw, torch.float32),
                                                   _ptr(dbias, torch.float32)))
 
+    def conv3d_bwd_weight_fused(self, x, c1, x2, upsample, dout, B, S, Cin, ksize, Cout, dw,
+                                dbias=None):
+        torch = _torch()
+        self._check(self.lib.gx_conv3d_bwd_weight_fused(
+            self.ctx, _ptr(x, torch.bfloat16), int(c1), _ptr(x2, torch.bfloat16), int(upsample),
+            _ptr(dout, torch.bfloat16), B, S, Cin, ksize, Cout, _ptr(dw, torch.float32),
+            _ptr(dbias, torch.float32)))
+
     def avgpool2(self, x, B, S, Cc, out, backward=False):
         torch = _torch()
         self._check(self.lib.gx_avgpool2(self.ctx, _ptr(x, torch.bfloat16), B, S, Cc,

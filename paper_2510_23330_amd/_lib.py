@@ -96,6 +96,7 @@ SIGNATURES = {
     "gx_conv_head": (I32, [P, P, I32, I32, I32, P, P, I32, I32, P, P, P, I32]),
     "gx_conv3d_bwd_data": (I32, [P, P, I32, I32, I32, P, I32, I32, P, P]),
     "gx_conv3d_bwd_weight": (I32, [P, P, P, I32, I32, I32, I32, I32, P, P]),
+    "gx_conv3d_bwd_weight_fused": (I32, [P, P, I32, P, I32, P, I32, I32, I32, I32, I32, P, P]),
     "gx_avgpool2": (I32, [P, P, I32, I32, I32, P, I32]),
     "gx_upsample2": (I32, [P, P, I32, I32, I32, P, I32]),
     "gx_concat": (I32, [P, P, I32, P, I32, I64, P, I32]),

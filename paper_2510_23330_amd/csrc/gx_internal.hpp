@@ -158,6 +158,8 @@ int gx_radix_sort(gx_ctx* ctx, TreeSlot& T, int64_t n, int key_bits);
 int gx_radix_sort_bufs(gx_ctx* ctx, Buf* key, Buf* val, int64_t n, int key_bits);
 // Level-order walk arrays of a built tree (kept until the next build).
 int gx_walk_tree(gx_ctx* ctx, TreeSlot& T);
+// the weight gradient takes the channel-major path (and a fused input)
+bool gx_wgrad_fused_ok(int S, int Cin, int Cout);
 // The same plus the level-order node kernel sizes for SPH walks with use_hmax.
 int gx_walk_tree_sph(gx_ctx* ctx, TreeSlot& T, int use_hmax);
 

@@ -818,16 +818,31 @@ __global__ __launch_bounds__(256) void k_conv3d_wgrad(const uint16_t* __restrict
 // the x offsets of -1 and +1 come from the same 8 voxels and their left and
 // right neighbours by byte alignment.
 // ---------------------------------------------------------------------------
-// out[b][c][v] = in[b][v][c] (bf16), one block per 64 voxels of one sample.
-__global__ __launch_bounds__(256) void k_to_cmajor(const uint16_t* __restrict__ in, int64_t V,
-                                                   int C, uint16_t* __restrict__ out) {
+// out[b][c][v] = in[b][v][c] (bf16), one block per 64 voxels of one sample
+// (V = S^3 voxels per sample, lgS = log2 S).  The input may be described as
+// the fused convolutions take it: channels c1 .. C - 1 from a second source
+// in2 (channel concatenation; c1 = C without one), and with up = 1 both
+// sources on the (S/2)^3 grid, read at the nearest-upsampled voxel.
+__global__ __launch_bounds__(256) void k_to_cmajor(const uint16_t* __restrict__ in,
+                                                   const uint16_t* __restrict__ in2, int c1,
+                                                   int up, int lgS, int64_t V, int C,
+                                                   uint16_t* __restrict__ out) {
     __shared__ uint16_t t[256 * 66];
     const int64_t v0 = (int64_t)blockIdx.x * 64;
     const int64_t b = v0 / V, vv = v0 - b * V;
     const int cg8 = C / 8;
     for (int e = threadIdx.x; e < 64 * cg8; e += 256) {
         const int vox = e / cg8, cg = e - vox * cg8;
-        const uint4 d = *reinterpret_cast<const uint4*>(in + (v0 + vox) * C + cg * 8);
+        int64_t sv = v0 + vox;  // voxel of the source (same grid)
+        if (up) {
+            const int64_t w = vv + vox, S = (int64_t)1 << lgS, h = S >> 1;
+            const int64_t z = w >> (2 * lgS), y = (w >> lgS) & (S - 1), x = w & (S - 1);
+            sv = (b * h + (z >> 1)) * h * h + (y >> 1) * h + (x >> 1);
+        }
+        const int c = cg * 8;
+        const uint16_t* src = (in2 && c >= c1) ? in2 + sv * (C - c1) + (c - c1)
+                                               : in + sv * (in2 ? c1 : C) + c;
+        const uint4 d = *reinterpret_cast<const uint4*>(src);
         const uint16_t* h = reinterpret_cast<const uint16_t*>(&d);
 #pragma unroll
         for (int q = 0; q < 8; q++) t[(cg * 8 + q) * 66 + vox] = h[q];
@@ -1686,18 +1701,18 @@ static int wgrad_staged(gx_ctx* ctx, const uint16_t* xt, const uint16_t* yt, con
 // Weight and bias gradients through channel-major copies (k_wgrad_cm): the
 // voxel range is split into chunks so that the tasks fill the device, each
 // chunk writes its partial gradient, and the partials are added in chunk order.
-static int wgrad_cmajor(gx_ctx* ctx, const uint16_t* in, const uint16_t* dout, const ConvGeom& g,
-                        float* dw, float* dbias) {
+static int wgrad_cmajor(gx_ctx* ctx, const uint16_t* in, const uint16_t* in2, int c1, int up,
+                        const uint16_t* dout, const ConvGeom& g, float* dw, float* dbias) {
     const int64_t V = (int64_t)g.S * g.S * g.S, M = g.M;
     const int lgS = ilog2(g.S);
     GX_TRY(gx_reserve(ctx, ctx->xcm, (size_t)M * g.Cin * sizeof(uint16_t)));
     GX_TRY(gx_reserve(ctx, ctx->ycm, (size_t)M * g.Cout * sizeof(uint16_t)));
     uint16_t* xt = (uint16_t*)ctx->xcm.p;
     uint16_t* yt = (uint16_t*)ctx->ycm.p;
-    hipLaunchKernelGGL(k_to_cmajor, dim3((unsigned)(M / 64)), dim3(256), 0, ctx->stream, in, V,
-                       g.Cin, xt);
-    hipLaunchKernelGGL(k_to_cmajor, dim3((unsigned)(M / 64)), dim3(256), 0, ctx->stream, dout, V,
-                       g.Cout, yt);
+    hipLaunchKernelGGL(k_to_cmajor, dim3((unsigned)(M / 64)), dim3(256), 0, ctx->stream, in, in2,
+                       c1, up, lgS, V, g.Cin, xt);
+    hipLaunchKernelGGL(k_to_cmajor, dim3((unsigned)(M / 64)), dim3(256), 0, ctx->stream, dout,
+                       (const uint16_t*)nullptr, g.Cout, 0, lgS, V, g.Cout, yt);
     if (g.kvol == 27 && (g.S == 16 || g.S == 32 || g.S == 64))
         return wgrad_staged(ctx, xt, yt, g, dw, dbias);
     const int ndz = g.kvol == 27 ? 3 : 1;
@@ -1722,6 +1737,30 @@ static int wgrad_cmajor(gx_ctx* ctx, const uint16_t* in, const uint16_t* dout, c
     return wgrad_reduce_chunks(ctx, part, bpart, nw, chunks, g.Cout, dw, dbias);
 }
 
+// Shapes of the weight gradient through channel-major copies (and of its
+// fused-input form).
+bool gx_wgrad_fused_ok(int S, int Cin, int Cout) {
+    return pow2(S) && S >= 8 && Cin <= 256 && Cout <= 256 && Cin % 8 == 0 && Cout % 8 == 0;
+}
+
+extern "C" int gx_conv3d_bwd_weight_fused(gx_ctx* ctx, const uint16_t* in, int c1,
+                                          const uint16_t* in2, int upsample,
+                                          const uint16_t* dout, int B, int S, int Cin, int ksize,
+                                          int Cout, float* dw, float* dbias) {
+    if (!ctx || !in || !dout || !dw) return GX_EINVAL;
+    GX_TRY(check_conv(ctx, B, S, Cin, Cout, ksize, Cin));
+    if (!gx_wgrad_fused_ok(S, Cin, Cout))
+        return gx_fail(ctx, GX_EINVAL, "conv3d_bwd_weight_fused: S a power of two >= 8, Cin and "
+                                       "Cout <= 256, multiples of 8");
+    if (in2 ? (c1 <= 0 || c1 >= Cin || c1 % 8 != 0) : c1 != Cin)
+        return gx_fail(ctx, GX_EINVAL, "conv3d_bwd_weight_fused: bad channel split");
+    if (upsample != 0 && upsample != 1) return gx_fail(ctx, GX_EINVAL, "bad upsample flag");
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    const int kv = ksize == 3 ? 27 : 1;
+    ConvGeom g{B, S, Cin, Cout, kv, (int64_t)B * S * S * S, kv * Cin, ilog2(Cin)};
+    return wgrad_cmajor(ctx, in, in2, c1, upsample, dout, g, dw, dbias);
+}
+
 extern "C" int gx_conv3d_bwd_weight(gx_ctx* ctx, const uint16_t* in, const uint16_t* dout, int B,
                                     int S, int Cin, int ksize, int Cout, float* dw, float* dbias) {
     if (!ctx || !in || !dout || !dw) return GX_EINVAL;
@@ -1729,8 +1768,8 @@ extern "C" int gx_conv3d_bwd_weight(gx_ctx* ctx, const uint16_t* in, const uint1
     GX_HIP(ctx, hipSetDevice(ctx->device));
     const int kv = ksize == 3 ? 27 : 1;
     ConvGeom g{B, S, Cin, Cout, kv, (int64_t)B * S * S * S, kv * Cin, ilog2(Cin)};
-    if (pow2(S) && S >= 8 && Cin <= 256 && Cout <= 256)
-        return wgrad_cmajor(ctx, in, dout, g, dw, dbias);
+    if (gx_wgrad_fused_ok(S, Cin, Cout))
+        return wgrad_cmajor(ctx, in, nullptr, Cin, 0, dout, g, dw, dbias);
     const int kt = (g.K + 63) / 64;
     const int bn = Cout % 64 == 0 ? 64 : (Cout % 32 == 0 ? 32 : 16);
     const int nt = Cout / bn;

@@ -187,19 +187,26 @@ extern "C" int gx_unet_forward(gx_ctx* ctx, const gx_unet* net, const uint16_t* 
         GX_TRY(A(da, V * ch[l], &pda));
         GX_TRY(A(db, V * ch[l], &pdb));
         pe = (uint16_t*)st.act["e" + ls + "b"].p;
-        if (save) {  // the backward pass needs the upsampled and concatenated inputs
-            uint16_t *pup, *pc;
+        // the backward pass needs the upsampled and concatenated inputs of
+        // the up path as copies only where its weight gradient cannot read
+        // them from their sources (gx_wgrad_fused_ok)
+        if (save && !gx_wgrad_fused_ok(s, ch[l + 1], ch[l])) {
+            uint16_t* pup;
             GX_TRY(A("up" + ls, V * ch[l + 1], &pup));
-            GX_TRY(A("c" + ls, V * 2 * ch[l], &pc));
             GX_TRY(gx_upsample2(ctx, h, B, s / 2, ch[l + 1], pup, 0));
             GX_TRY(gx_conv3d_fwd(ctx, pup, B, s, ch[l + 1], w(uc.c_str()), b(uc.c_str()), 3, ch[l], 1,
                                  pu, nullptr));
+        } else {
+            GX_TRY(gx_conv3d_fwd_fused(ctx, h, ch[l + 1], nullptr, 1, B, s, ch[l + 1], w(uc.c_str()),
+                                       b(uc.c_str()), ch[l], 1, pu, nullptr));
+        }
+        if (save && !gx_wgrad_fused_ok(s, 2 * ch[l], ch[l])) {
+            uint16_t* pc;
+            GX_TRY(A("c" + ls, V * 2 * ch[l], &pc));
             GX_TRY(gx_concat(ctx, pu, ch[l], pe, ch[l], V, pc, 0));
             GX_TRY(gx_conv3d_fwd(ctx, pc, B, s, 2 * ch[l], w(da.c_str()), b(da.c_str()), 3, ch[l], 1,
                                  pda, nullptr));
         } else {
-            GX_TRY(gx_conv3d_fwd_fused(ctx, h, ch[l + 1], nullptr, 1, B, s, ch[l + 1], w(uc.c_str()),
-                                       b(uc.c_str()), ch[l], 1, pu, nullptr));
             GX_TRY(gx_conv3d_fwd_fused(ctx, pu, ch[l], pe, 0, B, s, 2 * ch[l], w(da.c_str()),
                                        b(da.c_str()), ch[l], 1, pda, nullptr));
         }
@@ -285,15 +292,30 @@ extern "C" int gx_unet_backward(gx_ctx* ctx, const gx_unet* net, const uint16_t*
         const std::string uc = "u" + ls + "c", da = "d" + ls + "a", db = "d" + ls + "b";
         GX_TRY(wgrad(db, act(da), g[db], s));
         GX_TRY(dgrad(db, g[db], s, act(da), g[da]));
-        GX_TRY(wgrad(da, act("c" + ls), g[da], s));
+        if (gx_wgrad_fused_ok(s, 2 * ch[l], ch[l])) {
+            const ULayer& ly = *by.at(da);
+            GX_TRY(gx_conv3d_bwd_weight_fused(ctx, act(uc), ch[l], act("e" + ls + "b"), 0, g[da], B,
+                                              s, ly.cin, ly.ksize, ly.cout, grad + ly.w_off,
+                                              grad + ly.b_off));
+        } else {
+            GX_TRY(wgrad(da, act("c" + ls), g[da], s));
+        }
         GX_TRY(dgrad(da, g[da], s, nullptr, g["c" + ls]));
         GX_TRY(gx_concat(ctx, g[uc], ch[l], g["skip" + ls], ch[l], V, g["c" + ls], 1));
         GX_TRY(gx_grad_combine(ctx, V * ch[l], g[uc], nullptr, act(uc), g[uc]));
-        GX_TRY(wgrad(uc, act("up" + ls), g[uc], s));
-        GX_TRY(dgrad(uc, g[uc], s, nullptr, g["up" + ls]));
-        // into the next coarser level's output
+        // the coarser level's output, whose upsampling is this layer's input
         const std::string below =
             l + 1 < top ? "d" + std::to_string(l + 1) + "b" : "e" + std::to_string(top) + "b";
+        if (gx_wgrad_fused_ok(s, ch[l + 1], ch[l])) {
+            const ULayer& ly = *by.at(uc);
+            GX_TRY(gx_conv3d_bwd_weight_fused(ctx, act(below), ch[l + 1], nullptr, 1, g[uc], B, s,
+                                              ly.cin, ly.ksize, ly.cout, grad + ly.w_off,
+                                              grad + ly.b_off));
+        } else {
+            GX_TRY(wgrad(uc, act("up" + ls), g[uc], s));
+        }
+        GX_TRY(dgrad(uc, g[uc], s, nullptr, g["up" + ls]));
+        // into the next coarser level's output
         const int sc = s / 2;
         const int64_t Vc = (int64_t)B * sc * sc * sc;
         GX_TRY(gx_upsample2(ctx, g["up" + ls], B, sc, ch[l + 1], g[below], 1));
@@ -331,10 +353,15 @@ extern "C" int gx_unet_saved(gx_ctx* ctx, const char* name, int gradient, uint16
     auto& m = gradient ? st.grad : st.act;
     auto& fresh = gradient ? st.fresh_grad : st.fresh_act;
     auto it = m.find(name);
-    if (it == m.end() || !fresh.count(name))
+    const std::string nm = name;
+    // the up path's upsampled ("up{l}") and concatenated ("c{l}") inputs are
+    // kept only where their weight gradient cannot read them from their
+    // sources; otherwise they are formed again here from the kept activations
+    const bool rebuild = !gradient && (it == m.end() || !fresh.count(name)) &&
+                         (nm.rfind("up", 0) == 0 || (nm[0] == 'c' && nm.size() > 1));
+    if (!rebuild && (it == m.end() || !fresh.count(name)))
         return gx_fail(ctx, GX_EINVAL, "unet_saved: %s not written by the last pass", name);
     // element count of the tensor at the last pass's shape
-    const std::string nm = name;
     const int lv = st.levels;
     int l = -1;
     int64_t cmul = 1;
@@ -353,6 +380,26 @@ extern "C" int gx_unet_saved(gx_ctx* ctx, const char* name, int gradient, uint16
     *count = n;
     if (!dst) return GX_OK;
     if (cap < n) return gx_fail(ctx, GX_EINVAL, "unet_saved: %s needs %lld elements", name, (long long)n);
+    if (rebuild) {
+        if (l >= lv - 1) return gx_fail(ctx, GX_EINVAL, "unet_saved: bad name %s", name);
+        const int top = lv - 1;
+        auto kept = [&](const std::string& k) -> uint16_t* {
+            auto a = st.act.find(k);
+            return (a != st.act.end() && st.fresh_act.count(k)) ? (uint16_t*)a->second.p : nullptr;
+        };
+        const std::string ls = std::to_string(l);
+        if (nm[0] == 'u') {
+            const std::string below =
+                l + 1 < top ? "d" + std::to_string(l + 1) + "b" : "e" + std::to_string(top) + "b";
+            uint16_t* src = kept(below);
+            if (!src) return gx_fail(ctx, GX_EINVAL, "unet_saved: %s not written by the last pass", name);
+            return gx_upsample2(ctx, src, st.B, s / 2, (int)C, dst, 0);
+        }
+        uint16_t *pu = kept("u" + ls + "c"), *pe = kept("e" + ls + "b");
+        if (!pu || !pe) return gx_fail(ctx, GX_EINVAL, "unet_saved: %s not written by the last pass", name);
+        const int64_t V = (int64_t)st.B * s * s * s;
+        return gx_concat(ctx, pu, (int)(C / 2), pe, (int)(C / 2), V, dst, 0);
+    }
     GX_HIP(ctx, hipMemcpyAsync(dst, it->second.p, (size_t)n * sizeof(uint16_t),
                                hipMemcpyDeviceToDevice, ctx->stream));
     return GX_OK;

@@ -327,6 +327,45 @@ def test_cube_symmetries(gx, eng):
     assert torch.equal(twice, t)
 
 
+@pytest.mark.parametrize("case,S,Ca,Cb,Cout", [("upsample", 16, 64, 0, 32), ("concat", 16, 32, 32, 32),
+                                               ("upsample", 64, 64, 0, 32), ("concat", 64, 32, 32, 32),
+                                               ("both", 8, 16, 16, 48)])
+def test_wgrad_fused_inputs_equal_materialized(gx, eng, case, S, Ca, Cb, Cout):
+    # The weight gradient of a layer whose input is assembled on the fly
+    # (nearest x2 upsampling and/or a channel concatenation), as the U-Net's
+    # up path trains without materialising those inputs, equals the weight
+    # gradient on the materialised input bit for bit (the same channel-major
+    # copy, gathered from the sources).
+    import torch
+    rng = np.random.default_rng(23)
+    B = 2
+    up = case in ("upsample", "both")
+    Sin = S // 2 if up else S
+    a = _bf(oracle.bf16_round(rng.normal(size=(B, Sin, Sin, Sin, Ca))))
+    b = _bf(oracle.bf16_round(rng.normal(size=(B, Sin, Sin, Sin, Cb)))) if case != "upsample" else None
+    Cin = Ca + (Cb if b is not None else 0)
+    V = B * S ** 3
+    dy = _bf(oracle.bf16_round(rng.normal(size=(B, S, S, S, Cout))))
+    if b is not None:
+        cat = torch.zeros(B * Sin ** 3 * Cin, dtype=torch.bfloat16, device="cuda")
+        eng.concat(a, Ca, b, Cb, B * Sin ** 3, cat)
+    else:
+        cat = a
+    if up:
+        full = torch.zeros(V * Cin, dtype=torch.bfloat16, device="cuda")
+        eng.upsample2(cat, B, Sin, Cin, full)
+    else:
+        full = cat
+    dw_ref = torch.zeros(Cout * 27 * Cin, dtype=torch.float32, device="cuda")
+    db_ref = torch.zeros(Cout, dtype=torch.float32, device="cuda")
+    eng.conv3d_bwd_weight(full, dy, B, S, Cin, 3, Cout, dw_ref, db_ref)
+    dw, db = torch.zeros_like(dw_ref), torch.zeros_like(db_ref)
+    eng.conv3d_bwd_weight_fused(a, Ca if b is not None else Cin, b, int(up), dy, B, S, Cin, 3, Cout,
+                                dw, db)
+    assert torch.equal(dw, dw_ref) and torch.equal(db, db_ref)
+    assert float(dw_ref.abs().max()) > 0
+
+
 @pytest.mark.parametrize("case,Ca,Cb", [("upsample", 32, 0), ("concat", 32, 32), ("concat", 16, 16),
                                         ("both", 32, 32)])
 def test_conv_fused_inputs_equal_materialized(gx, eng, case, Ca, Cb):
