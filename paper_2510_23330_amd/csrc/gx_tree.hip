@@ -337,18 +337,14 @@ __global__ __launch_bounds__(256) void k_node_parent(int64_t nn, NodeRec* __rest
     for (; k < 8; k++) child[8 * p + k] = -1;
 }
 
-// Moments of the nodes of one level: leaves from their particles, internal
-// nodes from their children (parallel-axis shift of the quadrupoles).
-__global__ __launch_bounds__(256) void k_moments_level(int cnt, const int32_t* __restrict__ ids,
-                                                       NodeRec* __restrict__ nodes,
-                                                       MomRec* __restrict__ mom,
-                                                       double* __restrict__ q64,
-                                                       const double4* __restrict__ pos4,
-                                                       const float* __restrict__ e2s) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= cnt) return;
-    int id = ids[k];
-    NodeRec nd = nodes[id];
+// Moments of one node: a leaf from its particles, an internal node from its
+// children (parallel-axis shift of the quadrupoles).  Every sum runs in
+// particle or child key order, whichever thread or launch computes it.
+__device__ __forceinline__ void node_moments(int id, const NodeRec& nd, NodeRec* __restrict__ nodes,
+                                             MomRec* __restrict__ mom, double* __restrict__ q64,
+                                             const double4* __restrict__ pos4,
+                                             const float* __restrict__ e2s,
+                                             const int32_t* __restrict__ child) {
     double M = 0, cx = 0, cy = 0, cz = 0, e2 = 0;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     double q[6] = {0, 0, 0, 0, 0, 0};
@@ -382,26 +378,32 @@ __global__ __launch_bounds__(256) void k_moments_level(int cnt, const int32_t* _
             q[5] += p.w * 3 * dy * dz;
         }
     } else {
-        // at most eight children, linked by their next fields; the first pass
-        // keeps their positions so the second needs no link chasing
+        // the (one to eight) children from the child rows, in key order; the
+        // loads do not depend on each other (absent slots read the first
+        // child and add nothing)
+        const int nc = nd.nchild;
         int cid[8];
-        int c = id + 1;
+        const int4 c03 = *reinterpret_cast<const int4*>(child + 8 * (int64_t)id);
+        const int4 c47 = *reinterpret_cast<const int4*>(child + 8 * (int64_t)id + 4);
+        cid[0] = c03.x; cid[1] = c03.y; cid[2] = c03.z; cid[3] = c03.w;
+        cid[4] = c47.x; cid[5] = c47.y; cid[6] = c47.z; cid[7] = c47.w;
+#pragma unroll
+        for (int j = 1; j < 8; j++) cid[j] = j < nc ? cid[j] : cid[0];
 #pragma unroll
         for (int j = 0; j < 8; j++) {
-            cid[j] = c;
-            if (c < nd.next) {
-                MomRec mc = mom[c];
+            const int c = cid[j];
+            const MomRec mc = mom[c];
+            const NodeRec nc_ = nodes[c];
+            if (j < nc) {
                 M += mc.M;
                 cx += mc.M * mc.cx;
                 cy += mc.M * mc.cy;
                 cz += mc.M * mc.cz;
                 e2 += mc.M * (double)mc.e2;
-                NodeRec nc = nodes[c];
                 for (int d = 0; d < 3; d++) {
-                    lo[d] = fmin(lo[d], nc.lo[d]);
-                    hi[d] = fmax(hi[d], nc.hi[d]);
+                    lo[d] = fmin(lo[d], nc_.lo[d]);
+                    hi[d] = fmax(hi[d], nc_.hi[d]);
                 }
-                c = nc.next;
             }
         }
         cx /= M;
@@ -410,17 +412,19 @@ __global__ __launch_bounds__(256) void k_moments_level(int cnt, const int32_t* _
 #pragma unroll
         for (int j = 0; j < 8; j++) {
             const int c = cid[j];
-            if (c >= nd.next) continue;
-            MomRec mc = mom[c];
+            const MomRec mc = mom[c];
             const double* qc = &q64[6 * (int64_t)c];
-            double dx = mc.cx - cx, dy = mc.cy - cy, dz = mc.cz - cz;
-            double d2 = dx * dx + dy * dy + dz * dz;
-            q[0] += qc[0] + mc.M * (3 * dx * dx - d2);
-            q[1] += qc[1] + mc.M * (3 * dy * dy - d2);
-            q[2] += qc[2] + mc.M * (3 * dz * dz - d2);
-            q[3] += qc[3] + mc.M * 3 * dx * dy;
-            q[4] += qc[4] + mc.M * 3 * dx * dz;
-            q[5] += qc[5] + mc.M * 3 * dy * dz;
+            const double Q0 = qc[0], Q1 = qc[1], Q2 = qc[2], Q3 = qc[3], Q4 = qc[4], Q5 = qc[5];
+            if (j < nc) {
+                double dx = mc.cx - cx, dy = mc.cy - cy, dz = mc.cz - cz;
+                double d2 = dx * dx + dy * dy + dz * dz;
+                q[0] += Q0 + mc.M * (3 * dx * dx - d2);
+                q[1] += Q1 + mc.M * (3 * dy * dy - d2);
+                q[2] += Q2 + mc.M * (3 * dz * dz - d2);
+                q[3] += Q3 + mc.M * 3 * dx * dy;
+                q[4] += Q4 + mc.M * 3 * dx * dz;
+                q[5] += Q5 + mc.M * 3 * dy * dz;
+            }
         }
     }
     MomRec r;
@@ -439,6 +443,35 @@ __global__ __launch_bounds__(256) void k_moments_level(int cnt, const int32_t* _
         nodes[id].lo[d] = lo[d];
         nodes[id].hi[d] = hi[d];
     }
+}
+
+// Every leaf in one launch, one thread per node id: ids are in pre-order, so
+// the leaves of a wavefront cover one contiguous run of particles.
+__global__ __launch_bounds__(256) void k_moments_leaves(int64_t nn, NodeRec* __restrict__ nodes,
+                                                        MomRec* __restrict__ mom,
+                                                        double* __restrict__ q64,
+                                                        const double4* __restrict__ pos4,
+                                                        const float* __restrict__ e2s) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nn) return;
+    const NodeRec nd = nodes[id];
+    if (!nd.leaf) return;
+    node_moments((int)id, nd, nodes, mom, q64, pos4, e2s, nullptr);
+}
+
+// The internal nodes of one level (their children are done: leaves by the
+// leaf launch, internal children by the launch of the level below).
+__global__ __launch_bounds__(256) void k_moments_level(int cnt, const int32_t* __restrict__ ids,
+                                                       NodeRec* __restrict__ nodes,
+                                                       MomRec* __restrict__ mom,
+                                                       double* __restrict__ q64,
+                                                       const int32_t* __restrict__ child) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= cnt) return;
+    const int id = ids[k];
+    const NodeRec nd = nodes[id];
+    if (nd.leaf) return;
+    node_moments(id, nd, nodes, mom, q64, nullptr, nullptr, child);
 }
 
 __global__ __launch_bounds__(256) void k_group_flag(int64_t nn, const NodeRec* __restrict__ nodes,
@@ -614,13 +647,15 @@ extern "C" int gx_tree_build(gx_ctx* ctx, const gx_particles* p, int which, int 
     hipLaunchKernelGGL(k_node_parent, dim3(gx_blocks(nn, 256)), dim3(256), 0, st, nn,
                        (NodeRec*)T.nodes.p, (int32_t*)T.parent.p, (int32_t*)T.child.p);
     GX_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_moments_leaves, dim3(gx_blocks(nn, 256)), dim3(256), 0, st, nn,
+                       (NodeRec*)T.nodes.p, (MomRec*)T.mom.p, (double*)T.q64.p,
+                       (const double4*)T.pos4.p, (const float*)T.e2s.p);
     for (int l = GX_MAX_LEVEL; l >= 0; l--) {
         int c = (int)T.lvl_hist[l];
         if (!c) continue;
         hipLaunchKernelGGL(k_moments_level, dim3(gx_blocks(c, 256)), dim3(256), 0, st, c,
                            (const int32_t*)T.lvl_ids.p + lvl_off_h[l], (NodeRec*)T.nodes.p,
-                           (MomRec*)T.mom.p, (double*)T.q64.p, (const double4*)T.pos4.p,
-                           (const float*)T.e2s.p);
+                           (MomRec*)T.mom.p, (double*)T.q64.p, (const int32_t*)T.child.p);
     }
     GX_LAUNCH_CHECK(ctx);
 
