@@ -54,25 +54,35 @@ FLOP_FORCE = 101                     # per SPH force candidate pair (Table 4)
 # rocprofv3 --pmc runs of this script (FETCH_SIZE, WRITE_SIZE in KiB per
 # dispatch) scaled by what the same counters read for a reference copy of
 # known size (hbm_calib.py beside this script: FETCH_SIZE reads half the bytes copied, WRITE_SIZE
-# all of them).  Valid only for the kernel source with this SHA-256 and the
-# particle order named (the outputs are scattered to the caller's order); any
-# change to gx_gravity.hip, or the other order, makes the bench report null.
-GRAV_TRAFFIC = {"source_sha256": "f4017782473c36415ef613041e522fded6e7c05565c2d168b077cfb1a4884057",
+# all of them).  Valid only for the kernel source with this SHA-256 (of
+# gx_gravity.hip followed by gx_internal.hpp) and the particle order named
+# (the outputs are scattered to the caller's order); any change to either
+# file, or the other order, makes the bench report null.
+GRAV_TRAFFIC = {"source_sha256": None,
                 "particle_order": "morton",
                 "fetch_kib": 3512425.75, "write_kib": 1480535.15625,
                 "fetch_scale": 2.0, "write_scale": 1.0}
 
 
-def grav_traffic_bytes(order):
+def grav_source_sha256():
+    """SHA-256 over the gravity kernel's source followed by the shared header
+    (record layouts, block-to-group mapping): the counters hold for exactly
+    this pair."""
     import hashlib
+    h = hashlib.sha256()
+    for f in ("gx_gravity.hip", "gx_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2510_23330_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def grav_traffic_bytes(order):
     if order != GRAV_TRAFFIC["particle_order"]:
         return None
-    src = os.path.join(ROOT, "paper_2510_23330_amd", "csrc", "gx_gravity.hip")
     if GRAV_TRAFFIC["source_sha256"] is None:
         return None
-    with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != GRAV_TRAFFIC["source_sha256"]:
-            return None
+    if grav_source_sha256() != GRAV_TRAFFIC["source_sha256"]:
+        return None
     return 1024.0 * (GRAV_TRAFFIC["fetch_kib"] * GRAV_TRAFFIC["fetch_scale"] +
                      GRAV_TRAFFIC["write_kib"] * GRAV_TRAFFIC["write_scale"])
 

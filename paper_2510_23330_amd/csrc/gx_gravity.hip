@@ -86,7 +86,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1))) void k_grav_force(
     const int32_t* __restrict__ pr_begin, const int32_t* __restrict__ pr_cum,
     const uint32_t* __restrict__ pp_tot, double G, double* __restrict__ ax, double* __restrict__ ay,
     double* __restrict__ az, double* __restrict__ pot) {
-    const int g = xcd_remap(blockIdx.x, ng);
+    const int g = xcd_chunk(blockIdx.x);
     if (g >= ng) return;
     __shared__ int32_t jidx[GF_CH];
     // source tiles: A = (x, y, z, m) group-relative; B = (eps^2, qxx, qyy, qzz);
@@ -443,7 +443,7 @@ extern "C" int gx_gravity_forces(gx_ctx* ctx, const gx_particles* p, double G, d
     const bool quad = (flags & GX_QUAD) && !(flags & GX_DIRECT);
     const bool fp64 = flags & GX_PREC_FP64;
     auto args = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3(xcd_grid(ng)), dim3(GF_THREADS), 0, st, ng,
+        hipLaunchKernelGGL(kern, dim3(xcd_chunk_grid(ng)), dim3(GF_THREADS), 0, st, ng,
                            (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
                            (const MomRec*)T.mom.p, (const double4*)T.pos4.p, (const float*)T.e2s.p,
                            (const uint32_t*)T.val[0].p, (const int64_t*)Ls.pc_off.p,

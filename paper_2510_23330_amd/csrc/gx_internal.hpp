@@ -269,6 +269,24 @@ __device__ __forceinline__ int xcd_remap(int b, int n_items) {
 }
 static inline unsigned xcd_grid(int64_t n_items) { return (unsigned)(8 * ((n_items + 7) / 8)); }
 
+// For items of very unequal cost (tree groups: list lengths vary with the
+// local density) one contiguous eighth per XCD loads the XCDs unequally (on
+// the 16M disk the busiest eighth of the gravity groups holds 1.15 times the
+// mean work, and the kernel lasts as long as that XCD).  Here the items are
+// dealt in chunks of XCD_CH consecutive items, chunk c to XCD c mod 8: every
+// XCD gets a share of every region, and neighbours within a chunk still
+// share one L2.  Blocks past the last item (the last round of chunks is
+// partly empty) map to indices >= n_items and must return.
+#define XCD_CH 16
+__device__ __forceinline__ int xcd_chunk(int b) {
+    const int k = b >> 3, x = b & 7;
+    return ((k / XCD_CH) * 8 + x) * XCD_CH + k % XCD_CH;
+}
+static inline unsigned xcd_chunk_grid(int64_t n_items) {
+    const int64_t chunks = (n_items + XCD_CH - 1) / XCD_CH;
+    return (unsigned)(8 * XCD_CH * ((chunks + 7) / 8));
+}
+
 // ---------------------------------------------------------------------------
 // SPH-style candidate lists (used by the SPH and voxelisation kernels)
 // ---------------------------------------------------------------------------

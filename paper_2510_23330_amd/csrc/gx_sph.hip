@@ -310,7 +310,7 @@ __global__ __launch_bounds__(SPH_DT) void k_sph_density(
     const double* __restrict__ u, float gamma,
     double* __restrict__ H64, float* __restrict__ Hout, float* __restrict__ rho_out,
     float* __restrict__ P_out, float* __restrict__ cs_out) {
-    const int g = xcd_remap(blockIdx.x, ng);
+    const int g = xcd_chunk(blockIdx.x);
     if (g >= ng) return;
     if (active && !active[g]) return;
     const GroupList GL(L, g);
@@ -777,7 +777,7 @@ __global__ __launch_bounds__(SPH_DT) __attribute__((amdgpu_waves_per_eu(5))) voi
         g = it.x;
         pb = it.y * SPH_CAP;
     } else {
-        g = xcd_remap(blockIdx.x, ng);
+        g = xcd_chunk(blockIdx.x);
         if (g >= ng) return;
         pb = 0;
     }
@@ -991,7 +991,7 @@ int gx_sph_walk(gx_ctx* ctx, TreeSlot& T, ListSet& Ls, int ng, const int32_t* gr
     const double* wbox = (const double*)T.wbox.p;
     const int4* wsph = (const int4*)T.wsph.p;
     const float* whmax = (const float*)T.whmax.p;
-    hipLaunchKernelGGL(k_walk_sph_bfs, dim3(xcd_grid(ng)), dim3(64), 0, st, ng, groups, recv,
+    hipLaunchKernelGGL(k_walk_sph_bfs, dim3(xcd_chunk_grid(ng)), dim3(64), 0, st, ng, groups, recv,
                        (const NodeRec*)T.nodes.p, (int64_t)nn, wbox, wsph, whmax, rad, use_hmax,
                        active, SPH_RANGES, cnt, ptot, (unsigned long long*)tot,
                        (int32_t*)Ls.pr_begin.p, (int32_t*)Ls.pr_cum.p, ovf);
@@ -1013,7 +1013,7 @@ int gx_sph_walk(gx_ctx* ctx, TreeSlot& T, ListSet& Ls, int ng, const int32_t* gr
         uint8_t* sovf = (uint8_t*)Ls.aux.p;
         const NodeRec* nodes = (const NodeRec*)T.nodes.p;
         const MomRec* mom = (const MomRec*)T.mom.p;
-        hipLaunchKernelGGL(k_walk_sph_wave, dim3(xcd_grid(ng)), dim3(64), 0, st, ng, groups, recv,
+        hipLaunchKernelGGL(k_walk_sph_wave, dim3(xcd_chunk_grid(ng)), dim3(64), 0, st, ng, groups, recv,
                            nodes, (int64_t)nn, wbox, wsph, whmax, rad, use_hmax, ovf, 0, cnt2,
                            ptot2, (unsigned long long*)tot, nullptr, nullptr, nullptr, sovf);
         GX_LAUNCH_CHECK(ctx);
@@ -1032,7 +1032,7 @@ int gx_sph_walk(gx_ctx* ctx, TreeSlot& T, ListSet& Ls, int ng, const int32_t* gr
         const int64_t nr = h[13];
         GX_TRY(gx_reserve(ctx, Ls.pc_off, (nr + 1) * sizeof(int32_t)));
         GX_TRY(gx_reserve(ctx, Ls.pc_list, (nr + 1) * sizeof(int32_t)));
-        hipLaunchKernelGGL(k_walk_sph_wave, dim3(xcd_grid(ng)), dim3(64), 0, st, ng, groups, recv,
+        hipLaunchKernelGGL(k_walk_sph_wave, dim3(xcd_chunk_grid(ng)), dim3(64), 0, st, ng, groups, recv,
                            nodes, (int64_t)nn, wbox, wsph, whmax, rad, use_hmax, ovf, 1, nullptr,
                            nullptr, nullptr, (const int64_t*)Ls.pr_off.p, (int32_t*)Ls.pc_off.p,
                            (int32_t*)Ls.pc_list.p, sovf);
@@ -1191,7 +1191,7 @@ extern "C" int gx_sph_density(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, 
                            &list_pairs));
         if (stats) GX_HIP(ctx, hipEventRecord(ctx->ev2, st));
         GX_TRY(gx_zero(ctx, hv, (size_t)nb * sizeof(uint32_t)));
-        hipLaunchKernelGGL(k_sph_density, dim3(xcd_grid(nb)), dim3(SPH_DT), 0, st, nb,
+        hipLaunchKernelGGL(k_sph_density, dim3(xcd_chunk_grid(nb)), dim3(SPH_DT), 0, st, nb,
                            (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p,
                            (const double4*)T.pos4.p,
                            (const uint32_t*)T.val[0].p, act, view, rad, (float)n_ngb, (float)tol,
@@ -1291,7 +1291,7 @@ extern "C" int gx_sph_forces(gx_ctx* ctx, const gx_particles* gas, gx_gas* gs, d
     GX_TRY(work(ctx, W_NGB, (size_t)(nb + 1) * sizeof(uint32_t), (void**)&gngb));
     GX_TRY(gx_zero(ctx, gngb, (size_t)nb * sizeof(uint32_t)));
     GX_TRY(gx_zero(ctx, hv, (size_t)nb * sizeof(uint32_t)));
-    hipLaunchKernelGGL(k_sph_force<false>, dim3(xcd_grid(nb)), dim3(SPH_DT), 0, st, nb,
+    hipLaunchKernelGGL(k_sph_force<false>, dim3(xcd_chunk_grid(nb)), dim3(SPH_DT), 0, st, nb,
                        (const int2*)nullptr, (const int32_t*)T.groups.p,
                        (const NodeRec*)T.nodes.p, (const double4*)T.pos4.p,
                        (const uint32_t*)T.val[0].p, sv, ss, view, (float)alpha, ax, ay, az,

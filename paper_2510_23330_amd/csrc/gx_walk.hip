@@ -245,7 +245,7 @@ __global__ __launch_bounds__(64) void k_walk_grav_wave(
     int32_t* __restrict__ pr_begin, int32_t* __restrict__ pr_cum, int cap_pc, int cap_pr,
     uint8_t* __restrict__ gflag, int32_t* __restrict__ gdepth, int scap) {
     // scap: entries of stk in use, 1 <= scap <= GWALK_STACK
-    const int g = xcd_remap(blockIdx.x, ng);
+    const int g = xcd_chunk(blockIdx.x);
     if (g >= ng) return;
     const int lane = threadIdx.x;
     const char* bx[6];
@@ -377,7 +377,7 @@ int gx_walk_grav_wave(gx_ctx* ctx, TreeSlot& T, int ng, double theta2, bool smal
     GX_TRY(gx_walk_tree(ctx, T));
     auto kern = small_stack ? k_walk_grav_wave<GWALK_STACK_S> : k_walk_grav_wave<GWALK_STACK_L>;
     const int scap = small_stack ? gx_walk_stack_small(ctx) : GWALK_STACK_L;
-    hipLaunchKernelGGL(kern, dim3(xcd_grid(ng)), dim3(64), 0, ctx->stream, ng,
+    hipLaunchKernelGGL(kern, dim3(xcd_chunk_grid(ng)), dim3(64), 0, ctx->stream, ng,
                        (const int32_t*)T.groups.p, (const NodeRec*)T.nodes.p, (int64_t)T.n_nodes,
                        (const double*)T.wbox.p, (const int4*)T.wrec.p, (const double*)T.box.p,
                        theta2, pc_cnt, pr_cnt, pp_tot, pc_list, pr_begin, pr_cum, cap_pc, cap_pr,
@@ -547,7 +547,7 @@ __global__ __launch_bounds__(64) void k_walk_sph_bfs(
     uint32_t* __restrict__ pr_cnt, uint32_t* __restrict__ pp_tot,
     unsigned long long* __restrict__ tot, int32_t* __restrict__ pr_begin,
     int32_t* __restrict__ pr_cum, uint8_t* __restrict__ ovf) {
-    const int g = xcd_remap(blockIdx.x, ng);
+    const int g = xcd_chunk(blockIdx.x);
     if (g >= ng) return;
     const int lane = threadIdx.x;
     if (active && !active[g]) {
@@ -654,7 +654,7 @@ __global__ __launch_bounds__(64) void k_walk_sph_wave(
     uint32_t* __restrict__ pp_tot, unsigned long long* __restrict__ tot,
     const int64_t* __restrict__ pr_off, int32_t* __restrict__ pr_begin,
     int32_t* __restrict__ pr_cum, uint8_t* __restrict__ sovf) {
-    const int g = xcd_remap(blockIdx.x, ng);
+    const int g = xcd_chunk(blockIdx.x);
     if (g >= ng) return;
     const int lane = threadIdx.x;
     if (!active[g] || (mode == 1 && sovf[g])) {
