@@ -19,9 +19,10 @@ The surrogate has its own library context (its own gas-tree slot).  In the
 synchronous mode it runs on the galaxy's stream in the calling thread.  In
 the asynchronous mode -- the single-GPU counterpart of the paper's pool
 nodes, which work while the main nodes integrate -- the galaxy's stream
-copies the gas state at the hand-over into a snapshot, and a worker thread
-runs the pipeline on the snapshot on the surrogate's own stream (default
-priority) while the galaxy steps on, starting after the next step's gravity
+copies the gas state and the positions of all particles at the hand-over
+into a snapshot (device copies, no wait on the host), and a worker thread
+chooses the sites from the snapshot and runs the pipeline on it on the
+surrogate's own stream (default priority) while the galaxy steps on, starting after the next step's gravity
 kernel (in the shadow of the latency-bound SPH and tree phases, not beside
 the compute-bound gravity kernel); the galaxy's stream waits for a result's
 completion event only when its replacement falls due.  Both modes
@@ -153,6 +154,8 @@ class SNCoupling:
             # still read the other
             self._slots = [dict({a: torch.empty(ng, dtype=torch.float64, device=dev)
                                  for a in _SNAP_F64},
+                                **{a: torch.empty(p.n, dtype=torch.float64, device=dev)
+                                   for a in ("px", "py", "pz")},
                                 H=torch.empty(ng, dtype=torch.float32, device=dev),
                                 id=torch.empty(ng, dtype=torch.int64, device=dev),
                                 released=None, released_flag=threading.Event())
@@ -172,25 +175,28 @@ class SNCoupling:
             self._worker.start()
 
     # ---- sites ----------------------------------------------------------------
-    def sites(self, step_index: int):
+    def sites(self, step_index: int, pos=None):
         """This step's SN sites: candidate stars in a seeded random order,
         each kept unless its box would overlap the box of a site already kept
-        (so every gas particle belongs to at most one region), until K."""
+        (so every gas particle belongs to at most one region), until K.
+        `pos` = (x, y, z) of all particles (default: the galaxy's own
+        arrays; the asynchronous hand-over passes its snapshot of them)."""
         rng = np.random.default_rng(self.seed + step_index)
-        torch, p = self.torch, self.step.p
+        torch = self.torch
+        x, y, z = (self.step.p.x, self.step.p.y, self.step.p.z) if pos is None else pos
         side = self.side / PC_PER_KPC
         kept = np.zeros((0, 3))
         chosen, seen = [], set()
         want = min(self.K, self.cand.size)
         for _ in range(64):  # draws of 4K distinct candidates until K are kept
             draw = rng.choice(self.cand, size=min(4 * self.K, self.cand.size), replace=False)
-            idx = torch.as_tensor(draw, device=p.x.device)
-            pos = torch.stack([p.x[idx], p.y[idx], p.z[idx]], dim=1).cpu().numpy()
-            kept = keep_in_order(draw, pos, side, kept, seen, chosen, want)
+            idx = torch.as_tensor(draw, device=x.device)
+            at = torch.stack([x[idx], y[idx], z[idx]], dim=1).cpu().numpy()
+            kept = keep_in_order(draw, at, side, kept, seen, chosen, want)
             if len(chosen) == want:
                 break
-        s = torch.as_tensor(np.sort(np.asarray(chosen, np.int64)), device=p.x.device)
-        return torch.stack([p.x[s], p.y[s], p.z[s]], dim=1).contiguous()
+        s = torch.as_tensor(np.sort(np.asarray(chosen, np.int64)), device=x.device)
+        return torch.stack([x[s], y[s], z[s]], dim=1).contiguous()
 
     def _valid(self, pred, K):
         """Per-region check (gx_sn_check) that every predicted channel stays
@@ -271,9 +277,9 @@ class SNCoupling:
     def launch(self, step_index: int):
         """Hand this step's regions to the surrogate; queue their replacement."""
         st = self.step
-        centers = self.sites(step_index)
         item = Pending(step_index + self.delay)
         if not self.asynchronous:
+            centers = self.sites(step_index)
             snap = {a: getattr(st.gas, a) for a in ("x", "y", "z", "vx", "vy", "vz", "m")}
             snap.update(u=st.g.u, H=st.g.H, id=st.p.id[st.gas_offset:])
             self._count(self._pipeline(snap, centers, step_index, item))
@@ -291,12 +297,16 @@ class SNCoupling:
             slot["u"].copy_(st.g.u)
             slot["H"].copy_(st.g.H)
             slot["id"].copy_(st.p.id[st.gas_offset:])
+            # the sites are chosen by the worker from this copy of the
+            # positions, so the galaxy's thread neither reads back nor waits
+            for a, b in (("px", st.p.x), ("py", st.p.y), ("pz", st.p.z)):
+                slot[a].copy_(b)
             taken = torch.cuda.Event()
             taken.record(self.main_stream)
             slot["released_flag"].clear()
             with self._gate_cv:
                 need = len(self._gates) + 1
-            self._jobs.put((slot, taken, need, centers, step_index, item))
+            self._jobs.put((slot, taken, need, step_index, item))
         self.queue.append(item)
 
     def _publish_gate(self):
@@ -318,11 +328,12 @@ class SNCoupling:
             job = self._jobs.get()
             if job is None:
                 return
-            slot, taken, need, centers, step_index, item = job
+            slot, taken, need, step_index, item = job
             try:
-                gate = self._gate(need) if self.start == "after_gravity" else None
                 with torch.cuda.stream(self.sur_stream):
                     self.sur_stream.wait_event(taken)
+                    centers = self.sites(step_index, (slot["px"], slot["py"], slot["pz"]))
+                    gate = self._gate(need) if self.start == "after_gravity" else None
                     if gate is not None:
                         self.sur_stream.wait_event(gate)
                     t0 = torch.cuda.Event(enable_timing=True)
