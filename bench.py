@@ -376,8 +376,8 @@ def sn_region_leg(eng, n_cubes, infer_batch, weights, resampler="cdf", sweeps=4,
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                          "(sharding across GPUs is not built)"}))
+        print(json.dumps({"error": "this program runs on one GPU; --gpus must be 1 "
+                          "(sharding across GPUs is not implemented)"}))
         sys.exit(2)
     import torch
     import ics

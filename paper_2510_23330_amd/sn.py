@@ -1,5 +1,5 @@
 """Supernova regions: plain small-timestep SPH of many independent cubes (the
-surrogate's training-data generator, fallback and judge) and the surrogate
+surrogate's training-data generator, fallback and error reference) and the surrogate
 pipeline that replaces it (voxelize -> U-Net -> resample), Secs. 3.2-3.3.
 
 Units: pc, km/s, Msun (time unit 0.97779 Myr).  Cubes are placed far apart

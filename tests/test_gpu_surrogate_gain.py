@@ -2,7 +2,7 @@
 
 A small surrogate (32^3 voxels, 3 levels from 16 channels) is trained from
 scratch by the project's own kernels on supernova cubes that the plain
-small-timestep SPH generates, then judged on held-out cubes against that
+small-timestep SPH generates, then evaluated on held-out cubes against that
 plain SPH.  Without the surrogate the galaxy has two choices for such a
 region: keep its state for the 0.1 Myr (persistence: the explosion is
 missed) or integrate it at the global 2,000 yr step (far above the Courant
