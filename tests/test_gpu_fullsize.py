@@ -43,6 +43,12 @@ def test_fullsize_tree_gravity_sampled(gx, disk):
         print(f"16M gravity: {st['n_pp']:.3e} pp + {st['n_pc']:.3e} pc, kernel {st['ms_kernel']:.1f} ms")
         ax, ay, az, pot = (o.cpu().numpy() for o in out)
         del out, p
+        # every group was processed: each particle has a strictly negative
+        # potential (the sum of -G m_j / r over all other particles) and a
+        # finite, nonzero acceleration (outputs start at zero)
+        assert np.all(pot < 0)
+        assert np.all(np.isfinite(ax) & np.isfinite(ay) & np.isfinite(az))
+        assert np.all((ax != 0) | (ay != 0) | (az != 0))
         T = oracle.Tree(d, 16, 256)
         gsel = ics.sample_indices(T.n_groups, 48, 17)
         oax, oay, oaz, opot, npp, npc = T.gravity_groups(gsel, ics.G_KPC, 0.5, True)
