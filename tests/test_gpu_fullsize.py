@@ -77,6 +77,10 @@ def test_fullsize_sph_density_sampled_and_force_invariants(gx, disk):
         eng.tree_build(p, gx.GX_TREE_GAS, 8, 64)
         st = eng.sph_density(p, g, 64.0, GAMMA, 1e-3, 64)
         assert st["n_noconv"] == 0
+        # every group was processed: each density includes at least the
+        # particle's own kernel term (the outputs start at zero)
+        rho_all = g.rho.cpu().numpy()
+        assert np.all(rho_all > 0) and np.all(np.isfinite(rho_all))
         idx = ics.sample_indices(n, 256, 23)
         Ho, rho_o, it, nf, S = oracle.sph_density(gas, 64.0, 1e-10, 200, idx=idx, with_slope=True)
         assert nf == 0
@@ -91,6 +95,9 @@ def test_fullsize_sph_density_sampled_and_force_invariants(gx, disk):
         eng.sph_forces(p, g, *acc, gamma=GAMMA, alpha=1.0)
         a = [t.cpu().numpy() for t in acc]
         du = g.dudt.cpu().numpy()
+        vs_all = g.vsig.cpu().numpy()
+        assert all(np.all(np.isfinite(c)) for c in a) and np.all(np.isfinite(du))
+        assert np.all(vs_all > 0)
         m = gas["m"]
         tot = np.sum(m * np.sqrt(a[0] ** 2 + a[1] ** 2 + a[2] ** 2))
         for comp in a:
