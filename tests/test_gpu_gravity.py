@@ -139,6 +139,44 @@ def test_direct_fp32_vs_fp64_oracle(gx, eng):
         assert abs(np.sum(m * a)) <= 1e-6 * scale
 
 
+@pytest.mark.parametrize("mode", ["tree_quad", "tree_mono", "direct", "tree_fp64"])
+def test_one_and_two_particle_systems(gx, eng, mode):
+    # Degenerate systems with closed forms (Eq. 1): a lone particle feels no
+    # force and no potential (its own pair is excluded), and two particles
+    # attract along their separation with the softened law, softening
+    # eps_i^2 + eps_j^2 (values exact in the FP32 storage of eps^2).
+    flags = {"tree_quad": gx.GX_QUAD, "tree_mono": 0, "direct": gx.GX_DIRECT,
+             "tree_fp64": gx.GX_QUAD | gx.GX_PREC_FP64}[mode]
+    tol = 1e-12 if mode == "tree_fp64" else 1e-5
+    G = 1.0
+    zero = lambda n: np.zeros(n)
+    d1 = dict(x=np.array([0.25]), y=np.array([-0.5]), z=np.array([0.125]), vx=zero(1),
+              vy=zero(1), vz=zero(1), m=np.array([2.0]), eps2=np.array([1 / 64], np.float32))
+    p = _dev(gx, d1)
+    eng.tree_build(p, gx.GX_TREE_ALL, 16, 256)
+    out = _zeros(1)
+    eng.gravity_forces(p, G, 0.5, flags, *out)
+    assert all(float(v[0]) == 0.0 for v in _np(out))
+    x, y, z = np.array([0.25, 0.55]), np.array([-0.5, -0.7]), np.array([0.125, 0.225])
+    m, e2 = np.array([2.0, 0.5]), np.array([1 / 64, 1 / 256], np.float32)
+    d2 = dict(x=x, y=y, z=z, vx=zero(2), vy=zero(2), vz=zero(2), m=m, eps2=e2)
+    p = _dev(gx, d2)
+    eng.tree_build(p, gx.GX_TREE_ALL, 16, 256)
+    out = _zeros(2)
+    eng.gravity_forces(p, G, 0.5, flags, *out)
+    ax, ay, az, pot = _np(out)
+    o = oracle.direct_gravity(d2, G)
+    for i, j in ((0, 1), (1, 0)):
+        r = np.array([x[j] - x[i], y[j] - y[i], z[j] - z[i]])
+        s2 = r @ r + float(e2[i]) + float(e2[j])
+        a = G * m[j] / s2 ** 1.5 * r
+        phi = -G * m[j] / np.sqrt(s2)
+        assert np.max(np.abs(np.array([ax[i], ay[i], az[i]]) - a)) <= tol * np.linalg.norm(a)
+        assert abs(pot[i] - phi) <= tol * abs(phi)
+        assert np.max(np.abs(np.array([o[0][i], o[1][i], o[2][i]]) - a)) <= 1e-14 * np.linalg.norm(a)
+        assert abs(o[3][i] - phi) <= 1e-14 * abs(phi)
+
+
 def test_direct_fp64_mode_matches_oracle(gx, eng):
     d = ics.plummer(4096, 2)
     p = _dev(gx, d)
