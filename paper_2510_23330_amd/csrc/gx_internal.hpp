@@ -262,7 +262,8 @@ __device__ __forceinline__ T block_excl_scan256(T v, T* sh4, T* block_total) {
 
 // Map a linear block index to a work item so that each of the 8 XCDs (which
 // receive blocks round-robin) works on one contiguous eighth of the items:
-// neighbouring groups share tree nodes and then share that XCD's L2.
+// neighbouring items share data (the convolution slabs' halo planes) in that
+// XCD's L2.  For items of equal cost only; see xcd_chunk below otherwise.
 __device__ __forceinline__ int xcd_remap(int b, int n_items) {
     int per = (n_items + 7) / 8;
     return (b % 8) * per + b / 8;
