@@ -1359,6 +1359,117 @@ __global__ void k_grad_combine(int64_t n, const uint16_t* __restrict__ a,
     out[i] = f2bf(v);
 }
 
+// Backward-pass fusions of the up and down paths, eight channels (16 bytes)
+// per thread.  Each computes, value for value, what the separate passes it
+// replaces compute (the same bf16 roundings in the same order), so the
+// gradients are bit-identical to the unfused sequence.
+__device__ __forceinline__ float dact(float v, uint16_t y) {
+    return bf2f(y) > 0.0f ? v : v * LRELU_SLOPE;
+}
+
+// The gradient of a concatenated input [v][Ca + Cb] split into [v][Ca] and
+// [v][Cb], the first part times the leaky-ReLU derivative at ya (what the
+// split followed by the gradient combination with ya computes).
+__global__ __launch_bounds__(256) void k_split_dact(const uint16_t* __restrict__ gc, int64_t V,
+                                                    int Ca, int Cb,
+                                                    const uint16_t* __restrict__ ya,
+                                                    uint16_t* __restrict__ ga,
+                                                    uint16_t* __restrict__ gb) {
+    const int P = (Ca + Cb) / 8;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= V * P) return;
+    const int64_t v = e / P;
+    const int c = (int)(e - v * P) * 8;
+    const uint4 g = *reinterpret_cast<const uint4*>(gc + v * (Ca + Cb) + c);
+    if (c < Ca) {
+        const uint4 y = *reinterpret_cast<const uint4*>(ya + v * Ca + c);
+        const uint16_t* gh = reinterpret_cast<const uint16_t*>(&g);
+        const uint16_t* yh = reinterpret_cast<const uint16_t*>(&y);
+        uint4 o;
+        uint16_t* oh = reinterpret_cast<uint16_t*>(&o);
+#pragma unroll
+        for (int j = 0; j < 8; j++) oh[j] = f2bf(dact(bf2f(gh[j]), yh[j]));
+        *reinterpret_cast<uint4*>(ga + v * Ca + c) = o;
+    } else {
+        *reinterpret_cast<uint4*>(gb + v * Cb + (c - Ca)) = g;
+    }
+}
+
+// Nearest-upsampling backward (din at S: the sum of its 8 cells of dout at
+// 2S, rounded to bf16) times the leaky-ReLU derivative at y.
+__global__ __launch_bounds__(256) void k_upsample2_bwd_dact(const uint16_t* __restrict__ dout,
+                                                            int B, int S, int C,
+                                                            const uint16_t* __restrict__ y,
+                                                            uint16_t* __restrict__ din) {
+    const int P = C / 8;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)B * S * S * S * P) return;
+    const int c = (int)(e % P) * 8;
+    int64_t t = e / P;
+    const int x = (int)(t % S);
+    t /= S;
+    const int yy = (int)(t % S);
+    t /= S;
+    const int z = (int)(t % S);
+    const int64_t b = t / S;
+    const int Sf = 2 * S;
+    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int d = 0; d < 8; d++) {
+        const int X = 2 * x + (d & 1), Y = 2 * yy + ((d >> 1) & 1), Z = 2 * z + (d >> 2);
+        const uint4 g = *reinterpret_cast<const uint4*>(dout + (((b * Sf + Z) * Sf + Y) * Sf + X) * C + c);
+        const uint16_t* gh = reinterpret_cast<const uint16_t*>(&g);
+#pragma unroll
+        for (int j = 0; j < 8; j++) s[j] += bf2f(gh[j]);
+    }
+    const int64_t o0 = (((b * S + z) * S + yy) * S + x) * C + c;
+    const uint4 yv = *reinterpret_cast<const uint4*>(y + o0);
+    const uint16_t* yh = reinterpret_cast<const uint16_t*>(&yv);
+    uint4 o;
+    uint16_t* oh = reinterpret_cast<uint16_t*>(&o);
+#pragma unroll
+    for (int j = 0; j < 8; j++) oh[j] = f2bf(dact(bf2f(f2bf(s[j])), yh[j]));
+    *reinterpret_cast<uint4*>(din + o0) = o;
+}
+
+// 2^3 average-pooling backward (din at S: an eighth of its coarse cell of
+// dout, rounded to bf16) plus the skip gradient, times the leaky-ReLU
+// derivative at y.
+__global__ __launch_bounds__(256) void k_avgpool2_bwd_combine(const uint16_t* __restrict__ dout,
+                                                              int B, int S, int C,
+                                                              const uint16_t* __restrict__ skip,
+                                                              const uint16_t* __restrict__ y,
+                                                              uint16_t* __restrict__ din) {
+    const int P = C / 8;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)B * S * S * S * P) return;
+    const int c = (int)(e % P) * 8;
+    int64_t t = e / P;
+    const int x = (int)(t % S);
+    t /= S;
+    const int yy = (int)(t % S);
+    t /= S;
+    const int z = (int)(t % S);
+    const int64_t b = t / S;
+    const int So = S / 2;
+    const uint4 g = *reinterpret_cast<const uint4*>(
+        dout + (((b * So + z / 2) * So + yy / 2) * So + x / 2) * C + c);
+    const int64_t o0 = (((b * S + z) * S + yy) * S + x) * C + c;
+    const uint4 sk = *reinterpret_cast<const uint4*>(skip + o0);
+    const uint4 yv = *reinterpret_cast<const uint4*>(y + o0);
+    const uint16_t* gh = reinterpret_cast<const uint16_t*>(&g);
+    const uint16_t* sh = reinterpret_cast<const uint16_t*>(&sk);
+    const uint16_t* yh = reinterpret_cast<const uint16_t*>(&yv);
+    uint4 o;
+    uint16_t* oh = reinterpret_cast<uint16_t*>(&o);
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        float v = bf2f(f2bf(0.125f * bf2f(gh[j])));
+        v += bf2f(sh[j]);
+        oh[j] = f2bf(dact(v, yh[j]));
+    }
+    *reinterpret_cast<uint4*>(din + o0) = o;
+}
+
 __global__ void k_f32_to_bf16(const float* __restrict__ x, int64_t n, uint16_t* __restrict__ y) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) y[i] = f2bf(x[i]);
@@ -1895,6 +2006,45 @@ extern "C" int gx_grad_combine(gx_ctx* ctx, int64_t n, const uint16_t* a, const 
     GX_HIP(ctx, hipSetDevice(ctx->device));
     hipLaunchKernelGGL(k_grad_combine, dim3(gx_blocks(n, 256)), dim3(256), 0, ctx->stream, n, a, b, y,
                        out);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+// Fused backward steps of the network (used by gx_unet_backward; channel
+// counts multiples of 8, 16-byte aligned rows).  Each equals the unfused
+// sequence named in its kernel's comment, bit for bit.
+int gx_split_dact(gx_ctx* ctx, const uint16_t* gc, int64_t V, int Ca, int Cb, const uint16_t* ya,
+                  uint16_t* ga, uint16_t* gb) {
+    if (!ctx || !gc || !ya || !ga || !gb || V < 0 || Ca < 8 || Cb < 8 || Ca % 8 || Cb % 8)
+        return gx_fail(ctx, GX_EINVAL, "split_dact: bad arguments");
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    const int64_t n = V * ((Ca + Cb) / 8);
+    hipLaunchKernelGGL(k_split_dact, dim3(gx_blocks(n, 256)), dim3(256), 0, ctx->stream, gc, V, Ca,
+                       Cb, ya, ga, gb);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+int gx_upsample2_bwd_dact(gx_ctx* ctx, const uint16_t* dout, int B, int S, int C,
+                          const uint16_t* y, uint16_t* din) {
+    if (!ctx || !dout || !y || !din || B < 1 || S < 1 || C < 8 || C % 8)
+        return gx_fail(ctx, GX_EINVAL, "upsample2_bwd_dact: bad arguments");
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    const int64_t n = (int64_t)B * S * S * S * (C / 8);
+    hipLaunchKernelGGL(k_upsample2_bwd_dact, dim3(gx_blocks(n, 256)), dim3(256), 0, ctx->stream,
+                       dout, B, S, C, y, din);
+    GX_LAUNCH_CHECK(ctx);
+    return GX_OK;
+}
+
+int gx_avgpool2_bwd_combine(gx_ctx* ctx, const uint16_t* dout, int B, int S, int C,
+                            const uint16_t* skip, const uint16_t* y, uint16_t* din) {
+    if (!ctx || !dout || !skip || !y || !din || B < 1 || S < 2 || S % 2 || C < 8 || C % 8)
+        return gx_fail(ctx, GX_EINVAL, "avgpool2_bwd_combine: bad arguments");
+    GX_HIP(ctx, hipSetDevice(ctx->device));
+    const int64_t n = (int64_t)B * S * S * S * (C / 8);
+    hipLaunchKernelGGL(k_avgpool2_bwd_combine, dim3(gx_blocks(n, 256)), dim3(256), 0, ctx->stream,
+                       dout, B, S, C, skip, y, din);
     GX_LAUNCH_CHECK(ctx);
     return GX_OK;
 }

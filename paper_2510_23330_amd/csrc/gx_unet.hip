@@ -23,6 +23,14 @@
 #include <string>
 #include <vector>
 
+// fused backward steps (gx_nn.hip); channel counts multiples of 8
+int gx_split_dact(gx_ctx* ctx, const uint16_t* gc, int64_t V, int Ca, int Cb, const uint16_t* ya,
+                  uint16_t* ga, uint16_t* gb);
+int gx_upsample2_bwd_dact(gx_ctx* ctx, const uint16_t* dout, int B, int S, int C,
+                          const uint16_t* y, uint16_t* din);
+int gx_avgpool2_bwd_combine(gx_ctx* ctx, const uint16_t* dout, int B, int S, int C,
+                            const uint16_t* skip, const uint16_t* y, uint16_t* din);
+
 namespace {
 
 struct ULayer {
@@ -301,8 +309,13 @@ extern "C" int gx_unet_backward(gx_ctx* ctx, const gx_unet* net, const uint16_t*
             GX_TRY(wgrad(da, act("c" + ls), g[da], s));
         }
         GX_TRY(dgrad(da, g[da], s, nullptr, g["c" + ls]));
-        GX_TRY(gx_concat(ctx, g[uc], ch[l], g["skip" + ls], ch[l], V, g["c" + ls], 1));
-        GX_TRY(gx_grad_combine(ctx, V * ch[l], g[uc], nullptr, act(uc), g[uc]));
+        if (ch[l] % 8 == 0) {
+            GX_TRY(gx_split_dact(ctx, g["c" + ls], V, ch[l], ch[l], act(uc), g[uc],
+                                 g["skip" + ls]));
+        } else {
+            GX_TRY(gx_concat(ctx, g[uc], ch[l], g["skip" + ls], ch[l], V, g["c" + ls], 1));
+            GX_TRY(gx_grad_combine(ctx, V * ch[l], g[uc], nullptr, act(uc), g[uc]));
+        }
         // the coarser level's output, whose upsampling is this layer's input
         const std::string below =
             l + 1 < top ? "d" + std::to_string(l + 1) + "b" : "e" + std::to_string(top) + "b";
@@ -318,8 +331,13 @@ extern "C" int gx_unet_backward(gx_ctx* ctx, const gx_unet* net, const uint16_t*
         // into the next coarser level's output
         const int sc = s / 2;
         const int64_t Vc = (int64_t)B * sc * sc * sc;
-        GX_TRY(gx_upsample2(ctx, g["up" + ls], B, sc, ch[l + 1], g[below], 1));
-        GX_TRY(gx_grad_combine(ctx, Vc * ch[l + 1], g[below], nullptr, act(below), g[below]));
+        if (ch[l + 1] % 8 == 0) {
+            GX_TRY(gx_upsample2_bwd_dact(ctx, g["up" + ls], B, sc, ch[l + 1], act(below),
+                                         g[below]));
+        } else {
+            GX_TRY(gx_upsample2(ctx, g["up" + ls], B, sc, ch[l + 1], g[below], 1));
+            GX_TRY(gx_grad_combine(ctx, Vc * ch[l + 1], g[below], nullptr, act(below), g[below]));
+        }
     }
     // encoder, coarsest level first
     for (int l = top; l >= 0; l--) {
@@ -338,9 +356,14 @@ extern "C" int gx_unet_backward(gx_ctx* ctx, const gx_unet* net, const uint16_t*
         // through the pooling into level l-1's output, plus its skip gradient
         const int sf = 2 * s;
         const int64_t Vf = (int64_t)B * sf * sf * sf;
-        GX_TRY(gx_avgpool2(ctx, g[pl], B, sf, ch[l - 1], g[ebl], 1));
-        GX_TRY(gx_grad_combine(ctx, Vf * ch[l - 1], g[ebl], g["skip" + std::to_string(l - 1)],
-                               act(ebl), g[ebl]));
+        if (ch[l - 1] % 8 == 0) {
+            GX_TRY(gx_avgpool2_bwd_combine(ctx, g[pl], B, sf, ch[l - 1],
+                                           g["skip" + std::to_string(l - 1)], act(ebl), g[ebl]));
+        } else {
+            GX_TRY(gx_avgpool2(ctx, g[pl], B, sf, ch[l - 1], g[ebl], 1));
+            GX_TRY(gx_grad_combine(ctx, Vf * ch[l - 1], g[ebl], g["skip" + std::to_string(l - 1)],
+                                   act(ebl), g[ebl]));
+        }
     }
     return GX_OK;
 }
